@@ -1,0 +1,352 @@
+"""Plain FP64 CPU oracle of blocked modes sampling (Ghanem & Koch, arXiv:1912.01379).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of the
+benchmark are the only users.  The product (the GPU library and its binding) never
+imports this package, and this package never imports the product.
+
+Steps, in the paper's order:
+  1. whitening, Sec. III after Eq. (chi2): C^-1 = T^T T, g~ = T g, K~ = T K;
+  2. per-block SVD K~_b = U_b D_b V_b^T, Sec. IV.B/IV.C, with d := 0 beyond the
+     numerical rank (the paper's zero modes);
+  3. the random walk over blocked modes (C core, `core.c`);
+  4. averages of Eq. (MCint), their error bars, and the sensitivity of the average to
+     the data, d<f>/dg = -Cov(f, r~) T, which follows from differentiating the
+     posterior of Eq. (PI) (the normaliser depends on g).
+
+Readings where the paper leaves a choice open (shared by the GPU library by definition,
+not by code):
+  * numerical rank: d_i > max(M, N_b) * eps * d_1; the number of data modes of a block is
+    min(requested, rank);
+  * sign of a data mode: sum_n (n+1) V_ni > 0;
+  * zero-mode basis: the last N_b - k columns of the Householder product that
+    triangularises the data-mode columns (reflector x -> beta e_1, beta = -sign(x_1)|x|,
+    sign(0) = +1);
+  * start vector: the best constant fit c* = (K~ 1).g~ / |K~ 1|^2 (1 if c* <= 0);
+  * error bars: standard error of the mean over G independent chain groups (or G batches
+    of sweeps when there are fewer chains than groups).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_SRC = os.path.join(_HERE, "core.c")
+_lock = threading.Lock()
+_lib = None
+
+EPS = np.finfo(np.float64).eps
+
+
+def build(force: bool = False) -> str:
+    """Compile the C core with gcc (plain -O2, IEEE arithmetic, no fast-math)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("B", ctypes.c_int64),
+                ("Kt", ctypes.c_void_p), ("gt", ctypes.c_void_p), ("bstart", ctypes.c_void_p),
+                ("kb", ctypes.c_void_p), ("d", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("V", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("chains", ctypes.c_int64), ("burnin", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("problem_index", ctypes.c_int64),
+                ("refresh_every", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("want_cross", ctypes.c_int64), ("threads", ctypes.c_int64),
+                ("traj_chain", ctypes.c_int64), ("init", ctypes.c_void_p)]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("sumA", "sumA2", "count", "sumR", "sumRA", "final_A", "final_r", "final_chi2",
+                 "traj_A", "traj_chi2", "drift_max", "n_frozen", "n_clamped", "status")]
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_LIB_PATH)
+            L.orc_E.restype = ctypes.c_double
+            L.orc_E.argtypes = [ctypes.c_double, ctypes.c_double]
+            L.orc_S.restype = ctypes.c_double
+            L.orc_S.argtypes = [ctypes.c_double] * 4
+            L.orc_tn_draw.restype = ctypes.c_double
+            L.orc_tn_draw.argtypes = [ctypes.c_double] * 5
+            L.orc_mills.restype = ctypes.c_double
+            L.orc_mills.argtypes = [ctypes.c_double]
+            L.orc_Mk.restype = ctypes.c_double
+            L.orc_Mk.argtypes = [ctypes.c_int, ctypes.c_double]
+            L.orc_move_uniform.restype = ctypes.c_double
+            L.orc_move_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_int64] * 5
+            L.orc_philox.restype = None
+            L.orc_philox.argtypes = [ctypes.c_void_p] * 3
+            L.orc_run.restype = ctypes.c_int
+            L.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                                  ctypes.POINTER(_Out)]
+            _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------------------
+# scalar helpers exposed for the pins
+# --------------------------------------------------------------------------------------
+
+def E(a: float, t: float) -> float:
+    return lib().orc_E(float(a), float(t))
+
+
+def S(a: float, w: float, u: float, uc: Optional[float] = None) -> float:
+    uc = 1.0 - u if uc is None else uc
+    return lib().orc_S(float(a), float(w), float(u), float(uc))
+
+
+def tn_draw(c: float, d: float, lo: float, hi: float, u: float) -> float:
+    return lib().orc_tn_draw(float(c), float(d), float(lo), float(hi), float(u))
+
+
+def mills(x: float) -> float:
+    return lib().orc_mills(float(x))
+
+
+def Mk(k: int, z: float) -> float:
+    return lib().orc_Mk(int(k), float(z))
+
+
+def move_uniform(seed, problem, chain, sweep, block, mode) -> float:
+    return lib().orc_move_uniform(int(seed) & 0xFFFFFFFFFFFFFFFF, problem, chain, sweep, block, mode)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# setup: whitening and block factors
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class Prepared:
+    Kt: np.ndarray            # M x N
+    gt: np.ndarray            # M
+    bstart: np.ndarray        # B+1
+    kb: np.ndarray            # B (int32)
+    d: list                   # per block: singular values of the data modes
+    U: list                   # per block: M x kb
+    V: list                   # per block: Nb x Nb (columns = modes, data first)
+    dall: list                # per block: all singular values (min(M, Nb))
+    Tt: object                # callable y -> T^T y
+    init: np.ndarray          # N
+
+    @property
+    def M(self):
+        return int(self.Kt.shape[0])
+
+    @property
+    def N(self):
+        return int(self.Kt.shape[1])
+
+    @property
+    def B(self):
+        return int(len(self.bstart) - 1)
+
+
+def whiten(K, G, sigma=None, cov=None):
+    """C^-1 = T^T T; returns K~ = T K, g~ = T g and y -> T^T y."""
+    if cov is None:
+        s = np.asarray(sigma, dtype=np.float64)
+        Kt = K / s[:, None]
+        gt = G / s
+        return Kt, gt, (lambda y: np.asarray(y) / s)
+    L = np.linalg.cholesky(np.asarray(cov, dtype=np.float64))   # C = L L^T, T = L^-1
+    Kt = np.linalg.solve(L, K)
+    gt = np.linalg.solve(L, G)
+    return Kt, gt, (lambda y: np.linalg.solve(L.T, np.asarray(y)))
+
+
+def householder_complete(Vd: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the complement of the (orthonormal) columns of Vd.
+
+    Householder reflections H_0..H_{k-1} triangularise Vd; the completion is
+    Q e_j, j = k..nb-1, with Q = H_0 H_1 ... H_{k-1}.
+    """
+    nb, k = Vd.shape
+    X = np.array(Vd, dtype=np.float64, copy=True)
+    refl = []
+    for j in range(k):
+        x = X[j:, j]
+        alpha = x[0]
+        norm = np.sqrt(np.dot(x, x))
+        beta = -norm if alpha >= 0.0 else norm
+        v = x.copy()
+        v[0] = alpha - beta
+        vv = np.dot(v, v)
+        if vv > 0.0:
+            X[j:, j:] -= np.outer(v, (2.0 / vv) * (v @ X[j:, j:]))
+        refl.append((v, vv))
+    Z = np.zeros((nb, nb - k))
+    for col in range(k, nb):
+        e = np.zeros(nb)
+        e[col] = 1.0
+        for j in reversed(range(k)):
+            v, vv = refl[j]
+            if vv > 0.0:
+                e[j:] -= v * (2.0 / vv * np.dot(v, e[j:]))
+        Z[:, col - k] = e
+    return Z
+
+
+def block_factors(Kb: np.ndarray, k_req: Optional[int]):
+    """SVD of one whitened block with the rank cut, sign rule and zero-mode completion."""
+    M, nb = Kb.shape
+    Uf, sv, Vt = np.linalg.svd(Kb, full_matrices=False)
+    r = min(M, nb)
+    sv = sv[:r]
+    thr = max(M, nb) * EPS * (sv[0] if r > 0 else 0.0)
+    rank = int(np.sum(sv > thr)) if r > 0 and sv[0] > 0 else 0
+    k = rank if k_req is None else min(int(k_req), rank)
+    Vd = Vt[:k, :].T.copy()
+    Ud = Uf[:, :k].copy()
+    w = np.arange(1, nb + 1, dtype=np.float64)
+    for i in range(k):
+        if np.dot(w, Vd[:, i]) < 0.0:
+            Vd[:, i] = -Vd[:, i]
+            Ud[:, i] = -Ud[:, i]
+    Z = householder_complete(Vd)
+    V = np.concatenate([Vd, Z], axis=1)
+    return sv[:k].copy(), Ud, V, sv.copy()
+
+
+def prepare(problem, k=None) -> Prepared:
+    """Whitening + block factors + start vector for one workloads.Problem."""
+    Kt, gt, Tt = whiten(problem.K, problem.G, problem.sigma, problem.cov)
+    bs = np.asarray(problem.block_start, dtype=np.int64)
+    kreq = k if k is not None else problem.k
+    ds, Us, Vs, dall = [], [], [], []
+    kb = []
+    for b in range(len(bs) - 1):
+        Kb = Kt[:, bs[b]:bs[b + 1]]
+        kr = None if kreq is None else int(np.asarray(kreq)[b])
+        d, U, V, sv = block_factors(Kb, kr)
+        ds.append(d); Us.append(U); Vs.append(V); dall.append(sv)
+        kb.append(len(d))
+    one = Kt @ np.ones(Kt.shape[1])
+    cstar = float(np.dot(one, gt) / np.dot(one, one))
+    if not (cstar > 0.0 and np.isfinite(cstar)):
+        cstar = 1.0
+    init = np.full(Kt.shape[1], cstar)
+    return Prepared(Kt=np.ascontiguousarray(Kt), gt=np.ascontiguousarray(gt), bstart=bs,
+                    kb=np.asarray(kb, dtype=np.int32), d=ds, U=Us, V=Vs, dall=dall, Tt=Tt,
+                    init=init)
+
+
+# --------------------------------------------------------------------------------------
+# running the chains
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    mean: np.ndarray
+    stderr: np.ndarray
+    post_sd: np.ndarray
+    ess: np.ndarray
+    group_means: np.ndarray
+    final_A: np.ndarray
+    final_r: np.ndarray
+    final_chi2: np.ndarray
+    traj_A: Optional[np.ndarray]
+    traj_chi2: Optional[np.ndarray]
+    drift_max: float
+    n_frozen: int
+    n_clamped: int
+    status: int
+    cov_rA: Optional[np.ndarray]   # M x N sample Cov(r~, A)
+    mean_r: Optional[np.ndarray]
+    prep: Prepared
+
+
+def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index=0,
+        refresh_every=64, groups=32, want_cross=False, threads=None, traj_chain=-1,
+        init=None) -> Result:
+    L = lib()
+    M, N, B = prep.M, prep.N, prep.B
+    if threads is None:
+        threads = os.cpu_count() or 1
+    d_all = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x in prep.d]) if sum(prep.kb) else np.zeros(1))
+    U_all = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float64).ravel() for u in prep.U]) if sum(prep.kb) else np.zeros(1))
+    V_all = np.ascontiguousarray(np.concatenate([np.asarray(v, np.float64).ravel() for v in prep.V]))
+    bstart = np.ascontiguousarray(prep.bstart, dtype=np.int64)
+    kb = np.ascontiguousarray(prep.kb, dtype=np.int32)
+    start = np.ascontiguousarray(prep.init if init is None else np.asarray(init, np.float64))
+    G = int(groups)
+    total = burnin + sweeps
+    bufs = dict(
+        sumA=np.zeros(G * N), sumA2=np.zeros(G * N), count=np.zeros(G, np.int64),
+        sumR=np.zeros(M) if want_cross else None, sumRA=np.zeros(M * N) if want_cross else None,
+        final_A=np.zeros(chains * N), final_r=np.zeros(chains * M), final_chi2=np.zeros(chains),
+        traj_A=np.zeros(total * N) if traj_chain >= 0 else None,
+        traj_chi2=np.zeros(total) if traj_chain >= 0 else None,
+        drift_max=np.zeros(1), n_frozen=np.zeros(1, np.int64), n_clamped=np.zeros(1, np.int64),
+        status=np.zeros(1, np.int32))
+    p = _Problem(M=M, N=N, B=B, Kt=prep.Kt.ctypes.data, gt=prep.gt.ctypes.data,
+                 bstart=bstart.ctypes.data, kb=kb.ctypes.data, d=d_all.ctypes.data,
+                 U=U_all.ctypes.data, V=V_all.ctypes.data)
+    o = _Options(chains=chains, burnin=burnin, sweeps=sweeps, seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
+                 problem_index=problem_index, refresh_every=refresh_every, groups=G,
+                 want_cross=1 if want_cross else 0, threads=int(threads), traj_chain=traj_chain,
+                 init=start.ctypes.data)
+    out = _Out(**{k: (v.ctypes.data if v is not None else None) for k, v in bufs.items()})
+    L.orc_run(ctypes.byref(p), ctypes.byref(o), ctypes.byref(out))
+    sumA = bufs["sumA"].reshape(G, N)
+    sumA2 = bufs["sumA2"].reshape(G, N)
+    cnt = bufs["count"].astype(np.float64)
+    tot = float(cnt.sum())
+    mean = sumA.sum(0) / tot if tot > 0 else np.zeros(N)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        gm = sumA / cnt[:, None]
+    ok = cnt > 0
+    if ok.sum() >= 2:
+        se = np.std(gm[ok], axis=0, ddof=1) / np.sqrt(ok.sum())
+    else:
+        se = np.full(N, np.nan)
+    var = np.maximum(sumA2.sum(0) / tot - mean * mean, 0.0) if tot > 0 else np.zeros(N)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ess = var / (se * se)
+    cov_rA = mean_r = None
+    if want_cross and tot > 0:
+        mean_r = bufs["sumR"] / tot
+        cov_rA = bufs["sumRA"].reshape(M, N) / tot - np.outer(mean_r, mean)
+    return Result(mean=mean, stderr=se, post_sd=np.sqrt(var), ess=ess, group_means=gm,
+                  final_A=bufs["final_A"].reshape(chains, N),
+                  final_r=bufs["final_r"].reshape(chains, M), final_chi2=bufs["final_chi2"],
+                  traj_A=None if bufs["traj_A"] is None else bufs["traj_A"].reshape(total, N),
+                  traj_chi2=bufs["traj_chi2"], drift_max=float(bufs["drift_max"][0]),
+                  n_frozen=int(bufs["n_frozen"][0]), n_clamped=int(bufs["n_clamped"][0]),
+                  status=int(bufs["status"][0]), cov_rA=cov_rA, mean_r=mean_r, prep=prep)
+
+
+def vjp(res: Result, v: np.ndarray) -> np.ndarray:
+    """J^T v with J = d<A>/dg = -Cov(A, r~) T, i.e. J^T v = -T^T (Cov(r~, A) v)."""
+    if res.cov_rA is None:
+        raise ValueError("run(..., want_cross=True) is required for the VJP")
+    return -res.prep.Tt(res.cov_rA @ np.asarray(v, dtype=np.float64))

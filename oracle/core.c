@@ -1,0 +1,483 @@
+/*
+ * Plain FP64 CPU oracle for blocked modes sampling (Ghanem & Koch, arXiv:1912.01379).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference the
+ * GPU library is checked against.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code with the GPU library.
+ *
+ * What it computes (the paper's notation):
+ *   - whitened problem chi^2(f) = ||g~ - K~ f||^2 (Sec. III, whitening after Eq. (chi2));
+ *   - per-block SVD factors K~_b = U_b D_b V_b^T are inputs (computed by the Python
+ *     driver with LAPACK);
+ *   - a random walk over f >= 0 that updates one blocked mode e_i at a time (Sec. IV.B
+ *     "Modes Sampling", Sec. IV.C "Blocked Modes Sampling"): for d_i > 0 the new value
+ *     is drawn from a Gaussian of width 1/d_i centred on the best fit, for d_i = 0 from
+ *     a flat distribution, both truncated to the interval of Eq. (modeLimits);
+ *   - the estimate of Eq. (MCint) as the average of f over the post-burn-in samples.
+ *
+ * Readings where the paper is silent (each stated once more in the design notes):
+ *   - the truncated Gaussian is drawn by inversion of its distribution function with
+ *     one uniform number per move, not by rejection;
+ *   - uniform numbers come from Philox4x32-10 (Salmon et al., SC'11) on the counter
+ *     (chain, sweep, block<<16 | mode, 0) with key (seed_lo, seed_hi ^ problem);
+ *   - components that round below zero after a move are set to +0;
+ *   - modes of a block are visited in the order given (data modes by descending
+ *     singular value, then the zero modes), blocks in increasing order;
+ *   - the residual is recomputed from scratch every `refresh_every` sweeps.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EUNBOUNDED (-4)
+
+/* ------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as      */
+/* 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications with the key added      */
+/* into the high halves and a Weyl-sequence key schedule.                               */
+/* ------------------------------------------------------------------------------------ */
+static void philox4x32_10(const uint32_t in[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = in[0], x1 = in[1], x2 = in[2], x3 = in[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform on the open interval (0,1): 52 random bits plus one half, times 2^-52. */
+static double u01_from_words(uint32_t w0, uint32_t w1) {
+    uint64_t j = ((uint64_t)(w0 >> 6) << 26) | (uint64_t)(w1 >> 6);
+    return ((double)j + 0.5) * 0x1.0p-52;
+}
+
+static double move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
+                           int64_t block, int64_t mode) {
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu),
+                       (uint32_t)(seed >> 32) ^ (uint32_t)problem};
+    uint32_t ctr[4] = {(uint32_t)chain, (uint32_t)sweep,
+                       ((uint32_t)block << 16) | (uint32_t)mode, 0u};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    return u01_from_words(w[0], w[1]);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* One-dimensional truncated standard normal, by inversion.                             */
+/*                                                                                      */
+/* Everything is reduced to one problem: draw t in [0, w] from the density proportional */
+/* to p(t) = exp(-a t - t^2/2) with a >= 0.  Its unnormalised distribution function is  */
+/*     E(a, t) = int_0^t exp(-a s - s^2/2) ds                                           */
+/*             = m(a) - m(a + t) exp(-t (a + t/2)),  m(x) = Q(x)/phi(x) (Mills ratio).  */
+/* For small t the difference cancels, so a power series in t is used there:           */
+/*     E(a, t) = sum_j (-1/2)^j / j! * t^(2j+1) * M_2j(a t),                            */
+/*     M_k(z)  = int_0^1 v^k exp(-z v) dv.                                              */
+/* ------------------------------------------------------------------------------------ */
+static const double SQRT_HALF_PI = 1.2533141373155002512;  /* sqrt(pi/2) */
+
+/* Mills ratio Q(x)/phi(x) for x >= 0. */
+static double mills(double x) {
+    if (x < 5.0) {
+        /* erfc(x/sqrt2) * sqrt(pi/2) * exp(x^2/2); x^2 split exactly into hi + lo. */
+        double hi = x * x;
+        double lo = fma(x, x, -hi);
+        return SQRT_HALF_PI * erfc(x * 0.70710678118654752440) * exp(0.5 * hi) * exp(0.5 * lo);
+    }
+    /* Laplace continued fraction m(x) = 1/(x + 1/(x + 2/(x + 3/(x + ...)))),
+       evaluated from a deep tail backwards. */
+    double f = x;
+    for (int k = 400; k >= 1; --k) f = x + (double)k / f;
+    return 1.0 / f;
+}
+
+/* M_k(z) = int_0^1 v^k e^{-z v} dv, z >= 0. */
+static double Mk(int k, double z) {
+    if (k == 0) {
+        if (z == 0.0) return 1.0;
+        return -expm1(-z) / z;
+    }
+    if (z <= 50.0) {
+        /* gamma(k+1, z)/z^(k+1) = e^{-z} sum_j z^j / ((k+1)(k+2)...(k+1+j)) */
+        double term = 1.0 / (double)(k + 1);
+        double sum = term;
+        for (int j = 1; j < 400; ++j) {
+            term *= z / (double)(k + 1 + j);
+            sum += term;
+            if (term < 1e-18 * sum) break;
+        }
+        return exp(-z) * sum;
+    }
+    /* k!/z^(k+1) * (1 - e^{-z} sum_{j<=k} z^j/j!) */
+    double fact = 1.0, poly = 1.0, zj = 1.0;
+    for (int j = 1; j <= k; ++j) {
+        fact *= (double)j;
+        zj *= z / (double)j;
+        poly += zj;
+    }
+    double zk1 = pow(z, (double)(k + 1));
+    return fact / zk1 * (1.0 - exp(-z) * poly);
+}
+
+#define TSERIES 0.25
+
+double orc_E(double a, double t) {
+    if (t <= 0.0) return 0.0;
+    if (isinf(t)) return mills(a);
+    if (t <= TSERIES) {
+        double z = a * t;
+        double coef = t, sum = 0.0;
+        for (int j = 0; j < 10; ++j) {
+            sum += coef * Mk(2 * j, z);
+            coef *= -(t * t) / (2.0 * (double)(j + 1));
+        }
+        return sum;
+    }
+    return mills(a) - mills(a + t) * exp(-t * (a + 0.5 * t));
+}
+
+/* Draw t in [0, w] with density prop. to exp(-a t - t^2/2), a >= 0, by inversion at u;
+   uc = 1 - u is passed separately so that the caller can supply it without rounding.
+   For u <= 1/2 it solves E(a,t) = u E(a,w); otherwise it solves the upper tail
+   log T(t) = log(uc E(a,w)) with T(t) = int_t^w p = exp(-t(a+t/2)) E(a+t, w-t),
+   which keeps full relative accuracy near the far end.  Newton steps, kept inside a
+   bracket by bisection. */
+double orc_S(double a, double w, double u, double uc) {
+    double Ew = orc_E(a, w);
+    double tl = 0.0;
+    double th;
+    if (u <= 0.5) {
+        th = (w < 1.0) ? w : 1.0;  /* the median of the a=0 half-normal is 0.674 */
+        double target = u * Ew;
+        double t = 0.5 * (tl + th);
+        if (a > 0.0) {
+            /* start from the exponential-tilt solution */
+            double ts = -log1p(u * expm1(-a * w)) / a;
+            if (ts > tl && ts < th) t = ts;
+        } else if (w < 1.0) {
+            t = u * w;
+        }
+        for (int it = 0; it < 200; ++it) {
+            double f = orc_E(a, t) - target;
+            if (f < 0.0) tl = t; else th = t;
+            double fp = exp(-t * (a + 0.5 * t));
+            double tn = t - f / fp;
+            if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+            double dt = fabs(tn - t);
+            t = tn;
+            if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
+        }
+        return t;
+    } else {
+        th = (w < 40.0) ? w : 40.0;
+        double Lstar = log(uc) + log(Ew);
+        double t = 0.5 * (tl + th);
+        if (a > 0.0) {
+            double ts = -log1p(u * expm1(-a * w)) / a;
+            if (ts > tl && ts < th) t = ts;
+        } else if (w < 1.0) {
+            t = u * w;
+        }
+        for (int it = 0; it < 200; ++it) {
+            double tail = orc_E(a + t, w - t);
+            double h = -t * (a + 0.5 * t) + log(tail) - Lstar;  /* decreasing in t */
+            if (h > 0.0) tl = t; else th = t;
+            double tn = t + h * tail;
+            if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+            double dt = fabs(tn - t);
+            t = tn;
+            if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
+        }
+        return t;
+    }
+}
+
+/* Draw delta from N(c/d, 1/d^2) truncated to [lo, hi] (lo <= 0 <= hi, d > 0) at u.
+   Standardised x = d*delta - c lies in [a, b] with a = d*lo - c, b = d*hi - c. */
+double orc_tn_draw(double c, double d, double lo, double hi, double u) {
+    if (lo == hi) return lo;
+    double a = d * lo - c;
+    double b = d * hi - c;
+    double w = d * (hi - lo);
+    double delta;
+    const double uc = 1.0 - u;   /* exact: u is a multiple of 2^-53 in (0,1) */
+    if (a >= 0.0) {
+        double t = orc_S(a, w, u, uc);
+        delta = lo + t / d;
+    } else if (b <= 0.0) {
+        /* mirror x -> -x: the lower end becomes the far end */
+        double t = orc_S(-b, w, uc, u);
+        delta = hi - t / d;
+    } else {
+        /* two one-sided halves [a,0] and [0,b] with masses E(0,-a) and E(0,b) */
+        double pL = orc_E(0.0, -a);
+        double pR = orc_E(0.0, b);
+        double tot = pL + pR;
+        double q = u * tot;
+        if (q < pL) {
+            double t = orc_S(0.0, -a, (pL - q) / pL, q / pL);
+            delta = (c - t) / d;
+        } else {
+            double t = orc_S(0.0, b, (q - pL) / pR, (uc * tot) / pR);
+            delta = (c + t) / d;
+        }
+    }
+    if (delta < lo) delta = lo;
+    if (delta > hi) delta = hi;
+    return delta;
+}
+
+double orc_mills(double x) { return mills(x); }
+double orc_Mk(int k, double z) { return Mk(k, z); }
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    philox4x32_10(ctr, key, out);
+}
+double orc_move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
+                        int64_t block, int64_t mode) {
+    return move_uniform(seed, problem, chain, sweep, block, mode);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* The sampler.                                                                         */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    int64_t M, N, B;
+    const double *Kt;       /* M x N whitened kernel, row-major                          */
+    const double *gt;       /* M whitened data                                           */
+    const int64_t *bstart;  /* B+1 block offsets                                         */
+    const int32_t *kb;      /* data modes per block                                      */
+    const double *d;        /* concatenated data singular values (sum kb)                */
+    const double *U;        /* concatenated U_b, each M x kb row-major                   */
+    const double *V;        /* concatenated V_b, each Nb x Nb row-major, column = mode   */
+} orc_problem;
+
+typedef struct {
+    int64_t chains, burnin, sweeps;
+    uint64_t seed;
+    int64_t problem_index;
+    int64_t refresh_every;
+    int64_t groups;
+    int64_t want_cross;
+    int64_t threads;
+    int64_t traj_chain;     /* chain whose A is recorded after every sweep, or -1        */
+    const double *init;     /* N start vector (shared by all chains), >= 0               */
+} orc_options;
+
+typedef struct {
+    double *sumA;        /* groups x N                                                  */
+    double *sumA2;       /* groups x N                                                  */
+    int64_t *count;      /* groups                                                      */
+    double *sumR;        /* M              (want_cross)                                 */
+    double *sumRA;       /* M x N          (want_cross)                                 */
+    double *final_A;     /* chains x N                                                  */
+    double *final_r;     /* chains x M                                                  */
+    double *final_chi2;  /* chains                                                      */
+    double *traj_A;      /* (burnin+sweeps) x N, or NULL                                */
+    double *traj_chi2;   /* (burnin+sweeps), or NULL                                    */
+    double *drift_max;   /* 1                                                           */
+    int64_t *n_frozen;   /* 1                                                           */
+    int64_t *n_clamped;  /* 1                                                           */
+    int32_t *status;     /* 1                                                           */
+} orc_out;
+
+typedef struct {
+    const orc_problem *p;
+    const orc_options *o;
+    orc_out *out;
+    int64_t c0, c1;
+    /* per-thread accumulators */
+    double *sumA, *sumA2, *sumR, *sumRA;
+    int64_t *count;
+    double drift;
+    int64_t frozen, clamped;
+    int32_t status;
+} worker;
+
+static void refresh(const orc_problem *p, const double *A, double *r, double *chi2) {
+    double s = 0.0;
+    for (int64_t m = 0; m < p->M; ++m) {
+        double acc = p->gt[m];
+        const double *row = p->Kt + m * p->N;
+        for (int64_t n = 0; n < p->N; ++n) acc -= row[n] * A[n];
+        r[m] = acc;
+        s += acc * acc;
+    }
+    *chi2 = s;
+}
+
+static void *run_chains(void *arg) {
+    worker *wk = (worker *)arg;
+    const orc_problem *p = wk->p;
+    const orc_options *o = wk->o;
+    const int64_t M = p->M, N = p->N, B = p->B;
+    const int64_t total = o->burnin + o->sweeps;
+    double *A = (double *)malloc(sizeof(double) * N);
+    double *r = (double *)malloc(sizeof(double) * M);
+
+    /* offsets of each block's factors */
+    int64_t *offd = (int64_t *)malloc(sizeof(int64_t) * (B + 1));
+    int64_t *offU = (int64_t *)malloc(sizeof(int64_t) * (B + 1));
+    int64_t *offV = (int64_t *)malloc(sizeof(int64_t) * (B + 1));
+    offd[0] = offU[0] = offV[0] = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        int64_t nb = p->bstart[b + 1] - p->bstart[b];
+        offd[b + 1] = offd[b] + p->kb[b];
+        offU[b + 1] = offU[b] + M * p->kb[b];
+        offV[b + 1] = offV[b] + nb * nb;
+    }
+
+    for (int64_t c = wk->c0; c < wk->c1; ++c) {
+        for (int64_t n = 0; n < N; ++n) A[n] = o->init[n];
+        double chi2;
+        refresh(p, A, r, &chi2);
+        for (int64_t s = 0; s < total; ++s) {
+            for (int64_t b = 0; b < B; ++b) {
+                const int64_t n0 = p->bstart[b], nb = p->bstart[b + 1] - n0;
+                const int64_t kb = p->kb[b];
+                const double *Vb = p->V + offV[b];
+                const double *Ub = p->U + offU[b];
+                const double *db = p->d + offd[b];
+                for (int64_t i = 0; i < nb; ++i) {
+                    /* Eq. (modeLimits): f + delta V_i >= 0 */
+                    double lo = -INFINITY, hi = INFINITY;
+                    for (int64_t q = 0; q < nb; ++q) {
+                        double v = Vb[q * nb + i];
+                        if (v > 0.0) {
+                            double t = -A[n0 + q] / v;
+                            if (t > lo) lo = t;
+                        } else if (v < 0.0) {
+                            double t = -A[n0 + q] / v;
+                            if (t < hi) hi = t;
+                        }
+                    }
+                    double u = move_uniform(o->seed, o->problem_index, c, s, b, i);
+                    double delta, cdot = 0.0, dd = 0.0;
+                    if (i < kb) {
+                        dd = db[i];
+                        for (int64_t m = 0; m < M; ++m) cdot += Ub[m * kb + i] * r[m];
+                        delta = orc_tn_draw(cdot, dd, lo, hi, u);
+                    } else {
+                        if (isinf(lo) || isinf(hi)) {
+                            wk->status = ORC_EUNBOUNDED;
+                            delta = 0.0;
+                        } else {
+                            delta = lo + u * (hi - lo);
+                        }
+                    }
+                    if (lo == hi) wk->frozen++;
+                    for (int64_t q = 0; q < nb; ++q) {
+                        double an = A[n0 + q] + delta * Vb[q * nb + i];
+                        if (an < 0.0) {
+                            an = 0.0;
+                            wk->clamped++;
+                        }
+                        A[n0 + q] = an;
+                    }
+                    if (i < kb) {
+                        double e = delta * dd;
+                        for (int64_t m = 0; m < M; ++m) r[m] -= e * Ub[m * kb + i];
+                        chi2 += e * (e - 2.0 * cdot);
+                    }
+                }
+            }
+            if (o->refresh_every > 0 && (s + 1) % o->refresh_every == 0) {
+                double chi2_ref;
+                refresh(p, A, r, &chi2_ref);
+                double dr = fabs(chi2 - chi2_ref) / (chi2_ref > 0.0 ? chi2_ref : 1.0);
+                if (dr > wk->drift) wk->drift = dr;
+                chi2 = chi2_ref;
+            }
+            if (c == o->traj_chain && wk->out->traj_A) {
+                memcpy(wk->out->traj_A + s * N, A, sizeof(double) * N);
+                if (wk->out->traj_chi2) wk->out->traj_chi2[s] = chi2;
+            }
+            if (s >= o->burnin) {
+                int64_t g;
+                if (o->chains >= o->groups)
+                    g = c * o->groups / o->chains;
+                else
+                    g = (s - o->burnin) * o->groups / o->sweeps;
+                double *sa = wk->sumA + g * N, *sa2 = wk->sumA2 + g * N;
+                for (int64_t n = 0; n < N; ++n) {
+                    sa[n] += A[n];
+                    sa2[n] += A[n] * A[n];
+                }
+                wk->count[g]++;
+                if (o->want_cross) {
+                    for (int64_t m = 0; m < M; ++m) {
+                        wk->sumR[m] += r[m];
+                        double *row = wk->sumRA + m * N;
+                        for (int64_t n = 0; n < N; ++n) row[n] += r[m] * A[n];
+                    }
+                }
+            }
+        }
+        memcpy(wk->out->final_A + c * N, A, sizeof(double) * N);
+        memcpy(wk->out->final_r + c * M, r, sizeof(double) * M);
+        wk->out->final_chi2[c] = chi2;
+    }
+    free(A); free(r); free(offd); free(offU); free(offV);
+    return NULL;
+}
+
+int orc_run(const orc_problem *p, const orc_options *o, orc_out *out) {
+    int64_t nt = o->threads > 0 ? o->threads : 1;
+    if (nt > o->chains) nt = o->chains;
+    const int64_t N = p->N, M = p->M, G = o->groups;
+    worker *wk = (worker *)calloc((size_t)nt, sizeof(worker));
+    pthread_t *th = (pthread_t *)calloc((size_t)nt, sizeof(pthread_t));
+    for (int64_t t = 0; t < nt; ++t) {
+        wk[t].p = p; wk[t].o = o; wk[t].out = out;
+        wk[t].c0 = o->chains * t / nt;
+        wk[t].c1 = o->chains * (t + 1) / nt;
+        wk[t].sumA = (double *)calloc((size_t)(G * N), sizeof(double));
+        wk[t].sumA2 = (double *)calloc((size_t)(G * N), sizeof(double));
+        wk[t].count = (int64_t *)calloc((size_t)G, sizeof(int64_t));
+        if (o->want_cross) {
+            wk[t].sumR = (double *)calloc((size_t)M, sizeof(double));
+            wk[t].sumRA = (double *)calloc((size_t)(M * N), sizeof(double));
+        }
+        pthread_create(&th[t], NULL, run_chains, &wk[t]);
+    }
+    int32_t status = ORC_OK;
+    double drift = 0.0;
+    int64_t frozen = 0, clamped = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        pthread_join(th[t], NULL);
+        for (int64_t i = 0; i < G * N; ++i) {
+            out->sumA[i] += wk[t].sumA[i];
+            out->sumA2[i] += wk[t].sumA2[i];
+        }
+        for (int64_t g = 0; g < G; ++g) out->count[g] += wk[t].count[g];
+        if (o->want_cross) {
+            for (int64_t m = 0; m < M; ++m) out->sumR[m] += wk[t].sumR[m];
+            for (int64_t i = 0; i < M * N; ++i) out->sumRA[i] += wk[t].sumRA[i];
+            free(wk[t].sumR); free(wk[t].sumRA);
+        }
+        if (wk[t].status != ORC_OK) status = wk[t].status;
+        if (wk[t].drift > drift) drift = wk[t].drift;
+        frozen += wk[t].frozen;
+        clamped += wk[t].clamped;
+        free(wk[t].sumA); free(wk[t].sumA2); free(wk[t].count);
+    }
+    *out->drift_max = drift;
+    *out->n_frozen = frozen;
+    *out->n_clamped = clamped;
+    *out->status = status;
+    free(wk); free(th);
+    return status;
+}

@@ -1,0 +1,471 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test fixes a part of the oracle with a result the paper or the mathematics
+determines independently: closed forms, quadrature, a library routine that implements
+the same special function, or an independent re-derivation of a step in another basis.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+import workloads
+
+
+# --------------------------------------------------------------------------------------
+# special functions and the truncated normal
+# --------------------------------------------------------------------------------------
+
+def test_mills_ratio_matches_scipy_erfcx(orc):
+    # m(x) = Q(x)/phi(x) = sqrt(pi/2) erfcx(x/sqrt 2): two independent implementations
+    for x in [0.0, 1e-8, 0.3, 1.0, 2.5, 4.999, 5.0, 5.001, 7.0, 12.0, 30.0, 100.0, 1e4]:
+        ref = math.sqrt(math.pi / 2) * special.erfcx(x / math.sqrt(2.0))
+        assert abs(orc.mills(x) / ref - 1.0) < 5e-15, x
+
+
+def test_Mk_matches_quadrature(orc):
+    for k in [0, 2, 4, 10, 18]:
+        for z in [0.0, 1e-6, 0.5, 3.0, 20.0, 49.9, 50.1, 300.0]:
+            ref = integrate.quad(lambda v: v ** k * math.exp(-z * v), 0.0, 1.0,
+                                 epsabs=0, epsrel=1e-13, limit=200)[0]
+            assert abs(orc.Mk(k, z) / ref - 1.0) < 1e-12, (k, z)
+
+
+@pytest.mark.parametrize("a,t", [(0, 1e-9), (0, 0.1), (0, 0.25), (0, 0.2500001), (0, 3.0),
+                                 (2.0, 0.2), (2.0, 1.0), (50.0, 0.2), (3e3, 0.01), (1e-3, 1e-6),
+                                 (0.7, np.inf), (40.0, np.inf)])
+def test_E_matches_quadrature(orc, a, t):
+    f = lambda s: math.exp(-a * s - 0.5 * s * s)
+    ref = integrate.quad(f, 0.0, t, epsabs=0, epsrel=1e-13, limit=400)[0]
+    assert abs(orc.E(a, t) / ref - 1.0) < 2e-14
+
+
+def _trunc_cdf(x, c, d, lo, hi):
+    """Distribution function and density of N(c/d, 1/d^2) on [lo, hi], via log_ndtr."""
+    a, b, z = d * lo - c, d * hi - c, d * x - c
+    if a >= 0 or (b > 0 and -a < b):   # work with upper tails
+        la, lb, lz = special.log_ndtr(-a), special.log_ndtr(-b), special.log_ndtr(-z)
+        num = -np.expm1(lz - la)
+        den = -np.expm1(lb - la)
+    else:
+        la, lb, lz = special.log_ndtr(a), special.log_ndtr(b), special.log_ndtr(z)
+        num = -np.expm1(la - lz) * np.exp(lz - lb)
+        den = -np.expm1(la - lb)
+        la = lb
+    dens = d * np.exp(stats.norm.logpdf(z) - la) / den
+    return num / den, dens
+
+
+CASES = [(0.0, 1.0, -1.0, 2.0), (5.0, 2.0, -3.0, 0.5), (-40.0, 1.0, 0.0, np.inf),
+         (40.0, 1.0, -np.inf, 0.0), (1.0, 1e3, -0.01, 0.02), (0.0, 3.0, -np.inf, 1.0),
+         (2.0, 1.0, 0.0, np.inf), (-20.0, 1.0, -1.0, 0.0), (0.4, 0.5, -0.2, 0.1),
+         (12.0, 4.0, -1.0, 5.0)]
+
+
+@pytest.mark.parametrize("c,d,lo,hi", CASES)
+def test_tn_inverse_cdf(orc, c, d, lo, hi):
+    """The draw at u has distribution-function value u (checked with scipy's log_ndtr)."""
+    for k in [1, 3, 1000, 2 ** 30, 2 ** 51, 2 ** 52 - 1000, 2 ** 53 - 3]:
+        u = k * 2.0 ** -53
+        x = orc.tn_draw(c, d, lo, hi, u)
+        assert lo <= x <= hi
+        F, dens = _trunc_cdf(x, c, d, lo, hi)
+        # the error allowed is relative to the smaller tail, plus what rounding x to a
+        # double can move F by (density times a few ulps of x)
+        # the checker itself only resolves z = d x - c to a few ulps of c, d lo and d hi
+        ends = [abs(d * e) for e in (lo, hi) if np.isfinite(e)]
+        res = np.spacing(abs(x) + 1e-300) + (np.spacing(abs(c)) + sum(np.spacing(e) for e in ends)) / d
+        tol = 1e-9 * min(u, 1.0 - u) + 8.0 * dens * res
+        assert abs(F - u) <= tol, (u, x, F, tol)
+
+
+@pytest.mark.parametrize("a,w", [(0.0, np.inf), (0.0, 0.01), (3.0, 2.0), (40.0, np.inf),
+                                 (40.0, 1e-3), (1e4, 1.0), (0.5, 1e-12), (7.0, 0.3)])
+def test_S_inverts_E(orc, a, w):
+    """The one-sided draw t solves E(a, t) = u E(a, w) (E itself is pinned by quadrature)."""
+    Ew = orc.E(a, w)
+    for k in [1, 7, 2 ** 20, 2 ** 45, 2 ** 52 - 1, 2 ** 52 + 1, 2 ** 53 - 2 ** 20, 2 ** 53 - 1]:
+        u = k * 2.0 ** -53
+        t = orc.S(a, w, u)
+        assert 0.0 <= t <= w
+        if u <= 0.5:
+            assert abs(orc.E(a, t) / Ew - u) <= 1e-13 * u + 4 * np.spacing(t) / Ew
+        else:
+            tail = math.exp(-t * (a + 0.5 * t)) * orc.E(a + t, w - t) if t < w else 0.0
+            p_t = math.exp(-t * (a + 0.5 * t))
+            assert abs(tail / Ew - (1.0 - u)) <= 1e-12 * (1.0 - u) + 8 * np.spacing(t) * p_t / Ew
+
+
+def test_tn_narrow_interval_is_tilted_uniform(orc):
+    """d -> 0: the Gaussian is almost flat over [lo, hi]; the exact density is exp(-(d x - c)^2/2)."""
+    c, d, lo, hi = 0.3, 1e-9, -2.0, 3.0
+    for u in [1e-6, 0.25, 0.5, 0.9]:
+        x = orc.tn_draw(c, d, lo, hi, u)
+        # density ~ exp(c d x) (linear tilt); CDF of the tilt:
+        lam = c * d
+        ref = lo + math.log1p(u * math.expm1(lam * (hi - lo))) / lam
+        assert abs(x - ref) < 1e-12 * (hi - lo)
+
+
+@pytest.mark.parametrize("c,d,lo,hi", CASES[:8])
+def test_tn_mean_by_quantile_integration(orc, c, d, lo, hi):
+    """Integral of the quantile function over u equals the closed-form truncated mean."""
+    n = 4001
+    us = (np.arange(n) + 0.5) / n
+    xs = np.array([orc.tn_draw(c, d, lo, hi, float(u)) for u in us])
+    mu, tau = c / d, 1.0 / d
+    ref = stats.truncnorm.mean((lo - mu) / tau, (hi - mu) / tau, loc=mu, scale=tau)
+    spread = stats.truncnorm.std((lo - mu) / tau, (hi - mu) / tau, loc=mu, scale=tau)
+    assert abs(xs.mean() - ref) < 2e-3 * spread + 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------------------
+
+def test_uniforms_open_interval_and_uniform(orc):
+    us = np.array([orc.move_uniform(99, 0, c, s, b, i)
+                   for c in range(4) for s in range(25) for b in range(4) for i in range(25)])
+    assert np.all(us > 0) and np.all(us < 1)
+    # (2J+1) 2^-53 exactly
+    k = us * 2.0 ** 53
+    assert np.all(k == np.round(k)) and np.all(np.round(k) % 2 == 1)
+    hist, _ = np.histogram(us, bins=50, range=(0, 1))
+    chi2 = float(((hist - len(us) / 50) ** 2 / (len(us) / 50)).sum())
+    assert stats.chi2.sf(chi2, 49) > 1e-4
+    assert abs(np.corrcoef(us[:-1], us[1:])[0, 1]) < 0.05
+    assert len(np.unique(us)) == len(us)
+
+
+def test_philox_counter_sensitivity(orc):
+    base = orc.philox([1, 2, 3, 4], [5, 6])
+    for pos in range(4):
+        ctr = [1, 2, 3, 4]
+        ctr[pos] ^= 1
+        out = orc.philox(ctr, [5, 6])
+        # every output word changes, and about half of the 128 bits flip
+        flips = sum(bin(int(a) ^ int(b)).count("1") for a, b in zip(base, out))
+        assert 40 < flips < 88
+
+
+# --------------------------------------------------------------------------------------
+# problems with closed-form or quadrature answers
+# --------------------------------------------------------------------------------------
+
+def _problem(K, G, sigma, bstart, k=None):
+    M = K.shape[0]
+    return workloads.Problem(K=np.asarray(K, float), G=np.asarray(G, float),
+                             sigma=np.full(M, float(sigma)), block_start=np.asarray(bstart, np.int64),
+                             k=k)
+
+
+def _within(mc_mean, mc_se, ref, nsig=4.5, floor=1e-12):
+    z = np.abs(mc_mean - ref) / np.maximum(mc_se, floor)
+    return float(np.max(z))
+
+
+def test_one_point_grid_is_truncated_normal(orc):
+    """N = 1: <A> = mu + s phi(mu/s)/Phi(mu/s) (truncated normal mean)."""
+    rng = np.random.default_rng(3)
+    k = rng.uniform(0.5, 1.5, 7)
+    for mu_over_s in [3.0, 0.2, -2.0, -15.0]:
+        s = 1.0 / np.linalg.norm(k)
+        mu = mu_over_s * s
+        G = k * mu + 0.0
+        p = _problem(k[:, None], G, 1.0, [0, 1])
+        prep = orc.prepare(p)
+        res = orc.run(prep, chains=8, burnin=10, sweeps=20000, groups=16)
+        alpha = mu / s
+        ref = mu + s * math.exp(stats.norm.logpdf(alpha) - special.log_ndtr(alpha))
+        assert _within(res.mean, res.stderr, ref) < 4.5, (mu_over_s, res.mean, ref)
+
+
+def test_orthogonal_columns_factorise_including_tails(orc):
+    """K~ = Q diag(d): independent truncated normals, centres from -40 s to +40 s."""
+    rng = np.random.default_rng(5)
+    M, N = 12, 6
+    Q, _ = np.linalg.qr(rng.standard_normal((M, N)))
+    d = np.array([50.0, 20.0, 7.0, 3.0, 1.0, 0.3])
+    s = 1.0 / d
+    mu = np.array([-40.0, -6.0, -0.5, 0.0, 1.5, 40.0]) * s
+    K = Q * d[None, :]
+    G = Q @ (d * mu)
+    p = _problem(K, G, 1.0, [0, 3, 6])
+    prep = orc.prepare(p)
+    res = orc.run(prep, chains=8, burnin=10, sweeps=20000, groups=16)
+    alpha = mu / s
+    ref = mu + s * np.exp(stats.norm.logpdf(alpha) - special.log_ndtr(alpha))
+    assert _within(res.mean, res.stderr, ref) < 4.5
+
+
+def test_sum_rule_only_data_gives_flat_default(orc):
+    """K = 1^T, g = 1 (Eq. (def)): <A_n> = E[S]/N, S ~ S^(N-1) exp(-(S-1)^2/2s^2)."""
+    N, sig = 8, 0.3
+    ws = lambda S, p: S ** (N - 1 + p) * math.exp(-0.5 * ((S - 1.0) / sig) ** 2)
+    Z = integrate.quad(lambda S: ws(S, 0), 0, 10)[0]
+    ES = integrate.quad(lambda S: ws(S, 1), 0, 10)[0] / Z
+    ES2 = integrate.quad(lambda S: ws(S, 2), 0, 10)[0] / Z
+    EA = ES / N
+    EA2 = ES2 * 2.0 / (N * (N + 1))   # A_n/S ~ Beta(1, N-1)
+    for bstart in ([0, 8], [0, 4, 8]):
+        p = _problem(np.ones((1, N)), [1.0], sig, bstart)
+        prep = orc.prepare(p)
+        assert list(prep.kb) == [1] * (len(bstart) - 1)
+        res = orc.run(prep, chains=16, burnin=200, sweeps=20000, groups=16)
+        assert _within(res.mean, res.stderr, EA) < 4.5, (bstart, res.mean, EA)
+        assert np.allclose(res.post_sd, math.sqrt(EA2 - EA * EA), rtol=0.03)
+
+
+def _quad_mean_2d(K, G):
+    """<A> over A >= 0 for N = 2 by quadrature (inner integral in closed form)."""
+    k1, k2 = K[:, 0], K[:, 1]
+    n2 = k2 @ k2
+    s = 1.0 / math.sqrt(n2)
+
+    def parts(a1):
+        r1 = G - k1 * a1
+        m = (k2 @ r1) / n2
+        logz = -0.5 * (r1 @ r1 - n2 * m * m) + special.log_ndtr(m / s)
+        inner_mean = m + s * math.exp(stats.norm.logpdf(m / s) - special.log_ndtr(m / s))
+        return logz, inner_mean
+
+    grid = np.linspace(0, 5, 2001)
+    shift = max(parts(a)[0] for a in grid)
+    w = lambda a: math.exp(parts(a)[0] - shift)
+    Z = integrate.quad(w, 0, np.inf, limit=400, epsrel=1e-12)[0]
+    m1 = integrate.quad(lambda a: a * w(a), 0, np.inf, limit=400, epsrel=1e-12)[0] / Z
+    m2 = integrate.quad(lambda a: parts(a)[1] * w(a), 0, np.inf, limit=400, epsrel=1e-12)[0] / Z
+    return np.array([m1, m2])
+
+
+def test_two_point_grid_against_quadrature(orc):
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x = np.array([-1.0, 0.5])
+    K = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.05
+    G = K @ np.array([0.3, 0.02]) + sig * np.random.default_rng(8).standard_normal(11)
+    ref = _quad_mean_2d(K / sig, G / sig)
+    p = _problem(K, G, sig, [0, 2])
+    res = orc.run(orc.prepare(p), chains=16, burnin=100, sweeps=40000, groups=16)
+    assert _within(res.mean, res.stderr, ref) < 4.5, (res.mean, ref, res.stderr)
+    # two one-point blocks: components sampling, same average
+    p2 = _problem(K, G, sig, [0, 1, 2])
+    res2 = orc.run(orc.prepare(p2), chains=16, burnin=100, sweeps=40000, groups=16)
+    assert _within(res2.mean, res2.stderr, ref) < 4.5, (res2.mean, ref)
+
+
+def test_three_point_grid_against_quadrature(orc):
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x = np.array([-1.5, 0.0, 1.5])
+    K = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.05
+    G = K @ np.array([0.3, 0.05, 0.2]) + sig * np.random.default_rng(9).standard_normal(11)
+    Kt, gt = K / sig, G / sig
+    k3 = Kt[:, 2]
+    n3 = k3 @ k3
+    s3 = 1.0 / math.sqrt(n3)
+
+    def inner(a1, a2):
+        r = gt - Kt[:, 0] * a1 - Kt[:, 1] * a2
+        m = (k3 @ r) / n3
+        logz = -0.5 * (r @ r - n3 * m * m) + special.log_ndtr(m / s3)
+        mean3 = m + s3 * math.exp(stats.norm.logpdf(m / s3) - special.log_ndtr(m / s3))
+        return logz, mean3
+
+    # unconstrained optimum as a shift for the exponent
+    shift = max(inner(a, b)[0] for a in np.linspace(0, 2, 41) for b in np.linspace(0, 2, 41))
+    f = lambda b, a, p: (a if p == 1 else b if p == 2 else (inner(a, b)[1] if p == 3 else 1.0)) \
+        * math.exp(inner(a, b)[0] - shift)
+    up = 3.0
+    Z = integrate.dblquad(lambda b, a: f(b, a, 0), 0, up, 0, up, epsrel=1e-9)[0]
+    ref = np.array([integrate.dblquad(lambda b, a: f(b, a, p), 0, up, 0, up, epsrel=1e-9)[0] / Z
+                    for p in (1, 2, 3)])
+    p = _problem(K, G, sig, [0, 3])
+    res = orc.run(orc.prepare(p), chains=16, burnin=100, sweeps=40000, groups=16)
+    assert _within(res.mean, res.stderr, ref) < 4.5, (res.mean, ref, res.stderr)
+
+
+def test_gaussian_limit_mean_and_vjp(orc):
+    """Positivity inactive: <A> = (K~^T K~)^-1 K~^T g~, J = Cov K~^T T (closed forms)."""
+    p = workloads.gaussian_limit_problem()
+    prep = orc.prepare(p)
+    res = orc.run(prep, chains=32, burnin=20, sweeps=4000, groups=32, want_cross=True)
+    Kt, gt = prep.Kt, prep.gt
+    cov = np.linalg.inv(Kt.T @ Kt)
+    mean = cov @ Kt.T @ gt
+    assert _within(res.mean, res.stderr, mean) < 4.5
+    assert np.allclose(res.post_sd, np.sqrt(np.diag(cov)), rtol=0.02)
+    J = cov @ Kt.T / p.sigma[None, :]      # d<A>/dG = Cov K~^T T, T = diag(1/sigma)
+    v = np.array([1.0, -0.5, 0.25, 2.0])
+    ref = J.T @ v
+    got = orc.vjp(res, v)
+    assert np.linalg.norm(got - ref) < 0.03 * np.linalg.norm(ref)
+
+
+# --------------------------------------------------------------------------------------
+# invariants and structural limits
+# --------------------------------------------------------------------------------------
+
+def test_incremental_residual_matches_recomputed(orc):
+    p = workloads.small_problem(M=41, N=24, nblocks=2)
+    prep = orc.prepare(p)
+    res = orc.run(prep, chains=2, burnin=0, sweeps=1000, refresh_every=0, groups=2,
+                  traj_chain=0)
+    A = res.final_A[0]
+    r = prep.gt - prep.Kt @ A
+    assert np.linalg.norm(res.final_r[0] - r) <= 1e-10 * np.linalg.norm(r)
+    assert abs(res.final_chi2[0] - r @ r) <= 1e-10 * (r @ r)
+    assert np.all(res.traj_A >= 0.0)
+    chi2_traj = np.array([np.sum((prep.gt - prep.Kt @ a) ** 2) for a in res.traj_A])
+    assert np.max(np.abs(chi2_traj - res.traj_chi2) / chi2_traj) < 1e-10
+
+
+def _components_reference(Kt, gt, f0, seed, sweeps):
+    """Components sampling of Eq. (CompChi), written independently (scipy truncnorm)."""
+    import oracle as orc
+    f = f0.copy()
+    traj = []
+    for s in range(sweeps):
+        for n in range(len(f)):
+            kn = Kt[:, n]
+            r = gt - Kt @ f
+            nn = kn @ kn
+            mu = f[n] + (kn @ r) / nn
+            sd = 1.0 / math.sqrt(nn)
+            u = orc.move_uniform(seed, 0, 0, s, n, 0)
+            f[n] = stats.truncnorm.ppf(u, (0.0 - mu) / sd, np.inf, loc=mu, scale=sd)
+        traj.append(f.copy())
+    return np.array(traj)
+
+
+def test_one_point_blocks_are_components_sampling(orc):
+    beta = 10.0
+    tau = workloads.imaginary_times(9, beta)
+    x = np.array([-1.0, 0.0, 1.0, 2.0])
+    K = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.02
+    G = K @ np.array([0.2, 0.4, 0.1, 0.3]) + sig * np.random.default_rng(4).standard_normal(9)
+    p = _problem(K, G, sig, [0, 1, 2, 3, 4])
+    prep = orc.prepare(p)
+    res = orc.run(prep, chains=1, burnin=0, sweeps=20, refresh_every=0, groups=1, traj_chain=0,
+                  seed=77)
+    ref = _components_reference(prep.Kt, prep.gt, prep.init, 77, 20)
+    assert np.max(np.abs(res.traj_A - ref)) < 1e-8 * np.max(np.abs(ref))
+
+
+def test_single_block_is_modes_sampling_in_e_space(orc):
+    """Modes sampling of Sec. IV.B in the e = V^T f basis, written independently."""
+    rng = np.random.default_rng(21)
+    M, N = 5, 8
+    K = rng.standard_normal((M, N)) + 0.5
+    G = K @ rng.uniform(0.2, 1.0, N)
+    p = _problem(K, G, 0.5, [0, N])
+    prep = orc.prepare(p)
+    seed = 5
+    res = orc.run(prep, chains=1, burnin=0, sweeps=10, refresh_every=0, groups=1, traj_chain=0,
+                  seed=seed)
+    V = prep.V[0]
+    kb = int(prep.kb[0])
+    d = np.zeros(N)
+    d[:kb] = prep.d[0]
+    h = np.zeros(N)
+    h[:kb] = prep.U[0].T @ prep.gt
+    f = prep.init.copy()
+    traj = []
+    for s in range(10):
+        for i in range(N):
+            e = V.T @ f
+            Vi = V[:, i]
+            # Eq. (modeLimits): max{f/V | V<0} <= e_i - e_i' <= min{f/V | V>0}
+            lo_d = np.max(f[Vi < 0] / Vi[Vi < 0]) if np.any(Vi < 0) else -np.inf
+            hi_d = np.min(f[Vi > 0] / Vi[Vi > 0]) if np.any(Vi > 0) else np.inf
+            lo_e, hi_e = e[i] - hi_d, e[i] - lo_d
+            u = orc.move_uniform(seed, 0, 0, s, 0, i)
+            if d[i] > 0:
+                mu, sd = h[i] / d[i], 1.0 / d[i]
+                en = stats.truncnorm.ppf(u, (lo_e - mu) / sd, (hi_e - mu) / sd, loc=mu, scale=sd)
+            else:
+                en = lo_e + u * (hi_e - lo_e)
+            f = np.maximum(f + (en - e[i]) * Vi, 0.0)
+        traj.append(f.copy())
+    traj = np.array(traj)
+    assert np.max(np.abs(res.traj_A - traj)) < 1e-7 * np.max(np.abs(traj))
+
+
+def test_block_factors_are_an_orthonormal_svd(orc):
+    p = workloads.config2()
+    prep = orc.prepare(p)
+    for b in range(prep.B):
+        s0, s1 = prep.bstart[b], prep.bstart[b + 1]
+        Kb = prep.Kt[:, s0:s1]
+        V = prep.V[b]
+        kb = prep.kb[b]
+        assert 1 <= kb <= 20
+        assert np.allclose(V.T @ V, np.eye(V.shape[0]), atol=1e-12)
+        assert np.allclose(Kb @ V[:, :kb], prep.U[b] * prep.d[b][None, :],
+                           atol=1e-10 * prep.d[b][0])
+        # the completion spans the numerical null space
+        assert np.linalg.norm(Kb @ V[:, kb:]) < 1e-6 * prep.d[b][0]
+        w = np.arange(1, V.shape[0] + 1)
+        assert np.all(w @ V[:, :kb] > 0)
+
+
+def test_width_factor_invariance(orc):
+    """Eq. (Itrafo): sampling (K W, A) or (K, W A) gives <W A> = W <A>."""
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x, w = workloads.uniform_midpoint_grid(-3.0, 3.0, 6)
+    w = w * np.array([0.5, 1.0, 2.0, 1.5, 0.7, 1.2])
+    Kraw = workloads.fermionic_kernel(tau, x, beta)
+    A = workloads.gaussian_mixture(x, (1.0,), (0.0,), (1.0,))
+    sig = 0.02
+    G = Kraw @ (A * w) + sig * np.random.default_rng(12).standard_normal(11)
+    pa = _problem(Kraw * w[None, :], G, sig, [0, 3, 6])
+    pf = _problem(Kraw, G, sig, [0, 3, 6])
+    ra = orc.run(orc.prepare(pa), chains=32, burnin=200, sweeps=6000, groups=32)
+    rf = orc.run(orc.prepare(pf), chains=32, burnin=200, sweeps=6000, groups=32, seed=4321)
+    z = np.abs(rf.mean - w * ra.mean) / np.sqrt(rf.stderr ** 2 + (w * ra.stderr) ** 2)
+    assert np.max(z) < 4.5, z
+
+
+def test_cross_moment_equals_minus_K_cov(orc):
+    """r~ is affine in A, so Cov(r~, A) = -K~ Cov(A, A) exactly for the sample moments."""
+    p = workloads.small_problem(M=21, N=12, nblocks=2, sigma=1e-2)
+    prep = orc.prepare(p)
+    res = orc.run(prep, chains=1, burnin=50, sweeps=3000, refresh_every=16, groups=8,
+                  want_cross=True, traj_chain=0)
+    A = res.traj_A[50:]
+    mA = A.mean(0)
+    covAA = (A - mA).T @ (A - mA) / len(A)
+    ref = -prep.Kt @ covAA
+    assert np.max(np.abs(res.cov_rA - ref)) < 1e-8 * np.max(np.abs(ref))
+
+
+def test_vjp_against_common_random_number_differences(orc):
+    """v . (<A>(G + h u) - <A>(G - h u)) / 2h  ==  (J^T v) . u  (same random numbers)."""
+    p = workloads.small_problem(M=21, N=10, nblocks=2, sigma=2e-2, seed=31)
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(p.N)
+    u = rng.standard_normal(p.M)
+    u /= np.linalg.norm(u)
+    kw = dict(chains=64, burnin=300, sweeps=3000, groups=32, seed=2024)
+    base = orc.run(orc.prepare(p), want_cross=True, **kw)
+    jv = orc.vjp(base, v)
+    h = 1e-3 * p.sigma[0]
+    outs = []
+    for sgn in (+1, -1):
+        q = workloads.Problem(K=p.K, G=p.G + sgn * h * u, sigma=p.sigma, block_start=p.block_start)
+        outs.append(orc.run(orc.prepare(q), **kw).mean @ v)
+    fd = (outs[0] - outs[1]) / (2 * h)
+    assert abs(fd - jv @ u) < 0.1 * max(abs(fd), np.linalg.norm(jv) * 0.1), (fd, jv @ u)
+
+
+def test_unbounded_zero_mode_is_reported(orc):
+    # a null-space direction with all-positive entries makes the posterior improper
+    K = np.array([[1.0, -1.0]])
+    p = _problem(K, [0.0], 1.0, [0, 2])
+    res = orc.run(orc.prepare(p), chains=1, sweeps=2, groups=1)
+    assert res.status == -4
