@@ -173,10 +173,11 @@ double orc_S(double a, double w, double u, double uc) {
         }
         for (int it = 0; it < 200; ++it) {
             double f = orc_E(a, t) - target;
+            if (f == 0.0) break;  /* exact root */
             if (f < 0.0) tl = t; else th = t;
             double fp = exp(-t * (a + 0.5 * t));
             double tn = t - f / fp;
-            if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+            if (!(tn >= tl && tn <= th)) tn = 0.5 * (tl + th);
             double dt = fabs(tn - t);
             t = tn;
             if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
@@ -195,9 +196,10 @@ double orc_S(double a, double w, double u, double uc) {
         for (int it = 0; it < 200; ++it) {
             double tail = orc_E(a + t, w - t);
             double h = -t * (a + 0.5 * t) + log(tail) - Lstar;  /* decreasing in t */
+            if (h == 0.0) break;  /* exact root */
             if (h > 0.0) tl = t; else th = t;
             double tn = t + h * tail;
-            if (!(tn > tl && tn < th)) tn = 0.5 * (tl + th);
+            if (!(tn >= tl && tn <= th)) tn = 0.5 * (tl + th);
             double dt = fabs(tn - t);
             t = tn;
             if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
