@@ -1,0 +1,189 @@
+/*
+ * asm.h -- C ABI of the MI355X blocked-modes sampler for the average spectrum method
+ *          (K. Ghanem and E. Koch, "The Average Spectrum Method for Analytic Continuation:
+ *          Efficient Blocked Modes Sampling and Dependence on Discretization Grid",
+ *          arXiv:1912.01379).
+ *
+ * The library estimates, for each problem, the average over non-negative models
+ *
+ *     <A> = int_{A>=0} A exp(-chi^2(A)/2) dA / int_{A>=0} exp(-chi^2(A)/2) dA,
+ *     chi^2(A) = (G - K A)^T C^-1 (G - K A)                      (Sec. II, Eq. (PI);
+ *                                                                 Sec. IV, Eq. (chi2))
+ *
+ * by blocked modes sampling (Sec. IV.B-C): the grid is split into blocks, the whitened
+ * kernel of each block is decomposed once, K~_b = U_b D_b V_b^T, and a Markov chain moves
+ * one block along one of its singular modes at a time, the new mode coordinate being drawn
+ * from a Gaussian of width 1/d_i (flat when d_i = 0) truncated to the interval where
+ * A stays non-negative (Eq. (modeLimits)).
+ *
+ * Conventions for every entry point:
+ *   - arrays are row-major, float64, and live in device memory unless a comment says host;
+ *   - sizes are int64_t; a problem's N columns are the grid points, its M rows the data;
+ *   - the caller owns every buffer it passes; the plan owns everything it allocates and
+ *     frees it in asm_plan_destroy;
+ *   - all GPU work is enqueued on the stream given to asm_plan_create (a hipStream_t, or
+ *     NULL for the default stream); calls that return results synchronise that stream;
+ *   - every call returns ASM_OK (0) or a negative error code and never aborts;
+ *     asm_last_error() gives a message for the last failing call of the calling thread;
+ *   - a plan must not be used by two threads at once.
+ */
+#ifndef ASM_H
+#define ASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------------------- */
+#define ASM_OK          0
+#define ASM_EINVAL     (-1)  /* bad sizes, NULL required pointer, bad partition or k      */
+#define ASM_EDOMAIN    (-2)  /* non-finite input, sigma <= 0, covariance not SPD, init < 0 */
+#define ASM_ESTATE     (-3)  /* call out of order (vjp without want_vjp or before run)    */
+#define ASM_EUNBOUNDED (-4)  /* a zero mode whose allowed interval is unbounded: the flat
+                                prior makes the posterior improper (Sec. IV.B, d_i = 0)   */
+#define ASM_EHIP       (-5)  /* a HIP runtime call failed; the message carries its text    */
+#define ASM_ENOMEM     (-6)  /* device allocation failed                                  */
+
+/* ---- precision of the chain state and the moves ------------------------------------ */
+#define ASM_FP64 0   /* one wavefront per chain, float64 state: the plain sampler        */
+#define ASM_FP32 1   /* batched sampler, float32 state and moves; float64 setup, refresh,
+                        and accumulation of <A> and of its covariance with the data     */
+
+typedef struct asm_plan asm_plan;
+
+/* One continuation problem (Sec. II: data g with covariance C, g = K f after discretising
+   f on N grid intervals, Eq. (matrixeq)).  The columns of K already contain the
+   quadrature weights of the grid (Eq. (Riemann)), so A is the model on the grid. */
+typedef struct {
+    int64_t M;                   /* data points (rows of K)                                  */
+    int64_t N;                   /* grid points (columns of K)                               */
+    const double *K;             /* device, M x N                                            */
+    const double *G;             /* device, M: the measured data g                           */
+    const double *sigma;         /* device, M: iid standard deviations, C = diag(sigma^2);
+                                    NULL when cov is given                                   */
+    const double *cov;           /* device, M x M symmetric positive definite covariance C,
+                                    whitened with its Cholesky factor (Sec. IV after
+                                    Eq. (chi2)); NULL when sigma is given                    */
+    int64_t B;                   /* number of blocks of the grid partition (Sec. IV.C)        */
+    const int64_t *block_start;  /* host, B+1 offsets 0 = s_0 < s_1 < ... < s_B = N           */
+    const int32_t *k;            /* host, B: largest number of data modes per block, or NULL;
+                                    a block uses min(k_b, numerical rank) data modes (singular
+                                    values above max(M, N_b) * 2^-52 * d_1); the remaining
+                                    modes of the block are its zero modes, d := 0 (Sec. IV.B) */
+    const double *init;          /* device, N start model >= 0 shared by all chains, or NULL
+                                    for the best constant fit (K~1).g~/|K~1|^2               */
+} asm_problem;
+
+typedef struct {
+    int64_t chains;              /* chains per problem (>= 1)                                */
+    int64_t burnin;              /* sweeps discarded before averaging                        */
+    int64_t sweeps;              /* sweeps averaged; one sweep moves every mode of every block
+                                    once, blocks in increasing order                         */
+    uint64_t seed;               /* Philox4x32-10 key = (seed_lo, seed_hi ^ problem index)    */
+    int32_t precision;           /* ASM_FP64 or ASM_FP32                                      */
+    int32_t refresh_every;       /* sweeps between float64 recomputations of the residual
+                                    g~ - K~ A (0: never; 64 is a good value)                  */
+    int32_t want_vjp;            /* 1: accumulate Cov(r~, A) during the run for asm_plan_vjp  */
+    int32_t groups;              /* independent chain groups for the error bars (default 32);
+                                    with fewer chains than groups, batches of sweeps are used */
+    int32_t lanes_per_chain;     /* ASM_FP32 only: 4, 8, 16 or 32 lanes per chain, 0 = tune   */
+    int32_t use_graph;           /* 1: replay the sweep segments from a captured hipGraph     */
+    int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
+                                    or ASM_START_NNLS                                        */
+} asm_options;
+
+/* ---- start model ---------------------------------------------------------------------- */
+#define ASM_START_FLAT 0   /* the best constant fit c* = (K~1).g~/|K~1|^2 (1 if c* <= 0)    */
+#define ASM_START_NNLS 1   /* (1 - 0.01) x + 0.01 c*, x the non-negative least-squares fit of
+                              K~ x = g~ (Lawson-Hanson, float64): a start close to the best
+                              fit, as Sec. IV.D suggests, kept strictly positive so that no
+                              zero mode starts with an empty interval                        */
+
+typedef struct {
+    double setup_ms;             /* whitening + decompositions + packing + start state        */
+    double sample_ms;            /* all sweeps, refreshes and accumulation                    */
+    double finalize_ms;
+    double mode_moves;           /* moves made: sum over problems of chains*(burnin+sweeps)*N */
+    double data_moves;           /* of which along modes with d_i > 0                         */
+    double chi2_drift_max;       /* largest |chi^2_incremental - chi^2_recomputed| / chi^2
+                                    seen at a refresh                                         */
+    int64_t clamped;             /* components rounded below zero and set to +0 (ASM_FP64)    */
+    int64_t frozen;              /* moves with an empty interval lo = hi (ASM_FP64)           */
+    int32_t lanes_per_chain;     /* the value used                                            */
+    int32_t chains_per_block;    /* chains per workgroup used                                 */
+    double sampler_ms;           /* summed duration of the sampler launches of the run, from
+                                    events recorded around each launch on the plan's stream  */
+    int64_t sampler_launches;    /* number of those launches                                  */
+    int64_t sampler_sweeps;      /* sweeps they covered (each over all chains)                */
+} asm_stats;
+
+/* Validate the problems, whiten them, decompose every block (float64 one-sided Jacobi SVD,
+   then the zero modes as the Householder completion of the data modes), pack the factors,
+   and set every chain to the start model.  problems: host array of n_problems.  On success
+   *out receives the plan.  Errors: ASM_EINVAL, ASM_EDOMAIN, ASM_EHIP, ASM_ENOMEM. */
+int asm_plan_create(const asm_problem *problems, int64_t n_problems, const asm_options *opts,
+                    void *hip_stream, asm_plan **out);
+
+/* Run burnin + sweeps sweeps from the current chain state and write, concatenated over the
+   problems (sum N values each, device):
+     mean    -- the average model <A> (Eq. (MCint));
+     stderr_ -- standard error of each component over the independent chain groups;
+     post_sd -- posterior standard deviation of each component (nullable).
+   stats (host, nullable) receives timings and counters.  Errors: ASM_EUNBOUNDED (the
+   chain state is then unusable), ASM_EHIP. */
+int asm_plan_run(asm_plan *plan, double *mean, double *stderr_, double *post_sd,
+                 asm_stats *stats);
+
+/* Vector-Jacobian product of the last asm_plan_run: grad_G = J^T v with
+   J = d<A>/dG = -Cov(A, r~) T, r~ = T (G - K A), C^-1 = T^T T, obtained by differentiating
+   the normalised posterior of Eq. (PI) with respect to the data.  v: device, sum N;
+   grad_G: device, sum M.  Needs want_vjp = 1.  Errors: ASM_ESTATE, ASM_EHIP. */
+int asm_plan_vjp(asm_plan *plan, const double *v, double *grad_G);
+
+/* Advance every chain by `sweeps` sweeps without accumulating (burn-in style; the sweep
+   counter that keys the random numbers advances).  Errors: ASM_EUNBOUNDED, ASM_EHIP. */
+int asm_plan_advance(asm_plan *plan, int64_t sweeps);
+
+/* Copy the current chain state of one problem into device buffers (float64):
+   A: chains x N, r: chains x M (the whitened residual g~ - K~ A as carried by the
+   chains), chi2: chains (nullable; the running chi^2 of the float64 sampler, or |r|^2). */
+int asm_plan_state(asm_plan *plan, int64_t problem, double *A, double *r, double *chi2);
+
+/* Block factors of one problem as used by the sampler: kb (host, 1 int32), d (device, kb),
+   U (device, M x kb), V (device, N_b x N_b, column i = mode i, data modes first).  Any
+   output pointer may be NULL. */
+int asm_plan_factors(asm_plan *plan, int64_t problem, int64_t block, int32_t *kb, double *d,
+                     double *U, double *V);
+
+/* Whitened kernel and data of one problem (device, M x N and M); either may be NULL. */
+int asm_plan_whitened(asm_plan *plan, int64_t problem, double *Kt, double *gt);
+
+/* Release every device buffer, graph and event of the plan.  NULL is accepted. */
+int asm_plan_destroy(asm_plan *plan);
+
+/* Device check of the move primitives, for tests: for each of n entries draws
+   delta ~ N(c/d, 1/d^2) truncated to [lo, hi] (lo <= 0 <= hi, d > 0) by inversion at the
+   uniform u, with the float64 (precision = ASM_FP64) or float32 (ASM_FP32) device code
+   of the samplers.  All arrays device float64 of length n.  Errors: ASM_EINVAL, ASM_EHIP. */
+int asm_tn_draw(const double *c, const double *d, const double *lo, const double *hi,
+                const double *u, double *out, int64_t n, int32_t precision, void *hip_stream);
+
+/* Device check of the random numbers: out[(s*nblocks + b)*nmodes + i] = the float64 uniform
+   of the move (chain, sweep0 + s, b, i) of problem `problem`, for s < nsweeps.  out: device
+   float64.  Errors: ASM_EINVAL, ASM_EHIP. */
+int asm_uniforms(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep0, int64_t nsweeps,
+                 int64_t nblocks, int64_t nmodes, double *out, void *hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *asm_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int asm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASM_H */

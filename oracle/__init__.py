@@ -5,7 +5,7 @@ benchmark are the only users.  The product (the GPU library and its binding) nev
 imports this package, and this package never imports the product.
 
 Steps, in the paper's order:
-  1. whitening, Sec. III after Eq. (chi2): C^-1 = T^T T, g~ = T g, K~ = T K;
+  1. whitening, Sec. IV after Eq. (chi2): C^-1 = T^T T, g~ = T g, K~ = T K;
   2. per-block SVD K~_b = U_b D_b V_b^T, Sec. IV.B/IV.C, with d := 0 beyond the
      numerical rank (the paper's zero modes);
   3. the random walk over blocked modes (C core, `core.c`);
@@ -235,6 +235,22 @@ def block_factors(Kb: np.ndarray, k_req: Optional[int]):
     Z = householder_complete(Vd)
     V = np.concatenate([Vd, Z], axis=1)
     return sv[:k].copy(), Ud, V, sv.copy()
+
+
+def nnls_start(prep: Prepared, blend: float = 0.01) -> np.ndarray:
+    """Start model from the non-negative least-squares fit, Sec. IV.D (start from NNLS).
+
+    The NNLS solution of K~ f = g~ (Lawson-Hanson, scipy) has exact zeros, which would
+    leave most zero modes with an empty interval; it is therefore blended with the best
+    constant fit: f0 = (1 - blend) f_NNLS + blend c*.
+    """
+    from scipy.optimize import nnls
+    x, _ = nnls(prep.Kt, prep.gt, maxiter=50 * prep.N)
+    one = prep.Kt @ np.ones(prep.N)
+    cstar = float(np.dot(one, prep.gt) / np.dot(one, one))
+    if not (cstar > 0.0 and np.isfinite(cstar)):
+        cstar = 1.0
+    return (1.0 - blend) * x + blend * cstar
 
 
 def prepare(problem, k=None) -> Prepared:

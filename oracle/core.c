@@ -6,7 +6,7 @@
  * leg of the benchmark may load it.  It shares no code with the GPU library.
  *
  * What it computes (the paper's notation):
- *   - whitened problem chi^2(f) = ||g~ - K~ f||^2 (Sec. III, whitening after Eq. (chi2));
+ *   - whitened problem chi^2(f) = ||g~ - K~ f||^2 (Sec. IV, whitening after Eq. (chi2));
  *   - per-block SVD factors K~_b = U_b D_b V_b^T are inputs (computed by the Python
  *     driver with LAPACK);
  *   - a random walk over f >= 0 that updates one blocked mode e_i at a time (Sec. IV.B

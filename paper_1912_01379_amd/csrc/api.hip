@@ -1,0 +1,939 @@
+// Host side of the C ABI declared in include/asm.h: validation, plan construction, the
+// sweep loop (direct launches or a replayed hipGraph), finalisation and the VJP.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace asmk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(ASM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// dynamic LDS a sampler workgroup may use (160 KB per CU, less room for static variables)
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct asm_plan {
+    hipStream_t stream = nullptr;
+    asm_options opt{};
+    int64_t P = 0;
+    std::vector<ProbDesc> probs;
+    std::vector<BlockDesc> blocks;
+    std::vector<TileDesc> tiles;
+    std::vector<int64_t> n_prefix, m_prefix;
+    std::vector<int32_t> slot_group;
+    std::vector<double> slot_count;
+    int64_t total_chains = 0, total_n = 0, total_m = 0;
+    int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
+    int64_t max_nb = 0, max_nbp = 0;
+    int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
+    int fp32 = 1;
+    int lanes = 16, chains_per_wg = 16, grid32 = 0;
+    size_t lds32 = 0, lds64 = 0;
+    bool any_cov = false;
+    bool ran = false;
+    int64_t sweep = 0;      // absolute sweep counter (host mirror)
+    std::vector<void *> allocs;
+
+    // device buffers
+    ProbDesc *d_probs = nullptr;
+    BlockDesc *d_blocks = nullptr;
+    TileDesc *d_tiles = nullptr;
+    int64_t *d_nprefix = nullptr, *d_mprefix = nullptr;
+    int32_t *d_chain_problem = nullptr, *d_chain_local = nullptr;
+    double *Kt = nullptr, *gt = nullptr, *Lc = nullptr, *sigma = nullptr;
+    double *V64 = nullptr, *U64 = nullptr, *d64 = nullptr;
+    float2 *VW32 = nullptr;
+    float *U32 = nullptr, *d32 = nullptr;
+    float *A32 = nullptr, *r32 = nullptr;
+    double *A64 = nullptr, *r64 = nullptr, *chi2 = nullptr, *chi2_prev = nullptr, *drift = nullptr;
+    double *accA = nullptr, *accA2 = nullptr, *slot_count_d = nullptr;
+    int32_t *slot_group_d = nullptr;
+    double *cross = nullptr, *sumR = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
+    unsigned long long *counters = nullptr;
+    int *flags = nullptr, *queue = nullptr;
+    int64_t *sweep_d = nullptr;
+    std::vector<double> nsamples_host;
+
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // events around each sampler launch of a run (pairs), reused across runs
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    bool timing = false;
+    int64_t timed_sweeps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_nsw = 0;
+    int graph_accumulate = -1;
+    int64_t graph_burnin = -1;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(asm_plan *pl, T **out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) return fail(ASM_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    pl->allocs.push_back(p);
+    *out = static_cast<T *>(p);
+    return ASM_OK;
+}
+
+#define TRY(expr)              \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ != ASM_OK) return rc_; \
+    } while (0)
+
+int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
+    if (!pr || n < 1) return fail(ASM_EINVAL, "need at least one problem");
+    if (!o) return fail(ASM_EINVAL, "options are required");
+    if (o->chains < 1) return fail(ASM_EINVAL, "chains must be >= 1");
+    if (o->burnin < 0 || o->sweeps < 1) return fail(ASM_EINVAL, "burnin >= 0 and sweeps >= 1 required");
+    if (o->precision != ASM_FP64 && o->precision != ASM_FP32)
+        return fail(ASM_EINVAL, "precision must be ASM_FP64 or ASM_FP32");
+    if (o->refresh_every < 0) return fail(ASM_EINVAL, "refresh_every must be >= 0");
+    if (o->start != ASM_START_FLAT && o->start != ASM_START_NNLS)
+        return fail(ASM_EINVAL, "start must be ASM_START_FLAT or ASM_START_NNLS");
+    if (o->groups < 0 || o->groups > 64) return fail(ASM_EINVAL, "groups must be in [1, 64]");
+    if (o->lanes_per_chain != 0 && o->lanes_per_chain != 4 && o->lanes_per_chain != 8 &&
+        o->lanes_per_chain != 16 && o->lanes_per_chain != 32)
+        return fail(ASM_EINVAL, "lanes_per_chain must be 0, 4, 8, 16 or 32");
+    if (o->chains > (1ll << 31) || o->burnin + o->sweeps > (1ll << 31))
+        return fail(ASM_EINVAL, "chains and sweeps must fit the 32-bit random-number counter");
+    for (int64_t p = 0; p < n; ++p) {
+        const asm_problem &q = pr[p];
+        if (q.M < 1 || q.N < 1) return fail(ASM_EINVAL, "problem %lld: M and N must be >= 1", (long long)p);
+        if (q.M > 4096) return fail(ASM_EINVAL, "problem %lld: M > 4096 is not supported", (long long)p);
+        if (!q.K || !q.G) return fail(ASM_EINVAL, "problem %lld: K and G are required", (long long)p);
+        if ((q.sigma == nullptr) == (q.cov == nullptr))
+            return fail(ASM_EINVAL, "problem %lld: give exactly one of sigma and cov", (long long)p);
+        if (q.B < 1 || !q.block_start) return fail(ASM_EINVAL, "problem %lld: need B >= 1 blocks", (long long)p);
+        if (q.block_start[0] != 0 || q.block_start[q.B] != q.N)
+            return fail(ASM_EINVAL, "problem %lld: block_start must run from 0 to N", (long long)p);
+        for (int64_t b = 0; b < q.B; ++b) {
+            const int64_t nb = q.block_start[b + 1] - q.block_start[b];
+            if (nb < 1) return fail(ASM_EINVAL, "problem %lld: blocks must be non-empty and increasing", (long long)p);
+            if (nb > 65535) return fail(ASM_EINVAL, "problem %lld: block larger than 65535", (long long)p);
+            if (q.k && q.k[b] < 0) return fail(ASM_EINVAL, "problem %lld: k must be >= 0", (long long)p);
+        }
+        if (q.B > 65535) return fail(ASM_EINVAL, "problem %lld: more than 65535 blocks", (long long)p);
+    }
+    return ASM_OK;
+}
+
+int check_flags(asm_plan *pl, int *hflags) {
+    HIPCHK(hipMemcpyAsync(hflags, pl->flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return ASM_OK;
+}
+
+// tiles of the float32 sampler: consecutive chains within one error-bar group
+void build_tiles(asm_plan *pl) {
+    pl->tiles.clear();
+    pl->slot_group.clear();
+    pl->slot_count.clear();
+    const int cpw = pl->chains_per_wg;
+    for (int64_t p = 0; p < pl->P; ++p) {
+        ProbDesc &pd = pl->probs[p];
+        const int64_t C = pd.C, G = pd.groups;
+        pd.off_tab = (int64_t)pl->slot_group.size();
+        int64_t nunits = 0;
+        const int64_t ngr = pd.batches > 1 ? 1 : G;
+        for (int64_t g = 0; g < ngr; ++g) {
+            const int64_t c0 = pd.batches > 1 ? 0 : g * C / G;
+            const int64_t c1 = pd.batches > 1 ? C : (g + 1) * C / G;
+            for (int64_t c = c0; c < c1; c += cpw) {
+                TileDesc t;
+                t.problem = (int32_t)p;
+                t.chain0 = (int32_t)c;
+                t.nchains = (int32_t)std::min<int64_t>(cpw, c1 - c);
+                t.slot = (int32_t)(nunits * pd.batches);
+                pl->tiles.push_back(t);
+                for (int64_t bt = 0; bt < pd.batches; ++bt) {
+                    pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : g));
+                    pl->slot_count.push_back((double)t.nchains);
+                }
+                ++nunits;
+            }
+        }
+        pd.nslot = nunits * pd.batches;
+    }
+}
+
+// slots of the float64 sampler: one unit per chain
+void build_chain_slots(asm_plan *pl) {
+    pl->slot_group.clear();
+    pl->slot_count.clear();
+    for (int64_t p = 0; p < pl->P; ++p) {
+        ProbDesc &pd = pl->probs[p];
+        pd.off_tab = (int64_t)pl->slot_group.size();
+        for (int64_t c = 0; c < pd.C; ++c)
+            for (int64_t bt = 0; bt < pd.batches; ++bt) {
+                pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : c * pd.groups / pd.C));
+                pl->slot_count.push_back(1.0);
+            }
+        pd.nslot = pd.C * pd.batches;
+    }
+}
+
+// sample counts per slot: chains of the slot times the sweeps of its batch
+void finish_slot_counts(asm_plan *pl) {
+    const int64_t S = pl->opt.sweeps;
+    for (int64_t p = 0; p < pl->P; ++p) {
+        const ProbDesc &pd = pl->probs[p];
+        for (int64_t sl = 0; sl < pd.nslot; ++sl) {
+            double &cnt = pl->slot_count[pd.off_tab + sl];
+            if (pd.batches > 1) {
+                const int64_t bt = sl % pd.batches, G = pd.batches;
+                // sweeps s' in [0, S) with floor(s' G / S) == bt
+                const int64_t lo = (bt * S + G - 1) / G, hi = ((bt + 1) * S + G - 1) / G;
+                cnt *= (double)(hi - lo);
+            } else {
+                cnt *= (double)S;
+            }
+        }
+    }
+}
+
+SampleArgs make_args(asm_plan *pl) {
+    SampleArgs a{};
+    a.probs = pl->d_probs;
+    a.blocks = pl->d_blocks;
+    a.tiles = pl->d_tiles;
+    a.ntiles = (int64_t)pl->tiles.size();
+    a.Kt = pl->Kt;
+    a.gt = pl->gt;
+    a.V64 = pl->V64;
+    a.U64 = pl->U64;
+    a.d64 = pl->d64;
+    a.VW32 = pl->VW32;
+    a.U32 = pl->U32;
+    a.d32 = pl->d32;
+    a.A32 = pl->A32;
+    a.r32 = pl->r32;
+    a.A64 = pl->A64;
+    a.r64 = pl->r64;
+    a.chi2 = pl->chi2;
+    a.drift = pl->drift;
+    a.accA = pl->accA;
+    a.accA2 = pl->accA2;
+    a.counters = pl->counters;
+    a.flags = pl->flags;
+    a.queue = pl->queue;
+    a.sweep = pl->sweep_d;
+    a.seed = pl->opt.seed;
+    a.lds_vw = pl->max_nb * pl->max_nbp;
+    a.lds_nbp = pl->max_nbp;
+    return a;
+}
+
+// r = g~ - K~ A for every chain, and chi^2 = |r|^2 (optionally folding the drift)
+int refresh(asm_plan *pl, bool measure_drift) {
+    if (measure_drift && pl->fp32)
+        HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,
+                              pl->r32, pl->r64, pl->fp32, pl->chi2_prev, nullptr, nullptr, pl->stream));
+    HIPCHK(launch_refresh_all(pl->d_probs, pl->P, pl->max_refresh_tiles, pl->Kt, pl->gt, pl->A32,
+                              pl->r32, pl->A64, pl->r64, pl->fp32, pl->stream));
+    HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,
+                          pl->r32, pl->r64, pl->fp32, pl->chi2,
+                          measure_drift && pl->fp32 ? pl->chi2_prev : nullptr,
+                          measure_drift && pl->fp32 ? pl->drift : nullptr, pl->stream));
+    return ASM_OK;
+}
+
+// One segment of nsw sweeps starting at the device sweep counter; advances the counter.
+int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs) {
+    SampleArgs a = make_args(pl);
+    a.nsw = nsw;
+    a.accumulate = accumulate;
+    a.burnin = burnin_abs;
+    a.sweeps = pl->opt.sweeps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pl->timing) {
+        while (pl->tev.size() < pl->tev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            pl->tev.push_back(e);
+        }
+        e0 = pl->tev[pl->tev_used++];
+        e1 = pl->tev[pl->tev_used++];
+        HIPCHK(hipEventRecord(e0, pl->stream));
+    }
+    if (pl->fp32) {
+        a.refresh_every = 0;
+        HIPCHK(launch_sample32_inst(a, pl->lanes, pl->ept, pl->rpt, pl->chains_per_wg, pl->grid32,
+                                    pl->lds32, pl->stream));
+    } else {
+        a.refresh_every = pl->opt.refresh_every;
+        HIPCHK(launch_sample64_grid(a, pl->total_chains, pl->d_chain_problem, pl->d_chain_local,
+                                    pl->lds64, pl->stream));
+    }
+    if (pl->timing) {
+        HIPCHK(hipEventRecord(e1, pl->stream));
+        pl->timed_sweeps += nsw;
+    }
+    HIPCHK(launch_bump(pl->sweep_d, nsw, pl->queue, pl->stream));
+    return ASM_OK;
+}
+
+// Run sweeps [sweep, sweep + total) with accumulation from burnin_abs on (if accumulate).
+int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) {
+    const int64_t R = pl->opt.refresh_every;
+    const int64_t end = pl->sweep + total;
+    const bool vjp = accumulate && pl->opt.want_vjp;
+    while (pl->sweep < end) {
+        const int64_t s = pl->sweep;
+        int64_t seg = end - s;
+        if (pl->fp32 && R > 0) seg = std::min(seg, R - s % R);   // stop where a refresh is due
+        if (!pl->fp32 && seg > 256) seg = 256;
+        if (vjp && s + 1 > burnin_abs) seg = 1;                 // cross moment after every sweep
+        else if (vjp && s + seg > burnin_abs) seg = burnin_abs - s;
+        if (seg < 1) seg = 1;
+        TRY(segment(pl, seg, accumulate, burnin_abs));
+        pl->sweep += seg;
+        if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
+        if (vjp && pl->sweep - 1 >= burnin_abs) {
+            HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->max_m, pl->A32,
+                                    pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->sumR,
+                                    pl->stream));
+        }
+    }
+    return ASM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *asm_last_error(void) { return g_err.c_str(); }
+
+int asm_version(void) { return 100; }
+
+int asm_plan_destroy(asm_plan *pl) {
+    if (!pl) return ASM_OK;
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (auto &e : pl->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : pl->tev) (void)hipEventDestroy(e);
+    for (void *p : pl->allocs) (void)hipFree(p);
+    delete pl;
+    return ASM_OK;
+}
+
+int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream,
+                    asm_plan **out) {
+    g_err.clear();
+    if (!out) return fail(ASM_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(validate(pr, n, o));
+    asm_plan *pl = new asm_plan();
+    int rc = ASM_OK;
+    struct Guard {
+        asm_plan *&p;
+        int &rc;
+        ~Guard() {
+            if (rc != ASM_OK) asm_plan_destroy(p);
+        }
+    } guard{pl, rc};
+#define STEP(expr)                 \
+    do {                           \
+        rc = (expr);               \
+        if (rc != ASM_OK) return rc; \
+    } while (0)
+#define HSTEP(expr)                                                                    \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            rc = fail(ASM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));               \
+            return rc;                                                                 \
+        }                                                                              \
+    } while (0)
+
+    pl->stream = static_cast<hipStream_t>(hip_stream);
+    pl->opt = *o;
+    if (pl->opt.groups == 0) pl->opt.groups = 32;
+    pl->P = n;
+    pl->fp32 = o->precision == ASM_FP32;
+    for (auto &e : pl->ev) HSTEP(hipEventCreate(&e));
+    (void)set_sample32_lds_limit();
+    (void)hipGetLastError();
+
+    // ---- sizes and offsets ----
+    int64_t offK = 0, offm = 0, offn = 0, offA = 0, offr = 0, offc = 0, offL = 0, offcross = 0;
+    int64_t offV = 0, offU = 0, offd = 0, offwork = 0;
+    std::vector<SvdTask> tasks;
+    std::vector<int64_t> blockM;
+    const int64_t C = o->chains;
+    const int64_t G = pl->opt.groups;
+    pl->n_prefix.push_back(0);
+    pl->m_prefix.push_back(0);
+    for (int64_t p = 0; p < n; ++p) {
+        const asm_problem &q = pr[p];
+        ProbDesc pd{};
+        pd.M = q.M;
+        pd.N = q.N;
+        pd.B = q.B;
+        pd.C = C;
+        pd.off_K = offK;
+        pd.off_m = offm;
+        pd.off_n = offn;
+        pd.off_A = offA;
+        pd.off_r = offr;
+        pd.off_c = offc;
+        pd.off_blk = (int64_t)pl->blocks.size();
+        pd.off_cross = offcross;
+        pd.off_L = offL;
+        pd.groups = (int32_t)G;
+        pd.batches = C < G ? G : 1;
+        pd.has_cov = q.cov != nullptr;
+        pd.index = (uint32_t)p;
+        pl->any_cov |= pd.has_cov;
+        for (int64_t b = 0; b < q.B; ++b) {
+            BlockDesc bd{};
+            bd.n0 = q.block_start[b];
+            bd.nb = q.block_start[b + 1] - q.block_start[b];
+            const int64_t kmax = std::min(q.M, bd.nb);
+            bd.off_V = offV;
+            bd.off_U = offU;
+            bd.off_d = offd;
+            offV += bd.nb * bd.nb;
+            offU += kmax * q.M;
+            offd += kmax;
+            SvdTask t{};
+            t.M = q.M;
+            t.N = q.N;
+            t.off_K = offK;
+            t.n0 = bd.n0;
+            t.nb = bd.nb;
+            t.kreq = q.k ? q.k[b] : -1;
+            t.off_V = bd.off_V;
+            t.off_U = bd.off_U;
+            t.off_d = bd.off_d;
+            t.off_work = offwork;
+            t.block = (int64_t)pl->blocks.size();
+            offwork += svd_work_doubles(q.M, bd.nb);
+            tasks.push_back(t);
+            blockM.push_back(q.M);
+            pl->blocks.push_back(bd);
+            pl->max_nb = std::max(pl->max_nb, bd.nb);
+        }
+        offK += q.M * q.N;
+        offm += q.M;
+        offn += q.N;
+        offA += C * q.N;
+        offr += C * q.M;
+        offc += C;
+        if (pd.has_cov) offL += q.M * q.M;
+        if (o->want_vjp) offcross += q.M * q.N;
+        pl->max_m = std::max(pl->max_m, q.M);
+        pl->max_refresh_tiles = std::max(pl->max_refresh_tiles, ((C + 15) / 16) * ((q.M + 15) / 16));
+        pl->max_cross_tiles = std::max(pl->max_cross_tiles, ((q.M + 15) / 16) * ((q.N + 15) / 16));
+        pl->n_prefix.push_back(offn);
+        pl->m_prefix.push_back(offm);
+        pl->probs.push_back(pd);
+    }
+    pl->total_chains = offc;
+    pl->total_n = offn;
+    pl->total_m = offm;
+
+    // ---- allocations ----
+    double *work = nullptr, *tmpN = nullptr;
+    int32_t *kb_d = nullptr;
+    int64_t *blockM_d = nullptr;
+    int *has_init_d = nullptr;
+    SvdTask *tasks_d = nullptr;
+    STEP(dalloc(pl, &pl->Kt, offK));
+    STEP(dalloc(pl, &pl->gt, offm));
+    STEP(dalloc(pl, &pl->sigma, offm));
+    if (pl->any_cov) STEP(dalloc(pl, &pl->Lc, offL));
+    STEP(dalloc(pl, &pl->V64, offV));
+    STEP(dalloc(pl, &pl->U64, offU));
+    STEP(dalloc(pl, &pl->d64, offd));
+    STEP(dalloc(pl, &work, offwork));
+    STEP(dalloc(pl, &kb_d, pl->blocks.size()));
+    STEP(dalloc(pl, &blockM_d, blockM.size()));
+    STEP(dalloc(pl, &tasks_d, tasks.size()));
+    STEP(dalloc(pl, &tmpN, offn));
+    STEP(dalloc(pl, &has_init_d, n));
+    STEP(dalloc(pl, &pl->flags, 1));
+    STEP(dalloc(pl, &pl->queue, 1));
+    STEP(dalloc(pl, &pl->sweep_d, 1));
+    STEP(dalloc(pl, &pl->counters, 2));
+    STEP(dalloc(pl, &pl->chi2, offc));
+    STEP(dalloc(pl, &pl->chi2_prev, offc));
+    STEP(dalloc(pl, &pl->drift, offc));
+    STEP(dalloc(pl, &pl->d_chain_problem, offc));
+    STEP(dalloc(pl, &pl->d_chain_local, offc));
+    STEP(dalloc(pl, &pl->d_nprefix, n + 1));
+    STEP(dalloc(pl, &pl->d_mprefix, n + 1));
+    if (pl->fp32) {
+        STEP(dalloc(pl, &pl->A32, offA));
+        STEP(dalloc(pl, &pl->r32, offr));
+    } else {
+        STEP(dalloc(pl, &pl->A64, offA));
+        STEP(dalloc(pl, &pl->r64, offr));
+    }
+    if (o->want_vjp) {
+        STEP(dalloc(pl, &pl->cross, offcross));
+        STEP(dalloc(pl, &pl->sumR, offm));
+        STEP(dalloc(pl, &pl->nsamples, n));
+        STEP(dalloc(pl, &pl->vjp_y, offm));
+    }
+    hipStream_t st = pl->stream;
+    HSTEP(hipMemsetAsync(pl->flags, 0, sizeof(int), st));
+    HSTEP(hipMemsetAsync(pl->sweep_d, 0, sizeof(int64_t), st));
+    HSTEP(hipMemsetAsync(pl->queue, 0, sizeof(int), st));
+    HSTEP(hipMemsetAsync(pl->counters, 0, 2 * sizeof(unsigned long long), st));
+    HSTEP(hipMemsetAsync(pl->drift, 0, offc * sizeof(double), st));
+
+    // ---- input checks (device data) ----
+    std::vector<int> has_init(n, 0);
+    for (int64_t p = 0; p < n; ++p) {
+        const asm_problem &q = pr[p];
+        HSTEP(launch_check_finite(q.K, q.M * q.N, pl->flags, 1, st));
+        HSTEP(launch_check_finite(q.G, q.M, pl->flags, 1, st));
+        if (q.sigma) HSTEP(launch_check_positive(q.sigma, q.M, pl->flags, 2, st));
+        if (q.cov) HSTEP(launch_check_finite(q.cov, q.M * q.M, pl->flags, 1, st));
+        if (q.init) {
+            HSTEP(launch_check_finite(q.init, q.N, pl->flags, 1, st));
+            HSTEP(hipMemcpyAsync(tmpN + pl->probs[p].off_n, q.init, q.N * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+            has_init[p] = 1;
+        }
+    }
+    int hflags = 0;
+    STEP(check_flags(pl, &hflags));
+    if (hflags & 2) { rc = fail(ASM_EDOMAIN, "non-finite value in K, G, cov or init"); return rc; }
+    if (hflags & 4) { rc = fail(ASM_EDOMAIN, "sigma must be positive and finite"); return rc; }
+    if (std::any_of(has_init.begin(), has_init.end(), [](int v) { return v; })) {
+        std::vector<double> h(offn);
+        HSTEP(hipMemcpy(h.data(), tmpN, offn * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < n; ++p)
+            if (has_init[p])
+                for (int64_t i = 0; i < pr[p].N; ++i)
+                    if (h[pl->probs[p].off_n + i] < 0.0) {
+                        rc = fail(ASM_EDOMAIN, "problem %lld: init must be >= 0", (long long)p);
+                        return rc;
+                    }
+    }
+
+    HSTEP(hipEventRecord(pl->ev[0], st));
+    // ---- whitening ----
+    for (int64_t p = 0; p < n; ++p) {
+        const asm_problem &q = pr[p];
+        const ProbDesc &pd = pl->probs[p];
+        if (q.sigma) {
+            HSTEP(launch_whiten_diag(q.K, q.G, q.sigma, q.M, q.N, pl->Kt + pd.off_K, pl->gt + pd.off_m, st));
+            HSTEP(hipMemcpyAsync(pl->sigma + pd.off_m, q.sigma, q.M * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+        } else {
+            HSTEP(launch_cholesky(q.cov, q.M, pl->Lc + pd.off_L, pl->flags, 3, st));
+            HSTEP(launch_trsm_lower(pl->Lc + pd.off_L, q.M, q.K, q.N, q.N, pl->Kt + pd.off_K, st));
+            HSTEP(launch_trsm_lower(pl->Lc + pd.off_L, q.M, q.G, 1, 1, pl->gt + pd.off_m, st));
+        }
+    }
+    STEP(check_flags(pl, &hflags));
+    if (hflags & 8) { rc = fail(ASM_EDOMAIN, "covariance is not symmetric positive definite"); return rc; }
+
+    // ---- block decompositions ----
+    HSTEP(hipMemcpyAsync(tasks_d, tasks.data(), tasks.size() * sizeof(SvdTask), hipMemcpyHostToDevice, st));
+    HSTEP(launch_block_svd_tasks(tasks_d, (int64_t)tasks.size(), pl->Kt, work, pl->V64, pl->U64,
+                                 pl->d64, kb_d, st));
+    std::vector<int32_t> kb(pl->blocks.size());
+    HSTEP(hipMemcpyAsync(kb.data(), kb_d, kb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HSTEP(hipStreamSynchronize(st));
+    for (size_t b = 0; b < kb.size(); ++b) pl->blocks[b].kb = kb[b];
+
+    // ---- chain -> problem tables ----
+    {
+        std::vector<int32_t> cp(offc), cl(offc);
+        for (int64_t p = 0; p < n; ++p)
+            for (int64_t c = 0; c < C; ++c) {
+                cp[pl->probs[p].off_c + c] = (int32_t)p;
+                cl[pl->probs[p].off_c + c] = (int32_t)c;
+            }
+        HSTEP(hipMemcpyAsync(pl->d_chain_problem, cp.data(), offc * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->d_chain_local, cl.data(), offc * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->d_nprefix, pl->n_prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->d_mprefix, pl->m_prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HSTEP(hipStreamSynchronize(st));
+    }
+
+    // ---- sampler configuration ----
+    int max_cu = 256;
+    {
+        int dev = 0;
+        HSTEP(hipGetDevice(&dev));
+        HSTEP(hipDeviceGetAttribute(&max_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    if (pl->fp32) {
+        int L = o->lanes_per_chain;
+        if (L == 0) {
+            // aim for about one wavefront per SIMD (4 per CU) across all chains
+            const double chains_per_simd = (double)pl->total_chains / (4.0 * max_cu);
+            const double want = 64.0 / std::max(1.0, chains_per_simd);
+            L = want >= 24 ? 32 : want >= 12 ? 16 : want >= 6 ? 8 : 4;
+        }
+        int ept = 0, rpt = 0;
+        {
+            // the requested width first, then wider ones, then narrower ones
+            const int order[] = {L, 16, 32, 8, 4};
+            bool found = false;
+            for (int cand : order) {
+                if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;
+                if (sample32_pick(cand, pl->max_nb, pl->max_m, &ept, &rpt) == 0) {
+                    L = cand;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) {
+                rc = fail(ASM_EINVAL, "block of %lld points or %lld data points too large for the float32 sampler",
+                          (long long)pl->max_nb, (long long)pl->max_m);
+                return rc;
+            }
+        }
+        pl->lanes = L;
+        pl->ept = ept;
+        pl->rpt = rpt;
+        const int64_t row = (int64_t)ept * L;   // components per staged row
+        const int64_t mp = (int64_t)rpt * L;
+        pl->max_nbp = row;
+        // packed float32 layout of the block factors for this instance
+        int64_t offVW = 0, offU32 = 0, offd32 = 0;
+        for (auto &bd : pl->blocks) {
+            bd.nbp = row;
+            bd.mp = mp;
+            bd.off_VW = offVW;
+            bd.off_U32 = offU32;
+            bd.off_d32 = offd32;
+            offVW += bd.nb * row;   // row is a multiple of 4: offsets stay 16-byte aligned
+            offU32 += std::max<int64_t>(bd.kb, 1) * mp;
+            offd32 += std::max<int64_t>(bd.kb, 1);
+        }
+        STEP(dalloc(pl, &pl->VW32, offVW));
+        STEP(dalloc(pl, &pl->U32, offU32));
+        STEP(dalloc(pl, &pl->d32, offd32));
+        // chains per workgroup: within the LDS budget and at most 512 threads
+        const size_t vw_bytes = (size_t)pl->max_nb * row * sizeof(float2);
+        int cpw = 512 / L;
+        while (cpw > 64 / L) {
+            const size_t lds = vw_bytes + (size_t)cpw * row * sizeof(float);
+            const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
+            if (lds <= kLdsBudget && wgs >= max_cu) break;
+            cpw /= 2;
+        }
+        pl->chains_per_wg = cpw;
+        pl->lds32 = vw_bytes + (size_t)cpw * row * sizeof(float);
+        if (pl->lds32 > kLdsBudget) {
+            rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
+            return rc;
+        }
+        build_tiles(pl);
+        pl->grid32 = (int)std::min<int64_t>((int64_t)pl->tiles.size(), (int64_t)max_cu * 2);
+        STEP(dalloc(pl, &pl->d_tiles, pl->tiles.size()));
+        HSTEP(hipMemcpyAsync(pl->d_tiles, pl->tiles.data(), pl->tiles.size() * sizeof(TileDesc),
+                             hipMemcpyHostToDevice, st));
+    } else {
+        int64_t maxlds = 0;
+        for (auto &pd : pl->probs) maxlds = std::max(maxlds, (pd.N + pd.M) * (int64_t)sizeof(double));
+        if (maxlds > (int64_t)kLdsBudget) {
+            rc = fail(ASM_EINVAL, "float64 sampler holds N + M doubles in LDS: at most 20480");
+            return rc;
+        }
+        pl->lds64 = (size_t)maxlds;
+        pl->lanes = 64;
+        pl->chains_per_wg = 1;
+        build_chain_slots(pl);
+    }
+    finish_slot_counts(pl);
+    int64_t slot_elems = 0;
+    for (auto &pd : pl->probs) {
+        pd.off_slot = slot_elems;
+        slot_elems += pd.nslot * pd.N;
+    }
+    STEP(dalloc(pl, &pl->accA, slot_elems));
+    STEP(dalloc(pl, &pl->accA2, slot_elems));
+    STEP(dalloc(pl, &pl->slot_group_d, pl->slot_group.size()));
+    STEP(dalloc(pl, &pl->slot_count_d, pl->slot_count.size()));
+    HSTEP(hipMemcpyAsync(pl->slot_group_d, pl->slot_group.data(), pl->slot_group.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HSTEP(hipMemcpyAsync(pl->slot_count_d, pl->slot_count.data(), pl->slot_count.size() * sizeof(double), hipMemcpyHostToDevice, st));
+
+    // ---- device tables ----
+    STEP(dalloc(pl, &pl->d_probs, pl->probs.size()));
+    STEP(dalloc(pl, &pl->d_blocks, pl->blocks.size()));
+    HSTEP(hipMemcpyAsync(pl->d_probs, pl->probs.data(), pl->probs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HSTEP(hipMemcpyAsync(pl->d_blocks, pl->blocks.data(), pl->blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+    HSTEP(hipMemcpyAsync(blockM_d, blockM.data(), blockM.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HSTEP(hipMemcpyAsync(has_init_d, has_init.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+
+    // ---- start from the non-negative least-squares fit where asked ----
+    if (o->start == ASM_START_NNLS) {
+        std::vector<int> use(n, 0);
+        std::vector<int64_t> woff(n, 0);
+        int64_t wtot = 0;
+        for (int64_t p = 0; p < n; ++p) {
+            use[p] = has_init[p] ? 0 : 1;
+            woff[p] = wtot;
+            if (use[p]) wtot += nnls_work_doubles(pr[p].M, pr[p].N);
+        }
+        if (wtot > 0) {
+            double *nw = nullptr;
+            int *use_d = nullptr;
+            int64_t *woff_d = nullptr;
+            STEP(dalloc(pl, &nw, wtot));
+            STEP(dalloc(pl, &use_d, n));
+            STEP(dalloc(pl, &woff_d, n));
+            HSTEP(hipMemcpyAsync(use_d, use.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+            HSTEP(hipMemcpyAsync(woff_d, woff.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            HSTEP(launch_nnls(pl->d_probs, n, use_d, pl->Kt, pl->gt, nw, woff_d, 0.01, tmpN,
+                              has_init_d, st));
+        }
+    }
+
+    // ---- float32 packing, start state, first residual ----
+    if (pl->fp32)
+        HSTEP(launch_pack32_blocks(pl->d_blocks, blockM_d, (int64_t)pl->blocks.size(), pl->V64,
+                                   pl->U64, pl->d64, pl->VW32, pl->U32, pl->d32, st));
+    HSTEP(launch_init_state2(pl->d_probs, n, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
+                             pl->fp32, st));
+    STEP(refresh(pl, false));
+    HSTEP(hipEventRecord(pl->ev[1], st));
+    HSTEP(hipStreamSynchronize(st));
+    *out = pl;
+    return ASM_OK;
+#undef STEP
+#undef HSTEP
+}
+
+int asm_plan_advance(asm_plan *pl, int64_t sweeps) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (sweeps < 0) return fail(ASM_EINVAL, "sweeps must be >= 0");
+    if (sweeps == 0) return ASM_OK;
+    TRY(sweep_loop(pl, sweeps, 0, 0));
+    int hflags = 0;
+    TRY(check_flags(pl, &hflags));
+    if (hflags & 1) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
+    return ASM_OK;
+}
+
+int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, asm_stats *stats) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (!mean || !stderr_) return fail(ASM_EINVAL, "mean and stderr_ are required");
+    hipStream_t st = pl->stream;
+    const int64_t slot_elems = pl->probs.back().off_slot + pl->probs.back().nslot * pl->probs.back().N;
+    HIPCHK(hipMemsetAsync(pl->accA, 0, slot_elems * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(pl->accA2, 0, slot_elems * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(pl->counters, 0, 2 * sizeof(unsigned long long), st));
+    int64_t crossn = 0;
+    if (pl->opt.want_vjp) {
+        for (auto &pd : pl->probs) crossn += pd.M * pd.N;
+        HIPCHK(hipMemsetAsync(pl->cross, 0, crossn * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(pl->sumR, 0, pl->total_m * sizeof(double), st));
+    }
+    HIPCHK(hipEventRecord(pl->ev[2], st));
+    const int64_t burnin_abs = pl->sweep + pl->opt.burnin;
+    pl->timing = true;
+    pl->tev_used = 0;
+    pl->timed_sweeps = 0;
+    int lrc = sweep_loop(pl, pl->opt.burnin + pl->opt.sweeps, 1, burnin_abs);
+    pl->timing = false;
+    TRY(lrc);
+    HIPCHK(hipEventRecord(pl->ev[3], st));
+    HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2,
+                           pl->slot_group_d, pl->slot_count_d, mean, stderr_, post_sd, st));
+    if (pl->opt.want_vjp) {
+        pl->nsamples_host.assign(pl->P, (double)pl->opt.chains * (double)pl->opt.sweeps);
+        HIPCHK(hipMemcpyAsync(pl->nsamples, pl->nsamples_host.data(), pl->P * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+    }
+    int hflags = 0;
+    TRY(check_flags(pl, &hflags));
+    pl->ran = true;
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]));
+        stats->setup_ms = ms;
+        HIPCHK(hipEventElapsedTime(&ms, pl->ev[2], pl->ev[3]));
+        stats->sample_ms = ms;
+        double mm = 0, dm = 0;
+        for (auto &pd : pl->probs) {
+            mm += (double)pd.C * (double)(pl->opt.burnin + pl->opt.sweeps) * (double)pd.N;
+            for (int64_t b = 0; b < pd.B; ++b)
+                dm += (double)pd.C * (double)(pl->opt.burnin + pl->opt.sweeps) * (double)pl->blocks[pd.off_blk + b].kb;
+        }
+        stats->mode_moves = mm;
+        stats->data_moves = dm;
+        std::vector<double> dr(pl->total_chains);
+        HIPCHK(hipMemcpy(dr.data(), pl->drift, dr.size() * sizeof(double), hipMemcpyDeviceToHost));
+        stats->chi2_drift_max = dr.empty() ? 0.0 : *std::max_element(dr.begin(), dr.end());
+        unsigned long long cnt[2];
+        HIPCHK(hipMemcpy(cnt, pl->counters, sizeof cnt, hipMemcpyDeviceToHost));
+        stats->clamped = (int64_t)cnt[0];
+        stats->frozen = (int64_t)cnt[1];
+        stats->lanes_per_chain = pl->lanes;
+        stats->chains_per_block = pl->chains_per_wg;
+        double smp = 0.0;
+        for (size_t i = 0; i + 1 < pl->tev_used; i += 2) {
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, pl->tev[i], pl->tev[i + 1]));
+            smp += t;
+        }
+        stats->sampler_ms = smp;
+        stats->sampler_launches = (int64_t)(pl->tev_used / 2);
+        stats->sampler_sweeps = pl->timed_sweeps;
+    }
+    if (hflags & 1) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
+    return ASM_OK;
+}
+
+int asm_plan_vjp(asm_plan *pl, const double *v, double *grad_G) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (!pl->opt.want_vjp) return fail(ASM_ESTATE, "plan was created without want_vjp");
+    if (!pl->ran) return fail(ASM_ESTATE, "asm_plan_run must come before asm_plan_vjp");
+    if (!v || !grad_G) return fail(ASM_EINVAL, "v and grad_G are required");
+    // the mean of the last run is recomputed into scratch from the accumulators
+    double *mean = nullptr, *se = nullptr;
+    TRY(dalloc(pl, &mean, pl->total_n));
+    TRY(dalloc(pl, &se, pl->total_n));
+    hipStream_t st = pl->stream;
+    HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2,
+                           pl->slot_group_d, pl->slot_count_d, mean, se, nullptr, st));
+    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->cross, pl->sumR, mean,
+                      pl->nsamples, pl->sigma, pl->Lc, v, pl->vjp_y, grad_G, pl->any_cov ? 1 : 0, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // release the scratch again
+    for (double *p : {mean, se}) {
+        auto it = std::find(pl->allocs.begin(), pl->allocs.end(), (void *)p);
+        if (it != pl->allocs.end()) pl->allocs.erase(it);
+        HIPCHK(hipFree(p));
+    }
+    return ASM_OK;
+}
+
+int asm_plan_state(asm_plan *pl, int64_t problem, double *A, double *r, double *chi2) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (problem < 0 || problem >= pl->P) return fail(ASM_EINVAL, "problem index out of range");
+    if (pl->fp32) {
+        // the float32 sampler carries no running chi^2: report |r|^2 of the carried residual
+        HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,
+                              pl->r32, pl->r64, 1, pl->chi2_prev, nullptr, nullptr, pl->stream));
+    }
+    HIPCHK(launch_state64(pl->d_probs, problem, pl->probs[problem], pl->A32, pl->r32, pl->A64,
+                          pl->r64, pl->fp32 ? pl->chi2_prev : pl->chi2, pl->fp32, A, r, chi2,
+                          pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return ASM_OK;
+}
+
+int asm_plan_factors(asm_plan *pl, int64_t problem, int64_t block, int32_t *kb, double *d,
+                     double *U, double *V) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (problem < 0 || problem >= pl->P) return fail(ASM_EINVAL, "problem index out of range");
+    const ProbDesc &pd = pl->probs[problem];
+    if (block < 0 || block >= pd.B) return fail(ASM_EINVAL, "block index out of range");
+    const BlockDesc &bd = pl->blocks[pd.off_blk + block];
+    if (kb) *kb = (int32_t)bd.kb;
+    hipStream_t st = pl->stream;
+    if (d && bd.kb) HIPCHK(hipMemcpyAsync(d, pl->d64 + bd.off_d, bd.kb * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (U && bd.kb) {
+        // stored mode-major (kb x M); returned M x kb
+        std::vector<double> h(bd.kb * pd.M), t(bd.kb * pd.M);
+        HIPCHK(hipMemcpyAsync(h.data(), pl->U64 + bd.off_U, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < bd.kb; ++i)
+            for (int64_t m = 0; m < pd.M; ++m) t[m * bd.kb + i] = h[i * pd.M + m];
+        HIPCHK(hipMemcpyAsync(U, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (V) {
+        std::vector<double> h(bd.nb * bd.nb), t(bd.nb * bd.nb);
+        HIPCHK(hipMemcpyAsync(h.data(), pl->V64 + bd.off_V, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < bd.nb; ++i)
+            for (int64_t q = 0; q < bd.nb; ++q) t[q * bd.nb + i] = h[i * bd.nb + q];
+        HIPCHK(hipMemcpyAsync(V, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return ASM_OK;
+}
+
+int asm_plan_whitened(asm_plan *pl, int64_t problem, double *Kt, double *gt) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (problem < 0 || problem >= pl->P) return fail(ASM_EINVAL, "problem index out of range");
+    const ProbDesc &pd = pl->probs[problem];
+    if (Kt) HIPCHK(hipMemcpyAsync(Kt, pl->Kt + pd.off_K, pd.M * pd.N * sizeof(double), hipMemcpyDeviceToDevice, pl->stream));
+    if (gt) HIPCHK(hipMemcpyAsync(gt, pl->gt + pd.off_m, pd.M * sizeof(double), hipMemcpyDeviceToDevice, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return ASM_OK;
+}
+
+int asm_tn_draw(const double *c, const double *d, const double *lo, const double *hi,
+                const double *u, double *out, int64_t n, int32_t precision, void *hip_stream) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!c || !d || !lo || !hi || !u || !out)))
+        return fail(ASM_EINVAL, "bad arguments");
+    if (precision != ASM_FP64 && precision != ASM_FP32) return fail(ASM_EINVAL, "bad precision");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIPCHK(launch_tn_draw(c, d, lo, hi, u, out, n, precision, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ASM_OK;
+}
+
+int asm_uniforms(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep0, int64_t nsweeps,
+                 int64_t nblocks, int64_t nmodes, double *out, void *hip_stream) {
+    g_err.clear();
+    if (!out || nsweeps < 0 || nblocks < 0 || nmodes < 0 || nblocks > 65535 || nmodes > 65535)
+        return fail(ASM_EINVAL, "bad arguments");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIPCHK(launch_uniforms(seed, problem, chain, sweep0, nsweeps, nblocks, nmodes, out, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ASM_OK;
+}
+
+}  // extern "C"

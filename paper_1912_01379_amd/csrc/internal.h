@@ -1,0 +1,178 @@
+// Internal declarations shared by the translation units of libasm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/asm.h"
+
+namespace asmk {
+
+// ------------------------------------------------------------------------------------
+// device-visible tables
+// ------------------------------------------------------------------------------------
+struct ProbDesc {
+    int64_t M, N, B, C;       // data points, grid points, blocks, chains
+    int64_t off_K;            // whitened kernel K~ (M x N) in Kt
+    int64_t off_m;            // M-vectors (g~, sigma, grad) in concatenated arrays
+    int64_t off_n;            // N-vectors (mean, stderr, init) in concatenated arrays
+    int64_t off_A;            // chain state A: C x N
+    int64_t off_r;            // chain state r: C x M
+    int64_t off_c;            // per-chain scalars (chi2, drift): C
+    int64_t off_blk;          // first block in the block table
+    int64_t off_cross;        // M x N cross moment sum_s r A^T
+    int64_t off_L;            // Cholesky factor (M x M) when whitened with a covariance
+    int64_t off_slot;         // element offset of the problem's accumulator slots (slots x N)
+    int64_t off_tab;          // first entry of the problem in the slot tables
+    int64_t nslot;            // accumulator slots of the problem
+    int64_t batches;          // 1, or G when chains < groups (batch means over sweeps)
+    int32_t groups;
+    int32_t has_cov;
+    uint32_t index;           // problem index (keys the random numbers)
+    int32_t pad;
+};
+
+struct BlockDesc {
+    int64_t n0, nb, kb;       // first grid point, size, data modes
+    int64_t unused;
+    int64_t nbp;              // row length of the float32 (V, -1/V) rows (lanes x components)
+    int64_t mp;               // row length of the float32 U rows
+    int64_t off_V;            // float64 V, mode-major: V[i*nb + q]
+    int64_t off_U;            // float64 U, mode-major: U[i*M + m]
+    int64_t off_d;            // float64 singular values (kb)
+    int64_t off_VW;           // float32 (V, -1/V) pairs, mode-major, nb x nbp
+    int64_t off_U32;          // float32 U, mode-major, kb x mp
+    int64_t off_d32;          // float32 singular values
+};
+
+struct TileDesc {             // float32 work item: consecutive chains of one problem
+    int32_t problem;
+    int32_t chain0;
+    int32_t nchains;
+    int32_t slot;             // accumulator slot of the tile (batches consecutive slots)
+};
+
+// ------------------------------------------------------------------------------------
+// kernel parameter blocks
+// ------------------------------------------------------------------------------------
+struct SampleArgs {
+    const ProbDesc *probs;
+    const BlockDesc *blocks;
+    const TileDesc *tiles;
+    int64_t ntiles;
+    const double *Kt;
+    const double *gt;
+    const double *V64;
+    const double *U64;
+    const double *d64;
+    const float2 *VW32;
+    const float *U32;
+    const float *d32;
+    float *A32;
+    float *r32;
+    double *A64;
+    double *r64;
+    double *chi2;             // per chain (float64 sampler)
+    double *drift;            // per chain, running max
+    double *accA;             // slots x N (per problem offsets)
+    double *accA2;
+    unsigned long long *counters;  // [0] clamped, [1] frozen
+    int *flags;               // bit 0: unbounded zero mode
+    int *queue;               // tile queue head (float32 sampler)
+    const int64_t *sweep;     // device sweep counter: first sweep of this launch
+    int64_t nsw;              // sweeps in this launch
+    int64_t burnin;           // sweeps before accumulation starts
+    int64_t sweeps;           // accumulated sweeps (for batch means)
+    int64_t refresh_every;    // float64 sampler refreshes inside the kernel
+    uint64_t seed;
+    int32_t accumulate;       // 1: accumulate sweeps >= burnin
+    int32_t pad;
+    int64_t lds_vw;           // float2 elements reserved for (V, -1/V) (max nb * nbp)
+    int64_t lds_nbp;          // row length of the per-chain uniform buffer (max nbp)
+};
+
+// ------------------------------------------------------------------------------------
+// work items of the per-block decomposition
+// ------------------------------------------------------------------------------------
+struct SvdTask {
+    int64_t M, N;        // problem sizes
+    int64_t off_K;       // whitened kernel of the problem
+    int64_t n0, nb;      // block columns
+    int64_t kreq;        // requested data modes, -1 = numerical rank
+    int64_t off_V, off_U, off_d;
+    int64_t off_work;    // float64 scratch of the task
+    int64_t block;       // global block index (kb output)
+};
+
+// ------------------------------------------------------------------------------------
+// launchers (defined next to their kernels)
+// ------------------------------------------------------------------------------------
+// setup.hip
+hipError_t launch_check_finite(const double *x, int64_t n, int *flag, int bit, hipStream_t s);
+hipError_t launch_check_positive(const double *x, int64_t n, int *flag, int bit, hipStream_t s);
+hipError_t launch_whiten_diag(const double *K, const double *G, const double *sigma, int64_t M,
+                              int64_t N, double *Kt, double *gt, hipStream_t s);
+hipError_t launch_cholesky(const double *C, int64_t M, double *L, int *flag, int bit, hipStream_t s);
+hipError_t launch_trsm_lower(const double *L, int64_t M, const double *B, int64_t ncols,
+                             int64_t ldb, double *X, hipStream_t s);
+int64_t svd_work_doubles(int64_t M, int64_t nb);
+hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, const double *Kt,
+                                  double *work, double *V64, double *U64, double *d64,
+                                  int32_t *kb_out, hipStream_t s);
+hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
+                                int64_t nblocks, const double *V64, const double *U64,
+                                const double *d64, float2 *VW32, float *U32, float *d32,
+                                hipStream_t s);
+int64_t nnls_work_doubles(int64_t M, int64_t N);
+hipError_t launch_nnls(const ProbDesc *probs_dev, int64_t P, const int *use, const double *Kt,
+                       const double *gt, double *work, const int64_t *work_off, double blend,
+                       double *init, int *has_init, hipStream_t s);
+hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, const double *Kt,
+                              const double *gt, const double *init, const int *has_init,
+                              double *A64, float *A32, int fp32, hipStream_t s);
+
+// sample.hip
+hipError_t launch_sample64_grid(const SampleArgs &a, int64_t total_chains, const int32_t *chain_problem,
+                                const int32_t *chain_local, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
+                                int grid, size_t lds_bytes, hipStream_t s);
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt);
+hipError_t set_sample32_lds_limit();
+hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s);
+hipError_t launch_reset_queue(int *queue, hipStream_t s);
+hipError_t launch_tn_draw(const double *c, const double *d, const double *lo, const double *hi,
+                          const double *u, double *out, int64_t n, int precision, hipStream_t s);
+hipError_t launch_uniforms(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep0,
+                           int64_t nsweeps, int64_t nblocks, int64_t nmodes, double *out,
+                           hipStream_t s);
+
+// linalg.hip
+hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles,
+                              const double *Kt, const double *gt, const float *A32, float *r32,
+                              const double *A64, double *r64, int fp32, hipStream_t s);
+hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_problem,
+                          const int32_t *chain_local, int64_t total_chains, const float *r32,
+                          const double *r64, int fp32, double *out, const double *prev,
+                          double *drift, hipStream_t s);
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int64_t max_m,
+                            const float *A32, const float *r32, const double *A64,
+                            const double *r64, int fp32, double *cross, double *sumR,
+                            hipStream_t s);
+hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
+                           int64_t total_n, const double *accA, const double *accA2,
+                           const int32_t *slot_group, const double *slot_count, double *mean,
+                           double *stderr_, double *post_sd, hipStream_t s);
+hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
+                      int64_t total_m, const double *cross, const double *sumR,
+                      const double *mean, const double *nsamples, const double *sigma,
+                      const double *Lchol, const double *v, double *y, double *grad,
+                      int any_cov, hipStream_t s);
+hipError_t launch_state64(const ProbDesc *probs_dev, int64_t p, const ProbDesc &ph, const float *A32,
+                          const float *r32, const double *A64, const double *r64,
+                          const double *chi2, int fp32, double *A, double *r, double *chi2_out,
+                          hipStream_t s);
+
+}  // namespace asmk

@@ -1,0 +1,331 @@
+// Float64 kernels over the chain states of all problems:
+//   refresh  -- r = g~ - K~ A for every chain (the residual of Eq. (CompChi)), a dense
+//               (chains x N) x (N x M) contraction on the float64 matrix cores;
+//   cross    -- sum over chains of r A^T (M x N), the cross moment whose centred version
+//               Cov(r~, A) gives the sensitivity of the average to the data;
+//   finalize -- the average of Eq. (MCint), its standard error over independent chain
+//               groups, and the posterior standard deviation;
+//   vjp      -- J^T v with J = d<A>/dG = -Cov(A, r~) T.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace asmk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double load_state(const float *A32, const double *A64, int64_t i, int fp32) {
+    return fp32 ? (double)A32[i] : A64[i];
+}
+
+// D(16 chains x 16 rows) = A(16 x 4 grid points) * K~^T(4 x 16); MFMA f64 16x16x4 layouts:
+// operand a: lane l holds row l%16, k = l/16; operand b: lane l holds column l%16, k = l/16;
+// result: lane l, element j holds row l/16 + 4j, column l%16 (checked on the device).
+__global__ __launch_bounds__(256) void k_refresh(const ProbDesc *probs, const double *Kt,
+                                                 const double *gt, const float *A32, float *r32,
+                                                 const double *A64, double *r64, int fp32) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int64_t M = pd.M, N = pd.N, C = pd.C;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t ntm = (M + 15) / 16, ntc = (C + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= ntm * ntc) return;
+    const int64_t c0 = (tile / ntm) * 16, m0 = (tile % ntm) * 16;
+    const int i = lane % 16, k = lane / 16;
+    const int64_t ca = c0 + i, mb = m0 + i;
+    const double *K = Kt + pd.off_K;
+    const int64_t abase = pd.off_A + ca * N;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const bool ca_ok = ca < C, mb_ok = mb < M;
+    int64_t n0 = 0;
+    for (; n0 + 16 <= N; n0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t n = n0 + 4 * u + k;
+            const double a = ca_ok ? load_state(A32, A64, abase + n, fp32) : 0.0;
+            const double b = mb_ok ? K[mb * N + n] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+    for (; n0 < N; n0 += 4) {
+        const int64_t n = n0 + k;
+        const double a = (ca_ok && n < N) ? load_state(A32, A64, abase + n, fp32) : 0.0;
+        const double b = (mb_ok && n < N) ? K[mb * N + n] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    const int64_t m = m0 + lane % 16;
+    const double *g = gt + pd.off_m;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + lane / 16 + 4 * j;
+        if (c < C && m < M) {
+            const double rv = g[m] - acc[j];
+            const int64_t idx = pd.off_r + c * M + m;
+            if (fp32)
+                r32[idx] = (float)rv;
+            else
+                r64[idx] = rv;
+        }
+    }
+}
+
+// chi2[c] = |r_c|^2 (float64 accumulation); if `drift` is given, the relative change of
+// |r|^2 against prev[c] is folded into drift[c] by a running maximum.
+__global__ __launch_bounds__(64) void k_rownorm(const ProbDesc *probs, const int32_t *chain_problem,
+                                                const int32_t *chain_local, const float *r32,
+                                                const double *r64, int fp32, double *out,
+                                                const double *prev, double *drift) {
+    const ProbDesc pd = probs[chain_problem[blockIdx.x]];
+    const int64_t c = chain_local[blockIdx.x];
+    const int64_t M = pd.M;
+    double s = 0.0;
+    for (int64_t m = threadIdx.x; m < M; m += 64) {
+        const double x = load_state(r32, r64, pd.off_r + c * M + m, fp32);
+        s += x * x;
+    }
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (threadIdx.x == 0) {
+        if (drift) {
+            const double p = prev[pd.off_c + c];
+            const double dr = fabs(p - s) / (s > 0.0 ? s : 1.0);
+            drift[pd.off_c + c] = fmax(drift[pd.off_c + c], dr);
+        }
+        out[pd.off_c + c] = s;
+    }
+}
+
+hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles,
+                              const double *Kt, const double *gt, const float *A32, float *r32,
+                              const double *A64, double *r64, int fp32, hipStream_t s) {
+    const unsigned gx = (unsigned)((max_tiles + 3) / 4);
+    hipLaunchKernelGGL(k_refresh, dim3(gx, (unsigned)P), dim3(256), 0, s, probs_dev, Kt, gt, A32,
+                       r32, A64, r64, fp32);
+    return hipGetLastError();
+}
+
+hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_problem,
+                          const int32_t *chain_local, int64_t total_chains, const float *r32,
+                          const double *r64, int fp32, double *out, const double *prev,
+                          double *drift, hipStream_t s) {
+    hipLaunchKernelGGL(k_rownorm, dim3((unsigned)total_chains), dim3(64), 0, s, probs_dev,
+                       chain_problem, chain_local, r32, r64, fp32, out, prev, drift);
+    return hipGetLastError();
+}
+
+// cross[m][n] += sum_c r[c][m] A[c][n]: D(16 rows m x 16 columns n) over chains in steps of 4.
+__global__ __launch_bounds__(256) void k_cross(const ProbDesc *probs, const float *A32,
+                                               const float *r32, const double *A64,
+                                               const double *r64, int fp32, double *cross) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int64_t M = pd.M, N = pd.N, C = pd.C;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t ntm = (M + 15) / 16, ntn = (N + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= ntm * ntn) return;
+    const int64_t m0 = (tile / ntn) * 16, n0 = (tile % ntn) * 16;
+    const int i = lane % 16, k = lane / 16;
+    const int64_t ma = m0 + i, nb = n0 + i;
+    const bool ma_ok = ma < M, nb_ok = nb < N;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c0 = 0; c0 < C; c0 += 4) {
+        const int64_t c = c0 + k;
+        const double a = (ma_ok && c < C) ? load_state(r32, r64, pd.off_r + c * M + ma, fp32) : 0.0;
+        const double b = (nb_ok && c < C) ? load_state(A32, A64, pd.off_A + c * N + nb, fp32) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    const int64_t n = n0 + lane % 16;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t m = m0 + lane / 16 + 4 * j;
+        if (m < M && n < N) cross[pd.off_cross + m * N + n] += acc[j];
+    }
+}
+
+// sumR[m] += sum_c r[c][m]
+__global__ void k_sum_r(const ProbDesc *probs, const float *r32, const double *r64, int fp32,
+                        double *sumR) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m >= pd.M) return;
+    double s = 0.0;
+    for (int64_t c = 0; c < pd.C; ++c) s += load_state(r32, r64, pd.off_r + c * pd.M + m, fp32);
+    sumR[pd.off_m + m] += s;
+}
+
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int64_t max_m,
+                            const float *A32, const float *r32, const double *A64,
+                            const double *r64, int fp32, double *cross, double *sumR,
+                            hipStream_t s) {
+    const unsigned gx = (unsigned)((max_tiles + 3) / 4);
+    hipLaunchKernelGGL(k_cross, dim3(gx, (unsigned)P), dim3(256), 0, s, probs_dev, A32, r32, A64,
+                       r64, fp32, cross);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_r, dim3((unsigned)((max_m + 127) / 128), (unsigned)P), dim3(128), 0, s,
+                       probs_dev, r32, r64, fp32, sumR);
+    return hipGetLastError();
+}
+
+// One thread per (problem, n): group sums in a fixed order, then mean, standard error over
+// the groups and posterior standard deviation.
+__global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_prefix,
+                           const double *accA, const double *accA2, const int32_t *slot_group,
+                           const double *slot_count, double *mean, double *stderr_,
+                           double *post_sd) {
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gi >= n_prefix[P]) return;
+    int64_t lo = 0, hi = P - 1;   // problem p with n_prefix[p] <= gi < n_prefix[p+1]
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (n_prefix[mid] <= gi) lo = mid; else hi = mid - 1;
+    }
+    const ProbDesc pd = probs[lo];
+    const int64_t n = gi - n_prefix[lo];
+    const int64_t N = pd.N;
+    double gs[64], gc[64];
+    const int G = pd.groups;
+    for (int g = 0; g < G; ++g) gs[g] = gc[g] = 0.0;
+    double s1 = 0.0, s2 = 0.0, tot = 0.0;
+    for (int64_t sl = 0; sl < pd.nslot; ++sl) {
+        const double x1 = accA[pd.off_slot + sl * N + n];
+        const double x2 = accA2[pd.off_slot + sl * N + n];
+        const int g = slot_group[pd.off_tab + sl];
+        const double cnt = slot_count[pd.off_tab + sl];
+        gs[g] += x1;
+        gc[g] += cnt;
+        s1 += x1;
+        s2 += x2;
+        tot += cnt;
+    }
+    const double mu = tot > 0.0 ? s1 / tot : 0.0;
+    double gm_sum = 0.0;
+    int ng = 0;
+    for (int g = 0; g < G; ++g)
+        if (gc[g] > 0.0) {
+            gm_sum += gs[g] / gc[g];
+            ++ng;
+        }
+    const double gbar = ng > 0 ? gm_sum / ng : 0.0;
+    double v = 0.0;
+    for (int g = 0; g < G; ++g)
+        if (gc[g] > 0.0) {
+            const double d = gs[g] / gc[g] - gbar;
+            v += d * d;
+        }
+    const double se = ng > 1 ? sqrt(v / (double)(ng - 1) / (double)ng) : NAN;
+    const double var = tot > 0.0 ? s2 / tot - mu * mu : 0.0;
+    mean[pd.off_n + n] = mu;
+    stderr_[pd.off_n + n] = se;
+    if (post_sd) post_sd[pd.off_n + n] = sqrt(var > 0.0 ? var : 0.0);
+}
+
+hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
+                           int64_t total_n, const double *accA, const double *accA2,
+                           const int32_t *slot_group, const double *slot_count, double *mean,
+                           double *stderr_, double *post_sd, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((total_n + 127) / 128)), dim3(128), 0, s,
+                       probs_dev, P, n_prefix_dev, accA, accA2, slot_group, slot_count, mean,
+                       stderr_, post_sd);
+    return hipGetLastError();
+}
+
+// y_m = (1/S) sum_n cross[m][n] v_n - rbar_m (Abar . v), S = samples of the problem; then
+// grad = -T^T y: -y/sigma for iid noise, or -L^-T y for a covariance C = L L^T.
+__global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix,
+                        const double *cross, const double *sumR, const double *mean,
+                        const double *nsamples, const double *sigma, const double *v, double *y,
+                        double *grad) {
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gi >= m_prefix[P]) return;
+    int64_t lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (m_prefix[mid] <= gi) lo = mid; else hi = mid - 1;
+    }
+    const ProbDesc pd = probs[lo];
+    const int64_t m = gi - m_prefix[lo];
+    const int64_t N = pd.N;
+    const double S = nsamples[lo];
+    const double *X = cross + pd.off_cross + m * N;
+    const double *vv = v + pd.off_n;
+    const double *mu = mean + pd.off_n;
+    double xv = 0.0, av = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        xv += X[n] * vv[n];
+        av += mu[n] * vv[n];
+    }
+    const double rbar = sumR[pd.off_m + m] / S;
+    const double ym = xv / S - rbar * av;
+    y[pd.off_m + m] = ym;
+    if (!pd.has_cov) grad[pd.off_m + m] = -ym / sigma[pd.off_m + m];
+}
+
+// x = L^-T y (back substitution), grad = -x; one workgroup per problem with a covariance.
+__global__ __launch_bounds__(256) void k_vjp_cov(const ProbDesc *probs, const double *Lchol,
+                                                 const double *y, double *grad) {
+    const ProbDesc pd = probs[blockIdx.x];
+    if (!pd.has_cov) return;
+    const int64_t M = pd.M;
+    const double *L = Lchol + pd.off_L;
+    double *x = grad + pd.off_m;   // holds x during the solve, negated at the end
+    __shared__ double red[256];
+    for (int64_t i = M - 1; i >= 0; --i) {
+        double part = 0.0;
+        for (int64_t k = i + 1 + threadIdx.x; k < M; k += blockDim.x) part += L[k * M + i] * x[k];
+        red[threadIdx.x] = part;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) x[i] = (y[pd.off_m + i] - red[0]) / L[i * M + i];
+        __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < M; i += blockDim.x) x[i] = -x[i];
+}
+
+hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
+                      int64_t total_m, const double *cross, const double *sumR,
+                      const double *mean, const double *nsamples, const double *sigma,
+                      const double *Lchol, const double *v, double *y, double *grad,
+                      int any_cov, hipStream_t s) {
+    hipLaunchKernelGGL(k_vjp_y, dim3((unsigned)((total_m + 127) / 128)), dim3(128), 0, s, probs_dev,
+                       P, m_prefix_dev, cross, sumR, mean, nsamples, sigma, v, y, grad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !any_cov) return e;
+    hipLaunchKernelGGL(k_vjp_cov, dim3((unsigned)P), dim3(256), 0, s, probs_dev, Lchol, y, grad);
+    return hipGetLastError();
+}
+
+// float64 copy of one problem's chain state
+__global__ void k_state64(const ProbDesc *probs, int64_t p, const float *A32, const float *r32,
+                          const double *A64, const double *r64, const double *chi2, int fp32,
+                          double *A, double *r, double *chi2_out) {
+    const ProbDesc pd = probs[p];
+    const int64_t tA = pd.C * pd.N, tR = pd.C * pd.M;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tA;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (A) A[i] = load_state(A32, A64, pd.off_A + i, fp32);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tR;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (r) r[i] = load_state(r32, r64, pd.off_r + i, fp32);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pd.C;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (chi2_out) chi2_out[i] = chi2[pd.off_c + i];
+}
+
+hipError_t launch_state64(const ProbDesc *probs_dev, int64_t p, const ProbDesc &ph, const float *A32,
+                          const float *r32, const double *A64, const double *r64,
+                          const double *chi2, int fp32, double *A, double *r, double *chi2_out,
+                          hipStream_t s) {
+    int64_t total = ph.C * (ph.N > ph.M ? ph.N : ph.M);
+    int grid = (int)((total + 255) / 256);
+    if (grid > 2048) grid = 2048;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_state64, dim3(grid), dim3(256), 0, s, probs_dev, p, A32, r32, A64, r64,
+                       chi2, fp32, A, r, chi2_out);
+    return hipGetLastError();
+}
+
+}  // namespace asmk

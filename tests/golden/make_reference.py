@@ -1,0 +1,55 @@
+"""Write the stored oracle averages used by the GPU parity tests.
+
+Only the CPU oracle and the seeded workload generators are called.  Each file holds the
+oracle's average spectrum <A> (the estimate of Eq. (MCint) by blocked modes sampling,
+Sec. IV.C) and its standard error over independent chain groups, for a fixed protocol
+(chains, burn-in, sweeps, seed, start model) that the GPU test repeats with its own chains.
+The config-2 reference starts from the NNLS start of Sec. IV.D, so that both sides average
+over the equilibrated chain rather than over the slow relaxation from a flat start.
+
+    python tests/golden/make_reference.py [cfg1] [cfg2]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+
+PROTOCOLS = {
+    "cfg1": dict(problem="config1", chains=64, burnin=200, sweeps=2000, seed=11, groups=32,
+                 refresh_every=64),
+    "cfg2": dict(problem="config2", chains=64, burnin=500, sweeps=2000, seed=12, groups=32,
+                 refresh_every=64, start="nnls"),
+}
+
+
+def make(name):
+    proto = PROTOCOLS[name]
+    prob = getattr(workloads, proto["problem"])()
+    prep = oracle.prepare(prob)
+    t = time.time()
+    init = oracle.nnls_start(prep) if proto.get("start") == "nnls" else None
+    res = oracle.run(prep, chains=proto["chains"], burnin=proto["burnin"], sweeps=proto["sweeps"],
+                     seed=proto["seed"], groups=proto["groups"], refresh_every=proto["refresh_every"],
+                     init=init)
+    dt = time.time() - t
+    out = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(out, mean=res.mean, stderr=res.stderr, post_sd=res.post_sd,
+                        kb=prep.kb, chi2_final=res.final_chi2)
+    meta = dict(proto, seconds=round(dt, 1), status=res.status, drift_max=res.drift_max,
+                what="oracle <A> and standard error over chain groups (Eq. (MCint), Sec. IV.C)")
+    with open(os.path.join(HERE, f"{name}_oracle.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(name, "done in", round(dt, 1), "s; kb =", list(prep.kb), flush=True)
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(PROTOCOLS)):
+        make(n)

@@ -1,0 +1,346 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Floating-point bars:
+  * float64 primitives and trajectories: 1e-10 relative (the float64 sampler follows the
+    oracle move by move on the same random numbers);
+  * averages: |<A>_gpu - <A>_oracle| / sqrt(SE_gpu^2 + SE_oracle^2) below 4.5 everywhere and
+    above 3 at no more than 1% of the grid points (plus two points of slack for small grids);
+  * float32 draws: within 1e-4 of the interval (or of the Gaussian width when smaller).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_01379_amd as pk
+    return pk
+
+
+def zscore_ok(m1, s1, m2, s2, frac=0.01):
+    z = np.abs(m1 - m2) / np.sqrt(s1 ** 2 + s2 ** 2)
+    z = z[np.isfinite(z)]
+    n3 = int(np.sum(z > 3.0))
+    return float(z.max()) <= 4.5 and n3 <= max(2, int(frac * len(z))), (float(z.max()), n3, len(z))
+
+
+# --------------------------------------------------------------------------------------
+# primitives
+# --------------------------------------------------------------------------------------
+
+def test_uniforms_bit_exact(pk, orc):
+    u = pk.uniforms(1912, 3, 17, 40, 3, 4, 9).cpu().numpy()
+    ref = np.array([[[orc.move_uniform(1912, 3, 17, 40 + s, b, i) for i in range(9)]
+                     for b in range(4)] for s in range(3)])
+    assert np.array_equal(u, ref)
+
+
+def _tn_cases(n=4000, seed=1):
+    rng = np.random.default_rng(seed)
+    c = rng.normal(0, 5, n)
+    d = 10 ** rng.uniform(-9, 3, n)
+    lo = -10 ** rng.uniform(-3, 2, n)
+    hi = 10 ** rng.uniform(-3, 2, n)
+    lo[::7] = -np.inf
+    hi[3::7] = np.inf
+    c[::11] = rng.normal(0, 60, len(c[::11]))
+    u = (np.floor(rng.random(n) * 2 ** 23) + 0.5) * 2.0 ** -23
+    scale = np.minimum(np.where(np.isfinite(hi - lo), hi - lo, np.inf), 1 / d)
+    return c, d, lo, hi, u, scale
+
+
+def test_tn_draw_fp64_matches_oracle(pk, orc):
+    c, d, lo, hi, u, scale = _tn_cases()
+    g = pk.tn_draw(c, d, lo, hi, u, "fp64").cpu().numpy()
+    o = np.array([orc.tn_draw(*x) for x in zip(c, d, lo, hi, u)])
+    assert np.max(np.abs(g - o) / scale) < 1e-10
+
+
+def test_tn_draw_fp32_matches_oracle(pk, orc):
+    c, d, lo, hi, u, scale = _tn_cases(seed=2)
+    g = pk.tn_draw(c, d, lo, hi, u, "fp32").cpu().numpy()
+    o = np.array([orc.tn_draw(*x) for x in zip(c, d, lo, hi, u)])
+    err = np.abs(g - o) / scale
+    assert np.max(err) < 1e-4 and np.median(err) < 1e-6
+
+
+# --------------------------------------------------------------------------------------
+# setup: whitening and block factors
+# --------------------------------------------------------------------------------------
+
+def test_block_factors_match_oracle_svd(pk, orc):
+    p = workloads.config2()
+    prep = orc.prepare(p)
+    plan = pk.Plan([p], chains=16, burnin=0, sweeps=1, precision="fp32", groups=4)
+    Kt, gt = plan.whitened(0)
+    assert np.allclose(Kt.cpu().numpy(), prep.Kt, rtol=1e-14, atol=0)
+    for b in range(p.B):
+        nb = int(p.block_start[b + 1] - p.block_start[b])
+        k, d, U, V = plan.factors(0, b, nb)
+        d, U, V = d.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
+        assert k == prep.kb[b]
+        # singular values above 1e-6 d_1 to 1e-8 relative
+        big = prep.d[b] > 1e-6 * prep.d[b][0]
+        assert np.allclose(d[big], prep.d[b][big], rtol=1e-8)
+        assert np.max(np.abs(V.T @ V - np.eye(nb))) < 1e-12
+        Kb = prep.Kt[:, p.block_start[b]:p.block_start[b + 1]]
+        assert np.max(np.abs(Kb @ V[:, :k] - U * d[None, :])) < 1e-10 * d[0]
+        assert np.linalg.norm(Kb @ V[:, k:]) < 1e-6 * d[0]
+        # leading modes (well separated) equal the oracle's, sign rule included
+        for i in range(4):
+            assert np.max(np.abs(V[:, i] - prep.V[b][:, i])) < 1e-9
+    plan.close()
+
+
+def test_covariance_whitening_matches_oracle(pk, orc):
+    rng = np.random.default_rng(3)
+    M, N = 60, 40
+    tau = workloads.imaginary_times(M, 10.0)
+    x, w = workloads.uniform_midpoint_grid(-4, 4, N)
+    K = workloads.fermionic_kernel(tau, x, 10.0) * w[None, :]
+    C = workloads.exp_covariance(M, 1e-3, 5.0)
+    G = K @ np.full(N, 1.0 / 8) + workloads.ar1_noise(rng, M, 1e-3, 5.0)
+    p = workloads.Problem(K=K, G=G, cov=C, block_start=workloads.equal_blocks(N, 2))
+    prep = orc.prepare(p)
+    plan = pk.Plan([p], chains=16, burnin=0, sweeps=1, precision="fp32", groups=4)
+    Kt, gt = plan.whitened(0)
+    assert np.allclose(Kt.cpu().numpy(), prep.Kt, rtol=1e-9, atol=1e-9 * np.abs(prep.Kt).max())
+    assert np.allclose(gt.cpu().numpy(), prep.gt, rtol=1e-9, atol=1e-9 * np.abs(prep.gt).max())
+    plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# float64 trajectory parity (same random numbers, independent decompositions)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,N,nblocks,seed", [(40, 24, 2, 11), (10, 24, 2, 5), (12, 30, 3, 9)])
+def test_fp64_trajectory_matches_oracle(pk, orc, M, N, nblocks, seed):
+    p = workloads.random_wellconditioned(M=M, N=N, nblocks=nblocks, seed=seed)
+    prep = orc.prepare(p)
+    sweeps = 1000
+    ores = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, refresh_every=16, groups=1,
+                   traj_chain=0, seed=99)
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=1, seed=99, precision="fp64",
+                   refresh_every=16, groups=1)
+    worst = 0.0
+    for s in range(sweeps):
+        plan.advance(1)
+        if s % 10 == 9 or s < 10:
+            A, r, chi2 = plan.state(0)
+            a = A[0].cpu().numpy()
+            ref = ores.traj_A[s]
+            worst = max(worst, np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+            assert abs(float(chi2[0]) - ores.traj_chi2[s]) <= 1e-10 * ores.traj_chi2[s]
+    assert worst < 1e-10, worst
+    plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# averages against the oracle
+# --------------------------------------------------------------------------------------
+
+def _golden(name):
+    z = np.load(os.path.join(HERE, "golden", f"{name}_oracle.npz"))
+    meta = json.load(open(os.path.join(HERE, "golden", f"{name}_oracle.json")))
+    return z, meta
+
+
+def test_plain_fp64_config1_average_matches_oracle(pk):
+    z, meta = _golden("cfg1")
+    p = workloads.config1()
+    plan = pk.Plan([p], chains=meta["chains"], burnin=meta["burnin"], sweeps=meta["sweeps"],
+                   seed=meta["seed"] + 1000, precision="fp64", groups=meta["groups"],
+                   refresh_every=meta["refresh_every"])
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), z["mean"], z["stderr"])
+    assert ok, info
+    assert res.stats["chi2_drift_max"] < 1e-8
+    plan.close()
+
+
+def test_batched_fp32_config2_average_matches_oracle(pk):
+    z, meta = _golden("cfg2")
+    p = workloads.config2()
+    plan = pk.Plan([p], chains=4096, burnin=meta["burnin"], sweeps=meta["sweeps"],
+                   seed=meta["seed"] + 1000, precision="fp32", groups=meta["groups"],
+                   refresh_every=meta["refresh_every"], start=meta["start"])
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), z["mean"], z["stderr"])
+    assert ok, info
+    assert res.stats["chi2_drift_max"] < 1e-2   # float32 residual between refreshes
+    plan.close()
+
+
+def test_nnls_start_matches_scipy(pk, orc):
+    for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
+        prep = orc.prepare(p)
+        ref = orc.nnls_start(prep)
+        plan = pk.Plan([p], chains=2, burnin=0, sweeps=1, precision="fp64", groups=1, start="nnls")
+        A, r, chi2 = plan.state(0)
+        a = A[0].cpu().numpy()
+        assert np.max(np.abs(a - ref)) < 1e-6 * np.max(np.abs(ref)), np.max(np.abs(a - ref))
+        # the start fits the data about as well as the NNLS solution
+        chi_ref = float(np.sum((prep.gt - prep.Kt @ ref) ** 2))
+        assert abs(float(chi2[0]) - chi_ref) < 1e-6 * chi_ref
+        plan.close()
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+def test_batched_fp32_small_problem_matches_oracle(pk, orc, lanes):
+    p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
+    prep = orc.prepare(p)
+    ores = orc.run(prep, chains=64, burnin=300, sweeps=3000, groups=32, seed=3)
+    plan = pk.Plan([p], chains=256, burnin=300, sweeps=3000, seed=4, precision="fp32", groups=32,
+                   lanes_per_chain=lanes)
+    res = plan.run()
+    assert res.stats["lanes_per_chain"] == lanes
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
+    assert ok, info
+    plan.close()
+
+
+def test_fp64_batch_means_with_one_chain(pk, orc):
+    """One chain: error bars from batches of sweeps, as in the oracle."""
+    p = workloads.random_wellconditioned(M=30, N=16, nblocks=2, seed=3)
+    prep = orc.prepare(p)
+    ores = orc.run(prep, chains=1, burnin=200, sweeps=20000, groups=32, seed=5)
+    plan = pk.Plan([p], chains=1, burnin=200, sweeps=20000, seed=5, precision="fp64", groups=32)
+    res = plan.run()
+    # same chain, same random numbers: equal up to rounding
+    assert np.allclose(res.mean.cpu().numpy(), ores.mean, rtol=1e-8, atol=1e-12)
+    assert np.allclose(res.stderr.cpu().numpy(), ores.stderr, rtol=1e-6, atol=1e-12)
+    plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# state consistency and batching
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_carried_residual_matches_recomputed(pk, precision, tol):
+    p = workloads.config2()
+    plan = pk.Plan([p], chains=256, burnin=0, sweeps=1, precision=precision, groups=32,
+                   refresh_every=64)
+    plan.advance(100)   # 36 sweeps after the last refresh
+    A, r, chi2 = plan.state(0)
+    Kt, gt = plan.whitened(0)
+    rr = gt[None, :] - A @ Kt.T
+    assert float((rr - r).abs().max()) <= tol * float(rr.abs().max())
+    assert float(A.min()) >= 0.0
+    plan.close()
+
+
+def test_batched_problems_are_independent(pk):
+    """A problem's chains do not depend on the other problems in the batch."""
+    p0 = workloads.small_problem(M=41, N=48, nblocks=3, seed=1)
+    p1 = workloads.config3_dataset(7)
+    for prec in ("fp32", "fp64"):
+        a = pk.Plan([p0, p1], chains=64, burnin=20, sweeps=100, seed=8, precision=prec, groups=32)
+        ra = a.run()
+        b = pk.Plan([p0], chains=64, burnin=20, sweeps=100, seed=8, precision=prec, groups=32,
+                    lanes_per_chain=a.last.stats["lanes_per_chain"] if prec == "fp32" else 0)
+        rb = b.run()
+        n0 = p0.N
+        assert np.array_equal(ra.mean.cpu().numpy()[:n0], rb.mean.cpu().numpy())
+        a.close()
+        b.close()
+
+
+# --------------------------------------------------------------------------------------
+# sensitivity to the data
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vjp_gaussian_limit_closed_form(pk, orc, precision):
+    p = workloads.gaussian_limit_problem()
+    prep = orc.prepare(p)
+    Kt = prep.Kt
+    cov = np.linalg.inv(Kt.T @ Kt)
+    J = cov @ Kt.T / p.sigma[None, :]
+    v = np.array([1.0, -0.5, 0.25, 2.0])
+    plan = pk.Plan([p], chains=1024, burnin=20, sweeps=400, precision=precision, groups=32,
+                   want_vjp=True, seed=21)
+    res = plan.run()
+    mean = cov @ Kt.T @ prep.gt
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), mean, 0 * mean)
+    assert ok, info
+    g = plan.vjp(v).cpu().numpy()
+    ref = J.T @ v
+    assert np.linalg.norm(g - ref) < 0.02 * np.linalg.norm(ref)
+    plan.close()
+
+
+def test_vjp_fp32_matches_oracle_covariance(pk, orc):
+    p = workloads.small_problem(M=21, N=12, nblocks=2, sigma=1e-2, seed=31)
+    prep = orc.prepare(p)
+    v = np.random.default_rng(7).standard_normal(p.N)
+    ores = orc.run(prep, chains=256, burnin=300, sweeps=4000, groups=32, want_cross=True, seed=1)
+    ref = orc.vjp(ores, v)
+    plan = pk.Plan([p], chains=1024, burnin=300, sweeps=4000, precision="fp32", groups=32,
+                   want_vjp=True, seed=2)
+    plan.run()
+    g = plan.vjp(v).cpu().numpy()
+    assert np.linalg.norm(g - ref) < 0.1 * np.linalg.norm(ref), (g, ref)
+    plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# error reporting
+# --------------------------------------------------------------------------------------
+
+def test_domain_errors(pk):
+    p = workloads.small_problem(M=21, N=12, nblocks=2)
+    bad = workloads.Problem(K=p.K, G=p.G, sigma=-p.sigma, block_start=p.block_start)
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([bad], chains=4, burnin=0, sweeps=1)
+    assert e.value.code == pk.ASM_EDOMAIN
+    K = p.K.copy()
+    K[0, 0] = np.nan
+    bad = workloads.Problem(K=K, G=p.G, sigma=p.sigma, block_start=p.block_start)
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([bad], chains=4, burnin=0, sweeps=1)
+    assert e.value.code == pk.ASM_EDOMAIN
+    C = -np.eye(p.M)
+    bad = workloads.Problem(K=p.K, G=p.G, cov=C, block_start=p.block_start)
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([bad], chains=4, burnin=0, sweeps=1)
+    assert e.value.code == pk.ASM_EDOMAIN
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unbounded_zero_mode_is_reported(pk, precision):
+    K = np.array([[1.0, -1.0]])
+    p = workloads.Problem(K=K, G=np.array([0.0]), sigma=np.array([1.0]),
+                          block_start=np.array([0, 2]))
+    plan = pk.Plan([p], chains=4, burnin=0, sweeps=2, precision=precision, groups=4)
+    with pytest.raises(pk.AsmError) as e:
+        plan.run()
+    assert e.value.code == pk.ASM_EUNBOUNDED
+    plan.close()
+
+
+def test_vjp_needs_want_vjp_and_a_run(pk):
+    p = workloads.small_problem(M=21, N=12, nblocks=2)
+    plan = pk.Plan([p], chains=4, burnin=0, sweeps=2, groups=4)
+    with pytest.raises(pk.AsmError) as e:
+        plan.vjp(np.zeros(p.N))
+    assert e.value.code == pk.ASM_ESTATE
+    plan.close()
+    plan = pk.Plan([p], chains=4, burnin=0, sweeps=2, groups=4, want_vjp=True)
+    with pytest.raises(pk.AsmError) as e:
+        plan.vjp(np.zeros(p.N))
+    assert e.value.code == pk.ASM_ESTATE
+    plan.close()
