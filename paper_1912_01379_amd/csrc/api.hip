@@ -58,6 +58,7 @@ struct asm_plan {
     std::vector<double> slot_count;
     int64_t total_chains = 0, total_n = 0, total_m = 0;
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
+    int ksplit = 1;          // chain splits of the cross-moment partial sums
     int64_t max_nb = 0, max_nbp = 0;
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
@@ -82,7 +83,7 @@ struct asm_plan {
     double *A64 = nullptr, *r64 = nullptr, *chi2 = nullptr, *chi2_prev = nullptr, *drift = nullptr;
     double *accA = nullptr, *accA2 = nullptr, *slot_count_d = nullptr;
     int32_t *slot_group_d = nullptr;
-    double *cross = nullptr, *sumR = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
+    double *cross = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
     unsigned long long *counters = nullptr;
     int *flags = nullptr, *queue = nullptr;
     int64_t *sweep_d = nullptr;
@@ -330,9 +331,8 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         pl->sweep += seg;
         if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
         if (vjp && pl->sweep - 1 >= burnin_abs) {
-            HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->max_m, pl->A32,
-                                    pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->sumR,
-                                    pl->stream));
+            HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->ksplit, pl->A32,
+                                    pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->stream));
         }
     }
     return ASM_OK;
@@ -462,10 +462,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         offr += C * q.M;
         offc += C;
         if (pd.has_cov) offL += q.M * q.M;
-        if (o->want_vjp) offcross += q.M * q.N;
         pl->max_m = std::max(pl->max_m, q.M);
         pl->max_refresh_tiles = std::max(pl->max_refresh_tiles, ((C + 15) / 16) * ((q.M + 15) / 16));
-        pl->max_cross_tiles = std::max(pl->max_cross_tiles, ((q.M + 15) / 16) * ((q.N + 15) / 16));
+        pl->max_cross_tiles = std::max(pl->max_cross_tiles, ((q.M + 31) / 32) * ((q.N + 32) / 32));
         pl->n_prefix.push_back(offn);
         pl->m_prefix.push_back(offm);
         pl->probs.push_back(pd);
@@ -473,6 +472,15 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->total_chains = offc;
     pl->total_n = offn;
     pl->total_m = offm;
+    if (o->want_vjp) {
+        // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
+        const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
+        pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, C / 8}));
+        for (auto &pd : pl->probs) {
+            pd.off_cross = offcross;
+            offcross += (int64_t)pl->ksplit * pd.M * (pd.N + 1);
+        }
+    }
 
     // ---- allocations ----
     double *work = nullptr, *tmpN = nullptr;
@@ -513,7 +521,6 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     if (o->want_vjp) {
         STEP(dalloc(pl, &pl->cross, offcross));
-        STEP(dalloc(pl, &pl->sumR, offm));
         STEP(dalloc(pl, &pl->nsamples, n));
         STEP(dalloc(pl, &pl->vjp_y, offm));
     }
@@ -765,11 +772,10 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     HIPCHK(hipMemsetAsync(pl->accA, 0, slot_elems * sizeof(double), st));
     HIPCHK(hipMemsetAsync(pl->accA2, 0, slot_elems * sizeof(double), st));
     HIPCHK(hipMemsetAsync(pl->counters, 0, 2 * sizeof(unsigned long long), st));
-    int64_t crossn = 0;
     if (pl->opt.want_vjp) {
-        for (auto &pd : pl->probs) crossn += pd.M * pd.N;
+        const ProbDesc &lp = pl->probs.back();
+        const int64_t crossn = lp.off_cross + (int64_t)pl->ksplit * lp.M * (lp.N + 1);
         HIPCHK(hipMemsetAsync(pl->cross, 0, crossn * sizeof(double), st));
-        HIPCHK(hipMemsetAsync(pl->sumR, 0, pl->total_m * sizeof(double), st));
     }
     HIPCHK(hipEventRecord(pl->ev[2], st));
     const int64_t burnin_abs = pl->sweep + pl->opt.burnin;
@@ -841,7 +847,7 @@ int asm_plan_vjp(asm_plan *pl, const double *v, double *grad_G) {
     hipStream_t st = pl->stream;
     HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2,
                            pl->slot_group_d, pl->slot_count_d, mean, se, nullptr, st));
-    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->cross, pl->sumR, mean,
+    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->ksplit, pl->cross, mean,
                       pl->nsamples, pl->sigma, pl->Lc, v, pl->vjp_y, grad_G, pl->any_cov ? 1 : 0, st));
     HIPCHK(hipStreamSynchronize(st));
     // release the scratch again

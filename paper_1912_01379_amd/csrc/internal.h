@@ -23,7 +23,7 @@ struct ProbDesc {
     int64_t off_r;            // chain state r: C x M
     int64_t off_c;            // per-chain scalars (chi2, drift): C
     int64_t off_blk;          // first block in the block table
-    int64_t off_cross;        // M x N cross moment sum_s r A^T
+    int64_t off_cross;        // ksplit x M x (N+1) partial cross moments sum r [A, 1]^T
     int64_t off_L;            // Cholesky factor (M x M) when whitened with a covariance
     int64_t off_slot;         // element offset of the problem's accumulator slots (slots x N)
     int64_t off_tab;          // first entry of the problem in the slot tables
@@ -157,19 +157,17 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
                           const int32_t *chain_local, int64_t total_chains, const float *r32,
                           const double *r64, int fp32, double *out, const double *prev,
                           double *drift, hipStream_t s);
-hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int64_t max_m,
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
                             const float *A32, const float *r32, const double *A64,
-                            const double *r64, int fp32, double *cross, double *sumR,
-                            hipStream_t s);
+                            const double *r64, int fp32, double *cross, hipStream_t s);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,
                            double *stderr_, double *post_sd, hipStream_t s);
 hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
-                      int64_t total_m, const double *cross, const double *sumR,
-                      const double *mean, const double *nsamples, const double *sigma,
-                      const double *Lchol, const double *v, double *y, double *grad,
-                      int any_cov, hipStream_t s);
+                      int64_t total_m, int ksplit, const double *cross, const double *mean,
+                      const double *nsamples, const double *sigma, const double *Lchol,
+                      const double *v, double *y, double *grad, int any_cov, hipStream_t s);
 hipError_t launch_state64(const ProbDesc *probs_dev, int64_t p, const ProbDesc &ph, const float *A32,
                           const float *r32, const double *A64, const double *r64,
                           const double *chi2, int fp32, double *A, double *r, double *chi2_out,

@@ -113,57 +113,65 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
     return hipGetLastError();
 }
 
-// cross[m][n] += sum_c r[c][m] A[c][n]: D(16 rows m x 16 columns n) over chains in steps of 4.
-__global__ __launch_bounds__(256) void k_cross(const ProbDesc *probs, const float *A32,
-                                               const float *r32, const double *A64,
-                                               const double *r64, int fp32, double *cross) {
-    const ProbDesc pd = probs[blockIdx.y];
-    const int64_t M = pd.M, N = pd.N, C = pd.C;
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int64_t ntm = (M + 15) / 16, ntn = (N + 15) / 16;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+// Cross moment of one sweep, added to per-split float64 partial sums:
+//   X_k[m][n] += sum_{c in split k} r[c][m] A[c][n]  for n < N, and X_k[m][N] += sum r[c][m]
+// (the last column treats A as having an extra component equal to one).  One wavefront owns
+// a 32 x 32 tile of one split (2 x 2 MFMA f64 16x16x4 blocks), so the partial sums are
+// updated without atomics and the order of every addition is fixed.
+__device__ __forceinline__ double cross_b(const float *A32, const double *A64, int fp32, int64_t base,
+                                          int64_t n, int64_t N, bool ok) {
+    if (!ok) return 0.0;
+    if (n == N) return 1.0;
+    return load_state(A32, A64, base + n, fp32);
+}
+
+__global__ __launch_bounds__(64) void k_cross(const ProbDesc *probs, int ksplit, const float *A32,
+                                              const float *r32, const double *A64, const double *r64,
+                                              int fp32, double *cross) {
+    const ProbDesc pd = probs[blockIdx.z];
+    const int64_t M = pd.M, N = pd.N, C = pd.C, N1 = N + 1;
+    const int64_t ntm = (M + 31) / 32, ntn = (N1 + 31) / 32;
+    const int64_t tile = blockIdx.x;
     if (tile >= ntm * ntn) return;
-    const int64_t m0 = (tile / ntn) * 16, n0 = (tile % ntn) * 16;
+    const int split = blockIdx.y;
+    const int64_t m0 = (tile / ntn) * 32, n0 = (tile % ntn) * 32;
+    const int64_t c_lo = C * split / ksplit, c_hi = C * (split + 1) / ksplit;
+    const int lane = threadIdx.x;
     const int i = lane % 16, k = lane / 16;
-    const int64_t ma = m0 + i, nb = n0 + i;
-    const bool ma_ok = ma < M, nb_ok = nb < N;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t c0 = 0; c0 < C; c0 += 4) {
+    const int64_t ma0 = m0 + i, ma1 = m0 + 16 + i;
+    const int64_t nb0 = n0 + i, nb1 = n0 + 16 + i;
+    const bool okm0 = ma0 < M, okm1 = ma1 < M, okn0 = nb0 < N1, okn1 = nb1 < N1;
+    d4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a10 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+    for (int64_t c0 = c_lo; c0 < c_hi; c0 += 4) {
         const int64_t c = c0 + k;
-        const double a = (ma_ok && c < C) ? load_state(r32, r64, pd.off_r + c * M + ma, fp32) : 0.0;
-        const double b = (nb_ok && c < C) ? load_state(A32, A64, pd.off_A + c * N + nb, fp32) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        const bool okc = c < c_hi;
+        const int64_t rb = pd.off_r + c * M, ab = pd.off_A + c * N;
+        const double r0 = (okc && okm0) ? load_state(r32, r64, rb + ma0, fp32) : 0.0;
+        const double r1 = (okc && okm1) ? load_state(r32, r64, rb + ma1, fp32) : 0.0;
+        const double b0 = cross_b(A32, A64, fp32, ab, nb0, N, okc && okn0);
+        const double b1 = cross_b(A32, A64, fp32, ab, nb1, N, okc && okn1);
+        a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0, b0, a00, 0, 0, 0);
+        a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0, b1, a01, 0, 0, 0);
+        a10 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1, b0, a10, 0, 0, 0);
+        a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1, b1, a11, 0, 0, 0);
     }
-    const int64_t n = n0 + lane % 16;
+    double *X = cross + pd.off_cross + (int64_t)split * M * N1;
+    const int64_t col0 = n0 + lane % 16, col1 = col0 + 16;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int64_t m = m0 + lane / 16 + 4 * j;
-        if (m < M && n < N) cross[pd.off_cross + m * N + n] += acc[j];
+        const int64_t row0 = m0 + lane / 16 + 4 * j, row1 = row0 + 16;
+        if (row0 < M && col0 < N1) X[row0 * N1 + col0] += a00[j];
+        if (row0 < M && col1 < N1) X[row0 * N1 + col1] += a01[j];
+        if (row1 < M && col0 < N1) X[row1 * N1 + col0] += a10[j];
+        if (row1 < M && col1 < N1) X[row1 * N1 + col1] += a11[j];
     }
 }
 
-// sumR[m] += sum_c r[c][m]
-__global__ void k_sum_r(const ProbDesc *probs, const float *r32, const double *r64, int fp32,
-                        double *sumR) {
-    const ProbDesc pd = probs[blockIdx.y];
-    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (m >= pd.M) return;
-    double s = 0.0;
-    for (int64_t c = 0; c < pd.C; ++c) s += load_state(r32, r64, pd.off_r + c * pd.M + m, fp32);
-    sumR[pd.off_m + m] += s;
-}
-
-hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int64_t max_m,
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
                             const float *A32, const float *r32, const double *A64,
-                            const double *r64, int fp32, double *cross, double *sumR,
-                            hipStream_t s) {
-    const unsigned gx = (unsigned)((max_tiles + 3) / 4);
-    hipLaunchKernelGGL(k_cross, dim3(gx, (unsigned)P), dim3(256), 0, s, probs_dev, A32, r32, A64,
-                       r64, fp32, cross);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_r, dim3((unsigned)((max_m + 127) / 128), (unsigned)P), dim3(128), 0, s,
-                       probs_dev, r32, r64, fp32, sumR);
+                            const double *r64, int fp32, double *cross, hipStream_t s) {
+    hipLaunchKernelGGL(k_cross, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(64), 0, s,
+                       probs_dev, ksplit, A32, r32, A64, r64, fp32, cross);
     return hipGetLastError();
 }
 
@@ -230,12 +238,12 @@ hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *
     return hipGetLastError();
 }
 
-// y_m = (1/S) sum_n cross[m][n] v_n - rbar_m (Abar . v), S = samples of the problem; then
-// grad = -T^T y: -y/sigma for iid noise, or -L^-T y for a covariance C = L L^T.
-__global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix,
-                        const double *cross, const double *sumR, const double *mean,
-                        const double *nsamples, const double *sigma, const double *v, double *y,
-                        double *grad) {
+// y_m = (1/S) sum_n X[m][n] v_n - rbar_m (Abar . v) with X summed over the splits and
+// rbar_m = X[m][N] / S; then grad = -T^T y: -y/sigma for iid noise, or -L^-T y for a
+// covariance C = L L^T.
+__global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix, int ksplit,
+                        const double *cross, const double *mean, const double *nsamples,
+                        const double *sigma, const double *v, double *y, double *grad) {
     const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gi >= m_prefix[P]) return;
     int64_t lo = 0, hi = P - 1;
@@ -245,18 +253,18 @@ __global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefi
     }
     const ProbDesc pd = probs[lo];
     const int64_t m = gi - m_prefix[lo];
-    const int64_t N = pd.N;
+    const int64_t N = pd.N, N1 = N + 1, M = pd.M;
     const double S = nsamples[lo];
-    const double *X = cross + pd.off_cross + m * N;
     const double *vv = v + pd.off_n;
     const double *mu = mean + pd.off_n;
-    double xv = 0.0, av = 0.0;
-    for (int64_t n = 0; n < N; ++n) {
-        xv += X[n] * vv[n];
-        av += mu[n] * vv[n];
+    double xv = 0.0, av = 0.0, rs = 0.0;
+    for (int k = 0; k < ksplit; ++k) {
+        const double *X = cross + pd.off_cross + (int64_t)k * M * N1 + m * N1;
+        for (int64_t n = 0; n < N; ++n) xv += X[n] * vv[n];
+        rs += X[N];
     }
-    const double rbar = sumR[pd.off_m + m] / S;
-    const double ym = xv / S - rbar * av;
+    for (int64_t n = 0; n < N; ++n) av += mu[n] * vv[n];
+    const double ym = xv / S - (rs / S) * av;
     y[pd.off_m + m] = ym;
     if (!pd.has_cov) grad[pd.off_m + m] = -ym / sigma[pd.off_m + m];
 }
@@ -286,12 +294,11 @@ __global__ __launch_bounds__(256) void k_vjp_cov(const ProbDesc *probs, const do
 }
 
 hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
-                      int64_t total_m, const double *cross, const double *sumR,
-                      const double *mean, const double *nsamples, const double *sigma,
-                      const double *Lchol, const double *v, double *y, double *grad,
-                      int any_cov, hipStream_t s) {
+                      int64_t total_m, int ksplit, const double *cross, const double *mean,
+                      const double *nsamples, const double *sigma, const double *Lchol,
+                      const double *v, double *y, double *grad, int any_cov, hipStream_t s) {
     hipLaunchKernelGGL(k_vjp_y, dim3((unsigned)((total_m + 127) / 128)), dim3(128), 0, s, probs_dev,
-                       P, m_prefix_dev, cross, sumR, mean, nsamples, sigma, v, y, grad);
+                       P, m_prefix_dev, ksplit, cross, mean, nsamples, sigma, v, y, grad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !any_cov) return e;
     hipLaunchKernelGGL(k_vjp_cov, dim3((unsigned)P), dim3(256), 0, s, probs_dev, Lchol, y, grad);
