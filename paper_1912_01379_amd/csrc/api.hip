@@ -59,7 +59,9 @@ struct asm_plan {
     int64_t total_chains = 0, total_n = 0, total_m = 0;
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
     int ksplit = 1;          // chain splits of the cross-moment partial sums
-    int64_t max_nb = 0, max_nbp = 0;
+    int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
+    int64_t lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS layout
+    int u_lds = 0, acc_lds = 0;
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
     int lanes = 16, chains_per_wg = 16, grid32 = 0;
@@ -260,8 +262,11 @@ SampleArgs make_args(asm_plan *pl) {
     a.queue = pl->queue;
     a.sweep = pl->sweep_d;
     a.seed = pl->opt.seed;
-    a.lds_vw = pl->max_nb * pl->max_nbp;
-    a.lds_nbp = pl->max_nbp;
+    a.lds_off_u = pl->lds_off_u;
+    a.lds_off_unif = pl->lds_off_unif;
+    a.lds_off_acc = pl->lds_off_acc;
+    a.u_lds = pl->u_lds;
+    a.acc_lds = pl->acc_lds;
     return a;
 }
 
@@ -393,7 +398,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->P = n;
     pl->fp32 = o->precision == ASM_FP32;
     for (auto &e : pl->ev) HSTEP(hipEventCreate(&e));
-    (void)set_sample32_lds_limit();
+    (void)set_sample32_lds_limit(160 * 1024);
+    (void)set_sample64_lds_limit();
     (void)hipGetLastError();
 
     // ---- sizes and offsets ----
@@ -659,17 +665,44 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         STEP(dalloc(pl, &pl->VW32, offVW));
         STEP(dalloc(pl, &pl->U32, offU32));
         STEP(dalloc(pl, &pl->d32, offd32));
-        // chains per workgroup: within the LDS budget and at most 512 threads
-        const size_t vw_bytes = (size_t)pl->max_nb * row * sizeof(float2);
+        // LDS of a workgroup: the block's (V, -1/V) rows (two spare rows for the row loaded
+        // ahead), then its U rows when they fit, then one uniform row per chain, then the
+        // float64 per-tile sums when they fit and no problem uses batch means.
+        int64_t max_kb = 0, max_n = 0;
+        bool batch_means = false;
+        for (auto &bd : pl->blocks) max_kb = std::max(max_kb, bd.kb);
+        for (auto &pd : pl->probs) {
+            max_n = std::max(max_n, pd.N);
+            batch_means |= pd.batches > 1;
+        }
+        pl->max_kb = max_kb;
+        pl->max_n = max_n;
+        const size_t vw_bytes = (size_t)(pl->max_nb + 2) * row * sizeof(float2);
+        const size_t u_bytes = (size_t)max_kb * mp * sizeof(float);
+        const size_t acc_bytes = (size_t)2 * max_n * sizeof(double);
+        auto layout = [&](int cpw, bool with_u, bool with_acc) {
+            size_t off = vw_bytes;
+            pl->lds_off_u = (int64_t)off;
+            if (with_u) off += u_bytes;
+            off = (off + 15) / 16 * 16;
+            pl->lds_off_unif = (int64_t)off;
+            off += (size_t)cpw * row * sizeof(float);
+            off = (off + 15) / 16 * 16;
+            pl->lds_off_acc = (int64_t)off;
+            if (with_acc) off += acc_bytes;
+            return off;
+        };
+        // chains per workgroup: enough workgroups for every CU, at most 512 threads
         int cpw = 512 / L;
         while (cpw > 64 / L) {
-            const size_t lds = vw_bytes + (size_t)cpw * row * sizeof(float);
             const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
-            if (lds <= kLdsBudget && wgs >= max_cu) break;
+            if (layout(cpw, false, false) <= kLdsBudget && wgs >= max_cu) break;
             cpw /= 2;
         }
         pl->chains_per_wg = cpw;
-        pl->lds32 = vw_bytes + (size_t)cpw * row * sizeof(float);
+        pl->u_lds = layout(cpw, true, false) <= kLdsBudget ? 1 : 0;
+        pl->acc_lds = (!batch_means && layout(cpw, pl->u_lds, true) <= kLdsBudget) ? 1 : 0;
+        pl->lds32 = layout(cpw, pl->u_lds, pl->acc_lds);
         if (pl->lds32 > kLdsBudget) {
             rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
             return rc;

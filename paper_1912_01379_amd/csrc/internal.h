@@ -90,8 +90,11 @@ struct SampleArgs {
     uint64_t seed;
     int32_t accumulate;       // 1: accumulate sweeps >= burnin
     int32_t pad;
-    int64_t lds_vw;           // float2 elements reserved for (V, -1/V) (max nb * nbp)
-    int64_t lds_nbp;          // row length of the per-chain uniform buffer (max nbp)
+    int64_t lds_off_u;        // byte offsets in the float32 sampler's LDS: U rows,
+    int64_t lds_off_unif;     //   per-chain uniform rows,
+    int64_t lds_off_acc;      //   float64 per-tile sums (2 x max N)
+    int32_t u_lds;            // 1: U rows are staged in LDS (else read from global memory)
+    int32_t acc_lds;          // 1: accumulate in LDS and flush once per tile and launch
 };
 
 // ------------------------------------------------------------------------------------
@@ -137,10 +140,22 @@ hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, const double
 // sample.hip
 hipError_t launch_sample64_grid(const SampleArgs &a, int64_t total_chains, const int32_t *chain_problem,
                                 const int32_t *chain_local, size_t lds_bytes, hipStream_t s);
+hipError_t set_sample64_lds_limit();
+
+// sample32*.hip: the compiled float32 instances (lanes per chain L, components per lane
+// EPT, residual entries per lane RPT)
 hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
                                 int grid, size_t lds_bytes, hipStream_t s);
 int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt);
-hipError_t set_sample32_lds_limit();
+hipError_t set_sample32_lds_limit(int bytes);
+hipError_t launch_sample32_l4(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t launch_sample32_l8(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t launch_sample32_l16(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t launch_sample32_l32(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t allow_lds_sample32_l4(int bytes);
+hipError_t allow_lds_sample32_l8(int bytes);
+hipError_t allow_lds_sample32_l16(int bytes);
+hipError_t allow_lds_sample32_l32(int bytes);
 hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s);
 hipError_t launch_reset_queue(int *queue, hipStream_t s);
 hipError_t launch_tn_draw(const double *c, const double *d, const double *lo, const double *hi,

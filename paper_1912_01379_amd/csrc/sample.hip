@@ -11,13 +11,13 @@
 //   5. data mode: r -= delta d_i U_i (K~_b V_i = d_i U_i), chi^2 += e (e - 2c), e = delta d_i.
 //
 // sample64: one wavefront per chain, float64 state (the plain sampler; reproduces the CPU
-// reference trajectory).  sample32: many chains per workgroup, `L` lanes per chain, float32
-// state, the block's (V, -1/V) staged in LDS and shared by all chains of the workgroup.
+// reference trajectory).  The batched float32 sampler is in sample32.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "internal.h"
 #include "rng_tn.h"
+#include "tn32.h"
 
 namespace asmk {
 
@@ -157,257 +157,7 @@ hipError_t launch_sample64_grid(const SampleArgs &a, int64_t total_chains, const
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------------------
-// float32 batched sampler
-// ------------------------------------------------------------------------------------
-// Reductions over the L lanes of one chain (the lanes are contiguous and L divides 16 for
-// the DPP steps); every lane ends with the same bits.  `update_dpp` with the identity of
-// the operation as the old value lets the compiler fold each move into the min/add.
-template <int L>
-__device__ __forceinline__ uint32_t seg_umin(uint32_t x) {
-    if constexpr (L >= 2) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0xB1, 0xF, 0xF, false));
-    if constexpr (L >= 4) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x4E, 0xF, 0xF, false));
-    if constexpr (L >= 8) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x141, 0xF, 0xF, false));
-    if constexpr (L >= 16) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x140, 0xF, 0xF, false));
-    if constexpr (L >= 32) x = min(x, (uint32_t)__shfl_xor((int)x, 16));
-    if constexpr (L >= 64) x = min(x, (uint32_t)__shfl_xor((int)x, 32));
-    return x;
-}
-
-template <int L>
-__device__ __forceinline__ float seg_sum(float x) {
-    if constexpr (L >= 2) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-    if constexpr (L >= 4) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
-    if constexpr (L >= 8) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
-    if constexpr (L >= 16) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
-    if constexpr (L >= 32) x += __shfl_xor(x, 16);
-    if constexpr (L >= 64) x += __shfl_xor(x, 32);
-    return x;
-}
-
-// Interval of Eq. (modeLimits) for one mode from the lane's EPT components.  With
-// x_q = A_q * (-1/V_qi) and A_q >= +0, the sign bit of x_q is set exactly when V_qi > 0,
-// so the lower limit is -min over those |x_q| and the upper limit the min over the rest;
-// both are unsigned minima of the bit patterns.  Padding entries carry a NaN ratio, whose
-// patterns lie above +inf in either search, so they never win.
-template <int L, int EPT>
-__device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float (&Ar)[EPT], float &lo,
-                                           float &hi) {
-    uint32_t hb = 0xFFFFFFFFu, lb = 0xFFFFFFFFu;
-#pragma unroll
-    for (int t = 0; t < EPT; ++t) {
-        const uint32_t bits = __float_as_uint(Ar[t] * vw[t].y);
-        hb = min(hb, bits);
-        lb = min(lb, bits ^ 0x80000000u);
-    }
-    hb = seg_umin<L>(hb);
-    lb = seg_umin<L>(lb);
-    hi = hb >= 0x7F800000u ? INFINITY : __uint_as_float(hb);
-    lo = lb >= 0x7F800000u ? -INFINITY : -__uint_as_float(lb);
-}
-
-// Kept out of line: the inverse-CDF draw is long and only data modes need it, so its
-// registers are not added to those of the move loop.
-__device__ __noinline__ float tn_draw32(float c, float d, float lo, float hi, float u) {
-    return tn_draw_fast32(c, d, lo, hi, u);
-}
-
-// L lanes per chain; every lane owns EPT components of the current block (q = lane + L t)
-// and RPT residual entries (m = lane + L t).  Block rows are padded to EPT*L with the
-// neutral pair (0, NaN), U rows to RPT*L with zeros, so no lane ever branches on a size.
-template <int L, int EPT, int RPT>
-__global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
-    extern __shared__ __align__(16) unsigned char smem32[];
-    constexpr int ROW = EPT * L;
-    constexpr int MP = RPT * L;
-    const int tid = threadIdx.x;
-    const int lane = tid % L;
-    const int slotc = tid / L;
-    float2 *sVW = reinterpret_cast<float2 *>(smem32);
-    float *sUnif = reinterpret_cast<float *>(sVW + a.lds_vw);   // chains x ROW
-    __shared__ int s_tile;
-    const int64_t s0 = *a.sweep;
-    const int64_t nsw = a.nsw;
-
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int tile = s_tile;
-        __syncthreads();
-        if (tile >= a.ntiles) break;
-        const TileDesc td = a.tiles[tile];
-        const ProbDesc pd = a.probs[td.problem];
-        const int M = (int)pd.M;
-        const int64_t N = pd.N;
-        const bool active = slotc < td.nchains;
-        const int64_t chain = td.chain0 + (active ? slotc : 0);
-        float *Ag = a.A32 + pd.off_A + chain * N;
-        float *rg = a.r32 + pd.off_r + chain * (int64_t)M;
-        float rr[RPT];
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-            const int m = lane + L * t;
-            rr[t] = (m < M && active) ? rg[m] : 0.0f;
-        }
-        bool unbounded = false;
-        float *urow = sUnif + slotc * ROW;
-
-        for (int64_t s = s0; s < s0 + nsw; ++s) {
-            for (int64_t b = 0; b < pd.B; ++b) {
-                const BlockDesc bd = a.blocks[pd.off_blk + b];
-                const int nb = (int)bd.nb, kb = (int)bd.kb;
-                __syncthreads();
-                {   // stage the block's (V, -1/V) rows
-                    const float4 *src = reinterpret_cast<const float4 *>(a.VW32 + bd.off_VW);
-                    float4 *dst = reinterpret_cast<float4 *>(sVW);
-                    const int n4 = nb * ROW / 2;
-                    for (int i = tid; i < n4; i += blockDim.x) dst[i] = src[i];
-                }
-                // this block's uniforms: one Philox call per four modes
-                for (int g = lane; 4 * g < nb; g += L) {
-                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
-                                              (uint32_t)b, (uint32_t)g);
-                    float *d = urow + 4 * g;
-                    d[0] = word_u32(w.x);
-                    d[1] = word_u32(w.y);
-                    d[2] = word_u32(w.z);
-                    d[3] = word_u32(w.w);
-                }
-                __syncthreads();
-                float Ar[EPT];
-#pragma unroll
-                for (int t = 0; t < EPT; ++t) {
-                    const int q = lane + L * t;
-                    Ar[t] = (q < nb && active) ? Ag[bd.n0 + q] : 0.0f;
-                }
-                const float *U = a.U32 + bd.off_U32;
-                const float *dv = a.d32 + bd.off_d32;
-                float2 vw[EPT];
-#pragma unroll
-                for (int t = 0; t < EPT; ++t) vw[t] = sVW[lane + L * t];
-                for (int i = 0; i < nb; ++i) {
-                    // next row, loaded while this move is computed
-                    const float2 *nrow = sVW + (i + 1 < nb ? i + 1 : i) * ROW;
-                    float2 vn[EPT];
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) vn[t] = nrow[lane + L * t];
-                    float lo, hi;
-                    interval32<L, EPT>(vw, Ar, lo, hi);
-                    const float u = urow[i];
-                    float delta;
-                    if (i < kb) {
-                        const float *Ui = U + i * MP;
-                        float cp = 0.0f;
-#pragma unroll
-                        for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[lane + L * t], rr[t], cp);
-                        const float cdot = seg_sum<L>(cp);
-                        const float dd = dv[i];
-                        delta = tn_draw32(cdot, dd, lo, hi, u);
-                        const float e = delta * dd;
-#pragma unroll
-                        for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[lane + L * t], rr[t]);
-                    } else {
-                        const bool inf = __builtin_isinf(lo) || __builtin_isinf(hi);
-                        unbounded |= inf;
-                        delta = inf ? 0.0f : fmaf(u, hi - lo, lo);
-                    }
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) {
-                        Ar[t] = fmaxf(fmaf(delta, vw[t].x, Ar[t]), 0.0f);
-                        vw[t] = vn[t];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < EPT; ++t) {
-                    const int q = lane + L * t;
-                    if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
-                }
-                if (a.accumulate && s >= a.burnin) {
-                    // per-tile sums over the tile's chains, float64, owned by this workgroup
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) urow[lane + L * t] = active ? Ar[t] : 0.0f;
-                    __syncthreads();
-                    int64_t slot = td.slot;
-                    if (pd.batches > 1) slot += (s - a.burnin) * pd.batches / a.sweeps;
-                    double *s1 = a.accA + pd.off_slot + slot * N + bd.n0;
-                    double *s2 = a.accA2 + pd.off_slot + slot * N + bd.n0;
-                    for (int q = tid; q < nb; q += blockDim.x) {
-                        double x1 = 0.0, x2 = 0.0;
-                        for (int cs = 0; cs < td.nchains; ++cs) {
-                            const double x = (double)sUnif[cs * ROW + q];
-                            x1 += x;
-                            x2 += x * x;
-                        }
-                        s1[q] += x1;
-                        s2[q] += x2;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-            const int m = lane + L * t;
-            if (active && m < M) rg[m] = rr[t];
-        }
-        if (unbounded) atomicOr(a.flags, 1);
-    }
-}
-
-// The compiled instances: (lanes per chain, components per lane, residual entries per lane).
-struct Inst32 {
-    int L, EPT, RPT;
-};
-static const Inst32 kInst32[] = {{16, 7, 16}, {16, 8, 32}, {16, 2, 4}, {8, 13, 32}, {8, 16, 64},
-                                 {4, 32, 32}, {32, 4, 16}};
-
-int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt) {
-    int best = -1;
-    for (int k = 0; k < (int)(sizeof kInst32 / sizeof kInst32[0]); ++k) {
-        const Inst32 &c = kInst32[k];
-        if (c.L != lanes || (int64_t)c.EPT * c.L < max_nb || (int64_t)c.RPT * c.L < max_m) continue;
-        if (best < 0 || c.EPT * 4 + c.RPT < kInst32[best].EPT * 4 + kInst32[best].RPT) best = k;
-    }
-    if (best < 0) return -1;
-    *ept = kInst32[best].EPT;
-    *rpt = kInst32[best].RPT;
-    return 0;
-}
-
-template <int L, int EPT, int RPT>
-static hipError_t launch_one(const SampleArgs &a, int threads, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_sample32<L, EPT, RPT>), dim3(grid), dim3(threads), lds, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
-                                int grid, size_t lds_bytes, hipStream_t s) {
-    const int threads = lanes * chains_per_wg;
-    if (threads % 64 != 0 || threads > 512) return hipErrorInvalidValue;
-#define INST(L_, E_, R_) \
-    if (lanes == L_ && ept == E_ && rpt == R_) return launch_one<L_, E_, R_>(a, threads, grid, lds_bytes, s);
-    INST(16, 7, 16)
-    INST(16, 8, 32)
-    INST(16, 2, 4)
-    INST(8, 13, 32)
-    INST(8, 16, 64)
-    INST(4, 32, 32)
-    INST(32, 4, 16)
-#undef INST
-    return hipErrorInvalidValue;
-}
-
-hipError_t set_sample32_lds_limit() {
-    // allow up to 160 KB of LDS per workgroup on gfx950 (best effort)
-#define ATTR(L_, E_, R_) \
-    (void)hipFuncSetAttribute((const void *)k_sample32<L_, E_, R_>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    ATTR(16, 7, 16)
-    ATTR(16, 8, 32)
-    ATTR(16, 2, 4)
-    ATTR(8, 13, 32)
-    ATTR(8, 16, 64)
-    ATTR(4, 32, 32)
-    ATTR(32, 4, 16)
-#undef ATTR
+hipError_t set_sample64_lds_limit() {
     return hipFuncSetAttribute((const void *)k_sample64, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024);
 }
@@ -443,8 +193,8 @@ __global__ void k_tn_draw(const double *c, const double *d, const double *lo, co
     if (precision == ASM_FP64) {
         out[i] = tn_draw<double>(c[i], d[i], lo[i], hi[i], u[i]);
     } else {
-        out[i] = (double)tn_draw_fast32((float)c[i], (float)d[i], (float)lo[i], (float)hi[i],
-                                        (float)u[i]);
+        out[i] = (double)tn_draw32((float)c[i], (float)d[i], (float)lo[i], (float)hi[i],
+                                   (float)u[i]);
     }
 }
 

@@ -1,0 +1,306 @@
+// Batched float32 sampler of blocked modes sampling (Sec. IV.B-C).
+//
+// L lanes of one wavefront carry one chain; a workgroup carries `cpw` chains of one problem
+// (a tile) and walks the blocks of that problem in order.  For each block the workgroup
+// stages the block's factors in LDS, shared by all its chains:
+//   (V_qi, -1/V_qi) pairs, mode-major rows of ROW = EPT L entries (padding (0, NaN)),
+//   U_i rows of MP = RPT L entries (padding 0), when they fit,
+// and each chain draws the block's uniforms into its own LDS row.  A lane owns components
+// q = lane + L t (t < EPT) of the block, in registers, and residual entries m = lane + L t
+// (t < RPT), in registers for the whole launch.
+//
+// One move of mode i (the oracle's order: data modes i < k_b first, then the zero modes):
+//   1. interval of Eq. (modeLimits): x_q = A_q (-1/V_qi); x_q <= 0 (sign bit set) exactly
+//      when V_qi > 0, so lo is the signed-integer minimum of the bit patterns (the negative
+//      x closest to zero) and hi their unsigned minimum (the smallest non-negative x);
+//      padding and V_qi = 0 give a NaN x, which neither minimum can select;
+//   2. data mode: c = U_i . r and delta from the truncated normal (tn32.h); zero mode:
+//      delta = lo + u (hi - lo);
+//   3. A_q = max(A_q + delta V_qi, +0); data mode: r -= delta d_i U_i.
+// Sums over the L lanes of a chain use DPP row operations (L <= 16) or lane shuffles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+#include "rng_tn.h"
+#include "tn32.h"
+
+namespace asmk {
+
+template <int L>
+__device__ __forceinline__ uint32_t seg_umin(uint32_t x) {
+    if constexpr (L >= 2) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0xB1, 0xF, 0xF, false));
+    if constexpr (L >= 4) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x4E, 0xF, 0xF, false));
+    if constexpr (L >= 8) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x141, 0xF, 0xF, false));
+    if constexpr (L >= 16) x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, 0x140, 0xF, 0xF, false));
+    if constexpr (L >= 32) x = min(x, (uint32_t)__shfl_xor((int)x, 16));
+    if constexpr (L >= 64) x = min(x, (uint32_t)__shfl_xor((int)x, 32));
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ int32_t seg_imin(int32_t x) {
+    if constexpr (L >= 2) x = min(x, __builtin_amdgcn_update_dpp(0x7FFFFFFF, x, 0xB1, 0xF, 0xF, false));
+    if constexpr (L >= 4) x = min(x, __builtin_amdgcn_update_dpp(0x7FFFFFFF, x, 0x4E, 0xF, 0xF, false));
+    if constexpr (L >= 8) x = min(x, __builtin_amdgcn_update_dpp(0x7FFFFFFF, x, 0x141, 0xF, 0xF, false));
+    if constexpr (L >= 16) x = min(x, __builtin_amdgcn_update_dpp(0x7FFFFFFF, x, 0x140, 0xF, 0xF, false));
+    if constexpr (L >= 32) x = min(x, __shfl_xor(x, 16));
+    if constexpr (L >= 64) x = min(x, __shfl_xor(x, 32));
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ float seg_sum(float x) {
+    if constexpr (L >= 2) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    if constexpr (L >= 4) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    if constexpr (L >= 8) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+    if constexpr (L >= 16) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
+    if constexpr (L >= 32) x += __shfl_xor(x, 16);
+    if constexpr (L >= 64) x += __shfl_xor(x, 32);
+    return x;
+}
+
+// Interval [lo, hi] of the step along one mode (Eq. (modeLimits)) from the lane's EPT
+// components; every lane of the chain ends with the same values.
+template <int L, int EPT>
+__device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float (&Ar)[EPT], float &lo,
+                                           float &hi) {
+    uint32_t hb = 0xFFFFFFFFu;
+    int32_t lb = 0x7FFFFFFF;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const uint32_t bits = __float_as_uint(Ar[t] * vw[t].y);
+        hb = min(hb, bits);
+        lb = min(lb, (int32_t)bits);
+    }
+    hb = seg_umin<L>(hb);
+    lb = seg_imin<L>(lb);
+    // below 0x7F800000: a finite non-negative x; below the pattern of -inf (as a signed
+    // integer): a finite negative x, or -0
+    hi = hb < 0x7F800000u ? __uint_as_float(hb) : INFINITY;
+    lo = lb < (int32_t)0xFF800000u ? __int_as_float(lb) : -INFINITY;
+}
+
+// One zero-mode move (d_i = 0: flat on [lo, hi]).  `span` collects hi - lo, which is +inf
+// when a zero mode is unbounded (an improper posterior, reported after the launch).
+template <int L, int EPT>
+__device__ __forceinline__ void zero_move(const float2 (&vw)[EPT], float (&Ar)[EPT], float u, float &span) {
+    float lo, hi;
+    interval32<L, EPT>(vw, Ar, lo, hi);
+    const float w = hi - lo;
+    span = fmaxf(span, w);
+    const float delta = fmaf(u, w, lo);
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) Ar[t] = fmaxf(fmaf(delta, vw[t].x, Ar[t]), 0.0f);
+}
+
+template <int EPT>
+__device__ __forceinline__ void load_row(float2 (&vw)[EPT], const float2 *row, int lane, int L) {
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) vw[t] = row[lane + L * t];
+}
+
+// Copy n16 16-byte words from global memory to LDS with all threads, eight loads in flight
+// per thread.
+__device__ __forceinline__ void stage16(float4 *dst, const float4 *src, int n16, int tid, int nthr) {
+    int i = tid;
+    for (; i + 7 * nthr < n16; i += 8 * nthr) {
+        float4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = src[i + k * nthr];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[i + k * nthr] = v[k];
+    }
+    for (; i < n16; i += nthr) dst[i] = src[i];
+}
+
+template <int L, int EPT, int RPT>
+__global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
+    extern __shared__ __align__(16) unsigned char smem32[];
+    constexpr int ROW = EPT * L;
+    constexpr int MP = RPT * L;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = tid % L;
+    const int slotc = tid / L;
+    float2 *sVW = reinterpret_cast<float2 *>(smem32);
+    float *sU = reinterpret_cast<float *>(smem32 + a.lds_off_u);
+    float *sUnif = reinterpret_cast<float *>(smem32 + a.lds_off_unif);
+    double *sAcc = reinterpret_cast<double *>(smem32 + a.lds_off_acc);
+    __shared__ int s_tile;
+    const int64_t s0 = *a.sweep;
+    const int64_t nsw = a.nsw;
+    // this launch accumulates into the workgroup's LDS sums (flushed once per tile)
+    const bool acc_lds = a.accumulate && a.acc_lds && s0 + nsw > a.burnin;
+
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= a.ntiles) break;
+        const TileDesc td = a.tiles[tile];
+        const ProbDesc pd = a.probs[td.problem];
+        const int M = (int)pd.M;
+        const int64_t N = pd.N;
+        const bool active = slotc < td.nchains;
+        const int64_t chain = td.chain0 + (active ? slotc : 0);
+        float *Ag = a.A32 + pd.off_A + chain * N;
+        float *rg = a.r32 + pd.off_r + chain * (int64_t)M;
+        if (acc_lds)
+            for (int64_t n = tid; n < 2 * N; n += nthr) sAcc[n] = 0.0;
+        float rr[RPT];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int m = lane + L * t;
+            rr[t] = (m < M && active) ? rg[m] : 0.0f;
+        }
+        float span = 0.0f;
+        float *urow = sUnif + slotc * ROW;
+
+        for (int64_t s = s0; s < s0 + nsw; ++s) {
+            for (int64_t b = 0; b < pd.B; ++b) {
+                const BlockDesc bd = a.blocks[pd.off_blk + b];
+                const int nb = (int)bd.nb, kb = (int)bd.kb;
+                float Ar[EPT];
+#pragma unroll
+                for (int t = 0; t < EPT; ++t) {
+                    const int q = lane + L * t;
+                    Ar[t] = (q < nb && active) ? Ag[bd.n0 + q] : 0.0f;
+                }
+                __syncthreads();   // the previous block's readers of the LDS rows are done
+                stage16(reinterpret_cast<float4 *>(sVW), reinterpret_cast<const float4 *>(a.VW32 + bd.off_VW),
+                        nb * ROW / 2, tid, nthr);
+                if (a.u_lds)
+                    stage16(reinterpret_cast<float4 *>(sU), reinterpret_cast<const float4 *>(a.U32 + bd.off_U32),
+                            kb * MP / 4, tid, nthr);
+                // this block's uniforms: one Philox call per four modes
+                for (int g = lane; 4 * g < nb; g += L) {
+                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
+                                              (uint32_t)b, (uint32_t)g);
+                    float *d = urow + 4 * g;
+                    d[0] = word_u32(w.x);
+                    d[1] = word_u32(w.y);
+                    d[2] = word_u32(w.z);
+                    d[3] = word_u32(w.w);
+                }
+                __syncthreads();
+                const float *dv = a.d32 + bd.off_d32;
+                const float *Ug = a.U32 + bd.off_U32;
+                float2 vw[EPT];
+                load_row<EPT>(vw, sVW, lane, L);
+                // data modes
+                for (int i = 0; i < kb; ++i) {
+                    float Ui[RPT];
+                    if (a.u_lds) {
+#pragma unroll
+                        for (int t = 0; t < RPT; ++t) Ui[t] = sU[i * MP + lane + L * t];
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < RPT; ++t) Ui[t] = Ug[i * MP + lane + L * t];
+                    }
+                    const float u = urow[i];
+                    const float dd = dv[i];
+                    float2 vn[EPT];
+                    load_row<EPT>(vn, sVW + (i + 1) * ROW, lane, L);
+                    float lo, hi;
+                    interval32<L, EPT>(vw, Ar, lo, hi);
+                    float cp = 0.0f;
+#pragma unroll
+                    for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[t], rr[t], cp);
+                    const float cdot = seg_sum<L>(cp);
+                    const float delta = tn_draw32(cdot, dd, lo, hi, u);
+                    const float e = delta * dd;
+#pragma unroll
+                    for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) {
+                        Ar[t] = fmaxf(fmaf(delta, vw[t].x, Ar[t]), 0.0f);
+                        vw[t] = vn[t];
+                    }
+                }
+                // zero modes, two per iteration with the rows loaded one move ahead
+                int i = kb;
+                for (; i + 2 <= nb; i += 2) {
+                    float2 vb[EPT];
+                    load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
+                    const float u0 = urow[i], u1 = urow[i + 1];
+                    zero_move<L, EPT>(vw, Ar, u0, span);
+                    load_row<EPT>(vw, sVW + (i + 2) * ROW, lane, L);
+                    zero_move<L, EPT>(vb, Ar, u1, span);
+                }
+                if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i], span);
+#pragma unroll
+                for (int t = 0; t < EPT; ++t) {
+                    const int q = lane + L * t;
+                    if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
+                }
+                if (a.accumulate && s >= a.burnin) {
+                    // sums over the tile's chains, float64; the uniforms of this block are
+                    // consumed, so each chain's row now carries its components
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) urow[lane + L * t] = active ? Ar[t] : 0.0f;
+                    __syncthreads();
+                    if (acc_lds) {
+                        for (int q = tid; q < nb; q += nthr) {
+                            double x1 = 0.0, x2 = 0.0;
+                            for (int cs = 0; cs < td.nchains; ++cs) {
+                                const double x = (double)sUnif[cs * ROW + q];
+                                x1 += x;
+                                x2 = fma(x, x, x2);
+                            }
+                            sAcc[bd.n0 + q] += x1;
+                            sAcc[N + bd.n0 + q] += x2;
+                        }
+                    } else {
+                        int64_t slot = td.slot;
+                        if (pd.batches > 1) slot += (s - a.burnin) * pd.batches / a.sweeps;
+                        double *s1 = a.accA + pd.off_slot + slot * N + bd.n0;
+                        double *s2 = a.accA2 + pd.off_slot + slot * N + bd.n0;
+                        for (int q = tid; q < nb; q += nthr) {
+                            double x1 = 0.0, x2 = 0.0;
+                            for (int cs = 0; cs < td.nchains; ++cs) {
+                                const double x = (double)sUnif[cs * ROW + q];
+                                x1 += x;
+                                x2 = fma(x, x, x2);
+                            }
+                            s1[q] += x1;
+                            s2[q] += x2;
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int m = lane + L * t;
+            if (active && m < M) rg[m] = rr[t];
+        }
+        if (acc_lds) {
+            __syncthreads();
+            double *s1 = a.accA + pd.off_slot + (int64_t)td.slot * N;
+            double *s2 = a.accA2 + pd.off_slot + (int64_t)td.slot * N;
+            for (int64_t n = tid; n < N; n += nthr) {
+                s1[n] += sAcc[n];
+                s2[n] += sAcc[N + n];
+            }
+        }
+        if (!(span < INFINITY)) atomicOr(a.flags, 1);
+    }
+}
+
+template <int L, int EPT, int RPT>
+hipError_t launch_sample32_t(const SampleArgs &a, int threads, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_sample32<L, EPT, RPT>), dim3(grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int L, int EPT, int RPT>
+hipError_t allow_lds_sample32_t(int bytes) {
+    return hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace asmk

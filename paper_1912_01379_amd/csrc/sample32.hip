@@ -1,0 +1,52 @@
+// The compiled float32 sampler instances and their selection.
+#include "internal.h"
+
+namespace asmk {
+
+namespace {
+struct Inst32 {
+    int L, EPT, RPT;
+};
+// (lanes per chain, components per lane, residual entries per lane): a block of up to
+// EPT L grid points and a problem of up to RPT L data points
+const Inst32 kInst32[] = {
+    {4, 8, 16}, {4, 32, 52}, {8, 4, 8}, {8, 13, 26}, {8, 16, 52}, {16, 2, 4}, {16, 7, 13}, {16, 8, 26}, {16, 8, 32}, {32, 1, 2}, {32, 4, 7}, {32, 4, 13}};
+}  // namespace
+
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt) {
+    int best = -1;
+    for (int k = 0; k < (int)(sizeof kInst32 / sizeof kInst32[0]); ++k) {
+        const Inst32 &c = kInst32[k];
+        if (c.L != lanes || (int64_t)c.EPT * c.L < max_nb || (int64_t)c.RPT * c.L < max_m) continue;
+        // the least per-lane work: 4 operations per component, 2 per residual entry
+        if (best < 0 || 2 * c.EPT + c.RPT < 2 * kInst32[best].EPT + kInst32[best].RPT) best = k;
+    }
+    if (best < 0) return -1;
+    *ept = kInst32[best].EPT;
+    *rpt = kInst32[best].RPT;
+    return 0;
+}
+
+hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
+                                int grid, size_t lds_bytes, hipStream_t s) {
+    const int threads = lanes * chains_per_wg;
+    if (threads % 64 != 0 || threads > 512) return hipErrorInvalidValue;
+    switch (lanes) {
+    case 4: return launch_sample32_l4(a, ept, rpt, threads, grid, lds_bytes, s);
+    case 8: return launch_sample32_l8(a, ept, rpt, threads, grid, lds_bytes, s);
+    case 16: return launch_sample32_l16(a, ept, rpt, threads, grid, lds_bytes, s);
+    case 32: return launch_sample32_l32(a, ept, rpt, threads, grid, lds_bytes, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_sample32_lds_limit(int bytes) {
+    hipError_t e = hipSuccess, e1;
+    if ((e1 = allow_lds_sample32_l4(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_l8(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_l16(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_l32(bytes)) != hipSuccess) e = e1;
+    return e;
+}
+
+}  // namespace asmk

@@ -1,0 +1,193 @@
+// Float32 truncated-normal draw by inversion for the batched sampler (Sec. IV.B: a data
+// mode's coordinate is redrawn from N(c/d, 1/d^2) truncated to the interval of
+// Eq. (modeLimits)).
+//
+// In standard units a = d lo - c, b = d hi - c, w = b - a, the draw is x = F^-1(F(a) +
+// u (F(b) - F(a))) for the normal CDF F.  Every case is mapped onto one path that evaluates
+// the upper tail Q = 1 - F twice and its inverse once:
+//   a >= 0 (interval above the mean):   p = Q(a) - u (Q(a) - Q(a + w)), x = Q^-1(p);
+//   b <= 0 (interval below the mean):   the mirror image, with u and 1 - u exchanged;
+//   a < 0 < b:                          p = F(a) + u mass, x = -Q^-1(p) when p <= 1/2, else
+//                                       x = Q^-1(Q(b) + (1 - u) mass), mass = 1 - Q(-a) - Q(b);
+// each tail probability is formed from the end where it is small, so nothing cancels.
+// Q and Q^-1 are the polynomial fits of tn32_coef.h on the hardware exp2/log2/rcp/sqrt,
+// with one Newton step on Q^-1; they carry about 1e-7 relative error.
+// Two rare cases leave this path: intervals much narrower than the Gaussian (the density
+// is then an exponential tilt across the interval, drawn in closed form), and one-sided
+// intervals more than 10 standard deviations from the mean (the tail path on the Mills
+// ratio).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "tn32_coef.h"
+
+namespace asmk {
+
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// exp(-x^2/2) for 0 <= x < 14, carrying the rounding of x^2 and of the scaling to base 2
+__device__ __forceinline__ float exp_half_sq(float x) {
+    constexpr float kL2eHalf = 0.72134752f;           // log2(e) / 2, rounded
+    constexpr float kL2eHalfLo = 9.6298141e-09f;      // log2(e) / 2 - kL2eHalf
+    constexpr float kLn2 = 0.69314718f;
+    const float x2 = x * x;
+    const float x2lo = fmaf(x, x, -x2);               // x^2 = x2 + x2lo exactly
+    const float e = -x2 * kL2eHalf;
+    const float elo = fmaf(-x2, kL2eHalf, -e) - fmaf(x2, kL2eHalfLo, x2lo * kL2eHalf);
+    return hw_exp2(e) * fmaf(elo, kLn2, 1.0f);
+}
+
+// Q(x) = P(Z > x) for x >= 0 (+inf allowed)
+__device__ __forceinline__ float q_upper32(float x) {
+    using namespace tn32c;
+    const float r = hw_rcp(kQK + x);
+    const float v = fmaf(kQAlpha, r, kQBeta);
+    float h = kQ[kQDeg];
+#pragma unroll
+    for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
+    const float q = (kQK * r) * h * exp_half_sq(x);
+    return x < kQXmax ? q : 0.0f;
+}
+
+// z >= 0 with Q(z) = p, for 1e-33 <= p <= 1/2
+__device__ __forceinline__ float q_inv32(float p) {
+    using namespace tn32c;
+    constexpr float kLn2 = 0.69314718f;
+    constexpr float kSqrt2Pi = 2.5066283f;
+    p = fmaxf(p, 1e-33f);
+    const float y = fmaf(-2.0f, p, 1.0f);
+    const float w = -kLn2 * hw_log2(4.0f * p * (1.0f - p));
+    // centre: z = y P_c((w - wcut/2) / (wcut/2)); tail: z = s P_t(a s + b), s = sqrt(w)
+    const float vc = fmaf(w, 2.0f / kInvWcut, -1.0f);
+    float hc = kInvC[kInvDegC];
+#pragma unroll
+    for (int j = kInvDegC - 1; j >= 0; --j) hc = fmaf(hc, vc, kInvC[j]);
+    const float s = hw_sqrt(w);
+    const float vt = fmaf(kInvTa, s, kInvTb);
+    float ht = kInvT[kInvDegT];
+#pragma unroll
+    for (int j = kInvDegT - 1; j >= 0; --j) ht = fmaf(ht, vt, kInvT[j]);
+    float z = w < kInvWcut ? y * hc : s * ht;
+    // Newton on Q(z) = p: z += (Q(z) - p) / phi(z), Q(z) = E t H, phi(z) = E / sqrt(2 pi)
+    const float r = hw_rcp(kQK + z);
+    const float v = fmaf(kQAlpha, r, kQBeta);
+    float h = kQ[kQDeg];
+#pragma unroll
+    for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
+    const float E = exp_half_sq(z);
+    const float step = kSqrt2Pi * fmaf(-p, hw_rcp(E), (kQK * r) * h);
+    return E > 0.0f ? z + step : z;
+}
+
+// log1p(z) for z > -1 (the rounding of 1 + z is compensated)
+__device__ __forceinline__ float log1p32(float z) {
+    const float l1 = 1.0f + z;
+    return (l1 == 1.0f) ? z : logf(l1) * (z / (l1 - 1.0f));
+}
+
+// t in [0, w] with density proportional to exp(-lam t) (lam of either sign), by inversion
+__device__ __forceinline__ float tilt_draw32(float lam, float w, float u, float uc) {
+    const float x = lam * w;
+    if (fabsf(x) < 1e-6f) return u * w;
+    // the distance s from the end where the density is largest, s = -log(1 - v (1 - e^-|x|)) / |lam|,
+    // with v = u from the lower end (lam > 0) and v = 1 - u from the upper end (lam < 0)
+    const float v = lam > 0.0f ? u : uc;
+    const float s = -log1p32(v * expm1f(-fabsf(x))) / fabsf(lam);
+    return lam > 0.0f ? s : w - s;
+}
+
+// Mills ratio m(x) = Q(x) / phi(x) for x >= 0: the fit of Q below 14, the asymptotic
+// series 1/x (1 - 1/x^2 + 3/x^4 - 15/x^6) above (its first omitted term is 7e-11 there)
+__device__ __forceinline__ float mills32(float x) {
+    using namespace tn32c;
+    constexpr float kSqrt2Pi = 2.5066283f;
+    if (x < kQXmax) {
+        const float r = hw_rcp(kQK + x);
+        const float v = fmaf(kQAlpha, r, kQBeta);
+        float h = kQ[kQDeg];
+#pragma unroll
+        for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
+        return kSqrt2Pi * (kQK * r) * h;
+    }
+    const float ix = hw_rcp(x), i2 = ix * ix;
+    return ix * fmaf(i2, fmaf(i2, fmaf(i2, -15.0f, 3.0f), -1.0f), 1.0f);
+}
+
+// t in [0, w] with density proportional to exp(-a t - t^2/2) for a > 10, where Q(a + t)
+// underflows: solve log Q(a + t) - log Q(a) = log(1 - u (1 - Q(a + w) / Q(a))) for t with
+// log Q(a + t) - log Q(a) = -t (a + t/2) + log(m(a + t) / m(a)), by Newton from t = -target/a
+// (d/dt log Q(a + t) = -1 / m(a + t)).
+__device__ __forceinline__ float tail_draw32(float a, float w, float u) {
+    const float ma = mills32(a);
+    const float lr = __builtin_isinf(w) ? -INFINITY : -w * fmaf(0.5f, w, a) + logf(mills32(a + w) / ma);
+    const float target = log1p32(u * expm1f(lr));
+    float t = -target / a;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float mt = mills32(a + t);
+        const float g = -t * fmaf(0.5f, t, a) + logf(mt / ma) - target;
+        t = fmaf(g, mt, t);
+    }
+    return fminf(fmaxf(t, 0.0f), w);
+}
+
+// The draw in parameter units: delta in [lo, hi], lo <= 0 <= hi, d > 0, u in (0, 1).
+__device__ __forceinline__ float tn_draw32(float c, float d, float lo, float hi, float u) {
+    if (lo == hi) return lo;
+    const float uc = 1.0f - u;
+    const float a = fmaf(d, lo, -c);
+    const float b = fmaf(d, hi, -c);
+    const float w = d * (hi - lo);
+    const float rd = hw_rcp(d);
+    const float far = fmaxf(fabsf(a), fabsf(b));
+    float delta;
+    // The tilt below errs by about w^2/16 of the interval (the curvature it drops), the
+    // inversion by about 1.5e-7 max(1, |a|, |b|) / w (the float32 resolution of p and x):
+    // take the tilt where it is the more accurate of the two.
+    if (w * w * w < 2.4e-6f * fmaxf(1.0f, far)) {
+        // narrow interval: exponential tilt at the slope of the midpoint
+        const float lam = fmaf(0.5f, w, a);
+        delta = lo + tilt_draw32(lam, w, u, uc) * rd;
+    } else {
+        const bool lower = b <= 0.0f;                   // interval below the mean
+        const bool one = lower || a >= 0.0f;
+        const float a1 = lower ? -b : a;
+        const float u1 = lower ? uc : u;
+        const float uc1 = lower ? u : uc;
+        if (one && a1 > 10.0f) {
+            const float t = tail_draw32(a1, w, u1);
+            delta = lower ? hi - t * rd : lo + t * rd;
+        } else {
+            const float q1 = q_upper32(one ? a1 : -a);
+            const float q2 = q_upper32(one ? a1 + w : b);
+            const float dq = q1 - q2;
+            const float mass = (1.0f - q1) - q2;
+            const float plo = fmaf(u, mass, q1);
+            float p, sg;
+            if (one) {
+                p = u1 <= 0.5f ? fmaf(-u1, dq, q1) : fmaf(uc1, dq, q2);
+                sg = 1.0f;
+            } else {
+                p = plo <= 0.5f ? plo : fmaf(uc, mass, q2);
+                sg = plo <= 0.5f ? -1.0f : 1.0f;
+            }
+            const float x = sg * q_inv32(p);
+            if (one) {
+                const float t = fminf(fmaxf(x - a1, 0.0f), w);
+                delta = lower ? hi - t * rd : lo + t * rd;
+            } else {
+                delta = (x + c) * rd;
+            }
+        }
+    }
+    delta = delta < lo ? lo : delta;
+    delta = delta > hi ? hi : delta;
+    return delta;
+}
+
+}  // namespace asmk
