@@ -62,6 +62,7 @@ struct asm_plan {
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
     int64_t lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS layout
     int u_lds = 0, acc_lds = 0;
+    bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
     int lanes = 16, chains_per_wg = 16, grid32 = 0;
@@ -772,12 +773,17 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     // ---- float32 packing, start state, first residual ----
     if (pl->fp32)
         HSTEP(launch_pack32_blocks(pl->d_blocks, blockM_d, (int64_t)pl->blocks.size(), pl->V64,
-                                   pl->U64, pl->d64, pl->VW32, pl->U32, pl->d32, st));
+                                   pl->U64, pl->d64, pl->VW32, pl->U32, pl->d32, pl->flags, st));
     HSTEP(launch_init_state2(pl->d_probs, n, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
                              pl->fp32, st));
     STEP(refresh(pl, false));
     HSTEP(hipEventRecord(pl->ev[1], st));
     HSTEP(hipStreamSynchronize(st));
+    if (pl->fp32) {
+        // the float32 sampler relies on every zero mode having a finite interval
+        STEP(check_flags(pl, &hflags));
+        pl->unbounded = (hflags & 1) != 0;
+    }
     *out = pl;
     return ASM_OK;
 #undef STEP
@@ -789,6 +795,7 @@ int asm_plan_advance(asm_plan *pl, int64_t sweeps) {
     if (!pl) return fail(ASM_EINVAL, "plan is NULL");
     if (sweeps < 0) return fail(ASM_EINVAL, "sweeps must be >= 0");
     if (sweeps == 0) return ASM_OK;
+    if (pl->unbounded) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
     TRY(sweep_loop(pl, sweeps, 0, 0));
     int hflags = 0;
     TRY(check_flags(pl, &hflags));
@@ -800,6 +807,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     g_err.clear();
     if (!pl) return fail(ASM_EINVAL, "plan is NULL");
     if (!mean || !stderr_) return fail(ASM_EINVAL, "mean and stderr_ are required");
+    if (pl->unbounded) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
     hipStream_t st = pl->stream;
     const int64_t slot_elems = pl->probs.back().off_slot + pl->probs.back().nslot * pl->probs.back().N;
     HIPCHK(hipMemsetAsync(pl->accA, 0, slot_elems * sizeof(double), st));

@@ -127,7 +127,7 @@ hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, cons
                                   int32_t *kb_out, hipStream_t s);
 hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
                                 int64_t nblocks, const double *V64, const double *U64,
-                                const double *d64, float2 *VW32, float *U32, float *d32,
+                                const double *d64, float2 *VW32, float *U32, float *d32, int *flags,
                                 hipStream_t s);
 int64_t nnls_work_doubles(int64_t M, int64_t N);
 hipError_t launch_nnls(const ProbDesc *probs_dev, int64_t P, const int *use, const double *Kt,

@@ -16,7 +16,8 @@
 //      padding and V_qi = 0 give a NaN x, which neither minimum can select;
 //   2. data mode: c = U_i . r and delta from the truncated normal (tn32.h); zero mode:
 //      delta = lo + u (hi - lo);
-//   3. A_q = max(A_q + delta V_qi, +0); data mode: r -= delta d_i U_i.
+//   3. A_q += delta V_qi (non-negative by construction, see zero_move); data mode:
+//      r -= delta d_i U_i.
 // Sums over the L lanes of a chain use DPP row operations (L <= 16) or lane shuffles.
 #pragma once
 
@@ -63,8 +64,11 @@ __device__ __forceinline__ float seg_sum(float x) {
 }
 
 // Interval [lo, hi] of the step along one mode (Eq. (modeLimits)) from the lane's EPT
-// components; every lane of the chain ends with the same values.
-template <int L, int EPT>
+// components; every lane of the chain ends with the same values.  Without `bounded` an
+// unsigned minimum at or above the pattern of +inf means no finite non-negative x (hi =
+// +inf), and a signed minimum at or above the pattern of -inf means no finite negative x
+// nor -0 (lo = -inf).  Zero modes are `bounded`: both ends are finite by construction.
+template <int L, int EPT, bool bounded>
 __device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float (&Ar)[EPT], float &lo,
                                            float &hi) {
     uint32_t hb = 0xFFFFFFFFu;
@@ -77,23 +81,26 @@ __device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float 
     }
     hb = seg_umin<L>(hb);
     lb = seg_imin<L>(lb);
-    // below 0x7F800000: a finite non-negative x; below the pattern of -inf (as a signed
-    // integer): a finite negative x, or -0
-    hi = hb < 0x7F800000u ? __uint_as_float(hb) : INFINITY;
-    lo = lb < (int32_t)0xFF800000u ? __int_as_float(lb) : -INFINITY;
+    if (!bounded) {
+        hb = min(hb, 0x7F800000u);
+        lb = min(lb, (int32_t)0xFF800000u);
+    }
+    hi = __uint_as_float(hb);
+    lo = __int_as_float(lb);
 }
 
-// One zero-mode move (d_i = 0: flat on [lo, hi]).  `span` collects hi - lo, which is +inf
-// when a zero mode is unbounded (an improper posterior, reported after the launch).
+// One zero-mode move (d_i = 0: flat on [lo, hi]).  The packed ratios are shrunk by 2^-21
+// relative to -1/V, so the computed interval lies inside the exact one; with delta clamped
+// into it, every A_q + delta V_q is non-negative before rounding, hence after it, and no
+// component needs clamping.  Every zero mode has a finite interval: a mode whose V has
+// entries of only one sign makes the posterior improper and is rejected before sampling.
 template <int L, int EPT>
-__device__ __forceinline__ void zero_move(const float2 (&vw)[EPT], float (&Ar)[EPT], float u, float &span) {
+__device__ __forceinline__ void zero_move(const float2 (&vw)[EPT], float (&Ar)[EPT], float u) {
     float lo, hi;
-    interval32<L, EPT>(vw, Ar, lo, hi);
-    const float w = hi - lo;
-    span = fmaxf(span, w);
-    const float delta = fmaf(u, w, lo);
+    interval32<L, EPT, true>(vw, Ar, lo, hi);
+    const float delta = __builtin_amdgcn_fmed3f(fmaf(u, hi - lo, lo), lo, hi);
 #pragma unroll
-    for (int t = 0; t < EPT; ++t) Ar[t] = fmaxf(fmaf(delta, vw[t].x, Ar[t]), 0.0f);
+    for (int t = 0; t < EPT; ++t) Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
 }
 
 template <int EPT>
@@ -157,7 +164,6 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
             const int m = lane + L * t;
             rr[t] = (m < M && active) ? rg[m] : 0.0f;
         }
-        float span = 0.0f;
         float *urow = sUnif + slotc * ROW;
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
                     float2 vn[EPT];
                     load_row<EPT>(vn, sVW + (i + 1) * ROW, lane, L);
                     float lo, hi;
-                    interval32<L, EPT>(vw, Ar, lo, hi);
+                    interval32<L, EPT, false>(vw, Ar, lo, hi);
                     float cp = 0.0f;
 #pragma unroll
                     for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[t], rr[t], cp);
@@ -217,21 +223,28 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
                     for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
 #pragma unroll
                     for (int t = 0; t < EPT; ++t) {
-                        Ar[t] = fmaxf(fmaf(delta, vw[t].x, Ar[t]), 0.0f);
+                        Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
                         vw[t] = vn[t];
                     }
                 }
-                // zero modes, two per iteration with the rows loaded one move ahead
+                // zero modes, three per iteration, each row loaded two moves ahead (the
+                // rows past the block's last are spare LDS rows, loaded and never used)
                 int i = kb;
-                for (; i + 2 <= nb; i += 2) {
-                    float2 vb[EPT];
+                {
+                    float2 vb[EPT], vc[EPT];
                     load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
-                    const float u0 = urow[i], u1 = urow[i + 1];
-                    zero_move<L, EPT>(vw, Ar, u0, span);
-                    load_row<EPT>(vw, sVW + (i + 2) * ROW, lane, L);
-                    zero_move<L, EPT>(vb, Ar, u1, span);
+                    for (; i + 3 <= nb; i += 3) {
+                        load_row<EPT>(vc, sVW + (i + 2) * ROW, lane, L);
+                        const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
+                        zero_move<L, EPT>(vw, Ar, u0);
+                        load_row<EPT>(vw, sVW + (i + 3) * ROW, lane, L);
+                        zero_move<L, EPT>(vb, Ar, u1);
+                        load_row<EPT>(vb, sVW + (i + 4) * ROW, lane, L);
+                        zero_move<L, EPT>(vc, Ar, u2);
+                    }
+                    if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
+                    if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
                 }
-                if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i], span);
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) {
                     const int q = lane + L * t;
@@ -287,7 +300,6 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
                 s2[n] += sAcc[N + n];
             }
         }
-        if (!(span < INFINITY)) atomicOr(a.flags, 1);
     }
 }
 

@@ -361,28 +361,43 @@ hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, cons
 }
 
 // ------------------------------------------------------------------------------------
-// float32 packing: (V, -1/V) pairs, mode-major rows padded to nbp with (0, NaN); U rows
-// padded to mp with zeros.  A NaN ratio is neutral in the sampler's interval search and a
-// zero V leaves the padded component at zero.
+// float32 packing: (V, w) pairs with w = -(1/V)(1 - 2^-21), mode-major rows padded to nbp
+// with (0, NaN); U rows padded to mp with zeros.  The shrink of w keeps the sampler's
+// computed interval inside the exact one after its roundings.  A NaN w is neutral in the
+// interval search, so a component with V = 0 (which no step along the mode can make
+// negative; entries below 2^-100 in magnitude are taken as 0) and the padding constrain
+// nothing, and a zero V leaves the component unchanged.  A zero mode whose V has entries of
+// one sign only has an unbounded interval (Sec. IV.B, d_i = 0: the posterior is improper):
+// bit 0 of *flags is set.
 // ------------------------------------------------------------------------------------
-__global__ void k_pack32(const BlockDesc *blocks, int64_t M_unused, const int64_t *blockM,
-                         const double *V64, const double *U64, const double *d64, float2 *VW32,
-                         float *U32, float *d32) {
+__global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const double *V64,
+                         const double *U64, const double *d64, float2 *VW32, float *U32, float *d32,
+                         int *flags) {
     const BlockDesc bd = blocks[blockIdx.x];
     const int64_t M = blockM[blockIdx.x];
     const int64_t nb = bd.nb, nbp = bd.nbp, kb = bd.kb, mp = bd.mp;
+    constexpr double kTiny = 0x1.0p-100;
     for (int64_t i = threadIdx.x; i < nb * nbp; i += blockDim.x) {
         const int64_t mode = i / nbp, q = i % nbp;
         float2 vw;
-        if (q < nb) {
-            const float v = (float)V64[bd.off_V + mode * nb + q];
-            vw.x = v;
-            vw.y = (v == 0.0f) ? -1e30f : -1.0f / v;
+        const double v = q < nb ? V64[bd.off_V + mode * nb + q] : 0.0;
+        if (fabs(v) >= kTiny) {
+            vw.x = (float)v;
+            vw.y = (float)(-(1.0 / v) * (1.0 - 0x1.0p-21));
         } else {
             vw.x = 0.0f;
             vw.y = __builtin_nanf("");
         }
         VW32[bd.off_VW + i] = vw;
+    }
+    for (int64_t i = kb + threadIdx.x; i < nb; i += blockDim.x) {
+        bool pos = false, neg = false;
+        for (int64_t q = 0; q < nb; ++q) {
+            const double v = V64[bd.off_V + i * nb + q];
+            pos |= v >= kTiny;
+            neg |= v <= -kTiny;
+        }
+        if (!(pos && neg)) atomicOr(flags, 1);
     }
     for (int64_t i = threadIdx.x; i < kb * mp; i += blockDim.x) {
         const int64_t mode = i / mp, m = i % mp;
@@ -393,11 +408,11 @@ __global__ void k_pack32(const BlockDesc *blocks, int64_t M_unused, const int64_
 
 hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
                                 int64_t nblocks, const double *V64, const double *U64,
-                                const double *d64, float2 *VW32, float *U32, float *d32,
+                                const double *d64, float2 *VW32, float *U32, float *d32, int *flags,
                                 hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack32, dim3((unsigned)nblocks), dim3(256), 0, s, blocks_dev, (int64_t)0,
-                       blockM_dev, V64, U64, d64, VW32, U32, d32);
+    hipLaunchKernelGGL(k_pack32, dim3((unsigned)nblocks), dim3(256), 0, s, blocks_dev, blockM_dev, V64,
+                       U64, d64, VW32, U32, d32, flags);
     return hipGetLastError();
 }
 

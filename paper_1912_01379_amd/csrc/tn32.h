@@ -90,15 +90,48 @@ __device__ __forceinline__ float log1p32(float z) {
     return (l1 == 1.0f) ? z : logf(l1) * (z / (l1 - 1.0f));
 }
 
-// t in [0, w] with density proportional to exp(-lam t) (lam of either sign), by inversion
+// 1 - e^-X for X >= 0: the Taylor series to X^8 below 1/2 (the first omitted term is
+// below 2e-8 of the value there), the hardware exp2 above (no cancellation: 1 - e^-X > 0.39)
+__device__ __forceinline__ float one_minus_exp_neg(float X) {
+    constexpr float kL2e = 1.44269504f;
+    float p = -1.0f / 40320.0f;
+    p = fmaf(p, X, 1.0f / 5040.0f);
+    p = fmaf(p, X, -1.0f / 720.0f);
+    p = fmaf(p, X, 1.0f / 120.0f);
+    p = fmaf(p, X, -1.0f / 24.0f);
+    p = fmaf(p, X, 1.0f / 6.0f);
+    p = fmaf(p, X, -0.5f);
+    p = fmaf(p, X, 1.0f);
+    return X < 0.5f ? X * p : 1.0f - hw_exp2(-X * kL2e);
+}
+
+// -log(1 - y) for 0 <= y < 1: 2 atanh(t) = 2 (t + t^3/3 + ... + t^13/13), t = y / (2 - y)
+// <= 1/3, for y <= 1/2 (first omitted term below 2e-8 of the value); the hardware log2 of
+// 1 - y (exact there) above
+__device__ __forceinline__ float neg_log1m(float y) {
+    constexpr float kLn2 = 0.69314718f;
+    const float t = y * hw_rcp(2.0f - y);
+    const float t2 = t * t;
+    float p = 1.0f / 13.0f;
+    p = fmaf(p, t2, 1.0f / 11.0f);
+    p = fmaf(p, t2, 1.0f / 9.0f);
+    p = fmaf(p, t2, 1.0f / 7.0f);
+    p = fmaf(p, t2, 1.0f / 5.0f);
+    p = fmaf(p, t2, 1.0f / 3.0f);
+    p = fmaf(p, t2, 1.0f);
+    return y <= 0.5f ? 2.0f * t * p : -kLn2 * hw_log2(1.0f - y);
+}
+
+// t in [0, w] with density proportional to exp(-lam t) (lam of either sign), by inversion:
+// the distance s from the end where the density is largest is
+// s = -log(1 - v (1 - e^-|lam| w)) / |lam|, with v = u from the lower end (lam > 0) and
+// v = 1 - u from the upper end (lam < 0)
 __device__ __forceinline__ float tilt_draw32(float lam, float w, float u, float uc) {
-    const float x = lam * w;
-    if (fabsf(x) < 1e-6f) return u * w;
-    // the distance s from the end where the density is largest, s = -log(1 - v (1 - e^-|x|)) / |lam|,
-    // with v = u from the lower end (lam > 0) and v = 1 - u from the upper end (lam < 0)
+    const float X = fabsf(lam * w);
     const float v = lam > 0.0f ? u : uc;
-    const float s = -log1p32(v * expm1f(-fabsf(x))) / fabsf(lam);
-    return lam > 0.0f ? s : w - s;
+    const float s = neg_log1m(v * one_minus_exp_neg(X)) * hw_rcp(fabsf(lam));
+    const float sd = X < 1e-6f ? v * w : s;
+    return lam > 0.0f ? sd : w - sd;
 }
 
 // Mills ratio m(x) = Q(x) / phi(x) for x >= 0: the fit of Q below 14, the asymptotic
@@ -185,9 +218,7 @@ __device__ __forceinline__ float tn_draw32(float c, float d, float lo, float hi,
             }
         }
     }
-    delta = delta < lo ? lo : delta;
-    delta = delta > hi ? hi : delta;
-    return delta;
+    return __builtin_amdgcn_fmed3f(delta, lo, hi);
 }
 
 }  // namespace asmk
