@@ -60,7 +60,8 @@ struct asm_plan {
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
     int ksplit = 1;          // chain splits of the cross-moment partial sums
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
-    int64_t lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS layout
+    int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS
+    int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
     int u_lds = 0, acc_lds = 0;
     bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
@@ -80,8 +81,9 @@ struct asm_plan {
     int32_t *d_chain_problem = nullptr, *d_chain_local = nullptr;
     double *Kt = nullptr, *gt = nullptr, *Lc = nullptr, *sigma = nullptr;
     double *V64 = nullptr, *U64 = nullptr, *d64 = nullptr;
-    float2 *VW32 = nullptr;
-    float *U32 = nullptr, *d32 = nullptr;
+    float4 *F32 = nullptr;
+    float *U32 = nullptr;
+    ChunkLayout chunk{};
     float *A32 = nullptr, *r32 = nullptr;
     double *A64 = nullptr, *r64 = nullptr, *chi2 = nullptr, *chi2_prev = nullptr, *drift = nullptr;
     double *accA = nullptr, *accA2 = nullptr, *slot_count_d = nullptr;
@@ -247,9 +249,9 @@ SampleArgs make_args(asm_plan *pl) {
     a.V64 = pl->V64;
     a.U64 = pl->U64;
     a.d64 = pl->d64;
-    a.VW32 = pl->VW32;
+    a.F32 = pl->F32;
     a.U32 = pl->U32;
-    a.d32 = pl->d32;
+    a.chunk_words = pl->chunk.words;
     a.A32 = pl->A32;
     a.r32 = pl->r32;
     a.A64 = pl->A64;
@@ -263,11 +265,13 @@ SampleArgs make_args(asm_plan *pl) {
     a.queue = pl->queue;
     a.sweep = pl->sweep_d;
     a.seed = pl->opt.seed;
+    a.lds_off_d = pl->lds_off_d;
     a.lds_off_u = pl->lds_off_u;
     a.lds_off_unif = pl->lds_off_unif;
     a.lds_off_acc = pl->lds_off_acc;
     a.u_lds = pl->u_lds;
     a.acc_lds = pl->acc_lds;
+    a.prefetch = pl->prefetch;
     return a;
 }
 
@@ -626,14 +630,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             const double want = 64.0 / std::max(1.0, chains_per_simd);
             L = want >= 24 ? 32 : want >= 12 ? 16 : want >= 6 ? 8 : 4;
         }
-        int ept = 0, rpt = 0;
+        int ept = 0, rpt = 0, pf = 0;
         {
             // the requested width first, then wider ones, then narrower ones
             const int order[] = {L, 16, 32, 8, 4};
             bool found = false;
             for (int cand : order) {
                 if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;
-                if (sample32_pick(cand, pl->max_nb, pl->max_m, &ept, &rpt) == 0) {
+                if (sample32_pick(cand, pl->max_nb, pl->max_m, &ept, &rpt, &pf) == 0) {
                     L = cand;
                     found = true;
                     break;
@@ -648,27 +652,22 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pl->lanes = L;
         pl->ept = ept;
         pl->rpt = rpt;
+        pl->pf = pf;
         const int64_t row = (int64_t)ept * L;   // components per staged row
         const int64_t mp = (int64_t)rpt * L;
         pl->max_nbp = row;
-        // packed float32 layout of the block factors for this instance
-        int64_t offVW = 0, offU32 = 0, offd32 = 0;
+        int64_t offU32 = 0;
         for (auto &bd : pl->blocks) {
             bd.nbp = row;
             bd.mp = mp;
-            bd.off_VW = offVW;
             bd.off_U32 = offU32;
-            bd.off_d32 = offd32;
-            offVW += bd.nb * row;   // row is a multiple of 4: offsets stay 16-byte aligned
-            offU32 += std::max<int64_t>(bd.kb, 1) * mp;
-            offd32 += std::max<int64_t>(bd.kb, 1);
+            offU32 += std::max<int64_t>(bd.kb, 1) * mp;   // mp is a multiple of 4
         }
-        STEP(dalloc(pl, &pl->VW32, offVW));
         STEP(dalloc(pl, &pl->U32, offU32));
-        STEP(dalloc(pl, &pl->d32, offd32));
-        // LDS of a workgroup: the block's (V, -1/V) rows (two spare rows for the row loaded
-        // ahead), then its U rows when they fit, then one uniform row per chain, then the
-        // float64 per-tile sums when they fit and no problem uses batch means.
+        // LDS of a workgroup: the staging area (the block's (V, w) rows with two spare rows
+        // for the rows loaded ahead, its singular values, and its U rows when they fit), one
+        // uniform row per chain, and the float64 per-tile sums when they fit and no problem
+        // uses batch means.  Each block's packed chunk is the image of the staging area.
         int64_t max_kb = 0, max_n = 0;
         bool batch_means = false;
         for (auto &bd : pl->blocks) max_kb = std::max(max_kb, bd.kb);
@@ -679,10 +678,13 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pl->max_kb = max_kb;
         pl->max_n = max_n;
         const size_t vw_bytes = (size_t)(pl->max_nb + 2) * row * sizeof(float2);
+        const size_t d_bytes = (size_t)(max_kb + 3) / 4 * 16;
         const size_t u_bytes = (size_t)max_kb * mp * sizeof(float);
         const size_t acc_bytes = (size_t)2 * max_n * sizeof(double);
         auto layout = [&](int cpw, bool with_u, bool with_acc) {
             size_t off = vw_bytes;
+            pl->lds_off_d = (int64_t)off;
+            off += d_bytes;
             pl->lds_off_u = (int64_t)off;
             if (with_u) off += u_bytes;
             off = (off + 15) / 16 * 16;
@@ -708,6 +710,18 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
             return rc;
         }
+        // the packed chunks (one per block, the image of the staging area)
+        pl->chunk.rows = pl->max_nb + 2;
+        pl->chunk.row = row;
+        pl->chunk.d_len = (max_kb + 3) / 4 * 4;
+        pl->chunk.u_rows = pl->u_lds ? max_kb : 0;
+        pl->chunk.mp = mp;
+        pl->chunk.words = (int64_t)(vw_bytes + d_bytes + (pl->u_lds ? u_bytes : 0)) / 16;
+        for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
+        STEP(dalloc(pl, &pl->F32, pl->blocks.size() * pl->chunk.words));
+        // the next block's chunk is prefetched into registers when it fits the instance's
+        // per-thread budget
+        pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw) ? 1 : 0;
         build_tiles(pl);
         pl->grid32 = (int)std::min<int64_t>((int64_t)pl->tiles.size(), (int64_t)max_cu * 2);
         STEP(dalloc(pl, &pl->d_tiles, pl->tiles.size()));
@@ -773,7 +787,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     // ---- float32 packing, start state, first residual ----
     if (pl->fp32)
         HSTEP(launch_pack32_blocks(pl->d_blocks, blockM_d, (int64_t)pl->blocks.size(), pl->V64,
-                                   pl->U64, pl->d64, pl->VW32, pl->U32, pl->d32, pl->flags, st));
+                                   pl->U64, pl->d64, pl->chunk, pl->F32, pl->U32, pl->flags, st));
     HSTEP(launch_init_state2(pl->d_probs, n, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
                              pl->fp32, st));
     STEP(refresh(pl, false));

@@ -43,9 +43,10 @@ struct BlockDesc {
     int64_t off_V;            // float64 V, mode-major: V[i*nb + q]
     int64_t off_U;            // float64 U, mode-major: U[i*M + m]
     int64_t off_d;            // float64 singular values (kb)
-    int64_t off_VW;           // float32 (V, -1/V) pairs, mode-major, nb x nbp
-    int64_t off_U32;          // float32 U, mode-major, kb x mp
-    int64_t off_d32;          // float32 singular values
+    int64_t off_chunk;        // float32 factor chunk (16-byte words): the LDS image of the block
+    int64_t off_U32;          // float32 U, mode-major, kb x mp (read from global memory when the
+                              // U rows are not staged)
+    int64_t unused2;
 };
 
 struct TileDesc {             // float32 work item: consecutive chains of one problem
@@ -68,9 +69,9 @@ struct SampleArgs {
     const double *V64;
     const double *U64;
     const double *d64;
-    const float2 *VW32;
+    const float4 *F32;        // factor chunks, one per block, chunk_words 16-byte words each
     const float *U32;
-    const float *d32;
+    int64_t chunk_words;
     float *A32;
     float *r32;
     double *A64;
@@ -90,11 +91,14 @@ struct SampleArgs {
     uint64_t seed;
     int32_t accumulate;       // 1: accumulate sweeps >= burnin
     int32_t pad;
-    int64_t lds_off_u;        // byte offsets in the float32 sampler's LDS: U rows,
+    int64_t lds_off_d;        // byte offsets in the float32 sampler's LDS: singular values,
+    int64_t lds_off_u;        //   U rows,
     int64_t lds_off_unif;     //   per-chain uniform rows,
     int64_t lds_off_acc;      //   float64 per-tile sums (2 x max N)
     int32_t u_lds;            // 1: U rows are staged in LDS (else read from global memory)
     int32_t acc_lds;          // 1: accumulate in LDS and flush once per tile and launch
+    int32_t prefetch;         // 1: every block's factor stream fits the instance's prefetch
+    int32_t pad2;
 };
 
 // ------------------------------------------------------------------------------------
@@ -125,10 +129,18 @@ int64_t svd_work_doubles(int64_t M, int64_t nb);
 hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, const double *Kt,
                                   double *work, double *V64, double *U64, double *d64,
                                   int32_t *kb_out, hipStream_t s);
+struct ChunkLayout {           // float32 factor chunk of a block, in elements of its kind
+    int64_t rows;             // (V, w) rows (the largest block plus two spare rows)
+    int64_t row;              // pairs per row
+    int64_t d_len;            // singular values (largest k, rounded up to 4)
+    int64_t u_rows;           // U rows in the chunk (largest k, or 0)
+    int64_t mp;               // floats per U row
+    int64_t words;            // 16-byte words of the chunk
+};
 hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
                                 int64_t nblocks, const double *V64, const double *U64,
-                                const double *d64, float2 *VW32, float *U32, float *d32, int *flags,
-                                hipStream_t s);
+                                const double *d64, const ChunkLayout &cl, float4 *F32, float *U32,
+                                int *flags, hipStream_t s);
 int64_t nnls_work_doubles(int64_t M, int64_t N);
 hipError_t launch_nnls(const ProbDesc *probs_dev, int64_t P, const int *use, const double *Kt,
                        const double *gt, double *work, const int64_t *work_off, double blend,
@@ -146,7 +158,7 @@ hipError_t set_sample64_lds_limit();
 // EPT, residual entries per lane RPT)
 hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
                                 int grid, size_t lds_bytes, hipStream_t s);
-int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt);
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pf);
 hipError_t set_sample32_lds_limit(int bytes);
 hipError_t launch_sample32_l4(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t launch_sample32_l8(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);

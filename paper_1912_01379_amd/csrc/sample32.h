@@ -2,9 +2,10 @@
 //
 // L lanes of one wavefront carry one chain; a workgroup carries `cpw` chains of one problem
 // (a tile) and walks the blocks of that problem in order.  For each block the workgroup
-// stages the block's factors in LDS, shared by all its chains:
-//   (V_qi, -1/V_qi) pairs, mode-major rows of ROW = EPT L entries (padding (0, NaN)),
-//   U_i rows of MP = RPT L entries (padding 0), when they fit,
+// stages the block's factors in LDS, shared by all its chains, by copying the block's packed
+// chunk (setup.hip), which is the image of the staging area:
+//   (V_qi, w_qi) pairs, w ~ -1/V, mode-major rows of ROW = EPT L entries (padding (0, NaN)),
+//   the singular values, and U_i rows of MP = RPT L entries (padding 0) when they fit,
 // and each chain draws the block's uniforms into its own LDS row.  A lane owns components
 // q = lane + L t (t < EPT) of the block, in registers, and residual entries m = lane + L t
 // (t < RPT), in registers for the whole launch.
@@ -23,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <utility>
 
 #include "internal.h"
 #include "rng_tn.h"
@@ -109,22 +112,86 @@ __device__ __forceinline__ void load_row(float2 (&vw)[EPT], const float2 *row, i
     for (int t = 0; t < EPT; ++t) vw[t] = row[lane + L * t];
 }
 
-// Copy n16 16-byte words from global memory to LDS with all threads, eight loads in flight
-// per thread.
-__device__ __forceinline__ void stage16(float4 *dst, const float4 *src, int n16, int tid, int nthr) {
+// The data-mode moves of one block (d_i > 0, modes 0..kb-1): interval, c = U_i . r, the
+// truncated-normal step, and the updates of A and r.  On return vw holds row kb.
+template <int L, int EPT, int RPT, bool ULDS>
+__device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const float *sD, const float *U,
+                                           const float *urow, int lane, float2 (&vw)[EPT], float (&Ar)[EPT],
+                                           float (&rr)[RPT]) {
+    constexpr int ROW = EPT * L;
+    constexpr int MP = RPT * L;
+    for (int i = 0; i < kb; ++i) {
+        float Ui[RPT];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) Ui[t] = U[i * MP + lane + L * t];
+        const float u = urow[i];
+        const float dd = sD[i];
+        float2 vn[EPT];
+        load_row<EPT>(vn, sVW + (i + 1) * ROW, lane, L);
+        float lo, hi;
+        interval32<L, EPT, false>(vw, Ar, lo, hi);
+        float cp = 0.0f;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[t], rr[t], cp);
+        const float cdot = seg_sum<L>(cp);
+        const float delta = tn_draw32(cdot, dd, lo, hi, u);
+        const float e = delta * dd;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
+            vw[t] = vn[t];
+        }
+    }
+}
+
+// Copy a block's factor chunk (the image of the staging area) to LDS with all threads,
+// eight words in flight per thread.
+__device__ __forceinline__ void stage_sync(float4 *dst, const float4 *src, int n, int tid, int nthr) {
     int i = tid;
-    for (; i + 7 * nthr < n16; i += 8 * nthr) {
+    for (; i + 7 * nthr < n; i += 8 * nthr) {
         float4 v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = src[i + k * nthr];
 #pragma unroll
         for (int k = 0; k < 8; ++k) dst[i + k * nthr] = v[k];
     }
-    for (; i < n16; i += nthr) dst[i] = src[i];
+    for (; i < n; i += nthr) dst[i] = src[i];
 }
 
-template <int L, int EPT, int RPT>
-__global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
+// The prefetch registers: PF words per thread, addressed with constant indices only (a fold
+// over an index sequence instead of a loop) and of the compiler's native vector type, so that
+// they stay in registers.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PF>
+struct Prefetch {
+    f32x4 w[PF > 0 ? PF : 1];
+
+    template <int... K>
+    __device__ __forceinline__ void load_(const f32x4 *src, int tid, int nthr, int n, std::integer_sequence<int, K...>) {
+        ((tid + K * nthr < n ? (void)(w[K] = src[tid + K * nthr]) : (void)0), ...);
+    }
+    template <int... K>
+    __device__ __forceinline__ void store_(f32x4 *dst, int tid, int nthr, int n, std::integer_sequence<int, K...>) const {
+        ((tid + K * nthr < n ? (void)(dst[tid + K * nthr] = w[K]) : (void)0), ...);
+    }
+    __device__ __forceinline__ void load(const float4 *src, int tid, int nthr, int n) {
+        load_(reinterpret_cast<const f32x4 *>(src), tid, nthr, n, std::make_integer_sequence<int, PF>{});
+    }
+    __device__ __forceinline__ void store(float4 *dst, int tid, int nthr, int n) const {
+        store_(reinterpret_cast<f32x4 *>(dst), tid, nthr, n, std::make_integer_sequence<int, PF>{});
+    }
+};
+
+// L lanes per chain, EPT components and RPT residual entries per lane; PF > 0: the next
+// block's factor stream is loaded into PF registers per thread while the current block is
+// sampled (when the plan's largest stream fits), so the block switch only writes LDS.
+// Prefetching instances run at most 256 threads per workgroup (one wavefront per SIMD),
+// which leaves them the whole register file.
+template <int L, int EPT, int RPT, int PF>
+__global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem32[];
     constexpr int ROW = EPT * L;
     constexpr int MP = RPT * L;
@@ -133,6 +200,7 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
     const int lane = tid % L;
     const int slotc = tid / L;
     float2 *sVW = reinterpret_cast<float2 *>(smem32);
+    float *sD = reinterpret_cast<float *>(smem32 + a.lds_off_d);
     float *sU = reinterpret_cast<float *>(smem32 + a.lds_off_u);
     float *sUnif = reinterpret_cast<float *>(smem32 + a.lds_off_unif);
     double *sAcc = reinterpret_cast<double *>(smem32 + a.lds_off_acc);
@@ -141,6 +209,8 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
     const int64_t nsw = a.nsw;
     // this launch accumulates into the workgroup's LDS sums (flushed once per tile)
     const bool acc_lds = a.accumulate && a.acc_lds && s0 + nsw > a.burnin;
+    const bool prefetch = PF > 0 && a.prefetch;
+    Prefetch<PF> pf;
 
     for (;;) {
         if (tid == 0) s_tile = atomicAdd(a.queue, 1);
@@ -165,6 +235,9 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
             rr[t] = (m < M && active) ? rg[m] : 0.0f;
         }
         float *urow = sUnif + slotc * ROW;
+        const int nw = (int)a.chunk_words;
+        float4 *stage = reinterpret_cast<float4 *>(smem32);
+        if (prefetch) pf.load(a.F32 + a.blocks[pd.off_blk].off_chunk, tid, nthr, nw);
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
             for (int64_t b = 0; b < pd.B; ++b) {
@@ -177,11 +250,11 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
                     Ar[t] = (q < nb && active) ? Ag[bd.n0 + q] : 0.0f;
                 }
                 __syncthreads();   // the previous block's readers of the LDS rows are done
-                stage16(reinterpret_cast<float4 *>(sVW), reinterpret_cast<const float4 *>(a.VW32 + bd.off_VW),
-                        nb * ROW / 2, tid, nthr);
-                if (a.u_lds)
-                    stage16(reinterpret_cast<float4 *>(sU), reinterpret_cast<const float4 *>(a.U32 + bd.off_U32),
-                            kb * MP / 4, tid, nthr);
+                if (prefetch) {
+                    pf.store(stage, tid, nthr, nw);
+                } else {
+                    stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
+                }
                 // this block's uniforms: one Philox call per four modes
                 for (int g = lane; 4 * g < nb; g += L) {
                     const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
@@ -193,40 +266,19 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
                     d[3] = word_u32(w.w);
                 }
                 __syncthreads();
-                const float *dv = a.d32 + bd.off_d32;
+                if (prefetch && (b + 1 < pd.B || s + 1 < s0 + nsw)) {
+                    // the next block of this sweep, or the first of the next
+                    pf.load(a.F32 + a.blocks[pd.off_blk + (b + 1 < pd.B ? b + 1 : 0)].off_chunk, tid, nthr, nw);
+                }
                 const float *Ug = a.U32 + bd.off_U32;
                 float2 vw[EPT];
                 load_row<EPT>(vw, sVW, lane, L);
-                // data modes
-                for (int i = 0; i < kb; ++i) {
-                    float Ui[RPT];
-                    if (a.u_lds) {
-#pragma unroll
-                        for (int t = 0; t < RPT; ++t) Ui[t] = sU[i * MP + lane + L * t];
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < RPT; ++t) Ui[t] = Ug[i * MP + lane + L * t];
-                    }
-                    const float u = urow[i];
-                    const float dd = dv[i];
-                    float2 vn[EPT];
-                    load_row<EPT>(vn, sVW + (i + 1) * ROW, lane, L);
-                    float lo, hi;
-                    interval32<L, EPT, false>(vw, Ar, lo, hi);
-                    float cp = 0.0f;
-#pragma unroll
-                    for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[t], rr[t], cp);
-                    const float cdot = seg_sum<L>(cp);
-                    const float delta = tn_draw32(cdot, dd, lo, hi, u);
-                    const float e = delta * dd;
-#pragma unroll
-                    for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) {
-                        Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
-                        vw[t] = vn[t];
-                    }
-                }
+                // data modes (U rows from LDS, or from global memory when they do not fit;
+                // two copies of the loop, so the LDS one waits on no global loads)
+                if (a.u_lds)
+                    data_moves<L, EPT, RPT, true>(kb, sVW, sD, sU, urow, lane, vw, Ar, rr);
+                else
+                    data_moves<L, EPT, RPT, false>(kb, sVW, sD, Ug, urow, lane, vw, Ar, rr);
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
                 int i = kb;
@@ -303,15 +355,15 @@ __global__ __launch_bounds__(512) void k_sample32(SampleArgs a) {
     }
 }
 
-template <int L, int EPT, int RPT>
+template <int L, int EPT, int RPT, int PF>
 hipError_t launch_sample32_t(const SampleArgs &a, int threads, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_sample32<L, EPT, RPT>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_sample32<L, EPT, RPT, PF>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <int L, int EPT, int RPT>
+template <int L, int EPT, int RPT, int PF>
 hipError_t allow_lds_sample32_t(int bytes) {
-    return hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT>,
+    return hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, PF>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

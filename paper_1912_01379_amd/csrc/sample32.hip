@@ -5,15 +5,15 @@ namespace asmk {
 
 namespace {
 struct Inst32 {
-    int L, EPT, RPT;
+    int L, EPT, RPT, PF;
 };
-// (lanes per chain, components per lane, residual entries per lane): a block of up to
-// EPT L grid points and a problem of up to RPT L data points
+// (lanes per chain, components per lane, residual entries per lane, prefetch words per
+// thread): a block of up to EPT L grid points and a problem of up to RPT L data points
 const Inst32 kInst32[] = {
-    {4, 8, 16}, {4, 32, 52}, {8, 4, 8}, {8, 13, 26}, {8, 16, 52}, {16, 2, 4}, {16, 7, 13}, {16, 8, 26}, {16, 8, 32}, {32, 1, 2}, {32, 4, 7}, {32, 4, 13}};
+    {4, 8, 16, 0}, {4, 32, 52, 0}, {8, 4, 8, 0}, {8, 13, 26, 0}, {8, 16, 52, 0}, {16, 2, 4, 0}, {16, 7, 13, 26}, {16, 8, 26, 0}, {16, 8, 32, 0}, {32, 1, 2, 0}, {32, 4, 7, 0}, {32, 4, 13, 0}};
 }  // namespace
 
-int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt) {
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pf) {
     int best = -1;
     for (int k = 0; k < (int)(sizeof kInst32 / sizeof kInst32[0]); ++k) {
         const Inst32 &c = kInst32[k];
@@ -24,6 +24,7 @@ int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt) 
     if (best < 0) return -1;
     *ept = kInst32[best].EPT;
     *rpt = kInst32[best].RPT;
+    *pf = kInst32[best].PF;
     return 0;
 }
 
@@ -31,6 +32,8 @@ hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt
                                 int grid, size_t lds_bytes, hipStream_t s) {
     const int threads = lanes * chains_per_wg;
     if (threads % 64 != 0 || threads > 512) return hipErrorInvalidValue;
+    // prefetching instances are compiled for at most 256 threads
+    if (a.prefetch && threads > 256) return hipErrorInvalidValue;
     switch (lanes) {
     case 4: return launch_sample32_l4(a, ept, rpt, threads, grid, lds_bytes, s);
     case 8: return launch_sample32_l8(a, ept, rpt, threads, grid, lds_bytes, s);

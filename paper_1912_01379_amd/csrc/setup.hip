@@ -361,26 +361,33 @@ hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, cons
 }
 
 // ------------------------------------------------------------------------------------
-// float32 packing: (V, w) pairs with w = -(1/V)(1 - 2^-21), mode-major rows padded to nbp
-// with (0, NaN); U rows padded to mp with zeros.  The shrink of w keeps the sampler's
-// computed interval inside the exact one after its roundings.  A NaN w is neutral in the
-// interval search, so a component with V = 0 (which no step along the mode can make
-// negative; entries below 2^-100 in magnitude are taken as 0) and the padding constrain
-// nothing, and a zero V leaves the component unchanged.  A zero mode whose V has entries of
-// one sign only has an unbounded interval (Sec. IV.B, d_i = 0: the posterior is improper):
-// bit 0 of *flags is set.
+// float32 packing.  Each block gets a chunk that is the exact image of its LDS staging area:
+//   cl.rows rows of cl.row (V, w) pairs, w = -(1/V)(1 - 2^-21), rows past the block's modes
+//     and entries past its grid points (0, NaN);
+//   cl.d_len singular values (0 past k_b);
+//   cl.u_rows rows of cl.mp U values (0 past k_b rows and past M).
+// The shrink of w keeps the sampler's computed interval inside the exact one after its
+// roundings.  A NaN w is neutral in the interval search, so a component with V = 0 (which no
+// step along the mode can make negative; entries below 2^-100 in magnitude are taken as 0)
+// and the padding constrain nothing, and a zero V leaves the component unchanged.  U is also
+// written to U32 (k_b rows of mp) for plans that read it from global memory.  A zero mode
+// whose V has entries of one sign only has an unbounded interval (Sec. IV.B, d_i = 0: the
+// posterior is improper): bit 0 of *flags is set.
 // ------------------------------------------------------------------------------------
 __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const double *V64,
-                         const double *U64, const double *d64, float2 *VW32, float *U32, float *d32,
-                         int *flags) {
+                         const double *U64, const double *d64, ChunkLayout cl, float4 *F32,
+                         float *U32, int *flags) {
     const BlockDesc bd = blocks[blockIdx.x];
     const int64_t M = blockM[blockIdx.x];
-    const int64_t nb = bd.nb, nbp = bd.nbp, kb = bd.kb, mp = bd.mp;
+    const int64_t nb = bd.nb, kb = bd.kb, mp = bd.mp;
     constexpr double kTiny = 0x1.0p-100;
-    for (int64_t i = threadIdx.x; i < nb * nbp; i += blockDim.x) {
-        const int64_t mode = i / nbp, q = i % nbp;
+    float2 *vwc = reinterpret_cast<float2 *>(F32 + bd.off_chunk);
+    float *dc = reinterpret_cast<float *>(vwc + cl.rows * cl.row);
+    float *uc = dc + cl.d_len;
+    for (int64_t i = threadIdx.x; i < cl.rows * cl.row; i += blockDim.x) {
+        const int64_t mode = i / cl.row, q = i % cl.row;
         float2 vw;
-        const double v = q < nb ? V64[bd.off_V + mode * nb + q] : 0.0;
+        const double v = (mode < nb && q < nb) ? V64[bd.off_V + mode * nb + q] : 0.0;
         if (fabs(v) >= kTiny) {
             vw.x = (float)v;
             vw.y = (float)(-(1.0 / v) * (1.0 - 0x1.0p-21));
@@ -388,7 +395,16 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
             vw.x = 0.0f;
             vw.y = __builtin_nanf("");
         }
-        VW32[bd.off_VW + i] = vw;
+        vwc[i] = vw;
+    }
+    for (int64_t i = threadIdx.x; i < cl.d_len; i += blockDim.x) dc[i] = i < kb ? (float)d64[bd.off_d + i] : 0.0f;
+    for (int64_t i = threadIdx.x; i < cl.u_rows * cl.mp; i += blockDim.x) {
+        const int64_t mode = i / cl.mp, m = i % cl.mp;
+        uc[i] = (mode < kb && m < M) ? (float)U64[bd.off_U + mode * M + m] : 0.0f;
+    }
+    for (int64_t i = threadIdx.x; i < kb * mp; i += blockDim.x) {
+        const int64_t mode = i / mp, m = i % mp;
+        U32[bd.off_U32 + i] = (m < M) ? (float)U64[bd.off_U + mode * M + m] : 0.0f;
     }
     for (int64_t i = kb + threadIdx.x; i < nb; i += blockDim.x) {
         bool pos = false, neg = false;
@@ -399,20 +415,15 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
         }
         if (!(pos && neg)) atomicOr(flags, 1);
     }
-    for (int64_t i = threadIdx.x; i < kb * mp; i += blockDim.x) {
-        const int64_t mode = i / mp, m = i % mp;
-        U32[bd.off_U32 + i] = (m < M) ? (float)U64[bd.off_U + mode * M + m] : 0.0f;
-    }
-    for (int64_t i = threadIdx.x; i < kb; i += blockDim.x) d32[bd.off_d32 + i] = (float)d64[bd.off_d + i];
 }
 
 hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
                                 int64_t nblocks, const double *V64, const double *U64,
-                                const double *d64, float2 *VW32, float *U32, float *d32, int *flags,
-                                hipStream_t s) {
+                                const double *d64, const ChunkLayout &cl, float4 *F32, float *U32,
+                                int *flags, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack32, dim3((unsigned)nblocks), dim3(256), 0, s, blocks_dev, blockM_dev, V64,
-                       U64, d64, VW32, U32, d32, flags);
+                       U64, d64, cl, F32, U32, flags);
     return hipGetLastError();
 }
 
