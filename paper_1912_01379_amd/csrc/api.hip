@@ -59,6 +59,11 @@ struct asm_plan {
     int64_t total_chains = 0, total_n = 0, total_m = 0;
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
     int ksplit = 1;          // chain splits of the cross-moment partial sums
+    // float32 plans with want_vjp: per-sweep snapshots of (A, r), reduced into the cross
+    // moments after each launch
+    float *snapA = nullptr, *snapR = nullptr;
+    int64_t snap_rows = 0, max_snap_tiles = 0, snap_words_a = 0, snap_words_r = 0;
+    int snap_waves = 1;
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
     int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS
     int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
@@ -290,8 +295,13 @@ int refresh(asm_plan *pl, bool measure_drift) {
 }
 
 // One segment of nsw sweeps starting at the device sweep counter; advances the counter.
-int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs) {
+int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool snap) {
     SampleArgs a = make_args(pl);
+    if (snap) {
+        a.snapA = pl->snapA;
+        a.snapR = pl->snapR;
+        a.snap_rows = pl->snap_rows;
+    }
     a.nsw = nsw;
     a.accumulate = accumulate;
     a.burnin = burnin_abs;
@@ -334,16 +344,24 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         int64_t seg = end - s;
         if (pl->fp32 && R > 0) seg = std::min(seg, R - s % R);   // stop where a refresh is due
         if (!pl->fp32 && seg > 256) seg = 256;
-        if (vjp && s + 1 > burnin_abs) seg = 1;                 // cross moment after every sweep
-        else if (vjp && s + seg > burnin_abs) seg = burnin_abs - s;
+        if (vjp && s + seg > burnin_abs && s < burnin_abs) seg = burnin_abs - s;   // burn-in apart
+        if (vjp && s >= burnin_abs) {
+            // float32: as many sweeps as the snapshot rows hold; float64: one sweep, whose
+            // state the cross-moment kernel reads directly
+            seg = pl->fp32 ? std::min(seg, pl->snap_rows) : 1;
+        }
         if (seg < 1) seg = 1;
-        TRY(segment(pl, seg, accumulate, burnin_abs));
+        const bool snap = vjp && pl->fp32 && s >= burnin_abs;
+        TRY(segment(pl, seg, accumulate, burnin_abs, snap));
         pl->sweep += seg;
-        if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
-        if (vjp && pl->sweep - 1 >= burnin_abs) {
+        if (snap) {
+            HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->snap_waves, pl->ksplit, seg,
+                                     pl->snapA, pl->snapR, pl->cross, pl->stream));
+        } else if (vjp && s >= burnin_abs) {
             HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->ksplit, pl->A32,
                                     pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->stream));
         }
+        if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
     }
     return ASM_OK;
 }
@@ -484,9 +502,32 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->total_n = offn;
     pl->total_m = offm;
     if (o->want_vjp) {
-        // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
-        const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
-        pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, C / 8}));
+        if (pl->fp32) {
+            // snapshots of every accumulated sweep of a launch (at most refresh_every or 64
+            // sweeps, and at most 16 GiB), rows padded to whole 16-byte words, reduced by
+            // (tile, split) workgroups
+            int64_t per_row = 0, max_m = 0;
+            for (auto &pd : pl->probs) {
+                per_row += pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
+                max_m = std::max(max_m, pd.M);
+            }
+            const int64_t cap = (int64_t)16 << 30;
+            const int64_t want_rows = o->refresh_every > 0 ? o->refresh_every : 64;
+            pl->snap_rows = std::max<int64_t>(1, std::min<int64_t>(want_rows, cap / std::max<int64_t>(per_row, 1)));
+            pl->snap_waves = (int)cross_snap_waves(max_m);
+            for (auto &pd : pl->probs) {
+                pd.off_sa = pl->snap_words_a;
+                pd.off_sr = pl->snap_words_r;
+                pl->snap_words_a += pl->snap_rows * pd.C * ((pd.N + 3) / 4 * 4);
+                pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
+                pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N, pl->snap_waves));
+            }
+            pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (512 + pl->max_snap_tiles - 1) / pl->max_snap_tiles));
+        } else {
+            // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
+            const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
+            pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, C / 8}));
+        }
         for (auto &pd : pl->probs) {
             pd.off_cross = offcross;
             offcross += (int64_t)pl->ksplit * pd.M * (pd.N + 1);
@@ -532,6 +573,10 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     if (o->want_vjp) {
         STEP(dalloc(pl, &pl->cross, offcross));
+        if (pl->fp32) {
+            STEP(dalloc(pl, &pl->snapA, pl->snap_words_a));
+            STEP(dalloc(pl, &pl->snapR, pl->snap_words_r));
+        }
         STEP(dalloc(pl, &pl->nsamples, n));
         STEP(dalloc(pl, &pl->vjp_y, offm));
     }

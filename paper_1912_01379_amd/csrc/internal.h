@@ -33,6 +33,8 @@ struct ProbDesc {
     int32_t has_cov;
     uint32_t index;           // problem index (keys the random numbers)
     int32_t pad;
+    int64_t off_sa;           // float32 snapshots of A (sweep, chain) rows of round4(N) floats
+    int64_t off_sr;           // float32 snapshots of r rows of round4(M) floats
 };
 
 struct BlockDesc {
@@ -99,6 +101,9 @@ struct SampleArgs {
     int32_t acc_lds;          // 1: accumulate in LDS and flush once per tile and launch
     int32_t prefetch;         // 1: every block's factor stream fits the instance's prefetch
     int32_t pad2;
+    float *snapA;             // nullable: per-sweep snapshots of A and r of the accumulated
+    float *snapR;             //   sweeps of the launch (at the problems' off_sa / off_sr), for
+    int64_t snap_rows;        //   the cross moments; snapshot = sweep - first sweep of the launch
 };
 
 // ------------------------------------------------------------------------------------
@@ -187,6 +192,11 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
 hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
                             const float *A32, const float *r32, const double *A64,
                             const double *r64, int fp32, double *cross, hipStream_t s);
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int waves, int ksplit,
+                             int64_t nsnap, const float *snapA, const float *snapR, double *cross,
+                             hipStream_t s);
+__host__ __device__ int64_t cross_snap_waves(int64_t max_m);
+__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N, int64_t W);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,

@@ -175,6 +175,117 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
     return hipGetLastError();
 }
 
+// Cross moments from the per-sweep snapshots of one launch of the float32 sampler: with the
+// rows k = (sweep, chain) of the snapshots,
+//   X_split[m][n] += sum_{k in split} r_k[m] A_k[n] (n < N),  X_split[m][N] += sum r_k[m].
+// A workgroup of W wavefronts owns a (32 W) x 128 output tile and a range of rows; each
+// wavefront owns 32 x 128 of it (2 x 8 MFMA f64 16x16x4 blocks).  The rows pass through LDS
+// in chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile
+// that needs it; the float32 values are widened to float64 as they enter the MFMAs.  The
+// snapshot rows are padded to multiples of four floats (snap_ld_r, snap_ld_a).
+constexpr int kSnapTN = 128, kSnapKC = 32, kSnapMaxW = 8;
+
+__host__ __device__ int64_t cross_snap_waves(int64_t max_m) {
+    const int64_t w = (max_m + 31) / 32;
+    return w < kSnapMaxW ? w : kSnapMaxW;
+}
+
+__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N, int64_t W) {
+    return ((M + 32 * W - 1) / (32 * W)) * ((N + 1 + kSnapTN - 1) / kSnapTN);
+}
+
+__global__ __launch_bounds__(512) void k_cross_snap(const ProbDesc *probs, int ksplit, int64_t nsnap,
+                                                    const float *snapA, const float *snapR, double *cross) {
+    extern __shared__ __align__(16) float smx[];
+    const ProbDesc pd = probs[blockIdx.z];
+    const int W = blockDim.x / 64;
+    const int64_t M = pd.M, N = pd.N, N1 = N + 1;
+    const int64_t ldr = (M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
+    const int64_t TM = 32 * W;
+    const int64_t ntn = (N1 + kSnapTN - 1) / kSnapTN;
+    const int64_t tile = blockIdx.x;
+    if (tile >= cross_snap_tiles(M, N, W)) return;
+    const int split = blockIdx.y;
+    const int64_t m0 = (tile / ntn) * TM, n0 = (tile % ntn) * kSnapTN;
+    const int64_t K = nsnap * pd.C;
+    const int64_t k_lo = K * split / ksplit, k_hi = K * (split + 1) / ksplit;
+    const float *Rb = snapR + pd.off_sr;
+    const float *Ab = snapA + pd.off_sa;
+    float *sr = smx;                      // kSnapKC x TM
+    float *sa = smx + kSnapKC * TM;       // kSnapKC x kSnapTN
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int i = lane % 16, kk = lane / 16;
+    d4 acc[2][8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
+        const int64_t kc = (k_hi - c0) < kSnapKC ? (k_hi - c0) : kSnapKC;
+        __syncthreads();   // the previous chunk is consumed
+        // r rows: kc x TM (columns past M, rows past kc: 0)
+        for (int e = tid; e < kSnapKC * TM / 4; e += blockDim.x) {
+            const int row = e / (TM / 4), c4 = e % (TM / 4);
+            const int64_t m = m0 + 4 * c4;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < kc && m < ldr) v = *reinterpret_cast<const float4 *>(Rb + (c0 + row) * ldr + m);
+            if (m + 0 >= M) v.x = 0.f;
+            if (m + 1 >= M) v.y = 0.f;
+            if (m + 2 >= M) v.z = 0.f;
+            if (m + 3 >= M) v.w = 0.f;
+            *reinterpret_cast<float4 *>(sr + row * TM + 4 * c4) = v;
+        }
+        // A rows with the column of ones at n = N: kc x 128
+        for (int e = tid; e < kSnapKC * kSnapTN / 4; e += blockDim.x) {
+            const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
+            const int64_t n = n0 + 4 * c4;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < kc) {
+                if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + (c0 + row) * lda + n);
+                if (n + 0 >= N) v.x = (n + 0 == N) ? 1.f : 0.f;
+                if (n + 1 >= N) v.y = (n + 1 == N) ? 1.f : 0.f;
+                if (n + 2 >= N) v.z = (n + 2 == N) ? 1.f : 0.f;
+                if (n + 3 >= N) v.w = (n + 3 == N) ? 1.f : 0.f;
+            }
+            *reinterpret_cast<float4 *>(sa + row * kSnapTN + 4 * c4) = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k4 = 0; k4 < kSnapKC; k4 += 4) {
+            const int row = k4 + kk;
+            double ra[2], bb[8];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * TM + 32 * wave + 16 * a + i];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) bb[b] = (double)sa[row * kSnapTN + 16 * b + i];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    double *X = cross + pd.off_cross + (int64_t)split * M * N1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = m0 + 32 * wave + 16 * a + lane / 16 + 4 * j, col = n0 + 16 * b + lane % 16;
+                if (row < M && col < N1) X[row * N1 + col] += acc[a][b][j];
+            }
+}
+
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int waves, int ksplit,
+                             int64_t nsnap, const float *snapA, const float *snapR, double *cross,
+                             hipStream_t s) {
+    const size_t lds = (size_t)kSnapKC * (32 * waves + kSnapTN) * sizeof(float);
+    hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(64 * waves),
+                       lds, s, probs_dev, ksplit, nsnap, snapA, snapR, cross);
+    return hipGetLastError();
+}
+
 // One thread per (problem, n): group sums in a fixed order, then mean, standard error over
 // the groups and posterior standard deviation.
 __global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_prefix,
@@ -241,10 +352,12 @@ hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *
 // y_m = (1/S) sum_n X[m][n] v_n - rbar_m (Abar . v) with X summed over the splits and
 // rbar_m = X[m][N] / S; then grad = -T^T y: -y/sigma for iid noise, or -L^-T y for a
 // covariance C = L L^T.
-__global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix, int ksplit,
-                        const double *cross, const double *mean, const double *nsamples,
-                        const double *sigma, const double *v, double *y, double *grad) {
-    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix,
+                                               int ksplit, const double *cross, const double *mean,
+                                               const double *nsamples, const double *sigma, const double *v,
+                                               double *y, double *grad) {
+    // one workgroup per data point m (over all problems); threads over n
+    const int64_t gi = blockIdx.x;
     if (gi >= m_prefix[P]) return;
     int64_t lo = 0, hi = P - 1;
     while (lo < hi) {
@@ -258,15 +371,31 @@ __global__ void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefi
     const double *vv = v + pd.off_n;
     const double *mu = mean + pd.off_n;
     double xv = 0.0, av = 0.0, rs = 0.0;
-    for (int k = 0; k < ksplit; ++k) {
-        const double *X = cross + pd.off_cross + (int64_t)k * M * N1 + m * N1;
-        for (int64_t n = 0; n < N; ++n) xv += X[n] * vv[n];
-        rs += X[N];
+    for (int64_t n = threadIdx.x; n <= N; n += blockDim.x) {
+        double x = 0.0;
+        for (int k = 0; k < ksplit; ++k) x += cross[pd.off_cross + (int64_t)k * M * N1 + m * N1 + n];
+        if (n < N) {
+            xv += x * vv[n];
+            av += mu[n] * vv[n];
+        } else {
+            rs = x;
+        }
     }
-    for (int64_t n = 0; n < N; ++n) av += mu[n] * vv[n];
-    const double ym = xv / S - (rs / S) * av;
-    y[pd.off_m + m] = ym;
-    if (!pd.has_cov) grad[pd.off_m + m] = -ym / sigma[pd.off_m + m];
+    __shared__ double red[3][256];
+    red[0][threadIdx.x] = xv;
+    red[1][threadIdx.x] = av;
+    red[2][threadIdx.x] = rs;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ym = red[0][0] / S - (red[2][0] / S) * red[1][0];
+        y[pd.off_m + m] = ym;
+        if (!pd.has_cov) grad[pd.off_m + m] = -ym / sigma[pd.off_m + m];
+    }
 }
 
 // x = L^-T y (back substitution), grad = -x; one workgroup per problem with a covariance.
@@ -297,7 +426,7 @@ hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_pre
                       int64_t total_m, int ksplit, const double *cross, const double *mean,
                       const double *nsamples, const double *sigma, const double *Lchol,
                       const double *v, double *y, double *grad, int any_cov, hipStream_t s) {
-    hipLaunchKernelGGL(k_vjp_y, dim3((unsigned)((total_m + 127) / 128)), dim3(128), 0, s, probs_dev,
+    hipLaunchKernelGGL(k_vjp_y, dim3((unsigned)total_m), dim3(256), 0, s, probs_dev,
                        P, m_prefix_dev, ksplit, cross, mean, nsamples, sigma, v, y, grad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !any_cov) return e;

@@ -302,6 +302,14 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     const int q = lane + L * t;
                     if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
                 }
+                if (a.snapA && s >= a.burnin) {
+                    float *sa = a.snapA + pd.off_sa + ((s - s0) * pd.C + chain) * ((N + 3) / 4 * 4) + bd.n0;
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) {
+                        const int q = lane + L * t;
+                        if (active && q < nb) sa[q] = Ar[t];
+                    }
+                }
                 if (a.accumulate && s >= a.burnin) {
                     // sums over the tile's chains, float64; the uniforms of this block are
                     // consumed, so each chain's row now carries its components
@@ -335,6 +343,14 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                             s2[q] += x2;
                         }
                     }
+                }
+            }
+            if (a.snapR && s >= a.burnin) {
+                float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
+#pragma unroll
+                for (int t = 0; t < RPT; ++t) {
+                    const int m = lane + L * t;
+                    if (active && m < M) sr[m] = rr[t];
                 }
             }
         }
