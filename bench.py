@@ -10,10 +10,14 @@ burn-in and 10000 measured sweeps, float32 chain state):
 The problem arrays are on the GPU before the timed region starts.
 
 Prints one JSON line (see the fields below).  Only one GPU is supported.
+
+    python bench.py [--steps K] [--warmup W] [--no-vjp] [--no-cpu]
+    python bench.py --copy-probe     # a plain 1 GiB device copy, to calibrate HBM counters
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,21 +28,49 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_LANE_OPS = 256 * 64 * 2.4e9   # MI355X: 256 CUs x 64 fp32 lanes x 2.4 GHz (non-packed)
+# MI355X: 256 CUs x 64 float32 lanes x 2.4 GHz, one operation per lane per cycle (no packed
+# float32 arithmetic; a fused multiply-add counts as one operation)
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "tn32.h", "tn32_coef.h", "rng_tn.h", "internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sample32_single_continuation_traffic.md")
 
 
-def lane_ops_per_sweep(M, blocks):
+def lane_ops_per_sweep(M, blocks, s_tn=40, s_u=10):
     """Algorithmic lane-operations of one chain-sweep.
 
-    Per move of a block with nb components: 4 per component (ratio to the stored
-    reciprocal, min/max into the interval, fused update, clamp) plus the scalar draw
-    (4 for a flat draw, 40 for the truncated normal); a data move adds 2 per data point
-    (the dot product U_i . r and the residual update).
+    A move of a block with nb grid points costs 3 operations per component (the ratio that
+    bounds the step, its min/max into the interval, the update of A); a data move adds 2 per
+    data point (c = U_i . r and the update of r) and s_tn for the truncated-normal draw, a
+    zero move s_u for the flat draw.
     """
     ops = 0
     for nb, kb in blocks:
-        ops += kb * (4 * nb + 2 * M + 40) + (nb - kb) * (4 * nb + 4)
+        ops += kb * (2 * M + 3 * nb + s_tn) + (nb - kb) * (3 * nb + s_u)
     return ops
+
+
+def sampler_source_hash():
+    h = hashlib.sha256()
+    for name in SAMPLER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_01379_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sampler launch from the committed counter summary, if it was taken on
+    the current sampler sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                line = line.strip()
+                if line.startswith("{") and '"sources"' in line:
+                    rec = json.loads(line)
+                    if rec.get("sources") == sampler_source_hash():
+                        return rec
+    except OSError:
+        pass
+    return None
 
 
 class _DevProblem:
@@ -56,22 +88,36 @@ class _DevProblem:
 def cpu_baseline(prob, seconds_target=15.0):
     """The CPU oracle on the host cores, on a bounded sample of the same workload."""
     import oracle
-    threads = min(os.cpu_count() or 1, 64)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = max(1, min(threads, os.cpu_count() or 1, 64))
     prep = oracle.prepare(prob)
     chains = 4 * threads
     # calibrate on a short run, then size the sample to about seconds_target
     t = time.time()
     oracle.run(prep, chains=threads, burnin=0, sweeps=20, threads=threads, groups=1)
     dt = max(time.time() - t, 1e-3)
-    per_chain_sweep = dt / (20.0 * threads / threads)   # seconds per sweep of `threads` chains
-    sweeps = int(max(20, min(5000, seconds_target / (per_chain_sweep * chains / threads))))
+    sec_per_sweep = dt / 20.0 * (chains / threads)   # seconds per sweep of all sample chains
+    sweeps = int(max(20, min(5000, seconds_target / sec_per_sweep)))
     t = time.time()
     oracle.run(prep, chains=chains, burnin=0, sweeps=sweeps, threads=threads, groups=4)
     dt = time.time() - t
     moves = chains * sweeps * prob.N
     return {"value": moves / dt, "unit": "mode-moves/s", "cores": threads, "kind": "oracle",
             "sample": f"{chains} chains x {sweeps} sweeps of the same problem from the flat start "
-                      f"({moves:.3g} moves, {dt:.1f} s)"}
+                      f"({moves:.3g} moves, {dt:.1f} s, float64)"}
+
+
+def copy_probe():
+    """A plain device copy of 1 GiB, three times: the FETCH_SIZE / WRITE_SIZE counters of
+    this kernel calibrate the counters of the sampler."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "repeats": 3}))
 
 
 def main():
@@ -85,10 +131,14 @@ def main():
     ap.add_argument("--no-vjp", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import torch
     import workloads
@@ -132,16 +182,22 @@ def main():
 
     res, fwd_s, vjp_s, blocks, _ = outs[-1]
     st = res.stats
-    moves_per_step = args.chains * (args.burnin + args.sweeps) * prob.N
+    sweeps_total = args.burnin + args.sweeps
+    moves_per_step = args.chains * sweeps_total * prob.N
+    data_per_step = args.chains * sweeps_total * sum(k for _, k in blocks)
     value = moves_per_step * args.steps / elapsed
+    step_s = elapsed / args.steps
     # roofline of the sampler kernel from its own launch events
     ops_sweep = lane_ops_per_sweep(prob.M, blocks)
-    achieved = ops_sweep * args.chains * st["sampler_sweeps"] / (st["sampler_ms"] * 1e-3)
+    avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
+    ops_per_launch = ops_sweep * args.chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
+    achieved = ops_per_launch / avg_launch_s
+    tr = measured_traffic()
     mean = res.mean.cpu().numpy()
     se = res.stderr.cpu().numpy()
     sd = res.post_sd.cpu().numpy()
     ess = (sd / se) ** 2
-    step_s = elapsed / args.steps
+    tau = args.chains * args.sweeps / ess
 
     # the plain sampler: float64, one chain per launch
     plain = pk.Plan([dp], chains=1, burnin=0, sweeps=20, seed=7, precision="fp64", groups=1,
@@ -170,15 +226,21 @@ def main():
                    "chains_per_workgroup": st["chains_per_block"],
                    "data_modes_per_block": [k for _, k in blocks]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
-                     "unit": "lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "lane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": None if tr is None else tr["bytes_per_launch"],
                      "kernel": "k_sample32", "ops_per_chain_sweep": ops_sweep,
-                     "sampler_ms_per_step": st["sampler_ms"],
-                     "avg_launch_ms": st["sampler_ms"] / max(1, st["sampler_launches"])},
+                     "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches_per_step": st["sampler_launches"]},
+        "chain_sweeps_per_s": args.chains * sweeps_total * args.steps / elapsed,
+        "data_moves_per_s": data_per_step * args.steps / elapsed,
+        "zero_moves_per_s": (moves_per_step - data_per_step) * args.steps / elapsed,
         "ess_per_s": {"min": float(np.nanmin(ess)) / step_s, "median": float(np.nanmedian(ess)) / step_s},
+        "tau_int_sweeps": {"max": float(np.nanmax(tau)), "median": float(np.nanmedian(tau))},
         "forward_ms": fwd_s * 1e3,
         "vjp_ms": vjp_s * 1e3 if want_vjp else None,
         "vjp_over_forward": (vjp_s / fwd_s) if want_vjp else None,
         "setup_ms": st["setup_ms"],
+        "sampler_ms_per_step": st["sampler_ms"],
         "chi2_drift_max": st["chi2_drift_max"],
         "plain_fp64_mode_moves_per_s": plain_rate,
         "speedup_vs_plain": value / plain_rate,
