@@ -89,7 +89,9 @@ typedef struct {
     int32_t groups;              /* independent chain groups for the error bars (default 32);
                                     with fewer chains than groups, batches of sweeps are used */
     int32_t lanes_per_chain;     /* ASM_FP32 only: 4, 8, 16 or 32 lanes per chain, 0 = tune   */
-    int32_t use_graph;           /* 1: replay the sweep segments from a captured hipGraph     */
+    int32_t use_graph;           /* 1: ASM_FP32 plans replay each refresh cycle (sampler launch,
+                                    cross moments, float64 refresh) from a hipGraph captured
+                                    once per run; results are identical to eager launches    */
     int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
                                     or ASM_START_NNLS                                        */
 } asm_options;
@@ -117,6 +119,8 @@ typedef struct {
                                     events recorded around each launch on the plan's stream  */
     int64_t sampler_launches;    /* number of those launches                                  */
     int64_t sampler_sweeps;      /* sweeps they covered (each over all chains)                */
+    int64_t graph_replays;       /* refresh cycles replayed from a captured hipGraph (use_graph);
+                                    their sampler launches are not in sampler_ms             */
 } asm_stats;
 
 /* Validate the problems, whiten them, decompose every block (float64 one-sided Jacobi SVD,

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
                 ("clamped", ctypes.c_int64), ("frozen", ctypes.c_int64),
                 ("lanes_per_chain", ctypes.c_int32), ("chains_per_block", ctypes.c_int32),
                 ("sampler_ms", ctypes.c_double), ("sampler_launches", ctypes.c_int64),
-                ("sampler_sweeps", ctypes.c_int64)]
+                ("sampler_sweeps", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -105,11 +107,12 @@ struct asm_plan {
     size_t tev_used = 0;
     bool timing = false;
     int64_t timed_sweeps = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int64_t graph_nsw = 0;
-    int graph_accumulate = -1;
-    int64_t graph_burnin = -1;
+    // use_graph: one refresh cycle of the float32 sampler captured per kind (burn-in or
+    // accumulating, with or without VJP snapshots) and replayed; recaptured per run
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t gburnin[4] = {-1, -1, -1, -1};
+    hipStream_t gstream = nullptr;   // capture stream when the plan's stream is the null stream
+    int64_t graph_replays = 0;
 };
 
 namespace {
@@ -334,6 +337,54 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     return ASM_OK;
 }
 
+// One refresh cycle of the float32 sampler (R sweeps starting at a multiple of R): the
+// sampler launch, the sweep-counter bump, the cross moments of its snapshots and the float64
+// refresh.  With use_graph the cycle is captured once per run and kind and replayed; it holds
+// kernel launches only (no memsets, no host work), and every argument is the same for each
+// cycle of the run (the kernels read the sweep counter from device memory).
+int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap) {
+    auto body = [&]() -> int {
+        TRY(segment(pl, R, accumulate, burnin_abs, snap));
+        if (snap)
+            HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->snap_waves, pl->ksplit, R,
+                                     pl->snapA, pl->snapR, pl->cross, pl->stream));
+        TRY(refresh(pl, true));
+        return ASM_OK;
+    };
+    if (!pl->opt.use_graph) return body();
+    const int key = (accumulate ? 1 : 0) | (snap ? 2 : 0);
+    if (!pl->gexec[key] || pl->gburnin[key] != burnin_abs) {
+        if (pl->gexec[key]) HIPCHK(hipGraphExecDestroy(pl->gexec[key]));
+        pl->gexec[key] = nullptr;
+        // capture on the plan's stream, or on a private stream when that is the null stream
+        hipStream_t user = pl->stream;
+        if (!user) {
+            if (!pl->gstream) HIPCHK(hipStreamCreate(&pl->gstream));
+            pl->stream = pl->gstream;
+        }
+        const bool timing = pl->timing;
+        pl->timing = false;
+        HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeRelaxed));
+        const int brc = body();
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(pl->stream, &g);
+        pl->timing = timing;
+        pl->stream = user;
+        if (brc != ASM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return brc;
+        }
+        HIPCHK(ee);
+        const hipError_t ie = hipGraphInstantiate(&pl->gexec[key], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ie);
+        pl->gburnin[key] = burnin_abs;
+    }
+    HIPCHK(hipGraphLaunch(pl->gexec[key], pl->stream ? pl->stream : pl->gstream));
+    ++pl->graph_replays;
+    return ASM_OK;
+}
+
 // Run sweeps [sweep, sweep + total) with accumulation from burnin_abs on (if accumulate).
 int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) {
     const int64_t R = pl->opt.refresh_every;
@@ -341,6 +392,15 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     const bool vjp = accumulate && pl->opt.want_vjp;
     while (pl->sweep < end) {
         const int64_t s = pl->sweep;
+        // whole refresh cycles of the float32 sampler go through cycle() (a graph replay with
+        // use_graph); they must not straddle the end of burn-in and must fit the snapshots
+        if (pl->fp32 && R > 0 && s % R == 0 && s + R <= end && (s >= burnin_abs || s + R <= burnin_abs) &&
+            (!(vjp && s >= burnin_abs) || pl->snap_rows >= R)) {
+            const bool snap = vjp && s >= burnin_abs;
+            TRY(cycle(pl, R, accumulate, burnin_abs, snap));
+            pl->sweep += R;
+            continue;
+        }
         int64_t seg = end - s;
         if (pl->fp32 && R > 0) seg = std::min(seg, R - s % R);   // stop where a refresh is due
         if (!pl->fp32 && seg > 256) seg = 256;
@@ -366,6 +426,76 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     return ASM_OK;
 }
 
+// Lanes per chain for a float32 plan created with lanes_per_chain = 0: every width with a
+// compiled instance that fits the problems is timed on a throwaway plan (2 warm-up sweeps,
+// then 8 timed sweeps on the plan's stream) and the fastest is kept, per shape of the batch
+// (problem sizes, partitions, k, chains) for the rest of the process.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream, int *best) {
+    std::string key = std::to_string(o->chains) + ":" + std::to_string(o->refresh_every) + ":" +
+                      std::to_string(o->start);
+    int64_t max_nb = 0, max_m = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        key += "|" + std::to_string(pr[p].M) + "," + std::to_string(pr[p].N) + "," + (pr[p].cov ? "c" : "s");
+        max_m = std::max(max_m, pr[p].M);
+        for (int64_t b = 0; b < pr[p].B; ++b) {
+            const int64_t nb = pr[p].block_start[b + 1] - pr[p].block_start[b];
+            max_nb = std::max(max_nb, nb);
+            key += "," + std::to_string(nb) + ":" + std::to_string(pr[p].k ? pr[p].k[b] : -1);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = it->second;
+            return ASM_OK;
+        }
+    }
+    std::vector<int> cand;
+    for (int L : {4, 8, 16, 32}) {
+        int e, r, f;
+        if (sample32_pick(L, max_nb, max_m, &e, &r, &f) == 0) cand.push_back(L);
+    }
+    if (cand.empty()) return fail(ASM_EINVAL, "block of %lld points or %lld data points too large for the float32 sampler",
+                                  (long long)max_nb, (long long)max_m);
+    int chosen = cand[0];
+    if (cand.size() > 1) {
+        float best_ms = -1.0f;
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (int L : cand) {
+            asm_options so = *o;
+            so.lanes_per_chain = L;
+            so.want_vjp = 0;
+            so.use_graph = 0;
+            asm_plan *sp = nullptr;
+            if (asm_plan_create(pr, n, &so, hip_stream, &sp) != ASM_OK) continue;
+            float ms = -1.0f;
+            if (asm_plan_advance(sp, 2) == ASM_OK && hipEventRecord(e0, st) == hipSuccess &&
+                asm_plan_advance(sp, 8) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
+                hipEventSynchronize(e1) == hipSuccess)
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            asm_plan_destroy(sp);
+            if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                chosen = L;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        g_err.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = chosen;
+    *best = chosen;
+    return ASM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -376,8 +506,9 @@ int asm_version(void) { return 100; }
 
 int asm_plan_destroy(asm_plan *pl) {
     if (!pl) return ASM_OK;
-    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
-    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (auto &g : pl->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
     for (auto &e : pl->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : pl->tev) (void)hipEventDestroy(e);
@@ -392,6 +523,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (!out) return fail(ASM_EINVAL, "out is NULL");
     *out = nullptr;
     TRY(validate(pr, n, o));
+    asm_options tuned;
+    if (o->precision == ASM_FP32 && o->lanes_per_chain == 0) {
+        int L = 16;
+        TRY(tune_lanes(pr, n, o, hip_stream, &L));
+        tuned = *o;
+        tuned.lanes_per_chain = L;
+        o = &tuned;
+    }
     asm_plan *pl = new asm_plan();
     int rc = ASM_OK;
     struct Guard {
@@ -882,6 +1021,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     pl->timing = true;
     pl->tev_used = 0;
     pl->timed_sweeps = 0;
+    pl->graph_replays = 0;
     int lrc = sweep_loop(pl, pl->opt.burnin + pl->opt.sweeps, 1, burnin_abs);
     pl->timing = false;
     TRY(lrc);
@@ -929,6 +1069,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         stats->sampler_ms = smp;
         stats->sampler_launches = (int64_t)(pl->tev_used / 2);
         stats->sampler_sweeps = pl->timed_sweeps;
+        stats->graph_replays = pl->graph_replays;
     }
     if (hflags & 1) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
     return ASM_OK;

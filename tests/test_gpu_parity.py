@@ -344,3 +344,44 @@ def test_vjp_needs_want_vjp_and_a_run(pk):
         plan.vjp(np.zeros(p.N))
     assert e.value.code == pk.ASM_ESTATE
     plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# graph replay and the lanes-per-chain tuner
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("want_vjp", [False, True])
+def test_graph_replay_matches_eager(pk, want_vjp):
+    """Refresh cycles replayed from a captured hipGraph give the eager results bit for bit,
+    over two runs of the same plans (eager work and synchronisations between the replays)."""
+    p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
+    kw = dict(chains=128, burnin=64, sweeps=192, seed=31, precision="fp32", groups=32,
+              refresh_every=64, lanes_per_chain=16, want_vjp=want_vjp)
+    eager = pk.Plan([p], use_graph=False, **kw)
+    graph = pk.Plan([p], use_graph=True, **kw)
+    v = np.linspace(-1.0, 1.0, p.N)
+    for rep in range(2):
+        re_, rg = eager.run(), graph.run()
+        assert rg.stats["graph_replays"] == 4 and re_.stats["graph_replays"] == 0
+        for name in ("mean", "stderr", "post_sd"):
+            assert np.array_equal(getattr(re_, name).cpu().numpy(), getattr(rg, name).cpu().numpy()), (rep, name)
+        if want_vjp:
+            assert np.array_equal(eager.vjp(v).cpu().numpy(), graph.vjp(v).cpu().numpy())
+        Ae, re2, _ = eager.state(0)
+        Ag, rg2, _ = graph.state(0)
+        assert np.array_equal(Ae.cpu().numpy(), Ag.cpu().numpy())
+        assert np.array_equal(re2.cpu().numpy(), rg2.cpu().numpy())
+    eager.close()
+    graph.close()
+
+
+def test_tuner_picks_a_compiled_width_and_remembers_it(pk):
+    p = workloads.small_problem(M=41, N=48, nblocks=3, seed=5)
+    a = pk.Plan([p], chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, lanes_per_chain=0)
+    ra = a.run()
+    b = pk.Plan([p], chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, lanes_per_chain=0)
+    rb = b.run()
+    assert ra.stats["lanes_per_chain"] in (4, 8, 16, 32)
+    assert rb.stats["lanes_per_chain"] == ra.stats["lanes_per_chain"]
+    a.close()
+    b.close()
