@@ -120,6 +120,51 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": 4 * n, "repeats": 3}))
 
 
+def batched(args):
+    """The batched workload: 256 continuations of uneven size (M in [51, 201], N in
+    [200, 1000], B = round(N / 100) blocks, k = min(20, N_b)), 256 chains each, in one
+    persistent launch per refresh cycle, replayed from a hipGraph; lanes per chain tuned."""
+    import torch
+    import workloads
+    import paper_1912_01379_amd as pk
+    dev = torch.device("cuda:0")
+    probs = workloads.config3(256)
+    dps = [_DevProblem(p, dev) for p in probs]
+    chains = 256
+    sweeps_total = args.burnin + args.sweeps
+
+    def step():
+        plan = pk.Plan(dps, chains=chains, burnin=args.burnin, sweeps=args.sweeps, seed=2025,
+                       precision="fp32", refresh_every=64, want_vjp=False, groups=32,
+                       lanes_per_chain=args.lanes, use_graph=True, start="nnls", device=dev)
+        res = plan.run()
+        torch.cuda.synchronize()
+        plan.close()
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = res.stats
+    moves = chains * sweeps_total * sum(p.N for p in probs)
+    out = {"metric": "mode-moves/s", "value": moves * args.steps / elapsed, "unit": "mode-moves/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched: 256 continuations, M in [51,201], N in [200,1000], "
+                                  "B = round(N/100), k <= 20, 256 chains each, fp32, NNLS start, hipGraph",
+                      "chains_total": chains * len(probs), "burnin": args.burnin, "sweeps": args.sweeps,
+                      "lanes_per_chain": st["lanes_per_chain"], "chains_per_workgroup": st["chains_per_block"],
+                      "graph_replays": st["graph_replays"]},
+           "setup_ms": st["setup_ms"], "sample_ms": st["sample_ms"]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,12 +177,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--graph", action="store_true", help="replay refresh cycles from a hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "batched":
+        batched(args)
         return
 
     import torch
@@ -153,7 +203,7 @@ def main():
     def step():
         plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2024,
                        precision="fp32", refresh_every=64, want_vjp=want_vjp, groups=32,
-                       lanes_per_chain=args.lanes, start="nnls", device=dev)
+                       lanes_per_chain=args.lanes, start="nnls", use_graph=args.graph, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = plan.run()
