@@ -385,3 +385,51 @@ def test_tuner_picks_a_compiled_width_and_remembers_it(pk):
     assert rb.stats["lanes_per_chain"] == ra.stats["lanes_per_chain"]
     a.close()
     b.close()
+
+
+# --------------------------------------------------------------------------------------
+# differentiation by common random numbers, and the large correlated-noise workload
+# --------------------------------------------------------------------------------------
+
+def test_vjp_matches_common_random_number_differences(pk):
+    """v . (<A>(G + h u) - <A>(G - h u)) / 2h against (J^T v) . u, float64 sampler, the same
+    random numbers on both sides (the inverse-CDF draw is continuous in the data)."""
+    p = workloads.small_problem(M=21, N=10, nblocks=2, sigma=2e-2, seed=31)
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(p.N)
+    u = rng.standard_normal(p.M)
+    u /= np.linalg.norm(u)
+    kw = dict(chains=256, burnin=300, sweeps=3000, groups=32, seed=2024, precision="fp64")
+    base = pk.Plan([p], want_vjp=True, **kw)
+    base.run()
+    jv = base.vjp(v).cpu().numpy()
+    base.close()
+    h = 1e-3 * p.sigma[0]
+    outs = []
+    for sgn in (+1, -1):
+        q = workloads.Problem(K=p.K, G=p.G + sgn * h * u, sigma=p.sigma, block_start=p.block_start)
+        pl = pk.Plan([q], **kw)
+        outs.append(float(pl.run().mean.cpu().numpy() @ v))
+        pl.close()
+    fd = (outs[0] - outs[1]) / (2 * h)
+    assert abs(fd - jv @ u) < 0.1 * max(abs(fd), np.linalg.norm(jv) * 0.1), (fd, jv @ u)
+
+
+def test_large_correlated_noise_workload_properties(pk):
+    """The large workload (M 401, N 4000 in 32 blocks, k 30, Cholesky whitening of correlated
+    noise) at 1024 chains: carried residual equal to g~ - K~ A after a refresh, finite error
+    bars and VJP, and the sum rule of the spectrum kept."""
+    p = workloads.config5()
+    plan = pk.Plan([p], chains=1024, burnin=64, sweeps=64, seed=5, precision="fp32", refresh_every=64,
+                   want_vjp=True, groups=32, start="nnls")
+    res = plan.run()
+    g = plan.vjp(workloads.config4_cotangent(p.N)).cpu().numpy()
+    m, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
+    assert np.all(np.isfinite(m)) and np.all(m >= 0) and np.all(np.isfinite(se)) and np.all(np.isfinite(g))
+    assert abs(float(np.sum(m * p.weights)) - 1.0) < 0.02
+    A, r, _ = plan.state(0)
+    Kt, gt = plan.whitened(0)
+    rr = gt[None, :] - A[:128] @ Kt.T
+    assert float((r[:128] - rr).abs().max() / rr.abs().max()) < 1e-5
+    assert res.stats["chi2_drift_max"] < 1e-2
+    plan.close()
