@@ -63,9 +63,14 @@ struct asm_plan {
     int ksplit = 1;          // chain splits of the cross-moment partial sums
     // float32 plans with want_vjp: per-sweep snapshots of (A, r), reduced into the cross
     // moments after each launch
-    float *snapA = nullptr, *snapR = nullptr;
+    // two snapshot buffers: the sampler fills one while the cross moments of the other are
+    // reduced on a second stream (xstream), ordered by events
+    float *snapA[2] = {nullptr, nullptr}, *snapR[2] = {nullptr, nullptr};
     int64_t snap_rows = 0, max_snap_tiles = 0, snap_words_a = 0, snap_words_r = 0;
-    int snap_waves = 1;
+    hipStream_t xstream = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int snap_par = 0;
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
     int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS
     int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
@@ -109,8 +114,8 @@ struct asm_plan {
     int64_t timed_sweeps = 0;
     // use_graph: one refresh cycle of the float32 sampler captured per kind (burn-in or
     // accumulating, with or without VJP snapshots) and replayed; recaptured per run
-    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-    int64_t gburnin[4] = {-1, -1, -1, -1};
+    hipGraphExec_t gexec[8] = {};
+    int64_t gburnin[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
     hipStream_t gstream = nullptr;   // capture stream when the plan's stream is the null stream
     int64_t graph_replays = 0;
 };
@@ -298,11 +303,11 @@ int refresh(asm_plan *pl, bool measure_drift) {
 }
 
 // One segment of nsw sweeps starting at the device sweep counter; advances the counter.
-int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool snap) {
+int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool snap, int par = 0) {
     SampleArgs a = make_args(pl);
     if (snap) {
-        a.snapA = pl->snapA;
-        a.snapR = pl->snapR;
+        a.snapA = pl->snapA[par];
+        a.snapR = pl->snapR[par];
         a.snap_rows = pl->snap_rows;
     }
     a.nsw = nsw;
@@ -337,31 +342,60 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     return ASM_OK;
 }
 
+// The stream that runs the sampler: the plan's, or the private capture stream of graph mode
+// when the plan's stream is the null stream.
+hipStream_t main_stream(asm_plan *pl) { return pl->stream ? pl->stream : (pl->gstream ? pl->gstream : pl->stream); }
+
+// Before the sampler writes snapshot buffer `par`: the main stream waits until the previous
+// reduction of that buffer is done.
+int snap_acquire(asm_plan *pl, int par) {
+    if (pl->pending[par]) HIPCHK(hipStreamWaitEvent(main_stream(pl), pl->ev_done[par], 0));
+    return ASM_OK;
+}
+
+// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
+// moments on the second stream, after the main stream's work so far.
+int snap_release(asm_plan *pl, int par, int64_t nsnap) {
+    HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
+    HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
+    HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
+                             pl->snapR[par], pl->cross, pl->xstream));
+    HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
+    pl->pending[par] = true;
+    return ASM_OK;
+}
+
+// The caller's stream waits for every pending cross-moment reduction.
+int snap_join(asm_plan *pl) {
+    for (int j = 0; j < 2; ++j) {
+        if (!pl->pending[j]) continue;
+        HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_done[j], 0));
+        if (pl->gstream) HIPCHK(hipStreamWaitEvent(pl->gstream, pl->ev_done[j], 0));
+        pl->pending[j] = false;
+    }
+    return ASM_OK;
+}
+
 // One refresh cycle of the float32 sampler (R sweeps starting at a multiple of R): the
-// sampler launch, the sweep-counter bump, the cross moments of its snapshots and the float64
-// refresh.  With use_graph the cycle is captured once per run and kind and replayed; it holds
-// kernel launches only (no memsets, no host work), and every argument is the same for each
-// cycle of the run (the kernels read the sweep counter from device memory).
-int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap) {
+// sampler launch (writing snapshot buffer `par` when snap), the sweep-counter bump and the
+// float64 refresh.  With use_graph the cycle is captured once per run, kind and buffer and
+// replayed; it holds kernel launches only (no memsets, no host work), and every argument is
+// the same for each cycle of the run (the kernels read the sweep counter from device memory).
+int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap, int par) {
     auto body = [&]() -> int {
-        TRY(segment(pl, R, accumulate, burnin_abs, snap));
-        if (snap)
-            HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->snap_waves, pl->ksplit, R,
-                                     pl->snapA, pl->snapR, pl->cross, pl->stream));
+        TRY(segment(pl, R, accumulate, burnin_abs, snap, par));
         TRY(refresh(pl, true));
         return ASM_OK;
     };
     if (!pl->opt.use_graph) return body();
-    const int key = (accumulate ? 1 : 0) | (snap ? 2 : 0);
+    if (!pl->stream && !pl->gstream) HIPCHK(hipStreamCreate(&pl->gstream));
+    const int key = (accumulate ? 1 : 0) | (snap ? 2 : 0) | (snap && par ? 4 : 0);
     if (!pl->gexec[key] || pl->gburnin[key] != burnin_abs) {
         if (pl->gexec[key]) HIPCHK(hipGraphExecDestroy(pl->gexec[key]));
         pl->gexec[key] = nullptr;
         // capture on the plan's stream, or on a private stream when that is the null stream
         hipStream_t user = pl->stream;
-        if (!user) {
-            if (!pl->gstream) HIPCHK(hipStreamCreate(&pl->gstream));
-            pl->stream = pl->gstream;
-        }
+        pl->stream = main_stream(pl);
         const bool timing = pl->timing;
         pl->timing = false;
         HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeRelaxed));
@@ -380,7 +414,7 @@ int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap
         HIPCHK(ie);
         pl->gburnin[key] = burnin_abs;
     }
-    HIPCHK(hipGraphLaunch(pl->gexec[key], pl->stream ? pl->stream : pl->gstream));
+    HIPCHK(hipGraphLaunch(pl->gexec[key], main_stream(pl)));
     ++pl->graph_replays;
     return ASM_OK;
 }
@@ -397,7 +431,15 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         if (pl->fp32 && R > 0 && s % R == 0 && s + R <= end && (s >= burnin_abs || s + R <= burnin_abs) &&
             (!(vjp && s >= burnin_abs) || pl->snap_rows >= R)) {
             const bool snap = vjp && s >= burnin_abs;
-            TRY(cycle(pl, R, accumulate, burnin_abs, snap));
+            const int par = pl->snap_par;
+            if (snap) TRY(snap_acquire(pl, par));
+            TRY(cycle(pl, R, accumulate, burnin_abs, snap, par));
+            if (snap) {
+                // the cycle's refresh comes after the sampler; the reduction only needs the
+                // sampler's snapshots, but waiting for the whole cycle costs nothing
+                TRY(snap_release(pl, par, R));
+                pl->snap_par ^= 1;
+            }
             pl->sweep += R;
             continue;
         }
@@ -412,17 +454,20 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         }
         if (seg < 1) seg = 1;
         const bool snap = vjp && pl->fp32 && s >= burnin_abs;
-        TRY(segment(pl, seg, accumulate, burnin_abs, snap));
+        const int par = pl->snap_par;
+        if (snap) TRY(snap_acquire(pl, par));
+        TRY(segment(pl, seg, accumulate, burnin_abs, snap, par));
         pl->sweep += seg;
         if (snap) {
-            HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->snap_waves, pl->ksplit, seg,
-                                     pl->snapA, pl->snapR, pl->cross, pl->stream));
+            TRY(snap_release(pl, par, seg));
+            pl->snap_par ^= 1;
         } else if (vjp && s >= burnin_abs) {
             HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->ksplit, pl->A32,
                                     pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->stream));
         }
         if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
     }
+    TRY(snap_join(pl));
     return ASM_OK;
 }
 
@@ -509,6 +554,12 @@ int asm_plan_destroy(asm_plan *pl) {
     for (auto &g : pl->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+    if (pl->xstream) (void)hipStreamSynchronize(pl->xstream);
+    for (int j = 0; j < 2; ++j) {
+        if (pl->ev_ready[j]) (void)hipEventDestroy(pl->ev_ready[j]);
+        if (pl->ev_done[j]) (void)hipEventDestroy(pl->ev_done[j]);
+    }
+    if (pl->xstream) (void)hipStreamDestroy(pl->xstream);
     for (auto &e : pl->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : pl->tev) (void)hipEventDestroy(e);
@@ -642,26 +693,23 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->total_m = offm;
     if (o->want_vjp) {
         if (pl->fp32) {
-            // snapshots of every accumulated sweep of a launch (at most refresh_every or 64
-            // sweeps, and at most 16 GiB), rows padded to whole 16-byte words, reduced by
-            // (tile, split) workgroups
-            int64_t per_row = 0, max_m = 0;
-            for (auto &pd : pl->probs) {
-                per_row += pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
-                max_m = std::max(max_m, pd.M);
-            }
+            // two snapshot buffers for every accumulated sweep of a launch (at most
+            // refresh_every or 64 sweeps, and at most 16 GiB together), rows padded to whole
+            // 16-byte words, reduced by (tile, split) workgroups
+            int64_t per_row = 0;
+            for (auto &pd : pl->probs)
+                per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
             const int64_t cap = (int64_t)16 << 30;
             const int64_t want_rows = o->refresh_every > 0 ? o->refresh_every : 64;
             pl->snap_rows = std::max<int64_t>(1, std::min<int64_t>(want_rows, cap / std::max<int64_t>(per_row, 1)));
-            pl->snap_waves = (int)cross_snap_waves(max_m);
             for (auto &pd : pl->probs) {
                 pd.off_sa = pl->snap_words_a;
                 pd.off_sr = pl->snap_words_r;
                 pl->snap_words_a += pl->snap_rows * pd.C * ((pd.N + 3) / 4 * 4);
                 pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
-                pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N, pl->snap_waves));
+                pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N));
             }
-            pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (512 + pl->max_snap_tiles - 1) / pl->max_snap_tiles));
+            pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (1024 + pl->max_snap_tiles - 1) / pl->max_snap_tiles));
         } else {
             // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
             const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
@@ -713,8 +761,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (o->want_vjp) {
         STEP(dalloc(pl, &pl->cross, offcross));
         if (pl->fp32) {
-            STEP(dalloc(pl, &pl->snapA, pl->snap_words_a));
-            STEP(dalloc(pl, &pl->snapR, pl->snap_words_r));
+            for (int j = 0; j < 2; ++j) {
+                STEP(dalloc(pl, &pl->snapA[j], pl->snap_words_a));
+                STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
+                HSTEP(hipEventCreateWithFlags(&pl->ev_ready[j], hipEventDisableTiming));
+                HSTEP(hipEventCreateWithFlags(&pl->ev_done[j], hipEventDisableTiming));
+            }
+            // default priority; non-blocking, so that null-stream work does not serialise it
+            HSTEP(hipStreamCreateWithFlags(&pl->xstream, hipStreamNonBlocking));
         }
         STEP(dalloc(pl, &pl->nsamples, n));
         STEP(dalloc(pl, &pl->vjp_y, offm));

@@ -192,11 +192,9 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
 hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
                             const float *A32, const float *r32, const double *A64,
                             const double *r64, int fp32, double *cross, hipStream_t s);
-hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int waves, int ksplit,
-                             int64_t nsnap, const float *snapA, const float *snapR, double *cross,
-                             hipStream_t s);
-__host__ __device__ int64_t cross_snap_waves(int64_t max_m);
-__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N, int64_t W);
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
+                             const float *snapA, const float *snapR, double *cross, hipStream_t s);
+__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,

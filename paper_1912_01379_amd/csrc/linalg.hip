@@ -178,54 +178,49 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 // Cross moments from the per-sweep snapshots of one launch of the float32 sampler: with the
 // rows k = (sweep, chain) of the snapshots,
 //   X_split[m][n] += sum_{k in split} r_k[m] A_k[n] (n < N),  X_split[m][N] += sum r_k[m].
-// A workgroup of W wavefronts owns a (32 W) x 128 output tile and a range of rows; each
-// wavefront owns 32 x 128 of it (2 x 8 MFMA f64 16x16x4 blocks).  The rows pass through LDS
+// A workgroup of 4 wavefronts owns a 64 x 128 output tile and a range of rows; each
+// wavefront owns 32 x 64 of it (2 x 4 MFMA f64 16x16x4 blocks).  The rows pass through LDS
 // in chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile
 // that needs it; the float32 values are widened to float64 as they enter the MFMAs.  The
-// snapshot rows are padded to multiples of four floats (snap_ld_r, snap_ld_a).
-constexpr int kSnapTN = 128, kSnapKC = 32, kSnapMaxW = 8;
+// kernel is sized (12 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with the
+// sampler, which it runs beside on a second stream.  Snapshot rows are padded to multiples
+// of four floats.
+constexpr int kSnapTM = 64, kSnapTN = 128, kSnapKC = 16;
 
-__host__ __device__ int64_t cross_snap_waves(int64_t max_m) {
-    const int64_t w = (max_m + 31) / 32;
-    return w < kSnapMaxW ? w : kSnapMaxW;
+__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N) {
+    return ((M + kSnapTM - 1) / kSnapTM) * ((N + 1 + kSnapTN - 1) / kSnapTN);
 }
 
-__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N, int64_t W) {
-    return ((M + 32 * W - 1) / (32 * W)) * ((N + 1 + kSnapTN - 1) / kSnapTN);
-}
-
-__global__ __launch_bounds__(512) void k_cross_snap(const ProbDesc *probs, int ksplit, int64_t nsnap,
+__global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int ksplit, int64_t nsnap,
                                                     const float *snapA, const float *snapR, double *cross) {
-    extern __shared__ __align__(16) float smx[];
+    __shared__ __align__(16) float sr[kSnapKC * kSnapTM];
+    __shared__ __align__(16) float sa[kSnapKC * kSnapTN];
     const ProbDesc pd = probs[blockIdx.z];
-    const int W = blockDim.x / 64;
     const int64_t M = pd.M, N = pd.N, N1 = N + 1;
     const int64_t ldr = (M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
-    const int64_t TM = 32 * W;
     const int64_t ntn = (N1 + kSnapTN - 1) / kSnapTN;
     const int64_t tile = blockIdx.x;
-    if (tile >= cross_snap_tiles(M, N, W)) return;
+    if (tile >= cross_snap_tiles(M, N)) return;
     const int split = blockIdx.y;
-    const int64_t m0 = (tile / ntn) * TM, n0 = (tile % ntn) * kSnapTN;
+    const int64_t m0 = (tile / ntn) * kSnapTM, n0 = (tile % ntn) * kSnapTN;
     const int64_t K = nsnap * pd.C;
     const int64_t k_lo = K * split / ksplit, k_hi = K * (split + 1) / ksplit;
     const float *Rb = snapR + pd.off_sr;
     const float *Ab = snapA + pd.off_sa;
-    float *sr = smx;                      // kSnapKC x TM
-    float *sa = smx + kSnapKC * TM;       // kSnapKC x kSnapTN
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int wm = wave / 2, wn = wave % 2;   // the wavefront's 32 x 64 sub-tile
     const int i = lane % 16, kk = lane / 16;
-    d4 acc[2][8];
+    d4 acc[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = d4{0, 0, 0, 0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
     for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
         const int64_t kc = (k_hi - c0) < kSnapKC ? (k_hi - c0) : kSnapKC;
         __syncthreads();   // the previous chunk is consumed
-        // r rows: kc x TM (columns past M, rows past kc: 0)
-        for (int e = tid; e < kSnapKC * TM / 4; e += blockDim.x) {
-            const int row = e / (TM / 4), c4 = e % (TM / 4);
+        // r rows: kc x 64 (columns past M, rows past kc: 0); one 16-byte word per thread
+        {
+            const int row = tid / (kSnapTM / 4), c4 = tid % (kSnapTM / 4);
             const int64_t m = m0 + 4 * c4;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (row < kc && m < ldr) v = *reinterpret_cast<const float4 *>(Rb + (c0 + row) * ldr + m);
@@ -233,10 +228,12 @@ __global__ __launch_bounds__(512) void k_cross_snap(const ProbDesc *probs, int k
             if (m + 1 >= M) v.y = 0.f;
             if (m + 2 >= M) v.z = 0.f;
             if (m + 3 >= M) v.w = 0.f;
-            *reinterpret_cast<float4 *>(sr + row * TM + 4 * c4) = v;
+            *reinterpret_cast<float4 *>(sr + row * kSnapTM + 4 * c4) = v;
         }
-        // A rows with the column of ones at n = N: kc x 128
-        for (int e = tid; e < kSnapKC * kSnapTN / 4; e += blockDim.x) {
+        // A rows with the column of ones at n = N: kc x 128; two words per thread
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + h * 256;
             const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
             const int64_t n = n0 + 4 * c4;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -250,18 +247,18 @@ __global__ __launch_bounds__(512) void k_cross_snap(const ProbDesc *probs, int k
             *reinterpret_cast<float4 *>(sa + row * kSnapTN + 4 * c4) = v;
         }
         __syncthreads();
-#pragma unroll 2
+#pragma unroll
         for (int k4 = 0; k4 < kSnapKC; k4 += 4) {
             const int row = k4 + kk;
-            double ra[2], bb[8];
+            double ra[2], bb[4];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * TM + 32 * wave + 16 * a + i];
+            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * kSnapTM + 32 * wm + 16 * a + i];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) bb[b] = (double)sa[row * kSnapTN + 16 * b + i];
+            for (int b = 0; b < 4; ++b) bb[b] = (double)sa[row * kSnapTN + 64 * wn + 16 * b + i];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
+                for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
         }
     }
@@ -269,20 +266,19 @@ __global__ __launch_bounds__(512) void k_cross_snap(const ProbDesc *probs, int k
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t row = m0 + 32 * wave + 16 * a + lane / 16 + 4 * j, col = n0 + 16 * b + lane % 16;
+                const int64_t row = m0 + 32 * wm + 16 * a + lane / 16 + 4 * j;
+                const int64_t col = n0 + 64 * wn + 16 * b + lane % 16;
                 if (row < M && col < N1) X[row * N1 + col] += acc[a][b][j];
             }
 }
 
-hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int waves, int ksplit,
-                             int64_t nsnap, const float *snapA, const float *snapR, double *cross,
-                             hipStream_t s) {
-    const size_t lds = (size_t)kSnapKC * (32 * waves + kSnapTN) * sizeof(float);
-    hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(64 * waves),
-                       lds, s, probs_dev, ksplit, nsnap, snapA, snapR, cross);
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
+                             const float *snapA, const float *snapR, double *cross, hipStream_t s) {
+    hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(256), 0, s,
+                       probs_dev, ksplit, nsnap, snapA, snapR, cross);
     return hipGetLastError();
 }
 

@@ -112,37 +112,57 @@ __device__ __forceinline__ void load_row(float2 (&vw)[EPT], const float2 *row, i
     for (int t = 0; t < EPT; ++t) vw[t] = row[lane + L * t];
 }
 
-// The data-mode moves of one block (d_i > 0, modes 0..kb-1): interval, c = U_i . r, the
-// truncated-normal step, and the updates of A and r.  On return vw holds row kb.
+// One data-mode move: interval, c = U_i . r, the truncated-normal step, the updates of A and r.
+template <int L, int EPT, int RPT>
+__device__ __forceinline__ void data_move(const float2 (&vw)[EPT], const float (&Ui)[RPT], float u, float dd,
+                                          float (&Ar)[EPT], float (&rr)[RPT]) {
+    float lo, hi;
+    interval32<L, EPT, false>(vw, Ar, lo, hi);
+    float c0 = 0.0f, c1 = 0.0f;   // two partial sums for a shorter dependence chain
+#pragma unroll
+    for (int t = 0; t < RPT; t += 2) c0 = fmaf(Ui[t], rr[t], c0);
+#pragma unroll
+    for (int t = 1; t < RPT; t += 2) c1 = fmaf(Ui[t], rr[t], c1);
+    const float cdot = seg_sum<L>(c0 + c1);
+    const float delta = tn_draw32(cdot, dd, lo, hi, u);
+    const float e = delta * dd;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
+}
+
+template <int L, int RPT>
+__device__ __forceinline__ void load_u(float (&Ui)[RPT], const float *U, int row, int lane) {
+    constexpr int MP = RPT * L;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) Ui[t] = U[row * MP + lane + L * t];
+}
+
+// The data-mode moves of one block (d_i > 0, modes 0..kb-1), two per iteration with the next
+// (V, w) and U rows loaded one move ahead.  On entry vw holds row 0; on return row kb.
 template <int L, int EPT, int RPT, bool ULDS>
 __device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const float *sD, const float *U,
                                            const float *urow, int lane, float2 (&vw)[EPT], float (&Ar)[EPT],
                                            float (&rr)[RPT]) {
     constexpr int ROW = EPT * L;
-    constexpr int MP = RPT * L;
-    for (int i = 0; i < kb; ++i) {
-        float Ui[RPT];
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) Ui[t] = U[i * MP + lane + L * t];
-        const float u = urow[i];
-        const float dd = sD[i];
-        float2 vn[EPT];
-        load_row<EPT>(vn, sVW + (i + 1) * ROW, lane, L);
-        float lo, hi;
-        interval32<L, EPT, false>(vw, Ar, lo, hi);
-        float cp = 0.0f;
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) cp = fmaf(Ui[t], rr[t], cp);
-        const float cdot = seg_sum<L>(cp);
-        const float delta = tn_draw32(cdot, dd, lo, hi, u);
-        const float e = delta * dd;
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
-#pragma unroll
-        for (int t = 0; t < EPT; ++t) {
-            Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
-            vw[t] = vn[t];
-        }
+    if (kb <= 0) return;
+    float Ua[RPT], Ub[RPT];
+    load_u<L, RPT>(Ua, U, 0, lane);
+    int i = 0;
+    for (; i + 2 <= kb; i += 2) {
+        float2 vb[EPT];
+        load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
+        load_u<L, RPT>(Ub, U, i + 1, lane);
+        const float u0 = urow[i], u1 = urow[i + 1], d0 = sD[i], d1 = sD[i + 1];
+        data_move<L, EPT, RPT>(vw, Ua, u0, d0, Ar, rr);
+        load_row<EPT>(vw, sVW + (i + 2) * ROW, lane, L);
+        load_u<L, RPT>(Ua, U, i + 2 < kb ? i + 2 : i + 1, lane);
+        data_move<L, EPT, RPT>(vb, Ub, u1, d1, Ar, rr);
+    }
+    if (i < kb) {
+        data_move<L, EPT, RPT>(vw, Ua, urow[i], sD[i], Ar, rr);
+        load_row<EPT>(vw, sVW + (i + 1) * ROW, lane, L);
     }
 }
 
@@ -316,32 +336,37 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 #pragma unroll
                     for (int t = 0; t < EPT; ++t) urow[lane + L * t] = active ? Ar[t] : 0.0f;
                     __syncthreads();
+                    double *s1, *s2;
                     if (acc_lds) {
-                        for (int q = tid; q < nb; q += nthr) {
-                            double x1 = 0.0, x2 = 0.0;
-                            for (int cs = 0; cs < td.nchains; ++cs) {
-                                const double x = (double)sUnif[cs * ROW + q];
-                                x1 += x;
-                                x2 = fma(x, x, x2);
-                            }
-                            sAcc[bd.n0 + q] += x1;
-                            sAcc[N + bd.n0 + q] += x2;
-                        }
+                        s1 = sAcc + bd.n0;
+                        s2 = sAcc + N + bd.n0;
                     } else {
                         int64_t slot = td.slot;
                         if (pd.batches > 1) slot += (s - a.burnin) * pd.batches / a.sweeps;
-                        double *s1 = a.accA + pd.off_slot + slot * N + bd.n0;
-                        double *s2 = a.accA2 + pd.off_slot + slot * N + bd.n0;
-                        for (int q = tid; q < nb; q += nthr) {
-                            double x1 = 0.0, x2 = 0.0;
-                            for (int cs = 0; cs < td.nchains; ++cs) {
-                                const double x = (double)sUnif[cs * ROW + q];
+                        s1 = a.accA + pd.off_slot + slot * N + bd.n0;
+                        s2 = a.accA2 + pd.off_slot + slot * N + bd.n0;
+                    }
+                    for (int q = tid; q < nb; q += nthr) {
+                        double x1 = 0.0, x2 = 0.0;
+                        int cs = 0;
+                        for (; cs + 8 <= td.nchains; cs += 8) {   // eight LDS loads in flight
+                            float v[8];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) v[k] = sUnif[(cs + k) * ROW + q];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                const double x = (double)v[k];
                                 x1 += x;
                                 x2 = fma(x, x, x2);
                             }
-                            s1[q] += x1;
-                            s2[q] += x2;
                         }
+                        for (; cs < td.nchains; ++cs) {
+                            const double x = (double)sUnif[cs * ROW + q];
+                            x1 += x;
+                            x2 = fma(x, x, x2);
+                        }
+                        s1[q] += x1;
+                        s2[q] += x2;
                     }
                 }
             }
