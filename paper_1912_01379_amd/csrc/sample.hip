@@ -188,20 +188,24 @@ hipError_t launch_reset_queue(int *queue, hipStream_t s) {
 
 __global__ void k_tn_draw(const double *c, const double *d, const double *lo, const double *hi,
                           const double *u, double *out, int64_t n, int precision) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (precision == ASM_FP64) {
-        out[i] = tn_draw<double>(c[i], d[i], lo[i], hi[i], u[i]);
+        if (t >= n) return;
+        out[t] = tn_draw<double>(c[t], d[t], lo[t], hi[t], u[t]);
     } else {
-        out[i] = (double)tn_draw32((float)c[i], (float)d[i], (float)lo[i], (float)hi[i],
-                                   (float)u[i]);
+        // the float32 draw runs on a pair of lanes with the same arguments, as in the sampler
+        const int64_t i = t / 2;
+        if (i >= n) return;
+        const float v = tn_draw32((float)c[i], (float)d[i], (float)lo[i], (float)hi[i], (float)u[i]);
+        if ((t & 1) == 0) out[i] = (double)v;
     }
 }
 
 hipError_t launch_tn_draw(const double *c, const double *d, const double *lo, const double *hi,
                           const double *u, double *out, int64_t n, int precision, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tn_draw, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, c, d, lo, hi, u,
+    const int64_t threads = precision == ASM_FP64 ? n : 2 * n;
+    hipLaunchKernelGGL(k_tn_draw, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, c, d, lo, hi, u,
                        out, n, precision);
     return hipGetLastError();
 }

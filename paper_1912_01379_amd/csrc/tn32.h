@@ -79,7 +79,8 @@ __device__ __forceinline__ float q_inv32(float p) {
     float h = kQ[kQDeg];
 #pragma unroll
     for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
-    const float E = exp_half_sq(z);
+    // the step is about 1e-5 of z, so exp(-z^2/2) needs no compensation here
+    const float E = hw_exp2(-0.72134752f * z * z);
     const float step = kSqrt2Pi * fmaf(-p, hw_rcp(E), (kQK * r) * h);
     return E > 0.0f ? z + step : z;
 }
@@ -119,7 +120,8 @@ __device__ __forceinline__ float neg_log1m(float y) {
     p = fmaf(p, t2, 1.0f / 5.0f);
     p = fmaf(p, t2, 1.0f / 3.0f);
     p = fmaf(p, t2, 1.0f);
-    return y <= 0.5f ? 2.0f * t * p : -kLn2 * hw_log2(1.0f - y);
+    const float lg = -kLn2 * hw_log2(1.0f - y);   // both forms are computed: no branch
+    return y <= 0.5f ? 2.0f * t * p : lg;
 }
 
 // t in [0, w] with density proportional to exp(-lam t) (lam of either sign), by inversion:
@@ -130,7 +132,7 @@ __device__ __forceinline__ float tilt_draw32(float lam, float w, float u, float 
     const float X = fabsf(lam * w);
     const float v = lam > 0.0f ? u : uc;
     const float s = neg_log1m(v * one_minus_exp_neg(X)) * hw_rcp(fabsf(lam));
-    const float sd = X < 1e-6f ? v * w : s;
+    const float sd = X < 1e-6f ? v * w : s;   // also covers w = 0 and lam = 0
     return lam > 0.0f ? sd : w - sd;
 }
 
@@ -170,23 +172,25 @@ __device__ __forceinline__ float tail_draw32(float a, float w, float u) {
 }
 
 // The draw in parameter units: delta in [lo, hi], lo <= 0 <= hi, d > 0, u in (0, 1).
+// Lanes 2j and 2j + 1 must carry the same draw (the samplers give every lane of a chain the
+// same arguments): the two tail probabilities of the inversion are evaluated once, one on
+// each lane of the pair, and exchanged.
 __device__ __forceinline__ float tn_draw32(float c, float d, float lo, float hi, float u) {
-    if (lo == hi) return lo;
     const float uc = 1.0f - u;
     const float a = fmaf(d, lo, -c);
     const float b = fmaf(d, hi, -c);
     const float w = d * (hi - lo);
     const float rd = hw_rcp(d);
     const float far = fmaxf(fabsf(a), fabsf(b));
-    float delta;
-    // The tilt below errs by about w^2/16 of the interval (the curvature it drops), the
-    // inversion by about 1.5e-7 max(1, |a|, |b|) / w (the float32 resolution of p and x):
-    // take the tilt where it is the more accurate of the two.
-    if (w * w * w < 2.4e-6f * fmaxf(1.0f, far)) {
-        // narrow interval: exponential tilt at the slope of the midpoint
-        const float lam = fmaf(0.5f, w, a);
-        delta = lo + tilt_draw32(lam, w, u, uc) * rd;
-    } else {
+    // The tilt errs by about w^2/16 of the interval (the curvature it drops), the inversion
+    // by about 1.5e-7 max(1, |a|, |b|) / w (the float32 resolution of p and x): take the tilt
+    // where it is the more accurate of the two (lo = hi gives w = 0 and delta = lo).
+    const bool narrow = w * w * w < 2.4e-6f * fmaxf(1.0f, far);
+    // narrow interval: exponential tilt at the slope of the midpoint, computed without
+    // branches by every lane (most draws of the samplers take it)
+    const float lam = fmaf(0.5f, w, a);
+    float delta = fmaf(tilt_draw32(lam, w, u, uc), rd, lo);
+    if (!narrow) {
         const bool lower = b <= 0.0f;                   // interval below the mean
         const bool one = lower || a >= 0.0f;
         const float a1 = lower ? -b : a;
@@ -196,26 +200,23 @@ __device__ __forceinline__ float tn_draw32(float c, float d, float lo, float hi,
             const float t = tail_draw32(a1, w, u1);
             delta = lower ? hi - t * rd : lo + t * rd;
         } else {
-            const float q1 = q_upper32(one ? a1 : -a);
-            const float q2 = q_upper32(one ? a1 + w : b);
+            const bool odd = (__lane_id() & 1) != 0;
+            const float e1 = one ? a1 : -a, e2 = one ? a1 + w : b;
+            const float qm = q_upper32(odd ? e2 : e1);
+            const float qo = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(qm), 0xB1, 0xF, 0xF, false));
+            const float q1 = odd ? qo : qm;
+            const float q2 = odd ? qm : qo;
             const float dq = q1 - q2;
             const float mass = (1.0f - q1) - q2;
             const float plo = fmaf(u, mass, q1);
-            float p, sg;
-            if (one) {
-                p = u1 <= 0.5f ? fmaf(-u1, dq, q1) : fmaf(uc1, dq, q2);
-                sg = 1.0f;
-            } else {
-                p = plo <= 0.5f ? plo : fmaf(uc, mass, q2);
-                sg = plo <= 0.5f ? -1.0f : 1.0f;
-            }
+            const float p1 = u1 <= 0.5f ? fmaf(-u1, dq, q1) : fmaf(uc1, dq, q2);
+            const float p2 = plo <= 0.5f ? plo : fmaf(uc, mass, q2);
+            const float p = one ? p1 : p2;
+            const float sg = (one || plo > 0.5f) ? 1.0f : -1.0f;
             const float x = sg * q_inv32(p);
-            if (one) {
-                const float t = fminf(fmaxf(x - a1, 0.0f), w);
-                delta = lower ? hi - t * rd : lo + t * rd;
-            } else {
-                delta = (x + c) * rd;
-            }
+            const float t = fminf(fmaxf(x - a1, 0.0f), w);
+            const float d1 = lower ? hi - t * rd : lo + t * rd;
+            delta = one ? d1 : (x + c) * rd;
         }
     }
     return __builtin_amdgcn_fmed3f(delta, lo, hi);
