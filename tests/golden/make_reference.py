@@ -7,7 +7,7 @@ Sec. IV.C) and its standard error over independent chain groups, for a fixed pro
 The config-2 reference starts from the NNLS start of Sec. IV.D, so that both sides average
 over the equilibrated chain rather than over the slow relaxation from a flat start.
 
-    python tests/golden/make_reference.py [cfg1] [cfg2]
+    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3]
 """
 import json
 import os
@@ -28,11 +28,18 @@ PROTOCOLS = {
     "cfg2": dict(problem="config2", chains=64, burnin=500, sweeps=2000, seed=12, groups=32,
                  refresh_every=64, start="nnls"),
 }
+# three uneven datasets of the batched workload (N = 396, 670, 407 in 4, 7, 4 blocks); 256
+# chains, so that the reference error bars are half those of a 64-chain run
+for _i in (1, 2, 3):
+    PROTOCOLS[f"cfg3_{_i}"] = dict(problem="config3_dataset", index=_i, chains=256, burnin=500,
+                                   sweeps=2000, seed=30 + _i, groups=32, refresh_every=64,
+                                   start="nnls")
 
 
 def make(name):
     proto = PROTOCOLS[name]
-    prob = getattr(workloads, proto["problem"])()
+    gen = getattr(workloads, proto["problem"])
+    prob = gen(proto["index"]) if "index" in proto else gen()
     prep = oracle.prepare(prob)
     t = time.time()
     init = oracle.nnls_start(prep) if proto.get("start") == "nnls" else None

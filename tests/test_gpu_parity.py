@@ -30,11 +30,23 @@ def pk():
     return pk
 
 
-def zscore_ok(m1, s1, m2, s2, frac=0.01):
+def zscore_ok(m1, s1, m2, s2, frac=0.01, zmax=4.5, n3_min=2, mean_z2=None):
     z = np.abs(m1 - m2) / np.sqrt(s1 ** 2 + s2 ** 2)
     z = z[np.isfinite(z)]
     n3 = int(np.sum(z > 3.0))
-    return float(z.max()) <= 4.5 and n3 <= max(2, int(frac * len(z))), (float(z.max()), n3, len(z))
+    ok = float(z.max()) <= zmax and n3 <= max(n3_min, int(frac * len(z)))
+    if mean_z2 is not None:
+        ok = ok and float(np.mean(z ** 2)) <= mean_z2
+    return ok, (float(z.max()), n3, len(z), float(np.mean(z ** 2)))
+
+
+# The spectra of the batched workload have hundreds of strongly correlated points: one slow
+# collective fluctuation of a reference run moves many of them together, and the error bars
+# come from 32 groups (Student-t tails).  Oracle against oracle (24 runs of 64 chains against
+# one of 512 chains on these three datasets, different seeds) gave max z up to 4.6, up to
+# 2.1 % of the points above 3 and mean z^2 between 0.73 and 1.48; the bounds below sit above
+# that spread, and mean z^2 catches a bias common to many points.
+CORRELATED = dict(frac=0.03, zmax=5.0, n3_min=3, mean_z2=2.0)
 
 
 # --------------------------------------------------------------------------------------
@@ -432,4 +444,26 @@ def test_large_correlated_noise_workload_properties(pk):
     rr = gt[None, :] - A[:128] @ Kt.T
     assert float((r[:128] - rr).abs().max() / rr.abs().max()) < 1e-5
     assert res.stats["chi2_drift_max"] < 1e-2
+    plan.close()
+
+
+def test_batched_fp32_uneven_continuations_match_oracle(pk):
+    """Three uneven datasets of the batched workload in one plan (one persistent launch per
+    refresh cycle, graph replay, tuned width) against the oracle run of each."""
+    names = ["cfg3_1", "cfg3_2", "cfg3_3"]
+    gold = [_golden(n) for n in names]
+    meta = gold[0][1]
+    probs = [workloads.config3_dataset(g[1]["index"]) for g in gold]
+    plan = pk.Plan(probs, chains=1024, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=77,
+                   precision="fp32", groups=32, refresh_every=meta["refresh_every"], start="nnls",
+                   use_graph=True, lanes_per_chain=0)
+    res = plan.run()
+    mean, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
+    off = 0
+    for (z, _), p in zip(gold, probs):
+        ok, info = zscore_ok(mean[off:off + p.N], se[off:off + p.N], z["mean"], z["stderr"],
+                             **CORRELATED)
+        assert ok, info
+        off += p.N
+    assert res.stats["graph_replays"] > 0
     plan.close()
