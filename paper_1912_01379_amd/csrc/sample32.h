@@ -258,6 +258,17 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         const int nw = (int)a.chunk_words;
         float4 *stage = reinterpret_cast<float4 *>(smem32);
         if (prefetch) pf.load(a.F32 + a.blocks[pd.off_blk].off_chunk, tid, nthr, nw);
+        // components of the next block to sample, loaded one block ahead (blocks are disjoint,
+        // so sampling a block leaves the next one's components unchanged)
+        float An[EPT];
+        {
+            const BlockDesc b0 = a.blocks[pd.off_blk];
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int q = lane + L * t;
+                An[t] = (q < (int)b0.nb && active) ? Ag[b0.n0 + q] : 0.0f;
+            }
+        }
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
             for (int64_t b = 0; b < pd.B; ++b) {
@@ -265,9 +276,16 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
                 float Ar[EPT];
 #pragma unroll
-                for (int t = 0; t < EPT; ++t) {
-                    const int q = lane + L * t;
-                    Ar[t] = (q < nb && active) ? Ag[bd.n0 + q] : 0.0f;
+                for (int t = 0; t < EPT; ++t) Ar[t] = An[t];
+                if (pd.B > 1 && (b + 1 < pd.B || s + 1 < s0 + nsw)) {
+                    // the next block of this sweep, or the first of the next (its components
+                    // were stored when this sweep sampled it)
+                    const BlockDesc bn = a.blocks[pd.off_blk + (b + 1 < pd.B ? b + 1 : 0)];
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) {
+                        const int q = lane + L * t;
+                        An[t] = (q < (int)bn.nb && active) ? Ag[bn.n0 + q] : 0.0f;
+                    }
                 }
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 if (prefetch) {
@@ -321,6 +339,10 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 for (int t = 0; t < EPT; ++t) {
                     const int q = lane + L * t;
                     if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
+                }
+                if (pd.B == 1) {
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) An[t] = Ar[t];
                 }
                 if (a.snapA && s >= a.burnin) {
                     float *sa = a.snapA + pd.off_sa + ((s - s0) * pd.C + chain) * ((N + 3) / 4 * 4) + bd.n0;
