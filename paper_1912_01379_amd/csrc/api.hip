@@ -61,20 +61,21 @@ struct asm_plan {
     int64_t total_chains = 0, total_n = 0, total_m = 0;
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
     int ksplit = 1;          // chain splits of the cross-moment partial sums
-    // float32 plans with want_vjp: per-sweep snapshots of (A, r), reduced into the cross
-    // moments after each launch
-    // two snapshot buffers: the sampler fills one while the cross moments of the other are
-    // reduced on a second stream (xstream), ordered by events
+    // float32 plans: per-sweep snapshots of A (and of r with want_vjp) of the accumulated
+    // sweeps, reduced after each launch into the sums of A and A^2 (and the cross moments);
+    // two snapshot buffers: the sampler fills one while the other is reduced on a second
+    // stream (xstream), ordered by events
     float *snapA[2] = {nullptr, nullptr}, *snapR[2] = {nullptr, nullptr};
+    int64_t *snap_first = nullptr;   // per buffer: the sweep of its first row (device)
     int64_t snap_rows = 0, max_snap_tiles = 0, snap_words_a = 0, snap_words_r = 0;
     hipStream_t xstream = nullptr;
     hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
     bool pending[2] = {false, false};
     int snap_par = 0;
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
-    int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_acc = 0;   // float32 sampler LDS
+    int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0;   // float32 sampler LDS
     int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
-    int u_lds = 0, acc_lds = 0;
+    int u_lds = 0;
     bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
@@ -281,9 +282,7 @@ SampleArgs make_args(asm_plan *pl) {
     a.lds_off_d = pl->lds_off_d;
     a.lds_off_u = pl->lds_off_u;
     a.lds_off_unif = pl->lds_off_unif;
-    a.lds_off_acc = pl->lds_off_acc;
     a.u_lds = pl->u_lds;
-    a.acc_lds = pl->acc_lds;
     a.prefetch = pl->prefetch;
     return a;
 }
@@ -307,11 +306,13 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     SampleArgs a = make_args(pl);
     if (snap) {
         a.snapA = pl->snapA[par];
-        a.snapR = pl->snapR[par];
+        a.snapR = pl->opt.want_vjp ? pl->snapR[par] : nullptr;
         a.snap_rows = pl->snap_rows;
+        a.snap_first = pl->snap_first + par;
+        a.accumulate = 0;   // the sums come from the snapshots
     }
     a.nsw = nsw;
-    a.accumulate = accumulate;
+    if (!snap) a.accumulate = accumulate;
     a.burnin = burnin_abs;
     a.sweeps = pl->opt.sweeps;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -353,13 +354,18 @@ int snap_acquire(asm_plan *pl, int par) {
     return ASM_OK;
 }
 
-// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
-// moments on the second stream, after the main stream's work so far.
-int snap_release(asm_plan *pl, int par, int64_t nsnap) {
+// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the sums of A
+// and A^2 (and the cross moments with want_vjp) on the second stream, after the main stream's
+// work so far.
+int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
     HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
     HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
-                             pl->snapR[par], pl->cross, pl->xstream));
+    HIPCHK(launch_acc_snap(pl->d_probs, pl->d_tiles, (int64_t)pl->tiles.size(), pl->max_n, nsnap,
+                           pl->snapA[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps, pl->accA,
+                           pl->accA2, pl->xstream));
+    if (pl->opt.want_vjp)
+        HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
+                                 pl->snapR[par], pl->cross, pl->xstream));
     HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
     pl->pending[par] = true;
     return ASM_OK;
@@ -424,20 +430,22 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     const int64_t R = pl->opt.refresh_every;
     const int64_t end = pl->sweep + total;
     const bool vjp = accumulate && pl->opt.want_vjp;
+    const bool snapping = accumulate && pl->fp32;   // float32: sums from snapshots
+    if (snapping && !pl->snapA[0]) return fail(ASM_ESTATE, "plan has no snapshot buffers");
     while (pl->sweep < end) {
         const int64_t s = pl->sweep;
         // whole refresh cycles of the float32 sampler go through cycle() (a graph replay with
         // use_graph); they must not straddle the end of burn-in and must fit the snapshots
         if (pl->fp32 && R > 0 && s % R == 0 && s + R <= end && (s >= burnin_abs || s + R <= burnin_abs) &&
-            (!(vjp && s >= burnin_abs) || pl->snap_rows >= R)) {
-            const bool snap = vjp && s >= burnin_abs;
+            (!(snapping && s >= burnin_abs) || pl->snap_rows >= R)) {
+            const bool snap = snapping && s >= burnin_abs;
             const int par = pl->snap_par;
             if (snap) TRY(snap_acquire(pl, par));
             TRY(cycle(pl, R, accumulate, burnin_abs, snap, par));
             if (snap) {
                 // the cycle's refresh comes after the sampler; the reduction only needs the
                 // sampler's snapshots, but waiting for the whole cycle costs nothing
-                TRY(snap_release(pl, par, R));
+                TRY(snap_release(pl, par, R, burnin_abs));
                 pl->snap_par ^= 1;
             }
             pl->sweep += R;
@@ -446,20 +454,19 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         int64_t seg = end - s;
         if (pl->fp32 && R > 0) seg = std::min(seg, R - s % R);   // stop where a refresh is due
         if (!pl->fp32 && seg > 256) seg = 256;
-        if (vjp && s + seg > burnin_abs && s < burnin_abs) seg = burnin_abs - s;   // burn-in apart
-        if (vjp && s >= burnin_abs) {
-            // float32: as many sweeps as the snapshot rows hold; float64: one sweep, whose
-            // state the cross-moment kernel reads directly
-            seg = pl->fp32 ? std::min(seg, pl->snap_rows) : 1;
-        }
+        if ((vjp || snapping) && s + seg > burnin_abs && s < burnin_abs) seg = burnin_abs - s;   // burn-in apart
+        // float32: as many sweeps as the snapshot rows hold; float64 with want_vjp: one sweep,
+        // whose state the cross-moment kernel reads directly
+        if (snapping && s >= burnin_abs) seg = std::min(seg, pl->snap_rows);
+        else if (vjp && s >= burnin_abs) seg = 1;
         if (seg < 1) seg = 1;
-        const bool snap = vjp && pl->fp32 && s >= burnin_abs;
+        const bool snap = snapping && s >= burnin_abs;
         const int par = pl->snap_par;
         if (snap) TRY(snap_acquire(pl, par));
         TRY(segment(pl, seg, accumulate, burnin_abs, snap, par));
         pl->sweep += seg;
         if (snap) {
-            TRY(snap_release(pl, par, seg));
+            TRY(snap_release(pl, par, seg, burnin_abs));
             pl->snap_par ^= 1;
         } else if (vjp && s >= burnin_abs) {
             HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->ksplit, pl->A32,
@@ -477,6 +484,9 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
 // (problem sizes, partitions, k, chains) for the rest of the process.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;
+// set while the tuner creates its throwaway plans: they only advance, so they get no
+// snapshot buffers
+thread_local bool t_probe_plan = false;
 
 int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream, int *best) {
     std::string key = std::to_string(o->chains) + ":" + std::to_string(o->refresh_every) + ":" +
@@ -519,7 +529,10 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
             so.want_vjp = 0;
             so.use_graph = 0;
             asm_plan *sp = nullptr;
-            if (asm_plan_create(pr, n, &so, hip_stream, &sp) != ASM_OK) continue;
+            t_probe_plan = true;
+            const int crc = asm_plan_create(pr, n, &so, hip_stream, &sp);
+            t_probe_plan = false;
+            if (crc != ASM_OK) continue;
             float ms = -1.0f;
             if (asm_plan_advance(sp, 2) == ASM_OK && hipEventRecord(e0, st) == hipSuccess &&
                 asm_plan_advance(sp, 8) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
@@ -691,24 +704,27 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->total_chains = offc;
     pl->total_n = offn;
     pl->total_m = offm;
+    if (pl->fp32 && !t_probe_plan) {
+        // two snapshot buffers for every accumulated sweep of a launch (at most refresh_every
+        // or 64 sweeps, and at most 16 GiB together), rows padded to whole 16-byte words; r
+        // rows only with want_vjp
+        int64_t per_row = 0;
+        for (auto &pd : pl->probs)
+            per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (o->want_vjp ? (pd.M + 3) / 4 * 4 : 0)) * (int64_t)sizeof(float);
+        const int64_t cap = (int64_t)16 << 30;
+        const int64_t want_rows = o->refresh_every > 0 ? o->refresh_every : 64;
+        pl->snap_rows = std::max<int64_t>(1, std::min<int64_t>(want_rows, cap / std::max<int64_t>(per_row, 1)));
+        for (auto &pd : pl->probs) {
+            pd.off_sa = pl->snap_words_a;
+            pd.off_sr = pl->snap_words_r;
+            pl->snap_words_a += pl->snap_rows * pd.C * ((pd.N + 3) / 4 * 4);
+            if (o->want_vjp) pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
+            pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N));
+        }
+    }
     if (o->want_vjp) {
         if (pl->fp32) {
-            // two snapshot buffers for every accumulated sweep of a launch (at most
-            // refresh_every or 64 sweeps, and at most 16 GiB together), rows padded to whole
-            // 16-byte words, reduced by (tile, split) workgroups
-            int64_t per_row = 0;
-            for (auto &pd : pl->probs)
-                per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
-            const int64_t cap = (int64_t)16 << 30;
-            const int64_t want_rows = o->refresh_every > 0 ? o->refresh_every : 64;
-            pl->snap_rows = std::max<int64_t>(1, std::min<int64_t>(want_rows, cap / std::max<int64_t>(per_row, 1)));
-            for (auto &pd : pl->probs) {
-                pd.off_sa = pl->snap_words_a;
-                pd.off_sr = pl->snap_words_r;
-                pl->snap_words_a += pl->snap_rows * pd.C * ((pd.N + 3) / 4 * 4);
-                pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
-                pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N));
-            }
+            // cross moments reduced by (tile, split) workgroups
             pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (1024 + pl->max_snap_tiles - 1) / pl->max_snap_tiles));
         } else {
             // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
@@ -758,18 +774,19 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         STEP(dalloc(pl, &pl->A64, offA));
         STEP(dalloc(pl, &pl->r64, offr));
     }
+    if (pl->fp32 && !t_probe_plan) {
+        for (int j = 0; j < 2; ++j) {
+            STEP(dalloc(pl, &pl->snapA[j], pl->snap_words_a));
+            if (o->want_vjp) STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
+            HSTEP(hipEventCreateWithFlags(&pl->ev_ready[j], hipEventDisableTiming));
+            HSTEP(hipEventCreateWithFlags(&pl->ev_done[j], hipEventDisableTiming));
+        }
+        STEP(dalloc(pl, &pl->snap_first, 2));
+        // default priority; non-blocking, so that null-stream work does not serialise it
+        HSTEP(hipStreamCreateWithFlags(&pl->xstream, hipStreamNonBlocking));
+    }
     if (o->want_vjp) {
         STEP(dalloc(pl, &pl->cross, offcross));
-        if (pl->fp32) {
-            for (int j = 0; j < 2; ++j) {
-                STEP(dalloc(pl, &pl->snapA[j], pl->snap_words_a));
-                STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
-                HSTEP(hipEventCreateWithFlags(&pl->ev_ready[j], hipEventDisableTiming));
-                HSTEP(hipEventCreateWithFlags(&pl->ev_done[j], hipEventDisableTiming));
-            }
-            // default priority; non-blocking, so that null-stream work does not serialise it
-            HSTEP(hipStreamCreateWithFlags(&pl->xstream, hipStreamNonBlocking));
-        }
         STEP(dalloc(pl, &pl->nsamples, n));
         STEP(dalloc(pl, &pl->vjp_y, offm));
     }
@@ -903,23 +920,18 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         }
         STEP(dalloc(pl, &pl->U32, offU32));
         // LDS of a workgroup: the staging area (the block's (V, w) rows with two spare rows
-        // for the rows loaded ahead, its singular values, and its U rows when they fit), one
-        // uniform row per chain, and the float64 per-tile sums when they fit and no problem
-        // uses batch means.  Each block's packed chunk is the image of the staging area.
+        // for the rows loaded ahead, its singular values, and its U rows when they fit) and
+        // one uniform row per chain.  Each block's packed chunk is the image of the staging
+        // area.
         int64_t max_kb = 0, max_n = 0;
-        bool batch_means = false;
         for (auto &bd : pl->blocks) max_kb = std::max(max_kb, bd.kb);
-        for (auto &pd : pl->probs) {
-            max_n = std::max(max_n, pd.N);
-            batch_means |= pd.batches > 1;
-        }
+        for (auto &pd : pl->probs) max_n = std::max(max_n, pd.N);
         pl->max_kb = max_kb;
         pl->max_n = max_n;
         const size_t vw_bytes = (size_t)(pl->max_nb + 2) * row * sizeof(float2);
         const size_t d_bytes = (size_t)(max_kb + 3) / 4 * 16;
         const size_t u_bytes = (size_t)max_kb * mp * sizeof(float);
-        const size_t acc_bytes = (size_t)2 * max_n * sizeof(double);
-        auto layout = [&](int cpw, bool with_u, bool with_acc) {
+        auto layout = [&](int cpw, bool with_u) {
             size_t off = vw_bytes;
             pl->lds_off_d = (int64_t)off;
             off += d_bytes;
@@ -928,22 +940,18 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             off = (off + 15) / 16 * 16;
             pl->lds_off_unif = (int64_t)off;
             off += (size_t)cpw * row * sizeof(float);
-            off = (off + 15) / 16 * 16;
-            pl->lds_off_acc = (int64_t)off;
-            if (with_acc) off += acc_bytes;
             return off;
         };
         // chains per workgroup: enough workgroups for every CU, at most 512 threads
         int cpw = 512 / L;
         while (cpw > 64 / L) {
             const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
-            if (layout(cpw, false, false) <= kLdsBudget && wgs >= max_cu) break;
+            if (layout(cpw, false) <= kLdsBudget && wgs >= max_cu) break;
             cpw /= 2;
         }
         pl->chains_per_wg = cpw;
-        pl->u_lds = layout(cpw, true, false) <= kLdsBudget ? 1 : 0;
-        pl->acc_lds = (!batch_means && layout(cpw, pl->u_lds, true) <= kLdsBudget) ? 1 : 0;
-        pl->lds32 = layout(cpw, pl->u_lds, pl->acc_lds);
+        pl->u_lds = layout(cpw, true) <= kLdsBudget ? 1 : 0;
+        pl->lds32 = layout(cpw, pl->u_lds);
         if (pl->lds32 > kLdsBudget) {
             rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
             return rc;

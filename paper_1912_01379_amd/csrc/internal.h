@@ -95,15 +95,13 @@ struct SampleArgs {
     int32_t pad;
     int64_t lds_off_d;        // byte offsets in the float32 sampler's LDS: singular values,
     int64_t lds_off_u;        //   U rows,
-    int64_t lds_off_unif;     //   per-chain uniform rows,
-    int64_t lds_off_acc;      //   float64 per-tile sums (2 x max N)
+    int64_t lds_off_unif;     //   per-chain uniform rows
     int32_t u_lds;            // 1: U rows are staged in LDS (else read from global memory)
-    int32_t acc_lds;          // 1: accumulate in LDS and flush once per tile and launch
     int32_t prefetch;         // 1: every block's factor stream fits the instance's prefetch
-    int32_t pad2;
-    float *snapA;             // nullable: per-sweep snapshots of A and r of the accumulated
-    float *snapR;             //   sweeps of the launch (at the problems' off_sa / off_sr), for
-    int64_t snap_rows;        //   the cross moments; snapshot = sweep - first sweep of the launch
+    float *snapA;             // nullable: per-sweep snapshots of A (float32 sampler: the sums of
+    float *snapR;             //   A and A^2 are reduced from them) and of r (cross moments) of
+    int64_t snap_rows;        //   the accumulated sweeps of the launch, at the problems' off_sa /
+    int64_t *snap_first;      //   off_sr; row = sweep - first sweep, which goes to *snap_first
 };
 
 // ------------------------------------------------------------------------------------
@@ -195,6 +193,9 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
                              const float *snapA, const float *snapR, double *cross, hipStream_t s);
 __host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N);
+hipError_t launch_acc_snap(const ProbDesc *probs_dev, const TileDesc *tiles_dev, int64_t ntiles, int64_t max_n,
+                           int64_t nsnap, const float *snapA, const int64_t *snap_first, int64_t burnin,
+                           int64_t sweeps, double *accA, double *accA2, hipStream_t s);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,

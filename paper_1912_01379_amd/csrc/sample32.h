@@ -185,13 +185,30 @@ __device__ __forceinline__ void stage_sync(float4 *dst, const float4 *src, int n
 // they stay in registers.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// The plan's descriptor tables are written before any sampler launch and never during one:
+// read through the constant address space, their uniform loads become scalar loads, which
+// keep out of the vector-memory wait counts.
+template <typename T>
+__device__ __forceinline__ T cload(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    cword *src = (cword *)p;
+    T v;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+
 template <int PF>
 struct Prefetch {
     f32x4 w[PF > 0 ? PF : 1];
 
+    // every load is issued (indices past the chunk re-read its last word; store_ skips
+    // them), so no load sits in a branch and the compiler's wait counting stays exact
     template <int... K>
     __device__ __forceinline__ void load_(const f32x4 *src, int tid, int nthr, int n, std::integer_sequence<int, K...>) {
-        ((tid + K * nthr < n ? (void)(w[K] = src[tid + K * nthr]) : (void)0), ...);
+        ((w[K] = src[min(tid + K * nthr, n - 1)]), ...);
     }
     template <int... K>
     __device__ __forceinline__ void store_(f32x4 *dst, int tid, int nthr, int n, std::integer_sequence<int, K...>) const {
@@ -223,31 +240,28 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     float *sD = reinterpret_cast<float *>(smem32 + a.lds_off_d);
     float *sU = reinterpret_cast<float *>(smem32 + a.lds_off_u);
     float *sUnif = reinterpret_cast<float *>(smem32 + a.lds_off_unif);
-    double *sAcc = reinterpret_cast<double *>(smem32 + a.lds_off_acc);
     __shared__ int s_tile;
     const int64_t s0 = *a.sweep;
     const int64_t nsw = a.nsw;
-    // this launch accumulates into the workgroup's LDS sums (flushed once per tile)
-    const bool acc_lds = a.accumulate && a.acc_lds && s0 + nsw > a.burnin;
+    // the first sweep of the snapshot rows, for their reduction into the sums of A and A^2
+    if (a.snapA && blockIdx.x == 0 && tid == 0) *a.snap_first = s0;
     const bool prefetch = PF > 0 && a.prefetch;
     Prefetch<PF> pf;
 
     for (;;) {
         if (tid == 0) s_tile = atomicAdd(a.queue, 1);
         __syncthreads();
-        const int tile = s_tile;
+        const int tile = __builtin_amdgcn_readfirstlane(s_tile);   // uniform: descriptors load to SGPRs
         __syncthreads();
         if (tile >= a.ntiles) break;
-        const TileDesc td = a.tiles[tile];
-        const ProbDesc pd = a.probs[td.problem];
+        const TileDesc td = cload(a.tiles + tile);
+        const ProbDesc pd = cload(a.probs + td.problem);
         const int M = (int)pd.M;
         const int64_t N = pd.N;
         const bool active = slotc < td.nchains;
         const int64_t chain = td.chain0 + (active ? slotc : 0);
         float *Ag = a.A32 + pd.off_A + chain * N;
         float *rg = a.r32 + pd.off_r + chain * (int64_t)M;
-        if (acc_lds)
-            for (int64_t n = tid; n < 2 * N; n += nthr) sAcc[n] = 0.0;
         float rr[RPT];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
@@ -257,36 +271,48 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         float *urow = sUnif + slotc * ROW;
         const int nw = (int)a.chunk_words;
         float4 *stage = reinterpret_cast<float4 *>(smem32);
-        if (prefetch) pf.load(a.F32 + a.blocks[pd.off_blk].off_chunk, tid, nthr, nw);
+        if (prefetch) pf.load(a.F32 + cload(a.blocks + pd.off_blk).off_chunk, tid, nthr, nw);
         // components of the next block to sample, loaded one block ahead (blocks are disjoint,
         // so sampling a block leaves the next one's components unchanged)
         float An[EPT];
         {
-            const BlockDesc b0 = a.blocks[pd.off_blk];
+            const BlockDesc b0 = cload(a.blocks + pd.off_blk);
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) An[t] = Ag[b0.n0 + min(lane + L * t, (int)b0.nb - 1)];
+            // wait for them here (once per tile): the block loop then starts with no load of
+            // this path outstanding, so the prefetch below is not waited for early
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        }
+        // The components of the block sampled last (and its snapshot row) are stored while the
+        // next block is sampled: a store issued at the end of a block would still be in flight
+        // when the next block waits for its prefetched loads, and the wait would include it.
+        const int64_t NR = (N + 3) / 4 * 4;
+        float Ap[EPT];
+        int64_t p_n0 = 0, p_row = -1;
+        int p_nb = 0;
+        auto store_prev = [&]() {
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int q = lane + L * t;
-                An[t] = (q < (int)b0.nb && active) ? Ag[b0.n0 + q] : 0.0f;
+                if (active && q < p_nb) Ag[p_n0 + q] = Ap[t];
             }
-        }
+            if (p_row >= 0) {
+                float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0;
+#pragma unroll
+                for (int t = 0; t < EPT; ++t) {
+                    const int q = lane + L * t;
+                    if (active && q < p_nb) sa[q] = Ap[t];
+                }
+            }
+        };
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
             for (int64_t b = 0; b < pd.B; ++b) {
-                const BlockDesc bd = a.blocks[pd.off_blk + b];
+                const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
                 float Ar[EPT];
 #pragma unroll
-                for (int t = 0; t < EPT; ++t) Ar[t] = An[t];
-                if (pd.B > 1 && (b + 1 < pd.B || s + 1 < s0 + nsw)) {
-                    // the next block of this sweep, or the first of the next (its components
-                    // were stored when this sweep sampled it)
-                    const BlockDesc bn = a.blocks[pd.off_blk + (b + 1 < pd.B ? b + 1 : 0)];
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) {
-                        const int q = lane + L * t;
-                        An[t] = (q < (int)bn.nb && active) ? Ag[bn.n0 + q] : 0.0f;
-                    }
-                }
+                for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 if (prefetch) {
                     pf.store(stage, tid, nthr, nw);
@@ -304,10 +330,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     d[3] = word_u32(w.w);
                 }
                 __syncthreads();
-                if (prefetch && (b + 1 < pd.B || s + 1 < s0 + nsw)) {
-                    // the next block of this sweep, or the first of the next
-                    pf.load(a.F32 + a.blocks[pd.off_blk + (b + 1 < pd.B ? b + 1 : 0)].off_chunk, tid, nthr, nw);
-                }
+                store_prev();
                 const float *Ug = a.U32 + bd.off_U32;
                 float2 vw[EPT];
                 load_row<EPT>(vw, sVW, lane, L);
@@ -315,8 +338,25 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 // two copies of the loop, so the LDS one waits on no global loads)
                 if (a.u_lds)
                     data_moves<L, EPT, RPT, true>(kb, sVW, sD, sU, urow, lane, vw, Ar, rr);
-                else
+                else {
                     data_moves<L, EPT, RPT, false>(kb, sVW, sD, Ug, urow, lane, vw, Ar, rr);
+                    // the U row loaded ahead past the last data mode is never read: wait for
+                    // it here, or the compiler waits for every load in flight (the prefetch
+                    // below included) where its register is reused
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                }
+                {
+                    // the next block (of this sweep, or the first of the next): its components,
+                    // which were stored when this sweep sampled it, and its factor chunk, loaded
+                    // during the zero modes.  The component loads are unconditional and clamped
+                    // into the block (the padding lanes are zeroed when the block starts; with
+                    // one block the values are replaced below), so that no branch leaves the
+                    // compiler's wait counting inexact and nothing waits for them early.
+                    const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < pd.B ? b + 1 : 0));
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
+                    if (prefetch && (b + 1 < pd.B || s + 1 < s0 + nsw)) pf.load(a.F32 + bn.off_chunk, tid, nthr, nw);
+                }
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
                 int i = kb;
@@ -336,61 +376,14 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
                 }
 #pragma unroll
-                for (int t = 0; t < EPT; ++t) {
-                    const int q = lane + L * t;
-                    if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
-                }
-                if (pd.B == 1) {
+                for (int t = 0; t < EPT; ++t) Ap[t] = Ar[t];
+                if (pd.B == 1) {   // the next block is this one
 #pragma unroll
                     for (int t = 0; t < EPT; ++t) An[t] = Ar[t];
                 }
-                if (a.snapA && s >= a.burnin) {
-                    float *sa = a.snapA + pd.off_sa + ((s - s0) * pd.C + chain) * ((N + 3) / 4 * 4) + bd.n0;
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) {
-                        const int q = lane + L * t;
-                        if (active && q < nb) sa[q] = Ar[t];
-                    }
-                }
-                if (a.accumulate && s >= a.burnin) {
-                    // sums over the tile's chains, float64; the uniforms of this block are
-                    // consumed, so each chain's row now carries its components
-#pragma unroll
-                    for (int t = 0; t < EPT; ++t) urow[lane + L * t] = active ? Ar[t] : 0.0f;
-                    __syncthreads();
-                    double *s1, *s2;
-                    if (acc_lds) {
-                        s1 = sAcc + bd.n0;
-                        s2 = sAcc + N + bd.n0;
-                    } else {
-                        int64_t slot = td.slot;
-                        if (pd.batches > 1) slot += (s - a.burnin) * pd.batches / a.sweeps;
-                        s1 = a.accA + pd.off_slot + slot * N + bd.n0;
-                        s2 = a.accA2 + pd.off_slot + slot * N + bd.n0;
-                    }
-                    for (int q = tid; q < nb; q += nthr) {
-                        double x1 = 0.0, x2 = 0.0;
-                        int cs = 0;
-                        for (; cs + 8 <= td.nchains; cs += 8) {   // eight LDS loads in flight
-                            float v[8];
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) v[k] = sUnif[(cs + k) * ROW + q];
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) {
-                                const double x = (double)v[k];
-                                x1 += x;
-                                x2 = fma(x, x, x2);
-                            }
-                        }
-                        for (; cs < td.nchains; ++cs) {
-                            const double x = (double)sUnif[cs * ROW + q];
-                            x1 += x;
-                            x2 = fma(x, x, x2);
-                        }
-                        s1[q] += x1;
-                        s2[q] += x2;
-                    }
-                }
+                p_n0 = bd.n0;
+                p_nb = nb;
+                p_row = (a.snapA && s >= a.burnin) ? s - s0 : -1;
             }
             if (a.snapR && s >= a.burnin) {
                 float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
@@ -401,19 +394,11 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 }
             }
         }
+        store_prev();
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
             const int m = lane + L * t;
             if (active && m < M) rg[m] = rr[t];
-        }
-        if (acc_lds) {
-            __syncthreads();
-            double *s1 = a.accA + pd.off_slot + (int64_t)td.slot * N;
-            double *s2 = a.accA2 + pd.off_slot + (int64_t)td.slot * N;
-            for (int64_t n = tid; n < N; n += nthr) {
-                s1[n] += sAcc[n];
-                s2[n] += sAcc[N + n];
-            }
         }
     }
 }
