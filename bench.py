@@ -142,12 +142,14 @@ def batched(args):
         plan.close()
         return res
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         step()
+        print(f"warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         res = step()
+        print(f"step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = res.stats
@@ -220,13 +222,15 @@ def main():
         plan.close()
         return res, (t1 - t0), (t2 - t1), blocks, g
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         step()
+        print(f"warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     outs = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         outs.append(step())
+        print(f"step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
