@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 64 float32 lanes x 2.4 GHz, one operation per lane per cycle (no packed
 # float32 arithmetic; a fused multiply-add counts as one operation)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "tn32.h", "tn32_coef.h", "rng_tn.h", "internal.h"]
+SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "tn32.h", "tn32_coef.h",
+                   "rng_tn.h", "internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sample32_single_continuation_traffic.md")
 
 

@@ -94,6 +94,13 @@ typedef struct {
                                     once per run; results are identical to eager launches    */
     int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
                                     or ASM_START_NNLS                                        */
+    int32_t roles;               /* ASM_FP32 with 16 lanes per chain: 0 = two roles when the
+                                    problems allow it (every problem of two blocks or more),
+                                    1 = one role, 2 = two roles (ASM_EINVAL if not allowed).
+                                    Two roles run the data modes of block b + 1 beside the
+                                    zero modes of block b, which act on disjoint state (the
+                                    zero modes leave r~ unchanged, Sec. IV.C): the chains
+                                    are bit-identical to one role                            */
 } asm_options;
 
 /* ---- start model ---------------------------------------------------------------------- */
@@ -121,6 +128,7 @@ typedef struct {
     int64_t sampler_sweeps;      /* sweeps they covered (each over all chains)                */
     int64_t graph_replays;       /* refresh cycles replayed from a captured hipGraph (use_graph);
                                     their sampler launches are not in sampler_ms             */
+    int64_t roles;               /* 1 or 2: the float32 sampler's roles (see asm_options)     */
 } asm_stats;
 
 /* Validate the problems, whiten them, decompose every block (float64 one-sided Jacobi SVD,

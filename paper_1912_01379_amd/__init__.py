@@ -45,7 +45,7 @@ class _Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("want_vjp", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("start", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("start", ctypes.c_int32), ("roles", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("clamped", ctypes.c_int64), ("frozen", ctypes.c_int64),
                 ("lanes_per_chain", ctypes.c_int32), ("chains_per_block", ctypes.c_int32),
                 ("sampler_ms", ctypes.c_double), ("sampler_launches", ctypes.c_int64),
-                ("sampler_sweeps", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
+                ("sampler_sweeps", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("roles", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -133,7 +134,7 @@ class Plan:
 
     def __init__(self, problems, chains=256, burnin=100, sweeps=1000, seed=1234, precision="fp32",
                  refresh_every=64, want_vjp=False, groups=32, lanes_per_chain=0, use_graph=False,
-                 start="flat", device="cuda:0"):
+                 start="flat", roles=0, device="cuda:0"):
         self.device = torch.device(device)
         if isinstance(precision, str):
             precision = ASM_FP32 if precision.lower() == "fp32" else ASM_FP64
@@ -163,7 +164,8 @@ class Plan:
                                 refresh_every=int(refresh_every), want_vjp=int(bool(want_vjp)),
                                 groups=int(groups), lanes_per_chain=int(lanes_per_chain),
                                 use_graph=int(bool(use_graph)),
-                                start=ASM_START_NNLS if start == "nnls" else ASM_START_FLAT)
+                                start=ASM_START_NNLS if start == "nnls" else ASM_START_FLAT,
+                                roles=int(roles))
         self.chains = int(chains)
         self.handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libasm.so")
-SOURCES = ["api.hip", "setup.hip", "sample.hip", "linalg.hip", "sample32.hip", "sample32_l4.hip",
+SOURCES = ["api.hip", "setup.hip", "sample.hip", "linalg.hip", "sample32.hip", "sample32p_l16.hip", "sample32_l4.hip",
            "sample32_l8.hip", "sample32_l16.hip", "sample32_l32.hip"]
 
 FLAGS = [

@@ -76,6 +76,10 @@ struct asm_plan {
     int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0;   // float32 sampler LDS
     int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
     int u_lds = 0;
+    int roles = 1;           // 2: the two-role sampler (sample32p.h)
+    int64_t p_off_vwd = 0, p_off_d = 0, p_off_u = 0, p_off_vwz = 0, p_off_und = 0, p_off_unz = 0, p_off_h = 0;
+    int64_t p_du_word = 0;
+    int32_t p_wd = 0, p_wu = 0, p_kd = 0;
     bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
@@ -284,6 +288,17 @@ SampleArgs make_args(asm_plan *pl) {
     a.lds_off_unif = pl->lds_off_unif;
     a.u_lds = pl->u_lds;
     a.prefetch = pl->prefetch;
+    a.p_off_vwd = pl->p_off_vwd;
+    a.p_off_d = pl->p_off_d;
+    a.p_off_u = pl->p_off_u;
+    a.p_off_vwz = pl->p_off_vwz;
+    a.p_off_und = pl->p_off_und;
+    a.p_off_unz = pl->p_off_unz;
+    a.p_off_h = pl->p_off_h;
+    a.p_du_word = pl->p_du_word;
+    a.p_wd = pl->p_wd;
+    a.p_wu = pl->p_wu;
+    a.p_kd = pl->p_kd;
     return a;
 }
 
@@ -328,7 +343,10 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     }
     if (pl->fp32) {
         a.refresh_every = 0;
-        HIPCHK(launch_sample32_inst(a, pl->lanes, pl->ept, pl->rpt, pl->chains_per_wg, pl->grid32,
+        if (pl->roles == 2)
+            HIPCHK(launch_sample32p(a, pl->ept, pl->rpt, pl->grid32, pl->lds32, pl->stream));
+        else
+            HIPCHK(launch_sample32_inst(a, pl->lanes, pl->ept, pl->rpt, pl->chains_per_wg, pl->grid32,
                                     pl->lds32, pl->stream));
     } else {
         a.refresh_every = pl->opt.refresh_every;
@@ -625,6 +643,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     pl->fp32 = o->precision == ASM_FP32;
     for (auto &e : pl->ev) HSTEP(hipEventCreate(&e));
     (void)set_sample32_lds_limit(160 * 1024);
+    (void)allow_lds_sample32p(160 * 1024);
     (void)set_sample64_lds_limit();
     (void)hipGetLastError();
 
@@ -968,6 +987,45 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         // the next block's chunk is prefetched into registers when it fits the instance's
         // per-thread budget
         pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw) ? 1 : 0;
+        // two roles (data modes of the next block beside the zero modes of this one) when the
+        // instance, the partitions (two blocks or more) and the staging areas allow it
+        {
+            int pe = 0, pr = 0, pfr = 0, pfu = 0, pfz = 0;
+            bool ok = o->roles != 1 && L == 16 && pl->u_lds &&
+                      sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
+            for (auto &pd : pl->probs) ok = ok && pd.B >= 2;
+            const int64_t rw = row / 2;   // 16-byte words per (V, w) row
+            int64_t zrows = 0;
+            for (auto &bd : pl->blocks) zrows = std::max(zrows, bd.nb + 2 - bd.kb);
+            const int64_t wd = (max_kb + 2) * rw, wu = (pl->chunk.d_len + max_kb * mp) / 4;
+            ok = ok && wd <= 256LL * pfr && wu <= 256LL * pfu && zrows * rw <= 256LL * pfz;
+            size_t off = 0;
+            auto take = [&](size_t bytes) {
+                const size_t at = off;
+                off = (off + bytes + 15) / 16 * 16;
+                return (int64_t)at;
+            };
+            pl->p_off_vwd = take((size_t)wd * 16);
+            pl->p_off_d = take((size_t)wu * 16);
+            pl->p_off_u = pl->p_off_d + pl->chunk.d_len * (int64_t)sizeof(float);
+            pl->p_off_vwz = take((size_t)zrows * rw * 16);
+            pl->p_kd = (int32_t)((max_kb + 3) / 4 * 4);
+            pl->p_off_und = take((size_t)16 * pl->p_kd * sizeof(float));
+            pl->p_off_unz = take((size_t)16 * row * sizeof(float));
+            pl->p_off_h = take((size_t)2 * 16 * row * sizeof(float));
+            ok = ok && off <= kLdsBudget;
+            if (ok) {
+                pl->roles = 2;
+                pl->lds32 = off;
+                pl->p_wd = (int32_t)wd;
+                pl->p_wu = (int32_t)wu;
+                pl->p_du_word = pl->chunk.rows * rw;
+            } else if (o->roles == 2) {
+                rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, the (7, 13) instance, two blocks or "
+                                      "more per problem and the staging areas in LDS");
+                return rc;
+            }
+        }
         build_tiles(pl);
         pl->grid32 = (int)std::min<int64_t>((int64_t)pl->tiles.size(), (int64_t)max_cu * 2);
         STEP(dalloc(pl, &pl->d_tiles, pl->tiles.size()));
@@ -1132,6 +1190,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         stats->sampler_launches = (int64_t)(pl->tev_used / 2);
         stats->sampler_sweeps = pl->timed_sweeps;
         stats->graph_replays = pl->graph_replays;
+        stats->roles = pl->roles;
     }
     if (hflags & 1) return fail(ASM_EUNBOUNDED, "a zero mode has an unbounded interval: improper posterior");
     return ASM_OK;

@@ -102,6 +102,12 @@ struct SampleArgs {
     float *snapR;             //   A and A^2 are reduced from them) and of r (cross moments) of
     int64_t snap_rows;        //   the accumulated sweeps of the launch, at the problems' off_sa /
     int64_t *snap_first;      //   off_sr; row = sweep - first sweep, which goes to *snap_first
+    // two-role float32 sampler (sample32p.h): LDS byte offsets of its areas, the chunk word
+    // where the singular values (then the U rows) start, the words of the data rows part and
+    // of the d/U part, the data-role uniform row length
+    int64_t p_off_vwd, p_off_d, p_off_u, p_off_vwz, p_off_und, p_off_unz, p_off_h;
+    int64_t p_du_word;
+    int32_t p_wd, p_wu, p_kd, p_pad;
 };
 
 // ------------------------------------------------------------------------------------
@@ -171,6 +177,10 @@ hipError_t allow_lds_sample32_l4(int bytes);
 hipError_t allow_lds_sample32_l8(int bytes);
 hipError_t allow_lds_sample32_l16(int bytes);
 hipError_t allow_lds_sample32_l32(int bytes);
+// sample32p_l16.hip: the two-role instance (16 lanes per chain, 512 threads)
+hipError_t launch_sample32p(const SampleArgs &a, int ept, int rpt, int grid, size_t lds, hipStream_t s);
+int sample32p_pick(int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pfr, int *pfu, int *pfz);
+hipError_t allow_lds_sample32p(int bytes);
 hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s);
 hipError_t launch_reset_queue(int *queue, hipStream_t s);
 hipError_t launch_tn_draw(const double *c, const double *d, const double *lo, const double *hi,

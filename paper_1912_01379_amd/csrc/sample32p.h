@@ -1,0 +1,287 @@
+// Two-role float32 sampler: the data modes of block b + 1 run beside the zero modes of
+// block b (Sec. IV.B-C).
+//
+// A zero-mode move changes only the components of its own block (V_i lies in the null space
+// of the block's kernel, so r is untouched), and a data-mode move of block b + 1 reads only r
+// and the components of block b + 1.  The zero modes of block b and the data modes of block
+// b + 1 therefore act on disjoint state, and running them at the same time gives every move
+// exactly the inputs of the one-role order (data modes, then zero modes, block after block):
+// the results are bit-identical to k_sample32 with the same instance.
+//
+// A workgroup of 16 chains runs 512 threads in two roles of four wavefronts each, one of each
+// role per SIMD, so that each SIMD interleaves two independent instruction streams:
+//   data role (threads 0..255):   block steps j = 0, 1, ...: loads A of step j, runs its data
+//                                 modes, hands A to the zero role through LDS (two buffers);
+//                                 carries r for the whole launch;
+//   zero role (threads 256..511): step j - 1: takes A from the hand-off buffer, runs the zero
+//                                 modes, stores A (and its snapshot row).
+// Stage t runs data step t and zero step t - 1; the two barriers of a stage separate the
+// staging writes from the moves.  A block's components are stored by the zero role at stage
+// j + 1 and loaded again by the data role at stage j + B, so problems need B >= 2.
+// Each role stages its own part of the block's packed chunk, prefetched into registers one
+// stage ahead: the data part (rows 0..max k + 1 of (V, w), the singular values and the U rows)
+// and the zero part (rows k_b..n_b + 1 of (V, w)).
+#pragma once
+
+#include "sample32.h"
+
+namespace asmk {
+
+// LDS areas of the two-role sampler
+struct AreasP {
+    float2 *vwd;   // data rows 0..max k + 1
+    float *d;      // singular values, then the U rows (one staged range)
+    float *u;
+    float2 *vwz;   // zero rows k_b..n_b + 1 of the block of the zero role
+    float *und;    // data-role uniforms, p_kd per chain
+    float *unz;    // zero-role uniforms, ROW per chain (indexed by mode)
+    float *h;      // hand-off of A: two buffers of cpw rows of ROW
+};
+
+// Barrier with LDS ordering only: the stage's first barrier separates LDS readers from the
+// staging writes and needs no wait for global stores still in flight (the second barrier of
+// each stage is a full one, which orders the component stores before later loads).
+__device__ __forceinline__ void barrier_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The tile queue, walked by both roles with the same barriers: 0 and below is a tile,
+// -1 ends the launch.
+__device__ __forceinline__ int next_tile_p(const SampleArgs &a, int *s_tile, int tid) {
+    if (tid == 0) *s_tile = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int tile = __builtin_amdgcn_readfirstlane(*s_tile);
+    __syncthreads();
+    return tile < a.ntiles ? tile : -1;
+}
+
+// Data role: data modes of block step t at stage t; r for the whole launch.
+template <int L, int EPT, int RPT, int PFR, int PFU>
+__device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
+    constexpr int ROW = EPT * L;
+    constexpr int CPW = 256 / L;
+    const int lane = tid % L;
+    const int slotc = tid / L;
+    const int64_t s0 = *a.sweep;
+    const int64_t nsw = a.nsw;
+    Prefetch<PFR> pfr;
+    Prefetch<PFU> pfu;
+    for (;;) {
+        const int tile = next_tile_p(a, s_tile, tid);
+        if (tile < 0) break;
+        const TileDesc td = cload(a.tiles + tile);
+        const ProbDesc pd = cload(a.probs + td.problem);
+        const int M = (int)pd.M;
+        const int64_t N = pd.N;
+        const int B = (int)pd.B;
+        const bool active = slotc < td.nchains;
+        const int64_t chain = td.chain0 + (active ? slotc : 0);
+        float *Ag = a.A32 + pd.off_A + chain * N;
+        float *rg = a.r32 + pd.off_r + chain * (int64_t)M;
+        const int64_t total = nsw * B;
+        float rr[RPT];
+#pragma unroll
+        for (int t2 = 0; t2 < RPT; ++t2) {
+            const int m = lane + L * t2;
+            rr[t2] = (m < M && active) ? rg[m] : 0.0f;
+        }
+        float *urow = ar.und + slotc * a.p_kd;
+        // the data parts and the components of step 0; components are loaded one stage ahead
+        // when B >= 3 (the zero role stored them at least two stages before), else at the
+        // start of their stage (stored at the end of the stage before)
+        float An[EPT];
+        {
+            const BlockDesc b0 = cload(a.blocks + pd.off_blk);
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) An[t2] = Ag[b0.n0 + min(lane + L * t2, (int)b0.nb - 1)];
+            pfr.load(a.F32 + b0.off_chunk, tid, 256, a.p_wd);
+            pfu.load(a.F32 + b0.off_chunk + a.p_du_word, tid, 256, a.p_wu);
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), once per tile
+        }
+        for (int64_t t = 0; t <= total; ++t) {
+            const bool step = t < total;
+            const int64_t s = s0 + t / B;
+            const int b = (int)(t % B);
+            const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
+            const int nb = (int)bd.nb, kb = (int)bd.kb;
+            barrier_lds();   // the previous stage's readers of the staging areas are done
+            if (step) {
+                pfr.store(reinterpret_cast<float4 *>(ar.vwd), tid, 256, a.p_wd);
+                pfu.store(reinterpret_cast<float4 *>(ar.d), tid, 256, a.p_wu);
+                for (int g = lane; 4 * g < kb; g += L) {
+                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
+                                              (uint32_t)g);
+                    float *d = urow + 4 * g;
+                    d[0] = word_u32(w.x);
+                    d[1] = word_u32(w.y);
+                    d[2] = word_u32(w.z);
+                    d[3] = word_u32(w.w);
+                }
+            }
+            __syncthreads();
+            if (!step) continue;
+            if (B < 3 && t > 0) {
+#pragma unroll
+                for (int t2 = 0; t2 < EPT; ++t2) An[t2] = Ag[bd.n0 + min(lane + L * t2, nb - 1)];
+            }
+            float Ar[EPT];
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = (lane + L * t2 < nb && active) ? An[t2] : 0.0f;
+            if (t + 1 < total) {
+                // the data parts (and with B >= 3 the components) of the next step
+                const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < B ? b + 1 : 0));
+                if (B >= 3) {
+#pragma unroll
+                    for (int t2 = 0; t2 < EPT; ++t2) An[t2] = Ag[bn.n0 + min(lane + L * t2, (int)bn.nb - 1)];
+                }
+                pfr.load(a.F32 + bn.off_chunk, tid, 256, a.p_wd);
+                pfu.load(a.F32 + bn.off_chunk + a.p_du_word, tid, 256, a.p_wu);
+            }
+            float2 vw[EPT];
+            load_row<EPT>(vw, ar.vwd, lane, L);
+            data_moves<L, EPT, RPT, true>(kb, ar.vwd, ar.d, ar.u, urow, lane, vw, Ar, rr);
+            float *h = ar.h + ((t & 1) * CPW + slotc) * ROW;
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) h[lane + L * t2] = Ar[t2];
+            if (b == B - 1 && a.snapR && s >= a.burnin) {
+                float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
+#pragma unroll
+                for (int t2 = 0; t2 < RPT; ++t2) {
+                    const int m = lane + L * t2;
+                    if (active && m < M) sr[m] = rr[t2];
+                }
+            }
+        }
+#pragma unroll
+        for (int t2 = 0; t2 < RPT; ++t2) {
+            const int m = lane + L * t2;
+            if (active && m < M) rg[m] = rr[t2];
+        }
+    }
+}
+
+// Zero role: zero modes of block step t - 1 at stage t.
+template <int L, int EPT, int PFZ>
+__device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
+    constexpr int ROW = EPT * L;
+    constexpr int RW = ROW / 2;   // 16-byte words per (V, w) row
+    constexpr int CPW = 256 / L;
+    const int lane = tid % L;
+    const int slotc = tid / L;
+    const int64_t s0 = *a.sweep;
+    const int64_t nsw = a.nsw;
+    Prefetch<PFZ> pfz;
+    for (;;) {
+        const int tile = next_tile_p(a, s_tile, tid + 256);
+        if (tile < 0) break;
+        const TileDesc td = cload(a.tiles + tile);
+        const ProbDesc pd = cload(a.probs + td.problem);
+        const int64_t N = pd.N;
+        const int64_t NR = (N + 3) / 4 * 4;
+        const int B = (int)pd.B;
+        const bool active = slotc < td.nchains;
+        const int64_t chain = td.chain0 + (active ? slotc : 0);
+        float *Ag = a.A32 + pd.off_A + chain * N;
+        const int64_t total = nsw * B;
+        float *urow = ar.unz + slotc * ROW;
+        for (int64_t t = 0; t <= total; ++t) {
+            const bool step = t >= 1;
+            const int64_t j = step ? t - 1 : 0;
+            const int64_t s = s0 + j / B;
+            const int b = (int)(j % B);
+            const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
+            const int nb = (int)bd.nb, kb = (int)bd.kb;
+            barrier_lds();
+            if (step) {
+                pfz.store(reinterpret_cast<float4 *>(ar.vwz), tid, 256, (nb + 2 - kb) * RW);
+                for (int g = kb / 4 + lane; 4 * g < nb; g += L) {
+                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
+                                              (uint32_t)g);
+                    float *d = urow + 4 * g;
+                    d[0] = word_u32(w.x);
+                    d[1] = word_u32(w.y);
+                    d[2] = word_u32(w.z);
+                    d[3] = word_u32(w.w);
+                }
+            }
+            __syncthreads();
+            if (t < total) {
+                // the zero part of step t, sampled at the next stage
+                const BlockDesc bn = cload(a.blocks + pd.off_blk + (int)(t % B));
+                pfz.load(a.F32 + bn.off_chunk + bn.kb * RW, tid, 256, (int)(bn.nb + 2 - bn.kb) * RW);
+            }
+            if (!step) continue;
+            float Ar[EPT];
+            const float *h = ar.h + (((t - 1) & 1) * CPW + slotc) * ROW;
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
+            // zero modes, three per iteration, each row loaded two moves ahead (the two rows
+            // past the block's last are staged, loaded and never used)
+            int i = kb;
+            float2 vw[EPT], vb[EPT], vc[EPT];
+            load_row<EPT>(vw, ar.vwz, lane, L);
+            load_row<EPT>(vb, ar.vwz + ROW, lane, L);
+            for (; i + 3 <= nb; i += 3) {
+                const float2 *rw = ar.vwz + (i - kb) * ROW;
+                load_row<EPT>(vc, rw + 2 * ROW, lane, L);
+                const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
+                zero_move<L, EPT>(vw, Ar, u0);
+                load_row<EPT>(vw, rw + 3 * ROW, lane, L);
+                zero_move<L, EPT>(vb, Ar, u1);
+                load_row<EPT>(vb, rw + 4 * ROW, lane, L);
+                zero_move<L, EPT>(vc, Ar, u2);
+            }
+            if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
+            if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) {
+                const int q = lane + L * t2;
+                if (active && q < nb) Ag[bd.n0 + q] = Ar[t2];
+            }
+            if (a.snapA && s >= a.burnin) {
+                float *sa = a.snapA + pd.off_sa + ((s - s0) * pd.C + chain) * NR + bd.n0;
+#pragma unroll
+                for (int t2 = 0; t2 < EPT; ++t2) {
+                    const int q = lane + L * t2;
+                    if (active && q < nb) sa[q] = Ar[t2];
+                }
+            }
+        }
+    }
+}
+
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+__global__ __launch_bounds__(512) void k_sample32p(SampleArgs a) {
+    extern __shared__ __align__(16) unsigned char smem32[];
+    __shared__ int s_tile;
+    AreasP ar;
+    ar.vwd = reinterpret_cast<float2 *>(smem32 + a.p_off_vwd);
+    ar.d = reinterpret_cast<float *>(smem32 + a.p_off_d);
+    ar.u = reinterpret_cast<float *>(smem32 + a.p_off_u);
+    ar.vwz = reinterpret_cast<float2 *>(smem32 + a.p_off_vwz);
+    ar.und = reinterpret_cast<float *>(smem32 + a.p_off_und);
+    ar.unz = reinterpret_cast<float *>(smem32 + a.p_off_unz);
+    ar.h = reinterpret_cast<float *>(smem32 + a.p_off_h);
+    if (a.snapA && blockIdx.x == 0 && threadIdx.x == 0) *a.snap_first = *a.sweep;
+    // the role is uniform per wavefront; the two branches hold disjoint live registers
+    if (threadIdx.x < 256)
+        data_role_p<L, EPT, RPT, PFR, PFU>(a, ar, &s_tile, (int)threadIdx.x);
+    else
+        zero_role_p<L, EPT, PFZ>(a, ar, &s_tile, (int)threadIdx.x - 256);
+}
+
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+hipError_t launch_sample32p_t(const SampleArgs &a, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_sample32p<L, EPT, RPT, PFR, PFU, PFZ>), dim3(grid), dim3(512), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+hipError_t allow_lds_sample32p_t(int bytes) {
+    return hipFuncSetAttribute((const void *)k_sample32p<L, EPT, RPT, PFR, PFU, PFZ>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace asmk

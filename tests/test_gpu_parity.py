@@ -387,6 +387,41 @@ def test_graph_replay_matches_eager(pk, want_vjp):
     graph.close()
 
 
+@pytest.mark.parametrize("nblocks", [2, 3, 8])
+def test_two_roles_match_one_role_bit_for_bit(pk, nblocks):
+    """The two-role sampler (data modes of block b + 1 beside the zero modes of block b) moves
+    every mode with the inputs of the one-role order: states, averages, error bars and the
+    VJP agree bit for bit, with two blocks (components loaded at the start of their stage),
+    three and eight (loaded one stage ahead)."""
+    p = workloads.small_problem(M=101, N=100 * nblocks, nblocks=nblocks, sigma=2e-3, seed=9)
+    kw = dict(chains=256, burnin=64, sweeps=128, seed=77, precision="fp32", groups=32,
+              refresh_every=64, lanes_per_chain=16, want_vjp=True, start="nnls")
+    one = pk.Plan([p], roles=1, **kw)
+    two = pk.Plan([p], roles=2, **kw)
+    v = np.linspace(-1.0, 1.0, p.N)
+    for rep in range(2):
+        r1, r2 = one.run(), two.run()
+        assert r1.stats["roles"] == 1 and r2.stats["roles"] == 2
+        for name in ("mean", "stderr", "post_sd"):
+            assert np.array_equal(getattr(r1, name).cpu().numpy(), getattr(r2, name).cpu().numpy()), (rep, name)
+        assert np.array_equal(one.vjp(v).cpu().numpy(), two.vjp(v).cpu().numpy())
+        A1, q1, _ = one.state(0)
+        A2, q2, _ = two.state(0)
+        assert np.array_equal(A1.cpu().numpy(), A2.cpu().numpy())
+        assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
+    one.close()
+    two.close()
+
+
+def test_two_roles_refuse_a_single_block(pk):
+    p = workloads.small_problem(M=101, N=100, nblocks=1, sigma=2e-3, seed=9)
+    with pytest.raises(pk.AsmError):
+        pk.Plan([p], chains=64, burnin=0, sweeps=8, precision="fp32", lanes_per_chain=16, roles=2)
+    plan = pk.Plan([p], chains=64, burnin=0, sweeps=8, precision="fp32", lanes_per_chain=16, roles=0)
+    assert plan.run().stats["roles"] == 1
+    plan.close()
+
+
 def test_tuner_picks_a_compiled_width_and_remembers_it(pk):
     p = workloads.small_problem(M=41, N=48, nblocks=3, seed=5)
     a = pk.Plan([p], chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, lanes_per_chain=0)
