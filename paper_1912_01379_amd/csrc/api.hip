@@ -79,7 +79,7 @@ struct asm_plan {
     int roles = 1;           // 2: the two-role sampler (sample32p.h)
     int64_t p_off_vwd = 0, p_off_d = 0, p_off_u = 0, p_off_vwz = 0, p_off_und = 0, p_off_unz = 0, p_off_h = 0;
     int64_t p_du_word = 0;
-    int32_t p_wd = 0, p_wu = 0, p_kd = 0;
+    int32_t p_wd = 0, p_wu = 0, p_kd = 0, p_zs = 0;
     bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
@@ -299,6 +299,7 @@ SampleArgs make_args(asm_plan *pl) {
     a.p_wd = pl->p_wd;
     a.p_wu = pl->p_wu;
     a.p_kd = pl->p_kd;
+    a.p_zs = pl->p_zs;
     return a;
 }
 
@@ -995,9 +996,21 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                       sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
             for (auto &pd : pl->probs) ok = ok && pd.B >= 2;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
-            int64_t zrows = 0;
-            for (auto &bd : pl->blocks) zrows = std::max(zrows, bd.nb + 2 - bd.kb);
-            const int64_t wd = (max_kb + 2) * rw, wu = (pl->chunk.d_len + max_kb * mp) / 4;
+            // zero modes the data role runs per block, balancing the two roles: a data move
+            // costs about kDataOverZero zero moves
+            constexpr double kDataOverZero = 4.8;
+            double zsum = 0.0;
+            for (auto &bd : pl->blocks) zsum += 0.5 * ((double)(bd.nb - bd.kb) - kDataOverZero * (double)bd.kb);
+            int64_t zs = (int64_t)std::lround(zsum / std::max<size_t>(1, pl->blocks.size()));
+            // the data role's rows (0..max k + zs + 1) must fit its prefetch registers
+            zs = std::max<int64_t>(0, std::min<int64_t>(zs, 256LL * pfr / rw - 2 - max_kb));
+            int64_t zrows = 0, ke_max = 0;
+            for (auto &bd : pl->blocks) {
+                const int64_t ke = std::min(bd.kb + zs, bd.nb);
+                ke_max = std::max(ke_max, ke);
+                zrows = std::max(zrows, bd.nb + 2 - ke);
+            }
+            const int64_t wd = (ke_max + 2) * rw, wu = (pl->chunk.d_len + max_kb * mp) / 4;
             ok = ok && wd <= 256LL * pfr && wu <= 256LL * pfu && zrows * rw <= 256LL * pfz;
             size_t off = 0;
             auto take = [&](size_t bytes) {
@@ -1009,7 +1022,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             pl->p_off_d = take((size_t)wu * 16);
             pl->p_off_u = pl->p_off_d + pl->chunk.d_len * (int64_t)sizeof(float);
             pl->p_off_vwz = take((size_t)zrows * rw * 16);
-            pl->p_kd = (int32_t)((max_kb + 3) / 4 * 4);
+            pl->p_kd = (int32_t)((ke_max + 3) / 4 * 4);
             pl->p_off_und = take((size_t)16 * pl->p_kd * sizeof(float));
             pl->p_off_unz = take((size_t)16 * row * sizeof(float));
             pl->p_off_h = take((size_t)2 * 16 * row * sizeof(float));
@@ -1020,6 +1033,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 pl->p_wd = (int32_t)wd;
                 pl->p_wu = (int32_t)wu;
                 pl->p_du_word = pl->chunk.rows * rw;
+                pl->p_zs = (int32_t)zs;
             } else if (o->roles == 2) {
                 rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, the (7, 13) instance, two blocks or "
                                       "more per problem and the staging areas in LDS");

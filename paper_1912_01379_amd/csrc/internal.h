@@ -107,7 +107,7 @@ struct SampleArgs {
     // of the d/U part, the data-role uniform row length
     int64_t p_off_vwd, p_off_d, p_off_u, p_off_vwz, p_off_und, p_off_unz, p_off_h;
     int64_t p_du_word;
-    int32_t p_wd, p_wu, p_kd, p_pad;
+    int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
 };
 
 // ------------------------------------------------------------------------------------

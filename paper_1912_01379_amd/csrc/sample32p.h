@@ -18,9 +18,10 @@
 // Stage t runs data step t and zero step t - 1; the two barriers of a stage separate the
 // staging writes from the moves.  A block's components are stored by the zero role at stage
 // j + 1 and loaded again by the data role at stage j + B, so problems need B >= 2.
-// Each role stages its own part of the block's packed chunk, prefetched into registers one
-// stage ahead: the data part (rows 0..max k + 1 of (V, w), the singular values and the U rows)
-// and the zero part (rows k_b..n_b + 1 of (V, w)).
+// The data role also runs the first z zero modes of its block (z = p_zs, chosen to balance
+// the two roles), the zero role the rest.  Each role stages its own part of the block's
+// packed chunk, prefetched into registers one stage ahead: the data part (rows 0..max k + z
+// + 1 of (V, w), the singular values and the U rows) and the zero part (rows k_b + z..n_b + 1).
 #pragma once
 
 #include "sample32.h"
@@ -37,6 +38,30 @@ struct AreasP {
     float *unz;    // zero-role uniforms, ROW per chain (indexed by mode)
     float *h;      // hand-off of A: two buffers of cpw rows of ROW
 };
+
+// Zero modes i0..i1-1, three per iteration, each row loaded two moves ahead; row i is at
+// rows + (i - i0) ROW, and the two rows past i1 - 1 are staged, loaded and never used.
+template <int L, int EPT>
+__device__ __forceinline__ void zero_moves_p(const float2 *rows, int i0, int i1, const float *urow, int lane,
+                                             float (&Ar)[EPT]) {
+    constexpr int ROW = EPT * L;
+    float2 vw[EPT], vb[EPT], vc[EPT];
+    load_row<EPT>(vw, rows, lane, L);
+    load_row<EPT>(vb, rows + ROW, lane, L);
+    int i = i0;
+    for (; i + 3 <= i1; i += 3) {
+        const float2 *rw = rows + (i - i0) * ROW;
+        load_row<EPT>(vc, rw + 2 * ROW, lane, L);
+        const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
+        zero_move<L, EPT>(vw, Ar, u0);
+        load_row<EPT>(vw, rw + 3 * ROW, lane, L);
+        zero_move<L, EPT>(vb, Ar, u1);
+        load_row<EPT>(vb, rw + 4 * ROW, lane, L);
+        zero_move<L, EPT>(vc, Ar, u2);
+    }
+    if (i < i1) zero_move<L, EPT>(vw, Ar, urow[i]);
+    if (i + 1 < i1) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
+}
 
 // Barrier with LDS ordering only: the stage's first barrier separates LDS readers from the
 // staging writes and needs no wait for global stores still in flight (the second barrier of
@@ -106,11 +131,12 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             const int b = (int)(t % B);
             const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
             const int nb = (int)bd.nb, kb = (int)bd.kb;
+            const int ke = min(kb + a.p_zs, nb);   // this role runs modes 0..ke-1
             barrier_lds();   // the previous stage's readers of the staging areas are done
             if (step) {
                 pfr.store(reinterpret_cast<float4 *>(ar.vwd), tid, 256, a.p_wd);
                 pfu.store(reinterpret_cast<float4 *>(ar.d), tid, 256, a.p_wu);
-                for (int g = lane; 4 * g < kb; g += L) {
+                for (int g = lane; 4 * g < ke; g += L) {
                     const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
                                               (uint32_t)g);
                     float *d = urow + 4 * g;
@@ -142,6 +168,7 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             float2 vw[EPT];
             load_row<EPT>(vw, ar.vwd, lane, L);
             data_moves<L, EPT, RPT, true>(kb, ar.vwd, ar.d, ar.u, urow, lane, vw, Ar, rr);
+            if (ke > kb) zero_moves_p<L, EPT>(ar.vwd + kb * ROW, kb, ke, urow, lane, Ar);
             float *h = ar.h + ((t & 1) * CPW + slotc) * ROW;
 #pragma unroll
             for (int t2 = 0; t2 < EPT; ++t2) h[lane + L * t2] = Ar[t2];
@@ -192,11 +219,12 @@ __device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &a
             const int64_t s = s0 + j / B;
             const int b = (int)(j % B);
             const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
-            const int nb = (int)bd.nb, kb = (int)bd.kb;
+            const int nb = (int)bd.nb;
+            const int kz = min((int)bd.kb + a.p_zs, nb);   // this role runs modes kz..nb-1
             barrier_lds();
             if (step) {
-                pfz.store(reinterpret_cast<float4 *>(ar.vwz), tid, 256, (nb + 2 - kb) * RW);
-                for (int g = kb / 4 + lane; 4 * g < nb; g += L) {
+                pfz.store(reinterpret_cast<float4 *>(ar.vwz), tid, 256, (nb + 2 - kz) * RW);
+                for (int g = kz / 4 + lane; 4 * g < nb; g += L) {
                     const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
                                               (uint32_t)g);
                     float *d = urow + 4 * g;
@@ -210,31 +238,15 @@ __device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &a
             if (t < total) {
                 // the zero part of step t, sampled at the next stage
                 const BlockDesc bn = cload(a.blocks + pd.off_blk + (int)(t % B));
-                pfz.load(a.F32 + bn.off_chunk + bn.kb * RW, tid, 256, (int)(bn.nb + 2 - bn.kb) * RW);
+                const int kn = min((int)bn.kb + a.p_zs, (int)bn.nb);
+                pfz.load(a.F32 + bn.off_chunk + kn * RW, tid, 256, ((int)bn.nb + 2 - kn) * RW);
             }
             if (!step) continue;
             float Ar[EPT];
             const float *h = ar.h + (((t - 1) & 1) * CPW + slotc) * ROW;
 #pragma unroll
             for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
-            // zero modes, three per iteration, each row loaded two moves ahead (the two rows
-            // past the block's last are staged, loaded and never used)
-            int i = kb;
-            float2 vw[EPT], vb[EPT], vc[EPT];
-            load_row<EPT>(vw, ar.vwz, lane, L);
-            load_row<EPT>(vb, ar.vwz + ROW, lane, L);
-            for (; i + 3 <= nb; i += 3) {
-                const float2 *rw = ar.vwz + (i - kb) * ROW;
-                load_row<EPT>(vc, rw + 2 * ROW, lane, L);
-                const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
-                zero_move<L, EPT>(vw, Ar, u0);
-                load_row<EPT>(vw, rw + 3 * ROW, lane, L);
-                zero_move<L, EPT>(vb, Ar, u1);
-                load_row<EPT>(vb, rw + 4 * ROW, lane, L);
-                zero_move<L, EPT>(vc, Ar, u2);
-            }
-            if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
-            if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
+            zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
 #pragma unroll
             for (int t2 = 0; t2 < EPT; ++t2) {
                 const int q = lane + L * t2;
