@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "tn32.h", "tn32_coef.h",
                    "rng_tn.h", "internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sample32_single_continuation_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_single_continuation_traffic.md")
 
 
 def lane_ops_per_sweep(M, blocks, s_tn=40, s_u=10):
@@ -58,11 +58,11 @@ def sampler_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sampler launch from the committed counter summary, if it was taken on
-    the current sampler sources (else None)."""
+def measured_traffic(kernel):
+    """HBM bytes per sampler launch from the committed counter summary of that kernel, if it
+    was taken on the current sampler sources (else None)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(kernel=kernel)) as f:
             for line in f:
                 line = line.strip()
                 if line.startswith("{") and '"sources"' in line:
@@ -247,7 +247,8 @@ def main():
     avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
     ops_per_launch = ops_sweep * args.chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
     achieved = ops_per_launch / avg_launch_s
-    tr = measured_traffic()
+    kernel = "k_sample32p" if st.get("roles", 1) == 2 else "k_sample32"
+    tr = measured_traffic(kernel)
     mean = res.mean.cpu().numpy()
     se = res.stderr.cpu().numpy()
     sd = res.post_sd.cpu().numpy()
@@ -278,12 +279,12 @@ def main():
                                "8 blocks x 100, k<=20, sigma=1e-4, fp32 chains, NNLS start",
                    "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps,
                    "vjp": want_vjp, "lanes_per_chain": st["lanes_per_chain"],
-                   "chains_per_workgroup": st["chains_per_block"],
+                   "chains_per_workgroup": st["chains_per_block"], "roles": st.get("roles", 1),
                    "data_modes_per_block": [k for _, k in blocks]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "lane-op/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
-                     "kernel": "k_sample32", "ops_per_chain_sweep": ops_sweep,
+                     "kernel": kernel, "ops_per_chain_sweep": ops_sweep,
                      "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
                      "launches_per_step": st["sampler_launches"]},
         "chain_sweeps_per_s": args.chains * sweeps_total * args.steps / elapsed,

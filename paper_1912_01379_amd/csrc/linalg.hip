@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
     const int64_t k_lo = K * split / ksplit, k_hi = K * (split + 1) / ksplit;
     const float *Rb = snapR + pd.off_sr;
     const float *Ab = snapA + pd.off_sa;
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     const int wm = wave / 2, wn = wave % 2;   // the wavefront's 32 x 64 sub-tile
     const int i = lane % 16, kk = lane / 16;
     d4 acc[2][4];
@@ -215,38 +215,60 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-    for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
-        const int64_t kc = (k_hi - c0) < kSnapKC ? (k_hi - c0) : kSnapKC;
-        __syncthreads();   // the previous chunk is consumed
-        // r rows: kc x 64 (columns past M, rows past kc: 0); one 16-byte word per thread
-        {
-            const int row = tid / (kSnapTM / 4), c4 = tid % (kSnapTM / 4);
-            const int64_t m = m0 + 4 * c4;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < kc && m < ldr) v = *reinterpret_cast<const float4 *>(Rb + (c0 + row) * ldr + m);
-            if (m + 0 >= M) v.x = 0.f;
-            if (m + 1 >= M) v.y = 0.f;
-            if (m + 2 >= M) v.z = 0.f;
-            if (m + 3 >= M) v.w = 0.f;
-            *reinterpret_cast<float4 *>(sr + row * kSnapTM + 4 * c4) = v;
+    // 16 x 16 sub-tiles entirely past M or N + 1 are skipped (wavefront-uniform)
+    const int64_t mw = m0 + 32 * wm, nw = n0 + 64 * wn;
+    // one 16-byte word of r and two of A per thread and chunk, loaded a chunk ahead
+    const int rrow = tid / (kSnapTM / 4), rc4 = tid % (kSnapTM / 4);
+    const int64_t rm = m0 + 4 * rc4;
+    auto load_r = [&](int64_t c0, int64_t kc) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (rrow < kc && rm < ldr) v = *reinterpret_cast<const float4 *>(Rb + (c0 + rrow) * ldr + rm);
+        if (rm + 0 >= M) v.x = 0.f;
+        if (rm + 1 >= M) v.y = 0.f;
+        if (rm + 2 >= M) v.z = 0.f;
+        if (rm + 3 >= M) v.w = 0.f;
+        return v;
+    };
+    auto load_a = [&](int64_t c0, int64_t kc, int h) {
+        const int e = tid + h * 256;
+        const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
+        const int64_t n = n0 + 4 * c4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < kc) {
+            if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + (c0 + row) * lda + n);
+            if (n + 0 >= N) v.x = (n + 0 == N) ? 1.f : 0.f;
+            if (n + 1 >= N) v.y = (n + 1 == N) ? 1.f : 0.f;
+            if (n + 2 >= N) v.z = (n + 2 == N) ? 1.f : 0.f;
+            if (n + 3 >= N) v.w = (n + 3 == N) ? 1.f : 0.f;
         }
-        // A rows with the column of ones at n = N: kc x 128; two words per thread
+        return v;
+    };
+    float4 pr, pa0, pa1;
+    {
+        const int64_t kc = (k_hi - k_lo) < kSnapKC ? (k_hi - k_lo) : kSnapKC;
+        pr = load_r(k_lo, kc);
+        pa0 = load_a(k_lo, kc, 0);
+        pa1 = load_a(k_lo, kc, 1);
+    }
+    for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
+        __syncthreads();   // the previous chunk is consumed
+        // r rows: kc x 64 (columns past M, rows past kc: 0); A rows with the column of ones
+        // at n = N: kc x 128
+        *reinterpret_cast<float4 *>(sr + rrow * kSnapTM + 4 * rc4) = pr;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int e = tid + h * 256;
             const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
-            const int64_t n = n0 + 4 * c4;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < kc) {
-                if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + (c0 + row) * lda + n);
-                if (n + 0 >= N) v.x = (n + 0 == N) ? 1.f : 0.f;
-                if (n + 1 >= N) v.y = (n + 1 == N) ? 1.f : 0.f;
-                if (n + 2 >= N) v.z = (n + 2 == N) ? 1.f : 0.f;
-                if (n + 3 >= N) v.w = (n + 3 == N) ? 1.f : 0.f;
-            }
-            *reinterpret_cast<float4 *>(sa + row * kSnapTN + 4 * c4) = v;
+            *reinterpret_cast<float4 *>(sa + row * kSnapTN + 4 * c4) = h == 0 ? pa0 : pa1;
         }
         __syncthreads();
+        if (c0 + kSnapKC < k_hi) {
+            const int64_t c1 = c0 + kSnapKC;
+            const int64_t kc = (k_hi - c1) < kSnapKC ? (k_hi - c1) : kSnapKC;
+            pr = load_r(c1, kc);
+            pa0 = load_a(c1, kc, 0);
+            pa1 = load_a(c1, kc, 1);
+        }
 #pragma unroll
         for (int k4 = 0; k4 < kSnapKC; k4 += 4) {
             const int row = k4 + kk;
@@ -259,7 +281,8 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
+                    if (mw + 16 * a < M && nw + 16 * b < N1)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
         }
     }
     double *X = cross + pd.off_cross + (int64_t)split * M * N1;
