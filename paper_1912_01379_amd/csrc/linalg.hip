@@ -199,9 +199,14 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
     const int64_t M = pd.M, N = pd.N, N1 = N + 1;
     const int64_t ldr = (M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
     const int64_t ntn = (N1 + kSnapTN - 1) / kSnapTN;
-    const int64_t tile = blockIdx.x;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so workgroup x runs on XCD
+    // x % 8; all tiles of one chain split then run on one XCD and read the split's snapshot
+    // rows through that XCD's L2 (ksplit is a multiple of 8)
+    const int64_t maxt = gridDim.x / ksplit;
+    const int64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int split = (int)(xcd + 8 * (j / maxt));
+    const int64_t tile = j % maxt;
     if (tile >= cross_snap_tiles(M, N)) return;
-    const int split = blockIdx.y;
     const int64_t m0 = (tile / ntn) * kSnapTM, n0 = (tile % ntn) * kSnapTN;
     const int64_t K = nsnap * pd.C;
     const int64_t k_lo = K * split / ksplit, k_hi = K * (split + 1) / ksplit;
@@ -300,7 +305,8 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
 
 hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
                              const float *snapA, const float *snapR, double *cross, hipStream_t s) {
-    hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(256), 0, s,
+    if (ksplit % 8 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)(max_tiles * ksplit), 1, (unsigned)P), dim3(256), 0, s,
                        probs_dev, ksplit, nsnap, snapA, snapR, cross);
     return hipGetLastError();
 }
