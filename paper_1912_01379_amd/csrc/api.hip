@@ -744,10 +744,15 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     if (o->want_vjp) {
         if (pl->fp32) {
-            // cross moments reduced by (tile, split) workgroups
-            // about 1024 workgroups, a multiple of 8 chain splits (one XCD per split group)
-            const int64_t want = (1024 + pl->max_snap_tiles - 1) / pl->max_snap_tiles;
-            pl->ksplit = (int)std::max<int64_t>(8, std::min<int64_t>(64, (want + 7) / 8 * 8));
+            // cross moments reduced by (tile, split) workgroups: four workgroups fit a CU at
+            // once, and about four such rounds over the chip (a multiple of 8 chain splits,
+            // one XCD per split group) keep the last round nearly full
+            int cus = 256, dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus = 256;
+            const int64_t want = 16LL * cus / std::max<int64_t>(1, pl->max_snap_tiles);
+            pl->ksplit = (int)std::max<int64_t>(8, std::min<int64_t>(256, want / 8 * 8));
         } else {
             // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
             const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
