@@ -969,8 +969,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             off += (size_t)cpw * row * sizeof(float);
             return off;
         };
-        // chains per workgroup: enough workgroups for every CU, at most 512 threads
-        int cpw = 512 / L;
+        // chains per workgroup: enough workgroups for every CU, at most 512 threads (256 for
+        // the prefetching instances, compiled for one wavefront per SIMD)
+        int cpw = (pf > 0 ? 256 : 512) / L;
         while (cpw > 64 / L) {
             const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
             if (layout(cpw, false) <= kLdsBudget && wgs >= max_cu) break;
@@ -999,7 +1000,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         // instance, the partitions (two blocks or more) and the staging areas allow it
         {
             int pe = 0, pr = 0, pfr = 0, pfu = 0, pfz = 0;
+            // (in automatic mode only with enough chains for a 16-chain workgroup per CU)
             bool ok = o->roles != 1 && L == 16 && pl->u_lds &&
+                      (o->roles == 2 || pl->total_chains >= 16LL * max_cu) &&
                       sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
             for (auto &pd : pl->probs) ok = ok && pd.B >= 2;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
@@ -1036,6 +1039,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             ok = ok && off <= kLdsBudget;
             if (ok) {
                 pl->roles = 2;
+                pl->chains_per_wg = 256 / L;   // the two-role kernel's workgroup: 16 chains
                 pl->lds32 = off;
                 pl->p_wd = (int32_t)wd;
                 pl->p_wu = (int32_t)wu;

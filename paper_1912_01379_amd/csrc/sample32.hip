@@ -33,7 +33,8 @@ hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt
     const int threads = lanes * chains_per_wg;
     if (threads % 64 != 0 || threads > 512) return hipErrorInvalidValue;
     // prefetching instances are compiled for at most 256 threads
-    if (a.prefetch && threads > 256) return hipErrorInvalidValue;
+    for (const Inst32 &c : kInst32)
+        if (c.L == lanes && c.EPT == ept && c.RPT == rpt && c.PF > 0 && threads > 256) return hipErrorInvalidValue;
     switch (lanes) {
     case 4: return launch_sample32_l4(a, ept, rpt, threads, grid, lds_bytes, s);
     case 8: return launch_sample32_l8(a, ept, rpt, threads, grid, lds_bytes, s);
