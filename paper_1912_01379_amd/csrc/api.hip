@@ -1008,7 +1008,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
             // zero modes the data role runs per block, balancing the two roles: a data move
             // costs about kDataOverZero zero moves
-            constexpr double kDataOverZero = 3.4;
+            constexpr double kDataOverZero = 2.6;
             double zsum = 0.0;
             for (auto &bd : pl->blocks) zsum += 0.5 * ((double)(bd.nb - bd.kb) - kDataOverZero * (double)bd.kb);
             int64_t zs = (int64_t)std::lround(zsum / std::max<size_t>(1, pl->blocks.size()));

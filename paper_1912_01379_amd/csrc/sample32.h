@@ -241,7 +241,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     float *sU = reinterpret_cast<float *>(smem32 + a.lds_off_u);
     float *sUnif = reinterpret_cast<float *>(smem32 + a.lds_off_unif);
     __shared__ int s_tile;
-    const int64_t s0 = *a.sweep;
+    const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
     const int64_t nsw = a.nsw;
     // the first sweep of the snapshot rows, for their reduction into the sums of A and A^2
     if (a.snapA && blockIdx.x == 0 && tid == 0) *a.snap_first = s0;

@@ -89,7 +89,7 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
     constexpr int CPW = 256 / L;
     const int lane = tid % L;
     const int slotc = tid / L;
-    const int64_t s0 = *a.sweep;
+    const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
     const int64_t nsw = a.nsw;
     Prefetch<PFR> pfr;
     Prefetch<PFU> pfu;
@@ -189,78 +189,109 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
     }
 }
 
-// Zero role: zero modes of block step t - 1 at stage t.
-template <int L, int EPT, int PFZ>
-__device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
+// The zero role's stages of one tile.  With DELAY (four blocks or more) the components of a
+// finished block are stored at the next stage, after its second barrier: a store issued at the
+// end of a stage would still be in flight at the next stage's waits for the prefetched rows,
+// which count it.  The data role reads a block again B stages after the zero role took it
+// (B - 1 with its one-stage-ahead load), so the delayed store still precedes that load by a
+// barrier when B >= 4; with two or three blocks the stores stay at the end of the stage.
+template <int L, int EPT, int PFZ, bool DELAY>
+__device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP &ar, const ProbDesc &pd,
+                                              int64_t chain, bool active, int tid, int64_t s0) {
     constexpr int ROW = EPT * L;
     constexpr int RW = ROW / 2;   // 16-byte words per (V, w) row
     constexpr int CPW = 256 / L;
     const int lane = tid % L;
     const int slotc = tid / L;
-    const int64_t s0 = *a.sweep;
-    const int64_t nsw = a.nsw;
+    const int64_t N = pd.N;
+    const int64_t NR = (N + 3) / 4 * 4;
+    const int B = (int)pd.B;
+    float *Ag = a.A32 + pd.off_A + chain * N;
+    const int64_t total = a.nsw * B;
+    float *urow = ar.unz + slotc * ROW;
     Prefetch<PFZ> pfz;
+    float Ap[EPT];                      // a finished block's components, stored at the next stage
+    int64_t p_n0 = 0, p_row = -1;
+    int p_nb = 0;
+    auto store_prev = [&]() {
+#pragma unroll
+        for (int t2 = 0; t2 < EPT; ++t2) {
+            const int q = lane + L * t2;
+            if (active && q < p_nb) Ag[p_n0 + q] = Ap[t2];
+        }
+        if (p_row >= 0) {
+            float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0;
+#pragma unroll
+            for (int t2 = 0; t2 < EPT; ++t2) {
+                const int q = lane + L * t2;
+                if (active && q < p_nb) sa[q] = Ap[t2];
+            }
+        }
+        p_nb = 0;
+        p_row = -1;
+    };
+    for (int64_t t = 0; t <= total; ++t) {
+        const bool step = t >= 1;
+        const int64_t j = step ? t - 1 : 0;
+        const int64_t s = s0 + j / B;
+        const int b = (int)(j % B);
+        const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
+        const int nb = (int)bd.nb;
+        const int kz = min((int)bd.kb + a.p_zs, nb);   // this role runs modes kz..nb-1
+        barrier_lds();
+        if (step) {
+            pfz.store(reinterpret_cast<float4 *>(ar.vwz), tid, 256, (nb + 2 - kz) * RW);
+            for (int g = kz / 4 + lane; 4 * g < nb; g += L) {
+                const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
+                                          (uint32_t)g);
+                float *d = urow + 4 * g;
+                d[0] = word_u32(w.x);
+                d[1] = word_u32(w.y);
+                d[2] = word_u32(w.z);
+                d[3] = word_u32(w.w);
+            }
+        }
+        __syncthreads();
+        if (t < total) {
+            // the zero part of step t, sampled at the next stage
+            const BlockDesc bn = cload(a.blocks + pd.off_blk + (int)(t % B));
+            const int kn = min((int)bn.kb + a.p_zs, (int)bn.nb);
+            pfz.load(a.F32 + bn.off_chunk + kn * RW, tid, 256, ((int)bn.nb + 2 - kn) * RW);
+        }
+        // after the loads: their address arithmetic may wait for earlier memory operations
+        if (DELAY) store_prev();
+        if (!step) continue;
+        float Ar[EPT];
+        const float *h = ar.h + (((t - 1) & 1) * CPW + slotc) * ROW;
+#pragma unroll
+        for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
+        zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
+#pragma unroll
+        for (int t2 = 0; t2 < EPT; ++t2) Ap[t2] = Ar[t2];
+        p_n0 = bd.n0;
+        p_nb = nb;
+        p_row = (a.snapA && s >= a.burnin) ? s - s0 : -1;
+        if (!DELAY) store_prev();
+    }
+    if (DELAY) store_prev();
+}
+
+// Zero role: zero modes of block step t - 1 at stage t.
+template <int L, int EPT, int PFZ>
+__device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
+    const int slotc = tid / L;
+    const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
     for (;;) {
         const int tile = next_tile_p(a, s_tile, tid + 256);
         if (tile < 0) break;
         const TileDesc td = cload(a.tiles + tile);
         const ProbDesc pd = cload(a.probs + td.problem);
-        const int64_t N = pd.N;
-        const int64_t NR = (N + 3) / 4 * 4;
-        const int B = (int)pd.B;
         const bool active = slotc < td.nchains;
         const int64_t chain = td.chain0 + (active ? slotc : 0);
-        float *Ag = a.A32 + pd.off_A + chain * N;
-        const int64_t total = nsw * B;
-        float *urow = ar.unz + slotc * ROW;
-        for (int64_t t = 0; t <= total; ++t) {
-            const bool step = t >= 1;
-            const int64_t j = step ? t - 1 : 0;
-            const int64_t s = s0 + j / B;
-            const int b = (int)(j % B);
-            const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
-            const int nb = (int)bd.nb;
-            const int kz = min((int)bd.kb + a.p_zs, nb);   // this role runs modes kz..nb-1
-            barrier_lds();
-            if (step) {
-                pfz.store(reinterpret_cast<float4 *>(ar.vwz), tid, 256, (nb + 2 - kz) * RW);
-                for (int g = kz / 4 + lane; 4 * g < nb; g += L) {
-                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b,
-                                              (uint32_t)g);
-                    float *d = urow + 4 * g;
-                    d[0] = word_u32(w.x);
-                    d[1] = word_u32(w.y);
-                    d[2] = word_u32(w.z);
-                    d[3] = word_u32(w.w);
-                }
-            }
-            __syncthreads();
-            if (t < total) {
-                // the zero part of step t, sampled at the next stage
-                const BlockDesc bn = cload(a.blocks + pd.off_blk + (int)(t % B));
-                const int kn = min((int)bn.kb + a.p_zs, (int)bn.nb);
-                pfz.load(a.F32 + bn.off_chunk + kn * RW, tid, 256, ((int)bn.nb + 2 - kn) * RW);
-            }
-            if (!step) continue;
-            float Ar[EPT];
-            const float *h = ar.h + (((t - 1) & 1) * CPW + slotc) * ROW;
-#pragma unroll
-            for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
-            zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
-#pragma unroll
-            for (int t2 = 0; t2 < EPT; ++t2) {
-                const int q = lane + L * t2;
-                if (active && q < nb) Ag[bd.n0 + q] = Ar[t2];
-            }
-            if (a.snapA && s >= a.burnin) {
-                float *sa = a.snapA + pd.off_sa + ((s - s0) * pd.C + chain) * NR + bd.n0;
-#pragma unroll
-                for (int t2 = 0; t2 < EPT; ++t2) {
-                    const int q = lane + L * t2;
-                    if (active && q < nb) sa[q] = Ar[t2];
-                }
-            }
-        }
+        if (pd.B >= 4)
+            zero_stages_p<L, EPT, PFZ, true>(a, ar, pd, chain, active, tid, s0);
+        else
+            zero_stages_p<L, EPT, PFZ, false>(a, ar, pd, chain, active, tid, s0);
     }
 }
 
@@ -276,7 +307,7 @@ __global__ __launch_bounds__(512) void k_sample32p(SampleArgs a) {
     ar.und = reinterpret_cast<float *>(smem32 + a.p_off_und);
     ar.unz = reinterpret_cast<float *>(smem32 + a.p_off_unz);
     ar.h = reinterpret_cast<float *>(smem32 + a.p_off_h);
-    if (a.snapA && blockIdx.x == 0 && threadIdx.x == 0) *a.snap_first = *a.sweep;
+    if (a.snapA && blockIdx.x == 0 && threadIdx.x == 0) *a.snap_first = cload(a.sweep);
     // the role is uniform per wavefront; the two branches hold disjoint live registers
     if (threadIdx.x < 256)
         data_role_p<L, EPT, RPT, PFR, PFU>(a, ar, &s_tile, (int)threadIdx.x);
