@@ -440,6 +440,26 @@ def test_two_roles_with_many_chains(pk):
     two.close()
 
 
+def test_two_roles_partial_tiles_and_mixed_problems(pk):
+    """Chain counts that leave partly filled 16-chain workgroups, and two problems of different
+    sizes in one plan: the two-role chains equal the one-role chains bit for bit."""
+    p1 = workloads.small_problem(M=101, N=200, nblocks=2, sigma=2e-3, seed=9)
+    p2 = workloads.small_problem(M=77, N=500, nblocks=5, sigma=5e-3, seed=10)
+    kw = dict(chains=201, burnin=16, sweeps=48, seed=13, precision="fp32", groups=32,
+              refresh_every=64, lanes_per_chain=16, start="nnls")
+    one = pk.Plan([p1, p2], roles=1, **kw)
+    two = pk.Plan([p1, p2], roles=2, **kw)
+    r1, r2 = one.run(), two.run()
+    assert r2.stats["roles"] == 2
+    for q in range(2):
+        A1, g1, _ = one.state(q)
+        A2, g2, _ = two.state(q)
+        assert np.array_equal(A1.cpu().numpy(), A2.cpu().numpy()), q
+        assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy()), q
+    one.close()
+    two.close()
+
+
 def test_two_roles_refuse_a_single_block(pk):
     p = workloads.small_problem(M=101, N=100, nblocks=1, sigma=2e-3, seed=9)
     with pytest.raises(pk.AsmError):
