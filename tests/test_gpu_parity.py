@@ -549,3 +549,58 @@ def test_batched_fp32_uneven_continuations_match_oracle(pk):
         off += p.N
     assert res.stats["graph_replays"] > 0
     plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# the paper's own test case: optical conductivity (Sec. II), efficiency of Fig. 3
+# --------------------------------------------------------------------------------------
+
+def _gpu_median_step(pk, p, sweeps=200, burnin=500, chains=128):
+    plan = pk.Plan([p], chains=chains, burnin=0, sweeps=8, seed=21, precision="fp32", groups=32,
+                   refresh_every=64, lanes_per_chain=16, start="nnls")
+    plan.advance(burnin)
+    prev = plan.state(0)[0].cpu().numpy()
+    steps = []
+    for _ in range(sweeps):
+        plan.advance(1)
+        cur = plan.state(0)[0].cpu().numpy()
+        steps.append(np.linalg.norm(cur - prev, axis=1) / np.linalg.norm(prev, axis=1))
+        prev = cur
+    plan.close()
+    return float(np.median(np.concatenate(steps)))
+
+
+def test_conductivity_step_sizes_order_as_in_fig3(pk, orc):
+    """Fig. 3 with the float32 sampler: median Delta_i over chains and sweeps for components,
+    modes and blocked modes (4 blocks) on the small- and large-cutoff grids, in the order the
+    paper states, and within a factor 1.5 of the oracle's medians (one chain, 2000 sweeps)."""
+    med = {}
+    for n in (40, 120):
+        for nb in (n, 1, 4):
+            p = workloads.optical_conductivity(n, nb)
+            g = _gpu_median_step(pk, p)
+            prep = orc.prepare(p)
+            r = orc.run(prep, chains=1, burnin=0, sweeps=2500, seed=5, groups=1, traj_chain=0,
+                        init=orc.nnls_start(prep), threads=1)
+            A = r.traj_A
+            o = float(np.median((np.linalg.norm(np.diff(A, axis=0), axis=1) / np.linalg.norm(A[:-1], axis=1))[500:]))
+            assert 1 / 1.5 < g / o < 1.5, (n, nb, g, o)
+            med[(n, nb)] = g
+    assert med[(40, 40)] < 0.2 * med[(40, 1)] and med[(40, 40)] < 0.2 * med[(40, 4)]
+    assert 0.3 < med[(40, 1)] / med[(40, 4)] < 3.0
+    assert med[(120, 1)] < med[(120, 120)] < 0.2 * med[(120, 4)]
+
+
+@pytest.mark.parametrize("n_omega", [40, 120])
+def test_conductivity_average_matches_oracle(pk, orc, n_omega):
+    """<A> of the float32 sampler (4 blocks) against an oracle run on the same problem (R17)."""
+    p = workloads.optical_conductivity(n_omega, 4)
+    prep = orc.prepare(p)
+    ores = orc.run(prep, chains=64, burnin=500, sweeps=2000, seed=3, groups=32,
+                   init=orc.nnls_start(prep))
+    plan = pk.Plan([p], chains=1024, burnin=500, sweeps=2000, seed=4, precision="fp32", groups=32,
+                   refresh_every=64, lanes_per_chain=0, start="nnls")
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
+    assert ok, info
+    plan.close()

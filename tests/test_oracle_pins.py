@@ -469,3 +469,48 @@ def test_unbounded_zero_mode_is_reported(orc):
     p = _problem(K, [0.0], 1.0, [0, 2])
     res = orc.run(orc.prepare(p), chains=1, sweeps=2, groups=1)
     assert res.status == -4
+
+
+# --------------------------------------------------------------------------------------
+# the paper's own test case (Sec. II) and its efficiency comparison (Fig. 3)
+# --------------------------------------------------------------------------------------
+
+def test_conductivity_workload_sum_rule_and_kernel():
+    """Pi(i omega_0) is the sum rule (2/pi) int sigma (Eq. (optcond) at omega_m = 0): the
+    generator's fine-grid data against adaptive quadrature of Eq. (model); the kernel's first
+    row is (2/pi) times the grid weights."""
+    p = workloads.optical_conductivity(40, 4, sigma_rel=0.0)
+    total, _ = integrate.quad(lambda x: workloads.conductivity_model(np.array([x]))[0], 0.0, np.inf,
+                              limit=400)
+    assert abs(p.G[0] - 2.0 / math.pi * total) < 1e-7 * p.G[0]
+    wm1 = 2.0 * math.pi / 15.0
+    f = lambda x: (2.0 / math.pi) * x * x / (wm1 * wm1 + x * x) * workloads.conductivity_model(np.array([x]))[0]
+    v1, _ = integrate.quad(f, 0.0, np.inf, limit=400)
+    assert abs(p.G[1] - v1) < 1e-7 * p.G[1]
+    assert np.allclose(p.K[0], 2.0 / math.pi * 0.1, rtol=1e-15)
+    assert np.all(np.diff(p.G) < 0)
+
+
+def _median_step(orc, n, nblocks, sweeps=2500, skip=500):
+    p = workloads.optical_conductivity(n, nblocks)
+    prep = orc.prepare(p)
+    r = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, seed=5, groups=1, traj_chain=0,
+                init=orc.nnls_start(prep), threads=1)
+    A = r.traj_A
+    d = np.linalg.norm(np.diff(A, axis=0), axis=1) / np.linalg.norm(A[:-1], axis=1)
+    return float(np.median(d[skip:]))
+
+
+def test_step_sizes_order_as_in_fig3(orc):
+    """Fig. 3 / Sec. IV.D, on the optical-conductivity test case with accurate data: with the
+    small cutoff (40 points) modes and blocked modes take comparable steps and components
+    exceedingly small ones; with the large cutoff (120 points, the tail on the grid) the steps of
+    modes sampling collapse, below those of components, while blocked modes keep moving.
+    Delta_i = |f(i+1) - f(i)| / |f(i)| per sweep, median over one chain's sweeps; blocked modes
+    here use one fixed partition of 4 blocks."""
+    c40, m40, b40 = (_median_step(orc, 40, nb) for nb in (40, 1, 4))
+    c120, m120, b120 = (_median_step(orc, 120, nb) for nb in (120, 1, 4))
+    assert c40 < 0.2 * m40 and c40 < 0.2 * b40
+    assert 0.3 < m40 / b40 < 3.0
+    assert m120 < c120 < 0.2 * b120
+    assert m120 < 0.01 * b120

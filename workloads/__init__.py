@@ -242,6 +242,48 @@ def config5(seed: int = BASE_SEED + 5) -> Problem:
                    name="cfg5-large")
 
 
+# --------------------------------------------------------------------------------------
+# the paper's own test case (Sec. II): the optical conductivity from bosonic Matsubara data
+# --------------------------------------------------------------------------------------
+
+def conductivity_model(omega: np.ndarray, model: int = 1) -> np.ndarray:
+    """sigma(omega) of Eq. (model): a Drude peak (weight 0.3, width 0.3 for model 1, 0.6 for
+    model 2) and two peaks of weight 0.2 and width 1.2 at +-3, cut off by 1/(1 + (w/4)^6)."""
+    ge, w0, w1, g1, e1 = 4.0, 0.3, 0.2, 1.2, 3.0
+    g0 = 0.3 if model == 1 else 0.6
+    peaks = (w0 / (1.0 + (omega / g0) ** 2) + w1 / (1.0 + ((omega + e1) / g1) ** 2)
+             + w1 / (1.0 + ((omega - e1) / g1) ** 2))
+    return peaks / (1.0 + (omega / ge) ** 6)
+
+
+def bosonic_kernel(omega_m: np.ndarray, omega: np.ndarray) -> np.ndarray:
+    """K(i omega_m, omega) = (2/pi) omega^2 / (omega_m^2 + omega^2) of Eq. (optcond)."""
+    w2 = omega[None, :] ** 2
+    return (2.0 / np.pi) * w2 / (omega_m[:, None] ** 2 + w2)
+
+
+def optical_conductivity(n_omega: int = 40, nblocks: int = 4, model: int = 1,
+                         sigma_rel: float = 1e-3, beta: float = 15.0, n_matsubara: int = 60,
+                         seed: int = BASE_SEED + 6) -> Problem:
+    """The test case of Sec. II and Fig. 3: Pi(i omega_m) of Eq. (optcond) at the first 60
+    bosonic Matsubara frequencies (beta = 15) from sigma(omega) of Eq. (model), with relative
+    Gaussian noise of standard deviation sigma_rel; the grid is omega_n = 0.1 (n - 1/2),
+    n = 1..n_omega (40: small cutoff, 120: large), split into nblocks equal blocks (1: modes
+    sampling, n_omega: components sampling).  The data come from the continuous integral
+    (a fine mid-point rule up to omega = 400), not from the grid."""
+    wm = 2.0 * np.pi * np.arange(n_matsubara) / beta
+    x = 0.1 * (np.arange(1, n_omega + 1) - 0.5)
+    w = np.full(n_omega, 0.1)
+    K = bosonic_kernel(wm, x) * w[None, :]
+    xf = (np.arange(400000) + 0.5) * 1e-3
+    pi_exact = bosonic_kernel(wm, xf) @ (conductivity_model(xf, model) * 1e-3)
+    rng = np.random.default_rng(seed)
+    sig = sigma_rel * np.abs(pi_exact)
+    G = pi_exact + sig * rng.standard_normal(n_matsubara)
+    return Problem(K=K, G=G, sigma=sig, omega=x, weights=w, block_start=equal_blocks(n_omega, nblocks),
+                   k=None, A_true=conductivity_model(x, model), name=f"optcond-{n_omega}-{nblocks}")
+
+
 def small_problem(M: int = 41, N: int = 24, nblocks: int = 2, sigma: float = 1e-3,
                   beta: float = 10.0, seed: int = BASE_SEED + 7, k=None) -> Problem:
     """A small version of the cfg-1 problem used by parity tests (several blocks)."""
