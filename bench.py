@@ -168,6 +168,53 @@ def batched(args):
     print(json.dumps(out))
 
 
+def conductivity(args):
+    """The paper's own test case (optical conductivity, bosonic kernel, Sec. II) on both grids
+    of Fig. 3 (40 and 120 points) with components, modes and blocked-modes (4 blocks)
+    sampling: mode-moves/s, ESS/s and the median step size Delta_i of Fig. 3."""
+    import torch
+    import workloads
+    import paper_1912_01379_amd as pk
+    dev = torch.device("cuda:0")
+    rows = {}
+    for n in (40, 120):
+        for name, nb in (("components", n), ("modes", 1), ("blocked4", 4)):
+            p = workloads.optical_conductivity(n, nb)
+            dp = _DevProblem(p, dev)
+            plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2026,
+                           precision="fp32", refresh_every=64, groups=32, lanes_per_chain=args.lanes,
+                           start="nnls", use_graph=True, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = plan.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            se, sd = res.stderr.cpu().numpy(), res.post_sd.cpu().numpy()
+            ess = (sd / se) ** 2
+            prev = plan.state(0)[0].cpu().numpy()
+            steps = []
+            for _ in range(50):
+                plan.advance(1)
+                cur = plan.state(0)[0].cpu().numpy()
+                steps.append(np.linalg.norm(cur - prev, axis=1) / np.linalg.norm(prev, axis=1))
+                prev = cur
+            plan.close()
+            rows[f"N{n}_{name}"] = {
+                "mode_moves_per_s": args.chains * (args.burnin + args.sweeps) * n / dt,
+                "ess_per_s_min": float(np.nanmin(ess)) / dt, "ess_per_s_median": float(np.nanmedian(ess)) / dt,
+                "median_step": float(np.median(np.concatenate(steps))),
+                "lanes_per_chain": res.stats["lanes_per_chain"], "roles": res.stats["roles"]}
+            print(f"{n} {name} done", file=sys.stderr, flush=True)
+    main_row = rows["N120_blocked4"]
+    print(json.dumps({"metric": "mode-moves/s", "value": main_row["mode_moves_per_s"], "unit": "mode-moves/s",
+                      "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "optical conductivity (Sec. II): 60 bosonic Matsubara points, "
+                                             "beta 15, relative noise 1e-3, grids of 40 and 120 points",
+                                 "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps},
+                      "cases": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,7 +227,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "conductivity"], default="single")
     ap.add_argument("--graph", action="store_true", help="replay refresh cycles from a hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -191,6 +238,9 @@ def main():
         return
     if args.workload == "batched":
         batched(args)
+        return
+    if args.workload == "conductivity":
+        conductivity(args)
         return
 
     import torch
