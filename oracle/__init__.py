@@ -58,9 +58,10 @@ def build(force: bool = False) -> str:
 
 class _Problem(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("B", ctypes.c_int64),
-                ("Kt", ctypes.c_void_p), ("gt", ctypes.c_void_p), ("bstart", ctypes.c_void_p),
-                ("kb", ctypes.c_void_p), ("d", ctypes.c_void_p), ("U", ctypes.c_void_p),
-                ("V", ctypes.c_void_p)]
+                ("Kt", ctypes.c_void_p), ("gt", ctypes.c_void_p), ("bn0", ctypes.c_void_p),
+                ("bnb", ctypes.c_void_p), ("L", ctypes.c_int64), ("lfirst", ctypes.c_void_p),
+                ("lcount", ctypes.c_void_p), ("kb", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -95,6 +96,8 @@ def lib():
             L.orc_Mk.argtypes = [ctypes.c_int, ctypes.c_double]
             L.orc_move_uniform.restype = ctypes.c_double
             L.orc_move_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_int64] * 5
+            L.orc_sweep_level.restype = ctypes.c_int64
+            L.orc_sweep_level.argtypes = [ctypes.c_uint64] + [ctypes.c_int64] * 3
             L.orc_philox.restype = None
             L.orc_philox.argtypes = [ctypes.c_void_p] * 3
             L.orc_run.restype = ctypes.c_int
@@ -133,6 +136,11 @@ def move_uniform(seed, problem, chain, sweep, block, mode) -> float:
     return lib().orc_move_uniform(int(seed) & 0xFFFFFFFFFFFFFFFF, problem, chain, sweep, block, mode)
 
 
+def sweep_level(seed, problem, sweep, levels) -> int:
+    """The hierarchy level sampled in a sweep (shared by all chains of the problem)."""
+    return int(lib().orc_sweep_level(int(seed) & 0xFFFFFFFFFFFFFFFF, problem, sweep, levels))
+
+
 def philox(ctr, key):
     c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
     k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
@@ -149,8 +157,8 @@ def philox(ctr, key):
 class Prepared:
     Kt: np.ndarray            # M x N
     gt: np.ndarray            # M
-    bstart: np.ndarray        # B+1
-    kb: np.ndarray            # B (int32)
+    levels: list              # partitions of the hierarchy, each B_l+1 offsets
+    kb: np.ndarray            # B (int32), blocks of all levels in order
     d: list                   # per block: singular values of the data modes
     U: list                   # per block: M x kb
     V: list                   # per block: Nb x Nb (columns = modes, data first)
@@ -168,7 +176,19 @@ class Prepared:
 
     @property
     def B(self):
-        return int(len(self.bstart) - 1)
+        return int(sum(len(ls) - 1 for ls in self.levels))
+
+    @property
+    def bstart(self):
+        """The offsets of a single partition."""
+        if len(self.levels) != 1:
+            raise ValueError("a hierarchy has one partition per level")
+        return self.levels[0]
+
+    @property
+    def blocks(self):
+        """(first grid point, size) of every block, level after level."""
+        return [(int(ls[b]), int(ls[b + 1] - ls[b])) for ls in self.levels for b in range(len(ls) - 1)]
 
 
 def whiten(K, G, sigma=None, cov=None):
@@ -253,15 +273,40 @@ def nnls_start(prep: Prepared, blend: float = 0.01) -> np.ndarray:
     return (1.0 - blend) * x + blend * cstar
 
 
+def hierarchy(N: int, max_block: int = 0) -> list:
+    """The hierarchy of partitions of Fig. 2 (Sec. IV.C), top level first.
+
+    Level l splits the grid into intervals of width w = N / 2^l (one block at l = 0, two
+    halves at l = 1); on the even levels l >= 2 the intervals are shifted by w / 2, so that
+    the end blocks have half the width and the centre of the grid is not a boundary.  The
+    boundaries are floor(N (2j + s) / 2^(l+1)), s = 1 on shifted levels.  The blocked
+    levels run while w >= 2; the last level is the single grid points (components).
+    Levels with a block longer than max_block (> 0) are left out.
+    """
+    N = int(N)
+    out = []
+    lvl = 0
+    while N >= 2 ** (lvl + 1):           # w = N / 2^l >= 2
+        shift = 1 if lvl >= 2 and lvl % 2 == 0 else 0
+        inner = [N * (2 * j + shift) // 2 ** (lvl + 1) for j in range(2 ** lvl + 1)]
+        out.append(np.asarray([0] + [c for c in inner if 0 < c < N] + [N], np.int64))
+        lvl += 1
+    out.append(np.arange(N + 1, dtype=np.int64))
+    if max_block > 0:
+        out = [ls for ls in out if int(np.max(np.diff(ls))) <= max_block]
+    return out
+
+
 def prepare(problem, k=None) -> Prepared:
     """Whitening + block factors + start vector for one workloads.Problem."""
     Kt, gt, Tt = whiten(problem.K, problem.G, problem.sigma, problem.cov)
-    bs = np.asarray(problem.block_start, dtype=np.int64)
+    levels = problem.partitions()
+    spans = [(int(ls[b]), int(ls[b + 1])) for ls in levels for b in range(len(ls) - 1)]
     kreq = k if k is not None else problem.k
     ds, Us, Vs, dall = [], [], [], []
     kb = []
-    for b in range(len(bs) - 1):
-        Kb = Kt[:, bs[b]:bs[b + 1]]
+    for b, (s0, s1) in enumerate(spans):
+        Kb = Kt[:, s0:s1]
         kr = None if kreq is None else int(np.asarray(kreq)[b])
         d, U, V, sv = block_factors(Kb, kr)
         ds.append(d); Us.append(U); Vs.append(V); dall.append(sv)
@@ -271,7 +316,7 @@ def prepare(problem, k=None) -> Prepared:
     if not (cstar > 0.0 and np.isfinite(cstar)):
         cstar = 1.0
     init = np.full(Kt.shape[1], cstar)
-    return Prepared(Kt=np.ascontiguousarray(Kt), gt=np.ascontiguousarray(gt), bstart=bs,
+    return Prepared(Kt=np.ascontiguousarray(Kt), gt=np.ascontiguousarray(gt), levels=levels,
                     kb=np.asarray(kb, dtype=np.int32), d=ds, U=Us, V=Vs, dall=dall, Tt=Tt,
                     init=init)
 
@@ -311,7 +356,10 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
     d_all = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x in prep.d]) if sum(prep.kb) else np.zeros(1))
     U_all = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float64).ravel() for u in prep.U]) if sum(prep.kb) else np.zeros(1))
     V_all = np.ascontiguousarray(np.concatenate([np.asarray(v, np.float64).ravel() for v in prep.V]))
-    bstart = np.ascontiguousarray(prep.bstart, dtype=np.int64)
+    bn0 = np.ascontiguousarray([b[0] for b in prep.blocks], dtype=np.int64)
+    bnb = np.ascontiguousarray([b[1] for b in prep.blocks], dtype=np.int64)
+    lcount = np.ascontiguousarray([len(ls) - 1 for ls in prep.levels], dtype=np.int64)
+    lfirst = np.ascontiguousarray(np.concatenate([[0], np.cumsum(lcount)[:-1]]), dtype=np.int64)
     kb = np.ascontiguousarray(prep.kb, dtype=np.int32)
     start = np.ascontiguousarray(prep.init if init is None else np.asarray(init, np.float64))
     G = int(groups)
@@ -325,7 +373,8 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
         drift_max=np.zeros(1), n_frozen=np.zeros(1, np.int64), n_clamped=np.zeros(1, np.int64),
         status=np.zeros(1, np.int32))
     p = _Problem(M=M, N=N, B=B, Kt=prep.Kt.ctypes.data, gt=prep.gt.ctypes.data,
-                 bstart=bstart.ctypes.data, kb=kb.ctypes.data, d=d_all.ctypes.data,
+                 bn0=bn0.ctypes.data, bnb=bnb.ctypes.data, L=len(prep.levels),
+                 lfirst=lfirst.ctypes.data, lcount=lcount.ctypes.data, kb=kb.ctypes.data, d=d_all.ctypes.data,
                  U=U_all.ctypes.data, V=V_all.ctypes.data)
     o = _Options(chains=chains, burnin=burnin, sweeps=sweeps, seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
                  problem_index=problem_index, refresh_every=refresh_every, groups=G,

@@ -23,6 +23,10 @@
  *   - components that round below zero after a move are set to +0;
  *   - modes of a block are visited in the order given (data modes by descending
  *     singular value, then the zero modes), blocks in increasing order;
+ *   - with a hierarchy of partitions (Fig. 2, Sec. IV.C), every sweep samples all blocks of
+ *     one level, the same for all chains, chosen by Philox on the counter
+ *     (2^32 - 1, sweep, 0, 2): level = floor(w0 L / 2^32); the uniforms of a move keep the
+ *     block's index within its level;
  *   - the residual is recomputed from scratch every `refresh_every` sweeps.
  */
 #include <math.h>
@@ -64,6 +68,17 @@ static void philox4x32_10(const uint32_t in[4], const uint32_t key[2], uint32_t 
 static double u01_from_words(uint32_t w0, uint32_t w1) {
     uint64_t j = ((uint64_t)(w0 >> 6) << 26) | (uint64_t)(w1 >> 6);
     return ((double)j + 0.5) * 0x1.0p-52;
+}
+
+/* The hierarchy level of a sweep, shared by all chains of the problem. */
+static int64_t sweep_level(uint64_t seed, int64_t problem, int64_t sweep, int64_t L) {
+    if (L <= 1) return 0;
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu),
+                       (uint32_t)(seed >> 32) ^ (uint32_t)problem};
+    uint32_t ctr[4] = {0xffffffffu, (uint32_t)sweep, 0u, 2u};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    return (int64_t)(((uint64_t)w[0] * (uint64_t)L) >> 32);
 }
 
 static double move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
@@ -248,6 +263,9 @@ double orc_Mk(int k, double z) { return Mk(k, z); }
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
     philox4x32_10(ctr, key, out);
 }
+int64_t orc_sweep_level(uint64_t seed, int64_t problem, int64_t sweep, int64_t L) {
+    return sweep_level(seed, problem, sweep, L);
+}
 double orc_move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
                         int64_t block, int64_t mode) {
     return move_uniform(seed, problem, chain, sweep, block, mode);
@@ -257,10 +275,14 @@ double orc_move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t s
 /* The sampler.                                                                         */
 /* ------------------------------------------------------------------------------------ */
 typedef struct {
-    int64_t M, N, B;
+    int64_t M, N, B;        /* B: blocks of all levels together                          */
     const double *Kt;       /* M x N whitened kernel, row-major                          */
     const double *gt;       /* M whitened data                                           */
-    const int64_t *bstart;  /* B+1 block offsets                                         */
+    const int64_t *bn0;     /* B first grid points                                       */
+    const int64_t *bnb;     /* B block sizes                                             */
+    int64_t L;              /* levels of the hierarchy (1: one partition)                */
+    const int64_t *lfirst;  /* L: first block of each level                              */
+    const int64_t *lcount;  /* L: blocks of each level                                   */
     const int32_t *kb;      /* data modes per block                                      */
     const double *d;        /* concatenated data singular values (sum kb)                */
     const double *U;        /* concatenated U_b, each M x kb row-major                   */
@@ -336,7 +358,7 @@ static void *run_chains(void *arg) {
     int64_t *offV = (int64_t *)malloc(sizeof(int64_t) * (B + 1));
     offd[0] = offU[0] = offV[0] = 0;
     for (int64_t b = 0; b < B; ++b) {
-        int64_t nb = p->bstart[b + 1] - p->bstart[b];
+        int64_t nb = p->bnb[b];
         offd[b + 1] = offd[b] + p->kb[b];
         offU[b + 1] = offU[b] + M * p->kb[b];
         offV[b + 1] = offV[b] + nb * nb;
@@ -347,12 +369,14 @@ static void *run_chains(void *arg) {
         double chi2;
         refresh(p, A, r, &chi2);
         for (int64_t s = 0; s < total; ++s) {
-            for (int64_t b = 0; b < B; ++b) {
-                const int64_t n0 = p->bstart[b], nb = p->bstart[b + 1] - n0;
-                const int64_t kb = p->kb[b];
-                const double *Vb = p->V + offV[b];
-                const double *Ub = p->U + offU[b];
-                const double *db = p->d + offd[b];
+            const int64_t lvl = sweep_level(o->seed, o->problem_index, s, p->L);
+            for (int64_t b = 0; b < p->lcount[lvl]; ++b) {
+                const int64_t gb = p->lfirst[lvl] + b;   /* the block among all levels */
+                const int64_t n0 = p->bn0[gb], nb = p->bnb[gb];
+                const int64_t kb = p->kb[gb];
+                const double *Vb = p->V + offV[gb];
+                const double *Ub = p->U + offU[gb];
+                const double *db = p->d + offd[gb];
                 for (int64_t i = 0; i < nb; ++i) {
                     /* Eq. (modeLimits): f + delta V_i >= 0 */
                     double lo = -INFINITY, hi = INFINITY;

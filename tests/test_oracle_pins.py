@@ -217,6 +217,91 @@ def test_sum_rule_only_data_gives_flat_default(orc):
         assert np.allclose(res.post_sd, math.sqrt(EA2 - EA * EA), rtol=0.03)
 
 
+def test_sum_rule_only_data_with_a_hierarchy(orc):
+    """The same closed form as above, sampled with the hierarchy of Fig. 2 on 8 points (one
+    block, halves, the shifted quarters, the components; a random level per sweep)."""
+    N, sig = 8, 0.3
+    ws = lambda S, p: S ** (N - 1 + p) * math.exp(-0.5 * ((S - 1.0) / sig) ** 2)
+    Z = integrate.quad(lambda S: ws(S, 0), 0, 10)[0]
+    EA = integrate.quad(lambda S: ws(S, 1), 0, 10)[0] / Z / N
+    EA2 = integrate.quad(lambda S: ws(S, 2), 0, 10)[0] / Z * 2.0 / (N * (N + 1))
+    p = _problem(np.ones((1, N)), [1.0], sig, [0, N])
+    p.levels = orc.hierarchy(N)
+    prep = orc.prepare(p)
+    assert prep.B == 1 + 2 + 5 + 8 and list(prep.kb) == [1] * prep.B
+    res = orc.run(prep, chains=16, burnin=200, sweeps=20000, groups=16)
+    assert _within(res.mean, res.stderr, EA) < 4.5, (res.mean, EA)
+    assert np.allclose(res.post_sd, math.sqrt(EA2 - EA * EA), rtol=0.03)
+
+
+def test_hierarchy_partitions_of_fig2(orc):
+    """Fig. 2: one block on top, halves below it, the intervals shifted by half their width on
+    every other level (so that the grid centre is no boundary there), the single points at the
+    bottom.  8 points worked by hand; general N checked for the structure."""
+    h = orc.hierarchy(8)
+    assert [list(x) for x in h] == [[0, 8], [0, 4, 8], [0, 1, 3, 5, 7, 8], list(range(9))]
+    for N in (2, 3, 7, 40, 120, 800, 1000):
+        h = orc.hierarchy(N)
+        assert list(h[0]) == [0, N] and list(h[-1]) == list(range(N + 1))
+        for lvl, cuts in enumerate(h[:-1]):
+            assert cuts[0] == 0 and cuts[-1] == N and np.all(np.diff(cuts) > 0)
+            w = N / 2 ** lvl
+            assert w >= 2
+            sizes = np.diff(cuts)
+            if lvl >= 2 and lvl % 2 == 0:       # shifted: two half-width end blocks
+                assert len(sizes) == 2 ** lvl + 1
+                assert abs(sizes[0] - w / 2) < 1 and abs(sizes[-1] - w / 2) < 1
+                assert np.all(np.abs(sizes[1:-1] - w) < 1)
+                assert N % 2 or N // 2 not in set(cuts.tolist())
+            else:
+                assert len(sizes) == 2 ** lvl and np.all(np.abs(sizes - w) < 1)
+        # below the top, no boundary is shared by every blocked level
+        inner = [set(c[1:-1].tolist()) for c in h[1:-1]]
+        if len(inner) >= 2:
+            assert not set.intersection(*inner)
+        assert N < 4 or 2 ** len(h[:-1]) > N // 2   # the blocked levels reach width < 4
+    # levels with a block above the limit are left out
+    assert [len(x) - 1 for x in orc.hierarchy(800, max_block=128)] == [8, 17, 32, 65, 128, 257, 800]
+
+
+def test_hierarchy_levels_are_uniform_and_shared(orc):
+    """Sec. IV.C: each sweep samples one level chosen at random; the choice is uniform over the
+    levels, and differs between problems (keyed like the moves)."""
+    L, S = 7, 28000
+    lv = np.array([orc.sweep_level(11, 0, s, L) for s in range(S)])
+    assert lv.min() == 0 and lv.max() == L - 1
+    counts = np.bincount(lv, minlength=L)
+    chi2 = float(np.sum((counts - S / L) ** 2 / (S / L)))
+    assert chi2 < stats.chi2.ppf(0.9999, L - 1), counts
+    # consecutive sweeps are independent: pairs are uniform over L^2 cells
+    pairs = np.bincount(lv[:-1] * L + lv[1:], minlength=L * L)
+    chi2p = float(np.sum((pairs - (S - 1) / L ** 2) ** 2 / ((S - 1) / L ** 2)))
+    assert chi2p < stats.chi2.ppf(0.9999, L * L - 1)
+    other = np.array([orc.sweep_level(11, 1, s, L) for s in range(2000)])
+    assert np.mean(other == lv[:2000]) < 0.25
+    assert all(orc.sweep_level(11, 0, s, 1) == 0 for s in range(50))
+
+
+def test_hierarchy_keys_moves_by_the_block_within_its_level(orc):
+    """Two levels holding the same partition sample exactly as that partition alone: the
+    random numbers of a move depend on the block's index within its level, and the factors
+    come from the level's own blocks."""
+    p = workloads.small_problem(M=21, N=12, nblocks=3)
+    prep1 = orc.prepare(p)
+    p.levels = [p.block_start, p.block_start]
+    prep2 = orc.prepare(p)
+    assert prep2.B == 2 * prep1.B
+    r1 = orc.run(prep1, chains=3, burnin=0, sweeps=60, groups=3, traj_chain=1)
+    r2 = orc.run(prep2, chains=3, burnin=0, sweeps=60, groups=3, traj_chain=1)
+    assert np.array_equal(r1.traj_A, r2.traj_A) and np.array_equal(r1.final_r, r2.final_r)
+    # a different second level changes exactly the sweeps that pick it
+    p.levels = [p.block_start, np.array([0, 5, 12])]
+    r3 = orc.run(orc.prepare(p), chains=3, burnin=0, sweeps=60, groups=3, traj_chain=1)
+    first = next(s for s in range(60) if orc.sweep_level(1234, 0, s, 2) == 1)
+    assert np.array_equal(r3.traj_A[:first], r1.traj_A[:first])
+    assert not np.array_equal(r3.traj_A[first], r1.traj_A[first])
+
+
 def _quad_mean_2d(K, G):
     """<A> over A >= 0 for N = 2 by quadrature (inner integral in closed form)."""
     k1, k2 = K[:, 0], K[:, 1]
@@ -514,3 +599,25 @@ def test_step_sizes_order_as_in_fig3(orc):
     assert 0.3 < m40 / b40 < 3.0
     assert m120 < c120 < 0.2 * b120
     assert m120 < 0.01 * b120
+
+
+def test_hierarchy_steps_as_in_fig3(orc):
+    """Fig. 3 with the paper's own blocked modes, a random level of the Fig. 2 hierarchy per
+    sweep: large steps on both grids, far above components (40 points) and modes (120
+    points); the sweeps on the top level (modes of the full grid) and the bottom level
+    (components) take the small steps the paper remarks on."""
+    for n, small in ((40, 0.0075), (120, 0.0092)):
+        p = workloads.optical_conductivity(n, 1)
+        p.levels = orc.hierarchy(n)
+        prep = orc.prepare(p)
+        r = orc.run(prep, chains=1, burnin=0, sweeps=2500, seed=5, groups=1, traj_chain=0,
+                    init=orc.nnls_start(prep), threads=1)
+        A = r.traj_A
+        d = np.linalg.norm(np.diff(A, axis=0), axis=1) / np.linalg.norm(A[:-1], axis=1)
+        lv = np.array([orc.sweep_level(5, 0, s, len(prep.levels)) for s in range(1, 2500)])
+        med = float(np.median(d[500:]))
+        assert med > 10 * small, (n, med)
+        lv = lv[500:]                     # d[i]: the move of sweep i + 1
+        mid = np.median(d[500:][(lv > 0) & (lv < len(prep.levels) - 1)])
+        ends = np.median(d[500:][(lv == 0) | (lv == len(prep.levels) - 1)])
+        assert ends < 0.5 * mid, (n, ends, mid)

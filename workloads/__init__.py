@@ -123,6 +123,14 @@ class Problem:
     k: Optional[np.ndarray] = None      # requested data modes per block (None -> numerical rank)
     A_true: Optional[np.ndarray] = None
     name: str = ""
+    levels: Optional[list] = None       # a hierarchy of partitions (each B_l+1 offsets), used
+                                        # instead of block_start when given; k then covers the
+                                        # blocks of all levels in order
+
+    def partitions(self) -> list:
+        if self.levels is not None:
+            return [np.asarray(ls, np.int64) for ls in self.levels]
+        return [np.asarray(self.block_start, np.int64)]
 
     @property
     def M(self) -> int:
@@ -134,7 +142,7 @@ class Problem:
 
     @property
     def B(self) -> int:
-        return int(len(self.block_start) - 1)
+        return int(sum(len(ls) - 1 for ls in self.partitions()))
 
 
 def _finish(K, A_true, rng, sigma=None, cov_len=None, **kw) -> Problem:
