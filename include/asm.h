@@ -66,21 +66,31 @@ typedef struct {
     const double *cov;           /* device, M x M symmetric positive definite covariance C,
                                     whitened with its Cholesky factor (Sec. IV after
                                     Eq. (chi2)); NULL when sigma is given                    */
-    int64_t B;                   /* number of blocks of the grid partition (Sec. IV.C)        */
-    const int64_t *block_start;  /* host, B+1 offsets 0 = s_0 < s_1 < ... < s_B = N           */
+    int64_t B;                   /* number of blocks of the grid partition (Sec. IV.C); with a
+                                    hierarchy (levels > 1), of all its partitions together    */
+    const int64_t *block_start;  /* host, B+1 offsets 0 = s_0 < s_1 < ... < s_B = N; with a
+                                    hierarchy, the partitions one after another, each with its
+                                    own B_l+1 offsets from 0 to N (B + levels entries)        */
     const int32_t *k;            /* host, B: largest number of data modes per block, or NULL;
                                     a block uses min(k_b, numerical rank) data modes (singular
                                     values above max(M, N_b) * 2^-52 * d_1); the remaining
                                     modes of the block are its zero modes, d := 0 (Sec. IV.B) */
     const double *init;          /* device, N start model >= 0 shared by all chains, or NULL
                                     for the best constant fit (K~1).g~/|K~1|^2               */
+    int64_t levels;              /* partitions of a hierarchy (Fig. 2, Sec. IV.C); 0 or 1: the
+                                    single partition block_start.  With L > 1 levels every
+                                    sweep samples all blocks of one level, the same for all
+                                    chains of the problem: level floor(w_0 L / 2^32) of the
+                                    Philox words of counter (2^32 - 1, sweep, 0, 2); the moves
+                                    are keyed by the block's index within its level           */
+    const int64_t *level_blocks; /* host, levels: B_l per level (sum = B); NULL when levels <= 1 */
 } asm_problem;
 
 typedef struct {
     int64_t chains;              /* chains per problem (>= 1)                                */
     int64_t burnin;              /* sweeps discarded before averaging                        */
     int64_t sweeps;              /* sweeps averaged; one sweep moves every mode of every block
-                                    once, blocks in increasing order                         */
+                                    (of the sweep's level) once, blocks in increasing order  */
     uint64_t seed;               /* Philox4x32-10 key = (seed_lo, seed_hi ^ problem index)    */
     int32_t precision;           /* ASM_FP64 or ASM_FP32                                      */
     int32_t refresh_every;       /* sweeps between float64 recomputations of the residual
@@ -95,7 +105,8 @@ typedef struct {
     int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
                                     or ASM_START_NNLS                                        */
     int32_t roles;               /* ASM_FP32 with 16 lanes per chain: 0 = two roles when the
-                                    problems allow it (every problem of two blocks or more),
+                                    problems allow it (every problem of two blocks or more,
+                                    no hierarchy),
                                     1 = one role, 2 = two roles (ASM_EINVAL if not allowed).
                                     Two roles run the data modes of block b + 1 beside the
                                     zero modes of block b, which act on disjoint state (the
@@ -187,6 +198,19 @@ int asm_tn_draw(const double *c, const double *d, const double *lo, const double
    float64.  Errors: ASM_EINVAL, ASM_EHIP. */
 int asm_uniforms(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep0, int64_t nsweeps,
                  int64_t nblocks, int64_t nmodes, double *out, void *hip_stream);
+
+/* The hierarchy of partitions of Fig. 2 (Sec. IV.C) for N grid points, top level first:
+   level l splits the grid into intervals of width w = N / 2^l (one block, then halves, ...),
+   shifted by w / 2 on the even levels l >= 2 (so that the grid centre is not a boundary
+   there); the boundaries are floor(N (2j + s) / 2^(l+1)), s = 1 on shifted levels, the
+   blocked levels run while w >= 2, and the last level is the single points (components
+   sampling).  Levels with a block longer than max_block (> 0) are left out.  Host code only
+   (no GPU call).  Writes *levels and *n_starts (= B + levels); level_blocks (host, >= 64
+   entries) and starts (host, >= *n_starts entries) may be NULL to query the sizes, and
+   are filled in the layout of asm_problem.level_blocks and block_start.
+   Errors: ASM_EINVAL (N < 1 or N > 2^24). */
+int asm_hierarchy(int64_t N, int64_t max_block, int64_t *levels, int64_t *n_starts,
+                  int64_t *level_blocks, int64_t *starts);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *asm_last_error(void);

@@ -24,7 +24,7 @@ ASM_START_FLAT, ASM_START_NNLS = 0, 1
 
 EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_advance", "asm_plan_state",
             "asm_plan_factors", "asm_plan_whitened", "asm_plan_destroy", "asm_tn_draw",
-            "asm_uniforms", "asm_last_error", "asm_version"]
+            "asm_uniforms", "asm_hierarchy", "asm_last_error", "asm_version"]
 
 
 class AsmError(RuntimeError):
@@ -37,7 +37,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_void_p),
                 ("G", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("cov", ctypes.c_void_p),
                 ("B", ctypes.c_int64), ("block_start", ctypes.c_void_p), ("k", ctypes.c_void_p),
-                ("init", ctypes.c_void_p)]
+                ("init", ctypes.c_void_p), ("levels", ctypes.c_int64), ("level_blocks", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -80,6 +80,7 @@ def _load():
     L.asm_plan_destroy.argtypes = [vp]
     L.asm_tn_draw.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp]
     L.asm_uniforms.argtypes = [ctypes.c_uint64, i64, i64, i64, i64, i64, i64, vp, vp]
+    L.asm_hierarchy.argtypes = [i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp]
     for name in EXPORTED:
         if name not in ("asm_last_error", "asm_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -129,7 +130,8 @@ class Plan:
     """A set of continuation problems with their chains, living on one GPU.
 
     problems: sequence of objects with K (M x N), G (M), sigma (M) or cov (M x M),
-    block_start (B+1), optional k (B) and init (N); numpy arrays or tensors.
+    block_start (B+1) or levels (a list of such partitions: a hierarchy, see hierarchy()),
+    optional k (B, over the blocks of all levels) and init (N); numpy arrays or tensors.
     """
 
     def __init__(self, problems, chains=256, burnin=100, sweeps=1000, seed=1234, precision="fp32",
@@ -149,16 +151,21 @@ class Plan:
             if cov is not None:
                 sig = None
             init = _dev(getattr(p, "init", None), self.device)
-            bs = np.ascontiguousarray(np.asarray(p.block_start, dtype=np.int64))
+            lv = getattr(p, "levels", None)
+            parts = [np.asarray(x, dtype=np.int64) for x in lv] if lv is not None else \
+                [np.asarray(p.block_start, dtype=np.int64)]
+            bs = np.ascontiguousarray(np.concatenate(parts))
+            lb = np.ascontiguousarray([len(x) - 1 for x in parts], dtype=np.int64)
             kk = getattr(p, "k", None)
             kk = None if kk is None else np.ascontiguousarray(np.asarray(kk, dtype=np.int32))
-            self._keep += [K, G, sig, cov, init, bs, kk]
+            self._keep += [K, G, sig, cov, init, bs, lb, kk]
             M, N = int(K.shape[0]), int(K.shape[1])
             self.M.append(M)
             self.N.append(N)
             probs[i] = _Problem(M=M, N=N, K=_ptr(K), G=_ptr(G), sigma=_ptr(sig), cov=_ptr(cov),
-                                B=len(bs) - 1, block_start=bs.ctypes.data,
-                                k=None if kk is None else kk.ctypes.data, init=_ptr(init))
+                                B=int(lb.sum()), block_start=bs.ctypes.data,
+                                k=None if kk is None else kk.ctypes.data, init=_ptr(init),
+                                levels=len(parts), level_blocks=lb.ctypes.data if len(parts) > 1 else None)
         self.options = _Options(chains=int(chains), burnin=int(burnin), sweeps=int(sweeps),
                                 seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=int(precision),
                                 refresh_every=int(refresh_every), want_vjp=int(bool(want_vjp)),
@@ -239,6 +246,22 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(_lib.asm_plan_whitened(self.handle, problem, Kt.data_ptr(), gt.data_ptr()))
         return Kt, gt
+
+
+def hierarchy(N: int, max_block: int = 0) -> list:
+    """The library's hierarchy of partitions (Fig. 2) for N grid points: a list of block
+    offset arrays, top level (one block) first, single points last (asm_hierarchy)."""
+    nl, ns = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.asm_hierarchy(int(N), int(max_block), ctypes.byref(nl), ctypes.byref(ns), None, None))
+    lb = np.zeros(max(64, nl.value), np.int64)
+    st = np.zeros(ns.value, np.int64)
+    _check(_lib.asm_hierarchy(int(N), int(max_block), ctypes.byref(nl), ctypes.byref(ns),
+                              lb.ctypes.data, st.ctypes.data))
+    out, at = [], 0
+    for b in lb[:nl.value]:
+        out.append(st[at:at + int(b) + 1].copy())
+        at += int(b) + 1
+    return out
 
 
 def tn_draw(c, d, lo, hi, u, precision="fp64", device="cuda:0"):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "rng_tn.h"
 
 using namespace asmk;
 
@@ -86,6 +87,9 @@ struct asm_plan {
     int lanes = 16, chains_per_wg = 16, grid32 = 0;
     size_t lds32 = 0, lds64 = 0;
     bool any_cov = false;
+    bool any_levels = false;   // a problem with a hierarchy of partitions
+    std::vector<int32_t> lvl;  // level table (pairs: first block of the problem's, count)
+    int32_t *d_lvl = nullptr;
     bool ran = false;
     int64_t sweep = 0;      // absolute sweep counter (host mirror)
     std::vector<void *> allocs;
@@ -145,6 +149,46 @@ int dalloc(asm_plan *pl, T **out, size_t count) {
         if (rc_ != ASM_OK) return rc_; \
     } while (0)
 
+// The blocks of a problem, level after level, and the levels' block ranges.
+struct Partition {
+    std::vector<int64_t> n0, nb;          // per block (all levels)
+    std::vector<int32_t> lfirst, lcount;  // per level
+};
+
+int parse_partition(const asm_problem &q, int64_t p, Partition *out) {
+    out->n0.clear();
+    out->nb.clear();
+    out->lfirst.clear();
+    out->lcount.clear();
+    if (q.levels < 0 || q.levels > 64) return fail(ASM_EINVAL, "problem %lld: levels must be in [0, 64]", (long long)p);
+    const int64_t L = q.levels > 1 ? q.levels : 1;
+    if (L > 1 && !q.level_blocks) return fail(ASM_EINVAL, "problem %lld: level_blocks is required with levels > 1", (long long)p);
+    if (q.B < 1 || !q.block_start) return fail(ASM_EINVAL, "problem %lld: need B >= 1 blocks", (long long)p);
+    if (q.B > 65535) return fail(ASM_EINVAL, "problem %lld: more than 65535 blocks", (long long)p);
+    int64_t at = 0, total = 0;
+    for (int64_t l = 0; l < L; ++l) {
+        const int64_t Bl = L > 1 ? q.level_blocks[l] : q.B;
+        if (Bl < 1 || total + Bl > q.B)
+            return fail(ASM_EINVAL, "problem %lld: level_blocks must be >= 1 and sum to B", (long long)p);
+        const int64_t *cut = q.block_start + at;
+        if (cut[0] != 0 || cut[Bl] != q.N)
+            return fail(ASM_EINVAL, "problem %lld: block_start must run from 0 to N (level %lld)", (long long)p, (long long)l);
+        out->lfirst.push_back((int32_t)total);
+        out->lcount.push_back((int32_t)Bl);
+        for (int64_t b = 0; b < Bl; ++b) {
+            const int64_t nb = cut[b + 1] - cut[b];
+            if (nb < 1) return fail(ASM_EINVAL, "problem %lld: blocks must be non-empty and increasing", (long long)p);
+            if (nb > 65535) return fail(ASM_EINVAL, "problem %lld: block larger than 65535", (long long)p);
+            out->n0.push_back(cut[b]);
+            out->nb.push_back(nb);
+        }
+        at += Bl + 1;
+        total += Bl;
+    }
+    if (total != q.B) return fail(ASM_EINVAL, "problem %lld: level_blocks must sum to B", (long long)p);
+    return ASM_OK;
+}
+
 int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
     if (!pr || n < 1) return fail(ASM_EINVAL, "need at least one problem");
     if (!o) return fail(ASM_EINVAL, "options are required");
@@ -168,16 +212,10 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
         if (!q.K || !q.G) return fail(ASM_EINVAL, "problem %lld: K and G are required", (long long)p);
         if ((q.sigma == nullptr) == (q.cov == nullptr))
             return fail(ASM_EINVAL, "problem %lld: give exactly one of sigma and cov", (long long)p);
-        if (q.B < 1 || !q.block_start) return fail(ASM_EINVAL, "problem %lld: need B >= 1 blocks", (long long)p);
-        if (q.block_start[0] != 0 || q.block_start[q.B] != q.N)
-            return fail(ASM_EINVAL, "problem %lld: block_start must run from 0 to N", (long long)p);
-        for (int64_t b = 0; b < q.B; ++b) {
-            const int64_t nb = q.block_start[b + 1] - q.block_start[b];
-            if (nb < 1) return fail(ASM_EINVAL, "problem %lld: blocks must be non-empty and increasing", (long long)p);
-            if (nb > 65535) return fail(ASM_EINVAL, "problem %lld: block larger than 65535", (long long)p);
+        Partition part;
+        TRY(parse_partition(q, p, &part));
+        for (int64_t b = 0; b < q.B; ++b)
             if (q.k && q.k[b] < 0) return fail(ASM_EINVAL, "problem %lld: k must be >= 0", (long long)p);
-        }
-        if (q.B > 65535) return fail(ASM_EINVAL, "problem %lld: more than 65535 blocks", (long long)p);
     }
     return ASM_OK;
 }
@@ -300,6 +338,8 @@ SampleArgs make_args(asm_plan *pl) {
     a.p_wu = pl->p_wu;
     a.p_kd = pl->p_kd;
     a.p_zs = pl->p_zs;
+    a.lvl = pl->d_lvl;
+    a.stage_exact = pl->any_levels ? 1 : 0;
     return a;
 }
 
@@ -514,10 +554,14 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
     for (int64_t p = 0; p < n; ++p) {
         key += "|" + std::to_string(pr[p].M) + "," + std::to_string(pr[p].N) + "," + (pr[p].cov ? "c" : "s");
         max_m = std::max(max_m, pr[p].M);
+        Partition part;
+        TRY(parse_partition(pr[p], p, &part));
+        key += ";" + std::to_string(part.lcount.size());
         for (int64_t b = 0; b < pr[p].B; ++b) {
-            const int64_t nb = pr[p].block_start[b + 1] - pr[p].block_start[b];
+            const int64_t nb = part.nb[b];
             max_nb = std::max(max_nb, nb);
-            key += "," + std::to_string(nb) + ":" + std::to_string(pr[p].k ? pr[p].k[b] : -1);
+            key += "," + std::to_string(part.n0[b]) + "+" + std::to_string(nb) + ":" +
+                   std::to_string(pr[p].k ? pr[p].k[b] : -1);
         }
     }
     {
@@ -580,6 +624,49 @@ extern "C" {
 const char *asm_last_error(void) { return g_err.c_str(); }
 
 int asm_version(void) { return 100; }
+
+int asm_hierarchy(int64_t N, int64_t max_block, int64_t *levels, int64_t *n_starts, int64_t *level_blocks,
+                  int64_t *starts) {
+    g_err.clear();
+    if (!levels || !n_starts) return fail(ASM_EINVAL, "levels and n_starts are required");
+    if (N < 1 || N > (1LL << 24)) return fail(ASM_EINVAL, "N must be in [1, 2^24]");
+    int64_t nl = 0, ns = 0;
+    // one level: its cuts (0 < c < N) in increasing order, then N
+    auto emit = [&](const std::vector<int64_t> &cuts) {
+        int64_t widest = 0, prev = 0;
+        for (int64_t c : cuts) {
+            widest = std::max(widest, c - prev);
+            prev = c;
+        }
+        if (max_block > 0 && widest > max_block) return;
+        if (level_blocks) level_blocks[nl] = (int64_t)cuts.size();
+        if (starts) {
+            starts[ns] = 0;
+            for (size_t j = 0; j < cuts.size(); ++j) starts[ns + 1 + (int64_t)j] = cuts[j];
+        }
+        ns += (int64_t)cuts.size() + 1;
+        ++nl;
+    };
+    std::vector<int64_t> cuts;
+    for (int l = 0; (N >> (l + 1)) >= 1 && l < 62; ++l) {   // width N / 2^l >= 2
+        const int64_t den = 1LL << (l + 1);
+        const int64_t shift = (l >= 2 && l % 2 == 0) ? 1 : 0;   // every other level, by half a width
+        cuts.clear();
+        for (int64_t j = 0;; ++j) {
+            const int64_t c = (N * (2 * j + shift)) / den;   // N <= 2^24 and 2j + 1 <= 2N + 1
+            if (c >= N) break;
+            if (c > 0) cuts.push_back(c);
+        }
+        cuts.push_back(N);
+        emit(cuts);
+    }
+    cuts.clear();
+    for (int64_t c = 1; c <= N; ++c) cuts.push_back(c);   // the single points
+    emit(cuts);
+    *levels = nl;
+    *n_starts = ns;
+    return ASM_OK;
+}
 
 int asm_plan_destroy(asm_plan *pl) {
     if (!pl) return ASM_OK;
@@ -678,10 +765,19 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pd.has_cov = q.cov != nullptr;
         pd.index = (uint32_t)p;
         pl->any_cov |= pd.has_cov;
+        Partition part;
+        STEP(parse_partition(q, p, &part));
+        pd.levels = (int64_t)part.lcount.size();
+        pd.off_lvl = (int64_t)pl->lvl.size() / 2;
+        for (size_t l = 0; l < part.lcount.size(); ++l) {
+            pl->lvl.push_back(part.lfirst[l]);
+            pl->lvl.push_back(part.lcount[l]);
+        }
+        pl->any_levels |= pd.levels > 1;
         for (int64_t b = 0; b < q.B; ++b) {
             BlockDesc bd{};
-            bd.n0 = q.block_start[b];
-            bd.nb = q.block_start[b + 1] - q.block_start[b];
+            bd.n0 = part.n0[b];
+            bd.nb = part.nb[b];
             const int64_t kmax = std::min(q.M, bd.nb);
             bd.off_V = offV;
             bd.off_U = offU;
@@ -994,8 +1090,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
         STEP(dalloc(pl, &pl->F32, pl->blocks.size() * pl->chunk.words));
         // the next block's chunk is prefetched into registers when it fits the instance's
-        // per-thread budget
-        pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw) ? 1 : 0;
+        // per-thread budget (not with a hierarchy, whose blocks are staged to their own size)
+        pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw && !pl->any_levels) ? 1 : 0;
         // two roles (data modes of the next block beside the zero modes of this one) when the
         // instance, the partitions (two blocks or more) and the staging areas allow it
         {
@@ -1004,7 +1100,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             bool ok = o->roles != 1 && L == 16 && pl->u_lds &&
                       (o->roles == 2 || pl->total_chains >= 16LL * max_cu) &&
                       sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
-            for (auto &pd : pl->probs) ok = ok && pd.B >= 2;
+            for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
             // zero modes the data role runs per block, balancing the two roles: a data move
             // costs about kDataOverZero zero moves
@@ -1047,7 +1143,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 pl->p_zs = (int32_t)zs;
             } else if (o->roles == 2) {
                 rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, the (7, 13) instance, two blocks or "
-                                      "more per problem and the staging areas in LDS");
+                                      "more per problem, no hierarchy and the staging areas in LDS");
                 return rc;
             }
         }
@@ -1084,6 +1180,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     // ---- device tables ----
     STEP(dalloc(pl, &pl->d_probs, pl->probs.size()));
     STEP(dalloc(pl, &pl->d_blocks, pl->blocks.size()));
+    STEP(dalloc(pl, &pl->d_lvl, pl->lvl.size()));
+    HSTEP(hipMemcpyAsync(pl->d_lvl, pl->lvl.data(), pl->lvl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HSTEP(hipMemcpyAsync(pl->d_probs, pl->probs.data(), pl->probs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
     HSTEP(hipMemcpyAsync(pl->d_blocks, pl->blocks.data(), pl->blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
     HSTEP(hipMemcpyAsync(blockM_d, blockM.data(), blockM.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -1162,6 +1260,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         HIPCHK(hipMemsetAsync(pl->cross, 0, crossn * sizeof(double), st));
     }
     HIPCHK(hipEventRecord(pl->ev[2], st));
+    const int64_t run_first = pl->sweep;
     const int64_t burnin_abs = pl->sweep + pl->opt.burnin;
     pl->timing = true;
     pl->tev_used = 0;
@@ -1189,10 +1288,21 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         HIPCHK(hipEventElapsedTime(&ms, pl->ev[2], pl->ev[3]));
         stats->sample_ms = ms;
         double mm = 0, dm = 0;
+        const int64_t nsw = pl->opt.burnin + pl->opt.sweeps;
         for (auto &pd : pl->probs) {
-            mm += (double)pd.C * (double)(pl->opt.burnin + pl->opt.sweeps) * (double)pd.N;
-            for (int64_t b = 0; b < pd.B; ++b)
-                dm += (double)pd.C * (double)(pl->opt.burnin + pl->opt.sweeps) * (double)pl->blocks[pd.off_blk + b].kb;
+            mm += (double)pd.C * (double)nsw * (double)pd.N;
+            // data modes per sweep of each level, and the levels the run's sweeps sampled
+            std::vector<double> kbl(pd.levels, 0.0);
+            for (int64_t l = 0; l < pd.levels; ++l) {
+                const int32_t f = pl->lvl[2 * (pd.off_lvl + l)], c = pl->lvl[2 * (pd.off_lvl + l) + 1];
+                for (int32_t b = f; b < f + c; ++b) kbl[l] += (double)pl->blocks[pd.off_blk + b].kb;
+            }
+            if (pd.levels == 1) {
+                dm += (double)pd.C * (double)nsw * kbl[0];
+            } else {
+                for (int64_t s = run_first; s < run_first + nsw; ++s)
+                    dm += (double)pd.C * kbl[sweep_level(pl->opt.seed, pd.index, (uint32_t)s, (uint32_t)pd.levels)];
+            }
         }
         stats->mode_moves = mm;
         stats->data_moves = dm;

@@ -35,6 +35,8 @@ struct ProbDesc {
     int32_t pad;
     int64_t off_sa;           // float32 snapshots of A (sweep, chain) rows of round4(N) floats
     int64_t off_sr;           // float32 snapshots of r rows of round4(M) floats
+    int64_t levels;           // partitions of the hierarchy (1: one partition of B blocks)
+    int64_t off_lvl;          // first level in the level table (pairs: first block, count)
 };
 
 struct BlockDesc {
@@ -108,6 +110,10 @@ struct SampleArgs {
     int64_t p_off_vwd, p_off_d, p_off_u, p_off_vwz, p_off_und, p_off_unz, p_off_h;
     int64_t p_du_word;
     int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
+    const int32_t *lvl;       // level table: (first block relative to the problem's, count)
+    int32_t stage_exact;      // 1: stage only the rows, singular values and U rows of the block
+                              //    (blocks of very different sizes, as in a hierarchy)
+    int32_t pad2;
 };
 
 // ------------------------------------------------------------------------------------

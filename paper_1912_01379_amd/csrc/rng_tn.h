@@ -24,7 +24,7 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+__host__ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32 x 32 -> 64-bit product per multiplier gives both halves
@@ -49,6 +49,15 @@ __device__ __forceinline__ double move_u64(uint64_t seed, uint32_t problem, uint
     U4 o = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32) ^ problem);
     const uint64_t j = ((uint64_t)(o.x >> 6) << 26) | (uint64_t)(o.y >> 6);
     return ((double)j + 0.5) * 0x1.0p-52;
+}
+
+// the hierarchy level sampled in a sweep, the same for every chain of the problem (tag 2 in
+// the last word, chain field 2^32 - 1): floor(w0 L / 2^32), uniform over the L levels
+__host__ __device__ __forceinline__ uint32_t sweep_level(uint64_t seed, uint32_t problem, uint32_t sweep,
+                                                         uint32_t levels) {
+    const U4 c{0xFFFFFFFFu, sweep, 0u, 2u};
+    const U4 o = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32) ^ problem);
+    return (uint32_t)(((uint64_t)o.x * levels) >> 32);
 }
 
 // float32 uniforms: one Philox call serves four consecutive modes (tag 1 in the last word)

@@ -1,6 +1,9 @@
 // The two samplers of blocked modes sampling (Sec. IV.B-C).
 //
-// One move of mode i of block b (data modes, d_i > 0, first; then the zero modes):
+// A sweep moves every mode of every block of one partition, blocks in increasing order; with
+// a hierarchy of partitions (Fig. 2) the partition is the sweep's level, drawn for all chains
+// of the problem at once.  One move of mode i of block b (data modes, d_i > 0, first; then
+// the zero modes):
 //   1. interval of the step delta along V_i that keeps the block non-negative,
 //      Eq. (modeLimits): lo = max_{V_qi>0} -A_q/V_qi, hi = min_{V_qi<0} -A_q/V_qi;
 //   2. a uniform number of the counter-based generator keyed by (chain, sweep, b, i);
@@ -60,8 +63,16 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
     __syncthreads();
     const int64_t s0 = *a.sweep;
     for (int64_t s = s0; s < s0 + a.nsw; ++s) {
-        for (int64_t b = 0; b < pd.B; ++b) {
-            const BlockDesc bd = a.blocks[pd.off_blk + b];
+        // the sweep's level of the hierarchy (Fig. 2): its blocks are [lf, lf + lc); the
+        // moves are keyed by the block's index within the level
+        int64_t lf = 0, lc = pd.B;
+        if (pd.levels > 1) {
+            const int64_t l = sweep_level(a.seed, pd.index, (uint32_t)s, (uint32_t)pd.levels);
+            lf = a.lvl[2 * (pd.off_lvl + l)];
+            lc = a.lvl[2 * (pd.off_lvl + l) + 1];
+        }
+        for (int64_t b = 0; b < lc; ++b) {
+            const BlockDesc bd = a.blocks[pd.off_blk + lf + b];
             const int64_t nb = bd.nb, kb = bd.kb;
             const double *V = a.V64 + bd.off_V;
             const double *U = a.U64 + bd.off_U;

@@ -180,6 +180,19 @@ __device__ __forceinline__ void stage_sync(float4 *dst, const float4 *src, int n
     for (; i < n; i += nthr) dst[i] = src[i];
 }
 
+// Stage only what a block of nb points and kb data modes reads: its nb + 2 (V, w) rows (two
+// spare rows are read ahead), its singular values and its U rows (when staged); for blocks of
+// very different sizes, as in a hierarchy of partitions, where the chunk is sized for the
+// largest.
+__device__ __forceinline__ void stage_block(float4 *dst, const float4 *src, int nb, int kb, int row,
+                                            int mp, int64_t off_d, int64_t off_u, int u_lds, int tid,
+                                            int nthr) {
+    stage_sync(dst, src, (nb + 2) * row / 2, tid, nthr);
+    const int wd = (int)(off_d / 16), wu = (int)(off_u / 16);
+    stage_sync(dst + wd, src + wd, (kb + 3) / 4, tid, nthr);
+    if (u_lds) stage_sync(dst + wu, src + wu, kb * mp / 4, tid, nthr);
+}
+
 // The prefetch registers: PF words per thread, addressed with constant indices only (a fold
 // over an index sequence instead of a loop) and of the compiler's native vector type, so that
 // they stay in registers.
@@ -271,12 +284,28 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         float *urow = sUnif + slotc * ROW;
         const int nw = (int)a.chunk_words;
         float4 *stage = reinterpret_cast<float4 *>(smem32);
-        if (prefetch) pf.load(a.F32 + cload(a.blocks + pd.off_blk).off_chunk, tid, nthr, nw);
-        // components of the next block to sample, loaded one block ahead (blocks are disjoint,
-        // so sampling a block leaves the next one's components unchanged)
+        // the blocks of a sweep: all of the partition, or of the sweep's level of a hierarchy
+        // (Fig. 2), drawn for all chains of the problem at once
+        const int NL = (int)pd.levels;
+        auto level_of = [&](int64_t s, int &lf, int &lc) {
+            lf = 0;
+            lc = (int)pd.B;
+            if (NL > 1) {
+                const uint32_t l = sweep_level(a.seed, pd.index, (uint32_t)s, (uint32_t)NL);
+                const int2 e = cload(reinterpret_cast<const int2 *>(a.lvl) + pd.off_lvl + l);
+                lf = e.x;
+                lc = e.y;
+            }
+        };
+        int lf, lc;
+        level_of(s0, lf, lc);
+        if (prefetch) pf.load(a.F32 + cload(a.blocks + pd.off_blk + lf).off_chunk, tid, nthr, nw);
+        // components of the next block to sample, loaded one block ahead (the blocks of a
+        // partition are disjoint, so sampling a block leaves the next one's components
+        // unchanged; where a hierarchy's next level overlaps, they are loaded again below)
         float An[EPT];
         {
-            const BlockDesc b0 = cload(a.blocks + pd.off_blk);
+            const BlockDesc b0 = cload(a.blocks + pd.off_blk + lf);
 #pragma unroll
             for (int t = 0; t < EPT; ++t) An[t] = Ag[b0.n0 + min(lane + L * t, (int)b0.nb - 1)];
             // wait for them here (once per tile): the block loop then starts with no load of
@@ -307,8 +336,10 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         };
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
-            for (int64_t b = 0; b < pd.B; ++b) {
-                const BlockDesc bd = cload(a.blocks + pd.off_blk + b);
+            int nf, nc;   // the next sweep's level
+            level_of(s + 1, nf, nc);
+            for (int64_t b = 0; b < lc; ++b) {
+                const BlockDesc bd = cload(a.blocks + pd.off_blk + lf + b);
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
                 float Ar[EPT];
 #pragma unroll
@@ -316,6 +347,9 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 if (prefetch) {
                     pf.store(stage, tid, nthr, nw);
+                } else if (a.stage_exact) {
+                    stage_block(stage, a.F32 + bd.off_chunk, nb, kb, ROW, MP, a.lds_off_d, a.lds_off_u,
+                                a.u_lds, tid, nthr);
                 } else {
                     stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
                 }
@@ -345,6 +379,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     // below included) where its register is reused
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                 }
+                BlockDesc bn;
                 {
                     // the next block (of this sweep, or the first of the next): its components,
                     // which were stored when this sweep sampled it, and its factor chunk, loaded
@@ -352,10 +387,10 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     // into the block (the padding lanes are zeroed when the block starts; with
                     // one block the values are replaced below), so that no branch leaves the
                     // compiler's wait counting inexact and nothing waits for them early.
-                    const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < pd.B ? b + 1 : 0));
+                    bn = cload(a.blocks + pd.off_blk + (b + 1 < lc ? lf + b + 1 : nf));
 #pragma unroll
                     for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
-                    if (prefetch && (b + 1 < pd.B || s + 1 < s0 + nsw)) pf.load(a.F32 + bn.off_chunk, tid, nthr, nw);
+                    if (prefetch && (b + 1 < lc || s + 1 < s0 + nsw)) pf.load(a.F32 + bn.off_chunk, tid, nthr, nw);
                 }
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
@@ -375,6 +410,24 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
                     if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
                 }
+                if (NL > 1) {
+                    // a hierarchy's next block may overlap this block (whose components are
+                    // stored only while the next one is sampled) or the previous one: store
+                    // this block now and load the next one's components once the stores are
+                    // done
+                    const bool ov = (bn.n0 < bd.n0 + nb && bd.n0 < bn.n0 + bn.nb) ||
+                                    (p_nb > 0 && bn.n0 < p_n0 + p_nb && p_n0 < bn.n0 + bn.nb);
+                    if (ov) {
+#pragma unroll
+                        for (int t = 0; t < EPT; ++t) {
+                            const int q = lane + L * t;
+                            if (active && q < nb) Ag[bd.n0 + q] = Ar[t];
+                        }
+                        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the stores are done
+#pragma unroll
+                        for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
+                    }
+                }
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ap[t] = Ar[t];
                 if (pd.B == 1) {   // the next block is this one
@@ -393,6 +446,8 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     if (active && m < M) sr[m] = rr[t];
                 }
             }
+            lf = nf;
+            lc = nc;
         }
         store_prev();
 #pragma unroll

@@ -604,3 +604,132 @@ def test_conductivity_average_matches_oracle(pk, orc, n_omega):
     ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
     assert ok, info
     plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# the hierarchy of partitions (Fig. 2, Sec. IV.C): one random level per sweep
+# --------------------------------------------------------------------------------------
+
+def _with_levels(p, levels):
+    p.levels = [np.asarray(x, np.int64) for x in levels]
+    return p
+
+
+@pytest.mark.parametrize("M,N,seed", [(40, 24, 11), (36, 33, 9), (64, 57, 5)])
+def test_fp64_hierarchy_trajectory_matches_oracle(pk, orc, M, N, seed):
+    """The float64 sampler follows the oracle move by move through the levels: the same level
+    per sweep, the same blocks and the same random numbers.  N <= M, so that no block has a
+    null space: with one (12 x 30, say) the walk is chaotic, and the oracle against itself
+    with its factors perturbed by 1e-14 drifts past 1e-10 within about 90 sweeps."""
+    p = _with_levels(workloads.random_wellconditioned(M=M, N=N, nblocks=1, seed=seed), pk.hierarchy(N))
+    assert all(np.array_equal(a, b) for a, b in zip(p.levels, orc.hierarchy(N)))
+    prep = orc.prepare(p)
+    sweeps = 400
+    ores = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, refresh_every=16, groups=1,
+                   traj_chain=0, seed=99)
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=1, seed=99, precision="fp64",
+                   refresh_every=16, groups=1)
+    worst = 0.0
+    for s in range(sweeps):
+        plan.advance(1)
+        if s % 10 == 9 or s < 12:
+            A, r, chi2 = plan.state(0)
+            a = A[0].cpu().numpy()
+            ref = ores.traj_A[s]
+            worst = max(worst, np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+            assert abs(float(chi2[0]) - ores.traj_chi2[s]) <= 1e-10 * ores.traj_chi2[s]
+    assert worst < 1e-10, worst
+    plan.close()
+
+
+@pytest.mark.parametrize("bs", [[0, 48], [0, 20, 48], [0, 10, 25, 37, 48]])
+def test_fp32_repeated_level_is_the_partition_bit_for_bit(pk, bs):
+    """A hierarchy whose levels all hold one partition samples exactly that partition: the
+    moves are keyed by the block within its level and use the level's own factors.  With one
+    block every sweep's next block is the block itself (the overlap path)."""
+    out = []
+    for levels in ([bs], [bs, bs, bs]):
+        p = _with_levels(workloads.small_problem(M=41, N=48, nblocks=1, seed=4), levels)
+        plan = pk.Plan([p], chains=96, burnin=10, sweeps=150, seed=6, precision="fp32", groups=32,
+                       lanes_per_chain=16, roles=1)
+        res = plan.run()
+        A, r, _ = plan.state(0)
+        out.append((res.mean.cpu().numpy(), A.cpu().numpy(), r.cpu().numpy()))
+        plan.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+def test_fp32_hierarchy_keeps_state_consistent(pk, lanes):
+    """No refresh for 100 sweeps through overlapping levels: the carried residual equals
+    g~ - K~ A (a component read before the previous level stored it would break this)."""
+    N = 120
+    p = _with_levels(workloads.optical_conductivity(N, 1), pk.hierarchy(N))
+    plan = pk.Plan([p], chains=200, burnin=0, sweeps=1, precision="fp32", groups=8,
+                   refresh_every=0, lanes_per_chain=lanes, start="nnls")
+    plan.advance(100)
+    A, r, _ = plan.state(0)
+    Kt, gt = plan.whitened(0)
+    rr = gt[None, :] - A @ Kt.T
+    assert float((rr - r).abs().max()) <= 1e-3 * float(rr.abs().max())
+    assert float(A.min()) >= 0.0
+    plan.close()
+
+
+_HIER_ORACLE = {}
+
+
+@pytest.mark.parametrize("n_omega,lanes", [(40, 16), (40, 4), (120, 16), (120, 32)])
+def test_fp32_hierarchy_average_matches_oracle(pk, orc, n_omega, lanes):
+    """<A> of the float32 sampler with the Fig. 2 hierarchy on the optical-conductivity test
+    case against an oracle run of the same hierarchy."""
+    p = _with_levels(workloads.optical_conductivity(n_omega, 1), orc.hierarchy(n_omega))
+    if n_omega not in _HIER_ORACLE:
+        prep = orc.prepare(p)
+        _HIER_ORACLE[n_omega] = orc.run(prep, chains=64, burnin=500, sweeps=2000, seed=3, groups=32,
+                                        init=orc.nnls_start(prep))
+    ores = _HIER_ORACLE[n_omega]
+    plan = pk.Plan([p], chains=1024, burnin=500, sweeps=2000, seed=4, precision="fp32", groups=32,
+                   refresh_every=64, lanes_per_chain=lanes, start="nnls")
+    res = plan.run()
+    assert res.stats["roles"] == 1 and res.stats["lanes_per_chain"] == lanes
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
+    assert ok, info
+    # the data moves counted over the levels the sweeps drew (the library's own k_b)
+    kb_lvl, blk = [], 0
+    for ls in p.levels:
+        kb_lvl.append(0)
+        for b in range(len(ls) - 1):
+            kb_lvl[-1] += plan.factors(0, blk, int(ls[b + 1] - ls[b]))[0]
+            blk += 1
+    want = sum(kb_lvl[orc.sweep_level(4, 0, s, len(p.levels))] for s in range(2500)) * 1024
+    assert res.stats["data_moves"] == want
+    plan.close()
+
+
+def test_conductivity_hierarchy_steps_as_in_fig3(pk, orc):
+    """Fig. 3 with the paper's blocked modes (the Fig. 2 hierarchy) on the float32 sampler:
+    median Delta_i within a factor 1.5 of the oracle's and far above components (40 points)
+    and modes (120 points)."""
+    for n, nb_small in ((40, 40), (120, 1)):
+        p = _with_levels(workloads.optical_conductivity(n, 1), pk.hierarchy(n))
+        g = _gpu_median_step(pk, p)
+        prep = orc.prepare(p)
+        r = orc.run(prep, chains=1, burnin=0, sweeps=2500, seed=5, groups=1, traj_chain=0,
+                    init=orc.nnls_start(prep), threads=1)
+        A = r.traj_A
+        o = float(np.median((np.linalg.norm(np.diff(A, axis=0), axis=1) / np.linalg.norm(A[:-1], axis=1))[500:]))
+        assert 1 / 1.5 < g / o < 1.5, (n, g, o)
+        small = _gpu_median_step(pk, workloads.optical_conductivity(n, nb_small))
+        assert g > 10 * small, (n, g, small)
+
+
+def test_two_roles_refuse_a_hierarchy(pk):
+    p = _with_levels(workloads.small_problem(M=41, N=48, nblocks=1, seed=4), pk.hierarchy(48, 48))
+    with pytest.raises(pk.AsmError):
+        pk.Plan([p], chains=64, burnin=0, sweeps=4, precision="fp32", groups=32, lanes_per_chain=16,
+                roles=2)
+    plan = pk.Plan([p], chains=64, burnin=0, sweeps=4, precision="fp32", groups=32, lanes_per_chain=16)
+    assert plan.run().stats["roles"] == 1
+    plan.close()
