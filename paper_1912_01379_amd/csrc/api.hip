@@ -339,7 +339,7 @@ SampleArgs make_args(asm_plan *pl) {
     a.p_kd = pl->p_kd;
     a.p_zs = pl->p_zs;
     a.lvl = pl->d_lvl;
-    a.stage_exact = pl->any_levels ? 1 : 0;
+    a.hier = pl->any_levels ? 1 : 0;
     return a;
 }
 
@@ -551,12 +551,14 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
     std::string key = std::to_string(o->chains) + ":" + std::to_string(o->refresh_every) + ":" +
                       std::to_string(o->start);
     int64_t max_nb = 0, max_m = 0;
+    int hier = 0;
     for (int64_t p = 0; p < n; ++p) {
         key += "|" + std::to_string(pr[p].M) + "," + std::to_string(pr[p].N) + "," + (pr[p].cov ? "c" : "s");
         max_m = std::max(max_m, pr[p].M);
         Partition part;
         TRY(parse_partition(pr[p], p, &part));
         key += ";" + std::to_string(part.lcount.size());
+        hier |= part.lcount.size() > 1 ? 1 : 0;
         for (int64_t b = 0; b < pr[p].B; ++b) {
             const int64_t nb = part.nb[b];
             max_nb = std::max(max_nb, nb);
@@ -575,7 +577,7 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
     std::vector<int> cand;
     for (int L : {4, 8, 16, 32}) {
         int e, r, f;
-        if (sample32_pick(L, max_nb, max_m, &e, &r, &f) == 0) cand.push_back(L);
+        if (sample32_pick(L, max_nb, max_m, hier, &e, &r, &f) == 0) cand.push_back(L);
     }
     if (cand.empty()) return fail(ASM_EINVAL, "block of %lld points or %lld data points too large for the float32 sampler",
                                   (long long)max_nb, (long long)max_m);
@@ -1015,7 +1017,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             bool found = false;
             for (int cand : order) {
                 if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;
-                if (sample32_pick(cand, pl->max_nb, pl->max_m, &ept, &rpt, &pf) == 0) {
+                if (sample32_pick(cand, pl->max_nb, pl->max_m, pl->any_levels ? 1 : 0, &ept, &rpt, &pf) == 0) {
                     L = cand;
                     found = true;
                     break;

@@ -111,8 +111,8 @@ struct SampleArgs {
     int64_t p_du_word;
     int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
     const int32_t *lvl;       // level table: (first block relative to the problem's, count)
-    int32_t stage_exact;      // 1: stage only the rows, singular values and U rows of the block
-                              //    (blocks of very different sizes, as in a hierarchy)
+    int32_t hier;             // 1: a problem has a hierarchy of partitions (float32: the instances
+                              //    that draw a level per sweep and stage each block to its size)
     int32_t pad2;
 };
 
@@ -173,7 +173,7 @@ hipError_t set_sample64_lds_limit();
 // EPT, residual entries per lane RPT)
 hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt, int chains_per_wg,
                                 int grid, size_t lds_bytes, hipStream_t s);
-int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pf);
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int hier, int *ept, int *rpt, int *pf);
 hipError_t set_sample32_lds_limit(int bytes);
 hipError_t launch_sample32_l4(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t launch_sample32_l8(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);

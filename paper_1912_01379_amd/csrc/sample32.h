@@ -239,9 +239,12 @@ struct Prefetch {
 // block's factor stream is loaded into PF registers per thread while the current block is
 // sampled (when the plan's largest stream fits), so the block switch only writes LDS.
 // Prefetching instances run at most 256 threads per workgroup (one wavefront per SIMD),
-// which leaves them the whole register file.
-template <int L, int EPT, int RPT, int PF>
+// which leaves them the whole register file.  H: the instance for plans with a hierarchy of
+// partitions (a level drawn per sweep, blocks staged to their own size, no prefetch); the
+// single-partition instances carry none of its code.
+template <int L, int EPT, int RPT, int PF, bool H>
 __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
+    static_assert(!(H && PF > 0), "hierarchies run the non-prefetching instances");
     extern __shared__ __align__(16) unsigned char smem32[];
     constexpr int ROW = EPT * L;
     constexpr int MP = RPT * L;
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         float4 *stage = reinterpret_cast<float4 *>(smem32);
         // the blocks of a sweep: all of the partition, or of the sweep's level of a hierarchy
         // (Fig. 2), drawn for all chains of the problem at once
-        const int NL = (int)pd.levels;
+        const int NL = H ? (int)pd.levels : 1;
         auto level_of = [&](int64_t s, int &lf, int &lc) {
             lf = 0;
             lc = (int)pd.B;
@@ -345,11 +348,11 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
-                if (prefetch) {
-                    pf.store(stage, tid, nthr, nw);
-                } else if (a.stage_exact) {
+                if constexpr (H) {
                     stage_block(stage, a.F32 + bd.off_chunk, nb, kb, ROW, MP, a.lds_off_d, a.lds_off_u,
                                 a.u_lds, tid, nthr);
+                } else if (prefetch) {
+                    pf.store(stage, tid, nthr, nw);
                 } else {
                     stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
                 }
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
                     if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
                 }
-                if (NL > 1) {
+                if constexpr (H) {
                     // a hierarchy's next block may overlap this block (whose components are
                     // stored only while the next one is sampled) or the previous one: store
                     // this block now and load the next one's components once the stores are
@@ -460,14 +463,28 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 
 template <int L, int EPT, int RPT, int PF>
 hipError_t launch_sample32_t(const SampleArgs &a, int threads, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_sample32<L, EPT, RPT, PF>), dim3(grid), dim3(threads), lds, s, a);
+    if (a.hier) {
+        if constexpr (PF > 0) {
+            return hipErrorInvalidValue;   // hierarchies run the non-prefetching instances
+        } else {
+            hipLaunchKernelGGL((k_sample32<L, EPT, RPT, 0, true>), dim3(grid), dim3(threads), lds, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_sample32<L, EPT, RPT, PF, false>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 template <int L, int EPT, int RPT, int PF>
 hipError_t allow_lds_sample32_t(int bytes) {
-    return hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, PF>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, PF, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if constexpr (PF == 0) {
+        const hipError_t e1 = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, 0, true>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess) e = e1;
+    }
+    return e;
 }
 
 }  // namespace asmk

@@ -13,11 +13,12 @@ const Inst32 kInst32[] = {
     {4, 8, 16, 0}, {4, 32, 52, 0}, {8, 4, 8, 0}, {8, 13, 26, 0}, {8, 16, 52, 0}, {16, 2, 4, 0}, {16, 7, 13, 26}, {16, 8, 26, 0}, {16, 8, 32, 0}, {32, 1, 2, 0}, {32, 4, 7, 0}, {32, 4, 13, 0}};
 }  // namespace
 
-int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pf) {
+int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int hier, int *ept, int *rpt, int *pf) {
     int best = -1;
     for (int k = 0; k < (int)(sizeof kInst32 / sizeof kInst32[0]); ++k) {
         const Inst32 &c = kInst32[k];
         if (c.L != lanes || (int64_t)c.EPT * c.L < max_nb || (int64_t)c.RPT * c.L < max_m) continue;
+        if (hier && c.PF > 0) continue;   // hierarchies: non-prefetching instances only
         // the least per-lane work: 4 operations per component, 2 per residual entry
         if (best < 0 || 2 * c.EPT + c.RPT < 2 * kInst32[best].EPT + kInst32[best].RPT) best = k;
     }
