@@ -1089,6 +1089,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pl->chunk.u_rows = pl->u_lds ? max_kb : 0;
         pl->chunk.mp = mp;
         pl->chunk.words = (int64_t)(vw_bytes + d_bytes + (pl->u_lds ? u_bytes : 0)) / 16;
+        pl->chunk.compact = pl->any_levels ? 1 : 0;
         for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
         STEP(dalloc(pl, &pl->F32, pl->blocks.size() * pl->chunk.words));
         // the next block's chunk is prefetched into registers when it fits the instance's

@@ -151,6 +151,8 @@ struct ChunkLayout {           // float32 factor chunk of a block, in elements o
     int64_t u_rows;           // U rows in the chunk (largest k, or 0)
     int64_t mp;               // floats per U row
     int64_t words;            // 16-byte words of the chunk
+    int64_t compact;          // 1: each block's image packed to its own size (nb + 2 rows,
+                              //    round4(kb) values, kb U rows when staged), for hierarchies
 };
 hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *blockM_dev,
                                 int64_t nblocks, const double *V64, const double *U64,

@@ -180,19 +180,6 @@ __device__ __forceinline__ void stage_sync(float4 *dst, const float4 *src, int n
     for (; i < n; i += nthr) dst[i] = src[i];
 }
 
-// Stage only what a block of nb points and kb data modes reads: its nb + 2 (V, w) rows (two
-// spare rows are read ahead), its singular values and its U rows (when staged); for blocks of
-// very different sizes, as in a hierarchy of partitions, where the chunk is sized for the
-// largest.
-__device__ __forceinline__ void stage_block(float4 *dst, const float4 *src, int nb, int kb, int row,
-                                            int mp, int64_t off_d, int64_t off_u, int u_lds, int tid,
-                                            int nthr) {
-    stage_sync(dst, src, (nb + 2) * row / 2, tid, nthr);
-    const int wd = (int)(off_d / 16), wu = (int)(off_u / 16);
-    stage_sync(dst + wd, src + wd, (kb + 3) / 4, tid, nthr);
-    if (u_lds) stage_sync(dst + wu, src + wu, kb * mp / 4, tid, nthr);
-}
-
 // The prefetch registers: PF words per thread, addressed with constant indices only (a fold
 // over an index sequence instead of a loop) and of the compiler's native vector type, so that
 // they stay in registers.
@@ -348,9 +335,15 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
+                // the block's singular values and U rows in LDS: at the plan's fixed offsets, or,
+                // for a hierarchy, right after the block's own rows (its chunk is packed to its
+                // size: nb + 2 rows, round4(kb) values, kb U rows, one contiguous copy)
+                const float *sDb = sD, *sUb = sU;
                 if constexpr (H) {
-                    stage_block(stage, a.F32 + bd.off_chunk, nb, kb, ROW, MP, a.lds_off_d, a.lds_off_u,
-                                a.u_lds, tid, nthr);
+                    const int n1 = (nb + 2) * ROW / 2, n2 = (kb + 3) / 4, n3 = a.u_lds ? kb * MP / 4 : 0;
+                    stage_sync(stage, a.F32 + bd.off_chunk, n1 + n2 + n3, tid, nthr);
+                    sDb = reinterpret_cast<const float *>(stage + n1);
+                    sUb = sDb + 4 * n2;
                 } else if (prefetch) {
                     pf.store(stage, tid, nthr, nw);
                 } else {
@@ -374,9 +367,9 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 // data modes (U rows from LDS, or from global memory when they do not fit;
                 // two copies of the loop, so the LDS one waits on no global loads)
                 if (a.u_lds)
-                    data_moves<L, EPT, RPT, true>(kb, sVW, sD, sU, urow, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT, true>(kb, sVW, sDb, sUb, urow, lane, vw, Ar, rr);
                 else {
-                    data_moves<L, EPT, RPT, false>(kb, sVW, sD, Ug, urow, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT, false>(kb, sVW, sDb, Ug, urow, lane, vw, Ar, rr);
                     // the U row loaded ahead past the last data mode is never read: wait for
                     // it here, or the compiler waits for every load in flight (the prefetch
                     // below included) where its register is reused

@@ -9,6 +9,7 @@ hipError_t launch_sample32_l32(const SampleArgs &a, int ept, int rpt, int thread
     if (ept == 1 && rpt == 2) return launch_sample32_t<32, 1, 2, 0>(a, threads, grid, lds, s);
     if (ept == 4 && rpt == 7) return launch_sample32_t<32, 4, 7, 0>(a, threads, grid, lds, s);
     if (ept == 4 && rpt == 13) return launch_sample32_t<32, 4, 13, 0>(a, threads, grid, lds, s);
+    if (ept == 4 && rpt == 2) return launch_sample32_t<32, 4, 2, 0>(a, threads, grid, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -17,6 +18,7 @@ hipError_t allow_lds_sample32_l32(int bytes) {
     if ((e1 = allow_lds_sample32_t<32, 1, 2, 0>(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_t<32, 4, 7, 0>(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_t<32, 4, 13, 0>(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_t<32, 4, 2, 0>(bytes)) != hipSuccess) e = e1;
     return e;
 }
 

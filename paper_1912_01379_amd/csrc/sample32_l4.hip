@@ -8,6 +8,7 @@ hipError_t launch_sample32_l4(const SampleArgs &a, int ept, int rpt, int threads
                                hipStream_t s) {
     if (ept == 8 && rpt == 16) return launch_sample32_t<4, 8, 16, 0>(a, threads, grid, lds, s);
     if (ept == 32 && rpt == 52) return launch_sample32_t<4, 32, 52, 0>(a, threads, grid, lds, s);
+    if (ept == 32 && rpt == 16) return launch_sample32_t<4, 32, 16, 0>(a, threads, grid, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -15,6 +16,7 @@ hipError_t allow_lds_sample32_l4(int bytes) {
     hipError_t e = hipSuccess, e1;
     if ((e1 = allow_lds_sample32_t<4, 8, 16, 0>(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_t<4, 32, 52, 0>(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_t<4, 32, 16, 0>(bytes)) != hipSuccess) e = e1;
     return e;
 }
 

@@ -9,6 +9,7 @@ hipError_t launch_sample32_l8(const SampleArgs &a, int ept, int rpt, int threads
     if (ept == 4 && rpt == 8) return launch_sample32_t<8, 4, 8, 0>(a, threads, grid, lds, s);
     if (ept == 13 && rpt == 26) return launch_sample32_t<8, 13, 26, 0>(a, threads, grid, lds, s);
     if (ept == 16 && rpt == 52) return launch_sample32_t<8, 16, 52, 0>(a, threads, grid, lds, s);
+    if (ept == 16 && rpt == 8) return launch_sample32_t<8, 16, 8, 0>(a, threads, grid, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -17,6 +18,7 @@ hipError_t allow_lds_sample32_l8(int bytes) {
     if ((e1 = allow_lds_sample32_t<8, 4, 8, 0>(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_t<8, 13, 26, 0>(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_t<8, 16, 52, 0>(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_t<8, 16, 8, 0>(bytes)) != hipSuccess) e = e1;
     return e;
 }
 

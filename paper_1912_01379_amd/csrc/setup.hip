@@ -381,10 +381,13 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
     const int64_t M = blockM[blockIdx.x];
     const int64_t nb = bd.nb, kb = bd.kb, mp = bd.mp;
     constexpr double kTiny = 0x1.0p-100;
+    const int64_t rows = cl.compact ? nb + 2 : cl.rows;
+    const int64_t d_len = cl.compact ? (kb + 3) / 4 * 4 : cl.d_len;
+    const int64_t u_rows = cl.compact ? (cl.u_rows > 0 ? kb : 0) : cl.u_rows;
     float2 *vwc = reinterpret_cast<float2 *>(F32 + bd.off_chunk);
-    float *dc = reinterpret_cast<float *>(vwc + cl.rows * cl.row);
-    float *uc = dc + cl.d_len;
-    for (int64_t i = threadIdx.x; i < cl.rows * cl.row; i += blockDim.x) {
+    float *dc = reinterpret_cast<float *>(vwc + rows * cl.row);
+    float *uc = dc + d_len;
+    for (int64_t i = threadIdx.x; i < rows * cl.row; i += blockDim.x) {
         const int64_t mode = i / cl.row, q = i % cl.row;
         float2 vw;
         const double v = (mode < nb && q < nb) ? V64[bd.off_V + mode * nb + q] : 0.0;
@@ -397,8 +400,8 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
         }
         vwc[i] = vw;
     }
-    for (int64_t i = threadIdx.x; i < cl.d_len; i += blockDim.x) dc[i] = i < kb ? (float)d64[bd.off_d + i] : 0.0f;
-    for (int64_t i = threadIdx.x; i < cl.u_rows * cl.mp; i += blockDim.x) {
+    for (int64_t i = threadIdx.x; i < d_len; i += blockDim.x) dc[i] = i < kb ? (float)d64[bd.off_d + i] : 0.0f;
+    for (int64_t i = threadIdx.x; i < u_rows * cl.mp; i += blockDim.x) {
         const int64_t mode = i / cl.mp, m = i % cl.mp;
         uc[i] = (mode < kb && m < M) ? (float)U64[bd.off_U + mode * M + m] : 0.0f;
     }
