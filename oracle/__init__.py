@@ -8,7 +8,8 @@ Steps, in the paper's order:
   1. whitening, Sec. IV after Eq. (chi2): C^-1 = T^T T, g~ = T g, K~ = T K;
   2. per-block SVD K~_b = U_b D_b V_b^T, Sec. IV.B/IV.C, with d := 0 beyond the
      numerical rank (the paper's zero modes);
-  3. the random walk over blocked modes (C core, `core.c`);
+  3. the random walk over blocked modes (C core, `core.c`), optionally with the gamma-prior
+     weights prod_n A_n^(w_n - 1) of Sec. VI (Eq. (compat)) through an acceptance test per move;
   4. averages of Eq. (MCint), their error bars, and the sensitivity of the average to
      the data, d<f>/dg = -Cov(f, r~) T, which follows from differentiating the
      posterior of Eq. (PI) (the normaliser depends on g).
@@ -61,7 +62,7 @@ class _Problem(ctypes.Structure):
                 ("Kt", ctypes.c_void_p), ("gt", ctypes.c_void_p), ("bn0", ctypes.c_void_p),
                 ("bnb", ctypes.c_void_p), ("L", ctypes.c_int64), ("lfirst", ctypes.c_void_p),
                 ("lcount", ctypes.c_void_p), ("kb", ctypes.c_void_p), ("d", ctypes.c_void_p),
-                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("shape_m1", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -75,7 +76,8 @@ class _Options(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("sumA", "sumA2", "count", "sumR", "sumRA", "final_A", "final_r", "final_chi2",
-                 "traj_A", "traj_chi2", "drift_max", "n_frozen", "n_clamped", "status")]
+                 "traj_A", "traj_chi2", "drift_max", "n_frozen", "n_clamped", "status",
+                 "n_rejected")]
 
 
 def lib():
@@ -165,6 +167,7 @@ class Prepared:
     dall: list                # per block: all singular values (min(M, Nb))
     Tt: object                # callable y -> T^T y
     init: np.ndarray          # N
+    shape: Optional[np.ndarray] = None   # N gamma-prior shapes w_n (Eq. (compat)), or flat
 
     @property
     def M(self):
@@ -318,7 +321,8 @@ def prepare(problem, k=None) -> Prepared:
     init = np.full(Kt.shape[1], cstar)
     return Prepared(Kt=np.ascontiguousarray(Kt), gt=np.ascontiguousarray(gt), levels=levels,
                     kb=np.asarray(kb, dtype=np.int32), d=ds, U=Us, V=Vs, dall=dall, Tt=Tt,
-                    init=init)
+                    init=init, shape=None if getattr(problem, "prior_shape", None) is None
+                    else np.asarray(problem.prior_shape, np.float64))
 
 
 # --------------------------------------------------------------------------------------
@@ -341,6 +345,7 @@ class Result:
     n_frozen: int
     n_clamped: int
     status: int
+    n_rejected: int
     cov_rA: Optional[np.ndarray]   # M x N sample Cov(r~, A)
     mean_r: Optional[np.ndarray]
     prep: Prepared
@@ -371,11 +376,13 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
         traj_A=np.zeros(total * N) if traj_chain >= 0 else None,
         traj_chi2=np.zeros(total) if traj_chain >= 0 else None,
         drift_max=np.zeros(1), n_frozen=np.zeros(1, np.int64), n_clamped=np.zeros(1, np.int64),
-        status=np.zeros(1, np.int32))
+        status=np.zeros(1, np.int32), n_rejected=np.zeros(1, np.int64))
+    shape_m1 = None if prep.shape is None else np.ascontiguousarray(np.asarray(prep.shape, np.float64) - 1.0)
     p = _Problem(M=M, N=N, B=B, Kt=prep.Kt.ctypes.data, gt=prep.gt.ctypes.data,
                  bn0=bn0.ctypes.data, bnb=bnb.ctypes.data, L=len(prep.levels),
                  lfirst=lfirst.ctypes.data, lcount=lcount.ctypes.data, kb=kb.ctypes.data, d=d_all.ctypes.data,
-                 U=U_all.ctypes.data, V=V_all.ctypes.data)
+                 U=U_all.ctypes.data, V=V_all.ctypes.data,
+                 shape_m1=None if shape_m1 is None else shape_m1.ctypes.data)
     o = _Options(chains=chains, burnin=burnin, sweeps=sweeps, seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
                  problem_index=problem_index, refresh_every=refresh_every, groups=G,
                  want_cross=1 if want_cross else 0, threads=int(threads), traj_chain=traj_chain,
@@ -407,7 +414,8 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
                   traj_A=None if bufs["traj_A"] is None else bufs["traj_A"].reshape(total, N),
                   traj_chi2=bufs["traj_chi2"], drift_max=float(bufs["drift_max"][0]),
                   n_frozen=int(bufs["n_frozen"][0]), n_clamped=int(bufs["n_clamped"][0]),
-                  status=int(bufs["status"][0]), cov_rA=cov_rA, mean_r=mean_r, prep=prep)
+                  status=int(bufs["status"][0]), n_rejected=int(bufs["n_rejected"][0]),
+                  cov_rA=cov_rA, mean_r=mean_r, prep=prep)
 
 
 def vjp(res: Result, v: np.ndarray) -> np.ndarray:

@@ -27,7 +27,11 @@
  *     one level, the same for all chains, chosen by Philox on the counter
  *     (2^32 - 1, sweep, 0, 2): level = floor(w0 L / 2^32); the uniforms of a move keep the
  *     block's index within its level;
- *   - the residual is recomputed from scratch every `refresh_every` sweeps.
+ *   - the residual is recomputed from scratch every `refresh_every` sweeps;
+ *   - with gamma-prior weights prod_n A_n^(w_n - 1) (Sec. VI, Eq. (compat), the limit of
+ *     vanishing scale), each move's draw is a proposal accepted when
+ *     log u' < sum_q (w_q - 1) log(A'_q / A_q), u' the uniform of counter
+ *     (chain, sweep, block << 16 | mode, 3); a rejected move leaves the state unchanged.
  */
 #include <math.h>
 #include <pthread.h>
@@ -81,15 +85,30 @@ static int64_t sweep_level(uint64_t seed, int64_t problem, int64_t sweep, int64_
     return (int64_t)(((uint64_t)w[0] * (uint64_t)L) >> 32);
 }
 
-static double move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
-                           int64_t block, int64_t mode) {
+/* tag 0: the move's draw; tag 3: its acceptance test under a gamma prior */
+static double move_uniform_tag(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
+                               int64_t block, int64_t mode, uint32_t tag) {
     uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu),
                        (uint32_t)(seed >> 32) ^ (uint32_t)problem};
     uint32_t ctr[4] = {(uint32_t)chain, (uint32_t)sweep,
-                       ((uint32_t)block << 16) | (uint32_t)mode, 0u};
+                       ((uint32_t)block << 16) | (uint32_t)mode, tag};
     uint32_t w[4];
     philox4x32_10(ctr, key, w);
     return u01_from_words(w[0], w[1]);
+}
+
+static double move_uniform(uint64_t seed, int64_t problem, int64_t chain, int64_t sweep,
+                           int64_t block, int64_t mode) {
+    return move_uniform_tag(seed, problem, chain, sweep, block, mode, 0u);
+}
+
+/* (w - 1) log(a_new / a_old): one component's share of the log ratio of the gamma-prior
+   weights prod_n A_n^(w_n - 1) (Eq. (gammadist), Eq. (compat)) between two states. */
+static double prior_log_ratio(double a_new, double a_old, double wm1) {
+    if (wm1 == 0.0 || a_new == a_old) return 0.0;
+    if (a_old == 0.0) return wm1 > 0.0 ? INFINITY : -INFINITY;
+    if (a_new == 0.0) return wm1 > 0.0 ? -INFINITY : INFINITY;
+    return wm1 * log(a_new / a_old);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -287,6 +306,7 @@ typedef struct {
     const double *d;        /* concatenated data singular values (sum kb)                */
     const double *U;        /* concatenated U_b, each M x kb row-major                   */
     const double *V;        /* concatenated V_b, each Nb x Nb row-major, column = mode   */
+    const double *shape_m1; /* N: w_n - 1 of the gamma prior weights, or NULL (flat)      */
 } orc_problem;
 
 typedef struct {
@@ -316,6 +336,7 @@ typedef struct {
     int64_t *n_frozen;   /* 1                                                           */
     int64_t *n_clamped;  /* 1                                                           */
     int32_t *status;     /* 1                                                           */
+    int64_t *n_rejected; /* 1: moves rejected by the gamma-prior acceptance test         */
 } orc_out;
 
 typedef struct {
@@ -327,7 +348,7 @@ typedef struct {
     double *sumA, *sumA2, *sumR, *sumRA;
     int64_t *count;
     double drift;
-    int64_t frozen, clamped;
+    int64_t frozen, clamped, rejected;
     int32_t status;
 } worker;
 
@@ -405,6 +426,23 @@ static void *run_chains(void *arg) {
                         }
                     }
                     if (lo == hi) wk->frozen++;
+                    if (p->shape_m1) {
+                        /* Sec. VI: the target along the mode carries the weights
+                           prod_q A_q^(w_q - 1); the draw above (the Gaussian or flat
+                           conditional of the flat-prior posterior) is an independence proposal,
+                           accepted with probability min(1, R(delta) / R(0)) */
+                        double lr = 0.0;
+                        for (int64_t q = 0; q < nb; ++q) {
+                            double an = A[n0 + q] + delta * Vb[q * nb + i];
+                            if (an < 0.0) an = 0.0;
+                            lr += prior_log_ratio(an, A[n0 + q], p->shape_m1[n0 + q]);
+                        }
+                        double ua = move_uniform_tag(o->seed, o->problem_index, c, s, b, i, 3u);
+                        if (!(log(ua) < lr)) {
+                            delta = 0.0;
+                            wk->rejected++;
+                        }
+                    }
                     for (int64_t q = 0; q < nb; ++q) {
                         double an = A[n0 + q] + delta * Vb[q * nb + i];
                         if (an < 0.0) {
@@ -481,7 +519,7 @@ int orc_run(const orc_problem *p, const orc_options *o, orc_out *out) {
     }
     int32_t status = ORC_OK;
     double drift = 0.0;
-    int64_t frozen = 0, clamped = 0;
+    int64_t frozen = 0, clamped = 0, rejected = 0;
     for (int64_t t = 0; t < nt; ++t) {
         pthread_join(th[t], NULL);
         for (int64_t i = 0; i < G * N; ++i) {
@@ -498,11 +536,13 @@ int orc_run(const orc_problem *p, const orc_options *o, orc_out *out) {
         if (wk[t].drift > drift) drift = wk[t].drift;
         frozen += wk[t].frozen;
         clamped += wk[t].clamped;
+        rejected += wk[t].rejected;
         free(wk[t].sumA); free(wk[t].sumA2); free(wk[t].count);
     }
     *out->drift_max = drift;
     *out->n_frozen = frozen;
     *out->n_clamped = clamped;
+    if (out->n_rejected) *out->n_rejected = rejected;
     *out->status = status;
     free(wk); free(th);
     return status;

@@ -621,3 +621,73 @@ def test_hierarchy_steps_as_in_fig3(orc):
         mid = np.median(d[500:][(lv > 0) & (lv < len(prep.levels) - 1)])
         ends = np.median(d[500:][(lv == 0) | (lv == len(prep.levels) - 1)])
         assert ends < 0.5 * mid, (n, ends, mid)
+
+
+# --------------------------------------------------------------------------------------
+# gamma-prior weights (Sec. VI): prod_n A_n^(w_n - 1) exp(-chi^2 / 2), Eq. (compat)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w", [0.5, 2.5])
+def test_gamma_prior_one_point_against_quadrature(orc, w):
+    """N = 1: density f^(w-1) exp(-(f - mu)^2 / 2 s^2) on f > 0, mean by quadrature."""
+    rng = np.random.default_rng(13)
+    k = rng.uniform(0.5, 1.5, 7)
+    s = 1.0 / np.linalg.norm(k)
+    for mu_over_s in [-1.0, 0.5, 3.0]:
+        mu = mu_over_s * s
+        p = _problem(k[:, None], k * mu, 1.0, [0, 1])
+        p.prior_shape = np.array([w])
+        res = orc.run(orc.prepare(p), chains=16, burnin=50, sweeps=20000, groups=16)
+        dens = lambda f, j: f ** (w - 1 + j) * math.exp(-0.5 * ((f - mu) / s) ** 2)
+        up = max(mu, 0) + 12 * s
+        Z = integrate.quad(lambda f: dens(f, 0), 0, up, points=[s * 1e-3, s], limit=400)[0]
+        ref = integrate.quad(lambda f: dens(f, 1), 0, up, points=[s * 1e-3, s], limit=400)[0] / Z
+        assert _within(res.mean, res.stderr, ref) < 4.5, (w, mu_over_s, res.mean, ref)
+        assert 0 < res.n_rejected < 20000 * 16
+
+
+@pytest.mark.parametrize("w", [0.5, 2.0])
+def test_gamma_prior_sum_rule_closed_form(orc, w):
+    """K = 1^T, g = 1: S = sum A has density S^(N w - 1) exp(-(S - 1)^2 / 2 sigma^2) and
+    A / S ~ Dirichlet(w, ..., w), so <A_n> = E[S] / N and <A_n^2> = E[S^2] (w + 1) / (N (N w + 1))."""
+    N, sig = 8, 0.3
+    ws = lambda S, j: S ** (N * w - 1 + j) * math.exp(-0.5 * ((S - 1.0) / sig) ** 2)
+    Z = integrate.quad(lambda S: ws(S, 0), 0, 10, points=[1e-3, 1.0], limit=400)[0]
+    ES = integrate.quad(lambda S: ws(S, 1), 0, 10, limit=400)[0] / Z
+    ES2 = integrate.quad(lambda S: ws(S, 2), 0, 10, limit=400)[0] / Z
+    EA = ES / N
+    EA2 = ES2 * (w + 1) / (N * (N * w + 1))
+    p = _problem(np.ones((1, N)), [1.0], sig, [0, 4, 8])
+    p.prior_shape = np.full(N, w)
+    res = orc.run(orc.prepare(p), chains=16, burnin=500, sweeps=40000, groups=16)
+    assert _within(res.mean, res.stderr, EA) < 4.5, (res.mean, EA)
+    assert np.allclose(res.post_sd, math.sqrt(EA2 - EA * EA), rtol=0.04), (res.post_sd, math.sqrt(EA2 - EA * EA))
+
+
+def test_gamma_prior_halved_grid_reproduces_the_flat_coarse_grid(orc):
+    """Eq. (genconsistency) / Eq. (compat): each interval of a 3-point grid split in two halves
+    of the same kernel value (columns K_j / 2) and sampled with shape w = 1/2 per half gives,
+    for the pair averages, the flat-prior average of the coarse grid (two gamma(1/2) weights
+    convolve to the flat one), exactly up to Monte Carlo error."""
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x = np.array([-1.5, 0.0, 1.5])
+    Kc = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.05
+    G = Kc @ np.array([0.3, 0.05, 0.2]) + sig * np.random.default_rng(9).standard_normal(11)
+    coarse = orc.run(orc.prepare(_problem(Kc, G, sig, [0, 3])), chains=32, burnin=200,
+                     sweeps=20000, groups=32)
+    Kf = np.repeat(Kc / 2.0, 2, axis=1)
+    pf = _problem(Kf, G, sig, [0, 6])
+    pf.prior_shape = np.full(6, 0.5)
+    fine = orc.run(orc.prepare(pf), chains=32, burnin=200, sweeps=20000, groups=32)
+    pair = fine.group_means.reshape(32, 3, 2).mean(axis=2)
+    pm, pse = pair.mean(0), pair.std(0, ddof=1) / math.sqrt(32)
+    z = np.abs(pm - coarse.mean) / np.sqrt(pse ** 2 + coarse.stderr ** 2)
+    assert np.max(z) < 4.5, (pm, coarse.mean, z)
+    # the flat prior on the fine grid gives a different answer (the grid dependence of Sec. VI)
+    pflat = _problem(Kf, G, sig, [0, 6])
+    flat = orc.run(orc.prepare(pflat), chains=32, burnin=200, sweeps=20000, groups=32)
+    fp = flat.group_means.reshape(32, 3, 2).mean(axis=2)
+    zf = np.abs(fp.mean(0) - coarse.mean) / np.sqrt((fp.std(0, ddof=1) / math.sqrt(32)) ** 2 + coarse.stderr ** 2)
+    assert np.max(zf) > 6, (fp.mean(0), coarse.mean, zf)

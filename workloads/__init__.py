@@ -123,6 +123,8 @@ class Problem:
     k: Optional[np.ndarray] = None      # requested data modes per block (None -> numerical rank)
     A_true: Optional[np.ndarray] = None
     name: str = ""
+    prior_shape: Optional[np.ndarray] = None   # N gamma-prior shapes w_n (Eq. (compat));
+                                        # None: the flat prior (w = 1)
     levels: Optional[list] = None       # a hierarchy of partitions (each B_l+1 offsets), used
                                         # instead of block_start when given; k then covers the
                                         # blocks of all levels in order
