@@ -83,6 +83,7 @@ class _DevProblem:
         self.cov = None if p.cov is None else torch.as_tensor(p.cov, dtype=torch.float64, device=device)
         self.block_start = p.block_start
         self.levels = getattr(p, "levels", None)
+        self.prior_shape = getattr(p, "prior_shape", None)
         self.k = p.k
         self.init = None
 

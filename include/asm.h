@@ -39,7 +39,8 @@ extern "C" {
 /* ---- error codes ------------------------------------------------------------------- */
 #define ASM_OK          0
 #define ASM_EINVAL     (-1)  /* bad sizes, NULL required pointer, bad partition or k      */
-#define ASM_EDOMAIN    (-2)  /* non-finite input, sigma <= 0, covariance not SPD, init < 0 */
+#define ASM_EDOMAIN    (-2)  /* non-finite input, sigma <= 0, covariance not SPD, init < 0,
+                                prior shape not positive and finite                     */
 #define ASM_ESTATE     (-3)  /* call out of order (vjp without want_vjp or before run)    */
 #define ASM_EUNBOUNDED (-4)  /* a zero mode whose allowed interval is unbounded: the flat
                                 prior makes the posterior improper (Sec. IV.B, d_i = 0)   */
@@ -84,6 +85,16 @@ typedef struct {
                                     Philox words of counter (2^32 - 1, sweep, 0, 2); the moves
                                     are keyed by the block's index within its level           */
     const int64_t *level_blocks; /* host, levels: B_l per level (sum = B); NULL when levels <= 1 */
+    const double *prior_shape;   /* device, N shapes w_n > 0 of the gamma-prior weights, or NULL
+                                    for the flat prior: the chains then sample
+                                    prod_n A_n^(w_n - 1) exp(-chi^2/2) on A >= 0 (Sec. VI,
+                                    Eq. (gammadist) and Eq. (compat) in the limit of vanishing
+                                    scale; w_n = N rho(x_n) / (N~ rho~(x_n)) simulates the flat
+                                    prior of grid (N, rho) on this grid (N~, rho~)).  Each
+                                    move's draw is then a proposal, accepted when
+                                    log u' < sum_q (w_q - 1) log(A'_q / A_q), u' the float64
+                                    uniform of counter (chain, sweep, block << 16 | mode, 3);
+                                    a rejected move changes nothing.  ASM_FP64 only           */
 } asm_problem;
 
 typedef struct {
@@ -140,6 +151,7 @@ typedef struct {
     int64_t graph_replays;       /* refresh cycles replayed from a captured hipGraph (use_graph);
                                     their sampler launches are not in sampler_ms             */
     int64_t roles;               /* 1 or 2: the float32 sampler's roles (see asm_options)     */
+    int64_t rejected;            /* moves rejected by the gamma-prior test (prior_shape)      */
 } asm_stats;
 
 /* Validate the problems, whiten them, decompose every block (float64 one-sided Jacobi SVD,

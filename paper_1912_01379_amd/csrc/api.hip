@@ -108,6 +108,8 @@ struct asm_plan {
     float *A32 = nullptr, *r32 = nullptr;
     double *A64 = nullptr, *r64 = nullptr, *chi2 = nullptr, *chi2_prev = nullptr, *drift = nullptr;
     double *accA = nullptr, *accA2 = nullptr, *slot_count_d = nullptr;
+    double *shape = nullptr;   // gamma-prior shapes (problems with a prior, at off_n)
+    bool any_prior = false;
     int32_t *slot_group_d = nullptr;
     double *cross = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
     unsigned long long *counters = nullptr;
@@ -216,6 +218,8 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
         TRY(parse_partition(q, p, &part));
         for (int64_t b = 0; b < q.B; ++b)
             if (q.k && q.k[b] < 0) return fail(ASM_EINVAL, "problem %lld: k must be >= 0", (long long)p);
+        if (q.prior_shape && o->precision != ASM_FP64)
+            return fail(ASM_EINVAL, "problem %lld: prior_shape needs ASM_FP64", (long long)p);
     }
     return ASM_OK;
 }
@@ -339,6 +343,7 @@ SampleArgs make_args(asm_plan *pl) {
     a.p_kd = pl->p_kd;
     a.p_zs = pl->p_zs;
     a.lvl = pl->d_lvl;
+    a.shape = pl->shape;
     a.hier = pl->any_levels ? 1 : 0;
     return a;
 }
@@ -766,6 +771,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pd.batches = C < G ? G : 1;
         pd.has_cov = q.cov != nullptr;
         pd.index = (uint32_t)p;
+        pd.has_prior = q.prior_shape != nullptr;
+        pl->any_prior |= pd.has_prior != 0;
         pl->any_cov |= pd.has_cov;
         Partition part;
         STEP(parse_partition(q, p, &part));
@@ -884,7 +891,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     STEP(dalloc(pl, &pl->flags, 1));
     STEP(dalloc(pl, &pl->queue, 1));
     STEP(dalloc(pl, &pl->sweep_d, 1));
-    STEP(dalloc(pl, &pl->counters, 2));
+    STEP(dalloc(pl, &pl->counters, 3));
+    if (pl->any_prior) STEP(dalloc(pl, &pl->shape, offn));
     STEP(dalloc(pl, &pl->chi2, offc));
     STEP(dalloc(pl, &pl->chi2_prev, offc));
     STEP(dalloc(pl, &pl->drift, offc));
@@ -919,7 +927,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     HSTEP(hipMemsetAsync(pl->flags, 0, sizeof(int), st));
     HSTEP(hipMemsetAsync(pl->sweep_d, 0, sizeof(int64_t), st));
     HSTEP(hipMemsetAsync(pl->queue, 0, sizeof(int), st));
-    HSTEP(hipMemsetAsync(pl->counters, 0, 2 * sizeof(unsigned long long), st));
+    HSTEP(hipMemsetAsync(pl->counters, 0, 3 * sizeof(unsigned long long), st));
     HSTEP(hipMemsetAsync(pl->drift, 0, offc * sizeof(double), st));
 
     // ---- input checks (device data) ----
@@ -930,6 +938,11 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         HSTEP(launch_check_finite(q.G, q.M, pl->flags, 1, st));
         if (q.sigma) HSTEP(launch_check_positive(q.sigma, q.M, pl->flags, 2, st));
         if (q.cov) HSTEP(launch_check_finite(q.cov, q.M * q.M, pl->flags, 1, st));
+        if (q.prior_shape) {
+            HSTEP(launch_check_positive(q.prior_shape, q.N, pl->flags, 4, st));
+            HSTEP(hipMemcpyAsync(pl->shape + pl->probs[p].off_n, q.prior_shape, q.N * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+        }
         if (q.init) {
             HSTEP(launch_check_finite(q.init, q.N, pl->flags, 1, st));
             HSTEP(hipMemcpyAsync(tmpN + pl->probs[p].off_n, q.init, q.N * sizeof(double),
@@ -941,6 +954,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     STEP(check_flags(pl, &hflags));
     if (hflags & 2) { rc = fail(ASM_EDOMAIN, "non-finite value in K, G, cov or init"); return rc; }
     if (hflags & 4) { rc = fail(ASM_EDOMAIN, "sigma must be positive and finite"); return rc; }
+    if (hflags & 16) { rc = fail(ASM_EDOMAIN, "prior_shape must be positive and finite"); return rc; }
     if (std::any_of(has_init.begin(), has_init.end(), [](int v) { return v; })) {
         std::vector<double> h(offn);
         HSTEP(hipMemcpy(h.data(), tmpN, offn * sizeof(double), hipMemcpyDeviceToHost));
@@ -1256,7 +1270,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     const int64_t slot_elems = pl->probs.back().off_slot + pl->probs.back().nslot * pl->probs.back().N;
     HIPCHK(hipMemsetAsync(pl->accA, 0, slot_elems * sizeof(double), st));
     HIPCHK(hipMemsetAsync(pl->accA2, 0, slot_elems * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(pl->counters, 0, 2 * sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(pl->counters, 0, 3 * sizeof(unsigned long long), st));
     if (pl->opt.want_vjp) {
         const ProbDesc &lp = pl->probs.back();
         const int64_t crossn = lp.off_cross + (int64_t)pl->ksplit * lp.M * (lp.N + 1);
@@ -1312,10 +1326,11 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         std::vector<double> dr(pl->total_chains);
         HIPCHK(hipMemcpy(dr.data(), pl->drift, dr.size() * sizeof(double), hipMemcpyDeviceToHost));
         stats->chi2_drift_max = dr.empty() ? 0.0 : *std::max_element(dr.begin(), dr.end());
-        unsigned long long cnt[2];
+        unsigned long long cnt[3];
         HIPCHK(hipMemcpy(cnt, pl->counters, sizeof cnt, hipMemcpyDeviceToHost));
         stats->clamped = (int64_t)cnt[0];
         stats->frozen = (int64_t)cnt[1];
+        stats->rejected = (int64_t)cnt[2];
         stats->lanes_per_chain = pl->lanes;
         stats->chains_per_block = pl->chains_per_wg;
         double smp = 0.0;

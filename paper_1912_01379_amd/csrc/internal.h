@@ -32,7 +32,7 @@ struct ProbDesc {
     int32_t groups;
     int32_t has_cov;
     uint32_t index;           // problem index (keys the random numbers)
-    int32_t pad;
+    int32_t has_prior;        // 1: gamma-prior shapes at off_n in the shape array
     int64_t off_sa;           // float32 snapshots of A (sweep, chain) rows of round4(N) floats
     int64_t off_sr;           // float32 snapshots of r rows of round4(M) floats
     int64_t levels;           // partitions of the hierarchy (1: one partition of B blocks)
@@ -84,7 +84,7 @@ struct SampleArgs {
     double *drift;            // per chain, running max
     double *accA;             // slots x N (per problem offsets)
     double *accA2;
-    unsigned long long *counters;  // [0] clamped, [1] frozen
+    unsigned long long *counters;  // [0] clamped, [1] frozen, [2] rejected by the prior test
     int *flags;               // bit 0: unbounded zero mode
     int *queue;               // tile queue head (float32 sampler)
     const int64_t *sweep;     // device sweep counter: first sweep of this launch
@@ -111,6 +111,7 @@ struct SampleArgs {
     int64_t p_du_word;
     int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
     const int32_t *lvl;       // level table: (first block relative to the problem's, count)
+    const double *shape;      // gamma-prior shapes w_n (problems with has_prior, at off_n)
     int32_t hier;             // 1: a problem has a hierarchy of partitions (float32: the instances
                               //    that draw a level per sweep and stage each block to its size)
     int32_t pad2;

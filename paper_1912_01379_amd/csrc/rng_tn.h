@@ -42,10 +42,12 @@ __host__ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) 
     return c;
 }
 
-// float64 uniform of move (chain, sweep, block, mode): ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52
+// float64 uniform of move (chain, sweep, block, mode): ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52;
+// tag 0 for the move's draw, 3 for its acceptance test under a gamma prior
 __device__ __forceinline__ double move_u64(uint64_t seed, uint32_t problem, uint32_t chain,
-                                           uint32_t sweep, uint32_t block, uint32_t mode) {
-    U4 c{chain, sweep, (block << 16) | mode, 0u};
+                                           uint32_t sweep, uint32_t block, uint32_t mode,
+                                           uint32_t tag = 0u) {
+    U4 c{chain, sweep, (block << 16) | mode, tag};
     U4 o = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32) ^ problem);
     const uint64_t j = ((uint64_t)(o.x >> 6) << 26) | (uint64_t)(o.y >> 6);
     return ((double)j + 0.5) * 0x1.0p-52;

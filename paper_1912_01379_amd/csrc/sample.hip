@@ -40,6 +40,15 @@ __device__ __forceinline__ double wmin64(double v) {
     return v;
 }
 
+// (w - 1) log(a_new / a_old): one component's share of the log ratio of the gamma-prior
+// weights prod_n A_n^(w_n - 1) (Sec. VI) between the proposed and the current state
+__device__ __forceinline__ double prior_term(double a_new, double a_old, double wm1) {
+    if (wm1 == 0.0 || a_new == a_old) return 0.0;
+    if (a_old == 0.0) return wm1 > 0.0 ? INFINITY : -INFINITY;
+    if (a_new == 0.0) return wm1 > 0.0 ? -INFINITY : INFINITY;
+    return wm1 * log(a_new / a_old);
+}
+
 __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *chain_problem,
                                                  const int32_t *chain_local) {
     extern __shared__ double sm64[];
@@ -58,7 +67,8 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
     double drift = a.drift[pd.off_c + c];
     const double *Kc = a.Kt + pd.off_K;
     const double *gc = a.gt + pd.off_m;
-    unsigned long long clamped = 0, frozen = 0;
+    unsigned long long clamped = 0, frozen = 0, rejected = 0;
+    const double *wsh = pd.has_prior ? a.shape + pd.off_n : nullptr;
     int unbounded = 0;
     __syncthreads();
     const int64_t s0 = *a.sweep;
@@ -104,6 +114,23 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
                     delta = __dadd_rn(lo, __dmul_rn(u, __dadd_rn(hi, -lo)));
                 }
                 frozen += (lo == hi);
+                if (wsh) {
+                    // gamma prior (Sec. VI): the draw is a proposal along the mode, accepted
+                    // with probability min(1, R(delta) / R(0)), R = prod_q A_q^(w_q - 1)
+                    double lr = 0.0;
+                    for (int64_t q = lane; q < nb; q += 64) {
+                        double an = __dadd_rn(Ab[q], __dmul_rn(delta, Vi[q]));
+                        if (an < 0.0) an = 0.0;
+                        lr += prior_term(an, Ab[q], wsh[bd.n0 + q] - 1.0);
+                    }
+                    lr = wsum64(lr);
+                    const double ua = move_u64(a.seed, pd.index, (uint32_t)c, (uint32_t)s, (uint32_t)b,
+                                               (uint32_t)i, 3u);
+                    if (!(log(ua) < lr)) {
+                        delta = 0.0;
+                        rejected += (lane == 0);
+                    }
+                }
                 for (int64_t q = lane; q < nb; q += 64) {
                     double an = __dadd_rn(Ab[q], __dmul_rn(delta, Vi[q]));
                     if (an < 0.0) {
@@ -156,6 +183,7 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
         a.chi2[pd.off_c + c] = chi2;
         a.drift[pd.off_c + c] = drift;
         if (frozen) atomicAdd(&a.counters[1], frozen);
+        if (rejected) atomicAdd(&a.counters[2], rejected);
         if (unbounded) atomicOr(a.flags, 1);
     }
 }

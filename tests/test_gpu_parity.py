@@ -733,3 +733,86 @@ def test_two_roles_refuse_a_hierarchy(pk):
     plan = pk.Plan([p], chains=64, burnin=0, sweeps=4, precision="fp32", groups=32, lanes_per_chain=16)
     assert plan.run().stats["roles"] == 1
     plan.close()
+
+
+# --------------------------------------------------------------------------------------
+# gamma-prior weights (Sec. VI, Eq. (compat)): an acceptance test per move
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nblocks,levels", [(2, False), (1, True)])
+def test_fp64_gamma_prior_trajectory_matches_oracle(pk, orc, nblocks, levels):
+    """The float64 sampler with shapes w_n in [0.5, 2] follows the oracle move by move: the
+    same proposals, the same acceptance decisions (rejections counted alike)."""
+    p = workloads.random_wellconditioned(M=40, N=24, nblocks=nblocks, seed=11)
+    p.prior_shape = np.random.default_rng(5).uniform(0.5, 2.0, 24)
+    if levels:
+        p.levels = pk.hierarchy(24)
+    prep = orc.prepare(p)
+    sweeps = 600
+    ores = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, refresh_every=16, groups=1,
+                   traj_chain=0, seed=99)
+    assert ores.n_rejected > 0
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=1, seed=99, precision="fp64",
+                   refresh_every=16, groups=1)
+    worst = 0.0
+    for s in range(sweeps):
+        plan.advance(1)
+        if s % 10 == 9 or s < 12:
+            A, r, chi2 = plan.state(0)
+            a = A[0].cpu().numpy()
+            ref = ores.traj_A[s]
+            worst = max(worst, np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+            assert abs(float(chi2[0]) - ores.traj_chi2[s]) <= 1e-10 * ores.traj_chi2[s]
+    assert worst < 1e-10, worst
+    plan.close()
+    # a run of the same chain counts the oracle's rejections
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=sweeps, seed=99, precision="fp64",
+                   refresh_every=16, groups=1)
+    assert plan.run().stats["rejected"] == ores.n_rejected
+    plan.close()
+
+
+def test_gamma_prior_halved_grid_on_gpu(pk, orc):
+    """The halved-grid identity of Eq. (genconsistency) on the float64 sampler: pair averages
+    with shape 1/2 against the oracle's flat-prior average of the coarse grid."""
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x = np.array([-1.5, 0.0, 1.5])
+    Kc = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.05
+    G = Kc @ np.array([0.3, 0.05, 0.2]) + sig * np.random.default_rng(9).standard_normal(11)
+    pc = workloads.Problem(K=Kc, G=G, sigma=np.full(11, sig), block_start=np.array([0, 3]))
+    coarse = orc.run(orc.prepare(pc), chains=32, burnin=200, sweeps=20000, groups=32)
+    pf = workloads.Problem(K=np.repeat(Kc / 2.0, 2, axis=1), G=G, sigma=np.full(11, sig),
+                           block_start=np.array([0, 6]), prior_shape=np.full(6, 0.5))
+    plan = pk.Plan([pf], chains=512, burnin=200, sweeps=4000, seed=7, precision="fp64", groups=32)
+    res = plan.run()
+    m = res.mean.cpu().numpy().reshape(3, 2).mean(axis=1)
+    se = np.sqrt((res.stderr.cpu().numpy().reshape(3, 2) ** 2).sum(axis=1)) / 2   # upper bound
+    z = np.abs(m - coarse.mean) / np.sqrt(se ** 2 + coarse.stderr ** 2)
+    assert np.max(z) < 4.5, (m, coarse.mean, z)
+    assert res.stats["rejected"] > 0
+    plan.close()
+
+
+def test_gamma_prior_errors(pk):
+    p = workloads.small_problem(M=21, N=12, nblocks=2, seed=3)
+    p.prior_shape = np.ones(12)
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp32", groups=4)
+    assert e.value.code == pk.ASM_EINVAL
+    p.prior_shape = np.r_[np.ones(11), 0.0]
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp64", groups=4)
+    assert e.value.code == pk.ASM_EDOMAIN
+    # shapes of one are the flat prior: the same chains as without a prior, nothing rejected
+    p.prior_shape = np.ones(12)
+    a = pk.Plan([p], chains=8, burnin=0, sweeps=50, precision="fp64", groups=4, seed=3)
+    ra = a.run()
+    p.prior_shape = None
+    b = pk.Plan([p], chains=8, burnin=0, sweeps=50, precision="fp64", groups=4, seed=3)
+    rb = b.run()
+    assert np.array_equal(ra.mean.cpu().numpy(), rb.mean.cpu().numpy())
+    assert ra.stats["rejected"] == 0
+    a.close()
+    b.close()
