@@ -88,6 +88,9 @@ struct asm_plan {
     size_t lds32 = 0, lds64 = 0;
     bool any_cov = false;
     bool any_levels = false;   // a problem with a hierarchy of partitions
+    float *wm1f = nullptr;     // float32 exponents w_n - 1 of the gamma priors (float32 plans)
+    // the float32 sampler's extended instances: hierarchies and gamma priors
+    bool ext() const { return any_levels || any_prior; }
     std::vector<int32_t> lvl;  // level table (pairs: first block of the problem's, count)
     int32_t *d_lvl = nullptr;
     bool ran = false;
@@ -218,8 +221,6 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
         TRY(parse_partition(q, p, &part));
         for (int64_t b = 0; b < q.B; ++b)
             if (q.k && q.k[b] < 0) return fail(ASM_EINVAL, "problem %lld: k must be >= 0", (long long)p);
-        if (q.prior_shape && o->precision != ASM_FP64)
-            return fail(ASM_EINVAL, "problem %lld: prior_shape needs ASM_FP64", (long long)p);
     }
     return ASM_OK;
 }
@@ -344,7 +345,8 @@ SampleArgs make_args(asm_plan *pl) {
     a.p_zs = pl->p_zs;
     a.lvl = pl->d_lvl;
     a.shape = pl->shape;
-    a.hier = pl->any_levels ? 1 : 0;
+    a.hier = pl->ext() ? 1 : 0;
+    a.wm1f = pl->wm1f;
     return a;
 }
 
@@ -563,7 +565,7 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
         Partition part;
         TRY(parse_partition(pr[p], p, &part));
         key += ";" + std::to_string(part.lcount.size());
-        hier |= part.lcount.size() > 1 ? 1 : 0;
+        hier |= (part.lcount.size() > 1 || pr[p].prior_shape) ? 1 : 0;
         for (int64_t b = 0; b < pr[p].B; ++b) {
             const int64_t nb = part.nb[b];
             max_nb = std::max(max_nb, nb);
@@ -955,6 +957,18 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (hflags & 2) { rc = fail(ASM_EDOMAIN, "non-finite value in K, G, cov or init"); return rc; }
     if (hflags & 4) { rc = fail(ASM_EDOMAIN, "sigma must be positive and finite"); return rc; }
     if (hflags & 16) { rc = fail(ASM_EDOMAIN, "prior_shape must be positive and finite"); return rc; }
+    if (pl->fp32 && pl->any_prior) {
+        // the float32 sampler's exponents w_n - 1 (problems without a prior: 0)
+        std::vector<double> w(offn, 1.0);
+        for (int64_t p = 0; p < n; ++p)
+            if (pr[p].prior_shape)
+                HSTEP(hipMemcpy(w.data() + pl->probs[p].off_n, pr[p].prior_shape, pr[p].N * sizeof(double),
+                                hipMemcpyDeviceToHost));
+        std::vector<float> f(offn);
+        for (int64_t i = 0; i < offn; ++i) f[i] = (float)(w[i] - 1.0);
+        STEP(dalloc(pl, &pl->wm1f, offn));
+        HSTEP(hipMemcpy(pl->wm1f, f.data(), offn * sizeof(float), hipMemcpyHostToDevice));
+    }
     if (std::any_of(has_init.begin(), has_init.end(), [](int v) { return v; })) {
         std::vector<double> h(offn);
         HSTEP(hipMemcpy(h.data(), tmpN, offn * sizeof(double), hipMemcpyDeviceToHost));
@@ -1031,7 +1045,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             bool found = false;
             for (int cand : order) {
                 if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;
-                if (sample32_pick(cand, pl->max_nb, pl->max_m, pl->any_levels ? 1 : 0, &ept, &rpt, &pf) == 0) {
+                if (sample32_pick(cand, pl->max_nb, pl->max_m, pl->ext() ? 1 : 0, &ept, &rpt, &pf) == 0) {
                     L = cand;
                     found = true;
                     break;
@@ -1078,7 +1092,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             if (with_u) off += u_bytes;
             off = (off + 15) / 16 * 16;
             pl->lds_off_unif = (int64_t)off;
-            off += (size_t)cpw * row * sizeof(float);
+            off += (size_t)cpw * row * sizeof(float) * (pl->any_prior ? 2 : 1);   // prior: acceptance rows
             return off;
         };
         // chains per workgroup: enough workgroups for every CU, at most 512 threads (256 for
@@ -1103,12 +1117,12 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pl->chunk.u_rows = pl->u_lds ? max_kb : 0;
         pl->chunk.mp = mp;
         pl->chunk.words = (int64_t)(vw_bytes + d_bytes + (pl->u_lds ? u_bytes : 0)) / 16;
-        pl->chunk.compact = pl->any_levels ? 1 : 0;
+        pl->chunk.compact = pl->ext() ? 1 : 0;   // the extended instances stage packed chunks
         for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
         STEP(dalloc(pl, &pl->F32, pl->blocks.size() * pl->chunk.words));
         // the next block's chunk is prefetched into registers when it fits the instance's
         // per-thread budget (not with a hierarchy, whose blocks are staged to their own size)
-        pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw && !pl->any_levels) ? 1 : 0;
+        pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw && !pl->ext()) ? 1 : 0;
         // two roles (data modes of the next block beside the zero modes of this one) when the
         // instance, the partitions (two blocks or more) and the staging areas allow it
         {
@@ -1117,7 +1131,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             bool ok = o->roles != 1 && L == 16 && pl->u_lds &&
                       (o->roles == 2 || pl->total_chains >= 16LL * max_cu) &&
                       sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
-            for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1;
+            for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1 && !pd.has_prior;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
             // zero modes the data role runs per block, balancing the two roles: a data move
             // costs about kDataOverZero zero moves
@@ -1160,7 +1174,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 pl->p_zs = (int32_t)zs;
             } else if (o->roles == 2) {
                 rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, the (7, 13) instance, two blocks or "
-                                      "more per problem, no hierarchy and the staging areas in LDS");
+                                      "more per problem, no hierarchy or prior, and the staging areas in LDS");
                 return rc;
             }
         }

@@ -112,8 +112,11 @@ struct SampleArgs {
     int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
     const int32_t *lvl;       // level table: (first block relative to the problem's, count)
     const double *shape;      // gamma-prior shapes w_n (problems with has_prior, at off_n)
-    int32_t hier;             // 1: a problem has a hierarchy of partitions (float32: the instances
-                              //    that draw a level per sweep and stage each block to its size)
+    const float *wm1f;        // the same as float32 exponents w_n - 1 (float32 sampler)
+    int32_t hier;             // 1: a problem has a hierarchy of partitions or a gamma prior
+                              //    (float32: the extended instances, which draw a level per
+                              //    sweep, stage each block to its size, and test moves against
+                              //    the prior)
     int32_t pad2;
 };
 

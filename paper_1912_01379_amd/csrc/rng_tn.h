@@ -62,10 +62,12 @@ __host__ __device__ __forceinline__ uint32_t sweep_level(uint64_t seed, uint32_t
     return (uint32_t)(((uint64_t)o.x * levels) >> 32);
 }
 
-// float32 uniforms: one Philox call serves four consecutive modes (tag 1 in the last word)
+// float32 uniforms: one Philox call serves four consecutive modes (tag 1 in the last word;
+// tag 4 for the acceptance tests of a gamma prior)
 __device__ __forceinline__ U4 move_words32(uint64_t seed, uint32_t problem, uint32_t chain,
-                                           uint32_t sweep, uint32_t block, uint32_t quad) {
-    U4 c{chain, sweep, (block << 16) | quad, 1u};
+                                           uint32_t sweep, uint32_t block, uint32_t quad,
+                                           uint32_t tag = 1u) {
+    U4 c{chain, sweep, (block << 16) | quad, tag};
     return philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32) ^ problem);
 }
 

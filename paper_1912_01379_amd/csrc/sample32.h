@@ -97,11 +97,45 @@ __device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float 
 // into it, every A_q + delta V_q is non-negative before rounding, hence after it, and no
 // component needs clamping.  Every zero mode has a finite interval: a mode whose V has
 // entries of only one sign makes the posterior improper and is rejected before sampling.
+// Gamma-prior weights prod_q A_q^(w_q - 1) (Sec. VI): per lane the exponents w_q - 1 of its
+// components (0 on padding) and their log2, kept current so that a move needs one logarithm
+// per component; rejections are counted on the chain's first lane.
+template <int EPT>
+struct PriorRegs {
+    float W[EPT];
+    float Lg[EPT];
+    unsigned rej;
+};
+
+// The acceptance test of a proposed step: log2 u' < sum_q (w_q - 1) log2(A'_q / A_q), a term
+// being 0 where w_q = 1 or A'_q = A_q (the infinite cases at A = 0 follow the signs).
+// Returns the step, or 0 when rejected; every lane of the chain takes the same decision.
 template <int L, int EPT>
-__device__ __forceinline__ void zero_move(const float2 (&vw)[EPT], float (&Ar)[EPT], float u) {
+__device__ __forceinline__ float prior_accept(const float2 (&vw)[EPT], const float (&Ar)[EPT],
+                                              PriorRegs<EPT> &pr, float delta, float ua, int lane) {
+    float Ln[EPT];
+    float lr = 0.0f;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const float an = fmaf(delta, vw[t].x, Ar[t]);
+        Ln[t] = __log2f(an);
+        lr += (pr.W[t] == 0.0f || an == Ar[t]) ? 0.0f : pr.W[t] * (Ln[t] - pr.Lg[t]);
+    }
+    lr = seg_sum<L>(lr);
+    const bool acc = __log2f(ua) < lr;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) pr.Lg[t] = acc ? Ln[t] : pr.Lg[t];
+    pr.rej += (!acc && lane == 0) ? 1u : 0u;
+    return acc ? delta : 0.0f;
+}
+
+template <int L, int EPT, bool P = false>
+__device__ __forceinline__ void zero_move(const float2 (&vw)[EPT], float (&Ar)[EPT], float u,
+                                          PriorRegs<EPT> *pr = nullptr, float ua = 0.0f, int lane = 0) {
     float lo, hi;
     interval32<L, EPT, true>(vw, Ar, lo, hi);
-    const float delta = __builtin_amdgcn_fmed3f(fmaf(u, hi - lo, lo), lo, hi);
+    float delta = __builtin_amdgcn_fmed3f(fmaf(u, hi - lo, lo), lo, hi);
+    if constexpr (P) delta = prior_accept<L, EPT>(vw, Ar, *pr, delta, ua, lane);
 #pragma unroll
     for (int t = 0; t < EPT; ++t) Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
 }
@@ -113,9 +147,10 @@ __device__ __forceinline__ void load_row(float2 (&vw)[EPT], const float2 *row, i
 }
 
 // One data-mode move: interval, c = U_i . r, the truncated-normal step, the updates of A and r.
-template <int L, int EPT, int RPT>
+template <int L, int EPT, int RPT, bool P = false>
 __device__ __forceinline__ void data_move(const float2 (&vw)[EPT], const float (&Ui)[RPT], float u, float dd,
-                                          float (&Ar)[EPT], float (&rr)[RPT]) {
+                                          float (&Ar)[EPT], float (&rr)[RPT], PriorRegs<EPT> *pr = nullptr,
+                                          float ua = 0.0f, int lane = 0) {
     float lo, hi;
     interval32<L, EPT, false>(vw, Ar, lo, hi);
     float c0 = 0.0f, c1 = 0.0f;   // two partial sums for a shorter dependence chain
@@ -124,7 +159,8 @@ __device__ __forceinline__ void data_move(const float2 (&vw)[EPT], const float (
 #pragma unroll
     for (int t = 1; t < RPT; t += 2) c1 = fmaf(Ui[t], rr[t], c1);
     const float cdot = seg_sum<L>(c0 + c1);
-    const float delta = tn_draw32(cdot, dd, lo, hi, u);
+    float delta = tn_draw32(cdot, dd, lo, hi, u);
+    if constexpr (P) delta = prior_accept<L, EPT>(vw, Ar, *pr, delta, ua, lane);
     const float e = delta * dd;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
@@ -141,10 +177,11 @@ __device__ __forceinline__ void load_u(float (&Ui)[RPT], const float *U, int row
 
 // The data-mode moves of one block (d_i > 0, modes 0..kb-1), two per iteration with the next
 // (V, w) and U rows loaded one move ahead.  On entry vw holds row 0; on return row kb.
-template <int L, int EPT, int RPT, bool ULDS>
+template <int L, int EPT, int RPT, bool ULDS, bool P = false>
 __device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const float *sD, const float *U,
                                            const float *urow, int lane, float2 (&vw)[EPT], float (&Ar)[EPT],
-                                           float (&rr)[RPT]) {
+                                           float (&rr)[RPT], PriorRegs<EPT> *pr = nullptr,
+                                           const float *urowA = nullptr) {
     constexpr int ROW = EPT * L;
     if (kb <= 0) return;
     float Ua[RPT], Ub[RPT];
@@ -155,15 +192,46 @@ __device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const floa
         load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
         load_u<L, RPT>(Ub, U, i + 1, lane);
         const float u0 = urow[i], u1 = urow[i + 1], d0 = sD[i], d1 = sD[i + 1];
-        data_move<L, EPT, RPT>(vw, Ua, u0, d0, Ar, rr);
+        float a0 = 0.0f, a1 = 0.0f;
+        if constexpr (P) {
+            a0 = urowA[i];
+            a1 = urowA[i + 1];
+        }
+        data_move<L, EPT, RPT, P>(vw, Ua, u0, d0, Ar, rr, pr, a0, lane);
         load_row<EPT>(vw, sVW + (i + 2) * ROW, lane, L);
         load_u<L, RPT>(Ua, U, i + 2 < kb ? i + 2 : i + 1, lane);
-        data_move<L, EPT, RPT>(vb, Ub, u1, d1, Ar, rr);
+        data_move<L, EPT, RPT, P>(vb, Ub, u1, d1, Ar, rr, pr, a1, lane);
     }
     if (i < kb) {
-        data_move<L, EPT, RPT>(vw, Ua, urow[i], sD[i], Ar, rr);
+        float a0 = 0.0f;
+        if constexpr (P) a0 = urowA[i];
+        data_move<L, EPT, RPT, P>(vw, Ua, urow[i], sD[i], Ar, rr, pr, a0, lane);
         load_row<EPT>(vw, sVW + (i + 1) * ROW, lane, L);
     }
+}
+
+// The zero modes of one block (modes kb..nb-1) with the gamma-prior test, three per iteration,
+// each row loaded two moves ahead, as in the sampler's own loop.  On entry vw holds row kb.
+template <int L, int EPT, bool P>
+__device__ __forceinline__ void zero_moves(int kb, int nb, const float2 *sVW, const float *urow,
+                                           const float *urowA, int lane, float2 (&vw)[EPT],
+                                           float (&Ar)[EPT], PriorRegs<EPT> *pr) {
+    constexpr int ROW = EPT * L;
+    int i = kb;
+    float2 vb[EPT], vc[EPT];
+    load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
+    auto ua = [&](int j) { return P ? urowA[j] : 0.0f; };
+    for (; i + 3 <= nb; i += 3) {
+        load_row<EPT>(vc, sVW + (i + 2) * ROW, lane, L);
+        const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
+        zero_move<L, EPT, P>(vw, Ar, u0, pr, ua(i), lane);
+        load_row<EPT>(vw, sVW + (i + 3) * ROW, lane, L);
+        zero_move<L, EPT, P>(vb, Ar, u1, pr, ua(i + 1), lane);
+        load_row<EPT>(vb, sVW + (i + 4) * ROW, lane, L);
+        zero_move<L, EPT, P>(vc, Ar, u2, pr, ua(i + 2), lane);
+    }
+    if (i < nb) zero_move<L, EPT, P>(vw, Ar, urow[i], pr, ua(i), lane);
+    if (i + 1 < nb) zero_move<L, EPT, P>(vb, Ar, urow[i + 1], pr, ua(i + 1), lane);
 }
 
 // Copy a block's factor chunk (the image of the staging area) to LDS with all threads,
@@ -272,6 +340,11 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
             rr[t] = (m < M && active) ? rg[m] : 0.0f;
         }
         float *urow = sUnif + slotc * ROW;
+        // gamma prior: the acceptance uniforms in a second row per chain, after the first rows
+        const bool PRI = H && pd.has_prior;
+        float *urowA = sUnif + (nthr / L + slotc) * ROW;
+        PriorRegs<EPT> pr;
+        pr.rej = 0;
         const int nw = (int)a.chunk_words;
         float4 *stage = reinterpret_cast<float4 *>(smem32);
         // the blocks of a sweep: all of the partition, or of the sweep's level of a hierarchy
@@ -334,6 +407,14 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 float Ar[EPT];
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
+                if (PRI) {
+#pragma unroll
+                    for (int t = 0; t < EPT; ++t) {
+                        const int q = lane + L * t;
+                        pr.W[t] = q < nb ? a.wm1f[pd.off_n + bd.n0 + q] : 0.0f;
+                        pr.Lg[t] = __log2f(Ar[t]);
+                    }
+                }
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 // the block's singular values and U rows in LDS: at the plan's fixed offsets, or,
                 // for a hierarchy, right after the block's own rows (its chunk is packed to its
@@ -358,6 +439,15 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     d[1] = word_u32(w.y);
                     d[2] = word_u32(w.z);
                     d[3] = word_u32(w.w);
+                    if (PRI) {
+                        const U4 x = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
+                                                  (uint32_t)b, (uint32_t)g, 4u);
+                        float *e = urowA + 4 * g;
+                        e[0] = word_u32(x.x);
+                        e[1] = word_u32(x.y);
+                        e[2] = word_u32(x.z);
+                        e[3] = word_u32(x.w);
+                    }
                 }
                 __syncthreads();
                 store_prev();
@@ -366,7 +456,13 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 load_row<EPT>(vw, sVW, lane, L);
                 // data modes (U rows from LDS, or from global memory when they do not fit;
                 // two copies of the loop, so the LDS one waits on no global loads)
-                if (a.u_lds)
+                if (PRI) {
+                    if (a.u_lds)
+                        data_moves<L, EPT, RPT, true, true>(kb, sVW, sDb, sUb, urow, lane, vw, Ar, rr, &pr, urowA);
+                    else
+                        data_moves<L, EPT, RPT, false, true>(kb, sVW, sDb, Ug, urow, lane, vw, Ar, rr, &pr, urowA);
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                } else if (a.u_lds)
                     data_moves<L, EPT, RPT, true>(kb, sVW, sDb, sUb, urow, lane, vw, Ar, rr);
                 else {
                     data_moves<L, EPT, RPT, false>(kb, sVW, sDb, Ug, urow, lane, vw, Ar, rr);
@@ -390,8 +486,10 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 }
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
-                int i = kb;
-                {
+                if (PRI) {
+                    zero_moves<L, EPT, true>(kb, nb, sVW, urow, urowA, lane, vw, Ar, &pr);
+                } else {
+                    int i = kb;
                     float2 vb[EPT], vc[EPT];
                     load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
                     for (; i + 3 <= nb; i += 3) {
@@ -451,6 +549,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
             const int m = lane + L * t;
             if (active && m < M) rg[m] = rr[t];
         }
+        if (PRI && active && pr.rej) atomicAdd(&a.counters[2], (unsigned long long)pr.rej);
     }
 }
 

@@ -772,9 +772,10 @@ def test_fp64_gamma_prior_trajectory_matches_oracle(pk, orc, nblocks, levels):
     plan.close()
 
 
-def test_gamma_prior_halved_grid_on_gpu(pk, orc):
-    """The halved-grid identity of Eq. (genconsistency) on the float64 sampler: pair averages
-    with shape 1/2 against the oracle's flat-prior average of the coarse grid."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gamma_prior_halved_grid_on_gpu(pk, orc, precision):
+    """The halved-grid identity of Eq. (genconsistency) on both samplers: pair averages with
+    shape 1/2 against the oracle's flat-prior average of the coarse grid."""
     beta = 10.0
     tau = workloads.imaginary_times(11, beta)
     x = np.array([-1.5, 0.0, 1.5])
@@ -785,7 +786,8 @@ def test_gamma_prior_halved_grid_on_gpu(pk, orc):
     coarse = orc.run(orc.prepare(pc), chains=32, burnin=200, sweeps=20000, groups=32)
     pf = workloads.Problem(K=np.repeat(Kc / 2.0, 2, axis=1), G=G, sigma=np.full(11, sig),
                            block_start=np.array([0, 6]), prior_shape=np.full(6, 0.5))
-    plan = pk.Plan([pf], chains=512, burnin=200, sweeps=4000, seed=7, precision="fp64", groups=32)
+    chains, sweeps = (512, 4000) if precision == "fp64" else (4096, 2000)
+    plan = pk.Plan([pf], chains=chains, burnin=200, sweeps=sweeps, seed=7, precision=precision, groups=32)
     res = plan.run()
     m = res.mean.cpu().numpy().reshape(3, 2).mean(axis=1)
     se = np.sqrt((res.stderr.cpu().numpy().reshape(3, 2) ** 2).sum(axis=1)) / 2   # upper bound
@@ -795,24 +797,74 @@ def test_gamma_prior_halved_grid_on_gpu(pk, orc):
     plan.close()
 
 
-def test_gamma_prior_errors(pk):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gamma_prior_errors_and_flat_shapes(pk, precision):
     p = workloads.small_problem(M=21, N=12, nblocks=2, seed=3)
-    p.prior_shape = np.ones(12)
-    with pytest.raises(pk.AsmError) as e:
-        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp32", groups=4)
-    assert e.value.code == pk.ASM_EINVAL
     p.prior_shape = np.r_[np.ones(11), 0.0]
     with pytest.raises(pk.AsmError) as e:
-        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp64", groups=4)
+        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision=precision, groups=4)
     assert e.value.code == pk.ASM_EDOMAIN
     # shapes of one are the flat prior: the same chains as without a prior, nothing rejected
-    p.prior_shape = np.ones(12)
-    a = pk.Plan([p], chains=8, burnin=0, sweeps=50, precision="fp64", groups=4, seed=3)
-    ra = a.run()
-    p.prior_shape = None
-    b = pk.Plan([p], chains=8, burnin=0, sweeps=50, precision="fp64", groups=4, seed=3)
-    rb = b.run()
-    assert np.array_equal(ra.mean.cpu().numpy(), rb.mean.cpu().numpy())
-    assert ra.stats["rejected"] == 0
-    a.close()
-    b.close()
+    # (float32: the prior runs in the extended instance, the flat problem in the plain one)
+    out = []
+    for shape in (np.ones(12), None):
+        p.prior_shape = shape
+        plan = pk.Plan([p], chains=64, burnin=0, sweeps=50, precision=precision, groups=4, seed=3,
+                       lanes_per_chain=16 if precision == "fp32" else 0, roles=1)
+        res = plan.run()
+        out.append((res.mean.cpu().numpy(), res.stats["rejected"]))
+        plan.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == 0 and out[1][1] == 0
+
+
+@pytest.mark.parametrize("lanes", [4, 16, 32])
+def test_fp32_gamma_prior_average_matches_oracle(pk, orc, lanes):
+    """The float32 sampler with shapes w_n in [0.5, 2] against an oracle run (R17)."""
+    p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
+    p.prior_shape = np.random.default_rng(6).uniform(0.5, 2.0, 48)
+    prep = orc.prepare(p)
+    ores = orc.run(prep, chains=64, burnin=300, sweeps=3000, groups=32, seed=3)
+    plan = pk.Plan([p], chains=256, burnin=300, sweeps=3000, seed=4, precision="fp32", groups=32,
+                   lanes_per_chain=lanes)
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
+    assert ok, info
+    # rejection rates agree
+    rate_gpu = res.stats["rejected"] / res.stats["mode_moves"]
+    rate_orc = ores.n_rejected / (64 * 3300 * 48)
+    assert abs(rate_gpu - rate_orc) < 0.1 * rate_orc + 1e-4, (rate_gpu, rate_orc)
+    plan.close()
+
+
+@pytest.mark.parametrize("w", [0.5, 2.0])
+def test_fp32_gamma_prior_sum_rule_closed_form(pk, w):
+    """K = 1^T, g = 1 with shapes w: <A_n> = E[S] / N, S ~ S^(N w - 1) exp(-(S - 1)^2 / 2 sigma^2)."""
+    from scipy import integrate
+    N, sig = 8, 0.3
+    ws = lambda S, j: S ** (N * w - 1 + j) * math.exp(-0.5 * ((S - 1.0) / sig) ** 2)
+    Z = integrate.quad(lambda S: ws(S, 0), 0, 10, points=[1e-3, 1.0], limit=400)[0]
+    EA = integrate.quad(lambda S: ws(S, 1), 0, 10, limit=400)[0] / Z / N
+    p = workloads.Problem(K=np.ones((1, N)), G=np.array([1.0]), sigma=np.array([sig]),
+                          block_start=np.array([0, 4, 8]), prior_shape=np.full(N, w))
+    plan = pk.Plan([p], chains=4096, burnin=300, sweeps=2000, seed=9, precision="fp32", groups=32)
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), np.full(N, EA), np.zeros(N))
+    assert ok, info
+    plan.close()
+
+
+def test_fp32_gamma_prior_on_a_hierarchy_keeps_state_consistent(pk):
+    N = 120
+    p = workloads.optical_conductivity(N, 1)
+    p.levels = pk.hierarchy(N)
+    p.prior_shape = np.full(N, 0.5)
+    plan = pk.Plan([p], chains=200, burnin=0, sweeps=1, precision="fp32", groups=8,
+                   refresh_every=0, lanes_per_chain=16, start="nnls")
+    plan.advance(100)
+    A, r, _ = plan.state(0)
+    Kt, gt = plan.whitened(0)
+    rr = gt[None, :] - A @ Kt.T
+    assert float((rr - r).abs().max()) <= 1e-3 * float(rr.abs().max())
+    assert float(A.min()) >= 0.0
+    plan.close()
