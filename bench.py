@@ -174,58 +174,83 @@ def conductivity(args):
     """The paper's own test case (optical conductivity, bosonic kernel, Sec. II) on both grids
     of Fig. 3 (40 and 120 points) with components, modes, blocked modes on one partition of
     4 blocks, and blocked modes on the hierarchy of Fig. 2 (a random level per sweep):
-    mode-moves/s, ESS/s and the median step size Delta_i of Fig. 3."""
+    mode-moves/s, ESS/s and the median step size Delta_i of Fig. 3.  Then Fig. 7 (Sec. VI):
+    the flat prior of a grid of spacing 0.2 (60 points) simulated on the 120-point grid with
+    gamma shapes 1/2, and the 120-point grid simulated on the 60-point one with shapes 2,
+    compared through the averages over each pair of fine intervals."""
     import torch
     import workloads
     import paper_1912_01379_amd as pk
     dev = torch.device("cuda:0")
-    rows = {}
-    for n in (40, 120):
-        for name, nb in (("components", n), ("modes", 1), ("blocked4", 4), ("hierarchy", 1)):
-            if args.cases and f"N{n}_{name}" not in args.cases.split(","):
-                continue
-            p = workloads.optical_conductivity(n, nb)
-            if name == "hierarchy":
-                p.levels = pk.hierarchy(n)
-            dp = _DevProblem(p, dev)
-            plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2026,
-                           precision="fp32", refresh_every=64, groups=32, lanes_per_chain=args.lanes,
-                           start="nnls", use_graph=False, device=dev)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = plan.run()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            # the sampler's lane-operations per chain-sweep, averaged over the levels (uniform)
-            parts = p.levels if p.levels is not None else [p.block_start]
-            ops, blk = [], 0
-            for cuts in parts:
-                lv = []
-                for b in range(len(cuts) - 1):
-                    nb = int(cuts[b + 1] - cuts[b])
-                    lv.append((nb, plan.factors(0, blk, nb)[0]))
-                    blk += 1
-                ops.append(lane_ops_per_sweep(p.M, lv))
-            st = res.stats
-            us_sweep = 1e3 * st["sampler_ms"] / max(1, st["sampler_sweeps"])
-            frac = float(np.mean(ops)) * args.chains / (us_sweep * 1e-6) / PEAK_LANE_OPS
-            se, sd = res.stderr.cpu().numpy(), res.post_sd.cpu().numpy()
-            ess = (sd / se) ** 2
-            prev = plan.state(0)[0].cpu().numpy()
-            steps = []
-            for _ in range(50):
-                plan.advance(1)
-                cur = plan.state(0)[0].cpu().numpy()
-                steps.append(np.linalg.norm(cur - prev, axis=1) / np.linalg.norm(prev, axis=1))
-                prev = cur
-            plan.close()
-            rows[f"N{n}_{name}"] = {
-                "mode_moves_per_s": args.chains * (args.burnin + args.sweeps) * n / dt,
-                "ess_per_s_min": float(np.nanmin(ess)) / dt, "ess_per_s_median": float(np.nanmedian(ess)) / dt,
-                "median_step": float(np.median(np.concatenate(steps))),
-                "sampler_us_per_sweep": us_sweep, "alu_frac": frac,
-                "lanes_per_chain": res.stats["lanes_per_chain"], "roles": res.stats["roles"]}
-            print(f"{n} {name} done", file=sys.stderr, flush=True)
+    rows, means = {}, {}
+    cases = [(f"N{n}_{name}", n, nb, 0.1, name == "hierarchy", None)
+             for n in (40, 120)
+             for name, nb in (("components", n), ("modes", 1), ("blocked4", 4), ("hierarchy", 1))]
+    cases += [("N60s2_blocked4", 60, 4, 0.2, False, None), ("N120_prior60", 120, 4, 0.1, False, 0.5),
+              ("N60s2_prior120", 60, 4, 0.2, False, 2.0)]
+    for key, n, nb, step, hier, shape in cases:
+        if args.cases and key not in args.cases.split(","):
+            continue
+        p = workloads.optical_conductivity(n, nb, step=step)
+        if hier:
+            p.levels = pk.hierarchy(n)
+        if shape is not None:
+            p.prior_shape = np.full(n, shape)
+        dp = _DevProblem(p, dev)
+        plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2026,
+                       precision="fp32", refresh_every=64, groups=32, lanes_per_chain=args.lanes,
+                       start="nnls", use_graph=False, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # the sampler's lane-operations per chain-sweep, averaged over the levels (uniform)
+        parts = p.levels if p.levels is not None else [p.block_start]
+        ops, blk = [], 0
+        for cuts in parts:
+            lv = []
+            for b in range(len(cuts) - 1):
+                nb = int(cuts[b + 1] - cuts[b])
+                lv.append((nb, plan.factors(0, blk, nb)[0]))
+                blk += 1
+            ops.append(lane_ops_per_sweep(p.M, lv))
+        st = res.stats
+        us_sweep = 1e3 * st["sampler_ms"] / max(1, st["sampler_sweeps"])
+        frac = float(np.mean(ops)) * args.chains / (us_sweep * 1e-6) / PEAK_LANE_OPS
+        se, sd = res.stderr.cpu().numpy(), res.post_sd.cpu().numpy()
+        ess = (sd / se) ** 2
+        prev = plan.state(0)[0].cpu().numpy()
+        steps = []
+        for _ in range(50):
+            plan.advance(1)
+            cur = plan.state(0)[0].cpu().numpy()
+            steps.append(np.linalg.norm(cur - prev, axis=1) / np.linalg.norm(prev, axis=1))
+            prev = cur
+        plan.close()
+        means[key] = (res.mean.cpu().numpy(), se)
+        rows[key] = {
+            "mode_moves_per_s": args.chains * (args.burnin + args.sweeps) * n / dt,
+            "rejected_frac": res.stats["rejected"] / max(1.0, res.stats["mode_moves"]),
+            "ess_per_s_min": float(np.nanmin(ess)) / dt, "ess_per_s_median": float(np.nanmedian(ess)) / dt,
+            "median_step": float(np.median(np.concatenate(steps))),
+            "sampler_us_per_sweep": us_sweep, "alu_frac": frac,
+            "lanes_per_chain": res.stats["lanes_per_chain"], "roles": res.stats["roles"]}
+        print(f"{key} done", file=sys.stderr, flush=True)
+
+    # Fig. 7: relative L2 distance of the averages, fine grids compared through the average of
+    # each pair of fine intervals (the coarse interval they make up)
+    pair = lambda m: m.reshape(-1, 2).mean(axis=1)
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+    fig7 = {}
+    if all(k in means for k in ("N120_prior60", "N60s2_blocked4", "N120_blocked4")):
+        fig7["coarse_flat_simulated_on_fine"] = {
+            "rel_l2_to_coarse_flat": rel(pair(means["N120_prior60"][0]), means["N60s2_blocked4"][0]),
+            "fine_flat_rel_l2_to_coarse_flat": rel(pair(means["N120_blocked4"][0]), means["N60s2_blocked4"][0])}
+    if all(k in means for k in ("N60s2_prior120", "N60s2_blocked4", "N120_blocked4")):
+        fig7["fine_flat_simulated_on_coarse"] = {
+            "rel_l2_to_fine_flat": rel(means["N60s2_prior120"][0], pair(means["N120_blocked4"][0])),
+            "coarse_flat_rel_l2_to_fine_flat": rel(means["N60s2_blocked4"][0], pair(means["N120_blocked4"][0]))}
     main_row = rows.get("N120_hierarchy", next(iter(rows.values())))
     print(json.dumps({"metric": "mode-moves/s", "value": main_row["mode_moves_per_s"], "unit": "mode-moves/s",
                       "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
@@ -234,7 +259,7 @@ def conductivity(args):
                                              "beta 15, relative noise 1e-3, grids of 40 and 120 points; value: "
                                              "120 points, Fig. 2 hierarchy",
                                  "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps},
-                      "cases": rows}))
+                      "cases": rows, "fig7": fig7}))
 
 
 def main():
