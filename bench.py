@@ -279,7 +279,7 @@ def main():
     ap.add_argument("--cases", default="", help="conductivity workload: comma list such as N120_hierarchy")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; use --gpus 1"}))
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
