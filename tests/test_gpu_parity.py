@@ -868,3 +868,26 @@ def test_fp32_gamma_prior_on_a_hierarchy_keeps_state_consistent(pk):
     assert float((rr - r).abs().max()) <= 1e-3 * float(rr.abs().max())
     assert float(A.min()) >= 0.0
     plan.close()
+
+
+def test_fp32_mixed_batch_of_hierarchy_prior_and_plain_problems(pk, orc):
+    """One float32 plan holding a hierarchy, a gamma prior and a plain partition (different M,
+    N and blocks): each problem's average against its own oracle run (R17)."""
+    ph = workloads.optical_conductivity(40, 1)
+    ph.levels = orc.hierarchy(40)
+    pp = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3, seed=21)
+    pp.prior_shape = np.random.default_rng(8).uniform(0.6, 1.8, 48)
+    pq = workloads.small_problem(M=33, N=30, nblocks=2, sigma=2e-3, seed=22)
+    probs = [ph, pp, pq]
+    plan = pk.Plan(probs, chains=512, burnin=300, sweeps=2000, seed=12, precision="fp32", groups=32,
+                   start="nnls")
+    res = plan.run()
+    means, ses = res.split([p.N for p in probs])[:2]
+    for i, p in enumerate(probs):
+        prep = orc.prepare(p)
+        o = orc.run(prep, chains=64, burnin=300, sweeps=2000, seed=40 + i, groups=32,
+                    init=orc.nnls_start(prep))
+        ok, info = zscore_ok(means[i].cpu().numpy(), ses[i].cpu().numpy(), o.mean, o.stderr)
+        assert ok, (i, info)
+    assert res.stats["rejected"] > 0
+    plan.close()
