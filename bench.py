@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--workload", choices=["single", "batched", "conductivity"], default="single")
     ap.add_argument("--graph", action="store_true", help="replay refresh cycles from a hipGraph")
     ap.add_argument("--cases", default="", help="conductivity workload: comma list such as N120_hierarchy")
+    ap.add_argument("--hierarchy", action="store_true",
+                    help="single-continuation workload on the Fig. 2 hierarchy instead of its 8 blocks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; use --gpus 1"}))
@@ -297,6 +299,11 @@ def main():
 
     dev = torch.device("cuda:0")
     prob = workloads.config2()
+    if args.hierarchy:
+        # the Fig. 2 hierarchy of the 800-point grid, levels of blocks up to 128 points (the
+        # float32 instances' largest block): 8 blocks of 100 down to the single points
+        prob.levels = pk.hierarchy(prob.N, max_block=128)
+        prob.k = np.full(prob.B, 20, np.int32)
     v = torch.as_tensor(workloads.config4_cotangent(prob.N), dtype=torch.float64, device=dev)
     dp = _DevProblem(prob, dev)
     want_vjp = not args.no_vjp
@@ -313,11 +320,14 @@ def main():
         g = plan.vjp(v) if want_vjp else None
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        blocks = []
-        for b in range(prob.B):
-            nb = int(prob.block_start[b + 1] - prob.block_start[b])
-            k = plan.factors(0, b, nb)[0]
-            blocks.append((nb, k))
+        blocks, blk = [], 0   # per level: (N_b, k_b) of its blocks
+        for cuts in prob.partitions():
+            lv = []
+            for b in range(len(cuts) - 1):
+                nb = int(cuts[b + 1] - cuts[b])
+                lv.append((nb, plan.factors(0, blk, nb)[0]))
+                blk += 1
+            blocks.append(lv)
         plan.close()
         return res, (t1 - t0), (t2 - t1), blocks, g
 
@@ -337,11 +347,12 @@ def main():
     st = res.stats
     sweeps_total = args.burnin + args.sweeps
     moves_per_step = args.chains * sweeps_total * prob.N
-    data_per_step = args.chains * sweeps_total * sum(k for _, k in blocks)
+    # levels are drawn uniformly: per-sweep counts averaged over the levels
+    data_per_step = args.chains * sweeps_total * float(np.mean([sum(k for _, k in lv) for lv in blocks]))
     value = moves_per_step * args.steps / elapsed
     step_s = elapsed / args.steps
     # roofline of the sampler kernel from its own launch events
-    ops_sweep = lane_ops_per_sweep(prob.M, blocks)
+    ops_sweep = float(np.mean([lane_ops_per_sweep(prob.M, lv) for lv in blocks]))
     avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
     ops_per_launch = ops_sweep * args.chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
     achieved = ops_per_launch / avg_launch_s
@@ -374,11 +385,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "single continuation: beta=20, M=201, N=800 Lorentzian grid, "
-                               "8 blocks x 100, k<=20, sigma=1e-4, fp32 chains, NNLS start",
+                               + ("Fig. 2 hierarchy of 7 levels (8 to 800 blocks)" if args.hierarchy else "8 blocks x 100")
+                               + ", k<=20, sigma=1e-4, fp32 chains, NNLS start",
                    "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps,
                    "vjp": want_vjp, "lanes_per_chain": st["lanes_per_chain"],
                    "chains_per_workgroup": st["chains_per_block"], "roles": st.get("roles", 1),
-                   "data_modes_per_block": [k for _, k in blocks]},
+                   "data_modes_per_block": [k for _, k in blocks[0]] if len(blocks) == 1 else None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "lane-op/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
