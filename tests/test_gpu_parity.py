@@ -891,3 +891,59 @@ def test_fp32_mixed_batch_of_hierarchy_prior_and_plain_problems(pk, orc):
         assert ok, (i, info)
     assert res.stats["rejected"] > 0
     plan.close()
+
+
+def test_graph_replay_with_hierarchy_and_prior_matches_eager(pk):
+    """The extended instances (a level drawn per sweep, the prior's acceptance test) replayed
+    from captured hipGraphs give the eager results bit for bit, over two runs."""
+    p = workloads.small_problem(M=41, N=48, nblocks=1, sigma=2e-3)
+    p.levels = pk.hierarchy(48)
+    p.prior_shape = np.random.default_rng(4).uniform(0.7, 1.5, 48)
+    kw = dict(chains=128, burnin=64, sweeps=192, seed=33, precision="fp32", groups=32,
+              refresh_every=64, lanes_per_chain=16)
+    eager = pk.Plan([p], use_graph=False, **kw)
+    graph = pk.Plan([p], use_graph=True, **kw)
+    for rep in range(2):
+        re_, rg = eager.run(), graph.run()
+        assert rg.stats["graph_replays"] == 4
+        assert re_.stats["rejected"] == rg.stats["rejected"] > 0
+        for name in ("mean", "stderr", "post_sd"):
+            assert np.array_equal(getattr(re_, name).cpu().numpy(), getattr(rg, name).cpu().numpy()), (rep, name)
+        assert np.array_equal(eager.state(0)[0].cpu().numpy(), graph.state(0)[0].cpu().numpy())
+    eager.close()
+    graph.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_one_point_grid_is_a_truncated_normal(pk, precision):
+    """The degenerate grid of one point: <A> = mu + s phi(mu/s) / Phi(mu/s) in closed form."""
+    from scipy import special, stats
+    rng = np.random.default_rng(3)
+    k = rng.uniform(0.5, 1.5, 7)
+    s = 1.0 / np.linalg.norm(k)
+    for mu_over_s in [2.0, 0.0, -3.0]:
+        mu = mu_over_s * s
+        p = workloads.Problem(K=k[:, None], G=k * mu, sigma=np.ones(7), block_start=np.array([0, 1]))
+        plan = pk.Plan([p], chains=2048, burnin=20, sweeps=500, seed=5, precision=precision, groups=32)
+        res = plan.run()
+        ref = mu + s * math.exp(stats.norm.logpdf(mu_over_s) - special.log_ndtr(mu_over_s))
+        z = abs(float(res.mean[0]) - ref) / float(res.stderr[0])
+        assert z < 4.5, (precision, mu_over_s, float(res.mean[0]), ref)
+        plan.close()
+
+
+def test_size_limits_are_reported(pk):
+    """Blocks beyond the float32 instances (128 points) and problems beyond the float64
+    sampler's LDS (N + M doubles) are refused with ASM_EINVAL, not run."""
+    rng = np.random.default_rng(1)
+    K = rng.standard_normal((30, 200))
+    p = workloads.Problem(K=K, G=K @ np.ones(200), sigma=np.ones(30), block_start=np.array([0, 200]))
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=16, burnin=0, sweeps=4, precision="fp32", groups=4)
+    assert e.value.code == pk.ASM_EINVAL
+    K = rng.standard_normal((100, 20500)) * 1e-3
+    p = workloads.Problem(K=K, G=K @ np.ones(20500), sigma=np.ones(100),
+                          block_start=workloads.equal_blocks(20500, 205))
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=2, burnin=0, sweeps=4, precision="fp64", groups=2)
+    assert e.value.code == pk.ASM_EINVAL
