@@ -172,10 +172,10 @@ def batched(args):
 
 
 def conductivity(args):
-    """The paper's own test case (optical conductivity, bosonic kernel, Sec. II) on both grids
+    """The paper's own test case (optical conductivity, bosonic kernel, Sec. III) on both grids
     of Fig. 3 (40 and 120 points) with components, modes, blocked modes on one partition of
     4 blocks, and blocked modes on the hierarchy of Fig. 2 (a random level per sweep):
-    mode-moves/s, ESS/s and the median step size Delta_i of Fig. 3.  Then Fig. 7 (Sec. VI):
+    mode-moves/s, ESS/s and the median step size Delta_i of Fig. 3.  Then Fig. 7 (Sec. V.C):
     the flat prior of a grid of spacing 0.2 (60 points) simulated on the 120-point grid with
     gamma shapes 1/2, and the 120-point grid simulated on the 60-point one with shapes 2,
     compared through the averages over each pair of fine intervals."""
@@ -196,7 +196,7 @@ def conductivity(args):
         if hier:
             p.levels = pk.hierarchy(n)
         if shape == "noise":
-            # Sec. VI's cheap variant: the data variance scaled by 120 / 60 instead of the shapes
+            # Sec. V.C's cheap variant: the data variance scaled by 120 / 60 instead of the shapes
             p.sigma = p.sigma * math.sqrt(120 / 60)
         elif shape is not None:
             p.prior_shape = np.full(n, shape)
@@ -262,7 +262,7 @@ def conductivity(args):
     print(json.dumps({"metric": "mode-moves/s", "value": main_row["mode_moves_per_s"], "unit": "mode-moves/s",
                       "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                      "config": {"workload": "optical conductivity (Sec. II): 60 bosonic Matsubara points, "
+                      "config": {"workload": "optical conductivity (Sec. III): 60 bosonic Matsubara points, "
                                              "beta 15, relative noise 1e-3, grids of 40 and 120 points; value: "
                                              "120 points, Fig. 2 hierarchy",
                                  "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps},

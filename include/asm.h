@@ -54,7 +54,7 @@ extern "C" {
 
 typedef struct asm_plan asm_plan;
 
-/* One continuation problem (Sec. II: data g with covariance C, g = K f after discretising
+/* One continuation problem (Sec. II, Sec. IV: data g with covariance C, g = K f after discretising
    f on N grid intervals, Eq. (matrixeq)).  The columns of K already contain the
    quadrature weights of the grid (Eq. (Riemann)), so A is the model on the grid. */
 typedef struct {
@@ -87,7 +87,7 @@ typedef struct {
     const int64_t *level_blocks; /* host, levels: B_l per level (sum = B); NULL when levels <= 1 */
     const double *prior_shape;   /* device, N shapes w_n > 0 of the gamma-prior weights, or NULL
                                     for the flat prior: the chains then sample
-                                    prod_n A_n^(w_n - 1) exp(-chi^2/2) on A >= 0 (Sec. VI,
+                                    prod_n A_n^(w_n - 1) exp(-chi^2/2) on A >= 0 (Sec. V.C,
                                     Eq. (gammadist) and Eq. (compat) in the limit of vanishing
                                     scale; w_n = N rho(x_n) / (N~ rho~(x_n)) simulates the flat
                                     prior of grid (N, rho) on this grid (N~, rho~)).  Each

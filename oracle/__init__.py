@@ -9,7 +9,7 @@ Steps, in the paper's order:
   2. per-block SVD K~_b = U_b D_b V_b^T, Sec. IV.B/IV.C, with d := 0 beyond the
      numerical rank (the paper's zero modes);
   3. the random walk over blocked modes (C core, `core.c`), optionally with the gamma-prior
-     weights prod_n A_n^(w_n - 1) of Sec. VI (Eq. (compat)) through an acceptance test per move;
+     weights prod_n A_n^(w_n - 1) of Sec. V.C (Eq. (compat)) through an acceptance test per move;
   4. averages of Eq. (MCint), their error bars, and the sensitivity of the average to
      the data, d<f>/dg = -Cov(f, r~) T, which follows from differentiating the
      posterior of Eq. (PI) (the normaliser depends on g).

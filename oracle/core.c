@@ -28,7 +28,9 @@
  *     (2^32 - 1, sweep, 0, 2): level = floor(w0 L / 2^32); the uniforms of a move keep the
  *     block's index within its level;
  *   - the residual is recomputed from scratch every `refresh_every` sweeps;
- *   - with gamma-prior weights prod_n A_n^(w_n - 1) (Sec. VI, Eq. (compat), the limit of
+ *   - under a linear constraint c . A = F (Sec. IV.E), a block's modes span the part of the
+ *     block orthogonal to its share of c (nm = Nb - 1 modes), so every move keeps c . A;
+ *   - with gamma-prior weights prod_n A_n^(w_n - 1) (Sec. V.C, Eq. (compat), the limit of
  *     vanishing scale), each move's draw is a proposal accepted when
  *     log u' < sum_q (w_q - 1) log(A'_q / A_q), u' the uniform of counter
  *     (chain, sweep, block << 16 | mode, 3); a rejected move leaves the state unchanged.
@@ -307,6 +309,8 @@ typedef struct {
     const double *U;        /* concatenated U_b, each M x kb row-major                   */
     const double *V;        /* concatenated V_b, each Nb x Nb row-major, column = mode   */
     const double *shape_m1; /* N: w_n - 1 of the gamma prior weights, or NULL (flat)      */
+    const int64_t *bnm;     /* B modes per block (Nb, or Nb - 1 under a linear constraint),
+                               or NULL (Nb); V_b is then Nb x nm row-major               */
 } orc_problem;
 
 typedef struct {
@@ -379,10 +383,10 @@ static void *run_chains(void *arg) {
     int64_t *offV = (int64_t *)malloc(sizeof(int64_t) * (B + 1));
     offd[0] = offU[0] = offV[0] = 0;
     for (int64_t b = 0; b < B; ++b) {
-        int64_t nb = p->bnb[b];
+        int64_t nb = p->bnb[b], nm = p->bnm ? p->bnm[b] : nb;
         offd[b + 1] = offd[b] + p->kb[b];
         offU[b + 1] = offU[b] + M * p->kb[b];
-        offV[b + 1] = offV[b] + nb * nb;
+        offV[b + 1] = offV[b] + nb * nm;
     }
 
     for (int64_t c = wk->c0; c < wk->c1; ++c) {
@@ -394,15 +398,16 @@ static void *run_chains(void *arg) {
             for (int64_t b = 0; b < p->lcount[lvl]; ++b) {
                 const int64_t gb = p->lfirst[lvl] + b;   /* the block among all levels */
                 const int64_t n0 = p->bn0[gb], nb = p->bnb[gb];
+                const int64_t nm = p->bnm ? p->bnm[gb] : nb;   /* modes of the block */
                 const int64_t kb = p->kb[gb];
                 const double *Vb = p->V + offV[gb];
                 const double *Ub = p->U + offU[gb];
                 const double *db = p->d + offd[gb];
-                for (int64_t i = 0; i < nb; ++i) {
+                for (int64_t i = 0; i < nm; ++i) {
                     /* Eq. (modeLimits): f + delta V_i >= 0 */
                     double lo = -INFINITY, hi = INFINITY;
                     for (int64_t q = 0; q < nb; ++q) {
-                        double v = Vb[q * nb + i];
+                        double v = Vb[q * nm + i];
                         if (v > 0.0) {
                             double t = -A[n0 + q] / v;
                             if (t > lo) lo = t;
@@ -427,13 +432,13 @@ static void *run_chains(void *arg) {
                     }
                     if (lo == hi) wk->frozen++;
                     if (p->shape_m1) {
-                        /* Sec. VI: the target along the mode carries the weights
+                        /* Sec. V.C: the target along the mode carries the weights
                            prod_q A_q^(w_q - 1); the draw above (the Gaussian or flat
                            conditional of the flat-prior posterior) is an independence proposal,
                            accepted with probability min(1, R(delta) / R(0)) */
                         double lr = 0.0;
                         for (int64_t q = 0; q < nb; ++q) {
-                            double an = A[n0 + q] + delta * Vb[q * nb + i];
+                            double an = A[n0 + q] + delta * Vb[q * nm + i];
                             if (an < 0.0) an = 0.0;
                             lr += prior_log_ratio(an, A[n0 + q], p->shape_m1[n0 + q]);
                         }
@@ -444,7 +449,7 @@ static void *run_chains(void *arg) {
                         }
                     }
                     for (int64_t q = 0; q < nb; ++q) {
-                        double an = A[n0 + q] + delta * Vb[q * nb + i];
+                        double an = A[n0 + q] + delta * Vb[q * nm + i];
                         if (an < 0.0) {
                             an = 0.0;
                             wk->clamped++;

@@ -41,7 +41,7 @@ __device__ __forceinline__ double wmin64(double v) {
 }
 
 // (w - 1) log(a_new / a_old): one component's share of the log ratio of the gamma-prior
-// weights prod_n A_n^(w_n - 1) (Sec. VI) between the proposed and the current state
+// weights prod_n A_n^(w_n - 1) (Sec. V.C) between the proposed and the current state
 __device__ __forceinline__ double prior_term(double a_new, double a_old, double wm1) {
     if (wm1 == 0.0 || a_new == a_old) return 0.0;
     if (a_old == 0.0) return wm1 > 0.0 ? INFINITY : -INFINITY;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
                 }
                 frozen += (lo == hi);
                 if (wsh) {
-                    // gamma prior (Sec. VI): the draw is a proposal along the mode, accepted
+                    // gamma prior (Sec. V.C): the draw is a proposal along the mode, accepted
                     // with probability min(1, R(delta) / R(0)), R = prod_q A_q^(w_q - 1)
                     double lr = 0.0;
                     for (int64_t q = lane; q < nb; q += 64) {

@@ -97,7 +97,7 @@ __device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float 
 // into it, every A_q + delta V_q is non-negative before rounding, hence after it, and no
 // component needs clamping.  Every zero mode has a finite interval: a mode whose V has
 // entries of only one sign makes the posterior improper and is rejected before sampling.
-// Gamma-prior weights prod_q A_q^(w_q - 1) (Sec. VI): per lane the exponents w_q - 1 of its
+// Gamma-prior weights prod_q A_q^(w_q - 1) (Sec. V.C): per lane the exponents w_q - 1 of its
 // components (0 on padding) and their log2, kept current so that a move needs one logarithm
 // per component; rejections are counted on the chain's first lane.
 template <int EPT>

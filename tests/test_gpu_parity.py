@@ -552,7 +552,7 @@ def test_batched_fp32_uneven_continuations_match_oracle(pk):
 
 
 # --------------------------------------------------------------------------------------
-# the paper's own test case: optical conductivity (Sec. II), efficiency of Fig. 3
+# the paper's own test case: optical conductivity (Sec. III), efficiency of Fig. 3
 # --------------------------------------------------------------------------------------
 
 def _gpu_median_step(pk, p, sweeps=200, burnin=500, chains=128):
@@ -736,7 +736,7 @@ def test_two_roles_refuse_a_hierarchy(pk):
 
 
 # --------------------------------------------------------------------------------------
-# gamma-prior weights (Sec. VI, Eq. (compat)): an acceptance test per move
+# gamma-prior weights (Sec. V.C, Eq. (compat)): an acceptance test per move
 # --------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("nblocks,levels", [(2, False), (1, True)])

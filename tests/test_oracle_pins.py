@@ -557,7 +557,7 @@ def test_unbounded_zero_mode_is_reported(orc):
 
 
 # --------------------------------------------------------------------------------------
-# the paper's own test case (Sec. II) and its efficiency comparison (Fig. 3)
+# the paper's own test case (Sec. III) and its efficiency comparison (Fig. 3)
 # --------------------------------------------------------------------------------------
 
 def test_conductivity_workload_sum_rule_and_kernel():
@@ -624,7 +624,7 @@ def test_hierarchy_steps_as_in_fig3(orc):
 
 
 # --------------------------------------------------------------------------------------
-# gamma-prior weights (Sec. VI): prod_n A_n^(w_n - 1) exp(-chi^2 / 2), Eq. (compat)
+# gamma-prior weights (Sec. V.C): prod_n A_n^(w_n - 1) exp(-chi^2 / 2), Eq. (compat)
 # --------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("w", [0.5, 2.5])
@@ -685,7 +685,7 @@ def test_gamma_prior_halved_grid_reproduces_the_flat_coarse_grid(orc):
     pm, pse = pair.mean(0), pair.std(0, ddof=1) / math.sqrt(32)
     z = np.abs(pm - coarse.mean) / np.sqrt(pse ** 2 + coarse.stderr ** 2)
     assert np.max(z) < 4.5, (pm, coarse.mean, z)
-    # the flat prior on the fine grid gives a different answer (the grid dependence of Sec. VI)
+    # the flat prior on the fine grid gives a different answer (the grid dependence of Sec. V)
     pflat = _problem(Kf, G, sig, [0, 6])
     flat = orc.run(orc.prepare(pflat), chains=32, burnin=200, sweeps=20000, groups=32)
     fp = flat.group_means.reshape(32, 3, 2).mean(axis=2)

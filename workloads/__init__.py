@@ -253,7 +253,7 @@ def config5(seed: int = BASE_SEED + 5) -> Problem:
 
 
 # --------------------------------------------------------------------------------------
-# the paper's own test case (Sec. II): the optical conductivity from bosonic Matsubara data
+# the paper's own test case (Sec. III): the optical conductivity from bosonic Matsubara data
 # --------------------------------------------------------------------------------------
 
 def conductivity_model(omega: np.ndarray, model: int = 1) -> np.ndarray:
@@ -275,7 +275,7 @@ def bosonic_kernel(omega_m: np.ndarray, omega: np.ndarray) -> np.ndarray:
 def optical_conductivity(n_omega: int = 40, nblocks: int = 4, model: int = 1,
                          sigma_rel: float = 1e-3, beta: float = 15.0, n_matsubara: int = 60,
                          seed: int = BASE_SEED + 6, step: float = 0.1) -> Problem:
-    """The test case of Sec. II and Fig. 3: Pi(i omega_m) of Eq. (optcond) at the first 60
+    """The test case of Sec. III and Fig. 3: Pi(i omega_m) of Eq. (optcond) at the first 60
     bosonic Matsubara frequencies (beta = 15) from sigma(omega) of Eq. (model), with relative
     Gaussian noise of standard deviation sigma_rel; the grid is omega_n = 0.1 (n - 1/2),
     n = 1..n_omega (40: small cutoff, 120: large), split into nblocks equal blocks (1: modes
