@@ -62,7 +62,8 @@ class _Problem(ctypes.Structure):
                 ("Kt", ctypes.c_void_p), ("gt", ctypes.c_void_p), ("bn0", ctypes.c_void_p),
                 ("bnb", ctypes.c_void_p), ("L", ctypes.c_int64), ("lfirst", ctypes.c_void_p),
                 ("lcount", ctypes.c_void_p), ("kb", ctypes.c_void_p), ("d", ctypes.c_void_p),
-                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("shape_m1", ctypes.c_void_p)]
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("shape_m1", ctypes.c_void_p),
+                ("bnm", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
