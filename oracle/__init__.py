@@ -169,6 +169,9 @@ class Prepared:
     Tt: object                # callable y -> T^T y
     init: np.ndarray          # N
     shape: Optional[np.ndarray] = None   # N gamma-prior shapes w_n (Eq. (compat)), or flat
+    cvec: Optional[np.ndarray] = None    # N: linear constraint c . A = cval (Sec. IV.E), or None
+    cval: float = 0.0
+    nm: Optional[np.ndarray] = None      # B: modes per block (N_b, or N_b - 1 under the constraint)
 
     @property
     def M(self):
@@ -301,20 +304,51 @@ def hierarchy(N: int, max_block: int = 0) -> list:
     return out
 
 
+def constraint_basis(cb: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the part of a block orthogonal to its share c_b of a linear
+    constraint (Sec. IV.E): the Householder reflector H = I - 2 v v^T / v.v with H c_b =
+    beta e_1 (beta = -sign(c_b[0]) |c_b|, sign(0) = +1) has H e_1 parallel to c_b, so its other
+    columns span the complement.  A block where c_b = 0 keeps the identity."""
+    nb = len(cb)
+    if not np.any(cb != 0.0):
+        return np.eye(nb)
+    x = np.asarray(cb, np.float64)
+    alpha = x[0]
+    norm = np.sqrt(np.dot(x, x))
+    beta = -norm if alpha >= 0.0 else norm
+    v = x.copy()
+    v[0] = alpha - beta
+    H = np.eye(nb) - np.outer(v, v) * (2.0 / np.dot(v, v))
+    return H[:, 1:]
+
+
 def prepare(problem, k=None) -> Prepared:
     """Whitening + block factors + start vector for one workloads.Problem."""
     Kt, gt, Tt = whiten(problem.K, problem.G, problem.sigma, problem.cov)
     levels = problem.partitions()
     spans = [(int(ls[b]), int(ls[b + 1])) for ls in levels for b in range(len(ls) - 1)]
     kreq = k if k is not None else problem.k
+    cvec = getattr(problem, "constraint_c", None)
+    cvec = None if cvec is None else np.asarray(cvec, np.float64)
     ds, Us, Vs, dall = [], [], [], []
-    kb = []
+    kb, nm = [], []
     for b, (s0, s1) in enumerate(spans):
         Kb = Kt[:, s0:s1]
         kr = None if kreq is None else int(np.asarray(kreq)[b])
-        d, U, V, sv = block_factors(Kb, kr)
+        if cvec is None:
+            d, U, V, sv = block_factors(Kb, kr)
+        else:
+            # modes of the block restricted to the complement of its constraint share: the
+            # factors of K~_b Q_b, mapped back, V = Q_b V'
+            Q = constraint_basis(cvec[s0:s1])
+            if Q.shape[1] == 0:
+                d, U, V, sv = np.zeros(0), np.zeros((Kt.shape[0], 0)), np.zeros((s1 - s0, 0)), np.zeros(0)
+            else:
+                d, U, Vr, sv = block_factors(Kb @ Q, kr)
+                V = Q @ Vr
         ds.append(d); Us.append(U); Vs.append(V); dall.append(sv)
         kb.append(len(d))
+        nm.append(V.shape[1])
     one = Kt @ np.ones(Kt.shape[1])
     cstar = float(np.dot(one, gt) / np.dot(one, one))
     if not (cstar > 0.0 and np.isfinite(cstar)):
@@ -323,7 +357,9 @@ def prepare(problem, k=None) -> Prepared:
     return Prepared(Kt=np.ascontiguousarray(Kt), gt=np.ascontiguousarray(gt), levels=levels,
                     kb=np.asarray(kb, dtype=np.int32), d=ds, U=Us, V=Vs, dall=dall, Tt=Tt,
                     init=init, shape=None if getattr(problem, "prior_shape", None) is None
-                    else np.asarray(problem.prior_shape, np.float64))
+                    else np.asarray(problem.prior_shape, np.float64),
+                    cvec=cvec, cval=float(getattr(problem, "constraint_value", 0.0)),
+                    nm=np.asarray(nm, np.int64))
 
 
 # --------------------------------------------------------------------------------------
@@ -367,7 +403,20 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
     lcount = np.ascontiguousarray([len(ls) - 1 for ls in prep.levels], dtype=np.int64)
     lfirst = np.ascontiguousarray(np.concatenate([[0], np.cumsum(lcount)[:-1]]), dtype=np.int64)
     kb = np.ascontiguousarray(prep.kb, dtype=np.int32)
-    start = np.ascontiguousarray(prep.init if init is None else np.asarray(init, np.float64))
+    start = np.asarray(prep.init if init is None else np.asarray(init, np.float64), np.float64)
+    if prep.cvec is not None:
+        # the start moved onto c . A = F: scaled by F / (c . A) when that is positive (which
+        # keeps it non-negative), else projected along c; it must stay non-negative
+        c = prep.cvec
+        cs = float(np.dot(c, start))
+        if cs != 0.0 and prep.cval / cs > 0.0:
+            start = start * (prep.cval / cs)
+        else:
+            start = start + c * ((prep.cval - cs) / np.dot(c, c))
+        if np.min(start) < 0.0:
+            raise ValueError("the start moved onto the constraint has a negative component")
+    start = np.ascontiguousarray(start)
+    bnm = np.ascontiguousarray(prep.nm if prep.nm is not None else [b[1] for b in prep.blocks], dtype=np.int64)
     G = int(groups)
     total = burnin + sweeps
     bufs = dict(
@@ -383,7 +432,7 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
                  bn0=bn0.ctypes.data, bnb=bnb.ctypes.data, L=len(prep.levels),
                  lfirst=lfirst.ctypes.data, lcount=lcount.ctypes.data, kb=kb.ctypes.data, d=d_all.ctypes.data,
                  U=U_all.ctypes.data, V=V_all.ctypes.data,
-                 shape_m1=None if shape_m1 is None else shape_m1.ctypes.data)
+                 shape_m1=None if shape_m1 is None else shape_m1.ctypes.data, bnm=bnm.ctypes.data)
     o = _Options(chains=chains, burnin=burnin, sweeps=sweeps, seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
                  problem_index=problem_index, refresh_every=refresh_every, groups=G,
                  want_cross=1 if want_cross else 0, threads=int(threads), traj_chain=traj_chain,

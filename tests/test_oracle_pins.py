@@ -691,3 +691,60 @@ def test_gamma_prior_halved_grid_reproduces_the_flat_coarse_grid(orc):
     fp = flat.group_means.reshape(32, 3, 2).mean(axis=2)
     zf = np.abs(fp.mean(0) - coarse.mean) / np.sqrt((fp.std(0, ddof=1) / math.sqrt(32)) ** 2 + coarse.stderr ** 2)
     assert np.max(zf) > 6, (fp.mean(0), coarse.mean, zf)
+
+
+# --------------------------------------------------------------------------------------
+# a linear constraint c . A = F (Sec. IV.E): moves restricted to the complement of c
+# --------------------------------------------------------------------------------------
+
+def _flat_likelihood_problem(N, bstart, c, F):
+    rng = np.random.default_rng(2)
+    K = rng.uniform(0.1, 1.0, (3, N))
+    p = _problem(K, K @ np.ones(N), 1e7, bstart)   # sigma 1e7: chi^2 is flat on the scale of F
+    p.constraint_c = np.asarray(c, np.float64)
+    p.constraint_value = float(F)
+    return p
+
+
+@pytest.mark.parametrize("levels", [False, True])
+def test_constraint_flat_likelihood_is_uniform_on_the_simplex(orc, levels):
+    """With a flat likelihood, A >= 0 and c . A = F make B_n = c_n A_n / F uniform on the
+    standard simplex: <A_n> = F / (N c_n), Var A_n = F^2 (N - 1) / (N^2 (N + 1) c_n^2)."""
+    N, F = 6, 2.0
+    c = np.array([1.0, 0.5, 2.0, 1.0, 1.5, 0.8])
+    p = _flat_likelihood_problem(N, [0, N], c, F)
+    if levels:
+        p.levels = orc.hierarchy(N)
+    prep = orc.prepare(p)
+    assert list(prep.nm)[:1] == [N - 1]
+    res = orc.run(prep, chains=16, burnin=200, sweeps=20000, groups=16, traj_chain=3)
+    ref = F / (N * c)
+    assert _within(res.mean, res.stderr, ref) < 4.5, (res.mean, ref)
+    sd = F * math.sqrt((N - 1) / (N * N * (N + 1))) / c
+    assert np.allclose(res.post_sd, sd, rtol=0.04), (res.post_sd, sd)
+    # every state of the trajectory keeps the constraint
+    assert np.max(np.abs(res.traj_A @ c - F)) < 1e-12 * F
+    assert np.min(res.traj_A) >= 0.0
+
+
+def test_constraint_two_point_grid_against_quadrature(orc):
+    """Two points with A_1 + A_2 = F: the posterior lives on the segment t = A_1 in [0, F]."""
+    beta = 10.0
+    tau = workloads.imaginary_times(11, beta)
+    x = np.array([-1.0, 0.5])
+    K = workloads.fermionic_kernel(tau, x, beta)
+    sig = 0.05
+    G = K @ np.array([0.3, 0.2]) + sig * np.random.default_rng(8).standard_normal(11)
+    F = 0.5
+    p = _problem(K, G, sig, [0, 2])
+    p.constraint_c = np.ones(2)
+    p.constraint_value = F
+    res = orc.run(orc.prepare(p), chains=16, burnin=100, sweeps=20000, groups=16)
+    Kt, gt = K / sig, G / sig
+    w = lambda t: math.exp(-0.5 * np.sum((gt - Kt[:, 0] * t - Kt[:, 1] * (F - t)) ** 2))
+    lw = [math.log(w(t) + 1e-300) for t in np.linspace(0, F, 201)]
+    shift = max(lw)
+    Z = integrate.quad(lambda t: w(t) * math.exp(-shift), 0, F, epsabs=0, epsrel=1e-12, limit=200)[0]
+    m1 = integrate.quad(lambda t: t * w(t) * math.exp(-shift), 0, F, epsabs=0, epsrel=1e-12, limit=200)[0] / Z
+    ref = np.array([m1, F - m1])
+    assert _within(res.mean, res.stderr, ref) < 4.5, (res.mean, ref)

@@ -125,6 +125,8 @@ class Problem:
     name: str = ""
     prior_shape: Optional[np.ndarray] = None   # N gamma-prior shapes w_n (Eq. (compat));
                                         # None: the flat prior (w = 1)
+    constraint_c: Optional[np.ndarray] = None  # N: a linear constraint c . A = F (Sec. IV.E)
+    constraint_value: float = 0.0       # F
     levels: Optional[list] = None       # a hierarchy of partitions (each B_l+1 offsets), used
                                         # instead of block_start when given; k then covers the
                                         # blocks of all levels in order
