@@ -85,6 +85,8 @@ class _DevProblem:
         self.block_start = p.block_start
         self.levels = getattr(p, "levels", None)
         self.prior_shape = getattr(p, "prior_shape", None)
+        self.constraint_c = getattr(p, "constraint_c", None)
+        self.constraint_value = getattr(p, "constraint_value", 0.0)
         self.k = p.k
         self.init = None
 

@@ -94,7 +94,21 @@ typedef struct {
                                     move's draw is then a proposal, accepted when
                                     log u' < sum_q (w_q - 1) log(A'_q / A_q), u' the float64
                                     uniform of counter (chain, sweep, block << 16 | mode, 3);
-                                    a rejected move changes nothing.  ASM_FP64 only           */
+                                    a rejected move changes nothing                           */
+    const double *constraint_c;  /* device, N: a linear constraint c . A = F, or NULL (Sec. IV.E).
+                                    Each block moves only in the complement of its share c_b:
+                                    H = I - 2 v v^T / v.v with v = c_b - beta e_1,
+                                    beta = -sign(c_b[0]) |c_b| (sign(0) = +1), and
+                                    Q_b = [H e_2 ... H e_Nb]; the block's N_b - 1 modes are
+                                    V = Q_b V' from K~_b Q_b = U D V'^T (sign rule and zero-mode
+                                    completion taken in these coordinates).  A block with
+                                    c_b = 0 keeps its N_b modes.  The start (any kind) is scaled
+                                    by F / (c . A) when that is positive, else moved along c;
+                                    ASM_EDOMAIN if it then has a negative component.  With a
+                                    fixed partition each block keeps its own c_b . A_b: the
+                                    chains reach every state only when some level holds blocks
+                                    that span the constraint (one block, or a hierarchy)     */
+    double constraint_value;     /* F                                                         */
 } asm_problem;
 
 typedef struct {
@@ -136,7 +150,9 @@ typedef struct {
     double setup_ms;             /* whitening + decompositions + packing + start state        */
     double sample_ms;            /* all sweeps, refreshes and accumulation                    */
     double finalize_ms;
-    double mode_moves;           /* moves made: sum over problems of chains*(burnin+sweeps)*N */
+    double mode_moves;           /* moves made: sum over problems of chains*(burnin+sweeps)
+                                    * modes per sweep (N; fewer under a constraint; the mean
+                                    over the levels of a hierarchy)                          */
     double data_moves;           /* of which along modes with d_i > 0                         */
     double chi2_drift_max;       /* largest |chi^2_incremental - chi^2_recomputed| / chi^2
                                     seen at a refresh                                         */
@@ -187,8 +203,9 @@ int asm_plan_advance(asm_plan *plan, int64_t sweeps);
 int asm_plan_state(asm_plan *plan, int64_t problem, double *A, double *r, double *chi2);
 
 /* Block factors of one problem as used by the sampler: kb (host, 1 int32), d (device, kb),
-   U (device, M x kb), V (device, N_b x N_b, column i = mode i, data modes first).  Any
-   output pointer may be NULL. */
+   U (device, M x kb), V (device, N_b x N_b, column i = mode i, data modes first; under a
+   constraint the last column is 0, the block having N_b - 1 modes).  Any output pointer may
+   be NULL. */
 int asm_plan_factors(asm_plan *plan, int64_t problem, int64_t block, int32_t *kb, double *d,
                      double *U, double *V);
 

@@ -38,7 +38,8 @@ class _Problem(ctypes.Structure):
                 ("G", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("cov", ctypes.c_void_p),
                 ("B", ctypes.c_int64), ("block_start", ctypes.c_void_p), ("k", ctypes.c_void_p),
                 ("init", ctypes.c_void_p), ("levels", ctypes.c_int64), ("level_blocks", ctypes.c_void_p),
-                ("prior_shape", ctypes.c_void_p)]
+                ("prior_shape", ctypes.c_void_p), ("constraint_c", ctypes.c_void_p),
+                ("constraint_value", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -132,8 +133,9 @@ class Plan:
 
     problems: sequence of objects with K (M x N), G (M), sigma (M) or cov (M x M),
     block_start (B+1) or levels (a list of such partitions: a hierarchy, see hierarchy()),
-    optional k (B, over the blocks of all levels), init (N) and prior_shape (N gamma-prior
-    shapes, float64 plans); numpy arrays or tensors.
+    optional k (B, over the blocks of all levels), init (N), prior_shape (N gamma-prior
+    shapes) and constraint_c / constraint_value (a linear constraint c . A = F); numpy arrays
+    or tensors.
     """
 
     def __init__(self, problems, chains=256, burnin=100, sweeps=1000, seed=1234, precision="fp32",
@@ -154,6 +156,7 @@ class Plan:
                 sig = None
             init = _dev(getattr(p, "init", None), self.device)
             shape = _dev(getattr(p, "prior_shape", None), self.device)
+            cvec = _dev(getattr(p, "constraint_c", None), self.device)
             lv = getattr(p, "levels", None)
             parts = [np.asarray(x, dtype=np.int64) for x in lv] if lv is not None else \
                 [np.asarray(p.block_start, dtype=np.int64)]
@@ -161,7 +164,7 @@ class Plan:
             lb = np.ascontiguousarray([len(x) - 1 for x in parts], dtype=np.int64)
             kk = getattr(p, "k", None)
             kk = None if kk is None else np.ascontiguousarray(np.asarray(kk, dtype=np.int32))
-            self._keep += [K, G, sig, cov, init, shape, bs, lb, kk]
+            self._keep += [K, G, sig, cov, init, shape, cvec, bs, lb, kk]
             M, N = int(K.shape[0]), int(K.shape[1])
             self.M.append(M)
             self.N.append(N)
@@ -169,7 +172,8 @@ class Plan:
                                 B=int(lb.sum()), block_start=bs.ctypes.data,
                                 k=None if kk is None else kk.ctypes.data, init=_ptr(init),
                                 levels=len(parts), level_blocks=lb.ctypes.data if len(parts) > 1 else None,
-                                prior_shape=_ptr(shape))
+                                prior_shape=_ptr(shape), constraint_c=_ptr(cvec),
+                                constraint_value=float(getattr(p, "constraint_value", 0.0) or 0.0))
         self.options = _Options(chains=int(chains), burnin=int(burnin), sweeps=int(sweeps),
                                 seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=int(precision),
                                 refresh_every=int(refresh_every), want_vjp=int(bool(want_vjp)),

@@ -90,8 +90,13 @@ struct asm_plan {
     bool any_levels = false;   // a problem with a hierarchy of partitions
     float *wm1f = nullptr;     // float32 exponents w_n - 1 of the gamma priors (float32 plans)
     // the float32 sampler's extended instances: hierarchies and gamma priors
-    bool ext() const { return any_levels || any_prior; }
+    bool ext() const { return any_levels || any_prior || any_con; }
     std::vector<int32_t> lvl;  // level table (pairs: first block of the problem's, count)
+    std::vector<ConTask> ctasks;          // constrained blocks (setup)
+    std::vector<int64_t> ctask_svd;       // their decomposition tasks
+    ConTask *ctasks_d = nullptr;
+    double *hv = nullptr;                 // their Householder vectors
+    int64_t hv_words = 0, kq_words = 0, vp_words = 0;
     int32_t *d_lvl = nullptr;
     bool ran = false;
     int64_t sweep = 0;      // absolute sweep counter (host mirror)
@@ -113,6 +118,8 @@ struct asm_plan {
     double *accA = nullptr, *accA2 = nullptr, *slot_count_d = nullptr;
     double *shape = nullptr;   // gamma-prior shapes (problems with a prior, at off_n)
     bool any_prior = false;
+    bool any_con = false;      // a problem with a linear constraint c . A = F
+    double *con = nullptr;     // the constraint vectors c (at off_n)
     int32_t *slot_group_d = nullptr;
     double *cross = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
     unsigned long long *counters = nullptr;
@@ -775,6 +782,25 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pd.index = (uint32_t)p;
         pd.has_prior = q.prior_shape != nullptr;
         pl->any_prior |= pd.has_prior != 0;
+        // a linear constraint (Sec. IV.E): its vector is read here, since it decides how many
+        // modes each block has
+        std::vector<double> cvec;
+        if (q.constraint_c) {
+            cvec.resize(q.N);
+            HSTEP(hipMemcpy(cvec.data(), q.constraint_c, q.N * sizeof(double), hipMemcpyDeviceToHost));
+            bool any = false;
+            for (double x : cvec) {
+                if (!std::isfinite(x)) { rc = fail(ASM_EDOMAIN, "problem %lld: constraint_c must be finite", (long long)p); return rc; }
+                any |= x != 0.0;
+            }
+            if (!any || !std::isfinite(q.constraint_value)) {
+                rc = fail(ASM_EINVAL, "problem %lld: constraint_c must not vanish and F must be finite", (long long)p);
+                return rc;
+            }
+            pd.has_con = 1;
+            pd.con_value = q.constraint_value;
+            pl->any_con = true;
+        }
         pl->any_cov |= pd.has_cov;
         Partition part;
         STEP(parse_partition(q, p, &part));
@@ -789,7 +815,11 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             BlockDesc bd{};
             bd.n0 = part.n0[b];
             bd.nb = part.nb[b];
-            const int64_t kmax = std::min(q.M, bd.nb);
+            // under a constraint, a block with a non-zero share c_b has nb - 1 modes
+            bool cb = false;
+            for (int64_t j = 0; j < bd.nb && !cvec.empty(); ++j) cb |= cvec[bd.n0 + j] != 0.0;
+            bd.nm = cb ? bd.nb - 1 : bd.nb;
+            const int64_t kmax = std::min(q.M, bd.nm);
             bd.off_V = offV;
             bd.off_U = offU;
             bd.off_d = offd;
@@ -808,8 +838,33 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             t.off_d = bd.off_d;
             t.off_work = offwork;
             t.block = (int64_t)pl->blocks.size();
-            offwork += svd_work_doubles(q.M, bd.nb);
-            tasks.push_back(t);
+            if (cb && bd.nm > 0) {
+                // decompose K~_b Q_b (M x nm, at a place in the kernel array fixed below) into
+                // V' (nm x nm, in V64 after the modes); k_con_map forms V = Q_b V'
+                ConTask ct{};
+                ct.M = q.M;
+                ct.N = q.N;
+                ct.off_K = offK;
+                ct.n0 = bd.n0;
+                ct.nb = bd.nb;
+                ct.off_c = offn + bd.n0;
+                ct.off_v = pl->hv_words;
+                ct.off_kq = pl->kq_words;   // relative until the kernel array's size is known
+                ct.off_vp = pl->vp_words;   // relative until the mode array's size is known
+                ct.off_V = bd.off_V;
+                pl->hv_words += bd.nb + 1;
+                t.N = bd.nm;
+                t.n0 = 0;
+                t.nb = bd.nm;
+                t.off_K = pl->kq_words;      // relative, as above
+                t.off_V = pl->vp_words;
+                pl->kq_words += q.M * bd.nm;
+                pl->vp_words += bd.nm * bd.nm;
+                pl->ctasks.push_back(ct);
+                pl->ctask_svd.push_back((int64_t)tasks.size());
+            }
+            offwork += svd_work_doubles(q.M, std::max<int64_t>(bd.nm, 1));
+            if (bd.nm > 0) tasks.push_back(t);   // a one-point block under the constraint has no mode
             blockM.push_back(q.M);
             pl->blocks.push_back(bd);
             pl->max_nb = std::max(pl->max_nb, bd.nb);
@@ -830,6 +885,15 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     pl->total_chains = offc;
     pl->total_n = offn;
+    // the constrained blocks' matrices after the whitened kernels and their V' after the modes
+    for (size_t j = 0; j < pl->ctasks.size(); ++j) {
+        ConTask &ct = pl->ctasks[j];
+        SvdTask &t = tasks[pl->ctask_svd[j]];
+        ct.off_kq += offK;
+        ct.off_vp += offV;
+        t.off_K = ct.off_kq;
+        t.off_V = ct.off_vp;
+    }
     pl->total_m = offm;
     if (pl->fp32 && !t_probe_plan) {
         // two snapshot buffers for every accumulated sweep of a launch (at most refresh_every
@@ -877,11 +941,11 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     int64_t *blockM_d = nullptr;
     int *has_init_d = nullptr;
     SvdTask *tasks_d = nullptr;
-    STEP(dalloc(pl, &pl->Kt, offK));
+    STEP(dalloc(pl, &pl->Kt, offK + pl->kq_words));
     STEP(dalloc(pl, &pl->gt, offm));
     STEP(dalloc(pl, &pl->sigma, offm));
     if (pl->any_cov) STEP(dalloc(pl, &pl->Lc, offL));
-    STEP(dalloc(pl, &pl->V64, offV));
+    STEP(dalloc(pl, &pl->V64, offV + pl->vp_words));
     STEP(dalloc(pl, &pl->U64, offU));
     STEP(dalloc(pl, &pl->d64, offd));
     STEP(dalloc(pl, &work, offwork));
@@ -1000,9 +1064,24 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (hflags & 8) { rc = fail(ASM_EDOMAIN, "covariance is not symmetric positive definite"); return rc; }
 
     // ---- block decompositions ----
+    HSTEP(hipMemsetAsync(kb_d, 0, pl->blocks.size() * sizeof(int32_t), st));   // blocks with no mode
+    if (pl->any_con) {
+        STEP(dalloc(pl, &pl->con, offn));
+        STEP(dalloc(pl, &pl->hv, pl->hv_words));
+        STEP(dalloc(pl, &pl->ctasks_d, pl->ctasks.size()));
+        for (int64_t p = 0; p < n; ++p)
+            if (pr[p].constraint_c)
+                HSTEP(hipMemcpyAsync(pl->con + pl->probs[p].off_n, pr[p].constraint_c, pr[p].N * sizeof(double),
+                                     hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->ctasks_d, pl->ctasks.data(), pl->ctasks.size() * sizeof(ConTask),
+                             hipMemcpyHostToDevice, st));
+        HSTEP(launch_con_prep(pl->ctasks_d, (int64_t)pl->ctasks.size(), pl->Kt, pl->con, pl->Kt, pl->hv, st));
+    }
     HSTEP(hipMemcpyAsync(tasks_d, tasks.data(), tasks.size() * sizeof(SvdTask), hipMemcpyHostToDevice, st));
     HSTEP(launch_block_svd_tasks(tasks_d, (int64_t)tasks.size(), pl->Kt, work, pl->V64, pl->U64,
                                  pl->d64, kb_d, st));
+    if (pl->any_con)
+        HSTEP(launch_con_map(pl->ctasks_d, (int64_t)pl->ctasks.size(), pl->hv, pl->V64, pl->V64, st));
     std::vector<int32_t> kb(pl->blocks.size());
     HSTEP(hipMemcpyAsync(kb.data(), kb_d, kb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HSTEP(hipStreamSynchronize(st));
@@ -1248,6 +1327,21 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                                    pl->U64, pl->d64, pl->chunk, pl->F32, pl->U32, pl->flags, st));
     HSTEP(launch_init_state2(pl->d_probs, n, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
                              pl->fp32, st));
+    if (pl->any_con) {
+        std::vector<int32_t> which;
+        for (int64_t p = 0; p < n; ++p)
+            if (pl->probs[p].has_con) which.push_back((int32_t)p);
+        int32_t *which_d = nullptr;
+        STEP(dalloc(pl, &which_d, which.size()));
+        HSTEP(hipMemcpyAsync(which_d, which.data(), which.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HSTEP(launch_con_start(pl->d_probs, which_d, (int64_t)which.size(), pl->con, pl->A64, pl->A32, pl->fp32,
+                               pl->flags, 5, st));
+        STEP(check_flags(pl, &hflags));
+        if (hflags & 32) {
+            rc = fail(ASM_EDOMAIN, "the start moved onto the constraint has a negative component: pass an init");
+            return rc;
+        }
+    }
     STEP(refresh(pl, false));
     HSTEP(hipEventRecord(pl->ev[1], st));
     HSTEP(hipStreamSynchronize(st));
@@ -1321,7 +1415,13 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
         double mm = 0, dm = 0;
         const int64_t nsw = pl->opt.burnin + pl->opt.sweeps;
         for (auto &pd : pl->probs) {
-            mm += (double)pd.C * (double)nsw * (double)pd.N;
+            // modes per sweep of each level (N per level, fewer under a constraint)
+            double nm_sum = 0.0;
+            for (int64_t l = 0; l < pd.levels; ++l) {
+                const int32_t f = pl->lvl[2 * (pd.off_lvl + l)], c = pl->lvl[2 * (pd.off_lvl + l) + 1];
+                for (int32_t b = f; b < f + c; ++b) nm_sum += (double)pl->blocks[pd.off_blk + b].nm;
+            }
+            mm += (double)pd.C * (double)nsw * nm_sum / (double)pd.levels;
             // data modes per sweep of each level, and the levels the run's sweeps sampled
             std::vector<double> kbl(pd.levels, 0.0);
             for (int64_t l = 0; l < pd.levels; ++l) {
@@ -1429,8 +1529,8 @@ int asm_plan_factors(asm_plan *pl, int64_t problem, int64_t block, int32_t *kb, 
         std::vector<double> h(bd.nb * bd.nb), t(bd.nb * bd.nb);
         HIPCHK(hipMemcpyAsync(h.data(), pl->V64 + bd.off_V, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (int64_t i = 0; i < bd.nb; ++i)
-            for (int64_t q = 0; q < bd.nb; ++q) t[q * bd.nb + i] = h[i * bd.nb + q];
+        for (int64_t i = 0; i < bd.nb; ++i)   // a block under a constraint has nm < nb modes
+            for (int64_t q = 0; q < bd.nb; ++q) t[q * bd.nb + i] = i < bd.nm ? h[i * bd.nb + q] : 0.0;
         HIPCHK(hipMemcpyAsync(V, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipStreamSynchronize(st));

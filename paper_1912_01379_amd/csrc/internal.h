@@ -36,12 +36,14 @@ struct ProbDesc {
     int64_t off_sa;           // float32 snapshots of A (sweep, chain) rows of round4(N) floats
     int64_t off_sr;           // float32 snapshots of r rows of round4(M) floats
     int64_t levels;           // partitions of the hierarchy (1: one partition of B blocks)
+    int64_t has_con;          // 1: a linear constraint c . A = F (c at off_n in the constraint array)
+    double con_value;         // F
     int64_t off_lvl;          // first level in the level table (pairs: first block, count)
 };
 
 struct BlockDesc {
     int64_t n0, nb, kb;       // first grid point, size, data modes
-    int64_t unused;
+    int64_t nm;               // modes: nb, or nb - 1 under a linear constraint (V is nb x nm)
     int64_t nbp;              // row length of the float32 (V, -1/V) rows (lanes x components)
     int64_t mp;               // row length of the float32 U rows
     int64_t off_V;            // float64 V, mode-major: V[i*nb + q]
@@ -145,6 +147,22 @@ hipError_t launch_cholesky(const double *C, int64_t M, double *L, int *flag, int
 hipError_t launch_trsm_lower(const double *L, int64_t M, const double *B, int64_t ncols,
                              int64_t ldb, double *X, hipStream_t s);
 int64_t svd_work_doubles(int64_t M, int64_t nb);
+struct ConTask {              // a block under a linear constraint (nm = nb - 1 modes)
+    int64_t M, N;            // problem sizes
+    int64_t off_K;           // whitened kernel of the problem
+    int64_t n0, nb;          // block columns
+    int64_t off_c;           // constraint share c_b in the constraint array
+    int64_t off_v;           // Householder vector (nb) and v.v in the scratch
+    int64_t off_kq;          // K~_b Q_b (M x nm) in the kernel array
+    int64_t off_vp;          // V' (nm x nm) of its decomposition, in V64
+    int64_t off_V;           // the block's modes V = Q_b V' (nb x nm, mode-major), in V64
+};
+hipError_t launch_con_prep(const ConTask *tasks_dev, int64_t n, const double *Kt, const double *con, double *KQ,
+                           double *hv, hipStream_t s);
+hipError_t launch_con_map(const ConTask *tasks_dev, int64_t n, const double *hv, const double *Vp, double *V64,
+                          hipStream_t s);
+hipError_t launch_con_start(const ProbDesc *probs_dev, const int32_t *which, int64_t n, const double *con,
+                            double *A64, float *A32, int fp32, int *flag, int bit, hipStream_t s);
 hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, const double *Kt,
                                   double *work, double *V64, double *U64, double *d64,
                                   int32_t *kb_out, hipStream_t s);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_sample64(SampleArgs a, const int32_t *ch
             const double *U = a.U64 + bd.off_U;
             const double *dv = a.d64 + bd.off_d;
             double *Ab = A + bd.n0;
-            for (int64_t i = 0; i < nb; ++i) {
+            for (int64_t i = 0; i < bd.nm; ++i) {   // modes: nb, or nb - 1 under a constraint
                 const double *Vi = V + i * nb;
                 double lo = -INFINITY, hi = INFINITY;
                 for (int64_t q = lane; q < nb; q += 64) {

@@ -210,10 +210,10 @@ __device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const floa
     }
 }
 
-// The zero modes of one block (modes kb..nb-1) with the gamma-prior test, three per iteration,
+// The zero modes of one block (modes kb..nm-1) with the gamma-prior test, three per iteration,
 // each row loaded two moves ahead, as in the sampler's own loop.  On entry vw holds row kb.
 template <int L, int EPT, bool P>
-__device__ __forceinline__ void zero_moves(int kb, int nb, const float2 *sVW, const float *urow,
+__device__ __forceinline__ void zero_moves(int kb, int nm, const float2 *sVW, const float *urow,
                                            const float *urowA, int lane, float2 (&vw)[EPT],
                                            float (&Ar)[EPT], PriorRegs<EPT> *pr) {
     constexpr int ROW = EPT * L;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void zero_moves(int kb, int nb, const float2 *sVW, co
     float2 vb[EPT], vc[EPT];
     load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
     auto ua = [&](int j) { return P ? urowA[j] : 0.0f; };
-    for (; i + 3 <= nb; i += 3) {
+    for (; i + 3 <= nm; i += 3) {
         load_row<EPT>(vc, sVW + (i + 2) * ROW, lane, L);
         const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
         zero_move<L, EPT, P>(vw, Ar, u0, pr, ua(i), lane);
@@ -230,8 +230,8 @@ __device__ __forceinline__ void zero_moves(int kb, int nb, const float2 *sVW, co
         load_row<EPT>(vb, sVW + (i + 4) * ROW, lane, L);
         zero_move<L, EPT, P>(vc, Ar, u2, pr, ua(i + 2), lane);
     }
-    if (i < nb) zero_move<L, EPT, P>(vw, Ar, urow[i], pr, ua(i), lane);
-    if (i + 1 < nb) zero_move<L, EPT, P>(vb, Ar, urow[i + 1], pr, ua(i + 1), lane);
+    if (i < nm) zero_move<L, EPT, P>(vw, Ar, urow[i], pr, ua(i), lane);
+    if (i + 1 < nm) zero_move<L, EPT, P>(vb, Ar, urow[i + 1], pr, ua(i + 1), lane);
 }
 
 // Copy a block's factor chunk (the image of the staging area) to LDS with all threads,
@@ -404,6 +404,9 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
             for (int64_t b = 0; b < lc; ++b) {
                 const BlockDesc bd = cload(a.blocks + pd.off_blk + lf + b);
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
+                // modes of the block: one per grid point, or one fewer under a linear
+                // constraint (extended instances only)
+                const int nm = H ? (int)bd.nm : nb;
                 float Ar[EPT];
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
@@ -418,10 +421,10 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 // the block's singular values and U rows in LDS: at the plan's fixed offsets, or,
                 // for a hierarchy, right after the block's own rows (its chunk is packed to its
-                // size: nb + 2 rows, round4(kb) values, kb U rows, one contiguous copy)
+                // size: nm + 2 rows, round4(kb) values, kb U rows, one contiguous copy)
                 const float *sDb = sD, *sUb = sU;
                 if constexpr (H) {
-                    const int n1 = (nb + 2) * ROW / 2, n2 = (kb + 3) / 4, n3 = a.u_lds ? kb * MP / 4 : 0;
+                    const int n1 = (nm + 2) * ROW / 2, n2 = (kb + 3) / 4, n3 = a.u_lds ? kb * MP / 4 : 0;
                     stage_sync(stage, a.F32 + bd.off_chunk, n1 + n2 + n3, tid, nthr);
                     sDb = reinterpret_cast<const float *>(stage + n1);
                     sUb = sDb + 4 * n2;
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
                 }
                 // this block's uniforms: one Philox call per four modes
-                for (int g = lane; 4 * g < nb; g += L) {
+                for (int g = lane; 4 * g < nm; g += L) {
                     const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
                                               (uint32_t)b, (uint32_t)g);
                     float *d = urow + 4 * g;
@@ -487,12 +490,12 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
                 if (PRI) {
-                    zero_moves<L, EPT, true>(kb, nb, sVW, urow, urowA, lane, vw, Ar, &pr);
+                    zero_moves<L, EPT, true>(kb, nm, sVW, urow, urowA, lane, vw, Ar, &pr);
                 } else {
                     int i = kb;
                     float2 vb[EPT], vc[EPT];
                     load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
-                    for (; i + 3 <= nb; i += 3) {
+                    for (; i + 3 <= nm; i += 3) {
                         load_row<EPT>(vc, sVW + (i + 2) * ROW, lane, L);
                         const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
                         zero_move<L, EPT>(vw, Ar, u0);
@@ -501,8 +504,8 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                         load_row<EPT>(vb, sVW + (i + 4) * ROW, lane, L);
                         zero_move<L, EPT>(vc, Ar, u2);
                     }
-                    if (i < nb) zero_move<L, EPT>(vw, Ar, urow[i]);
-                    if (i + 1 < nb) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
+                    if (i < nm) zero_move<L, EPT>(vw, Ar, urow[i]);
+                    if (i + 1 < nm) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
                 }
                 if constexpr (H) {
                     // a hierarchy's next block may overlap this block (whose components are

@@ -381,7 +381,8 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
     const int64_t M = blockM[blockIdx.x];
     const int64_t nb = bd.nb, kb = bd.kb, mp = bd.mp;
     constexpr double kTiny = 0x1.0p-100;
-    const int64_t rows = cl.compact ? nb + 2 : cl.rows;
+    const int64_t nm = bd.nm;   // modes (V is nb x nm, mode-major)
+    const int64_t rows = cl.compact ? nm + 2 : cl.rows;
     const int64_t d_len = cl.compact ? (kb + 3) / 4 * 4 : cl.d_len;
     const int64_t u_rows = cl.compact ? (cl.u_rows > 0 ? kb : 0) : cl.u_rows;
     float2 *vwc = reinterpret_cast<float2 *>(F32 + bd.off_chunk);
@@ -390,7 +391,7 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
     for (int64_t i = threadIdx.x; i < rows * cl.row; i += blockDim.x) {
         const int64_t mode = i / cl.row, q = i % cl.row;
         float2 vw;
-        const double v = (mode < nb && q < nb) ? V64[bd.off_V + mode * nb + q] : 0.0;
+        const double v = (mode < nm && q < nb) ? V64[bd.off_V + mode * nb + q] : 0.0;
         if (fabs(v) >= kTiny) {
             vw.x = (float)v;
             vw.y = (float)(-(1.0 / v) * (1.0 - 0x1.0p-21));
@@ -409,7 +410,7 @@ __global__ void k_pack32(const BlockDesc *blocks, const int64_t *blockM, const d
         const int64_t mode = i / mp, m = i % mp;
         U32[bd.off_U32 + i] = (m < M) ? (float)U64[bd.off_U + mode * M + m] : 0.0f;
     }
-    for (int64_t i = kb + threadIdx.x; i < nb; i += blockDim.x) {
+    for (int64_t i = kb + threadIdx.x; i < nm; i += blockDim.x) {
         bool pos = false, neg = false;
         for (int64_t q = 0; q < nb; ++q) {
             const double v = V64[bd.off_V + i * nb + q];
@@ -427,6 +428,155 @@ hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *bloc
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack32, dim3((unsigned)nblocks), dim3(256), 0, s, blocks_dev, blockM_dev, V64,
                        U64, d64, cl, F32, U32, flags);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// a linear constraint c . A = F (Sec. IV.E): the modes of a block span the complement of its
+// share c_b of c.  The Householder reflector H = I - 2 v v^T / v.v maps c_b to beta e_1
+// (v = c_b - beta e_1, beta = -sign(c_b[0]) |c_b|, sign(0) = +1), so H e_1 is parallel to c_b
+// and Q_b = [H e_2 ... H e_nb] spans the complement: Q_b[q][p] = d_{q,p+1} - 2 v_q v_{p+1} / v.v.
+// The block is decomposed as K~_b Q_b = U D V'^T and its modes are V = Q_b V'.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_con_prep(const ConTask *tasks, const double *Kt, const double *con,
+                                                  double *KQ, double *hv) {
+    const ConTask t = tasks[blockIdx.x];
+    const int64_t M = t.M, N = t.N, nb = t.nb, nm = nb - 1;
+    const double *c = con + t.off_c;
+    double *v = hv + t.off_v;   // nb entries of v, then v.v
+    __shared__ double s_norm, s_vv;
+    __shared__ double s_part[256];
+    double a = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) a += c[q] * c[q];
+    s_part[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s_part[threadIdx.x] += s_part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double norm = sqrt(s_part[0]);
+        const double alpha = c[0];
+        const double beta = alpha >= 0.0 ? -norm : norm;
+        const double v0 = alpha - beta;
+        s_norm = norm;
+        s_vv = v0 * v0 + (s_part[0] - alpha * alpha);
+        v[0] = v0;
+        v[nb] = s_vv;
+    }
+    __syncthreads();
+    for (int64_t q = 1 + threadIdx.x; q < nb; q += blockDim.x) v[q] = c[q];
+    __syncthreads();
+    // KQ (M x nm, row-major): K~_b Q_b = K~_b[:, p+1] - (2 v_{p+1} / v.v) (K~_b v)
+    const double *K = Kt + t.off_K;
+    const double f = 2.0 / s_vv;
+    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
+        const double *row = K + m * N + t.n0;
+        double y = 0.0;
+        for (int64_t q = 0; q < nb; ++q) y += row[q] * v[q];
+        double *out = KQ + t.off_kq + m * nm;
+        for (int64_t p = 0; p < nm; ++p) out[p] = row[p + 1] - f * v[p + 1] * y;
+    }
+}
+
+// V = Q_b V' (V' nm x nm mode-major from the decomposition, V nb x nm mode-major)
+__global__ __launch_bounds__(256) void k_con_map(const ConTask *tasks, const double *hv, const double *Vp,
+                                                 double *V64) {
+    const ConTask t = tasks[blockIdx.x];
+    const int64_t nb = t.nb, nm = nb - 1;
+    const double *v = hv + t.off_v;
+    const double f = 2.0 / v[nb];
+    for (int64_t i = 0; i < nm; ++i) {
+        const double *vp = Vp + t.off_vp + i * nm;
+        __shared__ double s_part[256];
+        double a = 0.0;
+        for (int64_t p = threadIdx.x; p < nm; p += blockDim.x) a += v[p + 1] * vp[p];
+        s_part[threadIdx.x] = a;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) s_part[threadIdx.x] += s_part[threadIdx.x + o];
+            __syncthreads();
+        }
+        const double w = s_part[0];
+        for (int64_t q = threadIdx.x; q < nb; q += blockDim.x)
+            V64[t.off_V + i * nb + q] = (q >= 1 ? vp[q - 1] : 0.0) - f * v[q] * w;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_con_prep(const ConTask *tasks_dev, int64_t n, const double *Kt, const double *con, double *KQ,
+                           double *hv, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_con_prep, dim3((unsigned)n), dim3(256), 0, s, tasks_dev, Kt, con, KQ, hv);
+    return hipGetLastError();
+}
+
+hipError_t launch_con_map(const ConTask *tasks_dev, int64_t n, const double *hv, const double *Vp, double *V64,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_con_map, dim3((unsigned)n), dim3(256), 0, s, tasks_dev, hv, Vp, V64);
+    return hipGetLastError();
+}
+
+// The start moved onto c . A = F: scaled by F / (c . A) when that is positive (keeping it
+// non-negative), else projected along c; a negative component sets flag bit `bit`.  The
+// start is the same for every chain of a problem; one workgroup per constrained problem.
+__global__ __launch_bounds__(256) void k_con_start(const ProbDesc *probs, const int32_t *which,
+                                                   const double *con, double *A64, float *A32,
+                                                   int fp32, int *flag, int bit) {
+    const ProbDesc pd = probs[which[blockIdx.x]];
+    const int64_t N = pd.N;
+    const double *c = con + pd.off_n;
+    __shared__ double s_a[256], s_b[256];
+    double a = 0.0, bsum = 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double x = fp32 ? (double)A32[pd.off_A + n] : A64[pd.off_A + n];
+        a += c[n] * x;
+        bsum += c[n] * c[n];
+    }
+    s_a[threadIdx.x] = a;
+    s_b[threadIdx.x] = bsum;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s_a[threadIdx.x] += s_a[threadIdx.x + o];
+            s_b[threadIdx.x] += s_b[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    const double cs = s_a[0], cc = s_b[0], F = pd.con_value;
+    const bool scale = cs != 0.0 && F / cs > 0.0;
+    // the other chains first, from chain 0's values, then chain 0 itself
+    int bad = 0;
+    auto moved = [&](int64_t n) {
+        const double x0 = fp32 ? (double)A32[pd.off_A + n] : A64[pd.off_A + n];
+        return scale ? x0 * (F / cs) : x0 + c[n] * ((F - cs) / cc);
+    };
+    for (int64_t i = N + threadIdx.x; i < pd.C * N; i += blockDim.x) {
+        const double x = moved(i % N);
+        bad |= !(x >= 0.0);
+        if (fp32)
+            A32[pd.off_A + i] = (float)x;
+        else
+            A64[pd.off_A + i] = x;
+    }
+    __syncthreads();
+    for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double x = moved(n);
+        bad |= !(x >= 0.0);
+        if (fp32)
+            A32[pd.off_A + n] = (float)x;
+        else
+            A64[pd.off_A + n] = x;
+    }
+    if (bad) atomicOr(flag, 1 << bit);
+}
+
+hipError_t launch_con_start(const ProbDesc *probs_dev, const int32_t *which, int64_t n, const double *con,
+                            double *A64, float *A32, int fp32, int *flag, int bit, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_con_start, dim3((unsigned)n), dim3(256), 0, s, probs_dev, which, con, A64, A32, fp32,
+                       flag, bit);
     return hipGetLastError();
 }
 

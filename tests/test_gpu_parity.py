@@ -947,3 +947,91 @@ def test_size_limits_are_reported(pk):
     with pytest.raises(pk.AsmError) as e:
         pk.Plan([p], chains=2, burnin=0, sweeps=4, precision="fp64", groups=2)
     assert e.value.code == pk.ASM_EINVAL
+
+
+# --------------------------------------------------------------------------------------
+# a linear constraint c . A = F (Sec. IV.E)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("levels", [False, True])
+def test_fp64_constraint_trajectory_matches_oracle(pk, orc, levels):
+    """The float64 sampler follows the oracle move by move with each block's modes restricted
+    to the complement of its share of c, and keeps c . A = F."""
+    p = workloads.random_wellconditioned(M=40, N=24, nblocks=1, seed=11)
+    p.constraint_c = np.random.default_rng(3).uniform(0.5, 1.5, 24)
+    p.constraint_value = 20.0
+    if levels:
+        p.levels = pk.hierarchy(24)
+    prep = orc.prepare(p)
+    sweeps = 400
+    ores = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, refresh_every=16, groups=1,
+                   traj_chain=0, seed=99)
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=1, seed=99, precision="fp64",
+                   refresh_every=16, groups=1)
+    worst = 0.0
+    for s in range(sweeps):
+        plan.advance(1)
+        if s % 10 == 9 or s < 12:
+            A, r, chi2 = plan.state(0)
+            a = A[0].cpu().numpy()
+            ref = ores.traj_A[s]
+            worst = max(worst, np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+            assert abs(float(chi2[0]) - ores.traj_chi2[s]) <= 1e-10 * ores.traj_chi2[s]
+            assert abs(a @ p.constraint_c - 20.0) < 1e-11 * 20.0
+    assert worst < 1e-10, worst
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_constraint_flat_likelihood_is_uniform_on_the_simplex_on_gpu(pk, precision):
+    """Flat likelihood, A >= 0, c . A = F: <A_n> = F / (N c_n) exactly (one block)."""
+    N, F = 6, 2.0
+    c = np.array([1.0, 0.5, 2.0, 1.0, 1.5, 0.8])
+    rng = np.random.default_rng(2)
+    K = rng.uniform(0.1, 1.0, (3, N))
+    p = workloads.Problem(K=K, G=K @ np.ones(N), sigma=np.full(3, 1e7), block_start=np.array([0, N]),
+                          constraint_c=c, constraint_value=F)
+    chains, sweeps = (512, 2000) if precision == "fp64" else (4096, 2000)
+    plan = pk.Plan([p], chains=chains, burnin=100, sweeps=sweeps, seed=5, precision=precision, groups=32)
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), F / (N * c), np.zeros(N))
+    assert ok, info
+    A = plan.state(0)[0].cpu().numpy()
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert np.max(np.abs(A @ c - F)) < tol * F
+    plan.close()
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32])
+def test_fp32_constraint_on_a_hierarchy_matches_oracle(pk, orc, lanes):
+    """The sum rule sum_n w_n A_n = 1 on a hierarchy, float32 against an oracle run (R17)."""
+    p = workloads.small_problem(M=41, N=48, nblocks=1, sigma=2e-3)
+    p.levels = orc.hierarchy(48)
+    p.constraint_c = np.asarray(p.weights, np.float64)
+    p.constraint_value = 1.0
+    prep = orc.prepare(p)
+    ores = orc.run(prep, chains=64, burnin=300, sweeps=3000, groups=32, seed=3)
+    plan = pk.Plan([p], chains=256, burnin=300, sweeps=3000, seed=4, precision="fp32", groups=32,
+                   lanes_per_chain=lanes)
+    res = plan.run()
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
+    assert ok, info
+    A = plan.state(0)[0].cpu().numpy()
+    assert np.max(np.abs(A @ p.constraint_c - 1.0)) < 1e-4
+    assert res.stats["mode_moves"] < 256 * 3300 * 48   # fewer modes than points
+    plan.close()
+
+
+def test_constraint_errors(pk):
+    p = workloads.small_problem(M=21, N=12, nblocks=2, seed=3)
+    p.constraint_c = np.zeros(12)
+    p.constraint_value = 1.0
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp64", groups=4)
+    assert e.value.code == pk.ASM_EINVAL
+    # mixed signs: the start is moved along c and turns negative
+    p.constraint_c = np.r_[np.ones(6), -np.ones(6)]
+    p.constraint_value = 50.0
+    with pytest.raises(pk.AsmError) as e:
+        pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp32", groups=4)
+    assert e.value.code == pk.ASM_EDOMAIN
