@@ -190,14 +190,19 @@ def conductivity(args):
              for n in (40, 120)
              for name, nb in (("components", n), ("modes", 1), ("blocked4", 4), ("hierarchy", 1))]
     cases += [("N60s2_blocked4", 60, 4, 0.2, False, None), ("N120_prior60", 120, 4, 0.1, False, 0.5),
-              ("N60s2_prior120", 60, 4, 0.2, False, 2.0), ("N60s2_noise120", 60, 4, 0.2, False, "noise")]
+              ("N60s2_prior120", 60, 4, 0.2, False, 2.0), ("N60s2_noise120", 60, 4, 0.2, False, "noise"),
+              ("N120_hierarchy_sumrule", 120, 1, 0.1, True, "sumrule")]
     for key, n, nb, step, hier, shape in cases:
         if args.cases and key not in args.cases.split(","):
             continue
         p = workloads.optical_conductivity(n, nb, step=step)
         if hier:
             p.levels = pk.hierarchy(n)
-        if shape == "noise":
+        if shape == "sumrule":
+            # Sec. IV.E: the sum rule sum_n w_n sigma_n = (pi / 2) Pi(0) imposed exactly
+            p.constraint_c = np.asarray(p.weights, np.float64)
+            p.constraint_value = math.pi / 2.0 * float(p.G[0])
+        elif shape == "noise":
             # Sec. V.C's cheap variant: the data variance scaled by 120 / 60 instead of the shapes
             p.sigma = p.sigma * math.sqrt(120 / 60)
         elif shape is not None:
@@ -260,6 +265,9 @@ def conductivity(args):
     if all(k in means for k in ("N60s2_noise120", "N120_blocked4")):
         fig7["fine_flat_by_noise_scaling_on_coarse"] = {
             "rel_l2_to_fine_flat": rel(means["N60s2_noise120"][0], pair(means["N120_blocked4"][0]))}
+    if all(k in means for k in ("N120_hierarchy_sumrule", "N120_hierarchy")):
+        # Sec. IV.E: the sum rule is strongly represented in the data
+        fig7["sum_rule_imposed_rel_l2_to_free"] = rel(means["N120_hierarchy_sumrule"][0], means["N120_hierarchy"][0])
     main_row = rows.get("N120_hierarchy", next(iter(rows.values())))
     print(json.dumps({"metric": "mode-moves/s", "value": main_row["mode_moves_per_s"], "unit": "mode-moves/s",
                       "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
