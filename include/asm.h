@@ -128,7 +128,7 @@ typedef struct {
                                     cross moments, float64 refresh) from a hipGraph captured
                                     once per run; results are identical to eager launches    */
     int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
-                                    or ASM_START_NNLS                                        */
+                                    ASM_START_NNLS or ASM_START_NNLS_NOISED                   */
     int32_t roles;               /* ASM_FP32 with 16 lanes per chain: 0 = two roles when the
                                     problems allow it (every problem of two blocks or more,
                                     no hierarchy),
@@ -145,6 +145,11 @@ typedef struct {
                               K~ x = g~ (Lawson-Hanson, float64): a start close to the best
                               fit, as Sec. IV.D suggests, kept strictly positive so that no
                               zero mode starts with an empty interval                        */
+#define ASM_START_NNLS_NOISED 2   /* the same from noised data, as Sec. IV.D prefers: K~ x = g~ + xi
+                              and c* of g~ + xi, xi_m = sqrt(-2 ln u1) cos(2 pi u2) with u1, u2
+                              the float64 uniforms ((w0 >> 6) 2^26 + (w1 >> 6) + 1/2) 2^-52 of
+                              the words (w0, w1) and (w2, w3) of Philox4x32-10 on counter
+                              (2^32 - 2, m, 0, 5), key (seed_lo, seed_hi ^ problem index)    */
 
 typedef struct {
     double setup_ms;             /* whitening + decompositions + packing + start state        */

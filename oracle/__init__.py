@@ -264,17 +264,36 @@ def block_factors(Kb: np.ndarray, k_req: Optional[int]):
     return sv[:k].copy(), Ud, V, sv.copy()
 
 
-def nnls_start(prep: Prepared, blend: float = 0.01) -> np.ndarray:
+def data_noise(seed: int, problem: int, M: int) -> np.ndarray:
+    """Standard normal noise for the whitened data (Sec. IV.D suggests the NNLS fit of noised
+    data as the start): Box-Muller, xi_m = sqrt(-2 ln u1) cos(2 pi u2), with u1 and u2 the
+    uniforms of words (w0, w1) and (w2, w3) of Philox on counter (2^32 - 2, m, 0, 5)."""
+    seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    key = [seed & 0xFFFFFFFF, ((seed >> 32) ^ int(problem)) & 0xFFFFFFFF]
+
+    def u01(a, b):
+        return ((int(a) >> 6) * 2 ** 26 + (int(b) >> 6) + 0.5) * 2.0 ** -52
+
+    out = np.empty(M)
+    for m in range(M):
+        w = philox([0xFFFFFFFE, m, 0, 5], key)
+        out[m] = np.sqrt(-2.0 * np.log(u01(w[0], w[1]))) * np.cos(2.0 * np.pi * u01(w[2], w[3]))
+    return out
+
+
+def nnls_start(prep: Prepared, blend: float = 0.01, noise_seed=None, problem: int = 0) -> np.ndarray:
     """Start model from the non-negative least-squares fit, Sec. IV.D (start from NNLS).
 
     The NNLS solution of K~ f = g~ (Lawson-Hanson, scipy) has exact zeros, which would
     leave most zero modes with an empty interval; it is therefore blended with the best
-    constant fit: f0 = (1 - blend) f_NNLS + blend c*.
+    constant fit: f0 = (1 - blend) f_NNLS + blend c*.  With noise_seed, both are taken of the
+    noised data g~ + xi (data_noise).
     """
     from scipy.optimize import nnls
-    x, _ = nnls(prep.Kt, prep.gt, maxiter=50 * prep.N)
+    g = prep.gt if noise_seed is None else prep.gt + data_noise(noise_seed, problem, prep.M)
+    x, _ = nnls(prep.Kt, g, maxiter=50 * prep.N)
     one = prep.Kt @ np.ones(prep.N)
-    cstar = float(np.dot(one, prep.gt) / np.dot(one, one))
+    cstar = float(np.dot(one, g) / np.dot(one, one))
     if not (cstar > 0.0 and np.isfinite(cstar)):
         cstar = 1.0
     return (1.0 - blend) * x + blend * cstar

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libasm.so")
 
 ASM_OK, ASM_EINVAL, ASM_EDOMAIN, ASM_ESTATE, ASM_EUNBOUNDED, ASM_EHIP, ASM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 ASM_FP64, ASM_FP32 = 0, 1
-ASM_START_FLAT, ASM_START_NNLS = 0, 1
+ASM_START_FLAT, ASM_START_NNLS, ASM_START_NNLS_NOISED = 0, 1, 2
 
 EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_advance", "asm_plan_state",
             "asm_plan_factors", "asm_plan_whitened", "asm_plan_destroy", "asm_tn_draw",
@@ -179,7 +179,8 @@ class Plan:
                                 refresh_every=int(refresh_every), want_vjp=int(bool(want_vjp)),
                                 groups=int(groups), lanes_per_chain=int(lanes_per_chain),
                                 use_graph=int(bool(use_graph)),
-                                start=ASM_START_NNLS if start == "nnls" else ASM_START_FLAT,
+                                start={"nnls": ASM_START_NNLS, "nnls_noised": ASM_START_NNLS_NOISED}.get(
+                                    start, ASM_START_FLAT),
                                 roles=int(roles))
         self.chains = int(chains)
         self.handle = ctypes.c_void_p()

@@ -209,8 +209,8 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
     if (o->precision != ASM_FP64 && o->precision != ASM_FP32)
         return fail(ASM_EINVAL, "precision must be ASM_FP64 or ASM_FP32");
     if (o->refresh_every < 0) return fail(ASM_EINVAL, "refresh_every must be >= 0");
-    if (o->start != ASM_START_FLAT && o->start != ASM_START_NNLS)
-        return fail(ASM_EINVAL, "start must be ASM_START_FLAT or ASM_START_NNLS");
+    if (o->start != ASM_START_FLAT && o->start != ASM_START_NNLS && o->start != ASM_START_NNLS_NOISED)
+        return fail(ASM_EINVAL, "start must be ASM_START_FLAT, ASM_START_NNLS or ASM_START_NNLS_NOISED");
     if (o->groups < 0 || o->groups > 64) return fail(ASM_EINVAL, "groups must be in [1, 64]");
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 4 && o->lanes_per_chain != 8 &&
         o->lanes_per_chain != 16 && o->lanes_per_chain != 32)
@@ -1298,7 +1298,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     HSTEP(hipMemcpyAsync(has_init_d, has_init.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
 
     // ---- start from the non-negative least-squares fit where asked ----
-    if (o->start == ASM_START_NNLS) {
+    if (o->start == ASM_START_NNLS || o->start == ASM_START_NNLS_NOISED) {
         std::vector<int> use(n, 0);
         std::vector<int64_t> woff(n, 0);
         int64_t wtot = 0;
@@ -1316,7 +1316,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             STEP(dalloc(pl, &woff_d, n));
             HSTEP(hipMemcpyAsync(use_d, use.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
             HSTEP(hipMemcpyAsync(woff_d, woff.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st));
-            HSTEP(launch_nnls(pl->d_probs, n, use_d, pl->Kt, pl->gt, nw, woff_d, 0.01, tmpN,
+            const double *g = pl->gt;
+            if (o->start == ASM_START_NNLS_NOISED) {
+                double *gn = nullptr;
+                STEP(dalloc(pl, &gn, offm));
+                HSTEP(launch_noise_data(pl->d_probs, n, pl->gt, gn, o->seed, st));
+                g = gn;
+            }
+            HSTEP(launch_nnls(pl->d_probs, n, use_d, pl->Kt, g, nw, woff_d, 0.01, tmpN,
                               has_init_d, st));
         }
     }

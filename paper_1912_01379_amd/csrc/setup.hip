@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "rng_tn.h"
 
 namespace asmk {
 
@@ -428,6 +429,33 @@ hipError_t launch_pack32_blocks(const BlockDesc *blocks_dev, const int64_t *bloc
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack32, dim3((unsigned)nblocks), dim3(256), 0, s, blocks_dev, blockM_dev, V64,
                        U64, d64, cl, F32, U32, flags);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// noised data for the NNLS start (Sec. IV.D): g~ + xi, xi_m = sqrt(-2 ln u1) cos(2 pi u2) with
+// u1, u2 the float64 uniforms of words (w0, w1) and (w2, w3) of Philox on counter
+// (2^32 - 2, m, 0, 5), key (seed_lo, seed_hi ^ problem); one workgroup per problem
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_noise_data(const ProbDesc *probs, const double *gt, double *gn,
+                                                    uint64_t seed) {
+    const ProbDesc pd = probs[blockIdx.x];
+    auto u01 = [](uint32_t a, uint32_t b) {
+        const uint64_t j = ((uint64_t)(a >> 6) << 26) | (uint64_t)(b >> 6);
+        return ((double)j + 0.5) * 0x1.0p-52;
+    };
+    for (int64_t m = threadIdx.x; m < pd.M; m += blockDim.x) {
+        const U4 w = philox10(U4{0xFFFFFFFEu, (uint32_t)m, 0u, 5u}, (uint32_t)seed,
+                              (uint32_t)(seed >> 32) ^ pd.index);
+        const double xi = sqrt(-2.0 * log(u01(w.x, w.y))) * cos(2.0 * M_PI * u01(w.z, w.w));
+        gn[pd.off_m + m] = gt[pd.off_m + m] + xi;
+    }
+}
+
+hipError_t launch_noise_data(const ProbDesc *probs_dev, int64_t P, const double *gt, double *gn, uint64_t seed,
+                             hipStream_t s) {
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_noise_data, dim3((unsigned)P), dim3(256), 0, s, probs_dev, gt, gn, seed);
     return hipGetLastError();
 }
 

@@ -1035,3 +1035,18 @@ def test_constraint_errors(pk):
     with pytest.raises(pk.AsmError) as e:
         pk.Plan([p], chains=8, burnin=0, sweeps=4, precision="fp32", groups=4)
     assert e.value.code == pk.ASM_EDOMAIN
+
+
+def test_nnls_start_from_noised_data_matches_oracle(pk, orc):
+    """ASM_START_NNLS_NOISED: the NNLS fit (and c*) of g~ + xi, xi from the counter-based
+    normal draws, against scipy's NNLS of the oracle's noised data."""
+    for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
+        prep = orc.prepare(p)
+        ref = orc.nnls_start(prep, noise_seed=1234, problem=0)
+        plain = orc.nnls_start(prep)
+        plan = pk.Plan([p], chains=2, burnin=0, sweeps=1, precision="fp64", groups=1, seed=1234,
+                       start="nnls_noised")
+        a = plan.state(0)[0][0].cpu().numpy()
+        assert np.max(np.abs(a - ref)) < 1e-6 * np.max(np.abs(ref)), np.max(np.abs(a - ref))
+        assert np.max(np.abs(ref - plain)) > 1e-3 * np.max(np.abs(ref))   # the noise matters
+        plan.close()

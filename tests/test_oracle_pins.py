@@ -748,3 +748,12 @@ def test_constraint_two_point_grid_against_quadrature(orc):
     m1 = integrate.quad(lambda t: t * w(t) * math.exp(-shift), 0, F, epsabs=0, epsrel=1e-12, limit=200)[0] / Z
     ref = np.array([m1, F - m1])
     assert _within(res.mean, res.stderr, ref) < 4.5, (res.mean, ref)
+
+
+def test_data_noise_is_standard_normal(orc):
+    """The start's data noise (Box-Muller on Philox words) against the normal distribution."""
+    xi = orc.data_noise(77, 2, 20000)
+    assert abs(xi.mean()) < 4.5 / math.sqrt(20000)
+    assert abs(xi.var() - 1.0) < 4.5 * math.sqrt(2.0 / 20000)
+    assert stats.kstest(xi, "norm").pvalue > 1e-4
+    assert not np.array_equal(xi[:100], orc.data_noise(77, 3, 100))
