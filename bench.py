@@ -279,6 +279,54 @@ def conductivity(args):
                       "cases": rows, "fig7": fig7}))
 
 
+def grid_study(args):
+    """Sec. V-VI on the model-2 test case (Figs. 4, 8, 9, 10): the mean chi^2 / M of the
+    sampled spectra on uniform grids of step 0.1 with growing cutoff, and on Lorentzian
+    (width 2.5) and Gaussian (width 2.4) grids of growing N, with the Fig. 2 hierarchy (blocks
+    up to 128 points); and the default-model fit of Fig. 9 for each grid family."""
+    import torch
+    import workloads
+    import paper_1912_01379_amd as pk
+    from paper_1912_01379_amd import grids
+    dev = torch.device("cuda:0")
+    rows = {}
+    cases = [("uniform_cutoff%g" % (0.1 * n), n, None) for n in (40, 80, 120, 240)]
+    cases += [("lorentzian2.5_N%d" % n, n, ("lorentzian", 2.5)) for n in (32, 64, 128, 256, 512)]
+    cases += [("gaussian2.4_N%d" % n, n, ("gaussian", 2.4)) for n in (32, 64, 128, 256, 512)]
+    t_all = time.perf_counter()
+    moves = 0.0
+    for key, n, fam in cases:
+        g = None if fam is None else grids.grid(fam[0], fam[1], n)
+        p = workloads.optical_conductivity(n, 1, model=2, grid=g)
+        p.levels = pk.hierarchy(n, max_block=128)
+        dp = _DevProblem(p, dev)
+        plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2027,
+                       precision="fp32", refresh_every=64, groups=32, lanes_per_chain=args.lanes,
+                       start="nnls", device=dev)
+        res = plan.run()
+        chi2 = plan.state(0)[2].cpu().numpy() / len(p.G)
+        moves += res.stats["mode_moves"]
+        rows[key] = {"N": n, "chi2_over_M_mean": float(np.mean(chi2)), "chi2_over_M_p90": float(np.percentile(chi2, 90)),
+                     "sample_ms": res.stats["sample_ms"]}
+        plan.close()
+        print(f"{key} done", file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t_all
+    p = workloads.optical_conductivity(40, 1, model=2)
+    wm = 2.0 * np.pi * np.arange(len(p.G)) / 15.0
+    fit = {}
+    for fam, b in (("gaussian", (0.5, 10.0)), ("exponential", (0.3, 10.0)), ("lorentzian", (0.1, 10.0)),
+                   ("uniform", (1.0, 20.0))):
+        par, sse = grids.fit_default_model(fam, p.G, wm, b)
+        fit[fam] = {"best_parameter": par, "sse": sse}
+    print(json.dumps({"metric": "mode-moves/s", "value": moves / dt, "unit": "mode-moves/s", "n_gpus": 1,
+                      "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "grid study (Secs. V-VI): optical conductivity model 2, uniform, "
+                                             "Lorentzian and Gaussian grids, Fig. 2 hierarchy",
+                                 "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps},
+                      "cases": rows, "fig9_default_model_fit": fit}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,7 +339,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "conductivity"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "conductivity", "grids"], default="single")
     ap.add_argument("--graph", action="store_true", help="replay refresh cycles from a hipGraph")
     ap.add_argument("--cases", default="", help="conductivity workload: comma list such as N120_hierarchy")
     ap.add_argument("--hierarchy", action="store_true",
@@ -308,6 +356,9 @@ def main():
         return
     if args.workload == "conductivity":
         conductivity(args)
+        return
+    if args.workload == "grids":
+        grid_study(args)
         return
 
     import torch

@@ -1050,3 +1050,33 @@ def test_nnls_start_from_noised_data_matches_oracle(pk, orc):
         assert np.max(np.abs(a - ref)) < 1e-6 * np.max(np.abs(ref)), np.max(np.abs(a - ref))
         assert np.max(np.abs(ref - plain)) > 1e-3 * np.max(np.abs(ref))   # the noise matters
         plan.close()
+
+
+def _ndep_chi2(pk, fam, par, n, chains=1024, burnin=1000, sweeps=1000):
+    from paper_1912_01379_amd import grids
+    p = workloads.optical_conductivity(n, 1, model=2, grid=grids.grid(fam, par, n))
+    p.levels = pk.hierarchy(n, max_block=128)
+    plan = pk.Plan([p], chains=chains, burnin=burnin, sweeps=sweeps, seed=3, precision="fp32", groups=32,
+                   refresh_every=64, start="nnls")
+    res = plan.run()
+    chi2 = plan.state(0)[2].cpu().numpy() / len(p.G)
+    plan.close()
+    return float(np.mean(chi2)), res, p
+
+
+def test_grid_dependence_of_figs_8_and_10(pk, orc):
+    """Sec. VI, Figs. 8 and 10, on the model-2 test case with the Fig. 2 hierarchy: on the
+    Lorentzian grid of width 2.5 (a default model far from the data) the sampled fits worsen
+    as N grows; on the Gaussian grid of width 2.4 (a compatible default model) they do not.
+    The N = 64 averages match oracle runs."""
+    lor = [_ndep_chi2(pk, "lorentzian", 2.5, n)[0] for n in (32, 64, 128, 256)]
+    gau = [_ndep_chi2(pk, "gaussian", 2.4, n)[0] for n in (32, 64, 128, 256)]
+    assert all(b > a for a, b in zip(lor, lor[1:])) and lor[-1] > 1.3 * lor[0], lor
+    assert max(gau) < 1.05 * min(gau) and max(gau) < 1.0, gau
+    for fam, par in (("lorentzian", 2.5), ("gaussian", 2.4)):
+        _, res, p = _ndep_chi2(pk, fam, par, 64)
+        p.levels = orc.hierarchy(64, max_block=128)
+        prep = orc.prepare(p)
+        o = orc.run(prep, chains=64, burnin=1000, sweeps=1000, seed=8, groups=32, init=orc.nnls_start(prep))
+        ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), o.mean, o.stderr)
+        assert ok, (fam, info)

@@ -276,7 +276,7 @@ def bosonic_kernel(omega_m: np.ndarray, omega: np.ndarray) -> np.ndarray:
 
 def optical_conductivity(n_omega: int = 40, nblocks: int = 4, model: int = 1,
                          sigma_rel: float = 1e-3, beta: float = 15.0, n_matsubara: int = 60,
-                         seed: int = BASE_SEED + 6, step: float = 0.1) -> Problem:
+                         seed: int = BASE_SEED + 6, step: float = 0.1, grid=None) -> Problem:
     """The test case of Sec. III and Fig. 3: Pi(i omega_m) of Eq. (optcond) at the first 60
     bosonic Matsubara frequencies (beta = 15) from sigma(omega) of Eq. (model), with relative
     Gaussian noise of standard deviation sigma_rel; the grid is omega_n = 0.1 (n - 1/2),
@@ -285,8 +285,12 @@ def optical_conductivity(n_omega: int = 40, nblocks: int = 4, model: int = 1,
     (a fine mid-point rule up to omega = 400), not from the grid, so grids of another spacing
     (`step`) see the same data."""
     wm = 2.0 * np.pi * np.arange(n_matsubara) / beta
-    x = step * (np.arange(1, n_omega + 1) - 0.5)
-    w = np.full(n_omega, step)
+    if grid is None:
+        x = step * (np.arange(1, n_omega + 1) - 0.5)
+        w = np.full(n_omega, step)
+    else:   # (points, weights) of another grid on [0, inf)
+        x, w = (np.asarray(a, np.float64) for a in grid)
+        n_omega = len(x)
     K = bosonic_kernel(wm, x) * w[None, :]
     xf = (np.arange(400000) + 0.5) * 1e-3
     pi_exact = bosonic_kernel(wm, xf) @ (conductivity_model(xf, model) * 1e-3)
