@@ -572,13 +572,14 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
         Partition part;
         TRY(parse_partition(pr[p], p, &part));
         key += ";" + std::to_string(part.lcount.size());
-        hier |= (part.lcount.size() > 1 || pr[p].prior_shape) ? 1 : 0;
+        hier |= (part.lcount.size() > 1 || pr[p].prior_shape || pr[p].constraint_c) ? 1 : 0;
         for (int64_t b = 0; b < pr[p].B; ++b) {
             const int64_t nb = part.nb[b];
             max_nb = std::max(max_nb, nb);
             key += "," + std::to_string(part.n0[b]) + "+" + std::to_string(nb) + ":" +
                    std::to_string(pr[p].k ? pr[p].k[b] : -1);
         }
+        key += std::string(pr[p].prior_shape ? "p" : "") + (pr[p].constraint_c ? "c" : "");
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
