@@ -131,7 +131,7 @@ typedef struct {
                                     ASM_START_NNLS or ASM_START_NNLS_NOISED                   */
     int32_t roles;               /* ASM_FP32 with 16 lanes per chain: 0 = two roles when the
                                     problems allow it (every problem of two blocks or more,
-                                    no hierarchy),
+                                    no hierarchy, prior or constraint),
                                     1 = one role, 2 = two roles (ASM_EINVAL if not allowed).
                                     Two roles run the data modes of block b + 1 beside the
                                     zero modes of block b, which act on disjoint state (the
