@@ -353,6 +353,7 @@ SampleArgs make_args(asm_plan *pl) {
     a.lvl = pl->d_lvl;
     a.shape = pl->shape;
     a.hier = pl->ext() ? 1 : 0;
+    a.prior = pl->any_prior ? 1 : 0;
     a.wm1f = pl->wm1f;
     return a;
 }

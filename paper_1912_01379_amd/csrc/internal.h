@@ -119,7 +119,7 @@ struct SampleArgs {
                               //    (float32: the extended instances, which draw a level per
                               //    sweep, stage each block to its size, and test moves against
                               //    the prior)
-    int32_t pad2;
+    int32_t prior;            // 1: a problem has a gamma prior (the extended form with its test)
 };
 
 // ------------------------------------------------------------------------------------

@@ -297,9 +297,10 @@ struct Prefetch {
 // which leaves them the whole register file.  H: the instance for plans with a hierarchy of
 // partitions (a level drawn per sweep, blocks staged to their own size, no prefetch); the
 // single-partition instances carry none of its code.
-template <int L, int EPT, int RPT, int PF, bool H>
+template <int L, int EPT, int RPT, int PF, bool H, bool P>
 __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     static_assert(!(H && PF > 0), "hierarchies run the non-prefetching instances");
+    static_assert(H || !P, "the gamma prior runs in the extended instances");
     extern __shared__ __align__(16) unsigned char smem32[];
     constexpr int ROW = EPT * L;
     constexpr int MP = RPT * L;
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         }
         float *urow = sUnif + slotc * ROW;
         // gamma prior: the acceptance uniforms in a second row per chain, after the first rows
-        const bool PRI = H && pd.has_prior;
+        const bool PRI = P && pd.has_prior;
         float *urowA = sUnif + (nthr / L + slotc) * ROW;
         PriorRegs<EPT> pr;
         pr.rej = 0;
@@ -556,27 +557,35 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     }
 }
 
+// three compiled forms per shape: the plain one, the extended one (hierarchies, constraints)
+// and the extended one with the gamma prior's test, so that each carries only its own code
 template <int L, int EPT, int RPT, int PF>
 hipError_t launch_sample32_t(const SampleArgs &a, int threads, int grid, size_t lds, hipStream_t s) {
     if (a.hier) {
         if constexpr (PF > 0) {
-            return hipErrorInvalidValue;   // hierarchies run the non-prefetching instances
+            return hipErrorInvalidValue;   // the extended forms are non-prefetching
         } else {
-            hipLaunchKernelGGL((k_sample32<L, EPT, RPT, 0, true>), dim3(grid), dim3(threads), lds, s, a);
+            if (a.prior)
+                hipLaunchKernelGGL((k_sample32<L, EPT, RPT, 0, true, true>), dim3(grid), dim3(threads), lds, s, a);
+            else
+                hipLaunchKernelGGL((k_sample32<L, EPT, RPT, 0, true, false>), dim3(grid), dim3(threads), lds, s, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_sample32<L, EPT, RPT, PF, false>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_sample32<L, EPT, RPT, PF, false, false>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 template <int L, int EPT, int RPT, int PF>
 hipError_t allow_lds_sample32_t(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, PF, false>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, PF, false, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if constexpr (PF == 0) {
-        const hipError_t e1 = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, 0, true>,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        hipError_t e1 = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, 0, true, false>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess) e = e1;
+        e1 = hipFuncSetAttribute((const void *)k_sample32<L, EPT, RPT, 0, true, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess) e = e1;
     }
     return e;

@@ -1080,3 +1080,26 @@ def test_grid_dependence_of_figs_8_and_10(pk, orc):
         o = orc.run(prep, chains=64, burnin=1000, sweeps=1000, seed=8, groups=32, init=orc.nnls_start(prep))
         ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), o.mean, o.stderr)
         assert ok, (fam, info)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vjp_gaussian_limit_with_a_hierarchy(pk, orc, precision):
+    """The VJP's closed form in the Gaussian limit does not depend on the partitions: sampled
+    on the Fig. 2 hierarchy of its 4 points it is the same J^T v."""
+    p = workloads.gaussian_limit_problem()
+    p.levels = pk.hierarchy(p.N)
+    prep = orc.prepare(p)
+    Kt = prep.Kt
+    cov = np.linalg.inv(Kt.T @ Kt)
+    J = cov @ Kt.T / p.sigma[None, :]
+    v = np.array([1.0, -0.5, 0.25, 2.0])
+    plan = pk.Plan([p], chains=1024, burnin=20, sweeps=400, precision=precision, groups=32,
+                   want_vjp=True, seed=23)
+    res = plan.run()
+    mean = cov @ Kt.T @ prep.gt
+    ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), mean, 0 * mean)
+    assert ok, info
+    g = plan.vjp(v).cpu().numpy()
+    ref = J.T @ v
+    assert np.linalg.norm(g - ref) < 0.02 * np.linalg.norm(ref)
+    plan.close()
