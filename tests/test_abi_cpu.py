@@ -148,3 +148,33 @@ def test_hierarchy_matches_the_oracle():
     nl, ns = ctypes.c_int64(), ctypes.c_int64()
     assert pk.lib().asm_hierarchy(0, 0, ctypes.byref(nl), ctypes.byref(ns), None, None) == pk.ASM_EINVAL
     assert pk.lib().asm_hierarchy(5, 0, None, ctypes.byref(ns), None, None) == pk.ASM_EINVAL
+
+
+def test_a_c_program_uses_the_library(tmp_path):
+    """The header is plain C99 and the library links into a C program; the host-only entry
+    point runs without a GPU."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "asm.h"
+int main(void) {
+    int64_t levels = 0, n_starts = 0, lb[64], st[64];
+    if (asm_hierarchy(8, 0, &levels, &n_starts, lb, st) != ASM_OK) return 1;
+    printf("%lld %lld", (long long)levels, (long long)n_starts);
+    for (int64_t i = 0; i < n_starts; ++i) printf(" %lld", (long long)st[i]);
+    printf(" %d\n", asm_version());
+    return 0;
+}
+''')
+    exe = tmp_path / "use"
+    libdir = os.path.dirname(LIB)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-L", libdir, "-lasm", "-Wl,-rpath," + libdir, "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split()
+    # Fig. 2 on 8 points: [0 8], [0 4 8], [0 1 3 5 7 8], [0 1 ... 8]
+    assert out[:2] == ["4", "20"]
+    assert [int(x) for x in out[2:-1]] == [0, 8, 0, 4, 8, 0, 1, 3, 5, 7, 8] + list(range(9))
