@@ -363,6 +363,9 @@ int refresh(asm_plan *pl, bool measure_drift) {
     if (measure_drift && pl->fp32)
         HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,
                               pl->r32, pl->r64, pl->fp32, pl->chi2_prev, nullptr, nullptr, pl->stream));
+    if (pl->fp32 && pl->any_con)   // float32 chains back onto c . A = F
+        HIPCHK(launch_con_fix(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains, pl->con,
+                              pl->A32, pl->stream));
     HIPCHK(launch_refresh_all(pl->d_probs, pl->P, pl->max_refresh_tiles, pl->Kt, pl->gt, pl->A32,
                               pl->r32, pl->A64, pl->r64, pl->fp32, pl->stream));
     HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,

@@ -163,6 +163,8 @@ hipError_t launch_con_map(const ConTask *tasks_dev, int64_t n, const double *hv,
                           hipStream_t s);
 hipError_t launch_noise_data(const ProbDesc *probs_dev, int64_t P, const double *gt, double *gn, uint64_t seed,
                              hipStream_t s);
+hipError_t launch_con_fix(const ProbDesc *probs_dev, const int32_t *chain_problem, const int32_t *chain_local,
+                          int64_t total_chains, const double *con, float *A32, hipStream_t s);
 hipError_t launch_con_start(const ProbDesc *probs_dev, const int32_t *which, int64_t n, const double *con,
                             double *A64, float *A32, int fp32, int *flag, int bit, hipStream_t s);
 hipError_t launch_block_svd_tasks(const SvdTask *tasks_dev, int64_t ntasks, const double *Kt,

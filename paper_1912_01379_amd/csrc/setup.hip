@@ -600,6 +600,32 @@ __global__ __launch_bounds__(256) void k_con_start(const ProbDesc *probs, const 
     if (bad) atomicOr(flag, 1 << bit);
 }
 
+// The float32 chains drift off c . A = F by rounding (each move keeps it only to float32
+// precision); at every refresh each chain of a constrained problem is scaled back onto it, just
+// before its residual is recomputed.  One wavefront per chain.
+__global__ __launch_bounds__(64) void k_con_fix(const ProbDesc *probs, const int32_t *chain_problem,
+                                                const int32_t *chain_local, const double *con, float *A32) {
+    const ProbDesc pd = probs[chain_problem[blockIdx.x]];
+    if (!pd.has_con) return;
+    const int64_t N = pd.N;
+    float *A = A32 + pd.off_A + (int64_t)chain_local[blockIdx.x] * N;
+    const double *c = con + pd.off_n;
+    double cs = 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += 64) cs += c[n] * (double)A[n];
+    for (int o = 32; o >= 1; o >>= 1) cs += __shfl_xor(cs, o);
+    const double f = pd.con_value / cs;
+    if (!(cs != 0.0 && f > 0.0)) return;
+    for (int64_t n = threadIdx.x; n < N; n += 64) A[n] = (float)((double)A[n] * f);
+}
+
+hipError_t launch_con_fix(const ProbDesc *probs_dev, const int32_t *chain_problem, const int32_t *chain_local,
+                          int64_t total_chains, const double *con, float *A32, hipStream_t s) {
+    if (total_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_con_fix, dim3((unsigned)total_chains), dim3(64), 0, s, probs_dev, chain_problem,
+                       chain_local, con, A32);
+    return hipGetLastError();
+}
+
 hipError_t launch_con_start(const ProbDesc *probs_dev, const int32_t *which, int64_t n, const double *con,
                             double *A64, float *A32, int fp32, int *flag, int bit, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -1017,7 +1017,8 @@ def test_fp32_constraint_on_a_hierarchy_matches_oracle(pk, orc, lanes):
     ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), ores.mean, ores.stderr)
     assert ok, info
     A = plan.state(0)[0].cpu().numpy()
-    assert np.max(np.abs(A @ p.constraint_c - 1.0)) < 1e-4
+    # scaled back onto the constraint at every refresh: only the drift of the last 36 sweeps
+    assert np.max(np.abs(A @ p.constraint_c - 1.0)) < 1e-5
     assert res.stats["mode_moves"] < 256 * 3300 * 48   # fewer modes than points
     plan.close()
 
