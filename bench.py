@@ -279,8 +279,56 @@ def conductivity(args):
                       "cases": rows, "fig7": fig7}))
 
 
+def fig6_grid_dependence(dev, chains=4096, burnin=2000, sweeps=10000, lanes=16):
+    """Sec. V.B, Fig. 6: the model-2 test case on 64-point grids (uniform with spacing 0.125,
+    cutoff 8; Gaussian alpha = 4, exponential beta = 3, Lorentzian gamma = 2.5) at relative
+    noise 1e-3 and 1e-2, with the Fig. 2 hierarchy.  Reported per grid: the w-weighted relative
+    L2 distance of the average to the exact sigma; per pair of non-uniform grids: their
+    averages interpolated to 120 frequencies in [0.05, 6], the largest |difference| / combined
+    error bar, the fraction of frequencies beyond 3 error bars and the relative L2 difference.
+    Also the width dependence (Gaussian alpha = 3 against 5) beside the cutoff dependence
+    (uniform spacing 0.125 against 0.25, cutoffs 8 and 16) at noise 1e-3."""
+    import paper_1912_01379_amd as pk
+    import workloads
+    from paper_1912_01379_amd import grids
+    wc = np.linspace(0.05, 6.0, 120)
+
+    def average(srel, fam, par, step=0.125):
+        g = None if fam == "uniform" else grids.grid(fam, par, 64)
+        p = workloads.optical_conductivity(64, 1, model=2, sigma_rel=srel, step=step, grid=g)
+        p.levels = pk.hierarchy(64, max_block=128)
+        plan = pk.Plan([_DevProblem(p, dev)], chains=chains, burnin=burnin, sweeps=sweeps, seed=2029,
+                       precision="fp32", refresh_every=64, groups=32, lanes_per_chain=lanes, start="nnls",
+                       device=dev)
+        r = plan.run()
+        m, se = r.mean.cpu().numpy(), r.stderr.cpu().numpy()
+        plan.close()
+        ex = p.A_true
+        d = math.sqrt(np.sum(p.weights * (m - ex) ** 2) / np.sum(p.weights * ex ** 2))
+        return p.omega, m, se, d
+
+    def pair(r1, r2):
+        a, b = np.interp(wc, r1[0], r1[1]), np.interp(wc, r2[0], r2[1])
+        z = np.abs(a - b) / np.hypot(np.interp(wc, r1[0], r1[2]), np.interp(wc, r2[0], r2[2]))
+        return {"max_z": float(z.max()), "frac_beyond_3": float(np.mean(z > 3.0)),
+                "rel_l2": float(math.sqrt(np.sum((a - b) ** 2) / np.sum((0.5 * (a + b)) ** 2)))}
+
+    out = {}
+    fams = (("uniform", 0.0), ("gaussian", 4.0), ("exponential", 3.0), ("lorentzian", 2.5))
+    for srel in (1e-3, 1e-2):
+        res = {f: average(srel, f, par) for f, par in fams}
+        out[f"noise{srel:g}"] = {
+            "rel_l2_to_exact": {f: res[f][3] for f, _ in fams},
+            "pairs": {f"{f1}-{f2}": pair(res[f1], res[f2])
+                      for i, (f1, _) in enumerate(fams[1:]) for f2, _ in fams[i + 2:]}}
+    out["width_vs_cutoff"] = {"gaussian3-gaussian5": pair(average(1e-3, "gaussian", 3.0), average(1e-3, "gaussian", 5.0)),
+                              "uniform0.125-uniform0.25": pair(average(1e-3, "uniform", 0.0),
+                                                               average(1e-3, "uniform", 0.0, step=0.25))}
+    return out
+
+
 def grid_study(args):
-    """Sec. V-VI on the model-2 test case (Figs. 4, 8, 9, 10): the mean chi^2 / M of the
+    """Sec. V-VI on the model-2 test case (Figs. 4, 6, 8, 9, 10): the mean chi^2 / M of the
     sampled spectra on uniform grids of step 0.1 with growing cutoff, and on Lorentzian
     (width 2.5) and Gaussian (width 2.4) grids of growing N, with the Fig. 2 hierarchy (blocks
     up to 128 points); and the default-model fit of Fig. 9 for each grid family."""
@@ -324,7 +372,9 @@ def grid_study(args):
                       "config": {"workload": "grid study (Secs. V-VI): optical conductivity model 2, uniform, "
                                              "Lorentzian and Gaussian grids, Fig. 2 hierarchy",
                                  "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps},
-                      "cases": rows, "fig9_default_model_fit": fit}))
+                      "cases": rows, "fig9_default_model_fit": fit,
+                      "fig6_grid_dependence": fig6_grid_dependence(dev, args.chains, args.burnin, args.sweeps,
+                                                                   args.lanes or 16)}))
 
 
 def main():

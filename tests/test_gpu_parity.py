@@ -1083,6 +1083,27 @@ def test_grid_dependence_of_figs_8_and_10(pk, orc):
         assert ok, (fam, info)
 
 
+def test_grid_dependence_of_fig_6(pk):
+    """Sec. V.B, Fig. 6: on 64-point grids, the Gaussian and exponential grids (no cutoff)
+    give averages closer to the exact sigma than the uniform grid with cutoff 8; the averages
+    of different non-uniform grids differ by more than their error bars, more so at the larger
+    noise; the width parameter matters less than the cutoff."""
+    import torch
+    import bench
+    r = bench.fig6_grid_dependence(torch.device("cuda:0"))   # 4096 chains, 12,000 sweeps: seconds
+    print(r)
+    spread = {}
+    for nz in ("noise0.001", "noise0.01"):
+        d = r[nz]["rel_l2_to_exact"]
+        assert max(d["gaussian"], d["exponential"]) < 0.8 * d["uniform"], (nz, d)
+        assert all(q["frac_beyond_3"] > 0.5 for q in r[nz]["pairs"].values()), (nz, r[nz]["pairs"])
+        spread[nz] = np.mean([q["rel_l2"] for q in r[nz]["pairs"].values()])
+    # at noise 1e-3 shorter runs are not yet converged and spread more (0.056 after 5000 sweeps)
+    assert spread["noise0.01"] > 1.15 * spread["noise0.001"], spread
+    wv = r["width_vs_cutoff"]
+    assert wv["gaussian3-gaussian5"]["rel_l2"] < wv["uniform0.125-uniform0.25"]["rel_l2"], wv
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_vjp_gaussian_limit_with_a_hierarchy(pk, orc, precision):
     """The VJP's closed form in the Gaussian limit does not depend on the partitions: sampled
