@@ -44,6 +44,8 @@ _lock = threading.Lock()
 _lib = None
 
 EPS = np.finfo(np.float64).eps
+GL_NODES = 20
+_gl_keep = []
 
 
 def build(force: bool = False) -> str:
@@ -87,16 +89,14 @@ def lib():
         if _lib is None:
             build()
             L = ctypes.CDLL(_LIB_PATH)
-            L.orc_E.restype = ctypes.c_double
-            L.orc_E.argtypes = [ctypes.c_double, ctypes.c_double]
-            L.orc_S.restype = ctypes.c_double
-            L.orc_S.argtypes = [ctypes.c_double] * 4
+            L.orc_mass.restype = ctypes.c_double
+            L.orc_mass.argtypes = [ctypes.c_double] * 3
+            L.orc_set_quadrature.restype = None
+            L.orc_set_quadrature.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
             L.orc_tn_draw.restype = ctypes.c_double
             L.orc_tn_draw.argtypes = [ctypes.c_double] * 5
             L.orc_mills.restype = ctypes.c_double
             L.orc_mills.argtypes = [ctypes.c_double]
-            L.orc_Mk.restype = ctypes.c_double
-            L.orc_Mk.argtypes = [ctypes.c_int, ctypes.c_double]
             L.orc_move_uniform.restype = ctypes.c_double
             L.orc_move_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_int64] * 5
             L.orc_sweep_level.restype = ctypes.c_int64
@@ -106,6 +106,10 @@ def lib():
             L.orc_run.restype = ctypes.c_int
             L.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
                                   ctypes.POINTER(_Out)]
+            # the truncated-normal masses over short stretches: 20-point Gauss-Legendre
+            x, w = np.polynomial.legendre.leggauss(GL_NODES)
+            _gl_keep[:] = [np.ascontiguousarray(x), np.ascontiguousarray(w)]
+            L.orc_set_quadrature(GL_NODES, _gl_keep[0].ctypes.data, _gl_keep[1].ctypes.data)
             _lib = L
     return _lib
 
@@ -114,25 +118,20 @@ def lib():
 # scalar helpers exposed for the pins
 # --------------------------------------------------------------------------------------
 
-def E(a: float, t: float) -> float:
-    return lib().orc_E(float(a), float(t))
-
-
-def S(a: float, w: float, u: float, uc: Optional[float] = None) -> float:
-    uc = 1.0 - u if uc is None else uc
-    return lib().orc_S(float(a), float(w), float(u), float(uc))
+def mass(r0: float, t1: float, t2: float) -> float:
+    """int_{t1}^{t2} exp(-tau (2 r0 + tau) / 2) dtau: the normal mass of [r0 + t1, r0 + t2]
+    divided by the density at r0 (the truncated normal's distribution function is a ratio
+    of two of these)."""
+    return lib().orc_mass(float(r0), float(t1), float(t2))
 
 
 def tn_draw(c: float, d: float, lo: float, hi: float, u: float) -> float:
+    """The u-quantile of N(c/d, 1/d^2) restricted to [lo, hi] (Sec. IV.B), by bisection."""
     return lib().orc_tn_draw(float(c), float(d), float(lo), float(hi), float(u))
 
 
 def mills(x: float) -> float:
     return lib().orc_mills(float(x))
-
-
-def Mk(k: int, z: float) -> float:
-    return lib().orc_Mk(int(k), float(z))
 
 
 def move_uniform(seed, problem, chain, sweep, block, mode) -> float:

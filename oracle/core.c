@@ -114,173 +114,132 @@ static double prior_log_ratio(double a_new, double a_old, double wm1) {
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* One-dimensional truncated standard normal, by inversion.                             */
+/* One-dimensional truncated normal, by inversion of its distribution function          */
+/* (Sec. IV.B: a data mode is redrawn from a Gaussian of width 1/d centred on the best  */
+/* fit, cut to the interval of Eq. (modeLimits)).                                       */
 /*                                                                                      */
-/* Everything is reduced to one problem: draw t in [0, w] from the density proportional */
-/* to p(t) = exp(-a t - t^2/2) with a >= 0.  Its unnormalised distribution function is  */
-/*     E(a, t) = int_0^t exp(-a s - s^2/2) ds                                           */
-/*             = m(a) - m(a + t) exp(-t (a + t/2)),  m(x) = Q(x)/phi(x) (Mills ratio).  */
-/* For small t the difference cancels, so a power series in t is used there:           */
-/*     E(a, t) = sum_j (-1/2)^j / j! * t^(2j+1) * M_2j(a t),                            */
-/*     M_k(z)  = int_0^1 v^k exp(-z v) dv.                                              */
+/* In standard units x = d delta - c the step is the u-quantile of a standard normal    */
+/* restricted to [a, b], a = d lo - c, b = d hi - c: the x at which                     */
+/*     F(x) = P(a <= X <= x) / P(a <= X <= b)                                           */
+/* equals u.  It is found by plain bisection of F, nothing else.                        */
+/*                                                                                      */
+/* An interval below the centre (b <= 0) is first reflected (x -> -x, u -> 1 - u), so   */
+/* the interval either lies above the centre (a >= 0) or contains it.  Masses are then  */
+/* measured relative to the density at a reference point r0 (r0 = a above the centre,  */
+/* 0 around it), in the offset tau = x - r0, so that no tail underflows:                */
+/*     S(t1, t2) = int_{t1}^{t2} g(tau) dtau,   g(tau) = exp(-tau (2 r0 + tau) / 2).    */
+/* Over a short stretch (where g changes by at most a factor e^2) S is a Gauss-Legendre */
+/* sum, exact to rounding there.  Over a longer stretch it is a difference of upper     */
+/* tails T(tau) = int_tau^inf g = Q(r0 + tau) / phi(r0), Q the normal upper tail, which */
+/* then cancels by at most the factor 1 - e^-2.  Q / phi is taken from erfc below 8 and */
+/* from the Laplace continued fraction above.                                           */
+/* For u <= 1/2 the bisection solves S(ta, tau) = u S(ta, tb); above, it solves the     */
+/* complementary S(tau, tb) = (1 - u) S(ta, tb), so both tails keep relative accuracy.  */
 /* ------------------------------------------------------------------------------------ */
-static const double SQRT_HALF_PI = 1.2533141373155002512;  /* sqrt(pi/2) */
+static const double SQRT_2PI = 2.5066282746310002416;
 
-/* Mills ratio Q(x)/phi(x) for x >= 0. */
+/* Gauss-Legendre nodes and weights on [-1, 1], set by the Python driver from numpy's
+   leggauss before any draw. */
+#define GL_MAX 32
+static int gl_n = 0;
+static double gl_x[GL_MAX], gl_w[GL_MAX];
+
+void orc_set_quadrature(int n, const double *x, const double *w) {
+    if (n > GL_MAX) n = GL_MAX;
+    for (int i = 0; i < n; ++i) { gl_x[i] = x[i]; gl_w[i] = w[i]; }
+    gl_n = n;
+}
+
+/* Mills ratio Q(x) / phi(x), x >= 0. */
 static double mills(double x) {
-    if (x < 5.0) {
-        /* erfc(x/sqrt2) * sqrt(pi/2) * exp(x^2/2); x^2 split exactly into hi + lo. */
+    if (x < 8.0) {
+        /* Q(x) = erfc(x / sqrt2) / 2; 1 / phi(x) = sqrt(2 pi) exp(x^2 / 2), with x^2 split
+           exactly into hi + lo so that the exponential keeps its accuracy */
         double hi = x * x;
         double lo = fma(x, x, -hi);
-        return SQRT_HALF_PI * erfc(x * 0.70710678118654752440) * exp(0.5 * hi) * exp(0.5 * lo);
+        return 0.5 * erfc(x * 0.70710678118654752440) * SQRT_2PI * exp(0.5 * hi) * exp(0.5 * lo);
     }
-    /* Laplace continued fraction m(x) = 1/(x + 1/(x + 2/(x + 3/(x + ...)))),
-       evaluated from a deep tail backwards. */
+    /* m(x) = 1 / (x + 1 / (x + 2 / (x + 3 / (x + ...)))), evaluated from deep down */
     double f = x;
-    for (int k = 400; k >= 1; --k) f = x + (double)k / f;
+    for (int k = 200; k >= 1; --k) f = x + (double)k / f;
     return 1.0 / f;
 }
 
-/* M_k(z) = int_0^1 v^k e^{-z v} dv, z >= 0. */
-static double Mk(int k, double z) {
-    if (k == 0) {
-        if (z == 0.0) return 1.0;
-        return -expm1(-z) / z;
-    }
-    if (z <= 50.0) {
-        /* gamma(k+1, z)/z^(k+1) = e^{-z} sum_j z^j / ((k+1)(k+2)...(k+1+j)) */
-        double term = 1.0 / (double)(k + 1);
-        double sum = term;
-        for (int j = 1; j < 400; ++j) {
-            term *= z / (double)(k + 1 + j);
-            sum += term;
-            if (term < 1e-18 * sum) break;
-        }
-        return exp(-z) * sum;
-    }
-    /* k!/z^(k+1) * (1 - e^{-z} sum_{j<=k} z^j/j!) */
-    double fact = 1.0, poly = 1.0, zj = 1.0;
-    for (int j = 1; j <= k; ++j) {
-        fact *= (double)j;
-        zj *= z / (double)j;
-        poly += zj;
-    }
-    double zk1 = pow(z, (double)(k + 1));
-    return fact / zk1 * (1.0 - exp(-z) * poly);
+/* T(tau) = int_tau^inf g for r0 + tau >= 0: Q(r0 + tau) / phi(r0). */
+static double tail_T(double r0, double tau) {
+    if (isinf(tau)) return 0.0;
+    return mills(r0 + tau) * exp(-0.5 * tau * (2.0 * r0 + tau));
 }
 
-#define TSERIES 0.25
-
-double orc_E(double a, double t) {
-    if (t <= 0.0) return 0.0;
-    if (isinf(t)) return mills(a);
-    if (t <= TSERIES) {
-        double z = a * t;
-        double coef = t, sum = 0.0;
-        for (int j = 0; j < 10; ++j) {
-            sum += coef * Mk(2 * j, z);
-            coef *= -(t * t) / (2.0 * (double)(j + 1));
+/* S(t1, t2) = int_{t1}^{t2} g, t1 <= t2 (either may be infinite); r0 >= 0, and r0 > 0
+   only with t1 >= 0 (an interval above the centre). */
+static double mass_S(double r0, double t1, double t2) {
+    if (!(t2 > t1)) return 0.0;
+    if (isfinite(t1) && isfinite(t2)) {
+        /* the change of log g over the stretch */
+        double vmax = 0.5 * t2 * (2.0 * r0 + t2), vmin = 0.5 * t1 * (2.0 * r0 + t1);
+        double v;
+        if (r0 > 0.0 || t1 >= 0.0) v = vmax - vmin;
+        else if (t2 <= 0.0) v = vmin - vmax;
+        else v = fmax(vmin, vmax);
+        if (v <= 2.0) {
+            double h = 0.5 * (t2 - t1), m = 0.5 * (t1 + t2), s = 0.0;
+            for (int i = 0; i < gl_n; ++i) {
+                double tau = m + h * gl_x[i];
+                s += gl_w[i] * exp(-0.5 * tau * (2.0 * r0 + tau));
+            }
+            return h * s;
         }
-        return sum;
     }
-    return mills(a) - mills(a + t) * exp(-t * (a + 0.5 * t));
+    if (r0 > 0.0 || t1 >= 0.0) return tail_T(r0, t1) - tail_T(r0, t2);
+    /* r0 = 0 and the stretch starts below the centre: g is even */
+    if (t2 <= 0.0) return tail_T(0.0, -t2) - tail_T(0.0, -t1);
+    return SQRT_2PI - tail_T(0.0, -t1) - tail_T(0.0, t2);
 }
 
-/* Draw t in [0, w] with density prop. to exp(-a t - t^2/2), a >= 0, by inversion at u;
-   uc = 1 - u is passed separately so that the caller can supply it without rounding.
-   For u <= 1/2 it solves E(a,t) = u E(a,w); otherwise it solves the upper tail
-   log T(t) = log(uc E(a,w)) with T(t) = int_t^w p = exp(-t(a+t/2)) E(a+t, w-t),
-   which keeps full relative accuracy near the far end.  Newton steps, kept inside a
-   bracket by bisection. */
-double orc_S(double a, double w, double u, double uc) {
-    double Ew = orc_E(a, w);
-    double tl = 0.0;
-    double th;
-    if (u <= 0.5) {
-        th = (w < 1.0) ? w : 1.0;  /* the median of the a=0 half-normal is 0.674 */
-        double target = u * Ew;
-        double t = 0.5 * (tl + th);
-        if (a > 0.0) {
-            /* start from the exponential-tilt solution */
-            double ts = -log1p(u * expm1(-a * w)) / a;
-            if (ts > tl && ts < th) t = ts;
-        } else if (w < 1.0) {
-            t = u * w;
-        }
-        for (int it = 0; it < 200; ++it) {
-            double f = orc_E(a, t) - target;
-            if (f == 0.0) break;  /* exact root */
-            if (f < 0.0) tl = t; else th = t;
-            double fp = exp(-t * (a + 0.5 * t));
-            double tn = t - f / fp;
-            if (!(tn >= tl && tn <= th)) tn = 0.5 * (tl + th);
-            double dt = fabs(tn - t);
-            t = tn;
-            if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
-        }
-        return t;
-    } else {
-        th = (w < 40.0) ? w : 40.0;
-        double Lstar = log(uc) + log(Ew);
-        double t = 0.5 * (tl + th);
-        if (a > 0.0) {
-            double ts = -log1p(u * expm1(-a * w)) / a;
-            if (ts > tl && ts < th) t = ts;
-        } else if (w < 1.0) {
-            t = u * w;
-        }
-        for (int it = 0; it < 200; ++it) {
-            double tail = orc_E(a + t, w - t);
-            double h = -t * (a + 0.5 * t) + log(tail) - Lstar;  /* decreasing in t */
-            if (h == 0.0) break;  /* exact root */
-            if (h > 0.0) tl = t; else th = t;
-            double tn = t + h * tail;
-            if (!(tn >= tl && tn <= th)) tn = 0.5 * (tl + th);
-            double dt = fabs(tn - t);
-            t = tn;
-            if (dt <= 4e-16 * t || th - tl <= 4e-16 * th) break;
-        }
-        return t;
+/* The offset tau in [ta, tb] of the u-quantile, by bisection (uc = 1 - u exactly). */
+static double bisect_quantile(double r0, double ta, double tb, double u, double uc) {
+    const double tot = mass_S(r0, ta, tb);
+    /* a finite bracket: beyond 40 standard units of the reference nothing is left */
+    double lo = isinf(ta) ? -40.0 : ta;
+    double hi = isinf(tb) ? 40.0 : tb;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;   /* the bracket is two adjacent doubles */
+        double f = (u <= 0.5) ? mass_S(r0, ta, mid) - u * tot : uc * tot - mass_S(r0, mid, tb);
+        if (f < 0.0) lo = mid; else hi = mid;
     }
+    return 0.5 * (lo + hi);
 }
 
-/* Draw delta from N(c/d, 1/d^2) truncated to [lo, hi] (lo <= 0 <= hi, d > 0) at u.
-   Standardised x = d*delta - c lies in [a, b] with a = d*lo - c, b = d*hi - c. */
+/* Draw delta from N(c/d, 1/d^2) restricted to [lo, hi] (lo <= 0 <= hi, d > 0) at u. */
 double orc_tn_draw(double c, double d, double lo, double hi, double u) {
     if (lo == hi) return lo;
-    double a = d * lo - c;
-    double b = d * hi - c;
-    double w = d * (hi - lo);
+    const double uc = 1.0 - u;   /* exact: u is a multiple of 2^-53 in (0, 1) */
+    const double a = d * lo - c, b = d * hi - c;
+    /* the interval's length in standard units, taken from hi - lo rather than b - a, which
+       carries the rounding of both ends */
+    const double w = d * (hi - lo);
     double delta;
-    const double uc = 1.0 - u;   /* exact: u is a multiple of 2^-53 in (0,1) */
-    if (a >= 0.0) {
-        double t = orc_S(a, w, u, uc);
-        delta = lo + t / d;
+    if (!(w > 0.0)) {
+        /* too short for the Gaussian to vary across it at all: flat */
+        delta = lo + u * (hi - lo);
+    } else if (a >= 0.0) {
+        delta = lo + bisect_quantile(a, 0.0, w, u, uc) / d;
     } else if (b <= 0.0) {
-        /* mirror x -> -x: the lower end becomes the far end */
-        double t = orc_S(-b, w, uc, u);
-        delta = hi - t / d;
+        /* reflected: the upper end becomes the reference, and the quantile 1 - u */
+        delta = hi - bisect_quantile(-b, 0.0, w, uc, u) / d;
     } else {
-        /* two one-sided halves [a,0] and [0,b] with masses E(0,-a) and E(0,b) */
-        double pL = orc_E(0.0, -a);
-        double pR = orc_E(0.0, b);
-        double tot = pL + pR;
-        double q = u * tot;
-        if (q < pL) {
-            double t = orc_S(0.0, -a, (pL - q) / pL, q / pL);
-            delta = (c - t) / d;
-        } else {
-            double t = orc_S(0.0, b, (q - pL) / pR, (uc * tot) / pR);
-            delta = (c + t) / d;
-        }
+        delta = (c + bisect_quantile(0.0, a, b, u, uc)) / d;
     }
     if (delta < lo) delta = lo;
     if (delta > hi) delta = hi;
     return delta;
 }
 
+/* the pieces, for the pins */
 double orc_mills(double x) { return mills(x); }
-double orc_Mk(int k, double z) { return Mk(k, z); }
+double orc_mass(double r0, double t1, double t2) { return mass_S(r0, t1, t2); }
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
     philox4x32_10(ctr, key, out);
 }

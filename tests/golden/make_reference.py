@@ -7,7 +7,10 @@ Sec. IV.C) and its standard error over independent chain groups, for a fixed pro
 The config-2 reference starts from the NNLS start of Sec. IV.D, so that both sides average
 over the equilibrated chain rather than over the slow relaxation from a flat start.
 
-    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3]
+    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3] [cfg5]
+
+The config-5 reference (401 correlated data points whitened by their Cholesky factor, 4000
+grid points in 32 blocks, Sec. IV and Sec. IV.C) takes about half an hour on 8 cores.
 """
 import json
 import os
@@ -22,10 +25,16 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import workloads  # noqa: E402
 
+THREADS = int(os.environ.get("ORACLE_THREADS", "0")) or None
+
 PROTOCOLS = {
     "cfg1": dict(problem="config1", chains=64, burnin=200, sweeps=2000, seed=11, groups=32,
                  refresh_every=64),
-    "cfg2": dict(problem="config2", chains=64, burnin=500, sweeps=2000, seed=12, groups=32,
+    # 512 chains: the reference's error bars are then about a third of those of the float32
+    # run it is compared with, so a bias of one reference error bar is visible
+    "cfg2": dict(problem="config2", chains=512, burnin=500, sweeps=2000, seed=12, groups=32,
+                 refresh_every=64, start="nnls"),
+    "cfg5": dict(problem="config5", chains=256, burnin=1000, sweeps=5000, seed=15, groups=32,
                  refresh_every=64, start="nnls"),
 }
 # three uneven datasets of the batched workload (N = 396, 670, 407 in 4, 7, 4 blocks); 256
@@ -45,7 +54,7 @@ def make(name):
     init = oracle.nnls_start(prep) if proto.get("start") == "nnls" else None
     res = oracle.run(prep, chains=proto["chains"], burnin=proto["burnin"], sweeps=proto["sweeps"],
                      seed=proto["seed"], groups=proto["groups"], refresh_every=proto["refresh_every"],
-                     init=init)
+                     init=init, threads=THREADS)
     dt = time.time() - t
     out = os.path.join(HERE, f"{name}_oracle.npz")
     np.savez_compressed(out, mean=res.mean, stderr=res.stderr, post_sd=res.post_sd,

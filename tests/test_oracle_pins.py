@@ -24,37 +24,50 @@ def test_mills_ratio_matches_scipy_erfcx(orc):
         assert abs(orc.mills(x) / ref - 1.0) < 5e-15, x
 
 
-def test_Mk_matches_quadrature(orc):
-    for k in [0, 2, 4, 10, 18]:
-        for z in [0.0, 1e-6, 0.5, 3.0, 20.0, 49.9, 50.1, 300.0]:
-            ref = integrate.quad(lambda v: v ** k * math.exp(-z * v), 0.0, 1.0,
-                                 epsabs=0, epsrel=1e-13, limit=200)[0]
-            assert abs(orc.Mk(k, z) / ref - 1.0) < 1e-12, (k, z)
+@pytest.mark.parametrize("r0,t1,t2", [
+    (0.0, 0.0, 1e-9), (0.0, -0.3, 0.2), (0.0, 0.0, 1.9), (0.0, 0.0, 2.1), (0.0, -2.1, 0.5),
+    (0.0, -5.0, -1.0), (0.0, -np.inf, -3.0), (0.0, -np.inf, 1.0), (0.0, 1.0, np.inf), (0.0, -1.0, np.inf),
+    (2.0, 0.0, 0.2), (2.0, 0.0, 1.0), (2.0, 0.5, 3.0), (7.99, 0.0, np.inf), (8.0, 0.0, 0.1),
+    (50.0, 0.0, 0.03), (50.0, 0.01, np.inf), (3e3, 0.0, 0.01), (1e-3, 0.0, 1e-6),
+    (0.7, 0.0, np.inf), (40.0, 0.0, np.inf)])
+def test_mass_matches_quadrature(orc, r0, t1, t2):
+    """The scaled normal mass of [r0 + t1, r0 + t2] (both branches, the switch between them,
+    infinite ends) against adaptive quadrature of the same integrand."""
+    f = lambda t: math.exp(-0.5 * t * (2.0 * r0 + t))
+    ref = integrate.quad(f, t1, t2, epsabs=0, epsrel=1e-13, limit=400)[0]
+    assert abs(orc.mass(r0, t1, t2) / ref - 1.0) < 5e-14
 
 
-@pytest.mark.parametrize("a,t", [(0, 1e-9), (0, 0.1), (0, 0.25), (0, 0.2500001), (0, 3.0),
-                                 (2.0, 0.2), (2.0, 1.0), (50.0, 0.2), (3e3, 0.01), (1e-3, 1e-6),
-                                 (0.7, np.inf), (40.0, np.inf)])
-def test_E_matches_quadrature(orc, a, t):
-    f = lambda s: math.exp(-a * s - 0.5 * s * s)
-    ref = integrate.quad(f, 0.0, t, epsabs=0, epsrel=1e-13, limit=400)[0]
-    assert abs(orc.E(a, t) / ref - 1.0) < 2e-14
+def test_mass_matches_log_ndtr_in_far_tails(orc):
+    """Far above the centre the mass is Q(r0 + t1) - Q(r0 + t2) over phi(r0); scipy's log_ndtr
+    gives both tails independently."""
+    for r0, t1, t2 in [(10.0, 0.5, 2.0), (30.0, 0.1, 1.0), (37.0, 0.0, np.inf), (200.0, 0.02, 0.5)]:
+        lq1 = special.log_ndtr(-(r0 + t1))
+        lq2 = special.log_ndtr(-(r0 + t2)) if np.isfinite(t2) else -np.inf
+        lphi = stats.norm.logpdf(r0)
+        ref = math.exp(lq1 - lphi) * -math.expm1(lq2 - lq1)
+        # the reference subtracts logarithms of size (r0 + t1)^2 / 2: that is its resolution
+        tol = 2e-14 + 2.0 * np.finfo(float).eps * (r0 + t1) ** 2
+        assert abs(orc.mass(r0, t1, t2) / ref - 1.0) < tol, (r0, t1, t2)
 
 
 def _trunc_cdf(x, c, d, lo, hi):
-    """Distribution function and density of N(c/d, 1/d^2) on [lo, hi], via log_ndtr."""
-    a, b, z = d * lo - c, d * hi - c, d * x - c
-    if a >= 0 or (b > 0 and -a < b):   # work with upper tails
-        la, lb, lz = special.log_ndtr(-a), special.log_ndtr(-b), special.log_ndtr(-z)
-        num = -np.expm1(lz - la)
-        den = -np.expm1(lb - la)
+    """Distribution function F, its complement 1 - F, and the density of N(c/d, 1/d^2)
+    restricted to [lo, hi] at x, in 60-digit arithmetic (mpmath), each tail from the side
+    where it is small."""
+    import mpmath
+    mpmath.mp.dps = 60
+    c, d, x = mpmath.mpf(c), mpmath.mpf(d), mpmath.mpf(x)
+    a = d * mpmath.mpf(lo) - c if np.isfinite(lo) else -mpmath.inf
+    b = d * mpmath.mpf(hi) - c if np.isfinite(hi) else mpmath.inf
+    z = d * x - c
+    if a >= 0:   # above the centre: upper tails
+        qa, qb, qz = mpmath.ncdf(-a), mpmath.ncdf(-b), mpmath.ncdf(-z)
+        den, F, Fc = qa - qb, qa - qz, qz - qb
     else:
-        la, lb, lz = special.log_ndtr(a), special.log_ndtr(b), special.log_ndtr(z)
-        num = -np.expm1(la - lz) * np.exp(lz - lb)
-        den = -np.expm1(la - lb)
-        la = lb
-    dens = d * np.exp(stats.norm.logpdf(z) - la) / den
-    return num / den, dens
+        pa, pb, pz = mpmath.ncdf(a), mpmath.ncdf(b), mpmath.ncdf(z)
+        den, F, Fc = pb - pa, pz - pa, pb - pz
+    return F / den, Fc / den, d * mpmath.npdf(z) / den
 
 
 CASES = [(0.0, 1.0, -1.0, 2.0), (5.0, 2.0, -3.0, 0.5), (-40.0, 1.0, 0.0, np.inf),
@@ -65,36 +78,19 @@ CASES = [(0.0, 1.0, -1.0, 2.0), (5.0, 2.0, -3.0, 0.5), (-40.0, 1.0, 0.0, np.inf)
 
 @pytest.mark.parametrize("c,d,lo,hi", CASES)
 def test_tn_inverse_cdf(orc, c, d, lo, hi):
-    """The draw at u has distribution-function value u (checked with scipy's log_ndtr)."""
+    """The draw at u has distribution-function value u (checked in 60-digit arithmetic)."""
     for k in [1, 3, 1000, 2 ** 30, 2 ** 51, 2 ** 52 - 1000, 2 ** 53 - 3]:
         u = k * 2.0 ** -53
         x = orc.tn_draw(c, d, lo, hi, u)
         assert lo <= x <= hi
-        F, dens = _trunc_cdf(x, c, d, lo, hi)
-        # the error allowed is relative to the smaller tail, plus what rounding x to a
-        # double can move F by (density times a few ulps of x)
-        # the checker itself only resolves z = d x - c to a few ulps of c, d lo and d hi
+        F, Fc, dens = _trunc_cdf(x, c, d, lo, hi)
+        err = float(F) - u if u <= 0.5 else float(Fc) - (1.0 - u)
+        # what rounding x to a double moves F by (density times a few ulps of x), and the
+        # resolution of the standardised ends d lo - c, d hi - c that the draw starts from
         ends = [abs(d * e) for e in (lo, hi) if np.isfinite(e)]
         res = np.spacing(abs(x) + 1e-300) + (np.spacing(abs(c)) + sum(np.spacing(e) for e in ends)) / d
-        tol = 1e-9 * min(u, 1.0 - u) + 8.0 * dens * res
-        assert abs(F - u) <= tol, (u, x, F, tol)
-
-
-@pytest.mark.parametrize("a,w", [(0.0, np.inf), (0.0, 0.01), (3.0, 2.0), (40.0, np.inf),
-                                 (40.0, 1e-3), (1e4, 1.0), (0.5, 1e-12), (7.0, 0.3)])
-def test_S_inverts_E(orc, a, w):
-    """The one-sided draw t solves E(a, t) = u E(a, w) (E itself is pinned by quadrature)."""
-    Ew = orc.E(a, w)
-    for k in [1, 7, 2 ** 20, 2 ** 45, 2 ** 52 - 1, 2 ** 52 + 1, 2 ** 53 - 2 ** 20, 2 ** 53 - 1]:
-        u = k * 2.0 ** -53
-        t = orc.S(a, w, u)
-        assert 0.0 <= t <= w
-        if u <= 0.5:
-            assert abs(orc.E(a, t) / Ew - u) <= 1e-13 * u + 4 * np.spacing(t) / Ew
-        else:
-            tail = math.exp(-t * (a + 0.5 * t)) * orc.E(a + t, w - t) if t < w else 0.0
-            p_t = math.exp(-t * (a + 0.5 * t))
-            assert abs(tail / Ew - (1.0 - u)) <= 1e-12 * (1.0 - u) + 8 * np.spacing(t) * p_t / Ew
+        tol = 1e-13 * min(u, 1.0 - u) + 8.0 * float(dens) * res
+        assert abs(err) <= tol, (u, x, err, tol)
 
 
 def test_tn_narrow_interval_is_tilted_uniform(orc):
@@ -136,6 +132,18 @@ def test_uniforms_open_interval_and_uniform(orc):
     assert stats.chi2.sf(chi2, 49) > 1e-4
     assert abs(np.corrcoef(us[:-1], us[1:])[0, 1]) < 0.05
     assert len(np.unique(us)) == len(us)
+
+
+def test_philox_known_answers(orc):
+    """Philox4x32-10 against the known-answer vectors published with the generator
+    (Salmon et al., SC'11, Random123): zero counter and key, all-ones counter and key, and
+    the counter and key taken from the hexadecimal digits of pi."""
+    cases = [([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+             ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+             ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+              [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1])]
+    for ctr, key, want in cases:
+        assert [int(w) for w in orc.philox(ctr, key)] == want
 
 
 def test_philox_counter_sensitivity(orc):
@@ -215,6 +223,47 @@ def test_sum_rule_only_data_gives_flat_default(orc):
         res = orc.run(prep, chains=16, burnin=200, sweeps=20000, groups=16)
         assert _within(res.mean, res.stderr, EA) < 4.5, (bstart, res.mean, EA)
         assert np.allclose(res.post_sd, math.sqrt(EA2 - EA * EA), rtol=0.03)
+
+
+def _chi2_bounds(R):
+    """Bounds for the sum of R squared z-scores whose error bars come from 32 chain groups:
+    the 0.1% and 99.9% points of chi^2(R), the upper one widened by the Student-t variance
+    31/29 of a 31-degree-of-freedom error bar."""
+    return stats.chi2.ppf(0.001, R), stats.chi2.ppf(0.999, R) * 31.0 / 29.0
+
+
+def test_standard_error_is_calibrated_on_closed_forms(orc):
+    """The error bar (standard deviation of 32 chain-group means over sqrt(32)) is what every
+    parity test divides by.  On two closed forms, 120 seeded replicas each: the one-point grid
+    (a truncated normal) and the sum-rule-only data (E[S]/N by quadrature, Eq. (def)), the
+    sum of squared z-scores must fall inside chi^2(120).  An error bar inflated by sqrt(2)
+    (the sum then sits near 60 against a lower bound of 80) or deflated by it (near 240
+    against 185), let alone one off by sqrt(32), lands outside."""
+    R = 120
+    lo, hi = _chi2_bounds(R)
+    # one point: N(mu, s^2) restricted to A >= 0
+    k = np.array([0.8, 1.1, 0.6, 1.3])
+    s = 1.0 / np.linalg.norm(k)
+    mu = 0.4 * s
+    p1 = _problem(k[:, None], k * mu, 1.0, [0, 1])
+    ref1 = mu + s * math.exp(stats.norm.logpdf(mu / s) - special.log_ndtr(mu / s))
+    prep1 = orc.prepare(p1)
+    # sum rule on 6 points, one block
+    N, sig = 6, 0.3
+    ws = lambda S, q: S ** (N - 1 + q) * math.exp(-0.5 * ((S - 1.0) / sig) ** 2)
+    ref2 = integrate.quad(lambda S: ws(S, 1), 0, 10)[0] / integrate.quad(lambda S: ws(S, 0), 0, 10)[0] / N
+    prep2 = orc.prepare(_problem(np.ones((1, N)), [1.0], sig, [0, N]))
+    z1, z2 = [], []
+    for r in range(R):
+        a = orc.run(prep1, chains=64, burnin=20, sweeps=200, groups=32, seed=7000 + r, threads=4)
+        z1.append((a.mean[0] - ref1) / a.stderr[0])
+        b = orc.run(prep2, chains=64, burnin=300, sweeps=600, groups=32, seed=9000 + r, threads=4)
+        z2.append((b.mean[0] - ref2) / b.stderr[0])
+    for z in (np.array(z1), np.array(z2)):
+        q = float(np.sum(z ** 2))
+        assert lo < q < hi, (q, lo, hi)
+        # and no bias: the mean z is within 4 of its own standard error
+        assert abs(z.mean()) < 4.0 * z.std(ddof=1) / math.sqrt(R)
 
 
 def test_sum_rule_only_data_with_a_hierarchy(orc):
