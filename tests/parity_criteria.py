@@ -23,7 +23,9 @@ def zscore_ok(m1, s1, m2, s2, frac=0.01, zmax=4.5, n3_min=2, mean_z2=None):
     return ok, (float(z.max()), n3, len(z), float(np.mean(z ** 2)))
 
 
-# The batched workload's spectra: bounds above the spread of the oracle-against-oracle runs of
-# tests/golden/calibrate_correlated.py (its output, correlated_calibration.json, is checked
-# against these bounds by a CPU test).
-CORRELATED = dict(frac=0.03, zmax=5.0, n3_min=3, mean_z2=2.0)
+# Spectra of many strongly correlated points (the batched workload, the conductivity test case
+# on a hierarchy): bounds above the spread of the oracle-against-oracle runs of
+# tests/golden/calibrate_correlated.py (36 runs: max z up to 5.1, up to 2.5 % of the points
+# beyond 3, mean z^2 up to 1.8; its output, correlated_calibration.json, is checked against
+# these bounds by a CPU test).
+CORRELATED = dict(frac=0.035, zmax=5.5, n3_min=3, mean_z2=2.2)

@@ -806,3 +806,17 @@ def test_data_noise_is_standard_normal(orc):
     assert abs(xi.var() - 1.0) < 4.5 * math.sqrt(2.0 / 20000)
     assert stats.kstest(xi, "norm").pvalue > 1e-4
     assert not np.array_equal(xi[:100], orc.data_noise(77, 3, 100))
+
+
+def test_correlated_bounds_cover_the_oracle_against_oracle_spread():
+    """The pass bounds for correlated spectra sit above what independent oracle runs give
+    against the stored references (tests/golden/calibrate_correlated.py, oracle only)."""
+    import json
+    import os
+    from parity_criteria import CORRELATED
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "correlated_calibration.json")
+    cal = json.load(open(here))
+    assert cal["replicas"] >= 12 and len(cal["datasets"]) == 3
+    assert cal["max_of_max_z"] < CORRELATED["zmax"]
+    assert cal["max_frac3"] < CORRELATED["frac"]
+    assert cal["max_mean_z2"] < CORRELATED["mean_z2"]
