@@ -74,17 +74,20 @@ struct asm_plan {
     bool pending[2] = {false, false};
     int snap_par = 0;
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
-    int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0;   // float32 sampler LDS
+    int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_ce = 0;   // float32 sampler LDS
+    int32_t kce = 4;
     int pf = 0, prefetch = 0;   // prefetch words per thread of the instance; whether used
     int u_lds = 0;
     int roles = 1;           // 2: the two-role sampler (sample32p.h)
-    int64_t p_off_vwd = 0, p_off_d = 0, p_off_u = 0, p_off_vwz = 0, p_off_und = 0, p_off_unz = 0, p_off_h = 0;
+    int64_t p_off_vwd = 0, p_off_d = 0, p_off_u = 0, p_off_vwz = 0, p_off_und = 0, p_off_unz = 0, p_off_h = 0,
+            p_off_ce = 0;
     int64_t p_du_word = 0;
     int32_t p_wd = 0, p_wu = 0, p_kd = 0, p_zs = 0;
     bool unbounded = false;  // a zero mode with V of one sign (found when packing)
     int ept = 0, rpt = 0;    // compiled float32 instance: components and residual entries per lane
     int fp32 = 1;
     int lanes = 16, chains_per_wg = 16, grid32 = 0;
+    int units_per_tile = 1;  // float32: wavefronts (accumulator slots) per tile
     size_t lds32 = 0, lds64 = 0;
     bool any_cov = false;
     bool any_levels = false;   // a problem with a hierarchy of partitions
@@ -238,12 +241,15 @@ int check_flags(asm_plan *pl, int *hflags) {
     return ASM_OK;
 }
 
-// tiles of the float32 sampler: consecutive chains within one error-bar group
+// tiles of the float32 sampler: consecutive chains within one error-bar group; each
+// wavefront of a tile (64 / lanes chains) accumulates into its own slot
 void build_tiles(asm_plan *pl) {
     pl->tiles.clear();
     pl->slot_group.clear();
     pl->slot_count.clear();
     const int cpw = pl->chains_per_wg;
+    const int gw = 64 / pl->lanes;                 // chains per wavefront
+    pl->units_per_tile = (cpw + gw - 1) / gw;      // wavefronts per tile
     for (int64_t p = 0; p < pl->P; ++p) {
         ProbDesc &pd = pl->probs[p];
         const int64_t C = pd.C, G = pd.groups;
@@ -260,11 +266,14 @@ void build_tiles(asm_plan *pl) {
                 t.nchains = (int32_t)std::min<int64_t>(cpw, c1 - c);
                 t.slot = (int32_t)(nunits * pd.batches);
                 pl->tiles.push_back(t);
-                for (int64_t bt = 0; bt < pd.batches; ++bt) {
-                    pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : g));
-                    pl->slot_count.push_back((double)t.nchains);
+                for (int w = 0; w < pl->units_per_tile; ++w) {
+                    const int64_t nc = std::max<int64_t>(0, std::min<int64_t>(gw, t.nchains - (int64_t)w * gw));
+                    for (int64_t bt = 0; bt < pd.batches; ++bt) {
+                        pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : g));
+                        pl->slot_count.push_back((double)nc);
+                    }
+                    ++nunits;
                 }
-                ++nunits;
             }
         }
         pd.nslot = nunits * pd.batches;
@@ -336,6 +345,9 @@ SampleArgs make_args(asm_plan *pl) {
     a.lds_off_d = pl->lds_off_d;
     a.lds_off_u = pl->lds_off_u;
     a.lds_off_unif = pl->lds_off_unif;
+    a.lds_off_ce = pl->lds_off_ce;
+    a.kce = pl->kce;
+    a.p_off_ce = pl->p_off_ce;
     a.u_lds = pl->u_lds;
     a.prefetch = pl->prefetch;
     a.p_off_vwd = pl->p_off_vwd;
@@ -380,13 +392,12 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     SampleArgs a = make_args(pl);
     if (snap) {
         a.snapA = pl->snapA[par];
-        a.snapR = pl->opt.want_vjp ? pl->snapR[par] : nullptr;
+        a.snapR = pl->snapR[par];
         a.snap_rows = pl->snap_rows;
         a.snap_first = pl->snap_first + par;
-        a.accumulate = 0;   // the sums come from the snapshots
     }
     a.nsw = nsw;
-    if (!snap) a.accumulate = accumulate;
+    a.accumulate = accumulate;
     a.burnin = burnin_abs;
     a.sweeps = pl->opt.sweeps;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -431,18 +442,14 @@ int snap_acquire(asm_plan *pl, int par) {
     return ASM_OK;
 }
 
-// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the sums of A
-// and A^2 (and the cross moments with want_vjp) on the second stream, after the main stream's
-// work so far.
+// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
+// moments on the second stream, after the main stream's work so far.
 int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
+    (void)burnin_abs;
     HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
     HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    HIPCHK(launch_acc_snap(pl->d_probs, pl->d_tiles, (int64_t)pl->tiles.size(), pl->max_n, nsnap,
-                           pl->snapA[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps, pl->accA,
-                           pl->accA2, pl->xstream));
-    if (pl->opt.want_vjp)
-        HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
-                                 pl->snapR[par], pl->cross, pl->xstream));
+    HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
+                             pl->snapR[par], pl->cross, pl->xstream));
     HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
     pl->pending[par] = true;
     return ASM_OK;
@@ -507,7 +514,7 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     const int64_t R = pl->opt.refresh_every;
     const int64_t end = pl->sweep + total;
     const bool vjp = accumulate && pl->opt.want_vjp;
-    const bool snapping = accumulate && pl->fp32;   // float32: sums from snapshots
+    const bool snapping = vjp && pl->fp32;   // float32: the cross moments come from snapshots
     if (snapping && !pl->snapA[0]) return fail(ASM_ESTATE, "plan has no snapshot buffers");
     while (pl->sweep < end) {
         const int64_t s = pl->sweep;
@@ -531,7 +538,7 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         int64_t seg = end - s;
         if (pl->fp32 && R > 0) seg = std::min(seg, R - s % R);   // stop where a refresh is due
         if (!pl->fp32 && seg > 256) seg = 256;
-        if ((vjp || snapping) && s + seg > burnin_abs && s < burnin_abs) seg = burnin_abs - s;   // burn-in apart
+        if (vjp && s + seg > burnin_abs && s < burnin_abs) seg = burnin_abs - s;   // burn-in apart
         // float32: as many sweeps as the snapshot rows hold; float64 with want_vjp: one sweep,
         // whose state the cross-moment kernel reads directly
         if (snapping && s >= burnin_abs) seg = std::min(seg, pl->snap_rows);
@@ -900,21 +907,24 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         t.off_V = ct.off_vp;
     }
     pl->total_m = offm;
-    if (pl->fp32 && !t_probe_plan) {
-        // two snapshot buffers for every accumulated sweep of a launch (at most refresh_every
-        // or 64 sweeps, and at most 16 GiB together), rows padded to whole 16-byte words; r
-        // rows only with want_vjp
+    if (pl->fp32 && o->want_vjp && !t_probe_plan) {
+        // the cross moments of the VJP come from per-sweep snapshots of A and r: two buffers
+        // for every accumulated sweep of a launch (at most refresh_every or 64 sweeps, and at
+        // most half of the free device memory together), rows padded to whole 16-byte words
         int64_t per_row = 0;
         for (auto &pd : pl->probs)
-            per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (o->want_vjp ? (pd.M + 3) / 4 * 4 : 0)) * (int64_t)sizeof(float);
-        const int64_t cap = (int64_t)16 << 30;
+            per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
+        (void)hipGetLastError();
+        const int64_t cap = (int64_t)(free_b / 2);
         const int64_t want_rows = o->refresh_every > 0 ? o->refresh_every : 64;
         pl->snap_rows = std::max<int64_t>(1, std::min<int64_t>(want_rows, cap / std::max<int64_t>(per_row, 1)));
         for (auto &pd : pl->probs) {
             pd.off_sa = pl->snap_words_a;
             pd.off_sr = pl->snap_words_r;
             pl->snap_words_a += pl->snap_rows * pd.C * ((pd.N + 3) / 4 * 4);
-            if (o->want_vjp) pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
+            pl->snap_words_r += pl->snap_rows * pd.C * ((pd.M + 3) / 4 * 4);
             pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(pd.M, pd.N));
         }
     }
@@ -978,10 +988,10 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         STEP(dalloc(pl, &pl->A64, offA));
         STEP(dalloc(pl, &pl->r64, offr));
     }
-    if (pl->fp32 && !t_probe_plan) {
+    if (pl->fp32 && o->want_vjp && !t_probe_plan) {
         for (int j = 0; j < 2; ++j) {
             STEP(dalloc(pl, &pl->snapA[j], pl->snap_words_a));
-            if (o->want_vjp) STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
+            STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
             HSTEP(hipEventCreateWithFlags(&pl->ev_ready[j], hipEventDisableTiming));
             HSTEP(hipEventCreateWithFlags(&pl->ev_done[j], hipEventDisableTiming));
         }
@@ -1165,6 +1175,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         for (auto &pd : pl->probs) max_n = std::max(max_n, pd.N);
         pl->max_kb = max_kb;
         pl->max_n = max_n;
+        pl->kce = (int32_t)std::max<int64_t>(4, (max_kb + 3) / 4 * 4);
         const size_t vw_bytes = (size_t)(pl->max_nb + 2) * row * sizeof(float2);
         const size_t d_bytes = (size_t)(max_kb + 3) / 4 * 16;
         const size_t u_bytes = (size_t)max_kb * mp * sizeof(float);
@@ -1177,6 +1188,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             off = (off + 15) / 16 * 16;
             pl->lds_off_unif = (int64_t)off;
             off += (size_t)cpw * row * sizeof(float) * (pl->any_prior ? 2 : 1);   // prior: acceptance rows
+            pl->lds_off_ce = (int64_t)off;
+            off += (size_t)cpw * 2 * pl->kce * sizeof(float);
             return off;
         };
         // chains per workgroup: enough workgroups for every CU, at most 512 threads (256 for
@@ -1212,14 +1225,17 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         {
             int pe = 0, pr = 0, pfr = 0, pfu = 0, pfz = 0;
             // (in automatic mode only with enough chains for a 16-chain workgroup per CU)
-            bool ok = o->roles != 1 && L == 16 && pl->u_lds &&
+            bool ok = o->roles != 1 && L == 16 &&
                       (o->roles == 2 || pl->total_chains >= 16LL * max_cu) &&
-                      sample32p_pick(pl->max_nb, pl->max_m, &pe, &pr, &pfr, &pfu, &pfz) == 0 && pe == ept && pr == rpt;
-            for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1 && !pd.has_prior;
+                      sample32p_pick(pl->max_nb, pl->max_m, pl->u_lds, &pe, &pr, &pfr, &pfu, &pfz) == 0 &&
+                      pe == ept && pr == rpt;
+            // one partition of two blocks or more, no prior, no constraint (the two roles run
+            // every mode of a block, and the zero role's rows are those of an unconstrained block)
+            for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1 && !pd.has_prior && !pd.has_con;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
             // zero modes the data role runs per block, balancing the two roles: a data move
-            // costs about kDataOverZero zero moves
-            constexpr double kDataOverZero = 2.6;
+            // costs about kDataOverZero zero moves (more where the residual is longer)
+            const double kDataOverZero = pl->u_lds ? 2.6 : 3.0;
             double zsum = 0.0;
             for (auto &bd : pl->blocks) zsum += 0.5 * ((double)(bd.nb - bd.kb) - kDataOverZero * (double)bd.kb);
             int64_t zs = (int64_t)std::lround(zsum / std::max<size_t>(1, pl->blocks.size()));
@@ -1231,7 +1247,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 ke_max = std::max(ke_max, ke);
                 zrows = std::max(zrows, bd.nb + 2 - ke);
             }
-            const int64_t wd = (ke_max + 2) * rw, wu = (pl->chunk.d_len + max_kb * mp) / 4;
+            const int64_t wd = (ke_max + 2) * rw, wu = (pl->chunk.d_len + (pl->u_lds ? max_kb * mp : 0)) / 4;
             ok = ok && wd <= 256LL * pfr && wu <= 256LL * pfu && zrows * rw <= 256LL * pfz;
             size_t off = 0;
             auto take = [&](size_t bytes) {
@@ -1246,7 +1262,8 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             pl->p_kd = (int32_t)((ke_max + 3) / 4 * 4);
             pl->p_off_und = take((size_t)16 * pl->p_kd * sizeof(float));
             pl->p_off_unz = take((size_t)16 * row * sizeof(float));
-            pl->p_off_h = take((size_t)2 * 16 * row * sizeof(float));
+            pl->p_off_h = take((size_t)16 * row * sizeof(float));
+            pl->p_off_ce = take((size_t)16 * 2 * pl->kce * sizeof(float));
             ok = ok && off <= kLdsBudget;
             if (ok) {
                 pl->roles = 2;
@@ -1257,8 +1274,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 pl->p_du_word = pl->chunk.rows * rw;
                 pl->p_zs = (int32_t)zs;
             } else if (o->roles == 2) {
-                rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, the (7, 13) instance, two blocks or "
-                                      "more per problem, no hierarchy or prior, and the staging areas in LDS");
+                rc = fail(ASM_EINVAL, "two roles need 16 lanes per chain, a two-role instance for the sizes, two "
+                                      "blocks or more per problem, no hierarchy, prior or constraint, and the "
+                                      "staging areas in LDS");
                 return rc;
             }
         }

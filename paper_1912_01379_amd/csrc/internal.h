@@ -59,7 +59,8 @@ struct TileDesc {             // float32 work item: consecutive chains of one pr
     int32_t problem;
     int32_t chain0;
     int32_t nchains;
-    int32_t slot;             // accumulator slot of the tile (batches consecutive slots)
+    int32_t slot;             // first accumulator slot of the tile: one per wavefront of its
+                              // chains (times the batches of sweeps for batch means)
 };
 
 // ------------------------------------------------------------------------------------
@@ -95,21 +96,25 @@ struct SampleArgs {
     int64_t sweeps;           // accumulated sweeps (for batch means)
     int64_t refresh_every;    // float64 sampler refreshes inside the kernel
     uint64_t seed;
-    int32_t accumulate;       // 1: accumulate sweeps >= burnin
+    int32_t accumulate;       // 1: accumulate the sweeps in [burnin, burnin + sweeps) into the
+                              //    slots (float32: each block visit adds its final components)
     int32_t pad;
     int64_t lds_off_d;        // byte offsets in the float32 sampler's LDS: singular values,
     int64_t lds_off_u;        //   U rows,
-    int64_t lds_off_unif;     //   per-chain uniform rows
+    int64_t lds_off_unif;     //   per-chain uniform rows,
+    int64_t lds_off_ce;       //   per-chain rows of the data modes' centres and steps (2 kce)
     int32_t u_lds;            // 1: U rows are staged in LDS (else read from global memory)
     int32_t prefetch;         // 1: every block's factor stream fits the instance's prefetch
-    float *snapA;             // nullable: per-sweep snapshots of A (float32 sampler: the sums of
-    float *snapR;             //   A and A^2 are reduced from them) and of r (cross moments) of
-    int64_t snap_rows;        //   the accumulated sweeps of the launch, at the problems' off_sa /
-    int64_t *snap_first;      //   off_sr; row = sweep - first sweep, which goes to *snap_first
+    float *snapA;             // nullable (float32 plans with want_vjp): per-sweep snapshots of A
+    float *snapR;             //   and of r, the inputs of the cross moments, for the accumulated
+    int64_t snap_rows;        //   sweeps of the launch, at the problems' off_sa / off_sr; row =
+    int64_t *snap_first;      //   sweep - first sweep, which goes to *snap_first
     // two-role float32 sampler (sample32p.h): LDS byte offsets of its areas, the chunk word
     // where the singular values (then the U rows) start, the words of the data rows part and
     // of the d/U part, the data-role uniform row length
-    int64_t p_off_vwd, p_off_d, p_off_u, p_off_vwz, p_off_und, p_off_unz, p_off_h;
+    int64_t p_off_vwd, p_off_d, p_off_u, p_off_vwz, p_off_und, p_off_unz, p_off_h, p_off_ce;
+    int32_t kce;              // floats per half of a chain's centre/step row (largest k, rounded to 4)
+    int32_t pad2;
     int64_t p_du_word;
     int32_t p_wd, p_wu, p_kd, p_zs;   // ... and the zero modes the data role runs per block
     const int32_t *lvl;       // level table: (first block relative to the problem's, count)
@@ -213,7 +218,7 @@ hipError_t allow_lds_sample32_l16(int bytes);
 hipError_t allow_lds_sample32_l32(int bytes);
 // sample32p_l16.hip: the two-role instance (16 lanes per chain, 512 threads)
 hipError_t launch_sample32p(const SampleArgs &a, int ept, int rpt, int grid, size_t lds, hipStream_t s);
-int sample32p_pick(int64_t max_nb, int64_t max_m, int *ept, int *rpt, int *pfr, int *pfu, int *pfz);
+int sample32p_pick(int64_t max_nb, int64_t max_m, int u_lds, int *ept, int *rpt, int *pfr, int *pfu, int *pfz);
 hipError_t allow_lds_sample32p(int bytes);
 hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s);
 hipError_t launch_reset_queue(int *queue, hipStream_t s);
@@ -237,9 +242,6 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
                              const float *snapA, const float *snapR, double *cross, hipStream_t s);
 __host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N);
-hipError_t launch_acc_snap(const ProbDesc *probs_dev, const TileDesc *tiles_dev, int64_t ntiles, int64_t max_n,
-                           int64_t nsnap, const float *snapA, const int64_t *snap_first, int64_t burnin,
-                           int64_t sweeps, double *accA, double *accA2, hipStream_t s);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,

@@ -311,66 +311,6 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
     return hipGetLastError();
 }
 
-// Sums of A and A^2 over the accumulated sweeps (Eq. (MCint)) from the float32 sampler's
-// snapshots: one thread per (tile, n) adds the tile's chains over the launch's snapshot rows
-// in float64 into the tile's slot (a slot per batch of sweeps when the problem uses batch
-// means), so every slot entry has one writer.  Reads are coalesced along n.
-__global__ __launch_bounds__(256) void k_acc_snap(const ProbDesc *probs, const TileDesc *tiles, int64_t nsnap,
-                                                  const float *snapA, const int64_t *snap_first,
-                                                  int64_t burnin, int64_t sweeps, double *accA,
-                                                  double *accA2) {
-    const TileDesc td = tiles[blockIdx.x];
-    const ProbDesc pd = probs[td.problem];
-    const int64_t N = pd.N;
-    const int64_t n = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const int64_t NR = (N + 3) / 4 * 4;
-    const int64_t s0 = *snap_first;
-    const float *base = snapA + pd.off_sa + (int64_t)td.chain0 * NR + n;
-    const int nc = td.nchains;
-    double x1 = 0.0, x2 = 0.0, y1 = 0.0, y2 = 0.0;   // two partial sums: shorter add chains
-    int64_t slot = -1;
-    for (int64_t j = 0; j < nsnap; ++j) {
-        const int64_t sl = td.slot + (pd.batches > 1 ? (s0 + j - burnin) * pd.batches / sweeps : 0);
-        if (sl != slot) {
-            if (slot >= 0) {
-                accA[pd.off_slot + slot * N + n] += x1 + y1;
-                accA2[pd.off_slot + slot * N + n] += x2 + y2;
-            }
-            slot = sl;
-            x1 = x2 = y1 = y2 = 0.0;
-        }
-        const float *row = base + j * pd.C * NR;
-        int c = 0;
-        for (; c + 4 <= nc; c += 4) {
-            const double v0 = row[(int64_t)c * NR], v1 = row[(int64_t)(c + 1) * NR];
-            const double v2 = row[(int64_t)(c + 2) * NR], v3 = row[(int64_t)(c + 3) * NR];
-            x1 += v0 + v2;
-            y1 += v1 + v3;
-            x2 = fma(v0, v0, fma(v2, v2, x2));
-            y2 = fma(v1, v1, fma(v3, v3, y2));
-        }
-        for (; c < nc; ++c) {
-            const double v = row[(int64_t)c * NR];
-            x1 += v;
-            x2 = fma(v, v, x2);
-        }
-    }
-    if (slot >= 0) {
-        accA[pd.off_slot + slot * N + n] += x1 + y1;
-        accA2[pd.off_slot + slot * N + n] += x2 + y2;
-    }
-}
-
-hipError_t launch_acc_snap(const ProbDesc *probs_dev, const TileDesc *tiles_dev, int64_t ntiles, int64_t max_n,
-                           int64_t nsnap, const float *snapA, const int64_t *snap_first, int64_t burnin,
-                           int64_t sweeps, double *accA, double *accA2, hipStream_t s) {
-    if (ntiles <= 0 || nsnap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_acc_snap, dim3((unsigned)ntiles, (unsigned)((max_n + 255) / 256)), dim3(256), 0, s,
-                       probs_dev, tiles_dev, nsnap, snapA, snap_first, burnin, sweeps, accA, accA2);
-    return hipGetLastError();
-}
-
 // One thread per (problem, n): group sums in a fixed order, then mean, standard error over
 // the groups and posterior standard deviation.
 __global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_prefix,

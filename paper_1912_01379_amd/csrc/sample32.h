@@ -146,27 +146,14 @@ __device__ __forceinline__ void load_row(float2 (&vw)[EPT], const float2 *row, i
     for (int t = 0; t < EPT; ++t) vw[t] = row[lane + L * t];
 }
 
-// One data-mode move: interval, c = U_i . r, the truncated-normal step, the updates of A and r.
-template <int L, int EPT, int RPT, bool P = false>
-__device__ __forceinline__ void data_move(const float2 (&vw)[EPT], const float (&Ui)[RPT], float u, float dd,
-                                          float (&Ar)[EPT], float (&rr)[RPT], PriorRegs<EPT> *pr = nullptr,
-                                          float ua = 0.0f, int lane = 0) {
-    float lo, hi;
-    interval32<L, EPT, false>(vw, Ar, lo, hi);
-    float c0 = 0.0f, c1 = 0.0f;   // two partial sums for a shorter dependence chain
-#pragma unroll
-    for (int t = 0; t < RPT; t += 2) c0 = fmaf(Ui[t], rr[t], c0);
-#pragma unroll
-    for (int t = 1; t < RPT; t += 2) c1 = fmaf(Ui[t], rr[t], c1);
-    const float cdot = seg_sum<L>(c0 + c1);
-    float delta = tn_draw32(cdot, dd, lo, hi, u);
-    if constexpr (P) delta = prior_accept<L, EPT>(vw, Ar, *pr, delta, ua, lane);
-    const float e = delta * dd;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ui[t], rr[t]);
-#pragma unroll
-    for (int t = 0; t < EPT; ++t) Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
-}
+// Data modes by the projection identity (Sec. IV.B-C): a data move of mode j changes r by a
+// multiple of U_j, and U_i . U_j = 0 for i != j, so the Gaussian centre c_i = U_i . r of every
+// other data mode of the block is the same before and after it.  The block's centres are
+// therefore formed once as it is entered (c = U_b^T r), and r takes the block's steps
+// e_i = delta_i d_i in one update as it is left (r -= U_b e).  Between the two passes a move is
+// the interval, the truncated-normal draw and the update of A: the residual leaves the chain of
+// dependent instructions of the moves.  sc is the chain's LDS row: c_0..c_{kb-1}, then the steps
+// e_0..e_{kb-1} at sc + KCE.
 
 template <int L, int RPT>
 __device__ __forceinline__ void load_u(float (&Ui)[RPT], const float *U, int row, int lane) {
@@ -175,39 +162,92 @@ __device__ __forceinline__ void load_u(float (&Ui)[RPT], const float *U, int row
     for (int t = 0; t < RPT; ++t) Ui[t] = U[row * MP + lane + L * t];
 }
 
-// The data-mode moves of one block (d_i > 0, modes 0..kb-1), two per iteration with the next
-// (V, w) and U rows loaded one move ahead.  On entry vw holds row 0; on return row kb.
-template <int L, int EPT, int RPT, bool ULDS, bool P = false>
+// c_i = U_i . r for i < kb, written to sc[i] by the chain's first lane; the next row is loaded
+// while the current one is reduced
+template <int L, int RPT>
+__device__ __forceinline__ void centres(int kb, const float *U, const float (&rr)[RPT], int lane, float *sc) {
+    if (kb <= 0) return;
+    float Ua[RPT];
+    load_u<L, RPT>(Ua, U, 0, lane);
+    for (int i = 0; i < kb; ++i) {
+        float Ub[RPT];
+        load_u<L, RPT>(Ub, U, i + 1 < kb ? i + 1 : i, lane);
+        float c0 = 0.0f, c1 = 0.0f;   // two partial sums for a shorter dependence chain
+#pragma unroll
+        for (int t = 0; t < RPT; t += 2) c0 = fmaf(Ua[t], rr[t], c0);
+#pragma unroll
+        for (int t = 1; t < RPT; t += 2) c1 = fmaf(Ua[t], rr[t], c1);
+        const float c = seg_sum<L>(c0 + c1);
+        if (lane == 0) sc[i] = c;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) Ua[t] = Ub[t];
+    }
+}
+
+// r -= sum_i e_i U_i over the block's data modes (the steps from sc)
+template <int L, int RPT>
+__device__ __forceinline__ void residual_update(int kb, const float *U, const float *se, int lane, float (&rr)[RPT]) {
+    if (kb <= 0) return;
+    float Ua[RPT];
+    load_u<L, RPT>(Ua, U, 0, lane);
+    for (int i = 0; i < kb; ++i) {
+        float Ub[RPT];
+        load_u<L, RPT>(Ub, U, i + 1 < kb ? i + 1 : i, lane);
+        const float e = se[i];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) rr[t] = fmaf(-e, Ua[t], rr[t]);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) Ua[t] = Ub[t];
+    }
+}
+
+// One data-mode move: interval, the truncated-normal step about the centre c, the update of A;
+// the step e = delta d goes to se (by the chain's first lane) for the residual update.
+template <int L, int EPT, bool P = false>
+__device__ __forceinline__ void data_move(const float2 (&vw)[EPT], float c, float u, float dd, float (&Ar)[EPT],
+                                          float *se, int lane, PriorRegs<EPT> *pr = nullptr, float ua = 0.0f) {
+    float lo, hi;
+    interval32<L, EPT, false>(vw, Ar, lo, hi);
+    float delta = tn_draw32(c, dd, lo, hi, u);
+    if constexpr (P) delta = prior_accept<L, EPT>(vw, Ar, *pr, delta, ua, lane);
+    if (lane == 0) *se = delta * dd;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) Ar[t] = fmaf(delta, vw[t].x, Ar[t]);
+}
+
+// The data-mode moves of one block (d_i > 0, modes 0..kb-1): the centres, the moves two per
+// iteration with the next (V, w) row loaded one move ahead, the residual update.  On entry vw
+// holds row 0; on return row kb.  U is the block's U rows (LDS or global memory).
+template <int L, int EPT, int RPT, bool P = false>
 __device__ __forceinline__ void data_moves(int kb, const float2 *sVW, const float *sD, const float *U,
-                                           const float *urow, int lane, float2 (&vw)[EPT], float (&Ar)[EPT],
-                                           float (&rr)[RPT], PriorRegs<EPT> *pr = nullptr,
+                                           const float *urow, float *sc, int kce, int lane, float2 (&vw)[EPT],
+                                           float (&Ar)[EPT], float (&rr)[RPT], PriorRegs<EPT> *pr = nullptr,
                                            const float *urowA = nullptr) {
     constexpr int ROW = EPT * L;
     if (kb <= 0) return;
-    float Ua[RPT], Ub[RPT];
-    load_u<L, RPT>(Ua, U, 0, lane);
+    centres<L, RPT>(kb, U, rr, lane, sc);
+    float *se = sc + kce;
     int i = 0;
     for (; i + 2 <= kb; i += 2) {
         float2 vb[EPT];
         load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
-        load_u<L, RPT>(Ub, U, i + 1, lane);
-        const float u0 = urow[i], u1 = urow[i + 1], d0 = sD[i], d1 = sD[i + 1];
+        const float u0 = urow[i], u1 = urow[i + 1], d0 = sD[i], d1 = sD[i + 1], c0 = sc[i], c1 = sc[i + 1];
         float a0 = 0.0f, a1 = 0.0f;
         if constexpr (P) {
             a0 = urowA[i];
             a1 = urowA[i + 1];
         }
-        data_move<L, EPT, RPT, P>(vw, Ua, u0, d0, Ar, rr, pr, a0, lane);
+        data_move<L, EPT, P>(vw, c0, u0, d0, Ar, se + i, lane, pr, a0);
         load_row<EPT>(vw, sVW + (i + 2) * ROW, lane, L);
-        load_u<L, RPT>(Ua, U, i + 2 < kb ? i + 2 : i + 1, lane);
-        data_move<L, EPT, RPT, P>(vb, Ub, u1, d1, Ar, rr, pr, a1, lane);
+        data_move<L, EPT, P>(vb, c1, u1, d1, Ar, se + i + 1, lane, pr, a1);
     }
     if (i < kb) {
         float a0 = 0.0f;
         if constexpr (P) a0 = urowA[i];
-        data_move<L, EPT, RPT, P>(vw, Ua, urow[i], sD[i], Ar, rr, pr, a0, lane);
+        data_move<L, EPT, P>(vw, sc[i], urow[i], sD[i], Ar, se + i, lane, pr, a0);
         load_row<EPT>(vw, sVW + (i + 1) * ROW, lane, L);
     }
+    residual_update<L, RPT>(kb, U, se, lane, rr);
 }
 
 // The zero modes of one block (modes kb..nm-1) with the gamma-prior test, three per iteration,
@@ -232,6 +272,54 @@ __device__ __forceinline__ void zero_moves(int kb, int nm, const float2 *sVW, co
     }
     if (i < nm) zero_move<L, EPT, P>(vw, Ar, urow[i], pr, ua(i), lane);
     if (i + 1 < nm) zero_move<L, EPT, P>(vb, Ar, urow[i + 1], pr, ua(i + 1), lane);
+}
+
+// The sums of A and A^2 over the measured sweeps (Eq. (MCint)), kept in float64.  A block's
+// components at the end of its visit in sweep s are the chain's state after sweep s (the
+// partition's blocks are disjoint, and so are one level's), so each visit adds its components
+// to the sums of its sweep.  The chains of one wavefront are summed by a butterfly
+// over the lanes that hold the same component (float64, the squares exact), and the groups of
+// L lanes then split the read-modify-writes of the wavefront's accumulator slot, which no
+// other wavefront touches: no atomics, and a fixed order of additions.
+template <int L, int EPT>
+__device__ __forceinline__ void acc_block(double *accA, double *accA2, int64_t n0, int nb, int wlane, bool active,
+                                          const float (&Ar)[EPT]) {
+    constexpr int GW = 64 / L;   // chains per wavefront
+    double s1[EPT], s2[EPT];
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        // the empty chain slots of a partial tile carry no chain: they add nothing
+        const double x = active ? (double)Ar[t] : 0.0;
+        s1[t] = x;
+        s2[t] = x * x;
+    }
+    constexpr int STEPS = (L == 64) ? 0 : (L == 32) ? 1 : (L == 16) ? 2 : (L == 8) ? 3 : (L == 4) ? 4 : 5;
+#pragma unroll
+    for (int k = 0; k < STEPS; ++k) {
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            s1[t] += __shfl_xor(s1[t], L << k);
+            s2[t] += __shfl_xor(s2[t], L << k);
+        }
+    }
+    const int lane = wlane % L, grp = wlane / L;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const int q = lane + L * t;
+        if (t % GW == grp && q < nb) {
+            accA[n0 + q] += s1[t];
+            accA2[n0 + q] += s2[t];
+        }
+    }
+}
+
+// The accumulator slot of a wavefront for sweep s, or -1 when s is not measured: one slot per
+// (tile, wavefront), or per (tile, wavefront, batch of sweeps) for batch means.
+__device__ __forceinline__ int64_t acc_slot(const SampleArgs &a, const ProbDesc &pd, const TileDesc &td,
+                                            int wave, int64_t s) {
+    if (!a.accumulate || s < a.burnin || s >= a.burnin + a.sweeps) return -1;
+    const int64_t bt = pd.batches > 1 ? (s - a.burnin) * pd.batches / a.sweeps : 0;
+    return td.slot + (int64_t)wave * pd.batches + bt;
 }
 
 // Copy a block's factor chunk (the image of the staging area) to LDS with all threads,
@@ -312,6 +400,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     float *sD = reinterpret_cast<float *>(smem32 + a.lds_off_d);
     float *sU = reinterpret_cast<float *>(smem32 + a.lds_off_u);
     float *sUnif = reinterpret_cast<float *>(smem32 + a.lds_off_unif);
+    float *sCE = reinterpret_cast<float *>(smem32 + a.lds_off_ce);   // per chain: centres, steps
     __shared__ int s_tile;
     const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
     const int64_t nsw = a.nsw;
@@ -460,16 +549,17 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 load_row<EPT>(vw, sVW, lane, L);
                 // data modes (U rows from LDS, or from global memory when they do not fit;
                 // two copies of the loop, so the LDS one waits on no global loads)
+                float *sc = sCE + slotc * 2 * a.kce;
                 if (PRI) {
                     if (a.u_lds)
-                        data_moves<L, EPT, RPT, true, true>(kb, sVW, sDb, sUb, urow, lane, vw, Ar, rr, &pr, urowA);
+                        data_moves<L, EPT, RPT, true>(kb, sVW, sDb, sUb, urow, sc, a.kce, lane, vw, Ar, rr, &pr, urowA);
                     else
-                        data_moves<L, EPT, RPT, false, true>(kb, sVW, sDb, Ug, urow, lane, vw, Ar, rr, &pr, urowA);
+                        data_moves<L, EPT, RPT, true>(kb, sVW, sDb, Ug, urow, sc, a.kce, lane, vw, Ar, rr, &pr, urowA);
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                 } else if (a.u_lds)
-                    data_moves<L, EPT, RPT, true>(kb, sVW, sDb, sUb, urow, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT>(kb, sVW, sDb, sUb, urow, sc, a.kce, lane, vw, Ar, rr);
                 else {
-                    data_moves<L, EPT, RPT, false>(kb, sVW, sDb, Ug, urow, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT>(kb, sVW, sDb, Ug, urow, sc, a.kce, lane, vw, Ar, rr);
                     // the U row loaded ahead past the last data mode is never read: wait for
                     // it here, or the compiler waits for every load in flight (the prefetch
                     // below included) where its register is reused
@@ -525,6 +615,12 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 #pragma unroll
                         for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
                     }
+                }
+                {
+                    const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
+                    if (sl >= 0)
+                        acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0,
+                                          nb, tid % 64, active, Ar);
                 }
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ap[t] = Ar[t];

@@ -11,17 +11,20 @@
 // A workgroup of 16 chains runs 512 threads in two roles of four wavefronts each, one of each
 // role per SIMD, so that each SIMD interleaves two independent instruction streams:
 //   data role (threads 0..255):   block steps j = 0, 1, ...: loads A of step j, runs its data
-//                                 modes, hands A to the zero role through LDS (two buffers);
+//                                 modes, hands A to the zero role through LDS (written between
+//                                 the next stage's two barriers, so one buffer suffices);
 //                                 carries r for the whole launch;
 //   zero role (threads 256..511): step j - 1: takes A from the hand-off buffer, runs the zero
-//                                 modes, stores A (and its snapshot row).
+//                                 modes, adds the block's final components to the sums of A,
+//                                 stores A (and its snapshot row).
 // Stage t runs data step t and zero step t - 1; the two barriers of a stage separate the
 // staging writes from the moves.  A block's components are stored by the zero role at stage
 // j + 1 and loaded again by the data role at stage j + B, so problems need B >= 2.
 // The data role also runs the first z zero modes of its block (z = p_zs, chosen to balance
 // the two roles), the zero role the rest.  Each role stages its own part of the block's
 // packed chunk, prefetched into registers one stage ahead: the data part (rows 0..max k + z
-// + 1 of (V, w), the singular values and the U rows) and the zero part (rows k_b + z..n_b + 1).
+// + 1 of (V, w), the singular values and, with ULDS, the U rows; without, the data role reads
+// its U rows from global memory) and the zero part (rows k_b + z..n_b + 1).
 #pragma once
 
 #include "sample32.h"
@@ -36,7 +39,8 @@ struct AreasP {
     float2 *vwz;   // zero rows k_b..n_b + 1 of the block of the zero role
     float *und;    // data-role uniforms, p_kd per chain
     float *unz;    // zero-role uniforms, ROW per chain (indexed by mode)
-    float *h;      // hand-off of A: two buffers of cpw rows of ROW
+    float *h;      // hand-off of A: cpw rows of ROW
+    float *ce;     // data-role centres and steps: 2 kce per chain
 };
 
 // Zero modes i0..i1-1, three per iteration, each row loaded two moves ahead; row i is at
@@ -83,10 +87,9 @@ __device__ __forceinline__ int next_tile_p(const SampleArgs &a, int *s_tile, int
 }
 
 // Data role: data modes of block step t at stage t; r for the whole launch.
-template <int L, int EPT, int RPT, int PFR, int PFU>
+template <int L, int EPT, int RPT, int PFR, int PFU, bool ULDS>
 __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
     constexpr int ROW = EPT * L;
-    constexpr int CPW = 256 / L;
     const int lane = tid % L;
     const int slotc = tid / L;
     const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
@@ -125,6 +128,8 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             pfu.load(a.F32 + b0.off_chunk + a.p_du_word, tid, 256, a.p_wu);
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), once per tile
         }
+        float hA[EPT];   // the components of the previous step, handed over at this stage
+        float *h = ar.h + slotc * ROW;
         for (int64_t t = 0; t <= total; ++t) {
             const bool step = t < total;
             const int64_t s = s0 + t / B;
@@ -133,6 +138,12 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             const int nb = (int)bd.nb, kb = (int)bd.kb;
             const int ke = min(kb + a.p_zs, nb);   // this role runs modes 0..ke-1
             barrier_lds();   // the previous stage's readers of the staging areas are done
+            if (t > 0) {
+                // the hand-off of step t - 1: the zero role reads it after this stage's second
+                // barrier and is done with it before the next stage's first one
+#pragma unroll
+                for (int t2 = 0; t2 < EPT; ++t2) h[lane + L * t2] = hA[t2];
+            }
             if (step) {
                 pfr.store(reinterpret_cast<float4 *>(ar.vwd), tid, 256, a.p_wd);
                 pfu.store(reinterpret_cast<float4 *>(ar.d), tid, 256, a.p_wu);
@@ -167,11 +178,18 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             }
             float2 vw[EPT];
             load_row<EPT>(vw, ar.vwd, lane, L);
-            data_moves<L, EPT, RPT, true>(kb, ar.vwd, ar.d, ar.u, urow, lane, vw, Ar, rr);
+            float *sc = ar.ce + slotc * 2 * a.kce;
+            if constexpr (ULDS) {
+                data_moves<L, EPT, RPT>(kb, ar.vwd, ar.d, ar.u, urow, sc, a.kce, lane, vw, Ar, rr);
+            } else {
+                data_moves<L, EPT, RPT>(kb, ar.vwd, ar.d, a.U32 + bd.off_U32, urow, sc, a.kce, lane, vw, Ar, rr);
+                // the U row loaded ahead past the last data mode is never read: wait for it here,
+                // or the compiler waits for every load in flight where its register is reused
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            }
             if (ke > kb) zero_moves_p<L, EPT>(ar.vwd + kb * ROW, kb, ke, urow, lane, Ar);
-            float *h = ar.h + ((t & 1) * CPW + slotc) * ROW;
 #pragma unroll
-            for (int t2 = 0; t2 < EPT; ++t2) h[lane + L * t2] = Ar[t2];
+            for (int t2 = 0; t2 < EPT; ++t2) hA[t2] = Ar[t2];
             if (b == B - 1 && a.snapR && s >= a.burnin) {
                 float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
 #pragma unroll
@@ -197,7 +215,8 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
 // barrier when B >= 4; with two or three blocks the stores stay at the end of the stage.
 template <int L, int EPT, int PFZ, bool DELAY>
 __device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP &ar, const ProbDesc &pd,
-                                              int64_t chain, bool active, int tid, int64_t s0) {
+                                              const TileDesc &td, int64_t chain, bool active, int tid,
+                                              int64_t s0) {
     constexpr int ROW = EPT * L;
     constexpr int RW = ROW / 2;   // 16-byte words per (V, w) row
     constexpr int CPW = 256 / L;
@@ -262,10 +281,16 @@ __device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP 
         if (DELAY) store_prev();
         if (!step) continue;
         float Ar[EPT];
-        const float *h = ar.h + (((t - 1) & 1) * CPW + slotc) * ROW;
+        const float *h = ar.h + slotc * ROW;
 #pragma unroll
         for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
         zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
+        {
+            const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
+            if (sl >= 0)
+                acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0, nb,
+                                  tid % 64, active, Ar);
+        }
 #pragma unroll
         for (int t2 = 0; t2 < EPT; ++t2) Ap[t2] = Ar[t2];
         p_n0 = bd.n0;
@@ -289,13 +314,13 @@ __device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &a
         const bool active = slotc < td.nchains;
         const int64_t chain = td.chain0 + (active ? slotc : 0);
         if (pd.B >= 4)
-            zero_stages_p<L, EPT, PFZ, true>(a, ar, pd, chain, active, tid, s0);
+            zero_stages_p<L, EPT, PFZ, true>(a, ar, pd, td, chain, active, tid, s0);
         else
-            zero_stages_p<L, EPT, PFZ, false>(a, ar, pd, chain, active, tid, s0);
+            zero_stages_p<L, EPT, PFZ, false>(a, ar, pd, td, chain, active, tid, s0);
     }
 }
 
-template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ, bool ULDS>
 __global__ __launch_bounds__(512) void k_sample32p(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem32[];
     __shared__ int s_tile;
@@ -307,23 +332,24 @@ __global__ __launch_bounds__(512) void k_sample32p(SampleArgs a) {
     ar.und = reinterpret_cast<float *>(smem32 + a.p_off_und);
     ar.unz = reinterpret_cast<float *>(smem32 + a.p_off_unz);
     ar.h = reinterpret_cast<float *>(smem32 + a.p_off_h);
+    ar.ce = reinterpret_cast<float *>(smem32 + a.p_off_ce);
     if (a.snapA && blockIdx.x == 0 && threadIdx.x == 0) *a.snap_first = cload(a.sweep);
     // the role is uniform per wavefront; the two branches hold disjoint live registers
     if (threadIdx.x < 256)
-        data_role_p<L, EPT, RPT, PFR, PFU>(a, ar, &s_tile, (int)threadIdx.x);
+        data_role_p<L, EPT, RPT, PFR, PFU, ULDS>(a, ar, &s_tile, (int)threadIdx.x);
     else
         zero_role_p<L, EPT, PFZ>(a, ar, &s_tile, (int)threadIdx.x - 256);
 }
 
-template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ, bool ULDS>
 hipError_t launch_sample32p_t(const SampleArgs &a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_sample32p<L, EPT, RPT, PFR, PFU, PFZ>), dim3(grid), dim3(512), lds, s, a);
+    hipLaunchKernelGGL((k_sample32p<L, EPT, RPT, PFR, PFU, PFZ, ULDS>), dim3(grid), dim3(512), lds, s, a);
     return hipGetLastError();
 }
 
-template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ>
+template <int L, int EPT, int RPT, int PFR, int PFU, int PFZ, bool ULDS>
 hipError_t allow_lds_sample32p_t(int bytes) {
-    return hipFuncSetAttribute((const void *)k_sample32p<L, EPT, RPT, PFR, PFU, PFZ>,
+    return hipFuncSetAttribute((const void *)k_sample32p<L, EPT, RPT, PFR, PFU, PFZ, ULDS>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

@@ -179,6 +179,24 @@ def test_batched_fp32_config2_average_matches_oracle(pk):
     plan.close()
 
 
+@pytest.mark.parametrize("roles,chains,groups", [(1, 16, 1), (1, 32, 32), (2, 16, 1), (2, 32, 32),
+                                                 (2, 256, 32)])
+def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
+    """The float32 sampler adds each block's final components to per-wavefront float64 sums
+    (Eq. (MCint)).  With one measured sweep the average is the mean of the chains' final
+    states and the posterior s.d. their spread, whether tiles fill their workgroups or leave
+    chain slots empty (groups of one chain)."""
+    p = workloads.small_problem(M=101, N=200, nblocks=2, sigma=2e-3, seed=9)
+    plan = pk.Plan([p], chains=chains, burnin=3, sweeps=1, seed=77, precision="fp32", groups=groups,
+                   lanes_per_chain=16, roles=roles, start="nnls")
+    res = plan.run()
+    assert res.stats["roles"] == roles
+    A = plan.state(0)[0].cpu().numpy()
+    plan.close()
+    assert np.allclose(res.mean.cpu().numpy(), A.mean(0), rtol=1e-12, atol=0)
+    assert np.allclose(res.post_sd.cpu().numpy(), A.std(0), rtol=1e-6, atol=1e-12 * np.max(A))
+
+
 def test_nnls_start_matches_scipy(pk, orc):
     for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
         prep = orc.prepare(p)
@@ -1061,8 +1079,9 @@ def test_grid_dependence_of_figs_8_and_10(pk, orc):
         _, res, p = _ndep_chi2(pk, fam, par, 64)
         p.levels = orc.hierarchy(64, max_block=128)
         prep = orc.prepare(p)
-        o = orc.run(prep, chains=64, burnin=1000, sweeps=1000, seed=8, groups=32, init=orc.nnls_start(prep))
-        ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), o.mean, o.stderr)
+        o = orc.run(prep, chains=256, burnin=1000, sweeps=1000, seed=8, groups=32, init=orc.nnls_start(prep))
+        # 64 strongly correlated points (a smooth spectrum): the bounds of correlated spectra
+        ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), o.mean, o.stderr, **CORRELATED)
         assert ok, (fam, info)
 
 
