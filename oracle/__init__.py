@@ -73,14 +73,14 @@ class _Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("problem_index", ctypes.c_int64),
                 ("refresh_every", ctypes.c_int64), ("groups", ctypes.c_int64),
                 ("want_cross", ctypes.c_int64), ("threads", ctypes.c_int64),
-                ("traj_chain", ctypes.c_int64), ("init", ctypes.c_void_p)]
+                ("traj_chain", ctypes.c_int64), ("init", ctypes.c_void_p), ("vjp_v", ctypes.c_void_p)]
 
 
 class _Out(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("sumA", "sumA2", "count", "sumR", "sumRA", "final_A", "final_r", "final_chi2",
                  "traj_A", "traj_chi2", "drift_max", "n_frozen", "n_clamped", "status",
-                 "n_rejected")]
+                 "n_rejected", "gRv", "gR", "gAv")]
 
 
 def lib():
@@ -404,11 +404,14 @@ class Result:
     cov_rA: Optional[np.ndarray]   # M x N sample Cov(r~, A)
     mean_r: Optional[np.ndarray]
     prep: Prepared
+    vjp: Optional[np.ndarray] = None       # M: J^T v for the run's vjp_v (pooled covariance)
+    vjp_se: Optional[np.ndarray] = None    # M: its standard error over the chain groups
+    vjp_groups: Optional[np.ndarray] = None   # G x M: J^T v of each group's own covariance
 
 
 def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index=0,
         refresh_every=64, groups=32, want_cross=False, threads=None, traj_chain=-1,
-        init=None) -> Result:
+        init=None, vjp_v=None) -> Result:
     L = lib()
     M, N, B = prep.M, prep.N, prep.B
     if threads is None:
@@ -444,7 +447,11 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
         traj_A=np.zeros(total * N) if traj_chain >= 0 else None,
         traj_chi2=np.zeros(total) if traj_chain >= 0 else None,
         drift_max=np.zeros(1), n_frozen=np.zeros(1, np.int64), n_clamped=np.zeros(1, np.int64),
-        status=np.zeros(1, np.int32), n_rejected=np.zeros(1, np.int64))
+        status=np.zeros(1, np.int32), n_rejected=np.zeros(1, np.int64),
+        gRv=np.zeros(G * M) if vjp_v is not None else None,
+        gR=np.zeros(G * M) if vjp_v is not None else None,
+        gAv=np.zeros(G) if vjp_v is not None else None)
+    vv = None if vjp_v is None else np.ascontiguousarray(np.asarray(vjp_v, np.float64))
     shape_m1 = None if prep.shape is None else np.ascontiguousarray(np.asarray(prep.shape, np.float64) - 1.0)
     p = _Problem(M=M, N=N, B=B, Kt=prep.Kt.ctypes.data, gt=prep.gt.ctypes.data,
                  bn0=bn0.ctypes.data, bnb=bnb.ctypes.data, L=len(prep.levels),
@@ -454,7 +461,7 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
     o = _Options(chains=chains, burnin=burnin, sweeps=sweeps, seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
                  problem_index=problem_index, refresh_every=refresh_every, groups=G,
                  want_cross=1 if want_cross else 0, threads=int(threads), traj_chain=traj_chain,
-                 init=start.ctypes.data)
+                 init=start.ctypes.data, vjp_v=None if vv is None else vv.ctypes.data)
     out = _Out(**{k: (v.ctypes.data if v is not None else None) for k, v in bufs.items()})
     L.orc_run(ctypes.byref(p), ctypes.byref(o), ctypes.byref(out))
     sumA = bufs["sumA"].reshape(G, N)
@@ -476,7 +483,25 @@ def run(prep: Prepared, chains=1, burnin=0, sweeps=100, seed=1234, problem_index
     if want_cross and tot > 0:
         mean_r = bufs["sumR"] / tot
         cov_rA = bufs["sumRA"].reshape(M, N) / tot - np.outer(mean_r, mean)
+    vjp_p = vjp_g = vjp_se = None
+    if vv is not None and tot > 0:
+        # J^T v = -T^T Cov(r~, A) v (Sec. II, Eq. (PI) differentiated in the data): per group
+        # from the group's own moments, pooled from all samples; the error bar is the
+        # standard deviation of the group values over sqrt(G)
+        gRv = bufs["gRv"].reshape(G, M)
+        gR = bufs["gR"].reshape(G, M)
+        gAv = bufs["gAv"]
+        yp = gRv.sum(0) / tot - (gR.sum(0) / tot) * (gAv.sum() / tot)
+        vjp_p = -np.asarray(prep.Tt(yp))
+        rows = []
+        for g in range(G):
+            if cnt[g] > 0:
+                yg = gRv[g] / cnt[g] - (gR[g] / cnt[g]) * (gAv[g] / cnt[g])
+                rows.append(-np.asarray(prep.Tt(yg)))
+        vjp_g = np.array(rows)
+        vjp_se = np.std(vjp_g, axis=0, ddof=1) / np.sqrt(len(rows)) if len(rows) >= 2 else None
     return Result(mean=mean, stderr=se, post_sd=np.sqrt(var), ess=ess, group_means=gm,
+                  vjp=vjp_p, vjp_se=vjp_se, vjp_groups=vjp_g,
                   final_A=bufs["final_A"].reshape(chains, N),
                   final_r=bufs["final_r"].reshape(chains, M), final_chi2=bufs["final_chi2"],
                   traj_A=None if bufs["traj_A"] is None else bufs["traj_A"].reshape(total, N),

@@ -282,6 +282,7 @@ typedef struct {
     int64_t threads;
     int64_t traj_chain;     /* chain whose A is recorded after every sweep, or -1        */
     const double *init;     /* N start vector (shared by all chains), >= 0               */
+    const double *vjp_v;    /* N cotangent for per-group VJP moments, or NULL            */
 } orc_options;
 
 typedef struct {
@@ -300,6 +301,9 @@ typedef struct {
     int64_t *n_clamped;  /* 1                                                           */
     int32_t *status;     /* 1                                                           */
     int64_t *n_rejected; /* 1: moves rejected by the gamma-prior acceptance test         */
+    double *gRv;         /* groups x M: sum r (A . v)       (vjp_v)                      */
+    double *gR;          /* groups x M: sum r               (vjp_v)                      */
+    double *gAv;         /* groups: sum A . v               (vjp_v)                      */
 } orc_out;
 
 typedef struct {
@@ -309,6 +313,7 @@ typedef struct {
     int64_t c0, c1;
     /* per-thread accumulators */
     double *sumA, *sumA2, *sumR, *sumRA;
+    double *gRv, *gR, *gAv;
     int64_t *count;
     double drift;
     int64_t frozen, clamped, rejected;
@@ -445,6 +450,17 @@ static void *run_chains(void *arg) {
                     sa2[n] += A[n] * A[n];
                 }
                 wk->count[g]++;
+                if (o->vjp_v) {
+                    /* the moments of one group's covariance Cov(r~, A) v (Sec. II, Eq. (PI)
+                       differentiated in the data) */
+                    double av = 0.0;
+                    for (int64_t n = 0; n < N; ++n) av += A[n] * o->vjp_v[n];
+                    for (int64_t m = 0; m < M; ++m) {
+                        wk->gRv[g * M + m] += r[m] * av;
+                        wk->gR[g * M + m] += r[m];
+                    }
+                    wk->gAv[g] += av;
+                }
                 if (o->want_cross) {
                     for (int64_t m = 0; m < M; ++m) {
                         wk->sumR[m] += r[m];
@@ -479,6 +495,11 @@ int orc_run(const orc_problem *p, const orc_options *o, orc_out *out) {
             wk[t].sumR = (double *)calloc((size_t)M, sizeof(double));
             wk[t].sumRA = (double *)calloc((size_t)(M * N), sizeof(double));
         }
+        if (o->vjp_v) {
+            wk[t].gRv = (double *)calloc((size_t)(G * M), sizeof(double));
+            wk[t].gR = (double *)calloc((size_t)(G * M), sizeof(double));
+            wk[t].gAv = (double *)calloc((size_t)G, sizeof(double));
+        }
         pthread_create(&th[t], NULL, run_chains, &wk[t]);
     }
     int32_t status = ORC_OK;
@@ -491,6 +512,14 @@ int orc_run(const orc_problem *p, const orc_options *o, orc_out *out) {
             out->sumA2[i] += wk[t].sumA2[i];
         }
         for (int64_t g = 0; g < G; ++g) out->count[g] += wk[t].count[g];
+        if (o->vjp_v) {
+            for (int64_t i = 0; i < G * M; ++i) {
+                out->gRv[i] += wk[t].gRv[i];
+                out->gR[i] += wk[t].gR[i];
+            }
+            for (int64_t g = 0; g < G; ++g) out->gAv[g] += wk[t].gAv[g];
+            free(wk[t].gRv); free(wk[t].gR); free(wk[t].gAv);
+        }
         if (o->want_cross) {
             for (int64_t m = 0; m < M; ++m) out->sumR[m] += wk[t].sumR[m];
             for (int64_t i = 0; i < M * N; ++i) out->sumRA[i] += wk[t].sumRA[i];

@@ -439,6 +439,34 @@ def test_gaussian_limit_mean_and_vjp(orc):
     assert np.linalg.norm(got - ref) < 0.03 * np.linalg.norm(ref)
 
 
+def test_vjp_standard_error_is_calibrated_on_the_gaussian_limit(orc):
+    """The error bar of J^T v (standard deviation over 32 chain groups of each group's own
+    covariance estimate, over sqrt(32)) against the closed form J = Cov K~^T T of the Gaussian
+    limit: 120 seeded replicas, the sum of squared z-scores of three data points inside
+    chi^2(120) each, and the pooled estimate equal to the cross-moment route."""
+    p = workloads.gaussian_limit_problem()
+    prep = orc.prepare(p)
+    Kt = prep.Kt
+    cov = np.linalg.inv(Kt.T @ Kt)
+    J = cov @ Kt.T / p.sigma[None, :]
+    v = np.array([1.0, -0.5, 0.25, 2.0])
+    ref = J.T @ v
+    R = 120
+    lo, hi = _chi2_bounds(R)
+    ms = [0, 100, 200]
+    z = np.zeros((R, len(ms)))
+    for r in range(R):
+        res = orc.run(prep, chains=32, burnin=10, sweeps=100, groups=32, seed=300 + r, vjp_v=v,
+                      want_cross=(r == 0), threads=4)
+        if r == 0:
+            assert np.allclose(res.vjp, orc.vjp(res, v), rtol=1e-8, atol=1e-10 * np.abs(ref).max())
+        z[r] = (res.vjp[ms] - ref[ms]) / res.vjp_se[ms]
+    for j in range(len(ms)):
+        q = float(np.sum(z[:, j] ** 2))
+        assert lo < q < hi, (ms[j], q, lo, hi)
+        assert abs(z[:, j].mean()) < 4.0 * z[:, j].std(ddof=1) / math.sqrt(R)
+
+
 # --------------------------------------------------------------------------------------
 # invariants and structural limits
 # --------------------------------------------------------------------------------------
