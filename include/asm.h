@@ -192,11 +192,25 @@ int asm_plan_create(const asm_problem *problems, int64_t n_problems, const asm_o
 int asm_plan_run(asm_plan *plan, double *mean, double *stderr_, double *post_sd,
                  asm_stats *stats);
 
+/* The estimate of the last asm_plan_run again (mean, stderr_: device, sum N each) and the
+   average of each chain group (or batch of sweeps when there are fewer chains than groups)
+   behind its error bar: group_means, device, groups x sum N, group-major, NaN for a group
+   without samples.  The error bar of any statistic of <A> (a linear functional v . <A>, say)
+   is the spread of the statistic over the groups divided by sqrt(groups).
+   Errors: ASM_EINVAL, ASM_ESTATE (no run yet), ASM_EHIP. */
+int asm_plan_group_means(asm_plan *plan, double *mean, double *stderr_, double *group_means);
+
 /* Vector-Jacobian product of the last asm_plan_run: grad_G = J^T v with
    J = d<A>/dG = -Cov(A, r~) T, r~ = T (G - K A), C^-1 = T^T T, obtained by differentiating
-   the normalised posterior of Eq. (PI) with respect to the data.  v: device, sum N;
-   grad_G: device, sum M.  Needs want_vjp = 1.  Errors: ASM_ESTATE, ASM_EHIP. */
-int asm_plan_vjp(asm_plan *plan, const double *v, double *grad_G);
+   the normalised posterior of Eq. (PI) with respect to the data; Cov is the pooled sample
+   covariance of the run's measured sweeps.  grad_se (nullable): the standard error of each
+   entry, the standard deviation over the chain groups (over the batches of sweeps when there
+   are fewer chains than groups) of the same product formed from each group's own moments,
+   divided by sqrt(groups).  Float32 plans take the moments in the coordinates of an
+   orthonormal basis of range(K~) (relative cut 1e-10), where Cov(r~, A) lies.
+   v: device, sum N; grad_G, grad_se: device, sum M.  Needs want_vjp = 1.
+   Errors: ASM_ESTATE, ASM_EINVAL, ASM_EHIP. */
+int asm_plan_vjp(asm_plan *plan, const double *v, double *grad_G, double *grad_se);
 
 /* Advance every chain by `sweeps` sweeps without accumulating (burn-in style; the sweep
    counter that keys the random numbers advances).  Errors: ASM_EUNBOUNDED, ASM_EHIP. */

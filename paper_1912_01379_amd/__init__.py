@@ -22,7 +22,8 @@ ASM_OK, ASM_EINVAL, ASM_EDOMAIN, ASM_ESTATE, ASM_EUNBOUNDED, ASM_EHIP, ASM_ENOME
 ASM_FP64, ASM_FP32 = 0, 1
 ASM_START_FLAT, ASM_START_NNLS, ASM_START_NNLS_NOISED = 0, 1, 2
 
-EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_advance", "asm_plan_state",
+EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_group_means", "asm_plan_advance",
+            "asm_plan_state",
             "asm_plan_factors", "asm_plan_whitened", "asm_plan_destroy", "asm_tn_draw",
             "asm_uniforms", "asm_hierarchy", "asm_last_error", "asm_version"]
 
@@ -74,7 +75,8 @@ def _load():
     L.asm_plan_create.argtypes = [ctypes.POINTER(_Problem), i64, ctypes.POINTER(_Options), vp,
                                   ctypes.POINTER(vp)]
     L.asm_plan_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Stats)]
-    L.asm_plan_vjp.argtypes = [vp, vp, vp]
+    L.asm_plan_vjp.argtypes = [vp, vp, vp, vp]
+    L.asm_plan_group_means.argtypes = [vp, vp, vp, vp]
     L.asm_plan_advance.argtypes = [vp, i64]
     L.asm_plan_state.argtypes = [vp, i64, vp, vp, vp]
     L.asm_plan_factors.argtypes = [vp, i64, i64, ctypes.POINTER(i32), vp, vp, vp]
@@ -212,12 +214,25 @@ class Plan:
         self.last = RunResult(mean, se, sd, st.as_dict())
         return self.last
 
-    def vjp(self, v) -> torch.Tensor:
+    def vjp(self, v, stderr: bool = False):
+        """J^T v of the last run (float64, sum M); with stderr=True also its standard error over
+        the chain groups."""
         v = _dev(v, self.device)
         out = torch.empty(sum(self.M), dtype=torch.float64, device=self.device)
+        se = torch.empty_like(out) if stderr else None
         with torch.cuda.device(self.device):
-            _check(_lib.asm_plan_vjp(self.handle, v.data_ptr(), out.data_ptr()))
-        return out
+            _check(_lib.asm_plan_vjp(self.handle, v.data_ptr(), out.data_ptr(), _ptr(se)))
+        return (out, se) if stderr else out
+
+    def group_means(self) -> torch.Tensor:
+        """The last run's average of each chain group: (groups, sum N)."""
+        tot = sum(self.N)
+        m = torch.empty(tot, dtype=torch.float64, device=self.device)
+        se = torch.empty_like(m)
+        g = torch.empty((self.options.groups or 32, tot), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(_lib.asm_plan_group_means(self.handle, m.data_ptr(), se.data_ptr(), g.data_ptr()))
+        return g
 
     def advance(self, sweeps: int):
         with torch.cuda.device(self.device):
@@ -295,11 +310,12 @@ def uniforms(seed, problem, chain, sweep0, nsweeps, nblocks, nmodes, device="cud
 
 
 class AverageSpectrum(torch.autograd.Function):
-    """<A>(G) with a backward pass through the on-device covariance estimator.
+    """(<A>, its standard error) as functions of the data G, with a backward pass through the
+    on-device covariance estimator (asm_plan_vjp).
 
-    forward(G, plan_factory) runs a fresh plan on data G (a float64 device tensor) and
-    returns the average spectrum; backward returns J^T grad through asm_plan_vjp.
-    plan_factory(G) must build a Plan with want_vjp=True for the data G.
+    forward(G, plan_factory) builds a plan with plan_factory(G) (it must pass want_vjp=True),
+    runs it, and returns the average spectrum and its error bars (the error bars carry no
+    gradient).  backward(grad_mean, grad_stderr) returns J^T grad_mean and releases the plan.
     """
 
     @staticmethod
@@ -307,9 +323,13 @@ class AverageSpectrum(torch.autograd.Function):
         plan = plan_factory(G.detach())
         res = plan.run()
         ctx.plan = plan
-        return res.mean.clone()
+        ctx.mark_non_differentiable(res.stderr)
+        return res.mean.clone(), res.stderr.clone()
 
     @staticmethod
-    def backward(ctx, grad_mean):
-        g = ctx.plan.vjp(grad_mean.detach().to(torch.float64).contiguous())
+    def backward(ctx, grad_mean, grad_stderr):
+        plan = ctx.plan
+        g = plan.vjp(grad_mean.detach().to(torch.float64).contiguous())
+        plan.close()
+        ctx.plan = None
         return g, None

@@ -61,7 +61,11 @@ struct asm_plan {
     std::vector<double> slot_count;
     int64_t total_chains = 0, total_n = 0, total_m = 0;
     int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
-    int ksplit = 1;          // chain splits of the cross-moment partial sums
+    int parts = 1;           // cross-moment partial sums per chain group (splits = groups x parts)
+    int64_t cross_words = 0;
+    double *Qb = nullptr;     // range bases of the problems' K~ (float32 plans with want_vjp)
+    bool any_rank = false;    // a problem whose moments are taken in its range basis
+    double *vjp_scratch = nullptr;
     // float32 plans: per-sweep snapshots of A (and of r with want_vjp) of the accumulated
     // sweeps, reduced after each launch into the sums of A and A^2 (and the cross moments);
     // two snapshot buffers: the sampler fills one while the other is reduced on a second
@@ -124,11 +128,10 @@ struct asm_plan {
     bool any_con = false;      // a problem with a linear constraint c . A = F
     double *con = nullptr;     // the constraint vectors c (at off_n)
     int32_t *slot_group_d = nullptr;
-    double *cross = nullptr, *nsamples = nullptr, *vjp_y = nullptr;
+    double *cross = nullptr;
     unsigned long long *counters = nullptr;
     int *flags = nullptr, *queue = nullptr;
     int64_t *sweep_d = nullptr;
-    std::vector<double> nsamples_host;
 
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // events around each sampler launch of a run (pairs), reused across runs
@@ -445,11 +448,13 @@ int snap_acquire(asm_plan *pl, int par) {
 // After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
 // moments on the second stream, after the main stream's work so far.
 int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
-    (void)burnin_abs;
     HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
     HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, pl->ksplit, nsnap, pl->snapA[par],
-                             pl->snapR[par], pl->cross, pl->xstream));
+    if (pl->any_rank)
+        HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, nsnap, pl->Qb, pl->snapR[par], pl->xstream));
+    HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, (int)pl->opt.groups, pl->parts, nsnap,
+                             pl->snapA[par], pl->snapR[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps,
+                             pl->cross, pl->xstream));
     HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
     pl->pending[par] = true;
     return ASM_OK;
@@ -553,8 +558,11 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
             TRY(snap_release(pl, par, seg, burnin_abs));
             pl->snap_par ^= 1;
         } else if (vjp && s >= burnin_abs) {
-            HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, pl->ksplit, pl->A32,
-                                    pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->stream));
+            // the sweep just sampled: its chain groups, or its batch of sweeps
+            const int bgroup = pl->opt.chains < pl->opt.groups
+                                   ? (int)((s - burnin_abs) * pl->opt.groups / pl->opt.sweeps) : -1;
+            HIPCHK(launch_cross_all(pl->d_probs, pl->P, pl->max_cross_tiles, (int)pl->opt.groups, pl->parts, bgroup,
+                                    pl->A32, pl->r32, pl->A64, pl->r64, pl->fp32, pl->cross, pl->stream));
         }
         if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
     }
@@ -929,24 +937,21 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         }
     }
     if (o->want_vjp) {
+        // cross moments in partial sums per (chain group, part): the groups give the VJP its
+        // error bar, the parts the parallelism
+        int cus = 256, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        (void)hipGetLastError();
         if (pl->fp32) {
-            // cross moments reduced by (tile, split) workgroups: four workgroups fit a CU at
-            // once, and about four such rounds over the chip (a multiple of 8 chain splits,
-            // one XCD per split group) keep the last round nearly full
-            int cus = 256, dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                cus = 256;
-            const int64_t want = 16LL * cus / std::max<int64_t>(1, pl->max_snap_tiles);
-            pl->ksplit = (int)std::max<int64_t>(8, std::min<int64_t>(256, want / 8 * 8));
+            // (tile, split) workgroups: four fit a CU beside the sampler, about four rounds
+            const int64_t want = 16LL * cus / std::max<int64_t>(1, pl->max_snap_tiles * G);
+            pl->parts = (int)std::max<int64_t>(1, std::min<int64_t>(8, want));
         } else {
-            // enough (tile, split) wavefronts to fill the chip, at least 8 chains per split
-            const int64_t want = (2048 + pl->max_cross_tiles - 1) / pl->max_cross_tiles;
-            pl->ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, C / 8}));
-        }
-        for (auto &pd : pl->probs) {
-            pd.off_cross = offcross;
-            offcross += (int64_t)pl->ksplit * pd.M * (pd.N + 1);
+            // enough (tile, split) wavefronts to fill the chip, at least 8 chains per part
+            const int64_t want = (2048 + pl->max_cross_tiles * G - 1) / (pl->max_cross_tiles * G);
+            pl->parts = (int)std::max<int64_t>(1, std::min<int64_t>({want, 8, std::max<int64_t>(1, C / (8 * G))}));
         }
     }
 
@@ -999,11 +1004,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         // default priority; non-blocking, so that null-stream work does not serialise it
         HSTEP(hipStreamCreateWithFlags(&pl->xstream, hipStreamNonBlocking));
     }
-    if (o->want_vjp) {
-        STEP(dalloc(pl, &pl->cross, offcross));
-        STEP(dalloc(pl, &pl->nsamples, n));
-        STEP(dalloc(pl, &pl->vjp_y, offm));
-    }
+    if (o->want_vjp) STEP(dalloc(pl, &pl->vjp_scratch, vjp_scratch_doubles(n, offm, (int)G)));
     hipStream_t st = pl->stream;
     HSTEP(hipMemsetAsync(pl->flags, 0, sizeof(int), st));
     HSTEP(hipMemsetAsync(pl->sweep_d, 0, sizeof(int64_t), st));
@@ -1101,6 +1102,81 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     HSTEP(hipMemcpyAsync(kb.data(), kb_d, kb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HSTEP(hipStreamSynchronize(st));
     for (size_t b = 0; b < kb.size(); ++b) pl->blocks[b].kb = kb[b];
+
+    // ---- range bases and cross-moment sums (want_vjp) ----
+    if (o->want_vjp) {
+        if (pl->fp32) {
+            // the VJP's moments of the float32 plans are taken in the coordinates of a basis of
+            // range(K~), from the data modes of each problem's first partition
+            constexpr int kMaxRank = 128;
+            std::vector<int64_t> cfirst(1, 0), colU, colD, woff;
+            int64_t wtot = 0, qtot = 0, maxm = 0;
+            for (int64_t p = 0; p < n; ++p) {
+                ProbDesc &pd = pl->probs[p];
+                const int32_t lc = pl->lvl[2 * pd.off_lvl + 1];
+                for (int32_t b = 0; b < lc; ++b) {
+                    const BlockDesc &bd = pl->blocks[pd.off_blk + b];
+                    for (int64_t i = 0; i < bd.kb; ++i) {
+                        colU.push_back(bd.off_U + i * pd.M);
+                        colD.push_back(bd.off_d + i);
+                    }
+                }
+                const int64_t K = (int64_t)colU.size() - cfirst.back();
+                cfirst.push_back((int64_t)colU.size());
+                woff.push_back(wtot);
+                wtot += std::max<int64_t>(1, K) * pd.M;
+                pd.off_q = qtot;
+                qtot += pd.M * std::min<int64_t>({pd.M, std::max<int64_t>(K, 1), (int64_t)kMaxRank});
+                maxm = std::max(maxm, pd.M);
+            }
+            double *rwork = nullptr;
+            int64_t *cf_d = nullptr, *cu_d = nullptr, *cd_d = nullptr, *wo_d = nullptr;
+            int32_t *rk_d = nullptr;
+            ProbDesc *pb_d = nullptr;
+            STEP(dalloc(pl, &rwork, wtot));
+            STEP(dalloc(pl, &pl->Qb, qtot));
+            STEP(dalloc(pl, &cf_d, cfirst.size()));
+            STEP(dalloc(pl, &cu_d, colU.size()));
+            STEP(dalloc(pl, &cd_d, colD.size()));
+            STEP(dalloc(pl, &wo_d, woff.size()));
+            STEP(dalloc(pl, &rk_d, n));
+            STEP(dalloc(pl, &pb_d, n));
+            HSTEP(hipMemcpyAsync(pb_d, pl->probs.data(), n * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+            HSTEP(hipMemcpyAsync(cf_d, cfirst.data(), cfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            if (!colU.empty()) {
+                HSTEP(hipMemcpyAsync(cu_d, colU.data(), colU.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+                HSTEP(hipMemcpyAsync(cd_d, colD.data(), colD.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            }
+            HSTEP(hipMemcpyAsync(wo_d, woff.data(), woff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            HSTEP(launch_range_basis(pb_d, n, maxm, cf_d, cu_d, cd_d, pl->U64, pl->d64, wo_d, rwork, pl->Qb, rk_d,
+                                     kMaxRank, st));
+            std::vector<int32_t> rk(n);
+            HSTEP(hipMemcpyAsync(rk.data(), rk_d, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HSTEP(hipStreamSynchronize(st));
+            for (int64_t p = 0; p < n; ++p) {
+                pl->probs[p].rank_r = rk[p];
+                pl->any_rank |= rk[p] > 0;
+            }
+            // the scratch of the basis is not needed again
+            for (void *q : {(void *)rwork, (void *)cf_d, (void *)cu_d, (void *)cd_d, (void *)wo_d, (void *)rk_d,
+                            (void *)pb_d}) {
+                auto it = std::find(pl->allocs.begin(), pl->allocs.end(), q);
+                if (it != pl->allocs.end()) pl->allocs.erase(it);
+                HSTEP(hipFree(q));
+            }
+            pl->max_snap_tiles = 0;
+            for (auto &pd : pl->probs)
+                pl->max_snap_tiles = std::max(pl->max_snap_tiles,
+                                              cross_snap_tiles(pd.rank_r > 0 ? pd.rank_r : pd.M, pd.N));
+        }
+        int64_t offx = 0;
+        for (auto &pd : pl->probs) {
+            pd.off_cross = offx;
+            offx += (int64_t)G * pl->parts * (pd.rank_r > 0 ? pd.rank_r : pd.M) * (pd.N + 1);
+        }
+        pl->cross_words = offx;
+        STEP(dalloc(pl, &pl->cross, offx));
+    }
 
     // ---- chain -> problem tables ----
     {
@@ -1409,11 +1485,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     HIPCHK(hipMemsetAsync(pl->accA, 0, slot_elems * sizeof(double), st));
     HIPCHK(hipMemsetAsync(pl->accA2, 0, slot_elems * sizeof(double), st));
     HIPCHK(hipMemsetAsync(pl->counters, 0, 3 * sizeof(unsigned long long), st));
-    if (pl->opt.want_vjp) {
-        const ProbDesc &lp = pl->probs.back();
-        const int64_t crossn = lp.off_cross + (int64_t)pl->ksplit * lp.M * (lp.N + 1);
-        HIPCHK(hipMemsetAsync(pl->cross, 0, crossn * sizeof(double), st));
-    }
+    if (pl->opt.want_vjp) HIPCHK(hipMemsetAsync(pl->cross, 0, pl->cross_words * sizeof(double), st));
     HIPCHK(hipEventRecord(pl->ev[2], st));
     const int64_t run_first = pl->sweep;
     const int64_t burnin_abs = pl->sweep + pl->opt.burnin;
@@ -1426,12 +1498,7 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     TRY(lrc);
     HIPCHK(hipEventRecord(pl->ev[3], st));
     HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2,
-                           pl->slot_group_d, pl->slot_count_d, mean, stderr_, post_sd, st));
-    if (pl->opt.want_vjp) {
-        pl->nsamples_host.assign(pl->P, (double)pl->opt.chains * (double)pl->opt.sweeps);
-        HIPCHK(hipMemcpyAsync(pl->nsamples, pl->nsamples_host.data(), pl->P * sizeof(double),
-                              hipMemcpyHostToDevice, st));
-    }
+                           pl->slot_group_d, pl->slot_count_d, mean, stderr_, post_sd, nullptr, st));
     int hflags = 0;
     TRY(check_flags(pl, &hflags));
     pl->ran = true;
@@ -1493,28 +1560,28 @@ int asm_plan_run(asm_plan *pl, double *mean, double *stderr_, double *post_sd, a
     return ASM_OK;
 }
 
-int asm_plan_vjp(asm_plan *pl, const double *v, double *grad_G) {
+int asm_plan_vjp(asm_plan *pl, const double *v, double *grad_G, double *grad_se) {
     g_err.clear();
     if (!pl) return fail(ASM_EINVAL, "plan is NULL");
     if (!pl->opt.want_vjp) return fail(ASM_ESTATE, "plan was created without want_vjp");
     if (!pl->ran) return fail(ASM_ESTATE, "asm_plan_run must come before asm_plan_vjp");
     if (!v || !grad_G) return fail(ASM_EINVAL, "v and grad_G are required");
-    // the mean of the last run is recomputed into scratch from the accumulators
-    double *mean = nullptr, *se = nullptr;
-    TRY(dalloc(pl, &mean, pl->total_n));
-    TRY(dalloc(pl, &se, pl->total_n));
     hipStream_t st = pl->stream;
-    HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2,
-                           pl->slot_group_d, pl->slot_count_d, mean, se, nullptr, st));
-    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->ksplit, pl->cross, mean,
-                      pl->nsamples, pl->sigma, pl->Lc, v, pl->vjp_y, grad_G, pl->any_cov ? 1 : 0, st));
+    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->max_m, (int)pl->opt.groups, pl->parts,
+                      pl->cross, pl->accA, pl->slot_group_d, pl->slot_count_d, pl->Qb, pl->sigma, pl->Lc, v,
+                      pl->vjp_scratch, grad_G, grad_se, st));
     HIPCHK(hipStreamSynchronize(st));
-    // release the scratch again
-    for (double *p : {mean, se}) {
-        auto it = std::find(pl->allocs.begin(), pl->allocs.end(), (void *)p);
-        if (it != pl->allocs.end()) pl->allocs.erase(it);
-        HIPCHK(hipFree(p));
-    }
+    return ASM_OK;
+}
+
+int asm_plan_group_means(asm_plan *pl, double *mean, double *stderr_, double *group_means) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (!pl->ran) return fail(ASM_ESTATE, "asm_plan_run must come before asm_plan_group_means");
+    if (!mean || !stderr_ || !group_means) return fail(ASM_EINVAL, "mean, stderr_ and group_means are required");
+    HIPCHK(launch_finalize(pl->d_probs, pl->P, pl->d_nprefix, pl->total_n, pl->accA, pl->accA2, pl->slot_group_d,
+                           pl->slot_count_d, mean, stderr_, nullptr, group_means, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
     return ASM_OK;
 }
 

@@ -23,7 +23,8 @@ struct ProbDesc {
     int64_t off_r;            // chain state r: C x M
     int64_t off_c;            // per-chain scalars (chi2, drift): C
     int64_t off_blk;          // first block in the block table
-    int64_t off_cross;        // ksplit x M x (N+1) partial cross moments sum r [A, 1]^T
+    int64_t off_cross;        // groups x parts splits of Mx x (N+1) partial cross moments
+                              // sum x [A, 1]^T, x = r (Mx = M) or Q^T r (Mx = rank_r)
     int64_t off_L;            // Cholesky factor (M x M) when whitened with a covariance
     int64_t off_slot;         // element offset of the problem's accumulator slots (slots x N)
     int64_t off_tab;          // first entry of the problem in the slot tables
@@ -39,6 +40,9 @@ struct ProbDesc {
     int64_t has_con;          // 1: a linear constraint c . A = F (c at off_n in the constraint array)
     double con_value;         // F
     int64_t off_lvl;          // first level in the level table (pairs: first block, count)
+    int64_t rank_r;           // columns of the range basis Q of K~ (float32 VJP moments in its
+                              // coordinates), or 0: the moments are of r itself
+    int64_t off_q;            // Q (M x rank_r, column j at off_q + j M) in the basis array
 };
 
 struct BlockDesc {
@@ -236,20 +240,29 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
                           const int32_t *chain_local, int64_t total_chains, const float *r32,
                           const double *r64, int fp32, double *out, const double *prev,
                           double *drift, hipStream_t s);
-hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
-                            const float *A32, const float *r32, const double *A64,
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int groups, int parts,
+                            int bgroup, const float *A32, const float *r32, const double *A64,
                             const double *r64, int fp32, double *cross, hipStream_t s);
-hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
-                             const float *snapA, const float *snapR, double *cross, hipStream_t s);
-__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N);
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int groups, int parts,
+                             int64_t nsnap, const float *snapA, const float *snapR, const int64_t *snap_first,
+                             int64_t burnin, int64_t sweeps, double *cross, hipStream_t s);
+__host__ __device__ int64_t cross_snap_tiles(int64_t Mx, int64_t N);
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *Q,
+                          float *snapR, hipStream_t s);
+hipError_t launch_range_basis(const ProbDesc *probs_dev, int64_t P, int64_t max_m, const int64_t *col_first,
+                              const int64_t *colU, const int64_t *colD, const double *U64, const double *d64,
+                              const int64_t *work_off, double *work, double *Q, int32_t *rank_out, int max_r,
+                              hipStream_t s);
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,
-                           double *stderr_, double *post_sd, hipStream_t s);
-hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
-                      int64_t total_m, int ksplit, const double *cross, const double *mean,
-                      const double *nsamples, const double *sigma, const double *Lchol,
-                      const double *v, double *y, double *grad, int any_cov, hipStream_t s);
+                           double *stderr_, double *post_sd, double *gmean, hipStream_t s);
+hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev, int64_t total_m,
+                      int64_t max_m, int groups, int parts, const double *cross, const double *accA,
+                      const int32_t *slot_group, const double *slot_count, const double *Q, const double *sigma,
+                      const double *Lchol, const double *v, double *scratch, double *grad, double *grad_se,
+                      hipStream_t s);
+int64_t vjp_scratch_doubles(int64_t P, int64_t total_m, int groups);
 hipError_t launch_state64(const ProbDesc *probs_dev, int64_t p, const ProbDesc &ph, const float *A32,
                           const float *r32, const double *A64, const double *r64,
                           const double *chi2, int fp32, double *A, double *r, double *chi2_out,

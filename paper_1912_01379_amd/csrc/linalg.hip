@@ -113,10 +113,12 @@ hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_proble
     return hipGetLastError();
 }
 
-// Cross moment of one sweep, added to per-split float64 partial sums:
-//   X_k[m][n] += sum_{c in split k} r[c][m] A[c][n]  for n < N, and X_k[m][N] += sum r[c][m]
-// (the last column treats A as having an extra component equal to one).  One wavefront owns
-// a 32 x 32 tile of one split (2 x 2 MFMA f64 16x16x4 blocks), so the partial sums are
+// Cross moment of one sweep of the float64 sampler, added to per-split float64 partial sums:
+//   X_split[m][n] += sum_{c in split} r[c][m] A[c][n]  for n < N,  X_split[m][N] += sum r[c][m]
+// (the last column treats A as having an extra component equal to one).  The splits are
+// (group, part): the chains of chain group g in `parts` ranges, or, with batch means
+// (bgroup >= 0), all chains of the sweep in `parts` ranges of batch bgroup.  One wavefront
+// owns a 32 x 32 tile of one split (2 x 2 MFMA f64 16x16x4 blocks), so the partial sums are
 // updated without atomics and the order of every addition is fixed.
 __device__ __forceinline__ double cross_b(const float *A32, const double *A64, int fp32, int64_t base,
                                           int64_t n, int64_t N, bool ok) {
@@ -125,7 +127,7 @@ __device__ __forceinline__ double cross_b(const float *A32, const double *A64, i
     return load_state(A32, A64, base + n, fp32);
 }
 
-__global__ __launch_bounds__(64) void k_cross(const ProbDesc *probs, int ksplit, const float *A32,
+__global__ __launch_bounds__(64) void k_cross(const ProbDesc *probs, int parts, int bgroup, const float *A32,
                                               const float *r32, const double *A64, const double *r64,
                                               int fp32, double *cross) {
     const ProbDesc pd = probs[blockIdx.z];
@@ -133,9 +135,12 @@ __global__ __launch_bounds__(64) void k_cross(const ProbDesc *probs, int ksplit,
     const int64_t ntm = (M + 31) / 32, ntn = (N1 + 31) / 32;
     const int64_t tile = blockIdx.x;
     if (tile >= ntm * ntn) return;
-    const int split = blockIdx.y;
+    const int g = bgroup >= 0 ? bgroup : (int)blockIdx.y / parts, part = (int)blockIdx.y % parts;
+    const int split = g * parts + part;
+    const int64_t G = pd.groups;
+    const int64_t cg0 = bgroup >= 0 ? 0 : C * g / G, cg1 = bgroup >= 0 ? C : C * (g + 1) / G;
+    const int64_t c_lo = cg0 + (cg1 - cg0) * part / parts, c_hi = cg0 + (cg1 - cg0) * (part + 1) / parts;
     const int64_t m0 = (tile / ntn) * 32, n0 = (tile % ntn) * 32;
-    const int64_t c_lo = C * split / ksplit, c_hi = C * (split + 1) / ksplit;
     const int lane = threadIdx.x;
     const int i = lane % 16, k = lane / 16;
     const int64_t ma0 = m0 + i, ma1 = m0 + 16 + i;
@@ -167,49 +172,94 @@ __global__ __launch_bounds__(64) void k_cross(const ProbDesc *probs, int ksplit,
     }
 }
 
-hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit,
-                            const float *A32, const float *r32, const double *A64,
+hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int groups, int parts,
+                            int bgroup, const float *A32, const float *r32, const double *A64,
                             const double *r64, int fp32, double *cross, hipStream_t s) {
-    hipLaunchKernelGGL(k_cross, dim3((unsigned)max_tiles, (unsigned)ksplit, (unsigned)P), dim3(64), 0, s,
-                       probs_dev, ksplit, A32, r32, A64, r64, fp32, cross);
+    const unsigned gy = (unsigned)(bgroup >= 0 ? parts : groups * parts);
+    hipLaunchKernelGGL(k_cross, dim3((unsigned)max_tiles, gy, (unsigned)P), dim3(64), 0, s, probs_dev, parts,
+                       bgroup, A32, r32, A64, r64, fp32, cross);
     return hipGetLastError();
 }
 
-// Cross moments from the per-sweep snapshots of one launch of the float32 sampler: with the
-// rows k = (sweep, chain) of the snapshots,
-//   X_split[m][n] += sum_{k in split} r_k[m] A_k[n] (n < N),  X_split[m][N] += sum r_k[m].
-// A workgroup of 4 wavefronts owns a 64 x 128 output tile and a range of rows; each
-// wavefront owns 32 x 64 of it (2 x 4 MFMA f64 16x16x4 blocks).  The rows pass through LDS
-// in chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile
-// that needs it; the float32 values are widened to float64 as they enter the MFMAs.  The
-// kernel is sized (12 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with the
-// sampler, which it runs beside on a second stream.  Snapshot rows are padded to multiples
-// of four floats.
+// Cross moments from the per-sweep snapshots of one launch of the float32 sampler.  The
+// residual rows hold either r (M entries) or, for problems with a range basis Q (rank_r > 0),
+// its coordinates y = Q^T r (rank_r entries, written over the row by k_project); with x the
+// row entries and the snapshot rows k = (sweep, chain) of a split,
+//   X_split[i][n] += sum_{k in split} x_k[i] A_k[n] (n < N),  X_split[i][N] += sum x_k[i].
+// Splits are (group, part): the rows of chain group g (or, with batch means, of the sweeps of
+// batch g), in `parts` ranges, so the partial sums are per-group moments (the error bar of
+// the VJP).  A workgroup of 4 wavefronts owns a 64 x 128 output tile and one split; each
+// wavefront owns 32 x 64 of it (2 x 4 MFMA f64 16x16x4 blocks).  The rows pass through LDS in
+// chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile that
+// needs it; the float32 values are widened to float64 as they enter the MFMAs.  The kernel is
+// sized (12 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with the sampler, which it
+// runs beside on a second stream.  Snapshot rows are padded to multiples of four floats.
 constexpr int kSnapTM = 64, kSnapTN = 128, kSnapKC = 16;
 
-__host__ __device__ int64_t cross_snap_tiles(int64_t M, int64_t N) {
-    return ((M + kSnapTM - 1) / kSnapTM) * ((N + 1 + kSnapTN - 1) / kSnapTN);
+__host__ __device__ int64_t cross_snap_tiles(int64_t Mx, int64_t N) {
+    return ((Mx + kSnapTM - 1) / kSnapTM) * ((N + 1 + kSnapTN - 1) / kSnapTN);
 }
 
-__global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int ksplit, int64_t nsnap,
-                                                    const float *snapA, const float *snapR, double *cross) {
+// The snapshot rows of group g in a launch of nsnap sweeps from sweep s0: sweeps j in
+// [j0, j1) of the launch and chains [c0, c1) (chain groups), or every chain of the sweeps of
+// batch g (batch means: sweep s - burnin in batch floor((s - burnin) G / sweeps)).
+struct GroupRows {
+    int64_t j0, j1, c0, c1;
+};
+
+__device__ __forceinline__ GroupRows group_rows(const ProbDesc &pd, int g, int64_t nsnap, int64_t s0,
+                                                int64_t burnin, int64_t sweeps) {
+    GroupRows r;
+    const int64_t G = pd.groups;
+    if (pd.batches > 1) {
+        const int64_t lo = burnin + (g * sweeps + G - 1) / G, hi = burnin + ((g + 1) * sweeps + G - 1) / G;
+        r.j0 = min(max(lo - s0, (int64_t)0), nsnap);
+        r.j1 = min(max(hi - s0, (int64_t)0), nsnap);
+        r.c0 = 0;
+        r.c1 = pd.C;
+    } else {
+        r.j0 = 0;
+        r.j1 = nsnap;
+        r.c0 = pd.C * g / G;
+        r.c1 = pd.C * (g + 1) / G;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int parts, int64_t nsnap,
+                                                    const float *snapA, const float *snapR,
+                                                    const int64_t *snap_first, int64_t burnin, int64_t sweeps,
+                                                    double *cross) {
     __shared__ __align__(16) float sr[kSnapKC * kSnapTM];
     __shared__ __align__(16) float sa[kSnapKC * kSnapTN];
     const ProbDesc pd = probs[blockIdx.z];
+    const int ksplit = pd.groups * parts;
     const int64_t M = pd.M, N = pd.N, N1 = N + 1;
+    const int64_t Mx = pd.rank_r > 0 ? pd.rank_r : M;   // rows of the cross moment
     const int64_t ldr = (M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
     const int64_t ntn = (N1 + kSnapTN - 1) / kSnapTN;
-    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so workgroup x runs on XCD
-    // x % 8; all tiles of one chain split then run on one XCD and read the split's snapshot
-    // rows through that XCD's L2 (ksplit is a multiple of 8)
+    // XCD-aware order when the splits come in multiples of 8: workgroups are dealt to the 8
+    // XCDs in turn, so workgroup x runs on XCD x % 8; all tiles of one split then run on one
+    // XCD and read the split's snapshot rows through that XCD's L2
     const int64_t maxt = gridDim.x / ksplit;
-    const int64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
-    const int split = (int)(xcd + 8 * (j / maxt));
-    const int64_t tile = j % maxt;
-    if (tile >= cross_snap_tiles(M, N)) return;
+    int split;
+    int64_t tile;
+    if (ksplit % 8 == 0) {
+        const int64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+        split = (int)(xcd + 8 * (j / maxt));
+        tile = j % maxt;
+    } else {
+        split = (int)(blockIdx.x / maxt);
+        tile = blockIdx.x % maxt;
+    }
+    if (tile >= cross_snap_tiles(Mx, N)) return;
+    const int g = split / parts, part = split % parts;
+    const GroupRows gr = group_rows(pd, g, nsnap, *snap_first, burnin, sweeps);
+    const int64_t nc = gr.c1 - gr.c0;
+    const int64_t K = (gr.j1 - gr.j0) * nc;
+    const int64_t k_lo = K * part / parts, k_hi = K * (part + 1) / parts;
+    auto row_of = [&](int64_t kp) { return (gr.j0 + kp / nc) * pd.C + gr.c0 + kp % nc; };
     const int64_t m0 = (tile / ntn) * kSnapTM, n0 = (tile % ntn) * kSnapTN;
-    const int64_t K = nsnap * pd.C;
-    const int64_t k_lo = K * split / ksplit, k_hi = K * (split + 1) / ksplit;
     const float *Rb = snapR + pd.off_sr;
     const float *Ab = snapA + pd.off_sa;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
@@ -220,18 +270,18 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-    // 16 x 16 sub-tiles entirely past M or N + 1 are skipped (wavefront-uniform)
+    // 16 x 16 sub-tiles entirely past Mx or N + 1 are skipped (wavefront-uniform)
     const int64_t mw = m0 + 32 * wm, nw = n0 + 64 * wn;
-    // one 16-byte word of r and two of A per thread and chunk, loaded a chunk ahead
+    // one 16-byte word of x and two of A per thread and chunk, loaded a chunk ahead
     const int rrow = tid / (kSnapTM / 4), rc4 = tid % (kSnapTM / 4);
     const int64_t rm = m0 + 4 * rc4;
     auto load_r = [&](int64_t c0, int64_t kc) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (rrow < kc && rm < ldr) v = *reinterpret_cast<const float4 *>(Rb + (c0 + rrow) * ldr + rm);
-        if (rm + 0 >= M) v.x = 0.f;
-        if (rm + 1 >= M) v.y = 0.f;
-        if (rm + 2 >= M) v.z = 0.f;
-        if (rm + 3 >= M) v.w = 0.f;
+        if (rrow < kc && rm < ldr) v = *reinterpret_cast<const float4 *>(Rb + row_of(c0 + rrow) * ldr + rm);
+        if (rm + 0 >= Mx) v.x = 0.f;
+        if (rm + 1 >= Mx) v.y = 0.f;
+        if (rm + 2 >= Mx) v.z = 0.f;
+        if (rm + 3 >= Mx) v.w = 0.f;
         return v;
     };
     auto load_a = [&](int64_t c0, int64_t kc, int h) {
@@ -240,7 +290,7 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
         const int64_t n = n0 + 4 * c4;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (row < kc) {
-            if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + (c0 + row) * lda + n);
+            if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + row_of(c0 + row) * lda + n);
             if (n + 0 >= N) v.x = (n + 0 == N) ? 1.f : 0.f;
             if (n + 1 >= N) v.y = (n + 1 == N) ? 1.f : 0.f;
             if (n + 2 >= N) v.z = (n + 2 == N) ? 1.f : 0.f;
@@ -248,8 +298,8 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
         }
         return v;
     };
-    float4 pr, pa0, pa1;
-    {
+    float4 pr = make_float4(0.f, 0.f, 0.f, 0.f), pa0 = pr, pa1 = pr;
+    if (k_lo < k_hi) {
         const int64_t kc = (k_hi - k_lo) < kSnapKC ? (k_hi - k_lo) : kSnapKC;
         pr = load_r(k_lo, kc);
         pa0 = load_a(k_lo, kc, 0);
@@ -257,7 +307,7 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
     }
     for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
         __syncthreads();   // the previous chunk is consumed
-        // r rows: kc x 64 (columns past M, rows past kc: 0); A rows with the column of ones
+        // x rows: kc x 64 (columns past Mx, rows past kc: 0); A rows with the column of ones
         // at n = N: kc x 128
         *reinterpret_cast<float4 *>(sr + rrow * kSnapTM + 4 * rc4) = pr;
 #pragma unroll
@@ -286,11 +336,11 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    if (mw + 16 * a < M && nw + 16 * b < N1)
+                    if (mw + 16 * a < Mx && nw + 16 * b < N1)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
         }
     }
-    double *X = cross + pd.off_cross + (int64_t)split * M * N1;
+    double *X = cross + pd.off_cross + (int64_t)split * Mx * N1;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -299,15 +349,182 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int k
             for (int j = 0; j < 4; ++j) {
                 const int64_t row = m0 + 32 * wm + 16 * a + lane / 16 + 4 * j;
                 const int64_t col = n0 + 64 * wn + 16 * b + lane % 16;
-                if (row < M && col < N1) X[row * N1 + col] += acc[a][b][j];
+                if (row < Mx && col < N1) X[row * N1 + col] += acc[a][b][j];
             }
 }
 
-hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int ksplit, int64_t nsnap,
-                             const float *snapA, const float *snapR, double *cross, hipStream_t s) {
-    if (ksplit % 8 != 0) return hipErrorInvalidValue;
+hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles, int groups, int parts,
+                             int64_t nsnap, const float *snapA, const float *snapR, const int64_t *snap_first,
+                             int64_t burnin, int64_t sweeps, double *cross, hipStream_t s) {
+    const int64_t ksplit = (int64_t)groups * parts;
     hipLaunchKernelGGL(k_cross_snap, dim3((unsigned)(max_tiles * ksplit), 1, (unsigned)P), dim3(256), 0, s,
-                       probs_dev, ksplit, nsnap, snapA, snapR, cross);
+                       probs_dev, parts, nsnap, snapA, snapR, snap_first, burnin, sweeps, cross);
+    return hipGetLastError();
+}
+
+// y = Q^T r in place in the residual snapshot rows of a launch (problems with a range basis,
+// rank_r > 0): a workgroup of 4 wavefronts takes 16 rows; wavefront w forms the 16-column
+// tiles w and w + 4 of y (rank_r <= 128) by MFMA f64 16x16x4 over the M entries, and the rows
+// are overwritten only after every wavefront has read them.
+__global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t nsnap, const double *Q,
+                                                 float *snapR) {
+    const ProbDesc pd = probs[blockIdx.y];
+    if (pd.rank_r <= 0) return;
+    const int64_t M = pd.M, R = pd.rank_r, rows = nsnap * pd.C;
+    const int64_t ldr = (M + 3) / 4 * 4;
+    const int64_t k0 = (int64_t)blockIdx.x * 16;
+    if (k0 >= rows) return;
+    float *Rb = snapR + pd.off_sr;
+    const double *Qp = Q + pd.off_q;   // column j at Qp + j M
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int i = lane % 16, kk = lane / 16;
+    const int64_t ka = k0 + i;
+    const bool oka = ka < rows;
+    d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+    for (int h = 0; h < 2; ++h) {
+        const int64_t jt = 16 * (wave + 4 * h);
+        if (jt >= R) break;
+        const int64_t jb = jt + i;
+        const bool okb = jb < R;
+        for (int64_t m = 0; m < M; m += 4) {
+            const int64_t mm = m + kk;
+            const double a = (oka && mm < M) ? (double)Rb[ka * ldr + mm] : 0.0;
+            const double b = (okb && mm < M) ? Qp[jb * M + mm] : 0.0;
+            acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[h], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // every wavefront has read the 16 rows
+    for (int h = 0; h < 2; ++h) {
+        const int64_t jt = 16 * (wave + 4 * h);
+        if (jt >= R) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t row = k0 + lane / 16 + 4 * j, col = jt + lane % 16;
+            if (row < rows && col < R) Rb[row * ldr + col] = (float)acc[h][j];
+        }
+    }
+}
+
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *Q,
+                          float *snapR, hipStream_t s) {
+    if (max_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + 15) / 16), (unsigned)P), dim3(256), 0, s, probs_dev,
+                       nsnap, Q, snapR);
+    return hipGetLastError();
+}
+
+// Orthonormal basis Q of the range of K~ to a relative 1e-10, for the compressed cross moments
+// of the VJP: Cov(r~, A) = -K~ Cov(A, A) lies in range(K~) = the span of the blocks' columns
+// d_i U_i (their data modes, Sec. IV.B-C; what a block's rank cut drops is below the rounding
+// of K~).  Pivoted modified Gram-Schmidt: the column with the largest remaining norm becomes
+// the next direction, reorthogonalised once against the directions found, and is projected
+// out of every column; it stops when the largest remaining norm falls below 1e-10 of the
+// first, or at max_r directions (then rank 0: the problem keeps its uncompressed moments).
+// One workgroup per problem; the columns live in `work`.
+__global__ __launch_bounds__(1024) void k_range_basis(const ProbDesc *probs, const int64_t *col_first,
+                                                      const int64_t *colU, const int64_t *colD, const double *U64,
+                                                      const double *d64, const int64_t *work_off, double *work,
+                                                      double *Q, int32_t *rank_out, int max_r) {
+    extern __shared__ double rb_sm[];   // q (M), then reduction scratch
+    const int p = blockIdx.x;
+    const ProbDesc pd = probs[p];
+    const int64_t M = pd.M;
+    const int64_t cf = col_first[p], K = col_first[p + 1] - cf;
+    double *W = work + work_off[p];
+    double *Qp = Q + pd.off_q;
+    double *q = rb_sm;
+    double *red = rb_sm + M;            // blockDim.x values
+    int *redi = reinterpret_cast<int *>(red + blockDim.x);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int64_t e = tid; e < K * M; e += nt) {
+        const int64_t c = e / M, m = e % M;
+        W[e] = d64[colD[cf + c]] * U64[colU[cf + c] + m];
+    }
+    __syncthreads();
+    double first = -1.0;
+    int R = 0;
+    for (;;) {
+        // the column of largest remaining norm
+        double best = -1.0;
+        int bi = -1;
+        for (int64_t c = tid; c < K; c += nt) {
+            double s2 = 0.0;
+            for (int64_t m = 0; m < M; ++m) s2 = fma(W[c * M + m], W[c * M + m], s2);
+            if (s2 > best) {
+                best = s2;
+                bi = (int)c;
+            }
+        }
+        red[tid] = best;
+        redi[tid] = bi;
+        __syncthreads();
+        for (int o = nt / 2; o > 0; o >>= 1) {
+            if (tid < o && (red[tid + o] > red[tid] || (red[tid + o] == red[tid] && redi[tid + o] >= 0 &&
+                                                       (redi[tid] < 0 || redi[tid + o] < redi[tid])))) {
+                red[tid] = red[tid + o];
+                redi[tid] = redi[tid + o];
+            }
+            __syncthreads();
+        }
+        const double bn2 = red[0];
+        const int jb = redi[0];
+        __syncthreads();
+        if (first < 0.0) first = bn2;
+        if (jb < 0 || !(bn2 > 1e-20 * first) || R >= (int)M) break;
+        if (R >= max_r) {
+            R = 0;   // too many directions for the compressed form
+            break;
+        }
+        const double inv = 1.0 / sqrt(bn2);
+        for (int64_t m = tid; m < M; m += nt) q[m] = W[(int64_t)jb * M + m] * inv;
+        __syncthreads();
+        // reorthogonalise against the directions found: q -= Q (Q^T q), then normalise
+        for (int k = tid; k < R; k += nt) {
+            double dq = 0.0;
+            for (int64_t m = 0; m < M; ++m) dq = fma(Qp[(int64_t)k * M + m], q[m], dq);
+            red[k] = dq;
+        }
+        __syncthreads();
+        for (int64_t m = tid; m < M; m += nt) {
+            double x = q[m];
+            for (int k = 0; k < R; ++k) x = fma(-red[k], Qp[(int64_t)k * M + m], x);
+            q[m] = x;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int64_t m = tid; m < M; m += nt) part = fma(q[m], q[m], part);
+        red[tid] = part;
+        __syncthreads();
+        for (int o = nt / 2; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        const double qn = 1.0 / sqrt(red[0]);
+        __syncthreads();
+        for (int64_t m = tid; m < M; m += nt) {
+            q[m] *= qn;
+            Qp[(int64_t)R * M + m] = q[m];
+        }
+        __syncthreads();
+        // remove the direction from every column
+        for (int64_t c = tid; c < K; c += nt) {
+            double dq = 0.0;
+            for (int64_t m = 0; m < M; ++m) dq = fma(q[m], W[c * M + m], dq);
+            for (int64_t m = 0; m < M; ++m) W[c * M + m] = fma(-dq, q[m], W[c * M + m]);
+        }
+        __syncthreads();
+        ++R;
+    }
+    if (tid == 0) rank_out[p] = R;
+}
+
+hipError_t launch_range_basis(const ProbDesc *probs_dev, int64_t P, int64_t max_m, const int64_t *col_first,
+                              const int64_t *colU, const int64_t *colD, const double *U64, const double *d64,
+                              const int64_t *work_off, double *work, double *Q, int32_t *rank_out, int max_r,
+                              hipStream_t s) {
+    const size_t lds = (size_t)max_m * sizeof(double) + 1024 * (sizeof(double) + sizeof(int));
+    hipLaunchKernelGGL(k_range_basis, dim3((unsigned)P), dim3(1024), lds, s, probs_dev, col_first, colU, colD, U64,
+                       d64, work_off, work, Q, rank_out, max_r);
     return hipGetLastError();
 }
 
@@ -316,7 +533,7 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
 __global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_prefix,
                            const double *accA, const double *accA2, const int32_t *slot_group,
                            const double *slot_count, double *mean, double *stderr_,
-                           double *post_sd) {
+                           double *post_sd, double *gmean) {
     const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gi >= n_prefix[P]) return;
     int64_t lo = 0, hi = P - 1;   // problem p with n_prefix[p] <= gi < n_prefix[p+1]
@@ -358,6 +575,10 @@ __global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_pr
             v += d * d;
         }
     const double se = ng > 1 ? sqrt(v / (double)(ng - 1) / (double)ng) : NAN;
+    if (gmean) {   // the group means, groups x (sum N), NaN for a group without samples
+        const int64_t tn = n_prefix[P];
+        for (int g = 0; g < G; ++g) gmean[g * tn + pd.off_n + n] = gc[g] > 0.0 ? gs[g] / gc[g] : NAN;
+    }
     const double var = tot > 0.0 ? s2 / tot - mu * mu : 0.0;
     mean[pd.off_n + n] = mu;
     stderr_[pd.off_n + n] = se;
@@ -367,22 +588,161 @@ __global__ void k_finalize(const ProbDesc *probs, int64_t P, const int64_t *n_pr
 hipError_t launch_finalize(const ProbDesc *probs_dev, int64_t P, const int64_t *n_prefix_dev,
                            int64_t total_n, const double *accA, const double *accA2,
                            const int32_t *slot_group, const double *slot_count, double *mean,
-                           double *stderr_, double *post_sd, hipStream_t s) {
+                           double *stderr_, double *post_sd, double *gmean, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((total_n + 127) / 128)), dim3(128), 0, s,
                        probs_dev, P, n_prefix_dev, accA, accA2, slot_group, slot_count, mean,
-                       stderr_, post_sd);
+                       stderr_, post_sd, gmean);
     return hipGetLastError();
 }
 
-// y_m = (1/S) sum_n X[m][n] v_n - rbar_m (Abar . v) with X summed over the splits and
-// rbar_m = X[m][N] / S; then grad = -T^T y: -y/sigma for iid noise, or -L^-T y for a
-// covariance C = L L^T.
-__global__ __launch_bounds__(256) void k_vjp_y(const ProbDesc *probs, int64_t P, const int64_t *m_prefix,
-                                               int ksplit, const double *cross, const double *mean,
-                                               const double *nsamples, const double *sigma, const double *v,
-                                               double *y, double *grad) {
-    // one workgroup per data point m (over all problems); threads over n
-    const int64_t gi = blockIdx.x;
+// The VJP J^T v = -T^T Cov(r~, A) v (Sec. II: Eq. (PI) differentiated in the data; T the
+// whitening), per chain group from the group's own moments and pooled over all samples; its
+// error bar is the standard deviation of the group values over sqrt(G).  With a range basis
+// (rank_r > 0) the moments are of y = Q^T r and Cov(r~, A) = Q Cov(y, A).
+// Scratch per plan (total_m = sum of M over the problems, index g * total_m + off_m + i):
+//   XV[g][i] = sum_parts sum_n X[i][n] v_n,  XS[g][i] = sum_parts X[i][N]   (G groups)
+//   Z[g][i] (G + 1 rows: the groups, then the pooled value), GR[g][m] the same after -T^T Q
+//   AV[p G + g] = (sum of A over group g) . v,  NG[p G + g] = samples of group g
+
+// one workgroup per (row i of the moments, group g, problem)
+__global__ __launch_bounds__(256) void k_vjp_rows(const ProbDesc *probs, int64_t total_m, int parts,
+                                                  const double *cross, const double *v, double *XV, double *XS) {
+    const ProbDesc pd = probs[blockIdx.z];
+    const int64_t Mx = pd.rank_r > 0 ? pd.rank_r : pd.M;
+    const int64_t i = blockIdx.x;
+    if (i >= Mx) return;
+    const int g = blockIdx.y;
+    if (g >= pd.groups) return;
+    const int64_t N = pd.N, N1 = N + 1;
+    const double *vv = v + pd.off_n;
+    double xv = 0.0, xs = 0.0;
+    for (int part = 0; part < parts; ++part) {
+        const double *X = cross + pd.off_cross + ((int64_t)(g * parts + part) * Mx + i) * N1;
+        for (int64_t n = threadIdx.x; n < N; n += blockDim.x) xv = fma(X[n], vv[n], xv);
+        if (threadIdx.x == 0) xs += X[N];
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = xv;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        XV[g * total_m + pd.off_m + i] = red[0];
+        XS[g * total_m + pd.off_m + i] = xs;
+    }
+}
+
+// one workgroup per (group, problem): the group's sum of A dotted with v, and its samples
+__global__ __launch_bounds__(256) void k_vjp_group_av(const ProbDesc *probs, const double *accA,
+                                                      const int32_t *slot_group, const double *slot_count,
+                                                      const double *v, double *AV, double *NG) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int g = blockIdx.x;
+    if (g >= pd.groups) return;
+    const int64_t N = pd.N;
+    const double *vv = v + pd.off_n;
+    double av = 0.0, ng = 0.0;
+    for (int64_t sl = 0; sl < pd.nslot; ++sl) {
+        if (slot_group[pd.off_tab + sl] != g) continue;
+        ng += slot_count[pd.off_tab + sl];
+        const double *a = accA + pd.off_slot + sl * N;
+        for (int64_t n = threadIdx.x; n < N; n += blockDim.x) av = fma(a[n], vv[n], av);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = av;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        AV[blockIdx.y * (int64_t)pd.groups + g] = red[0];
+        NG[blockIdx.y * (int64_t)pd.groups + g] = ng;
+    }
+}
+
+// one thread per moment row over all problems: the centred moments z_g = XV_g / n_g -
+// (XS_g / n_g)(AV_g / n_g) of each group and the pooled one (row G)
+__global__ void k_vjp_z(const ProbDesc *probs, int64_t P, const int64_t *m_prefix, int64_t total_m,
+                        const double *XV, const double *XS, const double *AV, const double *NG, double *Z) {
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gi >= m_prefix[P]) return;
+    int64_t lo = 0, hi = P - 1;   // problem p with m_prefix[p] <= gi < m_prefix[p+1]
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (m_prefix[mid] <= gi) lo = mid; else hi = mid - 1;
+    }
+    const ProbDesc pd = probs[lo];
+    const int64_t i = gi - m_prefix[lo];
+    const int64_t Mx = pd.rank_r > 0 ? pd.rank_r : pd.M;
+    const int G = pd.groups;
+    if (i >= Mx) {
+        for (int g = 0; g <= G; ++g) Z[g * total_m + gi] = 0.0;
+        return;
+    }
+    double sxv = 0.0, sxs = 0.0, sav = 0.0, sn = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const double n = NG[lo * (int64_t)G + g];
+        const double xv = XV[g * total_m + gi], xs = XS[g * total_m + gi], av = AV[lo * (int64_t)G + g];
+        Z[g * total_m + gi] = n > 0.0 ? xv / n - (xs / n) * (av / n) : 0.0;
+        sxv += xv;
+        sxs += xs;
+        sav += av;
+        sn += n;
+    }
+    Z[G * total_m + gi] = sn > 0.0 ? sxv / sn - (sxs / sn) * (sav / sn) : 0.0;
+}
+
+// one workgroup per (row g of Z, problem): y = Q z (or z), then GR = -T^T y: -y / sigma for
+// iid noise, or -L^-T y (back substitution) for a covariance C = L L^T
+__global__ __launch_bounds__(256) void k_vjp_map(const ProbDesc *probs, int64_t total_m, const double *Q,
+                                                 const double *sigma, const double *Lchol, const double *Z,
+                                                 double *GR) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int g = blockIdx.x;
+    if (g > pd.groups) return;
+    const int64_t M = pd.M, R = pd.rank_r;
+    const double *z = Z + g * total_m + pd.off_m;
+    double *y = GR + g * total_m + pd.off_m;
+    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
+        double x = 0.0;
+        if (R > 0) {
+            for (int64_t k = 0; k < R; ++k) x = fma(Q[pd.off_q + k * M + m], z[k], x);
+        } else {
+            x = z[m];
+        }
+        y[m] = x;
+    }
+    __syncthreads();
+    if (!pd.has_cov) {
+        for (int64_t m = threadIdx.x; m < M; m += blockDim.x) y[m] = -y[m] / sigma[pd.off_m + m];
+        return;
+    }
+    // L^T x = y, in place from the last row up
+    const double *L = Lchol + pd.off_L;
+    __shared__ double red[256];
+    for (int64_t i = M - 1; i >= 0; --i) {
+        double part = 0.0;
+        for (int64_t k = i + 1 + threadIdx.x; k < M; k += blockDim.x) part += L[k * M + i] * y[k];
+        red[threadIdx.x] = part;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) y[i] = (y[i] - red[0]) / L[i * M + i];
+        __syncthreads();
+    }
+    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) y[m] = -y[m];
+}
+
+// one thread per data point: the pooled J^T v and the standard deviation of the group values
+// over sqrt(G) (groups with samples only)
+__global__ void k_vjp_out(const ProbDesc *probs, int64_t P, const int64_t *m_prefix, int64_t total_m,
+                          const double *GR, const double *NG, double *grad, double *grad_se) {
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gi >= m_prefix[P]) return;
     int64_t lo = 0, hi = P - 1;
     while (lo < hi) {
@@ -390,73 +750,54 @@ __global__ __launch_bounds__(256) void k_vjp_y(const ProbDesc *probs, int64_t P,
         if (m_prefix[mid] <= gi) lo = mid; else hi = mid - 1;
     }
     const ProbDesc pd = probs[lo];
-    const int64_t m = gi - m_prefix[lo];
-    const int64_t N = pd.N, N1 = N + 1, M = pd.M;
-    const double S = nsamples[lo];
-    const double *vv = v + pd.off_n;
-    const double *mu = mean + pd.off_n;
-    double xv = 0.0, av = 0.0, rs = 0.0;
-    for (int64_t n = threadIdx.x; n <= N; n += blockDim.x) {
-        double x = 0.0;
-        for (int k = 0; k < ksplit; ++k) x += cross[pd.off_cross + (int64_t)k * M * N1 + m * N1 + n];
-        if (n < N) {
-            xv += x * vv[n];
-            av += mu[n] * vv[n];
-        } else {
-            rs = x;
+    const int G = pd.groups;
+    grad[gi] = GR[G * total_m + gi];
+    if (!grad_se) return;
+    double s = 0.0;
+    int ng = 0;
+    for (int g = 0; g < G; ++g)
+        if (NG[lo * (int64_t)G + g] > 0.0) {
+            s += GR[g * total_m + gi];
+            ++ng;
         }
-    }
-    __shared__ double red[3][256];
-    red[0][threadIdx.x] = xv;
-    red[1][threadIdx.x] = av;
-    red[2][threadIdx.x] = rs;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w /= 2) {
-        if ((int)threadIdx.x < w)
-            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double ym = red[0][0] / S - (red[2][0] / S) * red[1][0];
-        y[pd.off_m + m] = ym;
-        if (!pd.has_cov) grad[pd.off_m + m] = -ym / sigma[pd.off_m + m];
-    }
+    const double mu = ng > 0 ? s / ng : 0.0;
+    double v = 0.0;
+    for (int g = 0; g < G; ++g)
+        if (NG[lo * (int64_t)G + g] > 0.0) {
+            const double d = GR[g * total_m + gi] - mu;
+            v += d * d;
+        }
+    grad_se[gi] = ng > 1 ? sqrt(v / (double)(ng - 1) / (double)ng) : NAN;
 }
 
-// x = L^-T y (back substitution), grad = -x; one workgroup per problem with a covariance.
-__global__ __launch_bounds__(256) void k_vjp_cov(const ProbDesc *probs, const double *Lchol,
-                                                 const double *y, double *grad) {
-    const ProbDesc pd = probs[blockIdx.x];
-    if (!pd.has_cov) return;
-    const int64_t M = pd.M;
-    const double *L = Lchol + pd.off_L;
-    double *x = grad + pd.off_m;   // holds x during the solve, negated at the end
-    __shared__ double red[256];
-    for (int64_t i = M - 1; i >= 0; --i) {
-        double part = 0.0;
-        for (int64_t k = i + 1 + threadIdx.x; k < M; k += blockDim.x) part += L[k * M + i] * x[k];
-        red[threadIdx.x] = part;
-        __syncthreads();
-        for (int o = 128; o >= 1; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) x[i] = (y[pd.off_m + i] - red[0]) / L[i * M + i];
-        __syncthreads();
-    }
-    for (int64_t i = threadIdx.x; i < M; i += blockDim.x) x[i] = -x[i];
-}
-
-hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev,
-                      int64_t total_m, int ksplit, const double *cross, const double *mean,
-                      const double *nsamples, const double *sigma, const double *Lchol,
-                      const double *v, double *y, double *grad, int any_cov, hipStream_t s) {
-    hipLaunchKernelGGL(k_vjp_y, dim3((unsigned)total_m), dim3(256), 0, s, probs_dev,
-                       P, m_prefix_dev, ksplit, cross, mean, nsamples, sigma, v, y, grad);
+hipError_t launch_vjp(const ProbDesc *probs_dev, int64_t P, const int64_t *m_prefix_dev, int64_t total_m,
+                      int64_t max_m, int groups, int parts, const double *cross, const double *accA,
+                      const int32_t *slot_group, const double *slot_count, const double *Q, const double *sigma,
+                      const double *Lchol, const double *v, double *scratch, double *grad, double *grad_se,
+                      hipStream_t s) {
+    const int64_t G = groups;
+    double *XV = scratch, *XS = XV + G * total_m, *Z = XS + G * total_m, *GR = Z + (G + 1) * total_m;
+    double *AV = GR + (G + 1) * total_m, *NG = AV + P * G;
+    hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)max_m, (unsigned)G, (unsigned)P), dim3(256), 0, s, probs_dev,
+                       total_m, parts, cross, v, XV, XS);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !any_cov) return e;
-    hipLaunchKernelGGL(k_vjp_cov, dim3((unsigned)P), dim3(256), 0, s, probs_dev, Lchol, y, grad);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vjp_group_av, dim3((unsigned)G, (unsigned)P), dim3(256), 0, s, probs_dev, accA, slot_group,
+                       slot_count, v, AV, NG);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vjp_z, dim3((unsigned)((total_m + 127) / 128)), dim3(128), 0, s, probs_dev, P, m_prefix_dev,
+                       total_m, XV, XS, AV, NG, Z);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vjp_map, dim3((unsigned)(G + 1), (unsigned)P), dim3(256), 0, s, probs_dev, total_m, Q,
+                       sigma, Lchol, Z, GR);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vjp_out, dim3((unsigned)((total_m + 127) / 128)), dim3(128), 0, s, probs_dev, P,
+                       m_prefix_dev, total_m, GR, NG, grad, grad_se);
     return hipGetLastError();
+}
+
+int64_t vjp_scratch_doubles(int64_t P, int64_t total_m, int groups) {
+    return (2 * (int64_t)groups + 2 * ((int64_t)groups + 1)) * total_m + 2 * P * groups;
 }
 
 // float64 copy of one problem's chain state

@@ -7,7 +7,7 @@ Sec. IV.C) and its standard error over independent chain groups, for a fixed pro
 The config-2 reference starts from the NNLS start of Sec. IV.D, so that both sides average
 over the equilibrated chain rather than over the slow relaxation from a flat start.
 
-    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3] [cfg5]
+    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3] [cfg4] [cfg5]
 
 The config-5 reference (401 correlated data points whitened by their Cholesky factor, 4000
 grid points in 32 blocks, Sec. IV and Sec. IV.C) takes about half an hour on 8 cores.
@@ -36,6 +36,10 @@ PROTOCOLS = {
                  refresh_every=64, start="nnls"),
     "cfg5": dict(problem="config5", chains=256, burnin=1000, sweeps=5000, seed=15, groups=32,
                  refresh_every=64, start="nnls"),
+    # the differentiation workload: the config-2 problem with its seeded cotangent v; J^T v
+    # (Sec. II, Eq. (PI) differentiated in the data) and its error bar over the chain groups
+    "cfg4": dict(problem="config2", chains=512, burnin=500, sweeps=2000, seed=14, groups=32,
+                 refresh_every=64, start="nnls", vjp="config4_cotangent"),
 }
 # three uneven datasets of the batched workload (N = 396, 670, 407 in 4, 7, 4 blocks); 256
 # chains, so that the reference error bars are half those of a 64-chain run
@@ -52,13 +56,15 @@ def make(name):
     prep = oracle.prepare(prob)
     t = time.time()
     init = oracle.nnls_start(prep) if proto.get("start") == "nnls" else None
+    v = getattr(workloads, proto["vjp"])(prep.N) if "vjp" in proto else None
     res = oracle.run(prep, chains=proto["chains"], burnin=proto["burnin"], sweeps=proto["sweeps"],
                      seed=proto["seed"], groups=proto["groups"], refresh_every=proto["refresh_every"],
-                     init=init, threads=THREADS)
+                     init=init, threads=THREADS, vjp_v=v)
     dt = time.time() - t
     out = os.path.join(HERE, f"{name}_oracle.npz")
+    extra = {} if v is None else dict(v=v, vjp=res.vjp, vjp_se=res.vjp_se)
     np.savez_compressed(out, mean=res.mean, stderr=res.stderr, post_sd=res.post_sd,
-                        kb=prep.kb, chi2_final=res.final_chi2)
+                        kb=prep.kb, chi2_final=res.final_chi2, **extra)
     meta = dict(proto, seconds=round(dt, 1), status=res.status, drift_max=res.drift_max,
                 what="oracle <A> and standard error over chain groups (Eq. (MCint), Sec. IV.C)")
     with open(os.path.join(HERE, f"{name}_oracle.json"), "w") as f:

@@ -197,6 +197,28 @@ def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
     assert np.allclose(res.post_sd.cpu().numpy(), A.std(0), rtol=1e-6, atol=1e-12 * np.max(A))
 
 
+def test_batched_fp32_config5_average_matches_oracle(pk):
+    """The large workload at its full size: 401 correlated data points whitened by their
+    Cholesky factor, 4000 grid points in 32 blocks of 125, 16384 float32 chains, 1000 + 5000
+    sweeps from the NNLS start, refresh every 64 sweeps (a hipGraph per cycle), against the
+    stored 256-chain float64 oracle run of the same protocol (4000 strongly correlated
+    points: the bounds of correlated spectra)."""
+    z, meta = _golden("cfg5")
+    p = workloads.config5()
+    plan = pk.Plan([p], chains=16384, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=meta["seed"] + 1000,
+                   precision="fp32", groups=meta["groups"], refresh_every=meta["refresh_every"],
+                   start=meta["start"], use_graph=True)
+    res = plan.run()
+    m, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
+    ok, info = zscore_ok(m, se, z["mean"], z["stderr"], **CORRELATED)
+    print("config 5: max |d<A>| / max <A> = %.3g, (max z, n > 3, n, mean z^2) =" %
+          (np.max(np.abs(m - z["mean"])) / np.max(z["mean"])), info, "lanes", res.stats["lanes_per_chain"],
+          "roles", res.stats["roles"], "sampler ms", res.stats["sampler_ms"])
+    assert ok, info
+    assert res.stats["graph_replays"] > 0 and res.stats["chi2_drift_max"] < 1e-2
+    plan.close()
+
+
 def test_nnls_start_matches_scipy(pk, orc):
     for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
         prep = orc.prepare(p)
@@ -278,6 +300,8 @@ def test_batched_problems_are_independent(pk):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_vjp_gaussian_limit_closed_form(pk, orc, precision):
+    """Positivity inactive: J = Cov K~^T T in closed form; every entry of J^T v within its error
+    bar (over the chain groups) of the closed form."""
     p = workloads.gaussian_limit_problem()
     prep = orc.prepare(p)
     Kt = prep.Kt
@@ -290,24 +314,109 @@ def test_vjp_gaussian_limit_closed_form(pk, orc, precision):
     mean = cov @ Kt.T @ prep.gt
     ok, info = zscore_ok(res.mean.cpu().numpy(), res.stderr.cpu().numpy(), mean, 0 * mean)
     assert ok, info
-    g = plan.vjp(v).cpu().numpy()
+    g, se = plan.vjp(v, stderr=True)
+    g, se = g.cpu().numpy(), se.cpu().numpy()
     ref = J.T @ v
+    ok, info = zscore_ok(g, se, ref, 0 * ref)
+    assert ok, info
     assert np.linalg.norm(g - ref) < 0.02 * np.linalg.norm(ref)
     plan.close()
 
 
-def test_vjp_fp32_matches_oracle_covariance(pk, orc):
+def test_vjp_fp32_matches_oracle_elementwise_small(pk, orc):
+    """A small problem with positivity active: the float32 J^T v against the float64 oracle's,
+    point by point within the combined error bars (reading R17)."""
     p = workloads.small_problem(M=21, N=12, nblocks=2, sigma=1e-2, seed=31)
     prep = orc.prepare(p)
     v = np.random.default_rng(7).standard_normal(p.N)
-    ores = orc.run(prep, chains=256, burnin=300, sweeps=4000, groups=32, want_cross=True, seed=1)
-    ref = orc.vjp(ores, v)
+    ores = orc.run(prep, chains=256, burnin=300, sweeps=4000, groups=32, vjp_v=v, seed=1)
     plan = pk.Plan([p], chains=1024, burnin=300, sweeps=4000, precision="fp32", groups=32,
                    want_vjp=True, seed=2)
     plan.run()
-    g = plan.vjp(v).cpu().numpy()
-    assert np.linalg.norm(g - ref) < 0.1 * np.linalg.norm(ref), (g, ref)
+    g, se = plan.vjp(v, stderr=True)
+    ok, info = zscore_ok(g.cpu().numpy(), se.cpu().numpy(), ores.vjp, ores.vjp_se)
+    assert ok, info
     plan.close()
+
+
+def test_vjp_config4_matches_oracle_elementwise(pk):
+    """The differentiation workload (the config-2 problem, 201 data points, with its seeded
+    cotangent): the float32 two-role plan's J^T v, its moments taken in the range basis of K~,
+    against the stored 512-chain float64 oracle value, point by point within the combined
+    error bars (the 201 entries are a smooth, strongly correlated function of tau: the bounds
+    of correlated spectra)."""
+    z, meta = _golden("cfg4")
+    p = workloads.config2()
+    plan = pk.Plan([p], chains=4096, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=meta["seed"] + 1000,
+                   precision="fp32", groups=meta["groups"], refresh_every=meta["refresh_every"],
+                   start=meta["start"], want_vjp=True)
+    res = plan.run()
+    assert res.stats["roles"] == 2
+    g, se = plan.vjp(z["v"], stderr=True)
+    g, se = g.cpu().numpy(), se.cpu().numpy()
+    ok, info = zscore_ok(g, se, z["vjp"], z["vjp_se"], **CORRELATED)
+    print("max |d(J^T v)| / max |J^T v| = %.3g, (max z, n > 3, n, mean z^2) =" %
+          (np.max(np.abs(g - z["vjp"])) / np.max(np.abs(z["vjp"]))), info)
+    assert ok, info
+    plan.close()
+
+
+def test_average_spectrum_autograd_matches_plan_vjp(pk):
+    """AverageSpectrum.apply(G, factory) returns (<A>, error bars); backward of v . <A> gives
+    the same J^T v, bit for bit, as a plan built and run with the same arguments."""
+    import torch
+    p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
+    kw = dict(chains=256, burnin=100, sweeps=400, seed=5, precision="fp32", groups=32, want_vjp=True)
+
+    def factory(G):
+        q = workloads.Problem(K=p.K, G=G.cpu().numpy(), sigma=p.sigma, block_start=p.block_start)
+        return pk.Plan([q], **kw)
+
+    G = torch.tensor(p.G, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    mean, se = pk.AverageSpectrum.apply(G, factory)
+    v = torch.linspace(-1.0, 1.0, p.N, dtype=torch.float64, device="cuda:0")
+    (mean * v).sum().backward()
+    ref_plan = factory(G.detach())
+    ref = ref_plan.run()
+    gref = ref_plan.vjp(v)
+    assert torch.equal(mean, ref.mean) and torch.equal(se, ref.stderr)
+    assert torch.equal(G.grad, gref)
+    ref_plan.close()
+
+
+def test_vjp_config2_fp64_against_common_random_number_differences(pk):
+    """The config-2 problem, float64 sampler: for 4 unit directions u of the data,
+    v . (<A>(G + h u) - <A>(G - h u)) / 2h with h = 1e-3 sigma and the same random numbers on
+    both sides, against (J^T v) . u, within 3 combined error bars (each side's from the chain
+    groups: the group averages of the differences, and the VJP's own error bars).  The chains
+    of this problem's null-space moves decorrelate within about a hundred sweeps, so the
+    difference quotient carries the error bars of two independent runs."""
+    p = workloads.config2()
+    v = workloads.config4_cotangent(p.N)
+    rng = np.random.default_rng(44)
+    kw = dict(chains=256, burnin=200, sweeps=600, groups=32, seed=2026, precision="fp64",
+              refresh_every=64, start="nnls")
+    base = pk.Plan([p], want_vjp=True, **kw)
+    base.run()
+    jv, jse = base.vjp(v, stderr=True)
+    jv, jse = jv.cpu().numpy(), jse.cpu().numpy()
+    base.close()
+    h = 1e-3 * float(p.sigma[0])
+    for k in range(4):
+        u = rng.standard_normal(p.M)
+        u /= np.linalg.norm(u)
+        gm = []
+        for sgn in (+1, -1):
+            q = workloads.Problem(K=p.K, G=p.G + sgn * h * u, sigma=p.sigma, block_start=p.block_start,
+                                  k=p.k)
+            pl = pk.Plan([q], **kw)
+            pl.run()
+            gm.append(pl.group_means().cpu().numpy() @ v)
+            pl.close()
+        fd_g = (gm[0] - gm[1]) / (2 * h)
+        fd, fd_se = fd_g.mean(), fd_g.std(ddof=1) / np.sqrt(len(fd_g))
+        ju, ju_se = float(jv @ u), float(np.abs(u) @ jse)   # the latter bounds the error bar
+        assert abs(fd - ju) < 3.0 * np.hypot(fd_se, ju_se), (k, fd, fd_se, ju, ju_se)
 
 
 # --------------------------------------------------------------------------------------
