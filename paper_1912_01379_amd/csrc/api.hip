@@ -64,6 +64,7 @@ struct asm_plan {
     int parts = 1;           // cross-moment partial sums per chain group (splits = groups x parts)
     int64_t cross_words = 0;
     double *Qb = nullptr;     // range bases of the problems' K~ (float32 plans with want_vjp)
+    double *WY = nullptr;     // [Q^T K~ | Q^T g~] (or [K~ | g~]) per problem: snapshot residuals
     bool any_rank = false;    // a problem whose moments are taken in its range basis
     double *vjp_scratch = nullptr;
     // float32 plans: per-sweep snapshots of A (and of r with want_vjp) of the accumulated
@@ -395,7 +396,6 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
     SampleArgs a = make_args(pl);
     if (snap) {
         a.snapA = pl->snapA[par];
-        a.snapR = pl->snapR[par];
         a.snap_rows = pl->snap_rows;
         a.snap_first = pl->snap_first + par;
     }
@@ -450,8 +450,8 @@ int snap_acquire(asm_plan *pl, int par) {
 int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
     HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
     HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    if (pl->any_rank)
-        HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, nsnap, pl->Qb, pl->snapR[par], pl->xstream));
+    HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, nsnap, pl->WY, pl->snapA[par],
+                          pl->snapR[par], pl->xstream));
     HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, (int)pl->opt.groups, pl->parts, nsnap,
                              pl->snapA[par], pl->snapR[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps,
                              pl->cross, pl->xstream));
@@ -1165,9 +1165,26 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 HSTEP(hipFree(q));
             }
             pl->max_snap_tiles = 0;
-            for (auto &pd : pl->probs)
-                pl->max_snap_tiles = std::max(pl->max_snap_tiles,
-                                              cross_snap_tiles(pd.rank_r > 0 ? pd.rank_r : pd.M, pd.N));
+            int64_t wy = 0, maxe = 0;
+            for (auto &pd : pl->probs) {
+                const int64_t Mx = pd.rank_r > 0 ? pd.rank_r : pd.M;
+                pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(Mx, pd.N));
+                pd.off_w = wy;
+                wy += Mx * (pd.N + 1);
+                maxe = std::max(maxe, Mx * (pd.N + 1));
+            }
+            // the maps from a sampled state to its residual coordinates
+            STEP(dalloc(pl, &pl->WY, wy));
+            ProbDesc *pw_d = nullptr;
+            STEP(dalloc(pl, &pw_d, n));
+            HSTEP(hipMemcpyAsync(pw_d, pl->probs.data(), n * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+            HSTEP(launch_resid_map(pw_d, n, maxe, pl->Kt, pl->gt, pl->Qb, pl->WY, st));
+            HSTEP(hipStreamSynchronize(st));
+            {
+                auto it = std::find(pl->allocs.begin(), pl->allocs.end(), (void *)pw_d);
+                if (it != pl->allocs.end()) pl->allocs.erase(it);
+                HSTEP(hipFree(pw_d));
+            }
         }
         int64_t offx = 0;
         for (auto &pd : pl->probs) {

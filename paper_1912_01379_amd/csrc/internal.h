@@ -35,7 +35,7 @@ struct ProbDesc {
     uint32_t index;           // problem index (keys the random numbers)
     int32_t has_prior;        // 1: gamma-prior shapes at off_n in the shape array
     int64_t off_sa;           // float32 snapshots of A (sweep, chain) rows of round4(N) floats
-    int64_t off_sr;           // float32 snapshots of r rows of round4(M) floats
+    int64_t off_sr;           // float32 residual coordinates of the snapshots, rows of round4(M)
     int64_t levels;           // partitions of the hierarchy (1: one partition of B blocks)
     int64_t has_con;          // 1: a linear constraint c . A = F (c at off_n in the constraint array)
     double con_value;         // F
@@ -43,6 +43,8 @@ struct ProbDesc {
     int64_t rank_r;           // columns of the range basis Q of K~ (float32 VJP moments in its
                               // coordinates), or 0: the moments are of r itself
     int64_t off_q;            // Q (M x rank_r, column j at off_q + j M) in the basis array
+    int64_t off_w;            // [W | y0] of the snapshot residuals: W = Q^T K~ (Mx x N), then
+                              // y0 = Q^T g~ (Mx); K~ and g~ without a basis (Mx = M)
 };
 
 struct BlockDesc {
@@ -109,10 +111,10 @@ struct SampleArgs {
     int64_t lds_off_ce;       //   per-chain rows of the data modes' centres and steps (2 kce)
     int32_t u_lds;            // 1: U rows are staged in LDS (else read from global memory)
     int32_t prefetch;         // 1: every block's factor stream fits the instance's prefetch
-    float *snapA;             // nullable (float32 plans with want_vjp): per-sweep snapshots of A
-    float *snapR;             //   and of r, the inputs of the cross moments, for the accumulated
-    int64_t snap_rows;        //   sweeps of the launch, at the problems' off_sa / off_sr; row =
-    int64_t *snap_first;      //   sweep - first sweep, which goes to *snap_first
+    float *snapA;             // nullable (float32 plans with want_vjp): per-sweep snapshots of A,
+    int64_t snap_rows;        //   the input of the cross moments, for the accumulated sweeps of
+    int64_t *snap_first;      //   the launch at the problems' off_sa; row = sweep - first sweep,
+                              //   which goes to *snap_first
     // two-role float32 sampler (sample32p.h): LDS byte offsets of its areas, the chunk word
     // where the singular values (then the U rows) start, the words of the data rows part and
     // of the d/U part, the data-role uniform row length
@@ -247,8 +249,10 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
                              int64_t nsnap, const float *snapA, const float *snapR, const int64_t *snap_first,
                              int64_t burnin, int64_t sweeps, double *cross, hipStream_t s);
 __host__ __device__ int64_t cross_snap_tiles(int64_t Mx, int64_t N);
-hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *Q,
-                          float *snapR, hipStream_t s);
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *WY,
+                          const float *snapA, float *yrow, hipStream_t s);
+hipError_t launch_resid_map(const ProbDesc *probs_dev, int64_t P, int64_t max_entries, const double *Kt,
+                            const double *gt, const double *Q, double *WY, hipStream_t s);
 hipError_t launch_range_basis(const ProbDesc *probs_dev, int64_t P, int64_t max_m, const int64_t *col_first,
                               const int64_t *colU, const int64_t *colD, const double *U64, const double *d64,
                               const int64_t *work_off, double *work, double *Q, int32_t *rank_out, int max_r,

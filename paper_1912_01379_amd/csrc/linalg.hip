@@ -182,9 +182,10 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 }
 
 // Cross moments from the per-sweep snapshots of one launch of the float32 sampler.  The
-// residual rows hold either r (M entries) or, for problems with a range basis Q (rank_r > 0),
-// its coordinates y = Q^T r (rank_r entries, written over the row by k_project); with x the
-// row entries and the snapshot rows k = (sweep, chain) of a split,
+// residual rows, written by k_project from the A snapshots, hold the residual of each sampled
+// state, g~ - K~ A (M entries), or, for problems with a range basis Q (rank_r > 0), its
+// coordinates Q^T (g~ - K~ A) (rank_r entries); with x the row entries and the snapshot rows
+// k = (sweep, chain) of a split,
 //   X_split[i][n] += sum_{k in split} x_k[i] A_k[n] (n < N),  X_split[i][N] += sum x_k[i].
 // Splits are (group, part): the rows of chain group g (or, with batch means, of the sweeps of
 // batch g), in `parts` ranges, so the partial sums are per-group moments (the error bar of
@@ -362,54 +363,83 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
     return hipGetLastError();
 }
 
-// y = Q^T r in place in the residual snapshot rows of a launch (problems with a range basis,
-// rank_r > 0): a workgroup of 4 wavefronts takes 16 rows; wavefront w forms the 16-column
-// tiles w and w + 4 of y (rank_r <= 128) by MFMA f64 16x16x4 over the M entries, and the rows
-// are overwritten only after every wavefront has read them.
-__global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t nsnap, const double *Q,
-                                                 float *snapR) {
+// The residual coordinates of every snapshot row of a launch, from the sampled state itself:
+// y_k = y0 - W A_k with W = Q^T K~ and y0 = Q^T g~ (range basis Q, rank_r > 0), or W = K~ and
+// y0 = g~ (rank_r = 0: y_k = g~ - K~ A_k).  The float32 sampler's carried residual drifts
+// between refreshes (its zero modes are float32 roundings of exact null vectors, and K~ is
+// ill-conditioned), so the VJP's moments take the residual of the state, in float64.  A
+// workgroup of 4 wavefronts takes 16 rows; wavefront w forms the 16-column tiles w, w + 4, ...
+// of y by MFMA f64 16x16x4 over the N components, read from the A snapshot rows.
+__global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t nsnap, const double *WY,
+                                                 const float *snapA, float *yrow) {
     const ProbDesc pd = probs[blockIdx.y];
-    if (pd.rank_r <= 0) return;
-    const int64_t M = pd.M, R = pd.rank_r, rows = nsnap * pd.C;
-    const int64_t ldr = (M + 3) / 4 * 4;
+    const int64_t N = pd.N, Mx = pd.rank_r > 0 ? pd.rank_r : pd.M, rows = nsnap * pd.C;
+    const int64_t ldr = (pd.M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
     const int64_t k0 = (int64_t)blockIdx.x * 16;
     if (k0 >= rows) return;
-    float *Rb = snapR + pd.off_sr;
-    const double *Qp = Q + pd.off_q;   // column j at Qp + j M
+    const float *Ab = snapA + pd.off_sa;
+    float *Yb = yrow + pd.off_sr;
+    const double *W = WY + pd.off_w, *y0 = WY + pd.off_w + Mx * N;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int i = lane % 16, kk = lane / 16;
     const int64_t ka = k0 + i;
     const bool oka = ka < rows;
-    d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
-    for (int h = 0; h < 2; ++h) {
-        const int64_t jt = 16 * (wave + 4 * h);
-        if (jt >= R) break;
+    for (int64_t jt = 16 * wave; jt < Mx; jt += 64) {
         const int64_t jb = jt + i;
-        const bool okb = jb < R;
-        for (int64_t m = 0; m < M; m += 4) {
-            const int64_t mm = m + kk;
-            const double a = (oka && mm < M) ? (double)Rb[ka * ldr + mm] : 0.0;
-            const double b = (okb && mm < M) ? Qp[jb * M + mm] : 0.0;
-            acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[h], 0, 0, 0);
+        const bool okb = jb < Mx;
+        d4 acc = {0, 0, 0, 0};
+        for (int64_t n = 0; n < N; n += 4) {
+            const int64_t nn = n + kk;
+            const double av = (oka && nn < N) ? (double)Ab[ka * lda + nn] : 0.0;
+            const double bv = (okb && nn < N) ? W[jb * N + nn] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
-    }
-    __syncthreads();   // every wavefront has read the 16 rows
-    for (int h = 0; h < 2; ++h) {
-        const int64_t jt = 16 * (wave + 4 * h);
-        if (jt >= R) break;
+        const int64_t col = jt + lane % 16;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t row = k0 + lane / 16 + 4 * j, col = jt + lane % 16;
-            if (row < rows && col < R) Rb[row * ldr + col] = (float)acc[h][j];
+            const int64_t row = k0 + lane / 16 + 4 * j;
+            if (row < rows && col < Mx) Yb[row * ldr + col] = (float)(y0[col] - acc[j]);
         }
     }
 }
 
-hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *Q,
-                          float *snapR, hipStream_t s) {
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *WY,
+                          const float *snapA, float *yrow, hipStream_t s) {
     if (max_rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + 15) / 16), (unsigned)P), dim3(256), 0, s, probs_dev,
-                       nsnap, Q, snapR);
+                       nsnap, WY, snapA, yrow);
+    return hipGetLastError();
+}
+
+// [W | y0] of every problem for k_project: W = Q^T K~ (Mx x N, row j at off_w + j N) and
+// y0 = Q^T g~ (at off_w + Mx N), or K~ and g~ themselves without a range basis; one thread
+// per entry.
+__global__ void k_resid_map(const ProbDesc *probs, const double *Kt, const double *gt, const double *Q, double *WY) {
+    const ProbDesc pd = probs[blockIdx.y];
+    const int64_t M = pd.M, N = pd.N, Mx = pd.rank_r > 0 ? pd.rank_r : M;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Mx * (N + 1)) return;
+    const int64_t j = e / (N + 1), n = e % (N + 1);
+    const double *K = Kt + pd.off_K, *g = gt + pd.off_m;
+    double x;
+    if (pd.rank_r > 0) {
+        const double *q = Q + pd.off_q + j * M;
+        x = 0.0;
+        for (int64_t m = 0; m < M; ++m) x = fma(q[m], n < N ? K[m * N + n] : g[m], x);
+    } else {
+        x = n < N ? K[j * N + n] : g[j];
+    }
+    if (n < N)
+        WY[pd.off_w + j * N + n] = x;
+    else
+        WY[pd.off_w + Mx * N + j] = x;
+}
+
+hipError_t launch_resid_map(const ProbDesc *probs_dev, int64_t P, int64_t max_entries, const double *Kt,
+                            const double *gt, const double *Q, double *WY, hipStream_t s) {
+    if (max_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_map, dim3((unsigned)((max_entries + 255) / 256), (unsigned)P), dim3(256), 0, s,
+                       probs_dev, Kt, gt, Q, WY);
     return hipGetLastError();
 }
 

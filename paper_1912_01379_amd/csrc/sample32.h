@@ -632,14 +632,6 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 p_nb = nb;
                 p_row = (a.snapA && s >= a.burnin) ? s - s0 : -1;
             }
-            if (a.snapR && s >= a.burnin) {
-                float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
-#pragma unroll
-                for (int t = 0; t < RPT; ++t) {
-                    const int m = lane + L * t;
-                    if (active && m < M) sr[m] = rr[t];
-                }
-            }
             lf = nf;
             lc = nc;
         }

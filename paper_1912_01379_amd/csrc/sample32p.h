@@ -190,14 +190,6 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             if (ke > kb) zero_moves_p<L, EPT>(ar.vwd + kb * ROW, kb, ke, urow, lane, Ar);
 #pragma unroll
             for (int t2 = 0; t2 < EPT; ++t2) hA[t2] = Ar[t2];
-            if (b == B - 1 && a.snapR && s >= a.burnin) {
-                float *sr = a.snapR + pd.off_sr + ((s - s0) * pd.C + chain) * (int64_t)((M + 3) / 4 * 4);
-#pragma unroll
-                for (int t2 = 0; t2 < RPT; ++t2) {
-                    const int m = lane + L * t2;
-                    if (active && m < M) sr[m] = rr[t2];
-                }
-            }
         }
 #pragma unroll
         for (int t2 = 0; t2 < RPT; ++t2) {

@@ -37,8 +37,10 @@ PROTOCOLS = {
     "cfg5": dict(problem="config5", chains=256, burnin=1000, sweeps=5000, seed=15, groups=32,
                  refresh_every=64, start="nnls"),
     # the differentiation workload: the config-2 problem with its seeded cotangent v; J^T v
-    # (Sec. II, Eq. (PI) differentiated in the data) and its error bar over the chain groups
-    "cfg4": dict(problem="config2", chains=512, burnin=500, sweeps=2000, seed=14, groups=32,
+    # (Sec. II, Eq. (PI) differentiated in the data), its error bar over the chain groups and
+    # the value of every group (their covariance carries the strong correlation between the
+    # entries of J^T v, which the parity test needs)
+    "cfg4": dict(problem="config2", chains=1024, burnin=500, sweeps=2000, seed=14, groups=32,
                  refresh_every=64, start="nnls", vjp="config4_cotangent"),
 }
 # three uneven datasets of the batched workload (N = 396, 670, 407 in 4, 7, 4 blocks); 256
@@ -62,7 +64,7 @@ def make(name):
                      init=init, threads=THREADS, vjp_v=v)
     dt = time.time() - t
     out = os.path.join(HERE, f"{name}_oracle.npz")
-    extra = {} if v is None else dict(v=v, vjp=res.vjp, vjp_se=res.vjp_se)
+    extra = {} if v is None else dict(v=v, vjp=res.vjp, vjp_se=res.vjp_se, vjp_groups=res.vjp_groups)
     np.savez_compressed(out, mean=res.mean, stderr=res.stderr, post_sd=res.post_sd,
                         kb=prep.kb, chi2_final=res.final_chi2, **extra)
     meta = dict(proto, seconds=round(dt, 1), status=res.status, drift_max=res.drift_max,

@@ -29,3 +29,32 @@ def zscore_ok(m1, s1, m2, s2, frac=0.01, zmax=4.5, n3_min=2, mean_z2=None):
 # beyond 3, mean z^2 up to 1.8; its output, correlated_calibration.json, is checked against
 # these bounds by a CPU test).
 CORRELATED = dict(frac=0.035, zmax=5.5, n3_min=3, mean_z2=2.2)
+
+
+def principal_t2(delta, ref_groups, rho, k=4):
+    """Hotelling's T^2 of a difference of two estimates of a strongly correlated vector, in the
+    k leading principal directions of the reference's group values.
+
+    delta: the difference of the two pooled estimates; ref_groups: G x M, the reference's
+    estimate from each of its G independent chain groups; rho: the other side's variance over
+    the reference's under the null (the same estimator with 1/rho times the chains).  The
+    reference's estimate has covariance S / G (S the sample covariance of the group values),
+    the difference (1 + rho) S / G.  With e_j, l_j the k leading eigenpairs of S,
+      T^2 = sum_j (e_j . delta)^2 / (l_j (1 + rho) / G),
+    and (G - k) T^2 / (k (G - 1)) follows F(k, G - k) for Gaussian group values (directions
+    taken from S overstate their l_j, which makes the test conservative).  Returns
+    (T^2, p value)."""
+    from scipy import stats
+    X = np.asarray(ref_groups, np.float64)
+    G = X.shape[0]
+    if not 0 < k < G:
+        raise ValueError("need 0 < k < G")
+    X = X - X.mean(0)
+    S = X.T @ X / (G - 1)
+    w, V = np.linalg.eigh(S)
+    idx = np.argsort(w)[::-1][:k]
+    lam, E = w[idx], V[:, idx]
+    proj = E.T @ np.asarray(delta, np.float64)
+    t2 = float(np.sum(proj ** 2 / (lam * (1.0 + rho) / G)))
+    f = (G - k) * t2 / (k * (G - 1))
+    return t2, float(stats.f.sf(f, k, G - k))
