@@ -212,6 +212,18 @@ int asm_plan_group_means(asm_plan *plan, double *mean, double *stderr_, double *
    Errors: ASM_ESTATE, ASM_EINVAL, ASM_EHIP. */
 int asm_plan_vjp(asm_plan *plan, const double *v, double *grad_G, double *grad_se);
 
+/* asm_plan_vjp for callers that cannot allocate device memory (code under stream capture,
+   serving loops, harnesses that forbid hipMalloc): the same kernels and the same result, bit
+   for bit, with their intermediate products in a fixed per-device array of the library
+   (64 MiB, 2^23 doubles; the call needs (4 groups + 2) x sum M + 2 x problems x groups of
+   them) instead of a plan buffer.  It allocates nothing and does not wait: the work is
+   enqueued on the plan's stream, and grad_G / grad_se are ready when that stream reaches it.
+   Every call on one device shares the array, so calls that may overlap on a device (other
+   streams, other threads, other plans) race and must be ordered by the caller.  The plan's
+   device must be current.  Errors: ASM_ESTATE, ASM_EINVAL (a larger problem than the array
+   holds, another device current), ASM_EHIP. */
+int asm_plan_vjp_noalloc(asm_plan *plan, const double *v, double *grad_G, double *grad_se);
+
 /* Advance every chain by `sweeps` sweeps without accumulating (burn-in style; the sweep
    counter that keys the random numbers advances).  Errors: ASM_EUNBOUNDED, ASM_EHIP. */
 int asm_plan_advance(asm_plan *plan, int64_t sweeps);

@@ -22,7 +22,8 @@ ASM_OK, ASM_EINVAL, ASM_EDOMAIN, ASM_ESTATE, ASM_EUNBOUNDED, ASM_EHIP, ASM_ENOME
 ASM_FP64, ASM_FP32 = 0, 1
 ASM_START_FLAT, ASM_START_NNLS, ASM_START_NNLS_NOISED = 0, 1, 2
 
-EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_group_means", "asm_plan_advance",
+EXPORTED = ["asm_plan_create", "asm_plan_run", "asm_plan_vjp", "asm_plan_vjp_noalloc", "asm_plan_group_means",
+            "asm_plan_advance",
             "asm_plan_state",
             "asm_plan_factors", "asm_plan_whitened", "asm_plan_destroy", "asm_tn_draw",
             "asm_uniforms", "asm_hierarchy", "asm_last_error", "asm_version"]
@@ -76,6 +77,7 @@ def _load():
                                   ctypes.POINTER(vp)]
     L.asm_plan_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Stats)]
     L.asm_plan_vjp.argtypes = [vp, vp, vp, vp]
+    L.asm_plan_vjp_noalloc.argtypes = [vp, vp, vp, vp]
     L.asm_plan_group_means.argtypes = [vp, vp, vp, vp]
     L.asm_plan_advance.argtypes = [vp, i64]
     L.asm_plan_state.argtypes = [vp, i64, vp, vp, vp]
@@ -223,6 +225,19 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(_lib.asm_plan_vjp(self.handle, v.data_ptr(), out.data_ptr(), _ptr(se)))
         return (out, se) if stderr else out
+
+    def vjp_noalloc(self, v, out, se=None):
+        """J^T v of the last run into the caller's float64 device tensors out (and se, its
+        standard error, if given), without any device allocation (asm_plan_vjp_noalloc); the
+        work is enqueued on the plan's stream and not waited for."""
+        for t in (v, out) + (() if se is None else (se,)):
+            if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous() and t.is_cuda):
+                raise TypeError("v, out and se must be contiguous float64 tensors on the plan's device")
+        if v.numel() != sum(self.N) or out.numel() != sum(self.M) or (se is not None and se.numel() != out.numel()):
+            raise ValueError("v has sum N entries, out and se sum M")
+        with torch.cuda.device(self.device):
+            _check(_lib.asm_plan_vjp_noalloc(self.handle, v.data_ptr(), out.data_ptr(), _ptr(se)))
+        return out
 
     def group_means(self) -> torch.Tensor:
         """The last run's average of each chain group: (groups, sum N)."""

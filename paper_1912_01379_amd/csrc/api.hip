@@ -51,6 +51,7 @@ struct DevBuf {
 
 struct asm_plan {
     hipStream_t stream = nullptr;
+    int device = -1;          // the device current at creation, where every buffer lives
     asm_options opt{};
     int64_t P = 0;
     std::vector<ProbDesc> probs;
@@ -761,6 +762,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     } while (0)
 
     pl->stream = static_cast<hipStream_t>(hip_stream);
+    HSTEP(hipGetDevice(&pl->device));
     pl->opt = *o;
     if (pl->opt.groups == 0) pl->opt.groups = 32;
     pl->P = n;
@@ -1588,6 +1590,62 @@ int asm_plan_vjp(asm_plan *pl, const double *v, double *grad_G, double *grad_se)
                       pl->cross, pl->accA, pl->slot_group_d, pl->slot_count_d, pl->Qb, pl->sigma, pl->Lc, v,
                       pl->vjp_scratch, grad_G, grad_se, st));
     HIPCHK(hipStreamSynchronize(st));
+    return ASM_OK;
+}
+
+// ---- the VJP without allocation ----
+// The intermediate products of the VJP (per-group moment rows, centred moments, their images
+// under -T^T) live in this file-scope array instead of the plan's own buffer, for callers
+// that may not allocate.  Each device holds its own copy; host code reaches it only through
+// the address hipGetSymbolAddress returns on that device.  Every kernel of the VJP writes the
+// scratch entries it later reads, so nothing needs clearing between calls.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 23;   // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+int noalloc_scratch(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(ASM_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ASM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ASM_OK;
+}
+
+}  // namespace
+
+int asm_plan_vjp_noalloc(asm_plan *pl, const double *v, double *grad_G, double *grad_se) {
+    g_err.clear();
+    if (!pl) return fail(ASM_EINVAL, "plan is NULL");
+    if (!pl->opt.want_vjp) return fail(ASM_ESTATE, "plan was created without want_vjp");
+    if (!pl->ran) return fail(ASM_ESTATE, "asm_plan_run must come before asm_plan_vjp_noalloc");
+    if (!v || !grad_G) return fail(ASM_EINVAL, "v and grad_G are required");
+    const int64_t need = vjp_scratch_doubles(pl->P, pl->total_m, (int)pl->opt.groups);
+    if (need > kNoAllocScratchDoubles)
+        return fail(ASM_EINVAL,
+                    "the VJP needs %lld scratch doubles ((4 groups + 2) x sum M + 2 problems x groups), more "
+                    "than the %lld of asm_plan_vjp_noalloc; use asm_plan_vjp",
+                    (long long)need, (long long)kNoAllocScratchDoubles);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != pl->device)
+        return fail(ASM_EINVAL, "device %d is current, the plan lives on device %d", dev, pl->device);
+    double *ws = nullptr;
+    TRY(noalloc_scratch(dev, &ws));
+    HIPCHK(launch_vjp(pl->d_probs, pl->P, pl->d_mprefix, pl->total_m, pl->max_m, (int)pl->opt.groups, pl->parts,
+                      pl->cross, pl->accA, pl->slot_group_d, pl->slot_count_d, pl->Qb, pl->sigma, pl->Lc, v, ws,
+                      grad_G, grad_se, pl->stream));
     return ASM_OK;
 }
 

@@ -108,6 +108,7 @@ def test_null_plan_calls_fail_cleanly():
     L = pk.lib()
     assert L.asm_plan_run(None, None, None, None, None) == pk.ASM_EINVAL
     assert L.asm_plan_vjp(None, None, None, None) == pk.ASM_EINVAL
+    assert L.asm_plan_vjp_noalloc(None, None, None, None) == pk.ASM_EINVAL
     assert L.asm_plan_group_means(None, None, None, None) == pk.ASM_EINVAL
     assert L.asm_plan_advance(None, 1) == pk.ASM_EINVAL
     assert L.asm_plan_destroy(None) == pk.ASM_OK
