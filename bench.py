@@ -1,18 +1,21 @@
 """Benchmark of the blocked-modes sampler on one MI355X.
 
-One step is one pass of the whole hot path over one synthetic continuation problem of
-the single-continuation workload (beta = 20, 201 imaginary times, 800 Lorentzian grid
-points in 8 blocks of 100 with up to 20 data modes, sigma = 1e-4, 4096 chains, 2000
-burn-in and 10000 measured sweeps, float32 chain state):
+One step is one pass of the whole hot path over one synthetic continuation problem, by
+default the large workload (beta = 50, 401 imaginary times with exponentially correlated
+noise, whitened by its Cholesky factor, 4000 Lorentzian grid points in 32 blocks of 125 with
+up to 30 data modes, sigma = 1e-4, 16384 chains, 1000 burn-in and 5000 measured sweeps,
+float32 chain state, refresh cycles replayed from a hipGraph):
     whitening -> float64 block SVDs -> float32 packing -> NNLS start -> sweeps with float64
-    residual refreshes every 64 sweeps -> float64 accumulation of <A> and of Cov(r~, A) ->
-    error bars -> VJP d<A>/dG v for a seeded cotangent v.
+    residual refreshes every 64 sweeps -> float64 accumulation of <A> (and of the moments of
+    Cov(r~, A)) -> error bars -> VJP d<A>/dG v, with its error bar, for a seeded cotangent v.
 The problem arrays are on the GPU before the timed region starts.
 
 Prints one JSON line (see the fields below).  Only one GPU is supported.
 
     python bench.py [--steps K] [--warmup W] [--no-vjp] [--no-cpu]
-    python bench.py --copy-probe     # a plain 1 GiB device copy, to calibrate HBM counters
+    python bench.py --workload single     # beta = 20, 201 points, 800 grid points, 4096 chains
+    python bench.py --workload batched    # 256 uneven continuations in one launch
+    python bench.py --copy-probe          # a plain 1 GiB device copy, to calibrate HBM counters
 """
 from __future__ import annotations
 
@@ -34,7 +37,8 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "tn32.h", "tn32_coef.h",
                    "rng_tn.h", "internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_single_continuation_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_{workload}_traffic.md")
+WORKLOAD_FILE_NAMES = {"large": "large_config5", "single": "single_continuation"}
 
 
 def lane_ops_per_sweep(M, blocks, s_tn=40, s_u=10):
@@ -59,11 +63,11 @@ def sampler_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per sampler launch from the committed counter summary of that kernel, if it
-    was taken on the current sampler sources (else None)."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per sampler launch from the committed counter summary of that kernel on that
+    workload, if it was taken on the current sampler sources (else None)."""
     try:
-        with open(TRAFFIC_FILE.format(kernel=kernel)) as f:
+        with open(TRAFFIC_FILE.format(kernel=kernel, workload=WORKLOAD_FILE_NAMES.get(workload, workload))) as f:
             for line in f:
                 line = line.strip()
                 if line.startswith("{") and '"sources"' in line:
@@ -109,6 +113,7 @@ def cpu_baseline(prob, seconds_target=15.0):
     dt = time.time() - t
     moves = chains * sweeps * prob.N
     return {"value": moves / dt, "unit": "mode-moves/s", "cores": threads, "kind": "oracle",
+            "chain_sweeps_per_s": chains * sweeps / dt,
             "sample": f"{chains} chains x {sweeps} sweeps of the same problem from the flat start "
                       f"({moves:.3g} moves, {dt:.1f} s, float64)"}
 
@@ -124,6 +129,42 @@ def copy_probe():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": 4 * n, "repeats": 3}))
+
+
+def micro():
+    """On-chip rates of one MI355X: float32 fused multiply-adds per second, and LDS read
+    bytes per second for 4-, 8- and 16-byte reads per lane, each word read by one lane or by
+    the four 16-lane groups of a wavefront (the samplers' pattern)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1912_01379_amd", "libasm_micro.so"))
+    lib.micro_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(64 * cus, dtype=torch.float32, device="cuda:0")
+    ms = ctypes.c_double()
+    out = {"cus": cus}
+
+    def run(kind, iters, grid, share=1):
+        rc = lib.micro_run(kind, iters, grid, share, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"micro_run({kind}) failed: {rc}")
+        return ms.value * 1e-3
+
+    for wpc in (4, 8, 16):   # 256-thread workgroups: 4 waves each
+        grid = cus * wpc // 4
+        iters = 20000
+        t = run(0, iters, grid)
+        out[f"valu_fma_per_s_{wpc}waves_per_cu"] = grid * 256 * iters * 16 / t
+    for kind, width in ((1, 4), (2, 8), (3, 16)):
+        for share in (1, 4):
+            grid = cus * 2   # two workgroups of 64 KiB per CU, 8 waves
+            iters = 4000
+            t = run(kind, iters, grid, share)
+            out[f"lds_read_b{8 * width}_share{share}_bytes_per_s"] = grid * 256 * iters * 8 * width / t
+    out["lds_bytes_per_clk_per_cu_at_2.4GHz"] = {k: v / (cus * 2.4e9) for k, v in out.items() if k.startswith("lds")}
+    out["valu_lane_ops_per_clk_per_cu_at_2.4GHz"] = out["valu_fma_per_s_8waves_per_cu"] / (cus * 2.4e9)
+    print(json.dumps({"micro": out}))
 
 
 def batched(args):
@@ -382,14 +423,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sweeps", type=int, default=10000)
-    ap.add_argument("--burnin", type=int, default=2000)
-    ap.add_argument("--chains", type=int, default=4096)
+    ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--burnin", type=int, default=None)
+    ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--no-vjp", action="store_true")
+    ap.add_argument("--no-overhead", action="store_true",
+                    help="skip the untimed forward without the VJP's moments")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "conductivity", "grids"], default="single")
+    ap.add_argument("--micro", action="store_true", help="on-chip VALU and LDS rates")
+    ap.add_argument("--workload", choices=["large", "single", "batched", "conductivity", "grids"],
+                    default="large")
     ap.add_argument("--graph", action="store_true", help="replay refresh cycles from a hipGraph")
     ap.add_argument("--cases", default="", help="conductivity workload: comma list such as N120_hierarchy")
     ap.add_argument("--hierarchy", action="store_true",
@@ -401,6 +446,14 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.micro:
+        micro()
+        return
+    if args.workload not in ONE_PROBLEM:
+        # the other workloads' defaults
+        args.burnin = 2000 if args.burnin is None else args.burnin
+        args.sweeps = args.sweeps or 10000
+        args.chains = args.chains or 4096
     if args.workload == "batched":
         batched(args)
         return
@@ -411,31 +464,60 @@ def main():
         grid_study(args)
         return
 
+    one_problem(args)
+
+
+# the two one-problem workloads: chains, burn-in, measured sweeps, and whether cycles replay
+# from a hipGraph by default
+ONE_PROBLEM = {
+    "large": dict(chains=16384, burnin=1000, sweeps=5000, graph=True),
+    "single": dict(chains=4096, burnin=2000, sweeps=10000, graph=False),
+}
+
+
+def one_problem(args):
+    """One continuation problem per step: the large workload (beta = 50, 401 correlated data
+    points whitened by their Cholesky factor, 4000 grid points in 32 blocks of 125 with up to 30
+    data modes, 16384 chains) or the single-continuation workload (beta = 20, 201 points, 800
+    grid points in 8 blocks of 100 with up to 20 data modes, 4096 chains); forward and VJP."""
     import torch
     import workloads
     import paper_1912_01379_amd as pk
 
     dev = torch.device("cuda:0")
-    prob = workloads.config2()
-    if args.hierarchy:
-        # the Fig. 2 hierarchy of the 800-point grid, levels of blocks up to 128 points (the
-        # float32 instances' largest block): 8 blocks of 100 down to the single points
-        prob.levels = pk.hierarchy(prob.N, max_block=128)
-        prob.k = np.full(prob.B, 20, np.int32)
+    d = ONE_PROBLEM[args.workload]
+    chains = args.chains or d["chains"]
+    burnin = d["burnin"] if args.burnin is None else args.burnin
+    sweeps = args.sweeps or d["sweeps"]
+    use_graph = d["graph"] or args.graph
+    if args.workload == "large":
+        prob = workloads.config5()
+        label = ("large: beta=50, M=401 correlated (length 5) whitened by Cholesky, N=4000 Lorentzian grid, "
+                 "32 blocks x 125, k<=30, sigma=1e-4, fp32 chains, NNLS start")
+    else:
+        prob = workloads.config2()
+        label = ("single continuation: beta=20, M=201, N=800 Lorentzian grid, "
+                 + ("Fig. 2 hierarchy of 7 levels (8 to 800 blocks)" if args.hierarchy else "8 blocks x 100")
+                 + ", k<=20, sigma=1e-4, fp32 chains, NNLS start")
+        if args.hierarchy:
+            # the Fig. 2 hierarchy of the 800-point grid, levels of blocks up to 128 points (the
+            # float32 instances' largest block): 8 blocks of 100 down to the single points
+            prob.levels = pk.hierarchy(prob.N, max_block=128)
+            prob.k = np.full(prob.B, 20, np.int32)
     v = torch.as_tensor(workloads.config4_cotangent(prob.N), dtype=torch.float64, device=dev)
     dp = _DevProblem(prob, dev)
     want_vjp = not args.no_vjp
 
-    def step():
-        plan = pk.Plan([dp], chains=args.chains, burnin=args.burnin, sweeps=args.sweeps, seed=2024,
-                       precision="fp32", refresh_every=64, want_vjp=want_vjp, groups=32,
-                       lanes_per_chain=args.lanes, start="nnls", use_graph=args.graph, device=dev)
+    def step(vjp=want_vjp):
+        plan = pk.Plan([dp], chains=chains, burnin=burnin, sweeps=sweeps, seed=2024,
+                       precision="fp32", refresh_every=64, want_vjp=vjp, groups=32,
+                       lanes_per_chain=args.lanes, start="nnls", use_graph=use_graph, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = plan.run()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        g = plan.vjp(v) if want_vjp else None
+        g = plan.vjp(v, stderr=True) if vjp else None
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         blocks, blk = [], 0   # per level: (N_b, k_b) of its blocks
@@ -461,26 +543,30 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
-    res, fwd_s, vjp_s, blocks, _ = outs[-1]
+    res, fwd_s, vjp_s, blocks, g = outs[-1]
     st = res.stats
-    sweeps_total = args.burnin + args.sweeps
-    moves_per_step = args.chains * sweeps_total * prob.N
+    sweeps_total = burnin + sweeps
+    moves_per_step = chains * sweeps_total * prob.N
     # levels are drawn uniformly: per-sweep counts averaged over the levels
-    data_per_step = args.chains * sweeps_total * float(np.mean([sum(k for _, k in lv) for lv in blocks]))
+    data_per_step = chains * sweeps_total * float(np.mean([sum(k for _, k in lv) for lv in blocks]))
     value = moves_per_step * args.steps / elapsed
     step_s = elapsed / args.steps
     # roofline of the sampler kernel from its own launch events
     ops_sweep = float(np.mean([lane_ops_per_sweep(prob.M, lv) for lv in blocks]))
     avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
-    ops_per_launch = ops_sweep * args.chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
+    ops_per_launch = ops_sweep * chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
     achieved = ops_per_launch / avg_launch_s
     kernel = "k_sample32p" if st.get("roles", 1) == 2 else "k_sample32"
-    tr = measured_traffic(kernel)
-    mean = res.mean.cpu().numpy()
+    tr = measured_traffic(kernel, args.workload)
     se = res.stderr.cpu().numpy()
     sd = res.post_sd.cpu().numpy()
     ess = (sd / se) ** 2
-    tau = args.chains * args.sweeps / ess
+    tau = chains * sweeps / ess
+    # the forward alone (untimed): what accumulating the VJP's moments costs the forward
+    fwd_novjp_s = None
+    if want_vjp and not args.no_overhead:
+        fwd_novjp_s = step(vjp=False)[1]
+        print("forward without the VJP's moments done", file=sys.stderr, flush=True)
 
     # the plain sampler: float64, one chain per launch
     plain = pk.Plan([dp], chains=1, burnin=0, sweeps=20, seed=7, precision="fp64", groups=1,
@@ -502,11 +588,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single continuation: beta=20, M=201, N=800 Lorentzian grid, "
-                               + ("Fig. 2 hierarchy of 7 levels (8 to 800 blocks)" if args.hierarchy else "8 blocks x 100")
-                               + ", k<=20, sigma=1e-4, fp32 chains, NNLS start",
-                   "chains": args.chains, "burnin": args.burnin, "sweeps": args.sweeps,
-                   "vjp": want_vjp, "lanes_per_chain": st["lanes_per_chain"],
+        "config": {"workload": label, "chains": chains, "burnin": burnin, "sweeps": sweeps,
+                   "vjp": want_vjp, "hipgraph": use_graph, "lanes_per_chain": st["lanes_per_chain"],
                    "chains_per_workgroup": st["chains_per_block"], "roles": st.get("roles", 1),
                    "data_modes_per_block": [k for _, k in blocks[0]] if len(blocks) == 1 else None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
@@ -515,7 +598,7 @@ def main():
                      "kernel": kernel, "ops_per_chain_sweep": ops_sweep,
                      "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
                      "launches_per_step": st["sampler_launches"]},
-        "chain_sweeps_per_s": args.chains * sweeps_total * args.steps / elapsed,
+        "chain_sweeps_per_s": chains * sweeps_total * args.steps / elapsed,
         "data_moves_per_s": data_per_step * args.steps / elapsed,
         "zero_moves_per_s": (moves_per_step - data_per_step) * args.steps / elapsed,
         "ess_per_s": {"min": float(np.nanmin(ess)) / step_s, "median": float(np.nanmedian(ess)) / step_s},
@@ -523,8 +606,13 @@ def main():
         "forward_ms": fwd_s * 1e3,
         "vjp_ms": vjp_s * 1e3 if want_vjp else None,
         "vjp_over_forward": (vjp_s / fwd_s) if want_vjp else None,
+        "forward_ms_without_vjp_moments": None if fwd_novjp_s is None else fwd_novjp_s * 1e3,
+        "vjp_moments_forward_overhead": None if fwd_novjp_s is None else fwd_s / fwd_novjp_s - 1.0,
+        "vjp_rel_stderr_median": (float(np.median(g[1].cpu().numpy() / np.abs(g[0].cpu().numpy()).max()))
+                                  if g is not None else None),
         "setup_ms": st["setup_ms"],
         "sampler_ms_per_step": st["sampler_ms"],
+        "graph_replays": st["graph_replays"],
         "chi2_drift_max": st["chi2_drift_max"],
         "plain_fp64_mode_moves_per_s": plain_rate,
         "speedup_vs_plain": value / plain_rate,
@@ -533,6 +621,10 @@ def main():
         cb = cpu_baseline(prob)
         out["cpu_baseline"] = cb
         out["speedup_vs_cpu_oracle"] = value / cb["value"]
+        # the oracle runs the same Markov chain (same moves, same integrated autocorrelation
+        # time), so its effective samples per second are its chain-sweeps per second over tau
+        tau_med = float(np.nanmedian(tau))
+        out["cpu_oracle_ess_per_s_median"] = cb["chain_sweeps_per_s"] / tau_med
     print(json.dumps(out))
 
 

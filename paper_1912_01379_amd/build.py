@@ -8,6 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libasm.so")
+# the on-chip microbenchmarks of bench.py --micro, in a library of their own
+MICRO_SRC, MICRO_OUT = "micro.hip", os.path.join(HERE, "libasm_micro.so")
 SOURCES = ["api.hip", "setup.hip", "sample.hip", "linalg.hip", "sample32.hip", "sample32p_l16.hip", "sample32_l4.hip",
            "sample32_l8.hip", "sample32_l16.hip", "sample32_l32.hip"]
 
@@ -44,6 +46,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
+    tmp = MICRO_OUT + ".tmp"
+    cmd = [hipcc] + FLAGS + [os.path.join(SRC, MICRO_SRC), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, MICRO_OUT)
     return OUT
 
 

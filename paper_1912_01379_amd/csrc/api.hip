@@ -65,7 +65,8 @@ struct asm_plan {
     int parts = 1;           // cross-moment partial sums per chain group (splits = groups x parts)
     int64_t cross_words = 0;
     double *Qb = nullptr;     // range bases of the problems' K~ (float32 plans with want_vjp)
-    double *WY = nullptr;     // [Q^T K~ | Q^T g~] (or [K~ | g~]) per problem: snapshot residuals
+    double *WY = nullptr;     // [(Q^T K~)^T | Q^T g~] (or [K~^T | g~]) per problem: snapshot residuals
+    int64_t max_mx = 0;       // the largest number of residual coordinates over the problems
     bool any_rank = false;    // a problem whose moments are taken in its range basis
     double *vjp_scratch = nullptr;
     // float32 plans: per-sweep snapshots of A (and of r with want_vjp) of the accumulated
@@ -439,6 +440,8 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
 // when the plan's stream is the null stream.
 hipStream_t main_stream(asm_plan *pl) { return pl->stream ? pl->stream : (pl->gstream ? pl->gstream : pl->stream); }
 
+constexpr bool kOverlapMoments = false;
+
 // Before the sampler writes snapshot buffer `par`: the main stream waits until the previous
 // reduction of that buffer is done.
 int snap_acquire(asm_plan *pl, int par) {
@@ -449,15 +452,20 @@ int snap_acquire(asm_plan *pl, int par) {
 // After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
 // moments on the second stream, after the main stream's work so far.
 int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
-    HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
-    HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, nsnap, pl->WY, pl->snapA[par],
-                          pl->snapR[par], pl->xstream));
+    hipStream_t xs = kOverlapMoments ? pl->xstream : main_stream(pl);
+    if (kOverlapMoments) {
+        HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
+        HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
+    }
+    HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, pl->max_mx, nsnap, pl->WY, pl->snapA[par],
+                          pl->snapR[par], xs));
     HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, (int)pl->opt.groups, pl->parts, nsnap,
                              pl->snapA[par], pl->snapR[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps,
-                             pl->cross, pl->xstream));
-    HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
-    pl->pending[par] = true;
+                             pl->cross, xs));
+    if (kOverlapMoments) {
+        HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
+        pl->pending[par] = true;
+    }
     return ASM_OK;
 }
 
@@ -1171,6 +1179,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             for (auto &pd : pl->probs) {
                 const int64_t Mx = pd.rank_r > 0 ? pd.rank_r : pd.M;
                 pl->max_snap_tiles = std::max(pl->max_snap_tiles, cross_snap_tiles(Mx, pd.N));
+                pl->max_mx = std::max(pl->max_mx, Mx);
                 pd.off_w = wy;
                 wy += Mx * (pd.N + 1);
                 maxe = std::max(maxe, Mx * (pd.N + 1));

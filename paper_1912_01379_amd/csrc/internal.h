@@ -43,8 +43,8 @@ struct ProbDesc {
     int64_t rank_r;           // columns of the range basis Q of K~ (float32 VJP moments in its
                               // coordinates), or 0: the moments are of r itself
     int64_t off_q;            // Q (M x rank_r, column j at off_q + j M) in the basis array
-    int64_t off_w;            // [W | y0] of the snapshot residuals: W = Q^T K~ (Mx x N), then
-                              // y0 = Q^T g~ (Mx); K~ and g~ without a basis (Mx = M)
+    int64_t off_w;            // [W^T | y0] of the snapshot residuals: W = Q^T K~ (Mx x N) stored
+                              // n-major, then y0 = Q^T g~ (Mx); K~ and g~ without a basis (Mx = M)
 };
 
 struct BlockDesc {
@@ -249,8 +249,8 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
                              int64_t nsnap, const float *snapA, const float *snapR, const int64_t *snap_first,
                              int64_t burnin, int64_t sweeps, double *cross, hipStream_t s);
 __host__ __device__ int64_t cross_snap_tiles(int64_t Mx, int64_t N);
-hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *WY,
-                          const float *snapA, float *yrow, hipStream_t s);
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t max_mx, int64_t nsnap,
+                          const double *WY, const float *snapA, float *yrow, hipStream_t s);
 hipError_t launch_resid_map(const ProbDesc *probs_dev, int64_t P, int64_t max_entries, const double *Kt,
                             const double *gt, const double *Q, double *WY, hipStream_t s);
 hipError_t launch_range_basis(const ProbDesc *probs_dev, int64_t P, int64_t max_m, const int64_t *col_first,

@@ -259,7 +259,24 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
     const int64_t nc = gr.c1 - gr.c0;
     const int64_t K = (gr.j1 - gr.j0) * nc;
     const int64_t k_lo = K * part / parts, k_hi = K * (part + 1) / parts;
-    auto row_of = [&](int64_t kp) { return (gr.j0 + kp / nc) * pd.C + gr.c0 + kp % nc; };
+    // the snapshot row of chunk row r (< kSnapKC) for the chunk starting at split row
+    // js nc + cs: rows run over the group's chains, then its sweeps (no division per row)
+    int64_t js = nc > 0 ? k_lo / nc : 0, cs = nc > 0 ? k_lo % nc : 0;
+    auto row_of = [&](int r) {
+        int64_t jj = js, cc = cs + r;
+        while (cc >= nc) {
+            cc -= nc;
+            ++jj;
+        }
+        return (gr.j0 + jj) * pd.C + gr.c0 + cc;
+    };
+    auto next_chunk = [&]() {
+        cs += kSnapKC;
+        while (cs >= nc) {
+            cs -= nc;
+            ++js;
+        }
+    };
     const int64_t m0 = (tile / ntn) * kSnapTM, n0 = (tile % ntn) * kSnapTN;
     const float *Rb = snapR + pd.off_sr;
     const float *Ab = snapA + pd.off_sa;
@@ -276,22 +293,22 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
     // one 16-byte word of x and two of A per thread and chunk, loaded a chunk ahead
     const int rrow = tid / (kSnapTM / 4), rc4 = tid % (kSnapTM / 4);
     const int64_t rm = m0 + 4 * rc4;
-    auto load_r = [&](int64_t c0, int64_t kc) {
+    auto load_r = [&](int64_t kc) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (rrow < kc && rm < ldr) v = *reinterpret_cast<const float4 *>(Rb + row_of(c0 + rrow) * ldr + rm);
+        if (rrow < kc && rm < ldr) v = *reinterpret_cast<const float4 *>(Rb + row_of(rrow) * ldr + rm);
         if (rm + 0 >= Mx) v.x = 0.f;
         if (rm + 1 >= Mx) v.y = 0.f;
         if (rm + 2 >= Mx) v.z = 0.f;
         if (rm + 3 >= Mx) v.w = 0.f;
         return v;
     };
-    auto load_a = [&](int64_t c0, int64_t kc, int h) {
+    auto load_a = [&](int64_t kc, int h) {
         const int e = tid + h * 256;
         const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
         const int64_t n = n0 + 4 * c4;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (row < kc) {
-            if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + row_of(c0 + row) * lda + n);
+            if (n < lda) v = *reinterpret_cast<const float4 *>(Ab + row_of(row) * lda + n);
             if (n + 0 >= N) v.x = (n + 0 == N) ? 1.f : 0.f;
             if (n + 1 >= N) v.y = (n + 1 == N) ? 1.f : 0.f;
             if (n + 2 >= N) v.z = (n + 2 == N) ? 1.f : 0.f;
@@ -302,9 +319,9 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f), pa0 = pr, pa1 = pr;
     if (k_lo < k_hi) {
         const int64_t kc = (k_hi - k_lo) < kSnapKC ? (k_hi - k_lo) : kSnapKC;
-        pr = load_r(k_lo, kc);
-        pa0 = load_a(k_lo, kc, 0);
-        pa1 = load_a(k_lo, kc, 1);
+        pr = load_r(kc);
+        pa0 = load_a(kc, 0);
+        pa1 = load_a(kc, 1);
     }
     for (int64_t c0 = k_lo; c0 < k_hi; c0 += kSnapKC) {
         __syncthreads();   // the previous chunk is consumed
@@ -321,9 +338,10 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
         if (c0 + kSnapKC < k_hi) {
             const int64_t c1 = c0 + kSnapKC;
             const int64_t kc = (k_hi - c1) < kSnapKC ? (k_hi - c1) : kSnapKC;
-            pr = load_r(c1, kc);
-            pa0 = load_a(c1, kc, 0);
-            pa1 = load_a(c1, kc, 1);
+            next_chunk();
+            pr = load_r(kc);
+            pa0 = load_a(kc, 0);
+            pa1 = load_a(kc, 1);
         }
 #pragma unroll
         for (int k4 = 0; k4 < kSnapKC; k4 += 4) {
@@ -367,59 +385,119 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
 // y_k = y0 - W A_k with W = Q^T K~ and y0 = Q^T g~ (range basis Q, rank_r > 0), or W = K~ and
 // y0 = g~ (rank_r = 0: y_k = g~ - K~ A_k).  The float32 sampler's carried residual drifts
 // between refreshes (its zero modes are float32 roundings of exact null vectors, and K~ is
-// ill-conditioned), so the VJP's moments take the residual of the state, in float64.  A
-// workgroup of 4 wavefronts takes 16 rows; wavefront w forms the 16-column tiles w, w + 4, ...
-// of y by MFMA f64 16x16x4 over the N components, read from the A snapshot rows.
+// ill-conditioned), so the VJP's moments take the residual of the state, in float64.
+// A (rows x N, float32) times W^T (N x Mx): a workgroup of 4 wavefronts owns 64 rows and up
+// to 128 columns (column group blockIdx.y); the grid points pass through LDS in chunks of
+// kProjKC, the A rows (64 x kProjKC floats, rows padded to kProjLDA words against bank
+// conflicts) and the map (kProjKC x 128 doubles, n-major as stored), the next chunk loaded
+// into registers while the current one is multiplied.  Wavefront w forms rows 16 w .. 16 w + 15
+// by MFMA f64 16x16x4, one accumulator per 16 columns.
+constexpr int kProjKC = 32, kProjLDA = 36, kProjCols = 128;
+
 __global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t nsnap, const double *WY,
                                                  const float *snapA, float *yrow) {
-    const ProbDesc pd = probs[blockIdx.y];
+    __shared__ __align__(16) float sA[64 * kProjLDA];
+    __shared__ __align__(16) double sW[kProjKC * kProjCols];
+    const ProbDesc pd = probs[blockIdx.z];
     const int64_t N = pd.N, Mx = pd.rank_r > 0 ? pd.rank_r : pd.M, rows = nsnap * pd.C;
     const int64_t ldr = (pd.M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
-    const int64_t k0 = (int64_t)blockIdx.x * 16;
-    if (k0 >= rows) return;
+    const int64_t r0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * kProjCols;
+    if (r0 >= rows || j0 >= Mx) return;
+    const int ncol = (int)min<int64_t>(kProjCols, Mx - j0);   // columns of this group
+    const int ncb = (ncol + 15) / 16;                          // 16-column MFMA blocks
     const float *Ab = snapA + pd.off_sa;
     float *Yb = yrow + pd.off_sr;
-    const double *W = WY + pd.off_w, *y0 = WY + pd.off_w + Mx * N;
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const double *WT = WY + pd.off_w, *y0 = WY + pd.off_w + Mx * N;   // WT[n Mx + j]
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int i = lane % 16, kk = lane / 16;
-    const int64_t ka = k0 + i;
-    const bool oka = ka < rows;
-    for (int64_t jt = 16 * wave; jt < Mx; jt += 64) {
-        const int64_t jb = jt + i;
-        const bool okb = jb < Mx;
-        d4 acc = {0, 0, 0, 0};
-        for (int64_t n = 0; n < N; n += 4) {
-            const int64_t nn = n + kk;
-            const double av = (oka && nn < N) ? (double)Ab[ka * lda + nn] : 0.0;
-            const double bv = (okb && nn < N) ? W[jb * N + nn] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    // staging: A, 64 rows x 8 float4 (two per thread); the map, kProjKC x ncol doubles as
+    // double2 words (up to eight per thread)
+    float4 pa[2];
+    double2 pw[8];
+    auto load = [&](int64_t n0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h, row = e / 8, c4 = e % 8;
+            const int64_t r = r0 + row, n = n0 + 4 * c4;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < rows && n < lda) v = *reinterpret_cast<const float4 *>(Ab + r * lda + n);
+            if (n + 0 >= N) v.x = 0.f;
+            if (n + 1 >= N) v.y = 0.f;
+            if (n + 2 >= N) v.z = 0.f;
+            if (n + 3 >= N) v.w = 0.f;
+            pa[h] = v;
         }
-        const int64_t col = jt + lane % 16;
+        const int half = (ncol + 1) / 2;   // double2 words per grid point
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, k = e / (kProjCols / 2), c2 = e % (kProjCols / 2);
+            double2 v = make_double2(0.0, 0.0);
+            const int64_t n = n0 + k;
+            if (k < kProjKC && c2 < half && n < N) {
+                const int64_t j = j0 + 2 * c2;
+                v.x = WT[n * Mx + j];
+                v.y = (2 * c2 + 1 < ncol) ? WT[n * Mx + j + 1] : 0.0;
+            }
+            pw[h] = v;
+        }
+    };
+    d4 acc[kProjCols / 16];
+#pragma unroll
+    for (int c = 0; c < kProjCols / 16; ++c) acc[c] = d4{0, 0, 0, 0};
+    load(0);
+    for (int64_t n0 = 0; n0 < N; n0 += kProjKC) {
+        __syncthreads();   // the previous chunk is consumed
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h, row = e / 8, c4 = e % 8;
+            *reinterpret_cast<float4 *>(sA + row * kProjLDA + 4 * c4) = pa[h];
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, k = e / (kProjCols / 2), c2 = e % (kProjCols / 2);
+            if (k < kProjKC) *reinterpret_cast<double2 *>(sW + k * kProjCols + 2 * c2) = pw[h];
+        }
+        __syncthreads();
+        if (n0 + kProjKC < N) load(n0 + kProjKC);
+#pragma unroll
+        for (int k4 = 0; k4 < kProjKC; k4 += 4) {
+            const double av = (double)sA[(16 * wave + i) * kProjLDA + k4 + kk];
+#pragma unroll
+            for (int c = 0; c < kProjCols / 16; ++c)
+                if (c < ncb) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sW[(k4 + kk) * kProjCols + 16 * c + i],
+                                                                          acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kProjCols / 16; ++c) {
+        if (c >= ncb) continue;
+        const int64_t col = j0 + 16 * c + lane % 16;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t row = k0 + lane / 16 + 4 * j;
-            if (row < rows && col < Mx) Yb[row * ldr + col] = (float)(y0[col] - acc[j]);
+            const int64_t row = r0 + 16 * wave + lane / 16 + 4 * j;
+            if (row < rows && col < Mx) Yb[row * ldr + col] = (float)(y0[col] - acc[c][j]);
         }
     }
 }
 
-hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t nsnap, const double *WY,
-                          const float *snapA, float *yrow, hipStream_t s) {
-    if (max_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + 15) / 16), (unsigned)P), dim3(256), 0, s, probs_dev,
-                       nsnap, WY, snapA, yrow);
+hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t max_mx, int64_t nsnap,
+                          const double *WY, const float *snapA, float *yrow, hipStream_t s) {
+    if (max_rows <= 0 || max_mx <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + 63) / 64), (unsigned)((max_mx + kProjCols - 1) / kProjCols),
+                                       (unsigned)P),
+                       dim3(256), 0, s, probs_dev, nsnap, WY, snapA, yrow);
     return hipGetLastError();
 }
 
-// [W | y0] of every problem for k_project: W = Q^T K~ (Mx x N, row j at off_w + j N) and
-// y0 = Q^T g~ (at off_w + Mx N), or K~ and g~ themselves without a range basis; one thread
-// per entry.
+// [W^T | y0] of every problem for k_project: W = Q^T K~ (Mx x N), stored n-major (entry
+// (j, n) at off_w + n Mx + j), and y0 = Q^T g~ (at off_w + N Mx), or K~ and g~ themselves
+// without a range basis; one thread per entry.
 __global__ void k_resid_map(const ProbDesc *probs, const double *Kt, const double *gt, const double *Q, double *WY) {
     const ProbDesc pd = probs[blockIdx.y];
     const int64_t M = pd.M, N = pd.N, Mx = pd.rank_r > 0 ? pd.rank_r : M;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Mx * (N + 1)) return;
-    const int64_t j = e / (N + 1), n = e % (N + 1);
+    const int64_t n = e / Mx, j = e % Mx;   // n = N: the entry of y0
     const double *K = Kt + pd.off_K, *g = gt + pd.off_m;
     double x;
     if (pd.rank_r > 0) {
@@ -429,10 +507,7 @@ __global__ void k_resid_map(const ProbDesc *probs, const double *Kt, const doubl
     } else {
         x = n < N ? K[j * N + n] : g[j];
     }
-    if (n < N)
-        WY[pd.off_w + j * N + n] = x;
-    else
-        WY[pd.off_w + Mx * N + j] = x;
+    WY[pd.off_w + n * Mx + j] = x;
 }
 
 hipError_t launch_resid_map(const ProbDesc *probs_dev, int64_t P, int64_t max_entries, const double *Kt,
