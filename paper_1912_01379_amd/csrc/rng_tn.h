@@ -7,9 +7,8 @@
 //   E(a, t) = int_0^t exp(-a s - s^2/2) ds = m(a) - m(a + t) exp(-t (a + t/2)),
 // and for small t (where the difference cancels) the series
 //   E(a, t) = sum_j (-1/2)^j / j! t^(2j+1) M_2j(a t),  M_k(z) = int_0^1 v^k e^(-z v) dv.
-// The float64 instance converges Newton's method to full precision (it is held to
-// trajectory parity with the CPU reference); the float32 instance starts from a closed
-// form and takes a few steps.
+// It is solved by Newton's method to full float64 precision (the float64 sampler is held to
+// trajectory parity with the CPU reference); the float32 samplers use tn32.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -76,28 +75,17 @@ __device__ __forceinline__ float word_u32(uint32_t w) {
 }
 
 // ------------------------------------------------------------------------------------
-// precision-generic math wrappers
+// math wrappers of the float64 draw
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
-__device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
-__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
-__device__ __forceinline__ float m_log(float x) { return logf(x); }
 __device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double m_erfcx(double x) { return erfcx(x); }
-__device__ __forceinline__ float m_erfcx(float x) { return erfcxf(x); }
 __device__ __forceinline__ double m_erf(double x) { return erf(x); }
-__device__ __forceinline__ float m_erf(float x) { return erff(x); }
 __device__ __forceinline__ double m_erfc(double x) { return erfc(x); }
-__device__ __forceinline__ float m_erfc(float x) { return erfcf(x); }
-__device__ __forceinline__ double m_erfcinv(double x) { return erfcinv(x); }
-__device__ __forceinline__ float m_erfcinv(float x) { return erfcinvf(x); }
 __device__ __forceinline__ double m_abs(double x) { return fabs(x); }
-__device__ __forceinline__ float m_abs(float x) { return fabsf(x); }
 __device__ __forceinline__ bool m_isinf(double x) { return __builtin_isinf(x); }
-__device__ __forceinline__ bool m_isinf(float x) { return __builtin_isinf(x); }
 
 template <typename T>
 struct TnCfg;
@@ -107,15 +95,6 @@ struct TnCfg<double> {
     static constexpr int terms = 10;             // terms of the series
     static constexpr int max_iter = 100;
     static constexpr double tol = 4e-16;
-    static constexpr bool precise = true;
-};
-template <>
-struct TnCfg<float> {
-    static constexpr float series_max = 0.05f;
-    static constexpr int terms = 3;
-    static constexpr int max_iter = 8;
-    static constexpr float tol = 3e-7f;
-    static constexpr bool precise = false;
 };
 
 // Mills ratio Q(x)/phi(x) = sqrt(pi/2) erfcx(x/sqrt 2), x >= 0
@@ -128,27 +107,15 @@ __device__ __forceinline__ T mills(T x) {
 template <typename T>
 __device__ T moment_k(int k, T z) {
     if (k == 0) return (z == T(0)) ? T(1) : -m_expm1(-z) / z;
-    if (TnCfg<T>::precise) {
-        if (z <= T(50)) {
-            // e^-z sum_j z^j / ((k+1)(k+2)...(k+1+j)), all terms positive
-            T term = T(1) / T(k + 1), sum = term;
-            for (int j = 1; j < 400; ++j) {
-                term *= z / T(k + 1 + j);
-                sum += term;
-                if (term < T(1e-18) * sum) break;
-            }
-            return m_exp(-z) * sum;
+    if (z <= T(50)) {
+        // e^-z sum_j z^j / ((k+1)(k+2)...(k+1+j)), all terms positive
+        T term = T(1) / T(k + 1), sum = term;
+        for (int j = 1; j < 400; ++j) {
+            term *= z / T(k + 1 + j);
+            sum += term;
+            if (term < T(1e-18) * sum) break;
         }
-    } else {
-        if (z <= T(1)) {
-            // sum_j (-z)^j / (j! (k+1+j))
-            T zj = T(1), sum = T(0);
-            for (int j = 0; j < 12; ++j) {
-                sum += zj / T(k + 1 + j);
-                zj *= -z / T(j + 1);
-            }
-            return sum;
-        }
+        return m_exp(-z) * sum;
     }
     // k!/z^(k+1) (1 - e^-z sum_{j<=k} z^j/j!)
     T fact = T(1), poly = T(1), zj = T(1), zk = z;
@@ -191,15 +158,6 @@ __device__ T tn_onesided(T a, T w, T u, T uc) {
         if (ts > tl && ts < th) t = ts;
     } else if (w < T(1)) {
         t = u * w;
-    }
-    if (!TnCfg<T>::precise && a <= T(4) && w > TnCfg<T>::series_max) {
-        // closed-form start from the normal distribution function (float32 only)
-        const T qa = T(0.5) * m_erfc(a * T(0.70710678118654752440));
-        const T qb = m_isinf(w) ? T(0) : T(0.5) * m_erfc((a + w) * T(0.70710678118654752440));
-        const T p = lower ? (qa - u * (qa - qb)) : (qb + uc * (qa - qb));
-        const T x = T(1.41421356237309504880) * m_erfcinv(T(2) * p);
-        const T ts = x - a;
-        if (ts > tl && ts < th) t = ts;
     }
     if (lower) {
         const T target = u * Ew;
@@ -254,89 +212,6 @@ __device__ T tn_draw(T c, T d, T lo, T hi, T u) {
         } else {
             delta = (c + tn_onesided<T>(T(0), b, (q - pl) / pr, (uc * tot) / pr)) / d;
         }
-    }
-    delta = delta < lo ? lo : delta;
-    delta = delta > hi ? hi : delta;
-    return delta;
-}
-
-// ------------------------------------------------------------------------------------
-// float32 draw for the batched sampler: the same distribution, from closed forms instead
-// of an iteration, accurate to a few float32 ulps of the quantile in the bulk and to a few
-// 1e-5 of the interval where the interval is short in units of the Gaussian width.
-//   * short interval (w = d (hi - lo) below max(1e-3, (1e-6 max|a|,|b|)^(1/3))): over
-//     [a, b] the log-density is linear up to a quadratic remainder below w^2/8, so t is
-//     drawn from the exponential with the midpoint slope lambda = a + w/2;
-//   * interval on one side of the centre with its near end a <= 8: inversion of the upper
-//     tail Q(x) = erfc(x/sqrt2)/2 between Q(a) and Q(b);
-//   * near end a > 8: the tail ratio Q(a+t)/Q(a) = exp(-t(a+t/2)) m(a+t)/m(a) is inverted by
-//     two Newton steps in log space from the exponential start;
-//   * centre inside the interval: inversion of Phi between Phi(a) and Phi(b).
-// ------------------------------------------------------------------------------------
-__device__ __forceinline__ float tn_expo_f32(float lam, float w, float u, float uc) {
-    // t in [0, w] with density prop. to exp(-lam t), by inversion (lam of either sign)
-    const float x = lam * w;
-    if (fabsf(x) < 1e-6f) return u * w;
-    if (lam > 0.0f) return -log1pf(u * expm1f(-x)) / lam;
-    // increasing density: invert from the far end
-    return w - log1pf(uc * expm1f(x)) / lam;
-}
-
-__device__ __forceinline__ float tn_upper_f32(float a, float w, float u, float uc) {
-    // t in [0, w] with density prop. to exp(-a t - t^2/2), a >= 0, w > 1e-3
-    const float s2 = 0.70710678118654752440f;
-    if (a <= 8.0f) {
-        const float qa = 0.5f * erfcf(a * s2);
-        const float qb = __builtin_isinf(w) ? 0.0f : 0.5f * erfcf((a + w) * s2);
-        const float p = (u <= 0.5f) ? qa - u * (qa - qb) : qb + uc * (qa - qb);
-        const float x = 1.41421356237309504880f * erfcinvf(2.0f * p);
-        const float t = x - a;
-        return t < 0.0f ? 0.0f : (t > w ? w : t);
-    }
-    // far tail: log Q(a+t) - log Q(a) = -t(a + t/2) + log(m(a+t)/m(a))
-    const float ma = mills(a);
-    const float lr = __builtin_isinf(w) ? -INFINITY
-                                         : -w * (a + 0.5f * w) + logf(mills(a + w) / ma);
-    // target log-ratio log(1 - u (1 - R)), R = exp(lr)
-    const float target = log1pf(-u * (-expm1f(lr)));
-    float t = -target / a;
-    for (int k = 0; k < 2; ++k) {
-        const float mt = mills(a + t);
-        const float g = -t * (a + 0.5f * t) + logf(mt / ma) - target;
-        t = t + g * mt;   // d/dt log Q(a+t) = -1/m(a+t)
-    }
-    return t < 0.0f ? 0.0f : (t > w ? w : t);
-}
-
-__device__ __forceinline__ float tn_draw_fast32(float c, float d, float lo, float hi, float u) {
-    if (lo == hi) return lo;
-    const float uc = 1.0f - u;
-    const float a = d * lo - c;
-    const float b = d * hi - c;
-    const float w = d * (hi - lo);
-    float delta;
-    // the exponential form errs by about w^2/16 of the interval, inversion from the ends by
-    // about eps |a| / w: take the exponential where it is the better of the two
-    const float far = fmaxf(fabsf(a), fabsf(b));
-    if (w < fmaxf(1e-3f, cbrtf(1e-6f * far))) {
-        const float lam = a + 0.5f * w;
-        delta = lo + tn_expo_f32(lam, w, u, uc) / d;
-    } else if (a >= 0.0f) {
-        delta = lo + tn_upper_f32(a, w, u, uc) / d;
-    } else if (b <= 0.0f) {
-        delta = hi - tn_upper_f32(-b, w, uc, u) / d;
-    } else {
-        const float s2 = 0.70710678118654752440f;
-        const float pa = 0.5f * erfcf(-a * s2);                                  // Phi(a)
-        const float qb = __builtin_isinf(b) ? 0.0f : 0.5f * erfcf(b * s2);       // Q(b)
-        const float mass = (1.0f - pa) - qb;
-        const float plo = pa + u * mass;
-        float x;
-        if (plo <= 0.5f)
-            x = -1.41421356237309504880f * erfcinvf(2.0f * plo);
-        else
-            x = 1.41421356237309504880f * erfcinvf(2.0f * (qb + uc * mass));
-        delta = (x + c) / d;
     }
     delta = delta < lo ? lo : delta;
     delta = delta > hi ? hi : delta;

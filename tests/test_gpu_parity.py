@@ -121,8 +121,12 @@ def test_covariance_whitening_matches_oracle(pk, orc):
 # float64 trajectory parity (same random numbers, independent decompositions)
 # --------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("M,N,nblocks,seed", [(40, 24, 2, 11), (10, 24, 2, 5), (12, 30, 3, 9)])
+@pytest.mark.parametrize("M,N,nblocks,seed", [(40, 24, 2, 11), (10, 24, 2, 5), (12, 30, 3, 9),
+                                               (150, 100, 1, 21)])
 def test_fp64_trajectory_matches_oracle(pk, orc, M, N, nblocks, seed):
+    """Move by move against the oracle for 1000 sweeps; the last case (one block of 100 grid
+    points, 150 data points, no null space) takes the float64 sampler's strided pass over
+    blocks and residuals longer than a wavefront."""
     p = workloads.random_wellconditioned(M=M, N=N, nblocks=nblocks, seed=seed)
     prep = orc.prepare(p)
     sweeps = 1000
@@ -141,6 +145,47 @@ def test_fp64_trajectory_matches_oracle(pk, orc, M, N, nblocks, seed):
             assert abs(float(chi2[0]) - ores.traj_chi2[s]) <= 1e-10 * ores.traj_chi2[s]
     assert worst < 1e-10, worst
     plan.close()
+
+
+def test_empty_intervals_from_the_zero_model(pk, orc):
+    """From A = 0 every mode whose V has entries of both signs has the empty interval
+    lo = hi = 0 (Eq. (modeLimits)): the float64 sampler follows the oracle move by move,
+    counting the same empty intervals, and one float32 sweep lands where the oracle's does."""
+    p = workloads.random_wellconditioned(M=40, N=24, nblocks=2, seed=11)
+    p.init = np.zeros(p.K.shape[1])
+    prep = orc.prepare(p)
+    sweeps = 20
+    ores = orc.run(prep, chains=1, burnin=0, sweeps=sweeps, refresh_every=16, groups=1, traj_chain=0,
+                   seed=7, init=p.init)
+    assert ores.n_frozen > 0
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=sweeps, seed=7, precision="fp64", refresh_every=16, groups=1)
+    res = plan.run()
+    A, _, _ = plan.state(0)
+    a = A[0].cpu().numpy()
+    ref = ores.final_A[0]
+    assert np.max(np.abs(a - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+    assert res.stats["frozen"] == ores.n_frozen
+    plan.close()
+    o1 = orc.run(prep, chains=1, burnin=0, sweeps=1, refresh_every=16, groups=1, seed=7, init=p.init)
+    plan = pk.Plan([p], chains=1, burnin=0, sweeps=1, seed=7, precision="fp32", refresh_every=16, groups=1,
+                   lanes_per_chain=8)
+    plan.advance(1)
+    A, _, _ = plan.state(0)
+    a = A[0].cpu().numpy()
+    ref = o1.final_A[0]
+    assert np.all(a >= 0.0)
+    assert np.max(np.abs(a - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+    plan.close()
+
+
+def test_two_roles_refuse_a_constraint(pk):
+    """The two-role sampler runs every mode of a block: a constrained problem (one mode fewer)
+    is refused when two roles are requested."""
+    p = workloads.config2()
+    p.constraint_c = np.asarray(p.weights, np.float64)
+    p.constraint_value = 1.0
+    with pytest.raises(pk.AsmError, match="two roles"):
+        pk.Plan([p], chains=256, burnin=0, sweeps=1, precision="fp32", roles=2)
 
 
 # --------------------------------------------------------------------------------------
