@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <map>
 #include <mutex>
@@ -69,17 +70,12 @@ struct asm_plan {
     int64_t max_mx = 0;       // the largest number of residual coordinates over the problems
     bool any_rank = false;    // a problem whose moments are taken in its range basis
     double *vjp_scratch = nullptr;
-    // float32 plans: per-sweep snapshots of A (and of r with want_vjp) of the accumulated
-    // sweeps, reduced after each launch into the sums of A and A^2 (and the cross moments);
-    // two snapshot buffers: the sampler fills one while the other is reduced on a second
-    // stream (xstream), ordered by events
-    float *snapA[2] = {nullptr, nullptr}, *snapR[2] = {nullptr, nullptr};
-    int64_t *snap_first = nullptr;   // per buffer: the sweep of its first row (device)
+    // float32 plans with want_vjp: per-sweep snapshots of A of the accumulated sweeps of a
+    // launch, and the residual coordinates formed from them, reduced after each launch into
+    // the cross moments on the sampler's stream
+    float *snapA = nullptr, *snapR = nullptr;
+    int64_t *snap_first = nullptr;   // the sweep of the first snapshot row (device)
     int64_t snap_rows = 0, max_snap_tiles = 0, snap_words_a = 0, snap_words_r = 0;
-    hipStream_t xstream = nullptr;
-    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
-    bool pending[2] = {false, false};
-    int snap_par = 0;
     int64_t max_nb = 0, max_nbp = 0, max_kb = 0, max_n = 0;
     int64_t lds_off_d = 0, lds_off_u = 0, lds_off_unif = 0, lds_off_ce = 0;   // float32 sampler LDS
     int32_t kce = 4;
@@ -145,6 +141,7 @@ struct asm_plan {
     // use_graph: one refresh cycle of the float32 sampler captured per kind (burn-in or
     // accumulating, with or without VJP snapshots) and replayed; recaptured per run
     hipGraphExec_t gexec[8] = {};
+    hipGraphExec_t gexec_refresh = nullptr;   // the refresh of a cycle, replayed after the sampler
     int64_t gburnin[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
     hipStream_t gstream = nullptr;   // capture stream when the plan's stream is the null stream
     int64_t graph_replays = 0;
@@ -394,12 +391,12 @@ int refresh(asm_plan *pl, bool measure_drift) {
 }
 
 // One segment of nsw sweeps starting at the device sweep counter; advances the counter.
-int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool snap, int par = 0) {
+int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool snap) {
     SampleArgs a = make_args(pl);
     if (snap) {
-        a.snapA = pl->snapA[par];
+        a.snapA = pl->snapA;
         a.snap_rows = pl->snap_rows;
-        a.snap_first = pl->snap_first + par;
+        a.snap_first = pl->snap_first;
     }
     a.nsw = nsw;
     a.accumulate = accumulate;
@@ -440,85 +437,81 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
 // when the plan's stream is the null stream.
 hipStream_t main_stream(asm_plan *pl) { return pl->stream ? pl->stream : (pl->gstream ? pl->gstream : pl->stream); }
 
-constexpr bool kOverlapMoments = false;
-
-// Before the sampler writes snapshot buffer `par`: the main stream waits until the previous
-// reduction of that buffer is done.
-int snap_acquire(asm_plan *pl, int par) {
-    if (pl->pending[par]) HIPCHK(hipStreamWaitEvent(main_stream(pl), pl->ev_done[par], 0));
-    return ASM_OK;
-}
-
-// After the sampler wrote snapshot buffer `par` (nsnap sweeps): reduce it into the cross
-// moments on the second stream, after the main stream's work so far.
-int snap_release(asm_plan *pl, int par, int64_t nsnap, int64_t burnin_abs) {
-    hipStream_t xs = kOverlapMoments ? pl->xstream : main_stream(pl);
-    if (kOverlapMoments) {
-        HIPCHK(hipEventRecord(pl->ev_ready[par], main_stream(pl)));
-        HIPCHK(hipStreamWaitEvent(pl->xstream, pl->ev_ready[par], 0));
-    }
-    HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, pl->max_mx, nsnap, pl->WY, pl->snapA[par],
-                          pl->snapR[par], xs));
+// After the sampler wrote the snapshots of nsnap sweeps: the residual coordinates of every
+// snapshot state, then their cross moments with A, on the sampler's stream (beside the
+// sampler, whose launches hold the register file, they only stretched its launches).
+int snap_reduce(asm_plan *pl, int64_t nsnap, int64_t burnin_abs) {
+    hipStream_t ms = main_stream(pl);
+    HIPCHK(launch_project(pl->d_probs, pl->P, nsnap * pl->opt.chains, pl->max_mx, nsnap, pl->WY, pl->snapA,
+                          pl->snapR, ms));
     HIPCHK(launch_cross_snap(pl->d_probs, pl->P, pl->max_snap_tiles, (int)pl->opt.groups, pl->parts, nsnap,
-                             pl->snapA[par], pl->snapR[par], pl->snap_first + par, burnin_abs, pl->opt.sweeps,
-                             pl->cross, xs));
-    if (kOverlapMoments) {
-        HIPCHK(hipEventRecord(pl->ev_done[par], pl->xstream));
-        pl->pending[par] = true;
-    }
-    return ASM_OK;
-}
-
-// The caller's stream waits for every pending cross-moment reduction.
-int snap_join(asm_plan *pl) {
-    for (int j = 0; j < 2; ++j) {
-        if (!pl->pending[j]) continue;
-        HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_done[j], 0));
-        if (pl->gstream) HIPCHK(hipStreamWaitEvent(pl->gstream, pl->ev_done[j], 0));
-        pl->pending[j] = false;
-    }
+                             pl->snapA, pl->snapR, pl->snap_first, burnin_abs, pl->opt.sweeps, pl->cross, ms));
     return ASM_OK;
 }
 
 // One refresh cycle of the float32 sampler (R sweeps starting at a multiple of R): the
-// sampler launch (writing snapshot buffer `par` when snap), the sweep-counter bump and the
-// float64 refresh.  With use_graph the cycle is captured once per run, kind and buffer and
-// replayed; it holds kernel launches only (no memsets, no host work), and every argument is
-// the same for each cycle of the run (the kernels read the sweep counter from device memory).
-int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap, int par) {
-    auto body = [&]() -> int {
-        TRY(segment(pl, R, accumulate, burnin_abs, snap, par));
+// sampler launch (writing the snapshots when snap), the sweep-counter bump and the
+// float64 refresh.  With use_graph the sampler and bump are captured once per run and kind,
+// and the refresh once per plan, as two graphs replayed one after the other (the
+// sampler graph between timing events); they hold kernel launches only (no memsets, no host
+// work), and every argument is the same for each cycle of the run (the kernels read the
+// sweep counter from device memory).
+int capture(asm_plan *pl, hipGraphExec_t *exec, const std::function<int()> &body) {
+    if (!pl->stream && !pl->gstream) HIPCHK(hipStreamCreate(&pl->gstream));
+    // capture on the plan's stream, or on a private stream when that is the null stream
+    hipStream_t user = pl->stream;
+    pl->stream = main_stream(pl);
+    const bool timing = pl->timing;
+    pl->timing = false;
+    HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeRelaxed));
+    const int brc = body();
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(pl->stream, &g);
+    pl->timing = timing;
+    pl->stream = user;
+    if (brc != ASM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return brc;
+    }
+    HIPCHK(ee);
+    const hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(ie);
+    return ASM_OK;
+}
+
+int cycle(asm_plan *pl, int64_t R, int accumulate, int64_t burnin_abs, bool snap) {
+    if (!pl->opt.use_graph) {
+        TRY(segment(pl, R, accumulate, burnin_abs, snap));
         TRY(refresh(pl, true));
         return ASM_OK;
-    };
-    if (!pl->opt.use_graph) return body();
-    if (!pl->stream && !pl->gstream) HIPCHK(hipStreamCreate(&pl->gstream));
-    const int key = (accumulate ? 1 : 0) | (snap ? 2 : 0) | (snap && par ? 4 : 0);
+    }
+    const int key = (accumulate ? 1 : 0) | (snap ? 2 : 0);
     if (!pl->gexec[key] || pl->gburnin[key] != burnin_abs) {
         if (pl->gexec[key]) HIPCHK(hipGraphExecDestroy(pl->gexec[key]));
         pl->gexec[key] = nullptr;
-        // capture on the plan's stream, or on a private stream when that is the null stream
-        hipStream_t user = pl->stream;
-        pl->stream = main_stream(pl);
-        const bool timing = pl->timing;
-        pl->timing = false;
-        HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeRelaxed));
-        const int brc = body();
-        hipGraph_t g = nullptr;
-        const hipError_t ee = hipStreamEndCapture(pl->stream, &g);
-        pl->timing = timing;
-        pl->stream = user;
-        if (brc != ASM_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return brc;
-        }
-        HIPCHK(ee);
-        const hipError_t ie = hipGraphInstantiate(&pl->gexec[key], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIPCHK(ie);
+        TRY(capture(pl, &pl->gexec[key], [&]() { return segment(pl, R, accumulate, burnin_abs, snap); }));
         pl->gburnin[key] = burnin_abs;
     }
-    HIPCHK(hipGraphLaunch(pl->gexec[key], main_stream(pl)));
+    if (!pl->gexec_refresh) TRY(capture(pl, &pl->gexec_refresh, [&]() { return refresh(pl, true); }));
+    hipStream_t ms = main_stream(pl);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pl->timing) {
+        while (pl->tev.size() < pl->tev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            pl->tev.push_back(e);
+        }
+        e0 = pl->tev[pl->tev_used++];
+        e1 = pl->tev[pl->tev_used++];
+        HIPCHK(hipEventRecord(e0, ms));
+    }
+    HIPCHK(hipGraphLaunch(pl->gexec[key], ms));
+    if (pl->timing) {
+        HIPCHK(hipEventRecord(e1, ms));
+        pl->timed_sweeps += R;
+    }
+    HIPCHK(hipGraphLaunch(pl->gexec_refresh, ms));
     ++pl->graph_replays;
     return ASM_OK;
 }
@@ -529,7 +522,7 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     const int64_t end = pl->sweep + total;
     const bool vjp = accumulate && pl->opt.want_vjp;
     const bool snapping = vjp && pl->fp32;   // float32: the cross moments come from snapshots
-    if (snapping && !pl->snapA[0]) return fail(ASM_ESTATE, "plan has no snapshot buffers");
+    if (snapping && !pl->snapA) return fail(ASM_ESTATE, "plan has no snapshot buffers");
     while (pl->sweep < end) {
         const int64_t s = pl->sweep;
         // whole refresh cycles of the float32 sampler go through cycle() (a graph replay with
@@ -537,15 +530,8 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         if (pl->fp32 && R > 0 && s % R == 0 && s + R <= end && (s >= burnin_abs || s + R <= burnin_abs) &&
             (!(snapping && s >= burnin_abs) || pl->snap_rows >= R)) {
             const bool snap = snapping && s >= burnin_abs;
-            const int par = pl->snap_par;
-            if (snap) TRY(snap_acquire(pl, par));
-            TRY(cycle(pl, R, accumulate, burnin_abs, snap, par));
-            if (snap) {
-                // the cycle's refresh comes after the sampler; the reduction only needs the
-                // sampler's snapshots, but waiting for the whole cycle costs nothing
-                TRY(snap_release(pl, par, R, burnin_abs));
-                pl->snap_par ^= 1;
-            }
+            TRY(cycle(pl, R, accumulate, burnin_abs, snap));
+            if (snap) TRY(snap_reduce(pl, R, burnin_abs));
             pl->sweep += R;
             continue;
         }
@@ -559,13 +545,10 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         else if (vjp && s >= burnin_abs) seg = 1;
         if (seg < 1) seg = 1;
         const bool snap = snapping && s >= burnin_abs;
-        const int par = pl->snap_par;
-        if (snap) TRY(snap_acquire(pl, par));
-        TRY(segment(pl, seg, accumulate, burnin_abs, snap, par));
+        TRY(segment(pl, seg, accumulate, burnin_abs, snap));
         pl->sweep += seg;
         if (snap) {
-            TRY(snap_release(pl, par, seg, burnin_abs));
-            pl->snap_par ^= 1;
+            TRY(snap_reduce(pl, seg, burnin_abs));
         } else if (vjp && s >= burnin_abs) {
             // the sweep just sampled: its chain groups, or its batch of sweeps
             const int bgroup = pl->opt.chains < pl->opt.groups
@@ -575,7 +558,6 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
         }
         if (pl->fp32 && R > 0 && pl->sweep % R == 0) TRY(refresh(pl, true));
     }
-    TRY(snap_join(pl));
     return ASM_OK;
 }
 
@@ -715,15 +697,10 @@ int asm_hierarchy(int64_t N, int64_t max_block, int64_t *levels, int64_t *n_star
 
 int asm_plan_destroy(asm_plan *pl) {
     if (!pl) return ASM_OK;
+    if (pl->gexec_refresh) (void)hipGraphExecDestroy(pl->gexec_refresh);
     for (auto &g : pl->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
-    if (pl->xstream) (void)hipStreamSynchronize(pl->xstream);
-    for (int j = 0; j < 2; ++j) {
-        if (pl->ev_ready[j]) (void)hipEventDestroy(pl->ev_ready[j]);
-        if (pl->ev_done[j]) (void)hipEventDestroy(pl->ev_done[j]);
-    }
-    if (pl->xstream) (void)hipStreamDestroy(pl->xstream);
     for (auto &e : pl->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : pl->tev) (void)hipEventDestroy(e);
@@ -926,12 +903,13 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     pl->total_m = offm;
     if (pl->fp32 && o->want_vjp && !t_probe_plan) {
-        // the cross moments of the VJP come from per-sweep snapshots of A and r: two buffers
-        // for every accumulated sweep of a launch (at most refresh_every or 64 sweeps, and at
-        // most half of the free device memory together), rows padded to whole 16-byte words
+        // the cross moments of the VJP come from per-sweep snapshots of A and the residual
+        // coordinates formed from them: rows for every accumulated sweep of a launch (at most
+        // refresh_every or 64 sweeps, and at most half of the free device memory), padded to
+        // whole 16-byte words
         int64_t per_row = 0;
         for (auto &pd : pl->probs)
-            per_row += 2 * pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
+            per_row += pd.C * ((pd.N + 3) / 4 * 4 + (pd.M + 3) / 4 * 4) * (int64_t)sizeof(float);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
         (void)hipGetLastError();
@@ -1004,15 +982,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         STEP(dalloc(pl, &pl->r64, offr));
     }
     if (pl->fp32 && o->want_vjp && !t_probe_plan) {
-        for (int j = 0; j < 2; ++j) {
-            STEP(dalloc(pl, &pl->snapA[j], pl->snap_words_a));
-            STEP(dalloc(pl, &pl->snapR[j], pl->snap_words_r));
-            HSTEP(hipEventCreateWithFlags(&pl->ev_ready[j], hipEventDisableTiming));
-            HSTEP(hipEventCreateWithFlags(&pl->ev_done[j], hipEventDisableTiming));
-        }
-        STEP(dalloc(pl, &pl->snap_first, 2));
-        // default priority; non-blocking, so that null-stream work does not serialise it
-        HSTEP(hipStreamCreateWithFlags(&pl->xstream, hipStreamNonBlocking));
+        STEP(dalloc(pl, &pl->snapA, pl->snap_words_a));
+        STEP(dalloc(pl, &pl->snapR, pl->snap_words_r));
+        STEP(dalloc(pl, &pl->snap_first, 1));
     }
     if (o->want_vjp) STEP(dalloc(pl, &pl->vjp_scratch, vjp_scratch_doubles(n, offm, (int)G)));
     hipStream_t st = pl->stream;

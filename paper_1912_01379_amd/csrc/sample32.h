@@ -479,11 +479,13 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 if (active && q < p_nb) Ag[p_n0 + q] = Ap[t];
             }
             if (p_row >= 0) {
+                // the snapshot rows stream past the caches (written once, read after the
+                // launch), which keep the block factors the staging reads
                 float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0;
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) {
                     const int q = lane + L * t;
-                    if (active && q < p_nb) sa[q] = Ap[t];
+                    if (active && q < p_nb) __builtin_nontemporal_store(Ap[t], sa + q);
                 }
             }
         };

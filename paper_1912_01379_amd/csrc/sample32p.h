@@ -235,7 +235,7 @@ __device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP 
 #pragma unroll
             for (int t2 = 0; t2 < EPT; ++t2) {
                 const int q = lane + L * t2;
-                if (active && q < p_nb) sa[q] = Ap[t2];
+                if (active && q < p_nb) __builtin_nontemporal_store(Ap[t2], sa + q);
             }
         }
         p_nb = 0;
