@@ -476,11 +476,12 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int q = lane + L * t;
-                if (active && q < p_nb) Ag[p_n0 + q] = Ap[t];
+                if (active && q < p_nb) __builtin_nontemporal_store(Ap[t], Ag + p_n0 + q);
             }
             if (p_row >= 0) {
-                // the snapshot rows stream past the caches (written once, read after the
-                // launch), which keep the block factors the staging reads
+                // the chain state and the snapshot rows stream past the caches (the state is
+                // read a sweep later, the rows after the launch), which keep the block
+                // factors the staging reads
                 float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0;
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) {
@@ -577,7 +578,8 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     // compiler's wait counting inexact and nothing waits for them early.
                     bn = cload(a.blocks + pd.off_blk + (b + 1 < lc ? lf + b + 1 : nf));
 #pragma unroll
-                    for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
+                    for (int t = 0; t < EPT; ++t)
+                        An[t] = __builtin_nontemporal_load(Ag + bn.n0 + min(lane + L * t, (int)bn.nb - 1));
                     if (prefetch && (b + 1 < lc || s + 1 < s0 + nsw)) pf.load(a.F32 + bn.off_chunk, tid, nthr, nw);
                 }
                 // zero modes, three per iteration, each row loaded two moves ahead (the

@@ -161,7 +161,8 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
             if (!step) continue;
             if (B < 3 && t > 0) {
 #pragma unroll
-                for (int t2 = 0; t2 < EPT; ++t2) An[t2] = Ag[bd.n0 + min(lane + L * t2, nb - 1)];
+                for (int t2 = 0; t2 < EPT; ++t2)
+                    An[t2] = __builtin_nontemporal_load(Ag + bd.n0 + min(lane + L * t2, nb - 1));
             }
             float Ar[EPT];
 #pragma unroll
@@ -171,7 +172,8 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
                 const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < B ? b + 1 : 0));
                 if (B >= 3) {
 #pragma unroll
-                    for (int t2 = 0; t2 < EPT; ++t2) An[t2] = Ag[bn.n0 + min(lane + L * t2, (int)bn.nb - 1)];
+                    for (int t2 = 0; t2 < EPT; ++t2)
+                        An[t2] = __builtin_nontemporal_load(Ag + bn.n0 + min(lane + L * t2, (int)bn.nb - 1));
                 }
                 pfr.load(a.F32 + bn.off_chunk, tid, 256, a.p_wd);
                 pfu.load(a.F32 + bn.off_chunk + a.p_du_word, tid, 256, a.p_wu);
@@ -228,7 +230,7 @@ __device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP 
 #pragma unroll
         for (int t2 = 0; t2 < EPT; ++t2) {
             const int q = lane + L * t2;
-            if (active && q < p_nb) Ag[p_n0 + q] = Ap[t2];
+            if (active && q < p_nb) __builtin_nontemporal_store(Ap[t2], Ag + p_n0 + q);
         }
         if (p_row >= 0) {
             float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0;
