@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "tn32.h", "tn32_coef.h",
                    "rng_tn.h", "internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_{workload}_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_{workload}.md")
 WORKLOAD_FILE_NAMES = {"large": "large_config5", "single": "single_continuation"}
 
 
@@ -429,6 +429,7 @@ def main():
     ap.add_argument("--no-vjp", action="store_true")
     ap.add_argument("--no-overhead", action="store_true",
                     help="skip the untimed forward without the VJP's moments")
+    ap.add_argument("--no-split", action="store_true", help="skip the untimed split-half equilibration check")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true")
@@ -568,6 +569,30 @@ def one_problem(args):
         fwd_novjp_s = step(vjp=False)[1]
         print("forward without the VJP's moments done", file=sys.stderr, flush=True)
 
+    # equilibration (untimed): the same chains' averages over the first and the second half of
+    # the measured sweeps, z = |<A>_1 - <A>_2| / sqrt(se_1^2 + se_2^2) per grid point; a drift
+    # of the chains between the halves (a burn-in too short for the slowest points) shows as
+    # z well above the few units of chance
+    split = None
+    if not args.no_split:
+        plan = pk.Plan([dp], chains=chains, burnin=0, sweeps=sweeps // 2, seed=2025, precision="fp32",
+                       refresh_every=64, want_vjp=False, groups=32, lanes_per_chain=args.lanes, start="nnls",
+                       use_graph=use_graph, device=dev)
+        plan.advance(burnin)
+        h1 = plan.run()
+        m1, s1 = h1.mean.cpu().numpy(), h1.stderr.cpu().numpy()
+        h2 = plan.run()
+        m2, s2 = h2.mean.cpu().numpy(), h2.stderr.cpu().numpy()
+        plan.close()
+        z = np.abs(m1 - m2) / np.sqrt(s1 ** 2 + s2 ** 2)
+        ok = np.isfinite(z)
+        slow = np.argsort(np.where(np.isfinite(tau), tau, -1.0))[::-1][:10]
+        split = {"burnin": burnin, "sweeps_per_half": sweeps // 2, "max_z": float(np.max(z[ok])),
+                 "frac_z_above_3": float(np.mean(z[ok] > 3.0)), "median_z": float(np.median(z[ok])),
+                 "z_at_10_slowest_points": [round(float(z[i]), 2) for i in slow],
+                 "tau_int_at_10_slowest_points": [round(float(tau[i]), 1) for i in slow]}
+        print("split-half equilibration check done", file=sys.stderr, flush=True)
+
     # the plain sampler: float64, one chain per launch
     plain = pk.Plan([dp], chains=1, burnin=0, sweeps=20, seed=7, precision="fp64", groups=1,
                     device=dev)
@@ -614,6 +639,7 @@ def one_problem(args):
         "sampler_ms_per_step": st["sampler_ms"],
         "graph_replays": st["graph_replays"],
         "chi2_drift_max": st["chi2_drift_max"],
+        "split_half": split,
         "plain_fp64_mode_moves_per_s": plain_rate,
         "speedup_vs_plain": value / plain_rate,
     }
