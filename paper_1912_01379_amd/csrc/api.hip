@@ -62,7 +62,7 @@ struct asm_plan {
     std::vector<int32_t> slot_group;
     std::vector<double> slot_count;
     int64_t total_chains = 0, total_n = 0, total_m = 0;
-    int64_t max_refresh_tiles = 0, max_cross_tiles = 0, max_m = 0;
+    int64_t max_cross_tiles = 0, max_m = 0;
     int parts = 1;           // cross-moment partial sums per chain group (splits = groups x parts)
     int64_t cross_words = 0;
     double *Qb = nullptr;     // range bases of the problems' K~ (float32 plans with want_vjp)
@@ -381,7 +381,7 @@ int refresh(asm_plan *pl, bool measure_drift) {
     if (pl->fp32 && pl->any_con)   // float32 chains back onto c . A = F
         HIPCHK(launch_con_fix(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains, pl->con,
                               pl->A32, pl->stream));
-    HIPCHK(launch_refresh_all(pl->d_probs, pl->P, pl->max_refresh_tiles, pl->Kt, pl->gt, pl->A32,
+    HIPCHK(launch_refresh_all(pl->d_probs, pl->P, pl->opt.chains, pl->max_m, pl->Kt, pl->gt, pl->A32,
                               pl->r32, pl->A64, pl->r64, pl->fp32, pl->stream));
     HIPCHK(launch_rownorm(pl->d_probs, pl->d_chain_problem, pl->d_chain_local, pl->total_chains,
                           pl->r32, pl->r64, pl->fp32, pl->chi2,
@@ -884,7 +884,6 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         offc += C;
         if (pd.has_cov) offL += q.M * q.M;
         pl->max_m = std::max(pl->max_m, q.M);
-        pl->max_refresh_tiles = std::max(pl->max_refresh_tiles, ((C + 15) / 16) * ((q.M + 15) / 16));
         pl->max_cross_tiles = std::max(pl->max_cross_tiles, ((q.M + 31) / 32) * ((q.N + 32) / 32));
         pl->n_prefix.push_back(offn);
         pl->m_prefix.push_back(offm);

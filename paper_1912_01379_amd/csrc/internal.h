@@ -235,7 +235,7 @@ hipError_t launch_uniforms(uint64_t seed, int64_t problem, int64_t chain, int64_
                            hipStream_t s);
 
 // linalg.hip
-hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles,
+hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_c, int64_t max_m,
                               const double *Kt, const double *gt, const float *A32, float *r32,
                               const double *A64, double *r64, int fp32, hipStream_t s);
 hipError_t launch_rownorm(const ProbDesc *probs_dev, const int32_t *chain_problem,

@@ -19,53 +19,94 @@ __device__ __forceinline__ double load_state(const float *A32, const double *A64
     return fp32 ? (double)A32[i] : A64[i];
 }
 
-// D(16 chains x 16 rows) = A(16 x 4 grid points) * K~^T(4 x 16); MFMA f64 16x16x4 layouts:
-// operand a: lane l holds row l%16, k = l/16; operand b: lane l holds column l%16, k = l/16;
-// result: lane l, element j holds row l/16 + 4j, column l%16 (checked on the device).
-__global__ __launch_bounds__(256) void k_refresh(const ProbDesc *probs, const double *Kt,
-                                                 const double *gt, const float *A32, float *r32,
-                                                 const double *A64, double *r64, int fp32) {
-    const ProbDesc pd = probs[blockIdx.y];
+// MFMA f64 16x16x4 layouts (checked on the device): operand a: lane l holds row l%16, k = l/16;
+// operand b: lane l holds column l%16, k = l/16; result: lane l, element j holds row l/16 + 4j,
+// column l%16.
+//
+// Refresh: r_c = g~ - K~ A_c for every chain c, the (chains x N) x (N x M) contraction on the
+// float64 matrix cores.  A workgroup of 4 wavefronts owns 64 chains and up to 128 data points
+// (column group blockIdx.y); the grid points pass through LDS in chunks of kRefKC, the chains'
+// components (64 x kRefKC, rows padded to kRefLDA words) and K~ (128 x kRefKC doubles, rows
+// padded to kRefLDK doubles, as stored: data point by data point), the next chunk loaded into
+// registers while the current one is multiplied.  Wavefront w forms chains 16 w .. 16 w + 15, one
+// accumulator per 16 data points.
+constexpr int kRefKC = 32, kRefLDA = 36, kRefLDK = 34, kRefCols = 128;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_refresh(const ProbDesc *probs, const double *Kt, const double *gt,
+                                                 const T *Ast, T *rst) {
+    __shared__ __align__(16) T sA[64 * kRefLDA];
+    __shared__ __align__(16) double sK[kRefCols * kRefLDK];
+    const ProbDesc pd = probs[blockIdx.z];
     const int64_t M = pd.M, N = pd.N, C = pd.C;
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int64_t ntm = (M + 15) / 16, ntc = (C + 15) / 16;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-    if (tile >= ntm * ntc) return;
-    const int64_t c0 = (tile / ntm) * 16, m0 = (tile % ntm) * 16;
-    const int i = lane % 16, k = lane / 16;
-    const int64_t ca = c0 + i, mb = m0 + i;
+    const int64_t c0 = (int64_t)blockIdx.x * 64, m0 = (int64_t)blockIdx.y * kRefCols;
+    if (c0 >= C || m0 >= M) return;
+    const int ncol = (int)min<int64_t>(kRefCols, M - m0);
+    const int ncb = (ncol + 15) / 16;
+    const T *Ab = Ast + pd.off_A;
     const double *K = Kt + pd.off_K;
-    const int64_t abase = pd.off_A + ca * N;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const bool ca_ok = ca < C, mb_ok = mb < M;
-    int64_t n0 = 0;
-    for (; n0 + 16 <= N; n0 += 16) {
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int i = lane % 16, kk = lane / 16;
+    // staging: the components, 64 chains x kRefKC values (8 per thread), and K~, ncol rows of
+    // kRefKC doubles as double2 words (8 per thread)
+    T pa[8];
+    double2 pk[8];
+    auto load = [&](int64_t n0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t n = n0 + 4 * u + k;
-            const double a = ca_ok ? load_state(A32, A64, abase + n, fp32) : 0.0;
-            const double b = mb_ok ? K[mb * N + n] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, row = e / kRefKC, k = e % kRefKC;
+            const int64_t c = c0 + row, n = n0 + k;
+            pa[h] = (c < C && n < N) ? Ab[c * N + n] : T(0);
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, col = e / (kRefKC / 2), k2 = e % (kRefKC / 2);
+            const int64_t m = m0 + col, n = n0 + 2 * k2;
+            double2 v = make_double2(0.0, 0.0);
+            if (col < ncol) {
+                if (n < N) v.x = K[m * N + n];
+                if (n + 1 < N) v.y = K[m * N + n + 1];
+            }
+            pk[h] = v;
+        }
+    };
+    d4 acc[kRefCols / 16];
+#pragma unroll
+    for (int c = 0; c < kRefCols / 16; ++c) acc[c] = d4{0, 0, 0, 0};
+    load(0);
+    for (int64_t n0 = 0; n0 < N; n0 += kRefKC) {
+        __syncthreads();   // the previous chunk is consumed
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, row = e / kRefKC, k = e % kRefKC;
+            sA[row * kRefLDA + k] = pa[h];
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int e = tid + 256 * h, col = e / (kRefKC / 2), k2 = e % (kRefKC / 2);
+            *reinterpret_cast<double2 *>(sK + col * kRefLDK + 2 * k2) = pk[h];
+        }
+        __syncthreads();
+        if (n0 + kRefKC < N) load(n0 + kRefKC);
+#pragma unroll
+        for (int k4 = 0; k4 < kRefKC; k4 += 4) {
+            const double av = (double)sA[(16 * wave + i) * kRefLDA + k4 + kk];
+#pragma unroll
+            for (int c = 0; c < kRefCols / 16; ++c)
+                if (c < ncb)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sK[(16 * c + i) * kRefLDK + k4 + kk], acc[c], 0,
+                                                                  0, 0);
         }
     }
-    for (; n0 < N; n0 += 4) {
-        const int64_t n = n0 + k;
-        const double a = (ca_ok && n < N) ? load_state(A32, A64, abase + n, fp32) : 0.0;
-        const double b = (mb_ok && n < N) ? K[mb * N + n] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-    const int64_t m = m0 + lane % 16;
     const double *g = gt + pd.off_m;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t c = c0 + lane / 16 + 4 * j;
-        if (c < C && m < M) {
-            const double rv = g[m] - acc[j];
-            const int64_t idx = pd.off_r + c * M + m;
-            if (fp32)
-                r32[idx] = (float)rv;
-            else
-                r64[idx] = rv;
+    for (int c = 0; c < kRefCols / 16; ++c) {
+        if (c >= ncb) continue;
+        const int64_t m = m0 + 16 * c + lane % 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t ch = c0 + 16 * wave + lane / 16 + 4 * j;
+            if (ch < C && m < M) rst[pd.off_r + ch * M + m] = (T)(g[m] - acc[c][j]);
         }
     }
 }
@@ -95,12 +136,14 @@ __global__ __launch_bounds__(64) void k_rownorm(const ProbDesc *probs, const int
     }
 }
 
-hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_tiles,
+hipError_t launch_refresh_all(const ProbDesc *probs_dev, int64_t P, int64_t max_c, int64_t max_m,
                               const double *Kt, const double *gt, const float *A32, float *r32,
                               const double *A64, double *r64, int fp32, hipStream_t s) {
-    const unsigned gx = (unsigned)((max_tiles + 3) / 4);
-    hipLaunchKernelGGL(k_refresh, dim3(gx, (unsigned)P), dim3(256), 0, s, probs_dev, Kt, gt, A32,
-                       r32, A64, r64, fp32);
+    const dim3 grid((unsigned)((max_c + 63) / 64), (unsigned)((max_m + kRefCols - 1) / kRefCols), (unsigned)P);
+    if (fp32)
+        hipLaunchKernelGGL(k_refresh<float>, grid, dim3(256), 0, s, probs_dev, Kt, gt, A32, r32);
+    else
+        hipLaunchKernelGGL(k_refresh<double>, grid, dim3(256), 0, s, probs_dev, Kt, gt, A64, r64);
     return hipGetLastError();
 }
 
