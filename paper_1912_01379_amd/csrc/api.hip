@@ -1290,8 +1290,47 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         pl->chunk.mp = mp;
         pl->chunk.words = (int64_t)(vw_bytes + d_bytes + (pl->u_lds ? u_bytes : 0)) / 16;
         pl->chunk.compact = pl->ext() ? 1 : 0;   // the extended instances stage packed chunks
-        for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
-        STEP(dalloc(pl, &pl->F32, pl->blocks.size() * pl->chunk.words));
+        int64_t f32_words = 0;
+        if (!pl->chunk.compact) {
+            for (size_t k = 0; k < pl->blocks.size(); ++k) pl->blocks[k].off_chunk = (int64_t)k * pl->chunk.words;
+            f32_words = (int64_t)pl->blocks.size() * pl->chunk.words;
+        } else {
+            // each block's image packed to its size (nm + 2 rows, round4(kb) values, kb U rows),
+            // the blocks back to back, so that consecutive blocks of a level are one copy
+            std::vector<int64_t> words(pl->blocks.size());
+            for (size_t k = 0; k < pl->blocks.size(); ++k) {
+                const BlockDesc &bd = pl->blocks[k];
+                words[k] = ((bd.nm + 2) * row * 8 + (bd.kb + 3) / 4 * 16 + (pl->u_lds ? bd.kb * mp * 4 : 0)) / 16;
+                pl->blocks[k].off_chunk = f32_words;
+                f32_words += words[k];
+            }
+            // groups: consecutive blocks of one level whose images fit the staging area together
+            // and whose uniforms (four per Philox call) fit one uniform row, staged and drawn at
+            // once (many small blocks share one pair of barriers)
+            const int64_t cap = pl->lds_off_unif / 16;
+            for (auto &pd : pl->probs) {
+                for (int64_t l = 0; l < pd.levels; ++l) {
+                    const int64_t f = pd.off_blk + pl->lvl[2 * (pd.off_lvl + l)];
+                    const int64_t c = pl->lvl[2 * (pd.off_lvl + l) + 1];
+                    int64_t k = f;
+                    while (k < f + c) {
+                        int64_t n = 0, w = 0, u = 0;
+                        while (k + n < f + c) {
+                            const int64_t wn = words[k + n], un = (pl->blocks[k + n].nm + 3) / 4 * 4;
+                            if (n > 0 && (w + wn > cap || u + un > row)) break;
+                            w += wn;
+                            u += un;
+                            ++n;
+                        }
+                        pl->blocks[k].grp_n = (int32_t)n;
+                        pl->blocks[k].grp_words = (int32_t)w;
+                        for (int64_t j = 1; j < n; ++j) pl->blocks[k + j].grp_n = pl->blocks[k + j].grp_words = 0;
+                        k += n;
+                    }
+                }
+            }
+        }
+        STEP(dalloc(pl, &pl->F32, f32_words));
         // the next block's chunk is prefetched into registers when it fits the instance's
         // per-thread budget (not with a hierarchy, whose blocks are staged to their own size)
         pl->prefetch = (pf > 0 && L * cpw <= 256 && pl->chunk.words <= (int64_t)pf * L * cpw && !pl->ext()) ? 1 : 0;

@@ -58,7 +58,9 @@ struct BlockDesc {
     int64_t off_chunk;        // float32 factor chunk (16-byte words): the LDS image of the block
     int64_t off_U32;          // float32 U, mode-major, kb x mp (read from global memory when the
                               // U rows are not staged)
-    int64_t unused2;
+    int32_t grp_n;            // extended instances, at the first block of a group: the consecutive
+                              // blocks of its level staged together (their chunks are contiguous)
+    int32_t grp_words;        //   and the 16-byte words of their chunks
 };
 
 struct TileDesc {             // float32 work item: consecutive chains of one problem

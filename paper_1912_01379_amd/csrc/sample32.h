@@ -313,6 +313,42 @@ __device__ __forceinline__ void acc_block(double *accA, double *accA2, int64_t n
     }
 }
 
+// The sums of A and A^2 from a chain's whole state after a sweep (read back from memory), in
+// chunks of 4 L components: as acc_block, for every component of the grid.
+template <int L>
+__device__ __forceinline__ void acc_state(double *accA, double *accA2, const float *Ag, int64_t N, int wlane,
+                                          bool active) {
+    constexpr int GW = 64 / L;
+    constexpr int STEPS = (L == 64) ? 0 : (L == 32) ? 1 : (L == 16) ? 2 : (L == 8) ? 3 : (L == 4) ? 4 : 5;
+    const int lane = wlane % L, grp = wlane / L;
+    for (int64_t q0 = 0; q0 < N; q0 += 4 * L) {
+        double s1[4], s2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t q = q0 + lane + L * t;
+            const double x = (active && q < N) ? (double)Ag[q] : 0.0;
+            s1[t] = x;
+            s2[t] = x * x;
+        }
+#pragma unroll
+        for (int k = 0; k < STEPS; ++k) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                s1[t] += __shfl_xor(s1[t], L << k);
+                s2[t] += __shfl_xor(s2[t], L << k);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t q = q0 + lane + L * t;
+            if (t % GW == grp && q < N) {
+                accA[q] += s1[t];
+                accA2[q] += s2[t];
+            }
+        }
+    }
+}
+
 // The accumulator slot of a wavefront for sweep s, or -1 when s is not measured: one slot per
 // (tile, wavefront), or per (tile, wavefront, batch of sweeps) for batch means.
 __device__ __forceinline__ int64_t acc_slot(const SampleArgs &a, const ProbDesc &pd, const TileDesc &td,
@@ -494,6 +530,8 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
         for (int64_t s = s0; s < s0 + nsw; ++s) {
             int nf, nc;   // the next sweep's level
             level_of(s + 1, nf, nc);
+            int64_t g_end = 0, g_chunk0 = 0;   // the staged group of blocks (extended instances)
+            int g_uoff = 0;                    // the next block's segment of the uniform rows
             for (int64_t b = 0; b < lc; ++b) {
                 const BlockDesc bd = cload(a.blocks + pd.off_blk + lf + b);
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
@@ -511,58 +549,95 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                         pr.Lg[t] = __log2f(Ar[t]);
                     }
                 }
-                __syncthreads();   // the previous block's readers of the LDS rows are done
-                // the block's singular values and U rows in LDS: at the plan's fixed offsets, or,
-                // for a hierarchy, right after the block's own rows (its chunk is packed to its
-                // size: nm + 2 rows, round4(kb) values, kb U rows, one contiguous copy)
+                // the block's rows, singular values and U rows in LDS and its uniforms: at the
+                // plan's fixed offsets, or, for the extended instances, in the image of its group
+                // (consecutive blocks of the level staged by one copy, each packed to its size:
+                // nm + 2 rows, round4(kb) values, kb U rows) and a segment of the uniform rows
                 const float *sDb = sD, *sUb = sU;
+                const float2 *sVWb = sVW;
+                float *urowb = urow, *urowAb = urowA;
                 if constexpr (H) {
-                    const int n1 = (nm + 2) * ROW / 2, n2 = (kb + 3) / 4, n3 = a.u_lds ? kb * MP / 4 : 0;
-                    stage_sync(stage, a.F32 + bd.off_chunk, n1 + n2 + n3, tid, nthr);
-                    sDb = reinterpret_cast<const float *>(stage + n1);
-                    sUb = sDb + 4 * n2;
-                } else if (prefetch) {
-                    pf.store(stage, tid, nthr, nw);
-                } else {
-                    stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
-                }
-                // this block's uniforms: one Philox call per four modes
-                for (int g = lane; 4 * g < nm; g += L) {
-                    const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
-                                              (uint32_t)b, (uint32_t)g);
-                    float *d = urow + 4 * g;
-                    d[0] = word_u32(w.x);
-                    d[1] = word_u32(w.y);
-                    d[2] = word_u32(w.z);
-                    d[3] = word_u32(w.w);
-                    if (PRI) {
-                        const U4 x = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
-                                                  (uint32_t)b, (uint32_t)g, 4u);
-                        float *e = urowA + 4 * g;
-                        e[0] = word_u32(x.x);
-                        e[1] = word_u32(x.y);
-                        e[2] = word_u32(x.z);
-                        e[3] = word_u32(x.w);
+                    if (b >= g_end) {
+                        const int gn = bd.grp_n > 0 ? bd.grp_n : 1;
+                        const int gw = bd.grp_n > 0 ? bd.grp_words
+                                                    : (nm + 2) * ROW / 2 + (kb + 3) / 4 + (a.u_lds ? kb * MP / 4 : 0);
+                        __syncthreads();   // the previous group's readers of the LDS rows are done
+                        stage_sync(stage, a.F32 + bd.off_chunk, gw, tid, nthr);
+                        // the group's uniforms, one Philox call per four modes of each block; the
+                        // calls of the group are dealt to the chain's lanes in turn
+                        int pcall = 0, uo = 0;
+                        for (int j = 0; j < gn; ++j) {
+                            const int nmj = j == 0 ? nm : (int)cload(a.blocks + pd.off_blk + lf + b + j).nm;
+                            const int cj = (nmj + 3) / 4;
+                            for (int g = ((lane - pcall) % L + L) % L; g < cj; g += L) {
+                                const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
+                                                          (uint32_t)(b + j), (uint32_t)g);
+                                float *d = urow + uo + 4 * g;
+                                d[0] = word_u32(w.x);
+                                d[1] = word_u32(w.y);
+                                d[2] = word_u32(w.z);
+                                d[3] = word_u32(w.w);
+                                if (PRI) {
+                                    const U4 x = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
+                                                              (uint32_t)(b + j), (uint32_t)g, 4u);
+                                    float *e = urowA + uo + 4 * g;
+                                    e[0] = word_u32(x.x);
+                                    e[1] = word_u32(x.y);
+                                    e[2] = word_u32(x.z);
+                                    e[3] = word_u32(x.w);
+                                }
+                            }
+                            pcall += cj;
+                            uo += 4 * cj;
+                        }
+                        __syncthreads();
+                        g_end = b + gn;
+                        g_chunk0 = bd.off_chunk;
+                        g_uoff = 0;
                     }
+                    const int64_t base = bd.off_chunk - g_chunk0;   // 16-byte words into the group image
+                    const int n1 = (nm + 2) * ROW / 2, n2 = (kb + 3) / 4;
+                    sVWb = reinterpret_cast<const float2 *>(stage + base);
+                    sDb = reinterpret_cast<const float *>(stage + base + n1);
+                    sUb = sDb + 4 * n2;
+                    urowb = urow + g_uoff;
+                    urowAb = urowA + g_uoff;
+                    g_uoff += 4 * ((nm + 3) / 4);
+                } else {
+                    __syncthreads();   // the previous block's readers of the LDS rows are done
+                    if (prefetch)
+                        pf.store(stage, tid, nthr, nw);
+                    else
+                        stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
+                    // this block's uniforms: one Philox call per four modes
+                    for (int g = lane; 4 * g < nm; g += L) {
+                        const U4 w = move_words32(a.seed, pd.index, (uint32_t)chain, (uint32_t)s,
+                                                  (uint32_t)b, (uint32_t)g);
+                        float *d = urow + 4 * g;
+                        d[0] = word_u32(w.x);
+                        d[1] = word_u32(w.y);
+                        d[2] = word_u32(w.z);
+                        d[3] = word_u32(w.w);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
                 store_prev();
                 const float *Ug = a.U32 + bd.off_U32;
                 float2 vw[EPT];
-                load_row<EPT>(vw, sVW, lane, L);
+                load_row<EPT>(vw, sVWb, lane, L);
                 // data modes (U rows from LDS, or from global memory when they do not fit;
                 // two copies of the loop, so the LDS one waits on no global loads)
                 float *sc = sCE + slotc * 2 * a.kce;
                 if (PRI) {
                     if (a.u_lds)
-                        data_moves<L, EPT, RPT, true>(kb, sVW, sDb, sUb, urow, sc, a.kce, lane, vw, Ar, rr, &pr, urowA);
+                        data_moves<L, EPT, RPT, true>(kb, sVWb, sDb, sUb, urowb, sc, a.kce, lane, vw, Ar, rr, &pr, urowAb);
                     else
-                        data_moves<L, EPT, RPT, true>(kb, sVW, sDb, Ug, urow, sc, a.kce, lane, vw, Ar, rr, &pr, urowA);
+                        data_moves<L, EPT, RPT, true>(kb, sVWb, sDb, Ug, urowb, sc, a.kce, lane, vw, Ar, rr, &pr, urowAb);
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                 } else if (a.u_lds)
-                    data_moves<L, EPT, RPT>(kb, sVW, sDb, sUb, urow, sc, a.kce, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT>(kb, sVWb, sDb, sUb, urowb, sc, a.kce, lane, vw, Ar, rr);
                 else {
-                    data_moves<L, EPT, RPT>(kb, sVW, sDb, Ug, urow, sc, a.kce, lane, vw, Ar, rr);
+                    data_moves<L, EPT, RPT>(kb, sVWb, sDb, Ug, urowb, sc, a.kce, lane, vw, Ar, rr);
                     // the U row loaded ahead past the last data mode is never read: wait for
                     // it here, or the compiler waits for every load in flight (the prefetch
                     // below included) where its register is reused
@@ -585,22 +660,22 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
                 if (PRI) {
-                    zero_moves<L, EPT, true>(kb, nm, sVW, urow, urowA, lane, vw, Ar, &pr);
+                    zero_moves<L, EPT, true>(kb, nm, sVWb, urowb, urowAb, lane, vw, Ar, &pr);
                 } else {
                     int i = kb;
                     float2 vb[EPT], vc[EPT];
-                    load_row<EPT>(vb, sVW + (i + 1) * ROW, lane, L);
+                    load_row<EPT>(vb, sVWb + (i + 1) * ROW, lane, L);
                     for (; i + 3 <= nm; i += 3) {
-                        load_row<EPT>(vc, sVW + (i + 2) * ROW, lane, L);
-                        const float u0 = urow[i], u1 = urow[i + 1], u2 = urow[i + 2];
+                        load_row<EPT>(vc, sVWb + (i + 2) * ROW, lane, L);
+                        const float u0 = urowb[i], u1 = urowb[i + 1], u2 = urowb[i + 2];
                         zero_move<L, EPT>(vw, Ar, u0);
-                        load_row<EPT>(vw, sVW + (i + 3) * ROW, lane, L);
+                        load_row<EPT>(vw, sVWb + (i + 3) * ROW, lane, L);
                         zero_move<L, EPT>(vb, Ar, u1);
-                        load_row<EPT>(vb, sVW + (i + 4) * ROW, lane, L);
+                        load_row<EPT>(vb, sVWb + (i + 4) * ROW, lane, L);
                         zero_move<L, EPT>(vc, Ar, u2);
                     }
-                    if (i < nm) zero_move<L, EPT>(vw, Ar, urow[i]);
-                    if (i + 1 < nm) zero_move<L, EPT>(vb, Ar, urow[i + 1]);
+                    if (i < nm) zero_move<L, EPT>(vw, Ar, urowb[i]);
+                    if (i + 1 < nm) zero_move<L, EPT>(vb, Ar, urowb[i + 1]);
                 }
                 if constexpr (H) {
                     // a hierarchy's next block may overlap this block (whose components are
@@ -620,7 +695,7 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                         for (int t = 0; t < EPT; ++t) An[t] = Ag[bn.n0 + min(lane + L * t, (int)bn.nb - 1)];
                     }
                 }
-                {
+                if constexpr (!H) {
                     const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
                     if (sl >= 0)
                         acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0,
@@ -635,6 +710,19 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                 p_n0 = bd.n0;
                 p_nb = nb;
                 p_row = (a.snapA && s >= a.burnin) ? s - s0 : -1;
+            }
+            if constexpr (H) {
+                // the extended instances add the sweep's state to the sums once per sweep (a
+                // level of many small blocks would otherwise wait for one read-modify-write of
+                // the sums per block): the last block is stored, the stores are waited for,
+                // and the state is read back
+                const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
+                if (sl >= 0) {
+                    store_prev();
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the state is in memory
+                    acc_state<L>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, Ag, N, tid % 64,
+                                 active);
+                }
             }
             lf = nf;
             lc = nc;
