@@ -95,7 +95,7 @@ class _DevProblem:
         self.init = None
 
 
-def cpu_baseline(prob, seconds_target=15.0):
+def cpu_baseline(prob, seconds_target=20.0):
     """The CPU oracle on the host cores, on a bounded sample of the same workload."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
@@ -162,6 +162,26 @@ def micro():
             iters = 4000
             t = run(kind, iters, grid, share)
             out[f"lds_read_b{8 * width}_share{share}_bytes_per_s"] = grid * 256 * iters * 8 * width / t
+    lib.micro_run2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p]
+
+    def run2(kind, iters, grid, src=None, dst=None):
+        rc = lib.micro_run2(kind, iters, grid, src, dst, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"micro_run2({kind}) failed: {rc}")
+        return ms.value * 1e-3
+
+    grid = cus * 4
+    t = run2(4, 10000, grid)
+    out["valu_fp64_fma_per_s_16waves_per_cu"] = grid * 256 * 10000 * 16 / t
+    t = run2(5, 20000, grid)
+    out["mfma_f64_flop_per_s"] = grid * 4 * 20000 * 8 * 2048 / t
+    n = (1 << 30) // 16   # 1 GiB of float4 words
+    src = torch.ones(4 * n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    t = run2(6, n, cus * 8, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()))
+    out["hbm_copy_bytes_per_s"] = 2 * 16 * n / t   # read + write
+    del src, dst
     out["lds_bytes_per_clk_per_cu_at_2.4GHz"] = {k: v / (cus * 2.4e9) for k, v in out.items() if k.startswith("lds")}
     out["valu_lane_ops_per_clk_per_cu_at_2.4GHz"] = out["valu_fma_per_s_8waves_per_cu"] / (cus * 2.4e9)
     print(json.dumps({"micro": out}))
