@@ -206,8 +206,16 @@ def batched(args):
                        lanes_per_chain=args.lanes, use_graph=True, start="nnls", device=dev)
         res = plan.run()
         torch.cuda.synchronize()
+        # algorithmic lane-operations of one sweep of every chain of the batch
+        ops = 0.0
+        for j, p in enumerate(probs):
+            blocks = []
+            for b in range(len(p.block_start) - 1):
+                nb = int(p.block_start[b + 1] - p.block_start[b])
+                blocks.append((nb, plan.factors(j, b, nb)[0]))
+            ops += chains * lane_ops_per_sweep(p.M, blocks)
         plan.close()
-        return res
+        return res, ops
 
     for w in range(args.warmup):
         step()
@@ -215,12 +223,15 @@ def batched(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        res = step()
+        res, ops_sweep = step()
         print(f"step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = res.stats
     moves = chains * sweeps_total * sum(p.N for p in probs)
+    avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
+    ops_per_launch = ops_sweep * st["sampler_sweeps"] / max(1, st["sampler_launches"])
+    kernel = "k_sample32p" if st.get("roles", 1) == 2 else "k_sample32"
     out = {"metric": "mode-moves/s", "value": moves * args.steps / elapsed, "unit": "mode-moves/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -229,7 +240,11 @@ def batched(args):
                                   "B = round(N/100), k <= 20, 256 chains each, fp32, NNLS start, hipGraph",
                       "chains_total": chains * len(probs), "burnin": args.burnin, "sweeps": args.sweeps,
                       "lanes_per_chain": st["lanes_per_chain"], "chains_per_workgroup": st["chains_per_block"],
-                      "graph_replays": st["graph_replays"]},
+                      "roles": st.get("roles", 1), "graph_replays": st["graph_replays"]},
+           "roofline": {"bound": "alu", "achieved": ops_per_launch / avg_launch_s, "peak": PEAK_LANE_OPS,
+                        "unit": "lane-op/s", "frac": ops_per_launch / avg_launch_s / PEAK_LANE_OPS,
+                        "traffic": None, "kernel": kernel, "ops_per_chain_sweep_batch": ops_sweep,
+                        "avg_launch_ms": avg_launch_s * 1e3, "launches_per_step": st["sampler_launches"]},
            "setup_ms": st["setup_ms"], "sample_ms": st["sample_ms"]}
     print(json.dumps(out))
 

@@ -124,9 +124,10 @@ typedef struct {
     int32_t groups;              /* independent chain groups for the error bars (default 32);
                                     with fewer chains than groups, batches of sweeps are used */
     int32_t lanes_per_chain;     /* ASM_FP32 only: 4, 8, 16 or 32 lanes per chain, 0 = tune   */
-    int32_t use_graph;           /* 1: ASM_FP32 plans replay each refresh cycle (sampler launch,
-                                    cross moments, float64 refresh) from a hipGraph captured
-                                    once per run; results are identical to eager launches    */
+    int32_t use_graph;           /* 1: ASM_FP32 plans replay each refresh cycle from two
+                                    hipGraphs (the sampler launch, captured once per run and
+                                    kind of cycle; the float64 refresh, once per plan);
+                                    results are identical to eager launches                  */
     int32_t start;               /* start model when a problem gives no init: ASM_START_FLAT
                                     ASM_START_NNLS or ASM_START_NNLS_NOISED                   */
     int32_t roles;               /* ASM_FP32 with 16 lanes per chain: 0 = two roles when the
@@ -137,6 +138,14 @@ typedef struct {
                                     zero modes of block b, which act on disjoint state (the
                                     zero modes leave r~ unchanged, Sec. IV.C): the chains
                                     are bit-identical to one role                            */
+    int32_t chains_per_workgroup;/* ASM_FP32 only: chains per workgroup, a power of two with
+                                    lanes_per_chain x chains a multiple of 64 and at most 512
+                                    (256 for the prefetching instances; the two-role sampler
+                                    takes 16); 0 = automatic (tuned with lanes_per_chain = 0).
+                                    The chains are the same for any value                    */
+    int32_t u_rows;              /* ASM_FP32 only: 0 = the blocks' U rows are staged in LDS
+                                    when they fit, 1 = read from global memory; the same
+                                    chains either way                                        */
 } asm_options;
 
 /* ---- start model ---------------------------------------------------------------------- */
@@ -169,8 +178,8 @@ typedef struct {
                                     events recorded around each launch on the plan's stream  */
     int64_t sampler_launches;    /* number of those launches                                  */
     int64_t sampler_sweeps;      /* sweeps they covered (each over all chains)                */
-    int64_t graph_replays;       /* refresh cycles replayed from a captured hipGraph (use_graph);
-                                    their sampler launches are not in sampler_ms             */
+    int64_t graph_replays;       /* refresh cycles replayed from captured hipGraphs (use_graph);
+                                    their sampler launches are timed like the others          */
     int64_t roles;               /* 1 or 2: the float32 sampler's roles (see asm_options)     */
     int64_t rejected;            /* moves rejected by the gamma-prior test (prior_shape)      */
 } asm_stats;

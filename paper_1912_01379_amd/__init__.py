@@ -49,7 +49,8 @@ class _Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("want_vjp", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("start", ctypes.c_int32), ("roles", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("start", ctypes.c_int32), ("roles", ctypes.c_int32),
+                ("chains_per_workgroup", ctypes.c_int32), ("u_rows", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -144,7 +145,7 @@ class Plan:
 
     def __init__(self, problems, chains=256, burnin=100, sweeps=1000, seed=1234, precision="fp32",
                  refresh_every=64, want_vjp=False, groups=32, lanes_per_chain=0, use_graph=False,
-                 start="flat", roles=0, device="cuda:0"):
+                 start="flat", roles=0, chains_per_workgroup=0, u_rows="auto", device="cuda:0"):
         self.device = torch.device(device)
         if isinstance(precision, str):
             precision = ASM_FP32 if precision.lower() == "fp32" else ASM_FP64
@@ -185,7 +186,8 @@ class Plan:
                                 use_graph=int(bool(use_graph)),
                                 start={"nnls": ASM_START_NNLS, "nnls_noised": ASM_START_NNLS_NOISED}.get(
                                     start, ASM_START_FLAT),
-                                roles=int(roles))
+                                roles=int(roles), chains_per_workgroup=int(chains_per_workgroup),
+                                u_rows={"auto": 0, "global": 1}[u_rows])
         self.chains = int(chains)
         self.handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -221,6 +221,10 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 4 && o->lanes_per_chain != 8 &&
         o->lanes_per_chain != 16 && o->lanes_per_chain != 32)
         return fail(ASM_EINVAL, "lanes_per_chain must be 0, 4, 8, 16 or 32");
+    if (o->chains_per_workgroup < 0 || o->chains_per_workgroup > 512 ||
+        (o->chains_per_workgroup & (o->chains_per_workgroup - 1)) != 0)
+        return fail(ASM_EINVAL, "chains_per_workgroup must be 0 or a power of two up to 512");
+    if (o->u_rows != 0 && o->u_rows != 1) return fail(ASM_EINVAL, "u_rows must be 0 or 1");
     if (o->chains > (1ll << 31) || o->burnin + o->sweeps > (1ll << 31))
         return fail(ASM_EINVAL, "chains and sweeps must fit the 32-bit random-number counter");
     for (int64_t p = 0; p < n; ++p) {
@@ -561,19 +565,26 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
     return ASM_OK;
 }
 
-// Lanes per chain for a float32 plan created with lanes_per_chain = 0: every width with a
-// compiled instance that fits the problems is timed on a throwaway plan (2 warm-up sweeps,
+// The float32 sampler's configuration for a plan created with lanes_per_chain = 0: for every
+// width with a compiled instance that fits the problems, the automatic configuration and its
+// neighbours (half and twice the chains per workgroup, the U rows read from global memory
+// instead of LDS, one role instead of two) are timed on throwaway plans (2 warm-up sweeps,
 // then 8 timed sweeps on the plan's stream) and the fastest is kept, per shape of the batch
-// (problem sizes, partitions, k, chains) for the rest of the process.
+// (problem sizes, partitions, k, chains, the options fixed by the caller) for the rest of the
+// process.  Every configuration samples the same chains.
+struct TuneConf {
+    int L = 16, cpw = 0, u_rows = 0, roles = 0;
+};
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, TuneConf> g_tune_cache;
 // set while the tuner creates its throwaway plans: they only advance, so they get no
 // snapshot buffers
 thread_local bool t_probe_plan = false;
 
-int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream, int *best) {
+int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream, TuneConf *best) {
     std::string key = std::to_string(o->chains) + ":" + std::to_string(o->refresh_every) + ":" +
-                      std::to_string(o->start);
+                      std::to_string(o->start) + ":" + std::to_string(o->chains_per_workgroup) + ":" +
+                      std::to_string(o->u_rows) + ":" + std::to_string(o->roles);
     int64_t max_nb = 0, max_m = 0;
     int hier = 0;
     for (int64_t p = 0; p < n; ++p) {
@@ -606,38 +617,91 @@ int tune_lanes(const asm_problem *pr, int64_t n, const asm_options *o, void *hip
     }
     if (cand.empty()) return fail(ASM_EINVAL, "block of %lld points or %lld data points too large for the float32 sampler",
                                   (long long)max_nb, (long long)max_m);
-    int chosen = cand[0];
-    if (cand.size() > 1) {
-        float best_ms = -1.0f;
-        hipStream_t st = static_cast<hipStream_t>(hip_stream);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        for (int L : cand) {
-            asm_options so = *o;
-            so.lanes_per_chain = L;
-            so.want_vjp = 0;
-            so.use_graph = 0;
-            asm_plan *sp = nullptr;
-            t_probe_plan = true;
-            const int crc = asm_plan_create(pr, n, &so, hip_stream, &sp);
-            t_probe_plan = false;
-            if (crc != ASM_OK) continue;
-            float ms = -1.0f;
-            if (asm_plan_advance(sp, 2) == ASM_OK && hipEventRecord(e0, st) == hipSuccess &&
-                asm_plan_advance(sp, 8) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
-                hipEventSynchronize(e1) == hipSuccess)
-                (void)hipEventElapsedTime(&ms, e0, e1);
-            asm_plan_destroy(sp);
-            if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
-                best_ms = ms;
-                chosen = L;
+    TuneConf chosen;
+    chosen.L = cand[0];
+    chosen.cpw = o->chains_per_workgroup;
+    chosen.u_rows = o->u_rows;
+    chosen.roles = o->roles;
+    float best_ms = -1.0f;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // time one configuration; fills the configuration the plan actually took
+    auto probe = [&](const TuneConf &c, TuneConf *took) -> float {
+        asm_options so = *o;
+        so.lanes_per_chain = c.L;
+        so.chains_per_workgroup = c.cpw;
+        so.u_rows = c.u_rows;
+        so.roles = c.roles;
+        so.want_vjp = 0;
+        so.use_graph = 0;
+        asm_plan *sp = nullptr;
+        t_probe_plan = true;
+        const int crc = asm_plan_create(pr, n, &so, hip_stream, &sp);
+        t_probe_plan = false;
+        if (crc != ASM_OK) return -1.0f;
+        float ms = -1.0f;
+        if (asm_plan_advance(sp, 2) == ASM_OK && hipEventRecord(e0, st) == hipSuccess &&
+            asm_plan_advance(sp, 8) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
+            hipEventSynchronize(e1) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, e0, e1);
+        if (took) {
+            took->L = c.L;
+            took->cpw = sp->chains_per_wg;
+            took->u_rows = sp->u_lds ? 0 : 1;
+            took->roles = sp->roles;
+        }
+        asm_plan_destroy(sp);
+        return ms;
+    };
+    auto consider = [&](const TuneConf &c, float ms) {
+        if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            chosen = c;
+        }
+    };
+    for (int L : cand) {
+        TuneConf a;
+        a.L = L;
+        a.cpw = o->chains_per_workgroup;
+        a.u_rows = o->u_rows;
+        a.roles = o->roles;
+        TuneConf took;
+        const float ms = probe(a, &took);
+        if (ms <= 0.0f) continue;
+        took.roles = a.roles == 0 ? 0 : took.roles;   // keep the automatic choice automatic
+        consider(took, ms);
+        if (cand.size() == 1 && o->chains_per_workgroup == 0 && o->u_rows == 0 && o->roles == 0 &&
+            took.cpw <= 64 / L && took.u_rows == 1)
+            break;   // nothing to vary
+        std::vector<TuneConf> alt;
+        if (o->roles == 0 && took.roles == 2) {   // one role, automatic workgroup
+            TuneConf c = a;
+            c.roles = 1;
+            alt.push_back(c);
+        }
+        if (o->chains_per_workgroup == 0) {
+            for (int f : {2, 0}) {   // half and twice the automatic workgroup, one role
+                const int cpw = f ? took.cpw / f : took.cpw * 2;
+                if (cpw < 1 || (L * cpw) % 64 != 0 || L * cpw > 512) continue;
+                TuneConf c = a;
+                c.cpw = cpw;
+                c.roles = o->roles == 2 ? 2 : 1;
+                if (c.roles == 2 && cpw != 16) continue;
+                alt.push_back(c);
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        g_err.clear();
+        if (o->u_rows == 0 && took.u_rows == 0) {   // U rows from global memory
+            TuneConf c = a;
+            c.u_rows = 1;
+            alt.push_back(c);
+        }
+        for (const TuneConf &c : alt) consider(c, probe(c, nullptr));
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_err.clear();
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = chosen;
     *best = chosen;
@@ -717,10 +781,13 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     TRY(validate(pr, n, o));
     asm_options tuned;
     if (o->precision == ASM_FP32 && o->lanes_per_chain == 0) {
-        int L = 16;
-        TRY(tune_lanes(pr, n, o, hip_stream, &L));
+        TuneConf c;
+        TRY(tune_sampler(pr, n, o, hip_stream, &c));
         tuned = *o;
-        tuned.lanes_per_chain = L;
+        tuned.lanes_per_chain = c.L;
+        tuned.chains_per_workgroup = c.cpw;
+        tuned.u_rows = c.u_rows;
+        tuned.roles = c.roles;
         o = &tuned;
     }
     asm_plan *pl = new asm_plan();
@@ -1270,13 +1337,22 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         // chains per workgroup: enough workgroups for every CU, at most 512 threads (256 for
         // the prefetching instances, compiled for one wavefront per SIMD)
         int cpw = (pf > 0 ? 256 : 512) / L;
-        while (cpw > 64 / L) {
-            const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
-            if (layout(cpw, false) <= kLdsBudget && wgs >= max_cu) break;
-            cpw /= 2;
+        if (o->chains_per_workgroup > 0) {
+            cpw = o->chains_per_workgroup;
+            if ((L * cpw) % 64 != 0 || L * cpw > (pf > 0 ? 256 : 512)) {
+                rc = fail(ASM_EINVAL, "chains_per_workgroup %d with %d lanes per chain: the threads must be a multiple "
+                                      "of 64 and at most %d", cpw, L, pf > 0 ? 256 : 512);
+                return rc;
+            }
+        } else {
+            while (cpw > 64 / L) {
+                const int64_t wgs = (pl->total_chains + cpw - 1) / cpw;
+                if (layout(cpw, false) <= kLdsBudget && wgs >= max_cu) break;
+                cpw /= 2;
+            }
         }
         pl->chains_per_wg = cpw;
-        pl->u_lds = layout(cpw, true) <= kLdsBudget ? 1 : 0;
+        pl->u_lds = (o->u_rows == 0 && layout(cpw, true) <= kLdsBudget) ? 1 : 0;
         pl->lds32 = layout(cpw, pl->u_lds);
         if (pl->lds32 > kLdsBudget) {
             rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
@@ -1339,7 +1415,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         {
             int pe = 0, pr = 0, pfr = 0, pfu = 0, pfz = 0;
             // (in automatic mode only with enough chains for a 16-chain workgroup per CU)
-            bool ok = o->roles != 1 && L == 16 &&
+            bool ok = o->roles != 1 && L == 16 && (o->chains_per_workgroup == 0 || o->chains_per_workgroup == 16) &&
                       (o->roles == 2 || pl->total_chains >= 16LL * max_cu) &&
                       sample32p_pick(pl->max_nb, pl->max_m, pl->u_lds, &pe, &pr, &pfr, &pfu, &pfz) == 0 &&
                       pe == ept && pr == rpt;

@@ -11,7 +11,8 @@ struct Inst32 {
 // thread): a block of up to EPT L grid points and a problem of up to RPT L data points
 const Inst32 kInst32[] = {
     {4, 8, 16, 0}, {4, 32, 16, 0}, {4, 32, 52, 0}, {8, 4, 8, 0}, {8, 13, 26, 0}, {8, 16, 8, 0}, {8, 16, 52, 0},
-    {16, 2, 4, 0}, {16, 7, 13, 26}, {16, 8, 4, 0}, {16, 8, 26, 0}, {16, 8, 32, 0}, {32, 1, 2, 0}, {32, 4, 2, 0},
+    {16, 2, 4, 0}, {16, 7, 13, 26}, {16, 8, 4, 0}, {16, 8, 13, 0}, {16, 8, 26, 0}, {16, 8, 32, 0}, {32, 1, 2, 0},
+    {32, 4, 2, 0},
     {32, 4, 7, 0}, {32, 4, 13, 0}};
 }  // namespace
 

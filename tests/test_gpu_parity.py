@@ -623,6 +623,24 @@ def test_two_roles_partial_tiles_and_mixed_problems(pk):
     two.close()
 
 
+def test_two_roles_with_wide_blocks_and_global_u_rows(pk):
+    """Blocks of 120 points (beyond the LDS-staged two-role instance's 112) with the U rows read
+    from global memory: the two-role chains equal the one-role chains bit for bit."""
+    p = workloads.small_problem(M=201, N=360, nblocks=3, sigma=2e-3, seed=21)
+    kw = dict(chains=300, burnin=16, sweeps=48, seed=29, precision="fp32", groups=32,
+              refresh_every=64, lanes_per_chain=16, u_rows="global", start="nnls")
+    one = pk.Plan([p], roles=1, **kw)
+    two = pk.Plan([p], roles=2, **kw)
+    r1, r2 = one.run(), two.run()
+    assert r1.stats["roles"] == 1 and r2.stats["roles"] == 2
+    A1, q1, _ = one.state(0)
+    A2, q2, _ = two.state(0)
+    assert np.array_equal(A1.cpu().numpy(), A2.cpu().numpy())
+    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
+    one.close()
+    two.close()
+
+
 def test_two_roles_refuse_a_single_block(pk):
     p = workloads.small_problem(M=101, N=100, nblocks=1, sigma=2e-3, seed=9)
     with pytest.raises(pk.AsmError):
@@ -632,16 +650,48 @@ def test_two_roles_refuse_a_single_block(pk):
     plan.close()
 
 
-def test_tuner_picks_a_compiled_width_and_remembers_it(pk):
+def test_tuner_picks_a_compiled_configuration_and_remembers_it(pk):
+    """The tuner (lanes per chain, chains per workgroup, U rows in LDS or global memory, one or
+    two roles) picks a compiled configuration, keeps it for the same shape, and its chains are
+    those of the same configuration requested explicitly."""
+    import torch
     p = workloads.small_problem(M=41, N=48, nblocks=3, seed=5)
-    a = pk.Plan([p], chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, lanes_per_chain=0)
+    kw = dict(chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, seed=9)
+    a = pk.Plan([p], lanes_per_chain=0, **kw)
     ra = a.run()
-    b = pk.Plan([p], chains=256, burnin=0, sweeps=8, precision="fp32", groups=32, lanes_per_chain=0)
+    b = pk.Plan([p], lanes_per_chain=0, **kw)
     rb = b.run()
-    assert ra.stats["lanes_per_chain"] in (4, 8, 16, 32)
-    assert rb.stats["lanes_per_chain"] == ra.stats["lanes_per_chain"]
-    a.close()
-    b.close()
+    L, cpw = ra.stats["lanes_per_chain"], ra.stats["chains_per_block"]
+    assert L in (4, 8, 16, 32) and cpw in (1, 2, 4, 8, 16, 32, 64, 128) and (L * cpw) % 64 == 0
+    assert rb.stats["lanes_per_chain"] == L and rb.stats["chains_per_block"] == cpw
+    c = pk.Plan([p], lanes_per_chain=L, chains_per_workgroup=cpw, roles=ra.stats["roles"], **kw)
+    rc = c.run()
+    assert torch.equal(rc.mean, ra.mean)
+    for x in (a, b, c):
+        x.close()
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_workgroup_size_and_u_layout_leave_the_chains_unchanged(pk, lanes):
+    """Chains per workgroup and the U rows' place (LDS or global memory) change only how the
+    chains are laid out on the GPU: the averages are equal bit for bit."""
+    import torch
+    p = workloads.config3_dataset(1)
+    kw = dict(chains=512, burnin=0, sweeps=40, precision="fp32", groups=32, seed=11, start="nnls",
+              lanes_per_chain=lanes, roles=1)
+    ref = None
+    # at most 256 threads: the prefetching instances are compiled for one wavefront per SIMD
+    for cpw, u in [(256 // lanes, "auto"), (128 // lanes, "auto"), (128 // lanes, "global"), (64 // lanes, "global")]:
+        plan = pk.Plan([p], chains_per_workgroup=cpw, u_rows=u, **kw)
+        r = plan.run()
+        assert r.stats["chains_per_block"] == cpw
+        if ref is None:
+            ref = r.mean.clone()
+        else:
+            assert torch.equal(r.mean, ref), (cpw, u)
+        plan.close()
+    with pytest.raises(pk.AsmError):
+        pk.Plan([p], chains_per_workgroup=3, **kw)
 
 
 # --------------------------------------------------------------------------------------
