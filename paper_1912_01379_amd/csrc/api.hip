@@ -262,10 +262,16 @@ void build_tiles(asm_plan *pl) {
         const int64_t C = pd.C, G = pd.groups;
         pd.off_tab = (int64_t)pl->slot_group.size();
         int64_t nunits = 0;
-        const int64_t ngr = pd.batches > 1 ? 1 : G;
+        // a wavefront's chains share one accumulator slot, so they must lie in one chain
+        // group; tiles may span groups when every group starts on a wavefront boundary (else
+        // each group gets tiles of its own, the last one partly filled)
+        bool span = pd.batches == 1;
+        for (int64_t g = 1; g < G && span; ++g) span = (g * C / G) % gw == 0;
+        const int64_t ngr = (pd.batches > 1 || span) ? 1 : G;
+        int64_t gu = 0;   // with spanning tiles: the group of the current unit
         for (int64_t g = 0; g < ngr; ++g) {
-            const int64_t c0 = pd.batches > 1 ? 0 : g * C / G;
-            const int64_t c1 = pd.batches > 1 ? C : (g + 1) * C / G;
+            const int64_t c0 = ngr == 1 ? 0 : g * C / G;
+            const int64_t c1 = ngr == 1 ? C : (g + 1) * C / G;
             for (int64_t c = c0; c < c1; c += cpw) {
                 TileDesc t;
                 t.problem = (int32_t)p;
@@ -275,8 +281,15 @@ void build_tiles(asm_plan *pl) {
                 pl->tiles.push_back(t);
                 for (int w = 0; w < pl->units_per_tile; ++w) {
                     const int64_t nc = std::max<int64_t>(0, std::min<int64_t>(gw, t.nchains - (int64_t)w * gw));
+                    // the unit's group: that of its first chain (of the tile's last one when
+                    // the unit is empty; it then counts no chain)
+                    const int64_t cu = nc > 0 ? c + (int64_t)w * gw : c + t.nchains - 1;
+                    if (span)
+                        while (gu + 1 < G && (gu + 1) * C / G <= cu) ++gu;
+                    else
+                        gu = g;
                     for (int64_t bt = 0; bt < pd.batches; ++bt) {
-                        pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : g));
+                        pl->slot_group.push_back((int32_t)(pd.batches > 1 ? bt : gu));
                         pl->slot_count.push_back((double)nc);
                     }
                     ++nunits;
@@ -1029,7 +1042,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     STEP(dalloc(pl, &tmpN, offn));
     STEP(dalloc(pl, &has_init_d, n));
     STEP(dalloc(pl, &pl->flags, 1));
-    STEP(dalloc(pl, &pl->queue, 1));
+    STEP(dalloc(pl, &pl->queue, 8));   // one counter per tile range
     STEP(dalloc(pl, &pl->sweep_d, 1));
     STEP(dalloc(pl, &pl->counters, 3));
     if (pl->any_prior) STEP(dalloc(pl, &pl->shape, offn));
@@ -1056,7 +1069,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     hipStream_t st = pl->stream;
     HSTEP(hipMemsetAsync(pl->flags, 0, sizeof(int), st));
     HSTEP(hipMemsetAsync(pl->sweep_d, 0, sizeof(int64_t), st));
-    HSTEP(hipMemsetAsync(pl->queue, 0, sizeof(int), st));
+    HSTEP(hipMemsetAsync(pl->queue, 0, 8 * sizeof(int), st));
     HSTEP(hipMemsetAsync(pl->counters, 0, 3 * sizeof(unsigned long long), st));
     HSTEP(hipMemsetAsync(pl->drift, 0, offc * sizeof(double), st));
 

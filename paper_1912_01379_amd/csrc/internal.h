@@ -97,7 +97,7 @@ struct SampleArgs {
     double *accA2;
     unsigned long long *counters;  // [0] clamped, [1] frozen, [2] rejected by the prior test
     int *flags;               // bit 0: unbounded zero mode
-    int *queue;               // tile queue head (float32 sampler)
+    int *queue;               // tile queue: 8 range counters (float32 samplers)
     const int64_t *sweep;     // device sweep counter: first sweep of this launch
     int64_t nsw;              // sweeps in this launch
     int64_t burnin;           // sweeps before accumulation starts

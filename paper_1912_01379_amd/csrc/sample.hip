@@ -204,15 +204,16 @@ hipError_t set_sample64_lds_limit() {
 // ------------------------------------------------------------------------------------
 // small kernels: sweep counter, tile queue, and test entry points
 // ------------------------------------------------------------------------------------
+// the float32 samplers' tile queue: kTileQueues range counters
+constexpr int kTileQueues = 8;
+
 __global__ void k_bump(int64_t *sweep, int64_t by, int *queue) {
-    if (threadIdx.x == 0) {
-        *sweep += by;
-        if (queue) *queue = 0;
-    }
+    if (threadIdx.x == 0) *sweep += by;
+    if (queue && threadIdx.x < kTileQueues) queue[threadIdx.x] = 0;
 }
 
 __global__ void k_reset_queue(int *queue) {
-    if (threadIdx.x == 0) *queue = 0;
+    if (threadIdx.x < kTileQueues) queue[threadIdx.x] = 0;
 }
 
 hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s) {

@@ -392,6 +392,27 @@ __device__ __forceinline__ T cload(const T *p) {
     return v;
 }
 
+// The tile queue: the tile list (problem by problem, chain groups in order) is cut into
+// kQueues equal ranges, each with its own counter.  Workgroup b starts on range b mod kQueues,
+// which is the XCD the dispatcher places it on, so the workgroups of one XCD walk the tiles
+// of a few problems at a time and share those problems' factor chunks in that XCD's L2; a
+// workgroup whose range is used up takes tiles from the next ranges.  Called by thread 0 of
+// the workgroup; *visited (thread 0's, 0 at the start of the launch) counts the ranges used up.
+constexpr int kQueues = 8;
+
+__device__ __forceinline__ int grab_tile(const SampleArgs &a, int *visited) {
+    const int ntiles = (int)a.ntiles;
+    while (*visited < kQueues) {
+        const int x = ((int)blockIdx.x + *visited) % kQueues;
+        const int lo = (int)((int64_t)x * ntiles / kQueues);
+        const int hi = (int)((int64_t)(x + 1) * ntiles / kQueues);
+        const int i = atomicAdd(a.queue + x, 1);
+        if (lo + i < hi) return lo + i;
+        ++*visited;
+    }
+    return ntiles;
+}
+
 template <int PF>
 struct Prefetch {
     f32x4 w[PF > 0 ? PF : 1];
@@ -445,8 +466,9 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
     const bool prefetch = PF > 0 && a.prefetch;
     Prefetch<PF> pf;
 
+    int visited = 0;   // thread 0's: tile ranges used up
     for (;;) {
-        if (tid == 0) s_tile = atomicAdd(a.queue, 1);
+        if (tid == 0) s_tile = grab_tile(a, &visited);
         __syncthreads();
         const int tile = __builtin_amdgcn_readfirstlane(s_tile);   // uniform: descriptors load to SGPRs
         __syncthreads();

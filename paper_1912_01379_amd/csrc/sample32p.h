@@ -76,10 +76,10 @@ __device__ __forceinline__ void barrier_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// The tile queue, walked by both roles with the same barriers: 0 and below is a tile,
-// -1 ends the launch.
-__device__ __forceinline__ int next_tile_p(const SampleArgs &a, int *s_tile, int tid) {
-    if (tid == 0) *s_tile = atomicAdd(a.queue, 1);
+// The tile queue, walked by both roles with the same barriers: 0 and above is a tile,
+// -1 ends the launch.  *visited is the data role's thread 0's count of used-up tile ranges.
+__device__ __forceinline__ int next_tile_p(const SampleArgs &a, int *s_tile, int tid, int *visited) {
+    if (tid == 0) *s_tile = grab_tile(a, visited);
     __syncthreads();
     const int tile = __builtin_amdgcn_readfirstlane(*s_tile);
     __syncthreads();
@@ -96,8 +96,9 @@ __device__ __forceinline__ void data_role_p(const SampleArgs &a, const AreasP &a
     const int64_t nsw = a.nsw;
     Prefetch<PFR> pfr;
     Prefetch<PFU> pfu;
+    int visited = 0;
     for (;;) {
-        const int tile = next_tile_p(a, s_tile, tid);
+        const int tile = next_tile_p(a, s_tile, tid, &visited);
         if (tile < 0) break;
         const TileDesc td = cload(a.tiles + tile);
         const ProbDesc pd = cload(a.probs + td.problem);
@@ -300,8 +301,9 @@ template <int L, int EPT, int PFZ>
 __device__ __forceinline__ void zero_role_p(const SampleArgs &a, const AreasP &ar, int *s_tile, int tid) {
     const int slotc = tid / L;
     const int64_t s0 = cload(a.sweep);   // constant during a launch (k_bump runs between launches)
+    int visited = 0;   // unused: thread 0 is in the data role
     for (;;) {
-        const int tile = next_tile_p(a, s_tile, tid + 256);
+        const int tile = next_tile_p(a, s_tile, tid + 256, &visited);
         if (tile < 0) break;
         const TileDesc td = cload(a.tiles + tile);
         const ProbDesc pd = cload(a.probs + td.problem);
