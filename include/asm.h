@@ -123,7 +123,7 @@ typedef struct {
     int32_t want_vjp;            /* 1: accumulate Cov(r~, A) during the run for asm_plan_vjp  */
     int32_t groups;              /* independent chain groups for the error bars (default 32);
                                     with fewer chains than groups, batches of sweeps are used */
-    int32_t lanes_per_chain;     /* ASM_FP32 only: 4, 8, 16 or 32 lanes per chain, 0 = tune   */
+    int32_t lanes_per_chain;     /* ASM_FP32 only: 4, 8, 16, 32 or 64 lanes per chain, 0 = tune */
     int32_t use_graph;           /* 1: ASM_FP32 plans replay each refresh cycle from two
                                     hipGraphs (the sampler launch, captured once per run and
                                     kind of cycle; the float64 refresh, once per plan);

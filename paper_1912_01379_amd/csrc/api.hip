@@ -219,8 +219,8 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
         return fail(ASM_EINVAL, "start must be ASM_START_FLAT, ASM_START_NNLS or ASM_START_NNLS_NOISED");
     if (o->groups < 0 || o->groups > 64) return fail(ASM_EINVAL, "groups must be in [1, 64]");
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 4 && o->lanes_per_chain != 8 &&
-        o->lanes_per_chain != 16 && o->lanes_per_chain != 32)
-        return fail(ASM_EINVAL, "lanes_per_chain must be 0, 4, 8, 16 or 32");
+        o->lanes_per_chain != 16 && o->lanes_per_chain != 32 && o->lanes_per_chain != 64)
+        return fail(ASM_EINVAL, "lanes_per_chain must be 0, 4, 8, 16, 32 or 64");
     if (o->chains_per_workgroup < 0 || o->chains_per_workgroup > 512 ||
         (o->chains_per_workgroup & (o->chains_per_workgroup - 1)) != 0)
         return fail(ASM_EINVAL, "chains_per_workgroup must be 0 or a power of two up to 512");
@@ -624,7 +624,7 @@ int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *h
         }
     }
     std::vector<int> cand;
-    for (int L : {4, 8, 16, 32}) {
+    for (int L : {4, 8, 16, 32, 64}) {
         int e, r, f;
         if (sample32_pick(L, max_nb, max_m, hier, &e, &r, &f) == 0) cand.push_back(L);
     }
@@ -1285,12 +1285,12 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             // aim for about one wavefront per SIMD (4 per CU) across all chains
             const double chains_per_simd = (double)pl->total_chains / (4.0 * max_cu);
             const double want = 64.0 / std::max(1.0, chains_per_simd);
-            L = want >= 24 ? 32 : want >= 12 ? 16 : want >= 6 ? 8 : 4;
+            L = want >= 48 ? 64 : want >= 24 ? 32 : want >= 12 ? 16 : want >= 6 ? 8 : 4;
         }
         int ept = 0, rpt = 0, pf = 0;
         {
             // the requested width first, then wider ones, then narrower ones
-            const int order[] = {L, 16, 32, 8, 4};
+            const int order[] = {L, 16, 32, 8, 4, 64};
             bool found = false;
             for (int cand : order) {
                 if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;

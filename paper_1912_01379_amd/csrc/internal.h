@@ -220,10 +220,12 @@ hipError_t launch_sample32_l4(const SampleArgs &a, int ept, int rpt, int threads
 hipError_t launch_sample32_l8(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t launch_sample32_l16(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t launch_sample32_l32(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t launch_sample32_l64(const SampleArgs &a, int ept, int rpt, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t allow_lds_sample32_l4(int bytes);
 hipError_t allow_lds_sample32_l8(int bytes);
 hipError_t allow_lds_sample32_l16(int bytes);
 hipError_t allow_lds_sample32_l32(int bytes);
+hipError_t allow_lds_sample32_l64(int bytes);
 // sample32p_l16.hip: the two-role instance (16 lanes per chain, 512 threads)
 hipError_t launch_sample32p(const SampleArgs &a, int ept, int rpt, int grid, size_t lds, hipStream_t s);
 int sample32p_pick(int64_t max_nb, int64_t max_m, int u_lds, int *ept, int *rpt, int *pfr, int *pfu, int *pfz);

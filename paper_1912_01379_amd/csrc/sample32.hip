@@ -12,8 +12,7 @@ struct Inst32 {
 const Inst32 kInst32[] = {
     {4, 8, 16, 0}, {4, 32, 16, 0}, {4, 32, 52, 0}, {8, 4, 8, 0}, {8, 13, 26, 0}, {8, 16, 8, 0}, {8, 16, 52, 0},
     {16, 2, 4, 0}, {16, 7, 13, 26}, {16, 8, 4, 0}, {16, 8, 13, 0}, {16, 8, 26, 0}, {16, 8, 32, 0}, {32, 1, 2, 0},
-    {32, 4, 2, 0},
-    {32, 4, 7, 0}, {32, 4, 13, 0}};
+    {32, 4, 2, 0}, {32, 4, 7, 0}, {32, 4, 13, 0}, {64, 1, 4, 0}, {64, 2, 7, 0}};
 }  // namespace
 
 int sample32_pick(int lanes, int64_t max_nb, int64_t max_m, int hier, int *ept, int *rpt, int *pf) {
@@ -44,6 +43,7 @@ hipError_t launch_sample32_inst(const SampleArgs &a, int lanes, int ept, int rpt
     case 8: return launch_sample32_l8(a, ept, rpt, threads, grid, lds_bytes, s);
     case 16: return launch_sample32_l16(a, ept, rpt, threads, grid, lds_bytes, s);
     case 32: return launch_sample32_l32(a, ept, rpt, threads, grid, lds_bytes, s);
+    case 64: return launch_sample32_l64(a, ept, rpt, threads, grid, lds_bytes, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -54,6 +54,7 @@ hipError_t set_sample32_lds_limit(int bytes) {
     if ((e1 = allow_lds_sample32_l8(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_l16(bytes)) != hipSuccess) e = e1;
     if ((e1 = allow_lds_sample32_l32(bytes)) != hipSuccess) e = e1;
+    if ((e1 = allow_lds_sample32_l64(bytes)) != hipSuccess) e = e1;
     return e;
 }
 

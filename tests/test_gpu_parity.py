@@ -282,7 +282,7 @@ def test_nnls_start_matches_scipy(pk, orc):
         plan.close()
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
 def test_batched_fp32_small_problem_matches_oracle(pk, orc, lanes):
     p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
     prep = orc.prepare(p)
@@ -662,7 +662,7 @@ def test_tuner_picks_a_compiled_configuration_and_remembers_it(pk):
     b = pk.Plan([p], lanes_per_chain=0, **kw)
     rb = b.run()
     L, cpw = ra.stats["lanes_per_chain"], ra.stats["chains_per_block"]
-    assert L in (4, 8, 16, 32) and cpw in (1, 2, 4, 8, 16, 32, 64, 128) and (L * cpw) % 64 == 0
+    assert L in (4, 8, 16, 32, 64) and cpw in (1, 2, 4, 8, 16, 32, 64, 128) and (L * cpw) % 64 == 0
     assert rb.stats["lanes_per_chain"] == L and rb.stats["chains_per_block"] == cpw
     c = pk.Plan([p], lanes_per_chain=L, chains_per_workgroup=cpw, roles=ra.stats["roles"], **kw)
     rc = c.run()
@@ -671,7 +671,7 @@ def test_tuner_picks_a_compiled_configuration_and_remembers_it(pk):
         x.close()
 
 
-@pytest.mark.parametrize("lanes", [8, 16])
+@pytest.mark.parametrize("lanes", [8, 16, 64])
 def test_workgroup_size_and_u_layout_leave_the_chains_unchanged(pk, lanes):
     """Chains per workgroup and the U rows' place (LDS or global memory) change only how the
     chains are laid out on the GPU: the averages and error bars are equal bit for bit.  With 16
@@ -874,7 +874,7 @@ def test_fp32_repeated_level_is_the_partition_bit_for_bit(pk, bs):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
 def test_fp32_hierarchy_keeps_state_consistent(pk, lanes):
     """No refresh for 100 sweeps through overlapping levels: the carried residual equals
     g~ - K~ A (a component read before the previous level stored it would break this)."""
@@ -1032,7 +1032,7 @@ def test_gamma_prior_errors_and_flat_shapes(pk, precision):
     assert out[0][1] == 0 and out[1][1] == 0
 
 
-@pytest.mark.parametrize("lanes", [4, 16, 32])
+@pytest.mark.parametrize("lanes", [4, 16, 32, 64])
 def test_fp32_gamma_prior_average_matches_oracle(pk, orc, lanes):
     """The float32 sampler with shapes w_n in [0.5, 2] against an oracle run (R17)."""
     p = workloads.small_problem(M=41, N=48, nblocks=3, sigma=2e-3)
