@@ -582,7 +582,7 @@ int sweep_loop(asm_plan *pl, int64_t total, int accumulate, int64_t burnin_abs) 
 // width with a compiled instance that fits the problems, the automatic configuration and its
 // neighbours (half and twice the chains per workgroup, the U rows read from global memory
 // instead of LDS, one role instead of two) are timed on throwaway plans (2 warm-up sweeps,
-// then 8 timed sweeps on the plan's stream) and the fastest is kept, per shape of the batch
+// then 24 timed sweeps on the plan's stream) and the fastest is kept, per shape of the batch
 // (problem sizes, partitions, k, chains, the options fixed by the caller) for the rest of the
 // process.  Every configuration samples the same chains.
 struct TuneConf {
@@ -656,7 +656,7 @@ int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *h
         if (crc != ASM_OK) return -1.0f;
         float ms = -1.0f;
         if (asm_plan_advance(sp, 2) == ASM_OK && hipEventRecord(e0, st) == hipSuccess &&
-            asm_plan_advance(sp, 8) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
+            asm_plan_advance(sp, 24) == ASM_OK && hipEventRecord(e1, st) == hipSuccess &&
             hipEventSynchronize(e1) == hipSuccess)
             (void)hipEventElapsedTime(&ms, e0, e1);
         if (took) {
@@ -1437,10 +1437,17 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             for (auto &pd : pl->probs) ok = ok && pd.B >= 2 && pd.levels == 1 && !pd.has_prior && !pd.has_con;
             const int64_t rw = row / 2;   // 16-byte words per (V, w) row
             // zero modes the data role runs per block, balancing the two roles: a data move
-            // costs about kDataOverZero zero moves (more where the residual is longer)
+            // costs about kDataOverZero zero moves at 201 data points and blocks of 100 points,
+            // scaled by the ratio of the algorithmic counts (2 M + 3 N_b + 40 against 3 N_b + 10)
+            // where that ratio is larger
             const double kDataOverZero = pl->u_lds ? 2.6 : 3.0;
+            const double kRatio201 = (2.0 * 201 + 3.0 * 100 + 40.0) / (3.0 * 100 + 10.0);
             double zsum = 0.0;
-            for (auto &bd : pl->blocks) zsum += 0.5 * ((double)(bd.nb - bd.kb) - kDataOverZero * (double)bd.kb);
+            for (auto &bd : pl->blocks) {
+                const double ratio = (2.0 * (double)pl->max_m + 3.0 * (double)bd.nb + 40.0) / (3.0 * (double)bd.nb + 10.0);
+                const double dz = kDataOverZero * std::max(1.0, ratio / kRatio201);
+                zsum += 0.5 * ((double)(bd.nb - bd.kb) - dz * (double)bd.kb);
+            }
             int64_t zs = (int64_t)std::lround(zsum / std::max<size_t>(1, pl->blocks.size()));
             // the data role's rows (0..max k + zs + 1) must fit its prefetch registers
             zs = std::max<int64_t>(0, std::min<int64_t>(zs, 256LL * pfr / rw - 2 - max_kb));

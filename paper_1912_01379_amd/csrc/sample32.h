@@ -276,15 +276,42 @@ __device__ __forceinline__ void zero_moves(int kb, int nm, const float2 *sVW, co
 
 // The sums of A and A^2 over the measured sweeps (Eq. (MCint)), kept in float64.  A block's
 // components at the end of its visit in sweep s are the chain's state after sweep s (the
-// partition's blocks are disjoint, and so are one level's), so each visit adds its components
-// to the sums of its sweep.  The chains of one wavefront are summed by a butterfly
-// over the lanes that hold the same component (float64, the squares exact), and the groups of
-// L lanes then split the read-modify-writes of the wavefront's accumulator slot, which no
-// other wavefront touches: no atomics, and a fixed order of additions.
+// partition's blocks are disjoint), so each visit adds its components to the sums of its sweep.
+// The chains of one wavefront are summed by a butterfly over the lanes that hold the same
+// component (float64, the squares exact), and the groups of L lanes then split the
+// read-modify-writes of the wavefront's accumulator slot, which no other wavefront touches: no
+// atomics, and a fixed order of additions.  The read of each read-modify-write is issued ahead
+// (acc_read_ahead, before the block's zero modes, which touch no global memory), so its latency
+// is hidden behind them; acc_block adds and stores.
+template <int L, int EPT>
+struct AccAhead {
+    static constexpr int GW = 64 / L;                 // chains per wavefront
+    static constexpr int KA = (EPT + GW - 1) / GW;    // components t = grp + GW j a lane updates
+    double a[KA], a2[KA];
+};
+
+// The slot entries the lane updates.  The loads are unconditional (clamped into the block) so
+// that no branch leaves the compiler's wait counts inexact; the values of lanes that store
+// nothing are never used.  The slot's previous update was stored a block visit earlier by the
+// same wavefront.
+template <int L, int EPT>
+__device__ __forceinline__ void acc_read_ahead(AccAhead<L, EPT> &h, const double *accA, const double *accA2,
+                                               int64_t n0, int nb, int wlane) {
+    constexpr int GW = 64 / L;
+    const int lane = wlane % L, grp = wlane / L;
+#pragma unroll
+    for (int j = 0; j < AccAhead<L, EPT>::KA; ++j) {
+        const int t = min(grp + GW * j, EPT - 1);
+        const int64_t q = n0 + min(lane + L * t, nb - 1);
+        h.a[j] = accA[q];
+        h.a2[j] = accA2[q];
+    }
+}
+
 template <int L, int EPT>
 __device__ __forceinline__ void acc_block(double *accA, double *accA2, int64_t n0, int nb, int wlane, bool active,
-                                          const float (&Ar)[EPT]) {
-    constexpr int GW = 64 / L;   // chains per wavefront
+                                          const float (&Ar)[EPT], const AccAhead<L, EPT> &h) {
+    constexpr int GW = 64 / L;
     double s1[EPT], s2[EPT];
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
@@ -307,8 +334,8 @@ __device__ __forceinline__ void acc_block(double *accA, double *accA2, int64_t n
     for (int t = 0; t < EPT; ++t) {
         const int q = lane + L * t;
         if (t % GW == grp && q < nb) {
-            accA[n0 + q] += s1[t];
-            accA2[n0 + q] += s2[t];
+            accA[n0 + q] = h.a[t / GW] + s1[t];
+            accA2[n0 + q] = h.a2[t / GW] + s2[t];
         }
     }
 }
@@ -679,6 +706,14 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                         An[t] = __builtin_nontemporal_load(Ag + bn.n0 + min(lane + L * t, (int)bn.nb - 1));
                     if (prefetch && (b + 1 < lc || s + 1 < s0 + nsw)) pf.load(a.F32 + bn.off_chunk, tid, nthr, nw);
                 }
+                // this visit's slot entries of the sums, read during the zero modes
+                AccAhead<L, EPT> acch;
+                int64_t acc_sl = -1;
+                if constexpr (!H) {
+                    acc_sl = acc_slot(a, pd, td, tid / 64, s);
+                    const int64_t o = pd.off_slot + (acc_sl >= 0 ? acc_sl : 0) * N;
+                    acc_read_ahead<L, EPT>(acch, a.accA + o, a.accA2 + o, bd.n0, nb, tid % 64);
+                }
                 // zero modes, three per iteration, each row loaded two moves ahead (the
                 // rows past the block's last are spare LDS rows, loaded and never used)
                 if (PRI) {
@@ -718,10 +753,9 @@ __global__ __launch_bounds__(PF > 0 ? 256 : 512) void k_sample32(SampleArgs a) {
                     }
                 }
                 if constexpr (!H) {
-                    const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
-                    if (sl >= 0)
-                        acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0,
-                                          nb, tid % 64, active, Ar);
+                    if (acc_sl >= 0)
+                        acc_block<L, EPT>(a.accA + pd.off_slot + acc_sl * N, a.accA2 + pd.off_slot + acc_sl * N,
+                                                bd.n0, nb, tid % 64, active, Ar, acch);
                 }
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ap[t] = Ar[t];

@@ -279,13 +279,17 @@ __device__ __forceinline__ void zero_stages_p(const SampleArgs &a, const AreasP 
         const float *h = ar.h + slotc * ROW;
 #pragma unroll
         for (int t2 = 0; t2 < EPT; ++t2) Ar[t2] = h[lane + L * t2];
-        zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
+        // this visit's slot entries of the sums, read during the zero modes
+        AccAhead<L, EPT> acch;
+        const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
         {
-            const int64_t sl = acc_slot(a, pd, td, tid / 64, s);
-            if (sl >= 0)
-                acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0, nb,
-                                  tid % 64, active, Ar);
+            const int64_t o = pd.off_slot + (sl >= 0 ? sl : 0) * N;
+            acc_read_ahead<L, EPT>(acch, a.accA + o, a.accA2 + o, bd.n0, nb, tid % 64);
         }
+        zero_moves_p<L, EPT>(ar.vwz, kz, nb, urow, lane, Ar);
+        if (sl >= 0)
+            acc_block<L, EPT>(a.accA + pd.off_slot + sl * N, a.accA2 + pd.off_slot + sl * N, bd.n0, nb,
+                                    tid % 64, active, Ar, acch);
 #pragma unroll
         for (int t2 = 0; t2 < EPT; ++t2) Ap[t2] = Ar[t2];
         p_n0 = bd.n0;

@@ -623,10 +623,12 @@ def test_two_roles_partial_tiles_and_mixed_problems(pk):
     two.close()
 
 
-def test_two_roles_with_wide_blocks_and_global_u_rows(pk):
+@pytest.mark.parametrize("M", [201, 300])
+def test_two_roles_with_wide_blocks_and_global_u_rows(pk, M):
     """Blocks of 120 points (beyond the LDS-staged two-role instance's 112) with the U rows read
-    from global memory: the two-role chains equal the one-role chains bit for bit."""
-    p = workloads.small_problem(M=201, N=360, nblocks=3, sigma=2e-3, seed=21)
+    from global memory, for residuals of 13 and 26 entries per lane: the two-role chains equal
+    the one-role chains bit for bit."""
+    p = workloads.small_problem(M=M, N=360, nblocks=3, sigma=2e-3, seed=21)
     kw = dict(chains=300, burnin=16, sweeps=48, seed=29, precision="fp32", groups=32,
               refresh_every=64, lanes_per_chain=16, u_rows="global", start="nnls")
     one = pk.Plan([p], roles=1, **kw)
