@@ -236,9 +236,12 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 // wavefront owns 32 x 64 of it (2 x 4 MFMA f64 16x16x4 blocks).  The rows pass through LDS in
 // chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile that
 // needs it; the float32 values are widened to float64 as they enter the MFMAs.  The kernel is
-// sized (12 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with the sampler, which it
-// runs beside on a second stream.  Snapshot rows are padded to multiples of four floats.
+// sized (14 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with other work.  Snapshot
+// rows are padded to multiples of four floats.
 constexpr int kSnapTM = 64, kSnapTN = 128, kSnapKC = 16;
+// LDS row strides (floats) of the chunk's x and A rows: 16 words past the tile width, so that
+// the four k-rows an MFMA operand reads fall into different LDS banks
+constexpr int kSnapLDR = kSnapTM + 16, kSnapLDA = kSnapTN + 16;
 
 __host__ __device__ int64_t cross_snap_tiles(int64_t Mx, int64_t N) {
     return ((Mx + kSnapTM - 1) / kSnapTM) * ((N + 1 + kSnapTN - 1) / kSnapTN);
@@ -274,8 +277,8 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
                                                     const float *snapA, const float *snapR,
                                                     const int64_t *snap_first, int64_t burnin, int64_t sweeps,
                                                     double *cross) {
-    __shared__ __align__(16) float sr[kSnapKC * kSnapTM];
-    __shared__ __align__(16) float sa[kSnapKC * kSnapTN];
+    __shared__ __align__(16) float sr[kSnapKC * kSnapLDR];
+    __shared__ __align__(16) float sa[kSnapKC * kSnapLDA];
     const ProbDesc pd = probs[blockIdx.z];
     const int ksplit = pd.groups * parts;
     const int64_t M = pd.M, N = pd.N, N1 = N + 1;
@@ -370,12 +373,12 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
         __syncthreads();   // the previous chunk is consumed
         // x rows: kc x 64 (columns past Mx, rows past kc: 0); A rows with the column of ones
         // at n = N: kc x 128
-        *reinterpret_cast<float4 *>(sr + rrow * kSnapTM + 4 * rc4) = pr;
+        *reinterpret_cast<float4 *>(sr + rrow * kSnapLDR + 4 * rc4) = pr;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int e = tid + h * 256;
             const int row = e / (kSnapTN / 4), c4 = e % (kSnapTN / 4);
-            *reinterpret_cast<float4 *>(sa + row * kSnapTN + 4 * c4) = h == 0 ? pa0 : pa1;
+            *reinterpret_cast<float4 *>(sa + row * kSnapLDA + 4 * c4) = h == 0 ? pa0 : pa1;
         }
         __syncthreads();
         if (c0 + kSnapKC < k_hi) {
@@ -391,9 +394,9 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
             const int row = k4 + kk;
             double ra[2], bb[4];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * kSnapTM + 32 * wm + 16 * a + i];
+            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * kSnapLDR + 32 * wm + 16 * a + i];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bb[b] = (double)sa[row * kSnapTN + 64 * wn + 16 * b + i];
+            for (int b = 0; b < 4; ++b) bb[b] = (double)sa[row * kSnapLDA + 64 * wn + 16 * b + i];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -429,22 +432,23 @@ hipError_t launch_cross_snap(const ProbDesc *probs_dev, int64_t P, int64_t max_t
 // y0 = g~ (rank_r = 0: y_k = g~ - K~ A_k).  The float32 sampler's carried residual drifts
 // between refreshes (its zero modes are float32 roundings of exact null vectors, and K~ is
 // ill-conditioned), so the VJP's moments take the residual of the state, in float64.
-// A (rows x N, float32) times W^T (N x Mx): a workgroup of 4 wavefronts owns 64 rows and up
-// to 128 columns (column group blockIdx.y); the grid points pass through LDS in chunks of
-// kProjKC, the A rows (64 x kProjKC floats, rows padded to kProjLDA words against bank
-// conflicts) and the map (kProjKC x 128 doubles, n-major as stored), the next chunk loaded
-// into registers while the current one is multiplied.  Wavefront w forms rows 16 w .. 16 w + 15
-// by MFMA f64 16x16x4, one accumulator per 16 columns.
-constexpr int kProjKC = 32, kProjLDA = 36, kProjCols = 128;
+// A (rows x N, float32) times W^T (N x Mx): a workgroup of 4 wavefronts owns kProjRows rows
+// and up to kProjCols columns (column group blockIdx.y); the grid points pass through LDS in
+// chunks of kProjKC, the A rows (kProjRows x kProjKC floats, rows padded to kProjLDA words) and
+// the map (kProjKC x kProjCols doubles, n-major as stored, rows padded to kProjLDW doubles), the
+// next chunk loaded into registers while the current one is multiplied.  The paddings put the
+// four k-rows an MFMA operand reads into different LDS banks.  Wavefront w forms rows
+// 32 w .. 32 w + 31 by MFMA f64 16x16x4, one accumulator per 16 x 16 block.
+constexpr int kProjKC = 32, kProjLDA = 36, kProjRows = 128, kProjCols = 64, kProjLDW = 80;
 
 __global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t nsnap, const double *WY,
                                                  const float *snapA, float *yrow) {
-    __shared__ __align__(16) float sA[64 * kProjLDA];
-    __shared__ __align__(16) double sW[kProjKC * kProjCols];
+    __shared__ __align__(16) float sA[kProjRows * kProjLDA];
+    __shared__ __align__(16) double sW[kProjKC * kProjLDW];
     const ProbDesc pd = probs[blockIdx.z];
     const int64_t N = pd.N, Mx = pd.rank_r > 0 ? pd.rank_r : pd.M, rows = nsnap * pd.C;
     const int64_t ldr = (pd.M + 3) / 4 * 4, lda = (N + 3) / 4 * 4;
-    const int64_t r0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * kProjCols;
+    const int64_t r0 = (int64_t)blockIdx.x * kProjRows, j0 = (int64_t)blockIdx.y * kProjCols;
     if (r0 >= rows || j0 >= Mx) return;
     const int ncol = (int)min<int64_t>(kProjCols, Mx - j0);   // columns of this group
     const int ncb = (ncol + 15) / 16;                          // 16-column MFMA blocks
@@ -453,14 +457,15 @@ __global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t 
     const double *WT = WY + pd.off_w, *y0 = WY + pd.off_w + Mx * N;   // WT[n Mx + j]
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int i = lane % 16, kk = lane / 16;
-    // staging: A, 64 rows x 8 float4 (two per thread); the map, kProjKC x ncol doubles as
-    // double2 words (up to eight per thread)
-    float4 pa[2];
-    double2 pw[8];
+    // staging: A, kProjRows rows x 8 float4 (four per thread); the map, kProjKC x ncol doubles
+    // as double2 words (four per thread)
+    constexpr int HA = kProjRows * (kProjKC / 4) / 256, HW = kProjKC * (kProjCols / 2) / 256;
+    float4 pa[HA];
+    double2 pw[HW];
     auto load = [&](int64_t n0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h, row = e / 8, c4 = e % 8;
+        for (int h = 0; h < HA; ++h) {
+            const int e = tid + 256 * h, row = e / (kProjKC / 4), c4 = e % (kProjKC / 4);
             const int64_t r = r0 + row, n = n0 + 4 * c4;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (r < rows && n < lda) v = *reinterpret_cast<const float4 *>(Ab + r * lda + n);
@@ -472,11 +477,11 @@ __global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t 
         }
         const int half = (ncol + 1) / 2;   // double2 words per grid point
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
+        for (int h = 0; h < HW; ++h) {
             const int e = tid + 256 * h, k = e / (kProjCols / 2), c2 = e % (kProjCols / 2);
             double2 v = make_double2(0.0, 0.0);
             const int64_t n = n0 + k;
-            if (k < kProjKC && c2 < half && n < N) {
+            if (c2 < half && n < N) {
                 const int64_t j = j0 + 2 * c2;
                 v.x = WT[n * Mx + j];
                 v.y = (2 * c2 + 1 < ncol) ? WT[n * Mx + j + 1] : 0.0;
@@ -484,49 +489,59 @@ __global__ __launch_bounds__(256) void k_project(const ProbDesc *probs, int64_t 
             pw[h] = v;
         }
     };
-    d4 acc[kProjCols / 16];
+    d4 acc[2][kProjCols / 16];
 #pragma unroll
-    for (int c = 0; c < kProjCols / 16; ++c) acc[c] = d4{0, 0, 0, 0};
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < kProjCols / 16; ++c) acc[a][c] = d4{0, 0, 0, 0};
     load(0);
     for (int64_t n0 = 0; n0 < N; n0 += kProjKC) {
         __syncthreads();   // the previous chunk is consumed
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h, row = e / 8, c4 = e % 8;
+        for (int h = 0; h < HA; ++h) {
+            const int e = tid + 256 * h, row = e / (kProjKC / 4), c4 = e % (kProjKC / 4);
             *reinterpret_cast<float4 *>(sA + row * kProjLDA + 4 * c4) = pa[h];
         }
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
+        for (int h = 0; h < HW; ++h) {
             const int e = tid + 256 * h, k = e / (kProjCols / 2), c2 = e % (kProjCols / 2);
-            if (k < kProjKC) *reinterpret_cast<double2 *>(sW + k * kProjCols + 2 * c2) = pw[h];
+            *reinterpret_cast<double2 *>(sW + k * kProjLDW + 2 * c2) = pw[h];
         }
         __syncthreads();
         if (n0 + kProjKC < N) load(n0 + kProjKC);
 #pragma unroll
         for (int k4 = 0; k4 < kProjKC; k4 += 4) {
-            const double av = (double)sA[(16 * wave + i) * kProjLDA + k4 + kk];
+            double av[2], wv[kProjCols / 16];
 #pragma unroll
-            for (int c = 0; c < kProjCols / 16; ++c)
-                if (c < ncb) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sW[(k4 + kk) * kProjCols + 16 * c + i],
-                                                                          acc[c], 0, 0, 0);
+            for (int a = 0; a < 2; ++a) av[a] = (double)sA[(32 * wave + 16 * a + i) * kProjLDA + k4 + kk];
+#pragma unroll
+            for (int c = 0; c < kProjCols / 16; ++c) wv[c] = sW[(k4 + kk) * kProjLDW + 16 * c + i];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < kProjCols / 16; ++c)
+                    if (c < ncb) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], wv[c], acc[a][c], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int c = 0; c < kProjCols / 16; ++c) {
-        if (c >= ncb) continue;
-        const int64_t col = j0 + 16 * c + lane % 16;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t row = r0 + 16 * wave + lane / 16 + 4 * j;
-            if (row < rows && col < Mx) Yb[row * ldr + col] = (float)(y0[col] - acc[c][j]);
+        for (int c = 0; c < kProjCols / 16; ++c) {
+            if (c >= ncb) continue;
+            const int64_t col = j0 + 16 * c + lane % 16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = r0 + 32 * wave + 16 * a + lane / 16 + 4 * j;
+                if (row < rows && col < Mx) Yb[row * ldr + col] = (float)(y0[col] - acc[a][c][j]);
+            }
         }
-    }
 }
 
 hipError_t launch_project(const ProbDesc *probs_dev, int64_t P, int64_t max_rows, int64_t max_mx, int64_t nsnap,
                           const double *WY, const float *snapA, float *yrow, hipStream_t s) {
     if (max_rows <= 0 || max_mx <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + 63) / 64), (unsigned)((max_mx + kProjCols - 1) / kProjCols),
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((max_rows + kProjRows - 1) / kProjRows),
+                                       (unsigned)((max_mx + kProjCols - 1) / kProjCols),
                                        (unsigned)P),
                        dim3(256), 0, s, probs_dev, nsnap, WY, snapA, yrow);
     return hipGetLastError();
