@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 64 float32 lanes x 2.4 GHz, one operation per lane per cycle (no packed
 # float32 arithmetic; a fused multiply-add counts as one operation)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "tn32.h", "tn32_coef.h",
+SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l16.hip", "sample32w.h", "sample32w_l8.hip",
+                   "tn32.h", "tn32_coef.h",
                    "rng_tn.h", "internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_{workload}.md")
 WORKLOAD_FILE_NAMES = {"large": "large_config5", "single": "single_continuation"}
@@ -231,7 +232,7 @@ def batched(args):
     moves = chains * sweeps_total * sum(p.N for p in probs)
     avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
     ops_per_launch = ops_sweep * st["sampler_sweeps"] / max(1, st["sampler_launches"])
-    kernel = "k_sample32p" if st.get("roles", 1) == 2 else "k_sample32"
+    kernel = {2: "k_sample32p", 3: "k_sample32w"}.get(st.get("roles", 1), "k_sample32")
     out = {"metric": "mode-moves/s", "value": moves * args.steps / elapsed, "unit": "mode-moves/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -592,7 +593,7 @@ def one_problem(args):
     avg_launch_s = st["sampler_ms"] * 1e-3 / max(1, st["sampler_launches"])
     ops_per_launch = ops_sweep * chains * st["sampler_sweeps"] / max(1, st["sampler_launches"])
     achieved = ops_per_launch / avg_launch_s
-    kernel = "k_sample32p" if st.get("roles", 1) == 2 else "k_sample32"
+    kernel = {2: "k_sample32p", 3: "k_sample32w"}.get(st.get("roles", 1), "k_sample32")
     tr = measured_traffic(kernel, args.workload)
     se = res.stderr.cpu().numpy()
     sd = res.post_sd.cpu().numpy()

@@ -137,7 +137,16 @@ typedef struct {
                                     Two roles run the data modes of block b + 1 beside the
                                     zero modes of block b, which act on disjoint state (the
                                     zero modes leave r~ unchanged, Sec. IV.C): the chains
-                                    are bit-identical to one role                            */
+                                    are bit-identical to one role.
+                                    3 = the eight-lane sampler: one role, 8 lanes and 64
+                                    chains per workgroup, the uniforms in registers and the
+                                    residual entries held in consecutive runs per lane
+                                    (one partition with no prior or constraint, blocks of
+                                    at most 128 points and 32 data modes, at most 416 data
+                                    points, U rows in LDS; ASM_EINVAL otherwise).  With
+                                    lanes_per_chain 8 and the automatic workgroup, 0 takes
+                                    it where allowed.  Its arithmetic order differs from the
+                                    other samplers (same distribution, other rounding)     */
     int32_t chains_per_workgroup;/* ASM_FP32 only: chains per workgroup, a power of two with
                                     lanes_per_chain x chains a multiple of 64 and at most 512
                                     (256 for the prefetching instances; the two-role sampler
@@ -180,7 +189,7 @@ typedef struct {
     int64_t sampler_sweeps;      /* sweeps they covered (each over all chains)                */
     int64_t graph_replays;       /* refresh cycles replayed from captured hipGraphs (use_graph);
                                     their sampler launches are timed like the others          */
-    int64_t roles;               /* 1 or 2: the float32 sampler's roles (see asm_options)     */
+    int64_t roles;               /* 1, 2 or 3: the float32 sampler that ran (asm_options.roles) */
     int64_t rejected;            /* moves rejected by the gamma-prior test (prior_shape)      */
 } asm_stats;
 

@@ -11,7 +11,7 @@ OUT = os.path.join(HERE, "libasm.so")
 # the on-chip microbenchmarks of bench.py --micro, in a library of their own
 MICRO_SRC, MICRO_OUT = "micro.hip", os.path.join(HERE, "libasm_micro.so")
 SOURCES = ["api.hip", "setup.hip", "sample.hip", "linalg.hip", "sample32.hip", "sample32p_l16.hip", "sample32_l4.hip",
-           "sample32_l8.hip", "sample32_l16.hip", "sample32_l32.hip", "sample32_l64.hip"]
+           "sample32_l8.hip", "sample32_l16.hip", "sample32_l32.hip", "sample32_l64.hip", "sample32w_l8.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -221,6 +221,7 @@ int validate(const asm_problem *pr, int64_t n, const asm_options *o) {
     if (o->lanes_per_chain != 0 && o->lanes_per_chain != 4 && o->lanes_per_chain != 8 &&
         o->lanes_per_chain != 16 && o->lanes_per_chain != 32 && o->lanes_per_chain != 64)
         return fail(ASM_EINVAL, "lanes_per_chain must be 0, 4, 8, 16, 32 or 64");
+    if (o->roles < 0 || o->roles > 3) return fail(ASM_EINVAL, "roles must be 0, 1, 2 or 3");
     if (o->chains_per_workgroup < 0 || o->chains_per_workgroup > 512 ||
         (o->chains_per_workgroup & (o->chains_per_workgroup - 1)) != 0)
         return fail(ASM_EINVAL, "chains_per_workgroup must be 0 or a power of two up to 512");
@@ -434,6 +435,8 @@ int segment(asm_plan *pl, int64_t nsw, int accumulate, int64_t burnin_abs, bool 
         a.refresh_every = 0;
         if (pl->roles == 2)
             HIPCHK(launch_sample32p(a, pl->ept, pl->rpt, pl->grid32, pl->lds32, pl->stream));
+        else if (pl->roles == 3)
+            HIPCHK(launch_sample32w(a, pl->ept, pl->rpt, pl->grid32, pl->lds32, pl->stream));
         else
             HIPCHK(launch_sample32_inst(a, pl->lanes, pl->ept, pl->rpt, pl->chains_per_wg, pl->grid32,
                                     pl->lds32, pl->stream));
@@ -689,7 +692,7 @@ int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *h
             took.cpw <= 64 / L && took.u_rows == 1)
             break;   // nothing to vary
         std::vector<TuneConf> alt;
-        if (o->roles == 0 && took.roles == 2) {   // one role, automatic workgroup
+        if (o->roles == 0 && (took.roles == 2 || took.roles == 3)) {   // one role, automatic workgroup
             TuneConf c = a;
             c.roles = 1;
             alt.push_back(c);
@@ -835,6 +838,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     for (auto &e : pl->ev) HSTEP(hipEventCreate(&e));
     (void)set_sample32_lds_limit(160 * 1024);
     (void)allow_lds_sample32p(160 * 1024);
+    (void)allow_lds_sample32w(160 * 1024);
     (void)set_sample64_lds_limit();
     (void)hipGetLastError();
 
@@ -1054,7 +1058,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     STEP(dalloc(pl, &pl->d_nprefix, n + 1));
     STEP(dalloc(pl, &pl->d_mprefix, n + 1));
     if (pl->fp32) {
-        STEP(dalloc(pl, &pl->A32, offA));
+        // 1024 spare floats past the last chain: the eight-lane sampler loads a block's
+        // components as whole rows of its lanes (up to 127 entries past the block's end)
+        STEP(dalloc(pl, &pl->A32, offA + 1024));
         STEP(dalloc(pl, &pl->r32, offr));
     } else {
         STEP(dalloc(pl, &pl->A64, offA));
@@ -1281,6 +1287,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     }
     if (pl->fp32) {
         int L = o->lanes_per_chain;
+        if (o->roles == 3) {
+            // the eight-lane sampler (sample32w.h)
+            if (L != 0 && L != 8) {
+                rc = fail(ASM_EINVAL, "roles 3 (the eight-lane sampler) needs lanes_per_chain 8 or 0");
+                return rc;
+            }
+            L = 8;
+        }
         if (L == 0) {
             // aim for about one wavefront per SIMD (4 per CU) across all chains
             const double chains_per_simd = (double)pl->total_chains / (4.0 * max_cu);
@@ -1293,7 +1307,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             const int order[] = {L, 16, 32, 8, 4, 64};
             bool found = false;
             for (int cand : order) {
-                if (o->lanes_per_chain != 0 && cand != o->lanes_per_chain) continue;
+                if ((o->lanes_per_chain != 0 || o->roles == 3) && cand != L) continue;
                 if (sample32_pick(cand, pl->max_nb, pl->max_m, pl->ext() ? 1 : 0, &ept, &rpt, &pf) == 0) {
                     L = cand;
                     found = true;
@@ -1303,6 +1317,36 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             if (!found) {
                 rc = fail(ASM_EINVAL, "block of %lld points or %lld data points too large for the float32 sampler",
                           (long long)pl->max_nb, (long long)pl->max_m);
+                return rc;
+            }
+        }
+        // the eight-lane sampler (sample32w.h): asked for with roles 3, or taken in automatic
+        // mode for eight lanes per chain with the automatic workgroup and U rows in LDS, when
+        // one of its instances holds the sizes and its staging area fits the LDS with 64 chains
+        bool wide = false;
+        {
+            int64_t mkb = 0;
+            for (auto &bd : pl->blocks) mkb = std::max(mkb, bd.kb);
+            int we = 0, wr = 0;
+            bool ok = L == 8 && !pl->ext() && (o->roles == 0 || o->roles == 3) &&
+                      (o->chains_per_workgroup == 0 || o->chains_per_workgroup == 64) && o->u_rows == 0 &&
+                      sample32w_pick(pl->max_nb, pl->max_m, mkb, &we, &wr) == 0;
+            if (ok) {
+                const size_t need = (size_t)(pl->max_nb + 2) * we * 8 * sizeof(float2) + (size_t)(mkb + 3) / 4 * 16 +
+                                    (size_t)mkb * wr * 8 * sizeof(float) +
+                                    (size_t)64 * std::max<int64_t>(mkb, 1) * sizeof(float);
+                ok = need <= kLdsBudget;
+            }
+            if (ok) {
+                wide = true;
+                ept = we;
+                rpt = wr;
+                pf = 0;
+            } else if (o->roles == 3) {
+                rc = fail(ASM_EINVAL, "roles 3 (the eight-lane sampler) needs one partition per problem with no prior "
+                                      "or constraint, blocks of at most 128 points with at most 32 data modes, at most "
+                                      "416 data points, 64 chains per workgroup, U rows in LDS, and its staging area "
+                                      "within the LDS");
                 return rc;
             }
         }
@@ -1330,7 +1374,9 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
         for (auto &pd : pl->probs) max_n = std::max(max_n, pd.N);
         pl->max_kb = max_kb;
         pl->max_n = max_n;
-        pl->kce = (int32_t)std::max<int64_t>(4, (max_kb + 3) / 4 * 4);
+        // centre/step rows: two halves of kce floats per chain; the eight-lane sampler keeps
+        // one slot per data mode (the step overwrites the centre)
+        pl->kce = wide ? (int32_t)std::max<int64_t>(1, max_kb) : (int32_t)std::max<int64_t>(4, (max_kb + 3) / 4 * 4);
         const size_t vw_bytes = (size_t)(pl->max_nb + 2) * row * sizeof(float2);
         const size_t d_bytes = (size_t)(max_kb + 3) / 4 * 16;
         const size_t u_bytes = (size_t)max_kb * mp * sizeof(float);
@@ -1342,15 +1388,18 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             if (with_u) off += u_bytes;
             off = (off + 15) / 16 * 16;
             pl->lds_off_unif = (int64_t)off;
-            off += (size_t)cpw * row * sizeof(float) * (pl->any_prior ? 2 : 1);   // prior: acceptance rows
+            if (!wide)   // the eight-lane sampler holds its uniforms in registers
+                off += (size_t)cpw * row * sizeof(float) * (pl->any_prior ? 2 : 1);   // prior: acceptance rows
             pl->lds_off_ce = (int64_t)off;
-            off += (size_t)cpw * 2 * pl->kce * sizeof(float);
+            off += (size_t)cpw * (wide ? 1 : 2) * pl->kce * sizeof(float);
             return off;
         };
         // chains per workgroup: enough workgroups for every CU, at most 512 threads (256 for
         // the prefetching instances, compiled for one wavefront per SIMD)
         int cpw = (pf > 0 ? 256 : 512) / L;
-        if (o->chains_per_workgroup > 0) {
+        if (wide) {
+            cpw = 64;
+        } else if (o->chains_per_workgroup > 0) {
             cpw = o->chains_per_workgroup;
             if ((L * cpw) % 64 != 0 || L * cpw > (pf > 0 ? 256 : 512)) {
                 rc = fail(ASM_EINVAL, "chains_per_workgroup %d with %d lanes per chain: the threads must be a multiple "
@@ -1365,7 +1414,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             }
         }
         pl->chains_per_wg = cpw;
-        pl->u_lds = (o->u_rows == 0 && layout(cpw, true) <= kLdsBudget) ? 1 : 0;
+        pl->u_lds = (wide || (o->u_rows == 0 && layout(cpw, true) <= kLdsBudget)) ? 1 : 0;
         pl->lds32 = layout(cpw, pl->u_lds);
         if (pl->lds32 > kLdsBudget) {
             rc = fail(ASM_EINVAL, "block factors need %zu bytes of LDS (limit 160 KB)", pl->lds32);
@@ -1490,6 +1539,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                 return rc;
             }
         }
+        if (wide) pl->roles = 3;
         build_tiles(pl);
         pl->grid32 = (int)std::min<int64_t>((int64_t)pl->tiles.size(), (int64_t)max_cu * 2);
         STEP(dalloc(pl, &pl->d_tiles, pl->tiles.size()));

@@ -230,6 +230,9 @@ hipError_t allow_lds_sample32_l64(int bytes);
 hipError_t launch_sample32p(const SampleArgs &a, int ept, int rpt, int grid, size_t lds, hipStream_t s);
 int sample32p_pick(int64_t max_nb, int64_t max_m, int u_lds, int *ept, int *rpt, int *pfr, int *pfu, int *pfz);
 hipError_t allow_lds_sample32p(int bytes);
+hipError_t launch_sample32w(const SampleArgs &a, int ept, int rpt, int grid, size_t lds, hipStream_t s);
+int sample32w_pick(int64_t max_nb, int64_t max_m, int64_t max_kb, int *ept, int *rpt);
+hipError_t allow_lds_sample32w(int bytes);
 hipError_t launch_bump(int64_t *sweep, int64_t by, int *queue, hipStream_t s);
 hipError_t launch_reset_queue(int *queue, hipStream_t s);
 hipError_t launch_tn_draw(const double *c, const double *d, const double *lo, const double *hi,

@@ -74,14 +74,23 @@ __device__ __forceinline__ float seg_sum(float x) {
 template <int L, int EPT, bool bounded>
 __device__ __forceinline__ void interval32(const float2 (&vw)[EPT], const float (&Ar)[EPT], float &lo,
                                            float &hi) {
-    uint32_t hb = 0xFFFFFFFFu;
-    int32_t lb = 0x7FFFFFFF;
+    // two partial minima of each kind (even and odd t), so that the chains of dependent
+    // minimum instructions are half as long; the minimum is exact in any order
+    uint32_t hb = 0xFFFFFFFFu, hb1 = 0xFFFFFFFFu;
+    int32_t lb = 0x7FFFFFFF, lb1 = 0x7FFFFFFF;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const uint32_t bits = __float_as_uint(Ar[t] * vw[t].y);
-        hb = min(hb, bits);
-        lb = min(lb, (int32_t)bits);
+        if (t & 1) {
+            hb1 = min(hb1, bits);
+            lb1 = min(lb1, (int32_t)bits);
+        } else {
+            hb = min(hb, bits);
+            lb = min(lb, (int32_t)bits);
+        }
     }
+    hb = min(hb, hb1);
+    lb = min(lb, lb1);
     hb = seg_umin<L>(hb);
     lb = seg_imin<L>(lb);
     if (!bounded) {

@@ -85,12 +85,6 @@ __device__ __forceinline__ float q_inv32(float p) {
     return E > 0.0f ? z + step : z;
 }
 
-// log1p(z) for z > -1 (the rounding of 1 + z is compensated)
-__device__ __forceinline__ float log1p32(float z) {
-    const float l1 = 1.0f + z;
-    return (l1 == 1.0f) ? z : logf(l1) * (z / (l1 - 1.0f));
-}
-
 // 1 - e^-X for X >= 0: the Taylor series to X^8 below 1/2 (the first omitted term is
 // below 2e-8 of the value there), the hardware exp2 above (no cancellation: 1 - e^-X > 0.39)
 __device__ __forceinline__ float one_minus_exp_neg(float X) {
@@ -137,35 +131,39 @@ __device__ __forceinline__ float tilt_draw32(float lam, float w, float u, float 
 }
 
 // Mills ratio m(x) = Q(x) / phi(x) for x >= 0: the fit of Q below 14, the asymptotic
-// series 1/x (1 - 1/x^2 + 3/x^4 - 15/x^6) above (its first omitted term is 7e-11 there)
+// series 1/x (1 - 1/x^2 + 3/x^4 - 15/x^6) above (its first omitted term is 7e-11 there);
+// both are formed and one is selected, so no branch splits a wavefront
 __device__ __forceinline__ float mills32(float x) {
     using namespace tn32c;
     constexpr float kSqrt2Pi = 2.5066283f;
-    if (x < kQXmax) {
-        const float r = hw_rcp(kQK + x);
-        const float v = fmaf(kQAlpha, r, kQBeta);
-        float h = kQ[kQDeg];
+    const float r = hw_rcp(kQK + x);
+    const float v = fmaf(kQAlpha, r, kQBeta);
+    float h = kQ[kQDeg];
 #pragma unroll
-        for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
-        return kSqrt2Pi * (kQK * r) * h;
-    }
+    for (int j = kQDeg - 1; j >= 0; --j) h = fmaf(h, v, kQ[j]);
+    const float fit = kSqrt2Pi * (kQK * r) * h;
     const float ix = hw_rcp(x), i2 = ix * ix;
-    return ix * fmaf(i2, fmaf(i2, fmaf(i2, -15.0f, 3.0f), -1.0f), 1.0f);
+    const float asym = ix * fmaf(i2, fmaf(i2, fmaf(i2, -15.0f, 3.0f), -1.0f), 1.0f);
+    return x < kQXmax ? fit : asym;
 }
 
 // t in [0, w] with density proportional to exp(-a t - t^2/2) for a > 10, where Q(a + t)
 // underflows: solve log Q(a + t) - log Q(a) = log(1 - u (1 - Q(a + w) / Q(a))) for t with
 // log Q(a + t) - log Q(a) = -t (a + t/2) + log(m(a + t) / m(a)), by Newton from t = -target/a
-// (d/dt log Q(a + t) = -1 / m(a + t)).
+// (d/dt log Q(a + t) = -1 / m(a + t)).  The logarithms of Mills-ratio quotients are small
+// corrections to t (a + t/2) > 10 t and take the hardware log2; the target is formed by the
+// series helpers above, which keep 1 - e^lr and log(1 - y) accurate near zero.
 __device__ __forceinline__ float tail_draw32(float a, float w, float u) {
-    const float ma = mills32(a);
-    const float lr = __builtin_isinf(w) ? -INFINITY : -w * fmaf(0.5f, w, a) + logf(mills32(a + w) / ma);
-    const float target = log1p32(u * expm1f(lr));
-    float t = -target / a;
+    constexpr float kLn2 = 0.69314718f;
+    const float rma = hw_rcp(mills32(a));
+    // log of Q(a + w) / Q(a) (-inf for a one-sided interval: w = +inf)
+    const float lr = fmaf(-w, fmaf(0.5f, w, a), kLn2 * hw_log2(mills32(a + w) * rma));
+    const float target = -neg_log1m(u * one_minus_exp_neg(w < INFINITY ? -lr : INFINITY));
+    float t = -target * hw_rcp(a);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const float mt = mills32(a + t);
-        const float g = -t * fmaf(0.5f, t, a) + logf(mt / ma) - target;
+        const float g = fmaf(-t, fmaf(0.5f, t, a), fmaf(kLn2, hw_log2(mt * rma), -target));
         t = fmaf(g, mt, t);
     }
     return fminf(fmaxf(t, 0.0f), w);

@@ -225,7 +225,7 @@ def test_batched_fp32_config2_average_matches_oracle(pk):
 
 
 @pytest.mark.parametrize("roles,chains,groups", [(1, 16, 1), (1, 32, 32), (2, 16, 1), (2, 32, 32),
-                                                 (2, 256, 32)])
+                                                 (2, 256, 32), (3, 16, 1), (3, 100, 32), (3, 256, 32)])
 def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
     """The float32 sampler adds each block's final components to per-wavefront float64 sums
     (Eq. (MCint)).  With one measured sweep the average is the mean of the chains' final
@@ -233,7 +233,7 @@ def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
     chain slots empty (groups of one chain)."""
     p = workloads.small_problem(M=101, N=200, nblocks=2, sigma=2e-3, seed=9)
     plan = pk.Plan([p], chains=chains, burnin=3, sweeps=1, seed=77, precision="fp32", groups=groups,
-                   lanes_per_chain=16, roles=roles, start="nnls")
+                   lanes_per_chain=8 if roles == 3 else 16, roles=roles, start="nnls")
     res = plan.run()
     assert res.stats["roles"] == roles
     A = plan.state(0)[0].cpu().numpy()
@@ -242,7 +242,8 @@ def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
     assert np.allclose(res.post_sd.cpu().numpy(), A.std(0), rtol=1e-6, atol=1e-12 * np.max(A))
 
 
-def test_batched_fp32_config5_average_matches_oracle(pk, orc):
+@pytest.mark.parametrize("lanes,roles", [(0, 0), (16, 2), (8, 3)])
+def test_batched_fp32_config5_average_matches_oracle(pk, orc, lanes, roles):
     """The large workload at its full size: 401 correlated data points whitened by their
     Cholesky factor, 4000 grid points in 32 blocks of 125, 16384 float32 chains, 1000 + 5000
     sweeps from the NNLS start, refresh every 64 sweeps (a hipGraph per cycle), against the
@@ -256,8 +257,10 @@ def test_batched_fp32_config5_average_matches_oracle(pk, orc):
     p.init = orc.nnls_start(orc.prepare(p))
     plan = pk.Plan([p], chains=16384, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=meta["seed"] + 1000,
                    precision="fp32", groups=meta["groups"], refresh_every=meta["refresh_every"],
-                   use_graph=True)
+                   use_graph=True, lanes_per_chain=lanes, roles=roles)
     res = plan.run()
+    if roles:
+        assert res.stats["roles"] == roles and res.stats["lanes_per_chain"] == lanes
     m, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
     ok, info = zscore_ok(m, se, z["mean"], z["stderr"], **CORRELATED)
     print("config 5: max |d<A>| / max <A> = %.3g, (max z, n > 3, n, mean z^2) =" %
@@ -325,6 +328,38 @@ def test_carried_residual_matches_recomputed(pk, precision, tol):
     assert float((rr - r).abs().max()) <= tol * float(rr.abs().max())
     assert float(A.min()) >= 0.0
     plan.close()
+
+
+@pytest.mark.parametrize("M,N,nblocks", [(201, 800, 8), (401, 1000, 8)])
+def test_eight_lane_sampler_keeps_the_residual(pk, M, N, nblocks):
+    """The eight-lane sampler carries r with the block's centres and residual update over the
+    lanes' blocked residual entries (52 or 28 per lane): after 36 sweeps past the last refresh r
+    still equals g~ - K~ A to float32 accuracy, A stays non-negative, and the sampler that ran
+    is the eight-lane one."""
+    p = workloads.config2() if M == 201 else workloads.small_problem(M=M, N=N, nblocks=nblocks, sigma=1e-3, seed=2,
+                                                                            k=[12] * nblocks)
+    plan = pk.Plan([p], chains=192, burnin=0, sweeps=1, precision="fp32", groups=32, refresh_every=64,
+                   lanes_per_chain=8, roles=3, start="nnls")
+    plan.advance(100)
+    A, r, chi2 = plan.state(0)
+    Kt, gt = plan.whitened(0)
+    rr = gt[None, :] - A @ Kt.T
+    assert float((rr - r).abs().max()) <= 1e-3 * float(rr.abs().max())
+    assert float(A.min()) >= 0.0
+    assert plan.run().stats["roles"] == 3
+    plan.close()
+
+
+def test_eight_lane_sampler_refuses_what_it_cannot_hold(pk):
+    p = workloads.small_problem(M=41, N=48, nblocks=3, seed=1)
+    for kw in (dict(lanes_per_chain=16), dict(lanes_per_chain=8, chains_per_workgroup=32),
+               dict(lanes_per_chain=8, u_rows="global")):
+        with pytest.raises(pk.AsmError):
+            pk.Plan([p], chains=64, burnin=0, sweeps=1, precision="fp32", roles=3, **kw)
+    q = workloads.small_problem(M=41, N=48, nblocks=3, seed=1)
+    q.levels = pk.hierarchy(q.N, max_block=16)
+    with pytest.raises(pk.AsmError):
+        pk.Plan([q], chains=64, burnin=0, sweeps=1, precision="fp32", roles=3, lanes_per_chain=8)
 
 
 def test_batched_problems_are_independent(pk):
