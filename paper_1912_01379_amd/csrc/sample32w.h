@@ -89,9 +89,14 @@ __device__ __forceinline__ void zero_window(const float2 *sVW, int i0, int n, co
     q[1] = c == 0 ? w1 : c == 1 ? w2 : c == 2 ? w3 : w0;
     q[2] = c == 0 ? w2 : c == 1 ? w3 : c == 2 ? w0 : w1;
     q[3] = c == 0 ? w3 : c == 1 ? w0 : c == 2 ? w1 : w2;
-    // bodies of 4 moves: move k of a body reads row set k mod 2 and word register k mod 4
+    // bodies of 4 moves: move k of a body reads row set k mod 2 and word register k mod 4; the
+    // body's four uniforms are fetched first, so that waiting for one of them leaves the rows
+    // loaded after it (a move ahead) in flight
 #pragma unroll 1
     for (int h = 0; h < 24; h += 4) {
+        float u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = __shfl(q[k], (c + h + k) >> 2, L);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int j = h + k;
@@ -99,10 +104,21 @@ __device__ __forceinline__ void zero_window(const float2 *sVW, int i0, int n, co
                 // row i0 + j + 1 into the set row i0 + j - 1 left (the row past the block's
                 // last mode is a spare row of the staging area)
                 load_row<EPT>(R[(k + 1) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
-                const float u = __shfl(q[k], (c + j) >> 2, L);
-                zero_move<L, EPT>(R[k % 2], Ar, u);
+                zero_move<L, EPT>(R[k % 2], Ar, u[k]);
             }
         }
+    }
+}
+
+// Copy words [w0, w1) of a block's chunk to the same words of the staging area by LDS-direct
+// loads (global_load_lds_dwordx4: no registers; done when vmcnt reaches zero).  The LDS
+// address of such a load is that of the wavefront's first lane, the others' words follow it.
+__device__ __forceinline__ void stage_direct(float4 *dst, const float4 *src, int w0, int w1, int tid, int nthr) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int wbase = tid & ~63;
+    for (int i0 = w0; i0 < w1; i0 += nthr) {
+        const int i = i0 + tid;
+        if (i < w1) __builtin_amdgcn_global_load_lds((const void *)(src + i), (lds_void *)(dst + i0 + wbase), 16, 0, 0);
     }
 }
 
@@ -163,6 +179,7 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
     const int64_t nsw = a.nsw;
     if (a.snapA && blockIdx.x == 0 && tid == 0) *a.snap_first = s0;
     const int nw = (int)a.chunk_words;
+    const int wrows = (int)(a.lds_off_d / 16);   // 16-byte words of the (V, w) rows
     float4 *stage = reinterpret_cast<float4 *>(smem32);
 
     int visited = 0;   // thread 0's: tile ranges used up
@@ -223,7 +240,14 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
-                stage_sync(stage, a.F32 + bd.off_chunk, nw, tid, nthr);
+                // the staging area by LDS-direct loads: first the rows the data modes read (0 ..
+                // kb + 1) and the singular values and U rows, waited for here; then the zero
+                // modes' rows, which arrive during the data modes and are waited for before the
+                // zero modes
+                const float4 *chunk = a.F32 + bd.off_chunk;
+                const int wd = min((kb + 2) * (ROW / 2), wrows);
+                stage_direct(stage, chunk, 0, wd, tid, nthr);
+                stage_direct(stage, chunk, wrows, nw, tid, nthr);
                 // the data modes' uniforms (modes 0 .. 4 L - 1, one Philox call per lane)
                 float ud[4];
                 {
@@ -234,7 +258,9 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     ud[2] = word_u32(x.z);
                     ud[3] = word_u32(x.w);
                 }
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the data part is in LDS
                 __syncthreads();
+                stage_direct(stage, chunk, wd, min((nb + 2) * (ROW / 2), wrows), tid, nthr);
                 float2 R[2][EPT];
                 load_row<EPT>(R[0], sVW, lane, L);
                 if (kb > 0) {
@@ -254,14 +280,15 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     }
                     residual_blocked<L, RPT>(kb, sU, sc, lane, rr);
                 }
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the zero modes' rows are in LDS
+                __syncthreads();
                 // the previous block's components (and snapshot row), stored after the data
                 // modes, whose waits would otherwise include them (vmcnt counts stores too), and
                 // before the next block's components are loaded (with two blocks that is the
                 // block stored here); the first wait after them is at the end of the zero modes
                 store_prev();
                 // the next block (of this sweep, or the first of the next): its components,
-                // loaded during the zero modes (unconditional and clamped into the block, so
-                // that no branch leaves the compiler's wait counting inexact)
+                // loaded during the zero modes
                 {
                     // whole rows from one base address (immediate offsets, no per-entry
                     // clamping: entries past the block belong to the next block, or to the
