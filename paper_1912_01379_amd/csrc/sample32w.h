@@ -14,10 +14,11 @@
 //     block's centres c = U_b^T r and its residual update read the U rows as 16-byte words;
 //   * keeps one LDS slot per data mode and chain: the centre c_i, overwritten by the step
 //     e_i = delta_i d_i once mode i has moved.
-// The zero modes run in windows of 24 modes from the first zero mode, fully unrolled: the 24
-// uniforms of a window come from at most seven Philox calls (one per lane), rotated at the
-// window's start so that move j reads a fixed register; the (V, w) rows rotate through three
-// register sets, loaded two moves ahead.
+// The uniforms of modes 0 .. 31 come from one Philox call per lane at the block's start (they
+// serve the data modes and the first zero modes), those of every later 32 modes from one call
+// per lane when the zero modes reach them; a move takes its uniform from the lane holding it,
+// the words rotated once per run so that a move reads a fixed register.  The (V, w) rows
+// alternate between two register sets, each loaded a move ahead.
 #pragma once
 
 #include "sample32.h"
@@ -72,41 +73,50 @@ __device__ __forceinline__ void residual_blocked(int kb, const float *sU, const 
     }
 }
 
-// Zero modes i0 .. i0 + n - 1 (n <= 24) of one window.  On entry R[0] holds row i0; on return
-// (n = 24) it holds row i0 + 24.
-template <int L, int EPT>
-__device__ __forceinline__ void zero_window(const float2 *sVW, int i0, int n, const SampleArgs &a, uint32_t problem,
-                                            uint32_t chain, uint32_t s, uint32_t b, int lane,
-                                            float2 (&R)[2][EPT], float (&Ar)[EPT]) {
+// Zero modes i0 .. i0 + n - 1 with their uniforms in registers: mode i0 + j is word q[j mod 4]
+// of lane lb + (c + j) / 4 of the chain (q holds a lane's four words rotated by c).  Move j
+// reads row set (j + P) mod 2, where row i0 + j was loaded a move ahead; on entry R[P] holds
+// row i0, on return R[(n + P) mod 2] holds row i0 + n.
+template <int L, int EPT, int P>
+__device__ __forceinline__ void zero_run(const float2 *sVW, int i0, int n, const float (&q)[4], int c, int lb,
+                                         int lane, float2 (&R)[2][EPT], float (&Ar)[EPT]) {
     constexpr int ROW = EPT * L;
-    // modes i0 .. i0 + 23 lie in the Philox groups i0/4 .. i0/4 + 6: lane j draws group i0/4 + j
-    const int g0 = i0 >> 2, c = i0 & 3;
-    const U4 x = move_words32(a.seed, problem, chain, s, b, (uint32_t)(g0 + lane));
-    const float w0 = word_u32(x.x), w1 = word_u32(x.y), w2 = word_u32(x.z), w3 = word_u32(x.w);
-    // q[k] = word (k + c) mod 4: mode i0 + j is word (c + j) mod 4 = q[j mod 4] of lane (c + j) / 4
-    float q[4];
-    q[0] = c == 0 ? w0 : c == 1 ? w1 : c == 2 ? w2 : w3;
-    q[1] = c == 0 ? w1 : c == 1 ? w2 : c == 2 ? w3 : w0;
-    q[2] = c == 0 ? w2 : c == 1 ? w3 : c == 2 ? w0 : w1;
-    q[3] = c == 0 ? w3 : c == 1 ? w0 : c == 2 ? w1 : w2;
-    // bodies of 4 moves: move k of a body reads row set k mod 2 and word register k mod 4; the
-    // body's four uniforms are fetched first, so that waiting for one of them leaves the rows
-    // loaded after it (a move ahead) in flight
+    // bodies of 4 moves (4 is a multiple of the 2 row sets and the 4 words); the body's
+    // uniforms are fetched first, so that waiting for one of them leaves the rows loaded after
+    // it (a move ahead) in flight
 #pragma unroll 1
-    for (int h = 0; h < 24; h += 4) {
+    for (int h = 0; h < n; h += 4) {
         float u[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = __shfl(q[k], (c + h + k) >> 2, L);
+        for (int k = 0; k < 4; ++k) u[k] = __shfl(q[k], lb + ((c + h + k) >> 2), L);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int j = h + k;
             if (j < n) {
                 // row i0 + j + 1 into the set row i0 + j - 1 left (the row past the block's
                 // last mode is a spare row of the staging area)
-                load_row<EPT>(R[(k + 1) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
-                zero_move<L, EPT>(R[k % 2], Ar, u[k]);
+                load_row<EPT>(R[(k + 1 + P) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
+                zero_move<L, EPT>(R[(k + P) % 2], Ar, u[k]);
             }
         }
+    }
+}
+
+// The zero modes z0 .. nb - 1 of a block: those below 4 L with the data modes' uniforms (lane
+// j holds modes 4 j .. 4 j + 3; q1 holds them rotated by z0 mod 4), then windows of 4 L modes,
+// one Philox call per lane each.  On entry R[0] holds row z0; (4 L - z0) is even, so that every
+// run after the first starts on row set 0.
+template <int L, int EPT>
+__device__ __forceinline__ void zero_modes_w(const float2 *sVW, int z0, int nb, const float (&q1)[4],
+                                             const SampleArgs &a, uint32_t problem, uint32_t chain, uint32_t s,
+                                             uint32_t b, int lane, float2 (&R)[2][EPT], float (&Ar)[EPT]) {
+    constexpr int W = 4 * L;
+    const int n1 = min(nb, W) - z0;
+    if (n1 > 0) zero_run<L, EPT, 0>(sVW, z0, n1, q1, z0 & 3, z0 >> 2, lane, R, Ar);
+    for (int w0 = W; w0 < nb; w0 += W) {
+        const U4 x = move_words32(a.seed, problem, chain, s, b, (uint32_t)(w0 / 4 + lane));
+        const float q[4] = {word_u32(x.x), word_u32(x.y), word_u32(x.z), word_u32(x.w)};
+        zero_run<L, EPT, 0>(sVW, w0, min(W, nb - w0), q, 0, 0, lane, R, Ar);
     }
 }
 
@@ -163,7 +173,7 @@ __device__ __forceinline__ void acc_block_chunked(double *accA, double *accA2, i
 
 template <int L, int EPT, int RPT>
 __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
-    static_assert(L == 8, "the window scheme draws seven Philox calls, one per lane of a chain");
+    static_assert(L == 8, "the uniform windows of 4 L modes hold one Philox call per lane of a chain");
     extern __shared__ __align__(16) unsigned char smem32[];
     constexpr int ROW = EPT * L;
     const int tid = threadIdx.x;
@@ -280,6 +290,18 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     }
                     residual_blocked<L, RPT>(kb, sU, sc, lane, rr);
                 }
+                // the first zero mode z0: kb, or kb + 1 when kb is odd (mode kb then moves on its
+                // own below), so that the zero modes below 4 L are an even number; the data
+                // modes' words for them, rotated by z0 mod 4
+                const int z0 = min(kb + (kb & 1), nb);
+                float q1[4];
+                {
+                    const int c = z0 & 3;
+                    q1[0] = c == 0 ? ud[0] : c == 1 ? ud[1] : c == 2 ? ud[2] : ud[3];
+                    q1[1] = c == 0 ? ud[1] : c == 1 ? ud[2] : c == 2 ? ud[3] : ud[0];
+                    q1[2] = c == 0 ? ud[2] : c == 1 ? ud[3] : c == 2 ? ud[0] : ud[1];
+                    q1[3] = c == 0 ? ud[3] : c == 1 ? ud[0] : c == 2 ? ud[1] : ud[2];
+                }
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the zero modes' rows are in LDS
                 __syncthreads();
                 // the previous block's components (and snapshot row), stored after the data
@@ -305,10 +327,14 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     const int64_t o = pd.off_slot + (acc_sl >= 0 ? acc_sl : 0) * N;
                     acc_read_ahead<L, EPT>(acch, a.accA + o, a.accA2 + o, bd.n0, nb, tid % 64);
                 }
-                // zero modes kb .. nb - 1 in windows of 24
-                for (int i0 = kb; i0 < nb; i0 += 24)
-                    zero_window<L, EPT>(sVW, i0, min(24, nb - i0), a, pd.index, (uint32_t)chain, (uint32_t)s,
-                                        (uint32_t)b, lane, R, Ar);
+                // zero modes kb .. nb - 1
+                if (z0 > kb) {
+                    // the odd zero mode kb, with its row loaded after it (once per block)
+                    zero_move<L, EPT>(R[0], Ar, data_uniform<L>(ud, kb));
+                    load_row<EPT>(R[0], sVW + (kb + 1) * ROW, lane, L);
+                }
+                zero_modes_w<L, EPT>(sVW, z0, nb, q1, a, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b, lane,
+                                     R, Ar);
                 if (acc_sl >= 0)
                     acc_block_chunked<L, EPT>(a.accA + pd.off_slot + acc_sl * N, a.accA2 + pd.off_slot + acc_sl * N,
                                               bd.n0, nb, tid % 64, active, Ar, acch);
