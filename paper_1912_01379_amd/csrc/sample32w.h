@@ -250,13 +250,12 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
 #pragma unroll
                 for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
-                // the staging area by LDS-direct loads: first the rows the data modes read (0 ..
-                // kb + 1) and the singular values and U rows, waited for here; then the zero
-                // modes' rows, which arrive during the data modes and are waited for before the
-                // zero modes
+                // the staging area by LDS-direct loads: the block's nb + 2 rows, its singular
+                // values and U rows (waiting here for all of it, with one barrier, measured
+                // faster than letting the zero modes' rows arrive during the data modes behind
+                // a second barrier, at which the wavefronts wait for the slowest data modes)
                 const float4 *chunk = a.F32 + bd.off_chunk;
-                const int wd = min((kb + 2) * (ROW / 2), wrows);
-                stage_direct(stage, chunk, 0, wd, tid, nthr);
+                stage_direct(stage, chunk, 0, min((nb + 2) * (ROW / 2), wrows), tid, nthr);
                 stage_direct(stage, chunk, wrows, nw, tid, nthr);
                 // the data modes' uniforms (modes 0 .. 4 L - 1, one Philox call per lane)
                 float ud[4];
@@ -268,9 +267,8 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     ud[2] = word_u32(x.z);
                     ud[3] = word_u32(x.w);
                 }
-                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the data part is in LDS
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the chunk is in LDS
                 __syncthreads();
-                stage_direct(stage, chunk, wd, min((nb + 2) * (ROW / 2), wrows), tid, nthr);
                 float2 R[2][EPT];
                 load_row<EPT>(R[0], sVW, lane, L);
                 if (kb > 0) {
@@ -302,8 +300,6 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     q1[2] = c == 0 ? ud[2] : c == 1 ? ud[3] : c == 2 ? ud[0] : ud[1];
                     q1[3] = c == 0 ? ud[3] : c == 1 ? ud[0] : c == 2 ? ud[1] : ud[2];
                 }
-                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the zero modes' rows are in LDS
-                __syncthreads();
                 // the previous block's components (and snapshot row), stored after the data
                 // modes, whose waits would otherwise include them (vmcnt counts stores too), and
                 // before the next block's components are loaded (with two blocks that is the
