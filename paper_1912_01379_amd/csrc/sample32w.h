@@ -74,49 +74,55 @@ __device__ __forceinline__ void residual_blocked(int kb, const float *sU, const 
 }
 
 // Zero modes i0 .. i0 + n - 1 with their uniforms in registers: mode i0 + j is word q[j mod 4]
-// of lane lb + (c + j) / 4 of the chain (q holds a lane's four words rotated by c).  Move j
-// reads row set (j + P) mod 2, where row i0 + j was loaded a move ahead; on entry R[P] holds
-// row i0, on return R[(n + P) mod 2] holds row i0 + n.
-template <int L, int EPT, int P>
-__device__ __forceinline__ void zero_run(const float2 *sVW, int i0, int n, const float (&q)[4], int c, int lb,
-                                         int lane, float2 (&R)[2][EPT], float (&Ar)[EPT]) {
+// of lane lb + (C + j) / 4 of the chain (q holds a lane's four words rotated by C = i0 mod 4;
+// C < 0: the rotation c is given at run time).  Move j reads row set j mod 2, where row i0 + j was loaded a move ahead; on entry
+// R[0] holds row i0, on return R[n mod 2] holds row i0 + n.  lbase is the byte address of the
+// chain's first lane for ds_bpermute.
+template <int L, int EPT, int C>
+__device__ __forceinline__ void zero_run(const float2 *sVW, int i0, int n, const float (&q)[4], int lb, int lbase,
+                                         int lane, float2 (&R)[2][EPT], float (&Ar)[EPT], int c = C) {
     constexpr int ROW = EPT * L;
     // bodies of 4 moves (4 is a multiple of the 2 row sets and the 4 words); the body's
     // uniforms are fetched first, so that waiting for one of them leaves the rows loaded after
-    // it (a move ahead) in flight
+    // it (a move ahead) in flight; within a body the source lanes are lb + h / 4 + (C + k) / 4,
+    // so one address per body serves the four shuffles (the rest is their immediate offsets)
 #pragma unroll 1
     for (int h = 0; h < n; h += 4) {
+        const int addr = lbase + ((lb + (h >> 2)) << 2);
         float u[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = __shfl(q[k], lb + ((c + h + k) >> 2), L);
+        for (int k = 0; k < 4; ++k)
+            u[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr + 4 * (((C < 0 ? c : C) + k) >> 2),
+                                                               __float_as_int(q[k])));
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int j = h + k;
             if (j < n) {
                 // row i0 + j + 1 into the set row i0 + j - 1 left (the row past the block's
                 // last mode is a spare row of the staging area)
-                load_row<EPT>(R[(k + 1 + P) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
-                zero_move<L, EPT>(R[(k + P) % 2], Ar, u[k]);
+                load_row<EPT>(R[(k + 1) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
+                zero_move<L, EPT>(R[k % 2], Ar, u[k]);
             }
         }
     }
 }
 
-// The zero modes z0 .. nb - 1 of a block: those below 4 L with the data modes' uniforms (lane
-// j holds modes 4 j .. 4 j + 3; q1 holds them rotated by z0 mod 4), then windows of 4 L modes,
-// one Philox call per lane each.  On entry R[0] holds row z0; (4 L - z0) is even, so that every
-// run after the first starts on row set 0.
+// The zero modes z0 .. nb - 1 of a block (z0 even): those below 4 L with the data modes'
+// uniforms (lane j holds modes 4 j .. 4 j + 3; q1 holds them rotated by z0 mod 4), then windows
+// of 4 L modes, one Philox call per lane each.  On entry R[0] holds row z0; 4 L - z0 is even,
+// so every run after the first starts on row set 0.
 template <int L, int EPT>
 __device__ __forceinline__ void zero_modes_w(const float2 *sVW, int z0, int nb, const float (&q1)[4],
                                              const SampleArgs &a, uint32_t problem, uint32_t chain, uint32_t s,
                                              uint32_t b, int lane, float2 (&R)[2][EPT], float (&Ar)[EPT]) {
     constexpr int W = 4 * L;
+    const int lbase = (int)((__lane_id() & ~(L - 1)) << 2);
     const int n1 = min(nb, W) - z0;
-    if (n1 > 0) zero_run<L, EPT, 0>(sVW, z0, n1, q1, z0 & 3, z0 >> 2, lane, R, Ar);
+    if (n1 > 0) zero_run<L, EPT, -1>(sVW, z0, n1, q1, z0 >> 2, lbase, lane, R, Ar, z0 & 3);
     for (int w0 = W; w0 < nb; w0 += W) {
         const U4 x = move_words32(a.seed, problem, chain, s, b, (uint32_t)(w0 / 4 + lane));
         const float q[4] = {word_u32(x.x), word_u32(x.y), word_u32(x.z), word_u32(x.w)};
-        zero_run<L, EPT, 0>(sVW, w0, min(W, nb - w0), q, 0, 0, lane, R, Ar);
+        zero_run<L, EPT, 0>(sVW, w0, min(W, nb - w0), q, 0, lbase, lane, R, Ar);
     }
 }
 
