@@ -12,6 +12,8 @@
 //     from the lane that holds it by a lane shuffle (no LDS storage);
 //   * blocks the residual per lane (lane j holds r_m for m in [52 j, 52 j + 52)), so that the
 //     block's centres c = U_b^T r and its residual update read the U rows as 16-byte words;
+//   * gives a lane pairs of neighbouring components, so that it reads its (V, w) entries of a
+//     row as 16-byte words too;
 //   * keeps one LDS slot per data mode and chain: the centre c_i, overwritten by the step
 //     e_i = delta_i d_i once mode i has moved.
 // The uniforms of modes 0 .. 31 come from one Philox call per lane at the block's start (they
@@ -31,6 +33,40 @@ __device__ __forceinline__ float data_uniform(const float (&ud)[4], int i) {
     const int k = i & 3;
     const float v = k == 0 ? ud[0] : k == 1 ? ud[1] : k == 2 ? ud[2] : ud[3];
     return __shfl(v, i >> 2, L);
+}
+
+// The components a lane holds: pairs of neighbours, q(t) = 2 lane + 2 L (t / 2) + t mod 2, so
+// that a lane reads its (V, w) entries of a row as 16-byte words (two neighbouring pairs of
+// the row per load; LDS serves 16-byte reads at about 1.4 times the rate of 8-byte ones)
+template <int L>
+__device__ __forceinline__ int comp_of(int lane, int t) {
+    return 2 * lane + 2 * L * (t >> 1) + (t & 1);
+}
+
+template <int L, int EPT>
+__device__ __forceinline__ void load_row_pairs(float2 (&vw)[EPT], const float2 *row, int lane) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(row) + lane;
+#pragma unroll
+    for (int j = 0; j < EPT / 2; ++j) {
+        const float4 x = r4[L * j];
+        vw[2 * j] = make_float2(x.x, x.y);
+        vw[2 * j + 1] = make_float2(x.z, x.w);
+    }
+}
+
+// acc_read_ahead (sample32.h) for the paired components
+template <int L, int EPT>
+__device__ __forceinline__ void acc_read_ahead_pairs(AccAhead<L, EPT> &h, const double *accA, const double *accA2,
+                                                     int64_t n0, int nb, int wlane) {
+    constexpr int GW = 64 / L;
+    const int lane = wlane % L, grp = wlane / L;
+#pragma unroll
+    for (int j = 0; j < AccAhead<L, EPT>::KA; ++j) {
+        const int t = min(grp + GW * j, EPT - 1);
+        const int64_t q = n0 + min(comp_of<L>(lane, t), nb - 1);
+        h.a[j] = accA[q];
+        h.a2[j] = accA2[q];
+    }
 }
 
 // c_i = U_i . r for the block's data modes, written to sc[i] by the chain's first lane; U rows
@@ -75,9 +111,9 @@ __device__ __forceinline__ void residual_blocked(int kb, const float *sU, const 
 
 // Zero modes i0 .. i0 + n - 1 with their uniforms in registers: mode i0 + j is word q[j mod 4]
 // of lane lb + (C + j) / 4 of the chain (q holds a lane's four words rotated by C = i0 mod 4;
-// C < 0: the rotation c is given at run time).  Move j reads row set j mod 2, where row i0 + j was loaded a move ahead; on entry
-// R[0] holds row i0, on return R[n mod 2] holds row i0 + n.  lbase is the byte address of the
-// chain's first lane for ds_bpermute.
+// C < 0: the rotation c is given at run time).  Move j reads row set j mod 2, where row i0 + j
+// was loaded a move ahead; on entry R[0] holds row i0, on return R[n mod 2] holds row i0 + n.
+// lbase is the byte address of the chain's first lane for ds_bpermute.
 template <int L, int EPT, int C>
 __device__ __forceinline__ void zero_run(const float2 *sVW, int i0, int n, const float (&q)[4], int lb, int lbase,
                                          int lane, float2 (&R)[2][EPT], float (&Ar)[EPT], int c = C) {
@@ -100,7 +136,7 @@ __device__ __forceinline__ void zero_run(const float2 *sVW, int i0, int n, const
             if (j < n) {
                 // row i0 + j + 1 into the set row i0 + j - 1 left (the row past the block's
                 // last mode is a spare row of the staging area)
-                load_row<EPT>(R[(k + 1) % 2], sVW + (i0 + j + 1) * ROW, lane, L);
+                load_row_pairs<L, EPT>(R[(k + 1) % 2], sVW + (i0 + j + 1) * ROW, lane);
                 zero_move<L, EPT>(R[k % 2], Ar, u[k]);
             }
         }
@@ -167,7 +203,7 @@ __device__ __forceinline__ void acc_block_chunked(double *accA, double *accA2, i
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int t = t0 + k;
-            const int q = lane + L * t;
+            const int q = comp_of<L>(lane, t);
             if (t % GW == grp && q < nb) {
                 accA[n0 + q] = h.a[t / GW] + s1[k];
                 accA2[n0 + q] = h.a2[t / GW] + s2[k];
@@ -225,7 +261,7 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
         {
             const BlockDesc b0 = cload(a.blocks + pd.off_blk);
 #pragma unroll
-            for (int t = 0; t < EPT; ++t) An[t] = Ag[b0.n0 + min(lane + L * t, (int)b0.nb - 1)];
+            for (int t = 0; t < EPT; ++t) An[t] = Ag[b0.n0 + min(comp_of<L>(lane, t), (int)b0.nb - 1)];
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), once per tile
         }
         // the components of the block sampled last (and its snapshot row), stored during the
@@ -236,15 +272,17 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
         int64_t p_n0 = 0, p_row = -1;
         int p_nb = 0;
         auto store_prev = [&]() {
-            float *dst = Ag + p_n0 + lane;
+            float *dst = Ag + p_n0 + 2 * lane;
 #pragma unroll
             for (int t = 0; t < EPT; ++t)
-                if (active && lane + L * t < p_nb) __builtin_nontemporal_store(Ap[t], dst + L * t);
+                if (active && comp_of<L>(lane, t) < p_nb)
+                    __builtin_nontemporal_store(Ap[t], dst + 2 * L * (t >> 1) + (t & 1));
             if (p_row >= 0) {
-                float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0 + lane;
+                float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0 + 2 * lane;
 #pragma unroll
                 for (int t = 0; t < EPT; ++t)
-                    if (active && lane + L * t < p_nb) __builtin_nontemporal_store(Ap[t], sa + L * t);
+                    if (active && comp_of<L>(lane, t) < p_nb)
+                        __builtin_nontemporal_store(Ap[t], sa + 2 * L * (t >> 1) + (t & 1));
             }
         };
 
@@ -254,7 +292,7 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                 const int nb = (int)bd.nb, kb = (int)bd.kb;
                 float Ar[EPT];
 #pragma unroll
-                for (int t = 0; t < EPT; ++t) Ar[t] = (lane + L * t < nb && active) ? An[t] : 0.0f;
+                for (int t = 0; t < EPT; ++t) Ar[t] = (comp_of<L>(lane, t) < nb && active) ? An[t] : 0.0f;
                 __syncthreads();   // the previous block's readers of the LDS rows are done
                 // the staging area by LDS-direct loads: the block's nb + 2 rows, its singular
                 // values and U rows (waiting here for all of it, with one barrier, measured
@@ -276,21 +314,21 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the chunk is in LDS
                 __syncthreads();
                 float2 R[2][EPT];
-                load_row<EPT>(R[0], sVW, lane, L);
+                load_row_pairs<L, EPT>(R[0], sVW, lane);
                 if (kb > 0) {
                     centres_blocked<L, RPT>(kb, sU, rr, lane, sc);
                     int i = 0;
                     for (; i + 2 <= kb; i += 2) {
-                        load_row<EPT>(R[1], sVW + (i + 1) * ROW, lane, L);
+                        load_row_pairs<L, EPT>(R[1], sVW + (i + 1) * ROW, lane);
                         const float u0 = data_uniform<L>(ud, i), u1 = data_uniform<L>(ud, i + 1);
                         const float d0 = sD[i], d1 = sD[i + 1], c0 = sc[i], c1 = sc[i + 1];
                         data_move<L, EPT>(R[0], c0, u0, d0, Ar, sc + i, lane);
-                        load_row<EPT>(R[0], sVW + (i + 2) * ROW, lane, L);
+                        load_row_pairs<L, EPT>(R[0], sVW + (i + 2) * ROW, lane);
                         data_move<L, EPT>(R[1], c1, u1, d1, Ar, sc + i + 1, lane);
                     }
                     if (i < kb) {
                         data_move<L, EPT>(R[0], sc[i], data_uniform<L>(ud, i), sD[i], Ar, sc + i, lane);
-                        load_row<EPT>(R[0], sVW + (i + 1) * ROW, lane, L);
+                        load_row_pairs<L, EPT>(R[0], sVW + (i + 1) * ROW, lane);
                     }
                     residual_blocked<L, RPT>(kb, sU, sc, lane, rr);
                 }
@@ -318,22 +356,22 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     // clamping: entries past the block belong to the next block, or to the
                     // spare floats past the last chain, and are never used)
                     const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < B ? b + 1 : 0));
-                    const float *src = Ag + bn.n0 + lane;
+                    const float *src = Ag + bn.n0 + 2 * lane;
 #pragma unroll
-                    for (int t = 0; t < EPT; ++t) An[t] = __builtin_nontemporal_load(src + L * t);
+                    for (int t = 0; t < EPT; ++t) An[t] = __builtin_nontemporal_load(src + 2 * L * (t >> 1) + (t & 1));
                 }
                 // this visit's slot entries of the sums, read during the zero modes
                 AccAhead<L, EPT> acch;
                 const int64_t acc_sl = acc_slot(a, pd, td, tid / 64, s);
                 {
                     const int64_t o = pd.off_slot + (acc_sl >= 0 ? acc_sl : 0) * N;
-                    acc_read_ahead<L, EPT>(acch, a.accA + o, a.accA2 + o, bd.n0, nb, tid % 64);
+                    acc_read_ahead_pairs<L, EPT>(acch, a.accA + o, a.accA2 + o, bd.n0, nb, tid % 64);
                 }
                 // zero modes kb .. nb - 1
                 if (z0 > kb) {
                     // the odd zero mode kb, with its row loaded after it (once per block)
                     zero_move<L, EPT>(R[0], Ar, data_uniform<L>(ud, kb));
-                    load_row<EPT>(R[0], sVW + (kb + 1) * ROW, lane, L);
+                    load_row_pairs<L, EPT>(R[0], sVW + (kb + 1) * ROW, lane);
                 }
                 zero_modes_w<L, EPT>(sVW, z0, nb, q1, a, pd.index, (uint32_t)chain, (uint32_t)s, (uint32_t)b, lane,
                                      R, Ar);
