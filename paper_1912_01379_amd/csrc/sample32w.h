@@ -54,6 +54,27 @@ __device__ __forceinline__ void load_row_pairs(float2 (&vw)[EPT], const float2 *
     }
 }
 
+// A lane's components stored past the caches as pairs (8-byte stores, 64 contiguous bytes per
+// chain and store; a block may start at an odd component, so the pairs are only 4-byte
+// aligned, which global stores allow), the last pair split when the block ends inside it
+typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <int L, int EPT>
+__device__ __forceinline__ void store_pairs(float *row, const float (&Ap)[EPT], int lane, int nb, bool active) {
+#pragma unroll
+    for (int j = 0; j < EPT / 2; ++j) {
+        const int q = comp_of<L>(lane, 2 * j);
+        if (active && q + 1 < nb) {
+            f32x2_a4 v;
+            v.x = Ap[2 * j];
+            v.y = Ap[2 * j + 1];
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x2_a4 *>(row + q));
+        } else if (active && q < nb) {
+            __builtin_nontemporal_store(Ap[2 * j], row + q);
+        }
+    }
+}
+
 // acc_read_ahead (sample32.h) for the paired components
 template <int L, int EPT>
 __device__ __forceinline__ void acc_read_ahead_pairs(AccAhead<L, EPT> &h, const double *accA, const double *accA2,
@@ -272,18 +293,9 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
         int64_t p_n0 = 0, p_row = -1;
         int p_nb = 0;
         auto store_prev = [&]() {
-            float *dst = Ag + p_n0 + 2 * lane;
-#pragma unroll
-            for (int t = 0; t < EPT; ++t)
-                if (active && comp_of<L>(lane, t) < p_nb)
-                    __builtin_nontemporal_store(Ap[t], dst + 2 * L * (t >> 1) + (t & 1));
-            if (p_row >= 0) {
-                float *sa = a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0 + 2 * lane;
-#pragma unroll
-                for (int t = 0; t < EPT; ++t)
-                    if (active && comp_of<L>(lane, t) < p_nb)
-                        __builtin_nontemporal_store(Ap[t], sa + 2 * L * (t >> 1) + (t & 1));
-            }
+            store_pairs<L, EPT>(Ag + p_n0, Ap, lane, p_nb, active);
+            if (p_row >= 0)
+                store_pairs<L, EPT>(a.snapA + pd.off_sa + (p_row * pd.C + chain) * NR + p_n0, Ap, lane, p_nb, active);
         };
 
         for (int64_t s = s0; s < s0 + nsw; ++s) {
