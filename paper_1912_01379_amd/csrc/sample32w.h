@@ -368,9 +368,14 @@ __global__ __launch_bounds__(512) void k_sample32w(SampleArgs a) {
                     // clamping: entries past the block belong to the next block, or to the
                     // spare floats past the last chain, and are never used)
                     const BlockDesc bn = cload(a.blocks + pd.off_blk + (b + 1 < B ? b + 1 : 0));
-                    const float *src = Ag + bn.n0 + 2 * lane;
+                    const float *src = Ag + bn.n0;
 #pragma unroll
-                    for (int t = 0; t < EPT; ++t) An[t] = __builtin_nontemporal_load(src + 2 * L * (t >> 1) + (t & 1));
+                    for (int j = 0; j < EPT / 2; ++j) {
+                        const f32x2_a4 v =
+                            __builtin_nontemporal_load(reinterpret_cast<const f32x2_a4 *>(src + comp_of<L>(lane, 2 * j)));
+                        An[2 * j] = v.x;
+                        An[2 * j + 1] = v.y;
+                    }
                 }
                 // this visit's slot entries of the sums, read during the zero modes
                 AccAhead<L, EPT> acch;
