@@ -733,6 +733,7 @@ __global__ __launch_bounds__(256) void k_nnls(const ProbDesc *probs, const int *
     int *P = reinterpret_cast<int *>(beta + PM);   // PM passive indices, then N flags
     int *inP = P + PM;
     __shared__ double red[16];
+    __shared__ int s_arg[16];
     __shared__ int s_np, s_t, s_stop;
     __shared__ double s_best, s_alpha, s_tol;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -775,20 +776,44 @@ __global__ __launch_bounds__(256) void k_nnls(const ProbDesc *probs, const int *
             w[n] = acc;
         }
         __syncthreads();
-        if (tid == 0) {
+        {
+            // the largest w_n above the tolerance over the active set, the smallest n among
+            // equal values (that of a scan in increasing n): each thread over its n, then the
+            // pairs (value, n) combined across the wavefront and the workgroup (thread 0 ends
+            // with the result)
             int best = -1;
             double bv = s_tol;
-            for (int64_t n = 0; n < N; ++n)
+            for (int64_t n = tid; n < N; n += nthr)
                 if (!inP[n] && w[n] > bv) {
                     bv = w[n];
                     best = (int)n;
                 }
-            s_t = best;
-            s_stop = (best < 0 || s_np >= PM) ? 1 : 0;
-            if (!s_stop) {
-                P[s_np] = best;
-                inP[best] = 1;
-                s_np = s_np + 1;
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int ob = __shfl_xor(best, o);
+                if (ob >= 0 && (best < 0 || ov > bv || (ov == bv && ob < best))) {
+                    bv = ov;
+                    best = ob;
+                }
+            }
+            if (lane == 0) {
+                red[wave] = bv;
+                s_arg[wave] = best;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int i = 1; i < nw; ++i)
+                    if (s_arg[i] >= 0 && (best < 0 || red[i] > bv || (red[i] == bv && s_arg[i] < best))) {
+                        bv = red[i];
+                        best = s_arg[i];
+                    }
+                s_t = best;
+                s_stop = (best < 0 || s_np >= PM) ? 1 : 0;
+                if (!s_stop) {
+                    P[s_np] = best;
+                    inP[best] = 1;
+                    s_np = s_np + 1;
+                }
             }
         }
         __syncthreads();
@@ -830,13 +855,17 @@ __global__ __launch_bounds__(256) void k_nnls(const ProbDesc *probs, const int *
                 }
                 __syncthreads();
             }
+            // R s = (Q^T g)[0:np]; R_kk = beta_k, R_ic = Q[c][i] for i < c: by columns, from the
+            // last, each solved value taken off the right-hand sides above it by all threads
+            for (int k = np - 1; k >= 0; --k) {
+                __syncthreads();   // qg[k] has every later column's part taken off
+                const double sk = qg[k] / beta[k];
+                if (tid == 0) s[P[k]] = sk;
+                const double *qk = Q + (int64_t)k * M;
+                for (int i = tid; i < k; i += nthr) qg[i] -= qk[i] * sk;
+            }
+            __syncthreads();
             if (tid == 0) {
-                // R s = (Q^T g)[0:np]; R_kk = beta_k, R_kc = Q[c][k] for c > k
-                for (int k = np - 1; k >= 0; --k) {
-                    double acc = qg[k];
-                    for (int c = k + 1; c < np; ++c) acc -= Q[(int64_t)c * M + k] * s[P[c]];
-                    s[P[k]] = acc / beta[k];
-                }
                 double amin = 2.0;
                 int ok = 1;
                 for (int k = 0; k < np; ++k) {
