@@ -315,6 +315,23 @@ def small_problem(M: int = 41, N: int = 24, nblocks: int = 2, sigma: float = 1e-
                    k=None if k is None else np.asarray(k, np.int32), name="small")
 
 
+def rank_limited(M: int, N: int, nblocks: int, rank: int, seed: int = 13, sigma: float = 0.05) -> Problem:
+    """Blocks of exactly the given numerical rank (each block's columns a random product of an
+    M x rank and a rank x N_b Gaussian matrix), with that many data modes per block: the
+    block kernels' remaining modes lie in their null spaces up to rounding, as in the
+    fermionic kernel past its numerical rank, while the number of data modes is fixed by
+    the input instead of by a singular-value decay."""
+    rng = np.random.default_rng(seed)
+    starts = equal_blocks(N, nblocks)
+    K = np.zeros((M, N))
+    for b in range(nblocks):
+        lo, hi = int(starts[b]), int(starts[b + 1])
+        K[:, lo:hi] = rng.standard_normal((M, rank)) @ rng.standard_normal((rank, hi - lo)) / math.sqrt(M * rank)
+    a = 0.5 + rng.random(N)
+    return _finish(K, a, rng, sigma=sigma, omega=np.arange(N, dtype=np.float64), weights=np.ones(N),
+                   block_start=starts, k=np.full(nblocks, rank, np.int32), name="rank-limited")
+
+
 def random_wellconditioned(M: int = 40, N: int = 24, nblocks: int = 2, seed: int = 11,
                            level: float = 1.0, sigma: float = 0.05) -> Problem:
     """Dense positive-and-negative kernel with well separated singular values.
