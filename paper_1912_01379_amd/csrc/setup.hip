@@ -180,6 +180,11 @@ __global__ __launch_bounds__(512) void k_block_svd(const SvdTask *tasks, const d
 
     const int64_t nc2 = ncol + (ncol & 1);
     const int64_t npairs = nc2 / 2;
+    // a pair counts as orthogonal once |x_p . x_q| <= sqrt(len) eps |x_p| |x_q|: the rounding
+    // error of the computed inner product itself is of that size, so a stricter test keeps
+    // rotating by angles of rounding size (columns at the rounding level of a rank-deficient
+    // block never pass it) and runs every sweep the loop allows
+    const double tol = sqrt((double)len) * 2.220446049250313e-16;
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(512) void k_block_svd(const SvdTask *tasks, const d
                 al = wave_sum(al);
                 be = wave_sum(be);
                 ga = wave_sum(ga);
-                if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al) * sqrt(be))) continue;
+                if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t);
@@ -713,7 +718,7 @@ int64_t nnls_work_doubles(int64_t M, int64_t N) {
     return 3 * N + 2 * M + M * P + P + (P + N + 1) / 2 + 64;
 }
 
-__global__ __launch_bounds__(256) void k_nnls(const ProbDesc *probs, const int *use, const double *Kt,
+__global__ __launch_bounds__(1024) void k_nnls(const ProbDesc *probs, const int *use, const double *Kt,
                                               const double *gt, double *work, const int64_t *work_off,
                                               double blend, double *init, int *has_init) {
     const int pidx = blockIdx.x;
@@ -923,7 +928,8 @@ __global__ __launch_bounds__(256) void k_nnls(const ProbDesc *probs, const int *
 hipError_t launch_nnls(const ProbDesc *probs_dev, int64_t P, const int *use, const double *Kt,
                        const double *gt, double *work, const int64_t *work_off, double blend,
                        double *init, int *has_init, hipStream_t s) {
-    hipLaunchKernelGGL(k_nnls, dim3((unsigned)P), dim3(256), 0, s, probs_dev, use, Kt, gt, work,
+    // one workgroup per problem, 16 wavefronts: its products with K~ are bound by memory latency
+    hipLaunchKernelGGL(k_nnls, dim3((unsigned)P), dim3(1024), 0, s, probs_dev, use, Kt, gt, work,
                        work_off, blend, init, has_init);
     return hipGetLastError();
 }
