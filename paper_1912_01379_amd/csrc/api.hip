@@ -1615,7 +1615,7 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (pl->fp32)
         HSTEP(launch_pack32_blocks(pl->d_blocks, blockM_d, (int64_t)pl->blocks.size(), pl->V64,
                                    pl->U64, pl->d64, pl->chunk, pl->F32, pl->U32, pl->flags, st));
-    HSTEP(launch_init_state2(pl->d_probs, n, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
+    HSTEP(launch_init_state2(pl->d_probs, n, o->chains, pl->Kt, pl->gt, tmpN, has_init_d, pl->A64, pl->A32,
                              pl->fp32, st));
     if (pl->any_con) {
         std::vector<int32_t> which;

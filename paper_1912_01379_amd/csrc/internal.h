@@ -201,7 +201,7 @@ int64_t nnls_work_doubles(int64_t M, int64_t N);
 hipError_t launch_nnls(const ProbDesc *probs_dev, int64_t P, const int *use, const double *Kt,
                        const double *gt, double *work, const int64_t *work_off, double blend,
                        double *init, int *has_init, hipStream_t s);
-hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, const double *Kt,
+hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, int64_t max_c, const double *Kt,
                               const double *gt, const double *init, const int *has_init,
                               double *A64, float *A32, int fp32, hipStream_t s);
 

@@ -180,14 +180,38 @@ __global__ __launch_bounds__(512) void k_block_svd(const SvdTask *tasks, const d
 
     const int64_t nc2 = ncol + (ncol & 1);
     const int64_t npairs = nc2 / 2;
-    // a pair counts as orthogonal once |x_p . x_q| <= sqrt(len) eps |x_p| |x_q|: the rounding
-    // error of the computed inner product itself is of that size, so a stricter test keeps
-    // rotating by angles of rounding size (columns at the rounding level of a rank-deficient
-    // block never pass it) and runs every sweep the loop allows
-    const double tol = sqrt((double)len) * 2.220446049250313e-16;
+    // A pair counts as orthogonal once |x_p . x_q| <= sqrt(len) eps |x_p| |x_q|, the size of
+    // the rounding error of the computed inner product.  A pair of columns both below
+    // skip |x|_max is not rotated: in a rank-deficient block such columns hold only the
+    // rounding noise of the rotations of the larger columns, which each of those renews, so
+    // their mutual test is never passed and the sweeps would run on for them alone.  Every
+    // pair with a larger column is still rotated until it passes, so the larger columns (the
+    // data modes) come out as without the skip; the small ones only shrink in rotations with
+    // larger ones and stay below skip |x|_max <= max(M, N_b) eps d_1 / 4, the rank threshold
+    // applied below, so they end as zero modes (built from the data-mode columns).
+    constexpr double kEps = 2.220446049250313e-16;
+    const double tol = sqrt((double)len) * kEps;
+    const double skip = fmin(4.0 * sqrt((double)len), 0.25 * (double)(M > nb ? M : nb)) * kEps;
+    __shared__ double s_cmax[8], s_thr2;
     for (int sweep = 0; sweep < 60; ++sweep) {
+        // the largest squared column norm of the sweep's start
+        double cm = 0.0;
+        for (int64_t j = wave; j < ncol; j += nwaves) {
+            const double *xj = X + j * len;
+            double a = 0.0;
+            for (int64_t e = lane; e < len; e += 64) a += xj[e] * xj[e];
+            cm = fmax(cm, wave_sum(a));
+        }
+        if (lane == 0) s_cmax[wave] = cm;
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        if (tid == 0) {
+            double m = 0.0;
+            for (int w = 0; w < nwaves; ++w) m = fmax(m, s_cmax[w]);
+            s_thr2 = skip * skip * m;
+        }
+        __syncthreads();
+        const double thr2 = s_thr2;
         int rotated = 0;
         for (int64_t r = 0; r < nc2 - 1; ++r) {
             for (int64_t k = wave; k < npairs; k += nwaves) {
@@ -209,6 +233,7 @@ __global__ __launch_bounds__(512) void k_block_svd(const SvdTask *tasks, const d
                 al = wave_sum(al);
                 be = wave_sum(be);
                 ga = wave_sum(ga);
+                if (al < thr2 && be < thr2) continue;
                 if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -640,7 +665,9 @@ hipError_t launch_con_start(const ProbDesc *probs_dev, const int32_t *which, int
 }
 
 // ------------------------------------------------------------------------------------
-// start state: A = init, or the best constant fit c* = (K~1).g~/|K~1|^2 (1 if c* <= 0)
+// start state: A = init, or the best constant fit c* = (K~1).g~/|K~1|^2 (1 if c* <= 0).
+// Workgroup (p, y) writes chains [y c_per, (y + 1) c_per) of problem p, each thread the
+// components n = tid + 256 t of every such chain (coalesced rows).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_init_state(const ProbDesc *probs, const double *Kt,
                                                     const double *gt, const double *init,
@@ -648,45 +675,54 @@ __global__ __launch_bounds__(256) void k_init_state(const ProbDesc *probs, const
                                                     int fp32) {
     const ProbDesc pd = probs[blockIdx.x];
     const int64_t M = pd.M, N = pd.N;
-    const double *K = Kt + pd.off_K;
-    const double *g = gt + pd.off_m;
-    __shared__ double s_num[256], s_den[256];
-    double num = 0, den = 0;
-    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
-        double sm = 0;
-        for (int64_t n = 0; n < N; ++n) sm += K[m * N + n];
-        num += sm * g[m];
-        den += sm * sm;
-    }
-    s_num[threadIdx.x] = num;
-    s_den[threadIdx.x] = den;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            s_num[threadIdx.x] += s_num[threadIdx.x + o];
-            s_den[threadIdx.x] += s_den[threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    double cstar = s_num[0] / s_den[0];
-    if (!(cstar > 0.0) || !isfinite(cstar)) cstar = 1.0;
+    const int64_t c_per = (pd.C + gridDim.y - 1) / gridDim.y;
+    const int64_t c0 = (int64_t)blockIdx.y * c_per, c1 = min(pd.C, c0 + c_per);
+    if (c0 >= c1) return;
     const bool use_init = has_init[blockIdx.x] != 0;
-    const int64_t total = pd.C * N;
-    for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
-        const int64_t n = i % N;
+    double cstar = 1.0;
+    if (!use_init) {
+        const double *K = Kt + pd.off_K;
+        const double *g = gt + pd.off_m;
+        __shared__ double s_num[256], s_den[256];
+        double num = 0, den = 0;
+        for (int64_t m = threadIdx.x; m < M; m += blockDim.x) {
+            double sm = 0;
+            for (int64_t n = 0; n < N; ++n) sm += K[m * N + n];
+            num += sm * g[m];
+            den += sm * sm;
+        }
+        s_num[threadIdx.x] = num;
+        s_den[threadIdx.x] = den;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                s_num[threadIdx.x] += s_num[threadIdx.x + o];
+                s_den[threadIdx.x] += s_den[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        cstar = s_num[0] / s_den[0];
+        if (!(cstar > 0.0) || !isfinite(cstar)) cstar = 1.0;
+    }
+    for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
         double a = use_init ? init[pd.off_n + n] : cstar;
         a = a + 0.0;   // a -0.0 start would look like a component of the other sign
-        if (fp32)
-            A32[pd.off_A + i] = (float)a;
-        else
-            A64[pd.off_A + i] = a;
+        for (int64_t c = c0; c < c1; ++c) {
+            const int64_t i = c * N + n;
+            if (fp32)
+                A32[pd.off_A + i] = (float)a;
+            else
+                A64[pd.off_A + i] = a;
+        }
     }
 }
 
-hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, const double *Kt,
+hipError_t launch_init_state2(const ProbDesc *probs_dev, int64_t P, int64_t max_c, const double *Kt,
                               const double *gt, const double *init, const int *has_init,
                               double *A64, float *A32, int fp32, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_state, dim3((unsigned)P), dim3(256), 0, s, probs_dev, Kt, gt, init,
+    // about 64 chains per workgroup, at most 256 workgroups per problem
+    const int64_t gy = std::min<int64_t>(256, std::max<int64_t>(1, (max_c + 63) / 64));
+    hipLaunchKernelGGL(k_init_state, dim3((unsigned)P, (unsigned)gy), dim3(256), 0, s, probs_dev, Kt, gt, init,
                        has_init, A64, A32, fp32);
     return hipGetLastError();
 }
