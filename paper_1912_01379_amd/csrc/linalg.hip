@@ -233,7 +233,7 @@ hipError_t launch_cross_all(const ProbDesc *probs_dev, int64_t P, int64_t max_ti
 // Splits are (group, part): the rows of chain group g (or, with batch means, of the sweeps of
 // batch g), in `parts` ranges, so the partial sums are per-group moments (the error bar of
 // the VJP).  A workgroup of 4 wavefronts owns a 64 x 128 output tile and one split; each
-// wavefront owns 32 x 64 of it (2 x 4 MFMA f64 16x16x4 blocks).  The rows pass through LDS in
+// wavefront owns 64 x 32 of it (4 x 2 MFMA f64 16x16x4 blocks).  The rows pass through LDS in
 // chunks of kSnapKC, so every snapshot value is read from memory once per workgroup tile that
 // needs it; the float32 values are widened to float64 as they enter the MFMAs.  The kernel is
 // sized (14 KB of LDS, about 100 VGPRs, 256 threads) to share CUs with other work.  Snapshot
@@ -327,15 +327,17 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
     const float *Rb = snapR + pd.off_sr;
     const float *Ab = snapA + pd.off_sa;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
-    const int wm = wave / 2, wn = wave % 2;   // the wavefront's 32 x 64 sub-tile
+    // the wavefront's 64 x 32 sub-tile: all rows of the tile, columns 32 wave .. 32 wave + 31,
+    // so that rows past Mx (the range basis' rank is rarely a multiple of 64) leave every
+    // wavefront the same number of MFMAs (a wavefront's SIMD is fixed by its index)
     const int i = lane % 16, kk = lane / 16;
-    d4 acc[2][4];
+    d4 acc[4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
     // 16 x 16 sub-tiles entirely past Mx or N + 1 are skipped (wavefront-uniform)
-    const int64_t mw = m0 + 32 * wm, nw = n0 + 64 * wn;
+    const int64_t nw = n0 + 32 * wave;
     // one 16-byte word of x and two of A per thread and chunk, loaded a chunk ahead
     const int rrow = tid / (kSnapTM / 4), rc4 = tid % (kSnapTM / 4);
     const int64_t rm = m0 + 4 * rc4;
@@ -392,28 +394,28 @@ __global__ __launch_bounds__(256) void k_cross_snap(const ProbDesc *probs, int p
 #pragma unroll
         for (int k4 = 0; k4 < kSnapKC; k4 += 4) {
             const int row = k4 + kk;
-            double ra[2], bb[4];
+            double ra[4], bb[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) ra[a] = (double)sr[row * kSnapLDR + 32 * wm + 16 * a + i];
+            for (int a = 0; a < 4; ++a) ra[a] = (double)sr[row * kSnapLDR + 16 * a + i];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bb[b] = (double)sa[row * kSnapLDA + 64 * wn + 16 * b + i];
+            for (int b = 0; b < 2; ++b) bb[b] = (double)sa[row * kSnapLDA + 32 * wave + 16 * b + i];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (mw + 16 * a < Mx && nw + 16 * b < N1)
+                for (int b = 0; b < 2; ++b)
+                    if (m0 + 16 * a < Mx && nw + 16 * b < N1)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a], bb[b], acc[a][b], 0, 0, 0);
         }
     }
     double *X = cross + pd.off_cross + (int64_t)split * Mx * N1;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t row = m0 + 32 * wm + 16 * a + lane / 16 + 4 * j;
-                const int64_t col = n0 + 64 * wn + 16 * b + lane % 16;
+                const int64_t row = m0 + 16 * a + lane / 16 + 4 * j;
+                const int64_t col = nw + 16 * b + lane % 16;
                 if (row < Mx && col < N1) X[row * N1 + col] += acc[a][b][j];
             }
 }
