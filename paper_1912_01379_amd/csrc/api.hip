@@ -596,6 +596,21 @@ std::map<std::string, TuneConf> g_tune_cache;
 // set while the tuner creates its throwaway plans: they only advance, so they get no
 // snapshot buffers
 thread_local bool t_probe_plan = false;
+// The block factors and the NNLS start depend on the problems alone, not on the sampler's
+// configuration, so the tuner's throwaway plans (of one batch) compute them once and copy them
+// afterwards (problems without a constraint, whose factors the constraint's map rewrites)
+struct ProbeShare {
+    double *V64 = nullptr, *U64 = nullptr, *d64 = nullptr, *init = nullptr;
+    int *has_init = nullptr;
+    size_t nV = 0, nU = 0, nd = 0, nN = 0;
+    std::vector<int32_t> kb;
+    bool factors = false, start = false;
+    ~ProbeShare() {
+        for (void *q : {(void *)V64, (void *)U64, (void *)d64, (void *)init, (void *)has_init})
+            if (q) (void)hipFree(q);
+    }
+};
+thread_local ProbeShare *t_probe_share = nullptr;
 
 int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *hip_stream, TuneConf *best) {
     std::string key = std::to_string(o->chains) + ":" + std::to_string(o->refresh_every) + ":" +
@@ -640,6 +655,11 @@ int tune_sampler(const asm_problem *pr, int64_t n, const asm_options *o, void *h
     chosen.roles = o->roles;
     float best_ms = -1.0f;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ProbeShare share;
+    struct ShareScope {
+        ~ShareScope() { t_probe_share = nullptr; }
+    } share_scope;
+    t_probe_share = &share;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1147,6 +1167,16 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     if (hflags & 8) { rc = fail(ASM_EDOMAIN, "covariance is not symmetric positive definite"); return rc; }
 
     // ---- block decompositions ----
+    ProbeShare *share = (t_probe_plan && !pl->any_con) ? t_probe_share : nullptr;
+    const size_t nV = (size_t)(offV + pl->vp_words);
+    std::vector<int32_t> kb(pl->blocks.size());
+    if (share && share->factors && share->nV == nV && share->nU == (size_t)offU && share->nd == (size_t)offd &&
+        share->kb.size() == kb.size()) {
+        HSTEP(hipMemcpyAsync(pl->V64, share->V64, nV * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->U64, share->U64, offU * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(pl->d64, share->d64, offd * sizeof(double), hipMemcpyDeviceToDevice, st));
+        kb = share->kb;
+    } else {
     HSTEP(hipMemsetAsync(kb_d, 0, pl->blocks.size() * sizeof(int32_t), st));   // blocks with no mode
     if (pl->any_con) {
         STEP(dalloc(pl, &pl->con, offn));
@@ -1165,9 +1195,22 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
                                  pl->d64, kb_d, st));
     if (pl->any_con)
         HSTEP(launch_con_map(pl->ctasks_d, (int64_t)pl->ctasks.size(), pl->hv, pl->V64, pl->V64, st));
-    std::vector<int32_t> kb(pl->blocks.size());
     HSTEP(hipMemcpyAsync(kb.data(), kb_d, kb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HSTEP(hipStreamSynchronize(st));
+    if (share && !share->factors) {
+        if (!share->V64) HSTEP(hipMalloc(&share->V64, nV * sizeof(double)));
+        if (!share->U64) HSTEP(hipMalloc(&share->U64, std::max<int64_t>(offU, 1) * sizeof(double)));
+        if (!share->d64) HSTEP(hipMalloc(&share->d64, std::max<int64_t>(offd, 1) * sizeof(double)));
+        HSTEP(hipMemcpyAsync(share->V64, pl->V64, nV * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(share->U64, pl->U64, offU * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(share->d64, pl->d64, offd * sizeof(double), hipMemcpyDeviceToDevice, st));
+        share->nV = nV;
+        share->nU = (size_t)offU;
+        share->nd = (size_t)offd;
+        share->kb = kb;
+        share->factors = true;
+    }
+    }
     for (size_t b = 0; b < kb.size(); ++b) pl->blocks[b].kb = kb[b];
 
     // ---- range bases and cross-moment sums (want_vjp) ----
@@ -1581,7 +1624,11 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
     HSTEP(hipMemcpyAsync(has_init_d, has_init.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
 
     // ---- start from the non-negative least-squares fit where asked ----
-    if (o->start == ASM_START_NNLS || o->start == ASM_START_NNLS_NOISED) {
+    if ((o->start == ASM_START_NNLS || o->start == ASM_START_NNLS_NOISED) && share && share->start &&
+        share->nN == (size_t)offn) {
+        HSTEP(hipMemcpyAsync(tmpN, share->init, offn * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HSTEP(hipMemcpyAsync(has_init_d, share->has_init, n * sizeof(int), hipMemcpyDeviceToDevice, st));
+    } else if (o->start == ASM_START_NNLS || o->start == ASM_START_NNLS_NOISED) {
         std::vector<int> use(n, 0);
         std::vector<int64_t> woff(n, 0);
         int64_t wtot = 0;
@@ -1608,6 +1655,14 @@ int asm_plan_create(const asm_problem *pr, int64_t n, const asm_options *o, void
             }
             HSTEP(launch_nnls(pl->d_probs, n, use_d, pl->Kt, g, nw, woff_d, 0.01, tmpN,
                               has_init_d, st));
+        }
+        if (share && !share->start) {
+            if (!share->init) HSTEP(hipMalloc(&share->init, std::max<int64_t>(offn, 1) * sizeof(double)));
+            if (!share->has_init) HSTEP(hipMalloc(&share->has_init, std::max<int64_t>(n, 1) * sizeof(int)));
+            HSTEP(hipMemcpyAsync(share->init, tmpN, offn * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HSTEP(hipMemcpyAsync(share->has_init, has_init_d, n * sizeof(int), hipMemcpyDeviceToDevice, st));
+            share->nN = (size_t)offn;
+            share->start = true;
         }
     }
 
