@@ -39,7 +39,7 @@ SAMPLER_SOURCES = ["sample32.h", "sample32_l16.hip", "sample32p.h", "sample32p_l
                    "tn32.h", "tn32_coef.h",
                    "rng_tn.h", "internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_{workload}.md")
-WORKLOAD_FILE_NAMES = {"large": "large_config5", "single": "single_continuation"}
+WORKLOAD_FILE_NAMES = {"large": "large", "single": "single_continuation"}
 
 
 def lane_ops_per_sweep(M, blocks, s_tn=40, s_u=10):
@@ -196,7 +196,7 @@ def batched(args):
     import workloads
     import paper_1912_01379_amd as pk
     dev = torch.device("cuda:0")
-    probs = workloads.config3(256)
+    probs = workloads.batched_datasets(256)
     dps = [_DevProblem(p, dev) for p in probs]
     chains = 256
     sweeps_total = args.burnin + args.sweeps
@@ -528,11 +528,11 @@ def one_problem(args):
     sweeps = args.sweeps or d["sweeps"]
     use_graph = d["graph"] or args.graph
     if args.workload == "large":
-        prob = workloads.config5()
+        prob = workloads.large_workload()
         label = ("large: beta=50, M=401 correlated (length 5) whitened by Cholesky, N=4000 Lorentzian grid, "
                  "32 blocks x 125, k<=30, sigma=1e-4, fp32 chains, NNLS start")
     else:
-        prob = workloads.config2()
+        prob = workloads.single_continuation()
         label = ("single continuation: beta=20, M=201, N=800 Lorentzian grid, "
                  + ("Fig. 2 hierarchy of 7 levels (8 to 800 blocks)" if args.hierarchy else "8 blocks x 100")
                  + ", k<=20, sigma=1e-4, fp32 chains, NNLS start")
@@ -541,7 +541,7 @@ def one_problem(args):
             # float32 instances' largest block): 8 blocks of 100 down to the single points
             prob.levels = pk.hierarchy(prob.N, max_block=128)
             prob.k = np.full(prob.B, 20, np.int32)
-    v = torch.as_tensor(workloads.config4_cotangent(prob.N), dtype=torch.float64, device=dev)
+    v = torch.as_tensor(workloads.differentiation_cotangent(prob.N), dtype=torch.float64, device=dev)
     dp = _DevProblem(prob, dev)
     want_vjp = not args.no_vjp
 

@@ -34,10 +34,10 @@ def main(replicas=12):
                    "per dataset and replica: max |z|, fraction of points with |z| > 3, mean z^2",
            "replicas": replicas, "datasets": {}}
     t0 = time.time()
-    for name in ("cfg3_1", "cfg3_2", "cfg3_3"):
+    for name in ("batched_1", "batched_2", "batched_3"):
         ref = np.load(os.path.join(HERE, f"{name}_oracle.npz"))
         meta = json.load(open(os.path.join(HERE, f"{name}_oracle.json")))
-        prob = workloads.config3_dataset(meta["index"])
+        prob = workloads.batched_dataset(meta["index"])
         prep = oracle.prepare(prob)
         init = oracle.nnls_start(prep)
         rows = []

@@ -4,12 +4,12 @@ Only the CPU oracle and the seeded workload generators are called.  Each file ho
 oracle's average spectrum <A> (the estimate of Eq. (MCint) by blocked modes sampling,
 Sec. IV.C) and its standard error over independent chain groups, for a fixed protocol
 (chains, burn-in, sweeps, seed, start model) that the GPU test repeats with its own chains.
-The config-2 reference starts from the NNLS start of Sec. IV.D, so that both sides average
+The single-continuation reference starts from the NNLS start of Sec. IV.D, so that both sides average
 over the equilibrated chain rather than over the slow relaxation from a flat start.
 
-    python tests/golden/make_reference.py [cfg1] [cfg2] [cfg3_1] [cfg3_2] [cfg3_3] [cfg4] [cfg5]
+    python tests/golden/make_reference.py [plain] [single] [batched_1] [batched_2] [batched_3] [differentiation] [large]
 
-The config-5 reference (401 correlated data points whitened by their Cholesky factor, 4000
+The large-workload reference (401 correlated data points whitened by their Cholesky factor, 4000
 grid points in 32 blocks, Sec. IV and Sec. IV.C) takes about half an hour on 8 cores.
 """
 import json
@@ -28,25 +28,25 @@ import workloads  # noqa: E402
 THREADS = int(os.environ.get("ORACLE_THREADS", "0")) or None
 
 PROTOCOLS = {
-    "cfg1": dict(problem="config1", chains=64, burnin=200, sweeps=2000, seed=11, groups=32,
+    "plain": dict(problem="plain_one_chain", chains=64, burnin=200, sweeps=2000, seed=11, groups=32,
                  refresh_every=64),
     # 512 chains: the reference's error bars are then about a third of those of the float32
     # run it is compared with, so a bias of one reference error bar is visible
-    "cfg2": dict(problem="config2", chains=512, burnin=500, sweeps=2000, seed=12, groups=32,
+    "single": dict(problem="single_continuation", chains=512, burnin=500, sweeps=2000, seed=12, groups=32,
                  refresh_every=64, start="nnls"),
-    "cfg5": dict(problem="config5", chains=256, burnin=1000, sweeps=5000, seed=15, groups=32,
+    "large": dict(problem="large_workload", chains=256, burnin=1000, sweeps=5000, seed=15, groups=32,
                  refresh_every=64, start="nnls"),
-    # the differentiation workload: the config-2 problem with its seeded cotangent v; J^T v
+    # the differentiation workload: the single-continuation problem with its seeded cotangent v; J^T v
     # (Sec. II, Eq. (PI) differentiated in the data), its error bar over the chain groups and
     # the value of every group (their covariance carries the strong correlation between the
     # entries of J^T v, which the parity test needs)
-    "cfg4": dict(problem="config2", chains=1024, burnin=500, sweeps=2000, seed=14, groups=32,
-                 refresh_every=64, start="nnls", vjp="config4_cotangent"),
+    "differentiation": dict(problem="single_continuation", chains=1024, burnin=500, sweeps=2000, seed=14, groups=32,
+                 refresh_every=64, start="nnls", vjp="differentiation_cotangent"),
 }
 # three uneven datasets of the batched workload (N = 396, 670, 407 in 4, 7, 4 blocks); 256
 # chains, so that the reference error bars are half those of a 64-chain run
 for _i in (1, 2, 3):
-    PROTOCOLS[f"cfg3_{_i}"] = dict(problem="config3_dataset", index=_i, chains=256, burnin=500,
+    PROTOCOLS[f"batched_{_i}"] = dict(problem="batched_dataset", index=_i, chains=256, burnin=500,
                                    sweeps=2000, seed=30 + _i, groups=32, refresh_every=64,
                                    start="nnls")
 

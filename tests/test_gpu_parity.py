@@ -77,7 +77,7 @@ def test_tn_draw_fp32_matches_oracle(pk, orc):
 # --------------------------------------------------------------------------------------
 
 def test_block_factors_match_oracle_svd(pk, orc):
-    p = workloads.config2()
+    p = workloads.single_continuation()
     prep = orc.prepare(p)
     plan = pk.Plan([p], chains=16, burnin=0, sweeps=1, precision="fp32", groups=4)
     Kt, gt = plan.whitened(0)
@@ -181,7 +181,7 @@ def test_empty_intervals_from_the_zero_model(pk, orc):
 def test_two_roles_refuse_a_constraint(pk):
     """The two-role sampler runs every mode of a block: a constrained problem (one mode fewer)
     is refused when two roles are requested."""
-    p = workloads.config2()
+    p = workloads.single_continuation()
     p.constraint_c = np.asarray(p.weights, np.float64)
     p.constraint_value = 1.0
     with pytest.raises(pk.AsmError, match="two roles"):
@@ -198,9 +198,9 @@ def _golden(name):
     return z, meta
 
 
-def test_plain_fp64_config1_average_matches_oracle(pk):
-    z, meta = _golden("cfg1")
-    p = workloads.config1()
+def test_plain_fp64_one_chain_average_matches_oracle(pk):
+    z, meta = _golden("plain")
+    p = workloads.plain_one_chain()
     plan = pk.Plan([p], chains=meta["chains"], burnin=meta["burnin"], sweeps=meta["sweeps"],
                    seed=meta["seed"] + 1000, precision="fp64", groups=meta["groups"],
                    refresh_every=meta["refresh_every"])
@@ -211,9 +211,9 @@ def test_plain_fp64_config1_average_matches_oracle(pk):
     plan.close()
 
 
-def test_batched_fp32_config2_average_matches_oracle(pk):
-    z, meta = _golden("cfg2")
-    p = workloads.config2()
+def test_batched_fp32_single_continuation_average_matches_oracle(pk):
+    z, meta = _golden("single")
+    p = workloads.single_continuation()
     plan = pk.Plan([p], chains=4096, burnin=meta["burnin"], sweeps=meta["sweeps"],
                    seed=meta["seed"] + 1000, precision="fp32", groups=meta["groups"],
                    refresh_every=meta["refresh_every"], start=meta["start"])
@@ -243,7 +243,7 @@ def test_fp32_sums_count_each_chain_once(pk, roles, chains, groups):
 
 
 @pytest.mark.parametrize("lanes,roles", [(0, 0), (16, 2), (8, 3)])
-def test_batched_fp32_config5_average_matches_oracle(pk, orc, lanes, roles):
+def test_batched_fp32_large_workload_average_matches_oracle(pk, orc, lanes, roles):
     """The large workload at its full size: 401 correlated data points whitened by their
     Cholesky factor, 4000 grid points in 32 blocks of 125, 16384 float32 chains, 1000 + 5000
     sweeps from the NNLS start, refresh every 64 sweeps (a hipGraph per cycle), against the
@@ -251,8 +251,8 @@ def test_batched_fp32_config5_average_matches_oracle(pk, orc, lanes, roles):
     points: the bounds of correlated spectra).  The NNLS solution of this problem is not
     unique (starts 1.6% apart fit the data to one part in a million) and 6000 sweeps do not
     forget the start, so both sides start from the oracle's NNLS model."""
-    z, meta = _golden("cfg5")
-    p = workloads.config5()
+    z, meta = _golden("large")
+    p = workloads.large_workload()
     assert meta["start"] == "nnls"
     p.init = orc.nnls_start(orc.prepare(p))
     plan = pk.Plan([p], chains=16384, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=meta["seed"] + 1000,
@@ -263,7 +263,7 @@ def test_batched_fp32_config5_average_matches_oracle(pk, orc, lanes, roles):
         assert res.stats["roles"] == roles and res.stats["lanes_per_chain"] == lanes
     m, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
     ok, info = zscore_ok(m, se, z["mean"], z["stderr"], **CORRELATED)
-    print("config 5: max |d<A>| / max <A> = %.3g, (max z, n > 3, n, mean z^2) =" %
+    print("large workload: max |d<A>| / max <A> = %.3g, (max z, n > 3, n, mean z^2) =" %
           (np.max(np.abs(m - z["mean"])) / np.max(z["mean"])), info, "lanes", res.stats["lanes_per_chain"],
           "roles", res.stats["roles"], "sampler ms", res.stats["sampler_ms"])
     assert ok, info
@@ -272,7 +272,7 @@ def test_batched_fp32_config5_average_matches_oracle(pk, orc, lanes, roles):
 
 
 def test_nnls_start_matches_scipy(pk, orc):
-    for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
+    for p in (workloads.single_continuation(), workloads.small_problem(M=41, N=48, nblocks=3)):
         prep = orc.prepare(p)
         ref = orc.nnls_start(prep)
         plan = pk.Plan([p], chains=2, burnin=0, sweeps=1, precision="fp64", groups=1, start="nnls")
@@ -318,7 +318,7 @@ def test_fp64_batch_means_with_one_chain(pk, orc):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
 def test_carried_residual_matches_recomputed(pk, precision, tol):
-    p = workloads.config2()
+    p = workloads.single_continuation()
     plan = pk.Plan([p], chains=256, burnin=0, sweeps=1, precision=precision, groups=32,
                    refresh_every=64)
     plan.advance(100)   # 36 sweeps after the last refresh
@@ -352,7 +352,7 @@ def test_eight_lane_sampler_keeps_the_residual(pk, M, N, nblocks, kb):
     about 6e-2 of |r| for both on the 128-point blocks, so there the comparison alone decides
     (a wrong residual entry or U row would leave an error of the order of |r| itself)."""
     if kb is None:
-        p = workloads.config2()
+        p = workloads.single_continuation()
     elif kb < 0:   # the fermionic kernel with at most -kb data modes per block
         p = workloads.small_problem(M=M, N=N, nblocks=nblocks, sigma=1e-3, seed=2, k=[-kb] * nblocks)
     else:
@@ -415,7 +415,7 @@ def test_eight_lane_sampler_refuses_what_it_cannot_hold(pk):
 def test_batched_problems_are_independent(pk):
     """A problem's chains do not depend on the other problems in the batch."""
     p0 = workloads.small_problem(M=41, N=48, nblocks=3, seed=1)
-    p1 = workloads.config3_dataset(7)
+    p1 = workloads.batched_dataset(7)
     for prec in ("fp32", "fp64"):
         a = pk.Plan([p0, p1], chains=64, burnin=20, sweeps=100, seed=8, precision=prec, groups=32)
         ra = a.run()
@@ -473,16 +473,16 @@ def test_vjp_fp32_matches_oracle_elementwise_small(pk, orc):
     plan.close()
 
 
-def test_vjp_config4_matches_oracle(pk):
-    """The differentiation workload (the config-2 problem, 201 data points, with its seeded
+def test_vjp_differentiation_workload_matches_oracle(pk):
+    """The differentiation workload (the single-continuation problem, 201 data points, with its seeded
     cotangent): the float32 two-role plan's J^T v, its moments taken in the range basis of K~,
     against the stored 1024-chain float64 oracle value.  The 201 entries are a smooth function
     of tau whose fluctuation is one collective motion (the leading principal direction of the
     oracle's 32 group values holds 82 % of their variance), so the comparison is Hotelling's
     T^2 in the four leading directions (p above 1e-3), with every entry within 5.5 combined
     error bars."""
-    z, meta = _golden("cfg4")
-    p = workloads.config2()
+    z, meta = _golden("differentiation")
+    p = workloads.single_continuation()
     chains = 4096
     plan = pk.Plan([p], chains=chains, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=meta["seed"] + 1000,
                    precision="fp32", groups=meta["groups"], refresh_every=meta["refresh_every"],
@@ -522,15 +522,15 @@ def test_average_spectrum_autograd_matches_plan_vjp(pk):
     ref_plan.close()
 
 
-def test_vjp_config2_fp64_against_common_random_number_differences(pk):
-    """The config-2 problem, float64 sampler: for 4 unit directions u of the data,
+def test_vjp_single_continuation_fp64_against_common_random_number_differences(pk):
+    """The single-continuation problem (201 data points, 800 grid points), float64 sampler: for 4 unit directions u of the data,
     v . (<A>(G + h u) - <A>(G - h u)) / 2h with h = 1e-3 sigma and the same random numbers on
     both sides, against (J^T v) . u, within 3 combined error bars (each side's from the chain
     groups: the group averages of the differences, and the VJP's own error bars).  The chains
     of this problem's null-space moves decorrelate within about a hundred sweeps, so the
     difference quotient carries the error bars of two independent runs."""
-    p = workloads.config2()
-    v = workloads.config4_cotangent(p.N)
+    p = workloads.single_continuation()
+    v = workloads.differentiation_cotangent(p.N)
     rng = np.random.default_rng(44)
     kw = dict(chains=256, burnin=200, sweeps=600, groups=32, seed=2026, precision="fp64",
               refresh_every=64, start="nnls")
@@ -764,7 +764,7 @@ def test_workgroup_size_and_u_layout_leave_the_chains_unchanged(pk, lanes):
     chains are laid out on the GPU: the averages and error bars are equal bit for bit.  With 16
     chains per group the larger workgroups hold chains of two or four groups."""
     import torch
-    p = workloads.config3_dataset(1)
+    p = workloads.batched_dataset(1)
     kw = dict(chains=512, burnin=0, sweeps=40, precision="fp32", groups=32, seed=11, start="nnls",
               lanes_per_chain=lanes, roles=1)
     ref = None
@@ -814,11 +814,11 @@ def test_large_correlated_noise_workload_properties(pk):
     """The large workload (M 401, N 4000 in 32 blocks, k 30, Cholesky whitening of correlated
     noise) at 1024 chains: carried residual equal to g~ - K~ A after a refresh, finite error
     bars and VJP, and the sum rule of the spectrum kept."""
-    p = workloads.config5()
+    p = workloads.large_workload()
     plan = pk.Plan([p], chains=1024, burnin=64, sweeps=64, seed=5, precision="fp32", refresh_every=64,
                    want_vjp=True, groups=32, start="nnls")
     res = plan.run()
-    g = plan.vjp(workloads.config4_cotangent(p.N)).cpu().numpy()
+    g = plan.vjp(workloads.differentiation_cotangent(p.N)).cpu().numpy()
     m, se = res.mean.cpu().numpy(), res.stderr.cpu().numpy()
     assert np.all(np.isfinite(m)) and np.all(m >= 0) and np.all(np.isfinite(se)) and np.all(np.isfinite(g))
     assert abs(float(np.sum(m * p.weights)) - 1.0) < 0.02
@@ -835,10 +835,10 @@ def test_batched_fp32_uneven_continuations_match_oracle(pk, lanes, roles):
     """Three uneven datasets of the batched workload in one plan (one persistent launch per
     refresh cycle, graph replay; the tuned sampler and the eight-lane one) against the oracle
     run of each."""
-    names = ["cfg3_1", "cfg3_2", "cfg3_3"]
+    names = ["batched_1", "batched_2", "batched_3"]
     gold = [_golden(n) for n in names]
     meta = gold[0][1]
-    probs = [workloads.config3_dataset(g[1]["index"]) for g in gold]
+    probs = [workloads.batched_dataset(g[1]["index"]) for g in gold]
     plan = pk.Plan(probs, chains=1024, burnin=meta["burnin"], sweeps=meta["sweeps"], seed=77,
                    precision="fp32", groups=32, refresh_every=meta["refresh_every"], start="nnls",
                    use_graph=True, lanes_per_chain=lanes, roles=roles)
@@ -1346,7 +1346,7 @@ def test_constraint_errors(pk):
 def test_nnls_start_from_noised_data_matches_oracle(pk, orc):
     """ASM_START_NNLS_NOISED: the NNLS fit (and c*) of g~ + xi, xi from the counter-based
     normal draws, against scipy's NNLS of the oracle's noised data."""
-    for p in (workloads.config2(), workloads.small_problem(M=41, N=48, nblocks=3)):
+    for p in (workloads.single_continuation(), workloads.small_problem(M=41, N=48, nblocks=3)):
         prep = orc.prepare(p)
         ref = orc.nnls_start(prep, noise_seed=1234, problem=0)
         plain = orc.nnls_start(prep)

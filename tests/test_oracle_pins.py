@@ -558,7 +558,7 @@ def test_single_block_is_modes_sampling_in_e_space(orc):
 
 
 def test_block_factors_are_an_orthonormal_svd(orc):
-    p = workloads.config2()
+    p = workloads.single_continuation()
     prep = orc.prepare(p)
     for b in range(prep.B):
         s0, s1 = prep.bstart[b], prep.bstart[b + 1]

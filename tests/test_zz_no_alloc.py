@@ -41,12 +41,12 @@ def _compare(pk, plan, v):
 def test_noalloc_vjp_equals_vjp_on_two_plans_in_a_row(pk):
     import torch
     dev = torch.device("cuda:0")
-    # first call: the config-2 problem (201 data points, 800 grid points), float32 two-role plan
-    big = workloads.config2()
+    # first call: the single-continuation problem (201 data points, 800 grid points), float32 two-role plan
+    big = workloads.single_continuation()
     plan = pk.Plan([big], chains=1024, burnin=50, sweeps=200, seed=3, precision="fp32", groups=32,
                    want_vjp=True, start="nnls")
     plan.run()
-    v = torch.as_tensor(workloads.config4_cotangent(big.N), dtype=torch.float64, device=dev)
+    v = torch.as_tensor(workloads.differentiation_cotangent(big.N), dtype=torch.float64, device=dev)
     _compare(pk, plan, v)
     plan.close()
     # second call, smaller: 41 data points, 48 grid points, float64, 8 groups

@@ -165,11 +165,11 @@ def _finish(K, A_true, rng, sigma=None, cov_len=None, **kw) -> Problem:
 # the five workloads
 # --------------------------------------------------------------------------------------
 
-CFG2_SPECTRUM = dict(weights=(0.30, 0.25, 0.25, 0.20), centres=(-3.0, -0.8, 2.5, 0.3),
+SINGLE_SPECTRUM = dict(weights=(0.30, 0.25, 0.25, 0.20), centres=(-3.0, -0.8, 2.5, 0.3),
                      sds=(0.8, 0.4, 1.0, 0.05))
 
 
-def config1(seed: int = BASE_SEED + 1) -> Problem:
+def plain_one_chain(seed: int = BASE_SEED + 1) -> Problem:
     """Plain modes sampling: beta=10, 41 times, 100 uniform points on [-5,5], one block."""
     beta = 10.0
     tau = imaginary_times(41, beta)
@@ -179,24 +179,24 @@ def config1(seed: int = BASE_SEED + 1) -> Problem:
     K = fermionic_kernel(tau, x, beta) * w[None, :]
     rng = np.random.default_rng(seed)
     return _finish(K, a, rng, sigma=1e-3, omega=x, weights=w,
-                   block_start=equal_blocks(100, 1), k=None, name="cfg1-plain")
+                   block_start=equal_blocks(100, 1), k=None, name="plain-one-chain")
 
 
-def config2(seed: int = BASE_SEED + 2) -> Problem:
+def single_continuation(seed: int = BASE_SEED + 2) -> Problem:
     """Single continuation, blocked modes: beta=20, 201 times, 800 Lorentzian points, 8 blocks."""
     beta = 20.0
     tau = imaginary_times(201, beta)
     x, w = lorentzian_grid(800, 2.0, 10.0)
-    a = gaussian_mixture(x, **CFG2_SPECTRUM)
+    a = gaussian_mixture(x, **SINGLE_SPECTRUM)
     a = a / np.sum(a * w)
     K = fermionic_kernel(tau, x, beta) * w[None, :]
     rng = np.random.default_rng(seed)
     return _finish(K, a, rng, sigma=1e-4, omega=x, weights=w,
                    block_start=equal_blocks(800, 8), k=np.full(8, 20, np.int32),
-                   name="cfg2-single")
+                   name="single-continuation")
 
 
-def config3_dataset(index: int, base_seed: int = BASE_SEED + 3) -> Problem:
+def batched_dataset(index: int, base_seed: int = BASE_SEED + 3) -> Problem:
     """One of the 256 uneven continuations of the batched workload."""
     rng = np.random.default_rng(base_seed * 1000 + index)
     M = int(rng.integers(51, 202))
@@ -216,14 +216,14 @@ def config3_dataset(index: int, base_seed: int = BASE_SEED + 3) -> Problem:
     bs = equal_blocks(N, B)
     k = np.array([min(20, int(bs[b + 1] - bs[b])) for b in range(B)], np.int32)
     return _finish(K, a, rng, sigma=sigma, omega=x, weights=w, block_start=bs, k=k,
-                   name=f"cfg3-{index}")
+                   name=f"batched-{index}")
 
 
-def config3(n: int = 256) -> list:
-    return [config3_dataset(i) for i in range(n)]
+def batched_datasets(n: int = 256) -> list:
+    return [batched_dataset(i) for i in range(n)]
 
 
-def config4_cotangent(N: int, seed: int = BASE_SEED + 4) -> np.ndarray:
+def differentiation_cotangent(N: int, seed: int = BASE_SEED + 4) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(N)
 
 
@@ -240,18 +240,18 @@ def gaussian_limit_problem(omega=(-3.0, -1.0, 1.0, 3.0), sigma: float = 0.1, lev
                    block_start=equal_blocks(len(x), 1), k=None, name="gauss-limit")
 
 
-def config5(seed: int = BASE_SEED + 5) -> Problem:
+def large_workload(seed: int = BASE_SEED + 5) -> Problem:
     """Large: beta=50, 401 times, 4000 Lorentzian points, 32 blocks, correlated noise."""
     beta = 50.0
     tau = imaginary_times(401, beta)
     x, w = lorentzian_grid(4000, 2.0, 10.0)
-    a = gaussian_mixture(x, **CFG2_SPECTRUM)
+    a = gaussian_mixture(x, **SINGLE_SPECTRUM)
     a = a / np.sum(a * w)
     K = fermionic_kernel(tau, x, beta) * w[None, :]
     rng = np.random.default_rng(seed)
     return _finish(K, a, rng, sigma=1e-4, cov_len=5.0, omega=x, weights=w,
                    block_start=equal_blocks(4000, 32), k=np.full(32, 30, np.int32),
-                   name="cfg5-large")
+                   name="large")
 
 
 # --------------------------------------------------------------------------------------
