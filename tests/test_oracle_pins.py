@@ -848,3 +848,19 @@ def test_correlated_bounds_cover_the_oracle_against_oracle_spread():
     assert cal["max_of_max_z"] < CORRELATED["zmax"]
     assert cal["max_frac3"] < CORRELATED["frac"]
     assert cal["max_mean_z2"] < CORRELATED["mean_z2"]
+
+
+@pytest.mark.parametrize("M,N,nblocks,k", [(224, 256, 2, 20), (416, 300, 3, 27)])
+def test_rank_limited_blocks_have_the_stated_rank(orc, M, N, nblocks, k):
+    """The rank-limited input generator (used at the eight-lane sampler's limits) gives blocks of
+    numerical rank k exactly: k singular values well above the rank threshold max(M, N_b) eps d_1
+    of Sec. IV.B-C's data-mode cut and the rest at rounding level, so the oracle's data-mode count
+    is k on every block."""
+    p = workloads.rank_limited(M, N, nblocks, k, seed=2)
+    prep = orc.prepare(p)
+    assert list(prep.kb) == [k] * nblocks
+    for b in range(nblocks):
+        Kb = prep.Kt[:, int(p.block_start[b]):int(p.block_start[b + 1])]
+        s = np.linalg.svd(Kb, compute_uv=False)
+        thr = max(Kb.shape) * np.finfo(float).eps * s[0]
+        assert s[k - 1] > 1e6 * thr and s[k] < 0.1 * thr
