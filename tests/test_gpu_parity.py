@@ -76,12 +76,22 @@ def test_tn_draw_fp32_matches_oracle(pk, orc):
 # setup: whitening and block factors
 # --------------------------------------------------------------------------------------
 
-def test_block_factors_match_oracle_svd(pk, orc):
-    p = workloads.single_continuation()
+@pytest.mark.parametrize("which", ["single_continuation", "large_workload"])
+def test_block_factors_match_oracle_svd(pk, orc, which):
+    """Block factors of the two workloads' rank-deficient blocks (numerical rank 13-15 of 100
+    points, 8-13 of 125) against the oracle's LAPACK SVDs (Sec. IV.B-C): the data-mode count of
+    every block, the singular values above 1e-6 d_1, orthonormal V, K~_b V_data = U D, the zero
+    modes in the null space up to the rank cut (|K~_b V_zero| <= sigma_(k+1) plus rounding, with
+    sigma_(k+1) below the cut max(M, N_b) eps d_1; bound 4 max(M, N_b) eps d_1), and the leading
+    modes with their signs."""
+    p = getattr(workloads, which)()
     prep = orc.prepare(p)
     plan = pk.Plan([p], chains=16, burnin=0, sweeps=1, precision="fp32", groups=4)
     Kt, gt = plan.whitened(0)
-    assert np.allclose(Kt.cpu().numpy(), prep.Kt, rtol=1e-14, atol=0)
+    Kt = Kt.cpu().numpy()
+    if p.cov is None:   # diagonal whitening: the same products on both sides
+        assert np.allclose(Kt, prep.Kt, rtol=1e-14, atol=0)
+    eps = np.finfo(float).eps
     for b in range(p.B):
         nb = int(p.block_start[b + 1] - p.block_start[b])
         k, d, U, V = plan.factors(0, b, nb)
@@ -91,9 +101,9 @@ def test_block_factors_match_oracle_svd(pk, orc):
         big = prep.d[b] > 1e-6 * prep.d[b][0]
         assert np.allclose(d[big], prep.d[b][big], rtol=1e-8)
         assert np.max(np.abs(V.T @ V - np.eye(nb))) < 1e-12
-        Kb = prep.Kt[:, p.block_start[b]:p.block_start[b + 1]]
+        Kb = Kt[:, p.block_start[b]:p.block_start[b + 1]]
         assert np.max(np.abs(Kb @ V[:, :k] - U * d[None, :])) < 1e-10 * d[0]
-        assert np.linalg.norm(Kb @ V[:, k:]) < 1e-6 * d[0]
+        assert np.linalg.norm(Kb @ V[:, k:], 2) < 4 * max(p.M, nb) * eps * d[0]
         # leading modes (well separated) equal the oracle's, sign rule included
         for i in range(4):
             assert np.max(np.abs(V[:, i] - prep.V[b][:, i])) < 1e-9
